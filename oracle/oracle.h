@@ -1,0 +1,102 @@
+/*
+ * oracle.h -- brute-force CPU reference for open-search database peptide search.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load or call this library.  The product
+ * (the HIP library under paper_2102_02286_amd/) never links, loads or calls it,
+ * and the two share no source, header, table or helper.
+ *
+ * What it computes (HiCOPS, arXiv 2102.02286):
+ *   - peptide database: tryptic digestion with missed cleavages and a length
+ *     range, variable modifications up to a per-peptide cap (Experimental Setup;
+ *     database-size model D = zeta * 2^m in Notations; Supplementary Algorithm 1);
+ *   - per spectrum: top-B most intense peaks (Superstep 3, sub-task R),
+ *     precursor-mass filter (filter_1), shared-fragment-ion counting over b/y
+ *     ions (filter_2; b/y only per the Superstep 1 footnote; shared peaks >= k
+ *     per Supplementary Text 4), hyperscore, top hits (Supplementary Algorithm 3),
+ *     a score histogram (Sampling section: the 2048-byte local null
+ *     distribution), Savitzky-Golay smoothing, linear tail fit and expect value
+ *     (Superstep 4; Supplementary Algorithm 4).
+ * Readings where the paper is silent are stated at each function in oracle.c.
+ *
+ * Everything floating-point is IEEE fp64; masses are exact int64 micro-Dalton.
+ */
+#ifndef PEPSCAN_ORACLE_H
+#define PEPSCAN_ORACLE_H
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_HIST_BINS 512
+#define ORC_MAX_MODS 16
+
+typedef struct orc_db orc_db;
+
+/* Database: proteins concatenated in `residues` with offsets `prot_off[n+1]`.
+ * Modification j: residues given by bit (letter-'A') of mod_res_mask[j], or the
+ * protein N-terminus when mod_nterm[j] != 0; mass delta mod_delta[j] (uDa).
+ * Returns NULL on invalid input. */
+orc_db* orc_db_create(const char* residues, const uint64_t* prot_off, uint64_t n_prot,
+                      uint32_t missed, uint32_t min_len, uint32_t max_len,
+                      uint32_t n_mods, const uint32_t* mod_res_mask, const int32_t* mod_nterm,
+                      const int64_t* mod_delta, uint32_t max_mods);
+void     orc_db_free(orc_db*);
+uint64_t orc_db_size(const orc_db*);
+/* Peptide `id` (rank in the sorted key order): mass, protein, start, length, site mask. */
+void     orc_db_get(const orc_db*, uint64_t id, int64_t* mass, uint32_t* prot,
+                    uint32_t* start, uint32_t* len, uint64_t* mask);
+/* Per-residue masses (uDa, modifications folded in) of peptide `id`; returns length. */
+uint32_t orc_db_residue_masses(const orc_db*, uint64_t id, int64_t* out, uint32_t cap);
+
+/* b_i and y_i, i = 1..n-1, of a residue-mass sequence (uDa). */
+void orc_ions(const int64_t* res_uda, uint32_t n, int64_t* b_out, int64_t* y_out);
+
+typedef struct {
+    int32_t  window_is_ppm;   /* 1: window in ppm of the precursor mass; 0: uDa */
+    int64_t  window;
+    int32_t  frag_tol_bins;   /* T: |bin(peak) - bin(ion)| <= T */
+    uint32_t top_peaks;       /* B */
+    uint32_t top_k;           /* k <= 64 */
+    uint32_t min_shared;      /* k_min */
+} orc_params;
+
+typedef struct {
+    uint32_t id; uint16_t n_b, n_y; uint32_t sum_q; uint32_t pad; double hyperscore;
+} orc_hit;
+
+typedef struct {
+    uint64_t n_window, n_scored;
+    double   evalue;
+    int32_t  status;          /* 0 ok, 1 no scored candidate, 2 < 3 fit points, 3 slope >= 0 */
+    int32_t  pad;
+    uint64_t lo, hi;          /* window as an id range [lo, hi) */
+    uint64_t pairs_total;     /* sum over window candidates of shared pairs */
+} orc_stat;
+
+/* Search n spectra (host CSR) with `threads` worker threads.
+ * hits[n*top_k], stats[n], hist[n*512] (hist may be NULL).  Returns 0, or -1 on
+ * invalid input. */
+int orc_search(const orc_db*, uint64_t n, const uint64_t* peak_off, const float* mz,
+               const float* intensity, const double* precursor_mz, const int8_t* charge,
+               const orc_params*, int threads, orc_hit* hits, orc_stat* stats, int32_t* hist);
+
+/* Every scored candidate (pairs >= k_min) of one spectrum, in id order.
+ * Returns the number found (entries written up to cap), or -1 on invalid input. */
+int64_t orc_scored(const orc_db*, const uint64_t* peak_off_2, const float* mz,
+                   const float* intensity, double precursor_mz, int8_t charge,
+                   const orc_params*, uint32_t* ids, uint16_t* n_b, uint16_t* n_y,
+                   uint32_t* sum_q, uint64_t cap);
+
+/* Pieces exposed for pin tests. */
+double orc_hyperscore(uint32_t n_b, uint32_t n_y, uint32_t sum_q);
+void   orc_sg_smooth(const int32_t* hist, double* out);          /* 512 -> 512 */
+int    orc_evalue(const int32_t* hist, double top_h, uint64_t n_scored,
+                  double* evalue, double* slope, double* intercept, int32_t* n_points);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,425 @@
+"""Pins of the CPU oracle against things other than itself (no GPU needed).
+
+Each test ties one part of the oracle to the paper, to chemistry, to a
+closed form, to an independent library routine, or to the pure-Python brute
+force in tests/bruteforce.py.
+"""
+import math
+import os
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ModSpec
+from paper_2102_02286_amd import synth
+from tests import bruteforce as bf
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _db(proteins, missed=2, min_len=2, max_len=40, mods=(), max_mods=0):
+    res = np.frombuffer("".join(proteins).encode(), dtype=np.uint8)
+    off = np.zeros(len(proteins) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in proteins])
+    return oracle.Database(res, off, missed, min_len, max_len, list(mods), max_mods)
+
+
+def _spectra(peak_lists, prec, charges):
+    off = np.zeros(len(peak_lists) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in peak_lists])
+    mz = np.array([m for pl in peak_lists for (m, _) in pl], np.float32)
+    it = np.array([i for pl in peak_lists for (_, i) in pl], np.float32)
+    return synth.Spectra(off, mz, it, np.asarray(prec, np.float64), np.asarray(charges, np.int8))
+
+
+# --------------------------------------------------------------------------
+# Masses: chemistry pins.
+# --------------------------------------------------------------------------
+
+def test_residue_masses_match_elemental_formulas():
+    """Each oracle residue mass equals its elemental formula (AME 2016 atomic masses)."""
+    letters = "GASPVTCLINDQKEMHFRYW"
+    # one protein holding every residue, digested with enough missed cleavages to
+    # produce the full-length peptide
+    seq = "GASPVTCLINDQKEMHFRYW"
+    db = _db([seq], missed=3, min_len=2, max_len=40)
+    tab = db.table()
+    full = [i for i in range(len(db)) if tab[i]["start"] == 0 and tab[i]["len"] == len(seq)]
+    assert len(full) == 1
+    r = db.residue_masses(full[0])
+    expect = bf.residue_masses_da()
+    for j, c in enumerate(letters):
+        assert abs(r[j] - expect[c] * 1e6) <= 1.0, c
+
+
+def test_golden_integer_masses_match_elemental_formulas():
+    d = bf.residue_masses_da()
+    for c, v in bf.RES_UDA.items():
+        assert abs(v - d[c] * 1e6) <= 1.0, c
+    assert abs(bf.WATER_UDA - (2 * bf.EL["H"] + bf.EL["O"]) * 1e6) <= 0.5
+    assert abs(bf.PROTON_UDA - bf.EL["proton"] * 1e6) <= 0.5
+
+
+def test_calibrant_peptide_masses():
+    """[M+H]+ of standard calibration peptides, to the printed 4 decimals."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "calibrant_peptides.txt")) if not l.startswith("#")]
+    for name, seq, mh in rows:
+        db = _db([seq], missed=10, min_len=2, max_len=60)
+        tab = db.table()
+        full = [i for i in range(len(db)) if tab[i]["start"] == 0 and tab[i]["len"] == len(seq)]
+        assert len(full) == 1, name
+        m = tab[full[0]]["mass"]
+        assert abs((m + bf.PROTON_UDA) * 1e-6 - float(mh)) <= 2e-4, name
+
+
+def test_modification_deltas_match_elemental_formulas():
+    el = bf.EL
+    expect = {
+        "Oxidation": el["O"],
+        "Phospho": el["H"] + el["P"] + 3 * el["O"],
+        "Acetyl": 2 * el["C"] + 2 * el["H"] + el["O"],
+        "Deamidation": el["O"] - el["N"] - el["H"],
+    }
+    for m in (synth.OXIDATION, synth.PHOSPHO, synth.ACETYL_NTERM, synth.DEAMIDATION):
+        uda = oracle.mods_from_synth([m])[0].delta_uda
+        assert abs(uda - expect[m.name] * 1e6) <= 1.0, m.name
+
+
+# --------------------------------------------------------------------------
+# Ion series: closed form and the paper's worked example.
+# --------------------------------------------------------------------------
+
+def test_b_plus_y_equals_precursor_plus_two_protons():
+    """b_i + y_(n-i) = M + 2 H+ exactly in integer uDa, with modifications."""
+    prot = synth.make_proteome(30, seed=5)
+    mods = oracle.mods_from_synth([synth.OXIDATION, synth.PHOSPHO, synth.ACETYL_NTERM])
+    db = oracle.Database(prot.residues, prot.offsets, 1, 7, 30, mods, 2)
+    rng = np.random.default_rng(0)
+    for pid in rng.integers(0, len(db), size=300):
+        mass = db.get(int(pid))[0]
+        r = db.residue_masses(int(pid))
+        b, y = oracle.ions(r)
+        n = len(r)
+        assert int(r.sum()) + bf.WATER_UDA == mass
+        for i in range(1, n):
+            assert b[i - 1] + y[n - i - 1] == mass + 2 * bf.PROTON_UDA
+
+
+def test_mod_distance_worked_example():
+    """Supplementary Text 3: p = MEGSYIRK shares 3 b/y ions with q (E*, I*) and
+    6 with r (S*, Y*); Mod Distance 2 - a/max(len) = 1.625 and 1.25.
+
+    The shared-ion counts come out of the oracle's full search path: the
+    noise-free theoretical spectrum of p searched at T = 0 against a database
+    holding p's modified forms."""
+    p = "MEGSYIRK"
+    mods = [ModSpec("EI", 16_000_000), ModSpec("SY", 80_000_000)]
+    db = _db([p], missed=1, min_len=8, max_len=8, mods=mods, max_mods=2)
+    tab = db.table()
+    b, y = oracle.ions(np.array([bf.RES_UDA[c] for c in p], np.int64))
+    peaks = [(m * 1e-6, 10.0) for m in np.concatenate([b, y])]
+    mass_p = int(sum(bf.RES_UDA[c] for c in p) + bf.WATER_UDA)
+    sp = _spectra([peaks], [(mass_p + bf.PROTON_UDA) * 1e-6], [1])
+    ids, nb, ny, sq = db.scored(sp, 0, False, 10**12, 0, 1000, min_shared=1)
+    counts = {}
+    for i, a, c in zip(ids, nb, ny):
+        start, ln, mask = tab[i]["start"], tab[i]["len"], tab[i]["mask"]
+        counts[int(mask)] = int(a) + int(c)
+    # sites of MEGSYIRK in bit order: E(2)->bit0, S(4)->bit1, Y(5)->bit2, I(6)->bit3
+    mask_q = (1 << 0) | (1 << 3)
+    mask_r = (1 << 1) | (1 << 2)
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "mod_distance_example.txt"))
+            if l.strip() and not l.startswith("#") and not l.startswith("peptide")]
+    expect = {r[0]: (int(r[3]), float(r[5])) for r in rows}
+    assert counts[mask_q] == expect["q"][0] == 3
+    assert counts[mask_r] == expect["r"][0] == 6
+    assert 2 - counts[mask_q] / len(p) == pytest.approx(expect["q"][1])
+    assert 2 - counts[mask_r] / len(p) == pytest.approx(expect["r"][1])
+    assert counts[0] == 2 * (len(p) - 1)       # p against itself: every b and y ion
+
+
+# --------------------------------------------------------------------------
+# Database generation: brute force and combinatorics.
+# --------------------------------------------------------------------------
+
+HAND_PROTEINS = ["MKPAKRPGGKKAAR", "AAAAKAAAAARPAAAAKPAAAAR", "GGGGGGGK", "KRKRKRPK",
+                 "MSTYMNQKAAMSSRLLLLLLK", "PEPTIDEKMSTYR"]
+
+
+@pytest.mark.parametrize("missed,min_len,max_len", [(0, 1 + 1, 40), (1, 2, 40), (2, 3, 10), (3, 5, 12)])
+def test_digestion_matches_substring_bruteforce(missed, min_len, max_len):
+    prot = synth.make_proteome(8, seed=11, len_lo=20, len_hi=60)
+    proteins = HAND_PROTEINS + [p.decode() for p in prot.as_list()]
+    db = _db(proteins, missed=missed, min_len=min_len, max_len=max_len)
+    tab = db.table()
+    got = sorted(set((int(r["prot"]), int(r["start"]), int(r["len"])) for r in tab))
+    want = sorted((p, s, ln) for p, seq in enumerate(proteins) for s, ln in bf.digest(seq, missed, min_len, max_len))
+    assert got == want
+    assert len(tab) == len(want)           # no modifications: one entry per peptide
+
+
+def test_variant_counts_are_binomial_sums():
+    """Each peptide with s sites appears sum_{j<=m} C(s, j) times (D = zeta * 2^m model)."""
+    proteins = HAND_PROTEINS + ["MSSTTYYMK", "STYSTYSTYSTYR"]
+    mods = [ModSpec("M", 15_994_915), ModSpec("STY", 79_966_331), ModSpec("", 42_010_565, nterm=True)]
+    for max_mods in (0, 1, 2, 3):
+        db = _db(proteins, missed=1, min_len=2, max_len=30, mods=mods, max_mods=max_mods)
+        tab = db.table()
+        groups = {}
+        for r in tab:
+            groups.setdefault((int(r["prot"]), int(r["start"]), int(r["len"])), []).append(int(r["mask"]))
+        for (p, s, ln), masks in groups.items():
+            seq = proteins[p][s:s + ln]
+            n_sites = sum(c in "MSTY" for c in seq) + (1 if s == 0 else 0)
+            assert len(masks) == sum(math.comb(n_sites, j) for j in range(min(max_mods, n_sites) + 1))
+            assert len(set(masks)) == len(masks)
+            assert all(bin(m).count("1") <= max_mods for m in masks)
+
+
+def test_database_matches_python_bruteforce_with_mods():
+    proteins = ["MSTYMNQKAAMSSRLLLLLLK", "PEPTIDEKMSTYRNQ", "ACDEFGHIKLMNPQRSTVWY"]
+    mods_o = [ModSpec("M", 15_994_915), ModSpec("STY", 79_966_331), ModSpec("", 42_010_565, nterm=True),
+              ModSpec("NQ", 984_016)]
+    db = _db(proteins, missed=2, min_len=3, max_len=20, mods=mods_o, max_mods=2)
+    rows = bf.database(proteins, 2, 3, 20, mods_o, 2)
+    tab = db.table()
+    assert len(tab) == len(rows)
+    for i, r in enumerate(rows):
+        assert (int(tab[i]["mass"]), int(tab[i]["prot"]), int(tab[i]["start"]), int(tab[i]["len"]),
+                int(tab[i]["mask"])) == r[:5]
+        assert list(db.residue_masses(i)) == r[5]
+
+
+# --------------------------------------------------------------------------
+# Scoring and statistics: closed forms and independent library routines.
+# --------------------------------------------------------------------------
+
+def test_hyperscore_closed_form():
+    assert oracle.hyperscore(2, 3, 100) == pytest.approx(3.0791812460476247, rel=1e-15, abs=0)
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        nb, ny, s = int(rng.integers(0, 60)), int(rng.integers(0, 60)), int(rng.integers(1, 20000))
+        assert oracle.hyperscore(nb, ny, s) == pytest.approx(bf.hyperscore(nb, ny, s), rel=1e-13)
+
+
+def test_savitzky_golay_matches_scipy_and_keeps_quadratics():
+    from scipy.signal import savgol_coeffs, savgol_filter
+    assert np.allclose(savgol_coeffs(5, 2) * 35.0, [-3, 12, 17, 12, -3])
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        h = rng.integers(0, 1000, size=512).astype(np.int32)
+        h[rng.random(512) < 0.3] = 0
+        want = savgol_filter(h.astype(np.float64), 5, 2, mode="constant", cval=0.0)
+        want = np.where(want < 0, 0.0, want)
+        assert np.allclose(oracle.sg_smooth(h), want, rtol=1e-12, atol=1e-9)
+    j = np.arange(512, dtype=np.int64)
+    quad = (3 * (j - 200) ** 2 + 7 * j + 11).astype(np.int32)
+    sm = oracle.sg_smooth(quad)
+    assert np.array_equal(sm[2:-2], quad[2:-2].astype(np.float64))
+
+
+def test_evalue_matches_numpy_pipeline():
+    rng = np.random.default_rng(5)
+    checked = 0
+    for _ in range(200):
+        h = np.zeros(512, np.int32)
+        n = int(rng.integers(5, 5000))
+        scores = rng.gumbel(2.5, 0.4, size=n)
+        top = float(scores.max() + rng.uniform(0, 3))
+        for s in list(scores) + [top]:
+            h[min(511, int(math.floor(10.0 * s)))] += 1
+        st, ev, w, b, npts = oracle.evalue(h, top, n + 1)
+        st2, ev2 = bf.evalue_numpy(h, top, n + 1)
+        assert st == st2
+        if st == 0:
+            assert ev == pytest.approx(ev2, rel=1e-9)
+            checked += 1
+    assert checked > 100
+
+
+def test_evalue_special_cases():
+    h = np.zeros(512, np.int32)
+    assert oracle.evalue(h, 0.0, 0)[0] == 1               # nothing scored
+    h[40] = 1
+    assert oracle.evalue(h, 4.05, 1)[0] == 2              # top bin is the mode: no tail points
+    h = np.zeros(512, np.int32)
+    h[10:20] = np.arange(1, 11)                            # rising histogram up to the top hit
+    st = oracle.evalue(h, 1.95, int(h.sum()))[0]
+    assert st in (2, 3)
+
+
+def test_evalue_geometric_tail_recovers_decay_rate():
+    """A histogram halving every bin has survival ~ 2^-j, so the fitted slope is
+    log10(1/2) / 0.1 = -3.0103 per hyperscore unit (up to the clipped first
+    bins), and the fit equals an independent least-squares fit of the same points."""
+    h = np.array([2 ** (30 - j) if j <= 30 else 0 for j in range(512)], dtype=np.int64).astype(np.int32)
+    top_h = 1.65                                  # bin 16 -> fit bins mode..15
+    st, ev, w, b, npts = oracle.evalue(h, top_h, 1000)
+    assert st == 0
+    assert w == pytest.approx(math.log10(0.5) / 0.1, rel=0.03)
+    kern = np.array([-3, 12, 17, 12, -3], np.int64)
+    num = np.convolve(h.astype(np.int64), kern, mode="same")
+    hs = np.where(num < 0, 0, num) / 35.0
+    mode = int(np.argmax(hs))
+    tail = np.cumsum(hs[::-1])[::-1] / hs.sum()
+    xs = 0.1 * np.arange(mode, 16)
+    wf, bf_ = np.polyfit(xs, np.log10(tail[mode:16]), 1)
+    assert npts == len(xs)
+    assert w == pytest.approx(wf, rel=1e-9) and b == pytest.approx(bf_, rel=1e-9)
+    assert ev == pytest.approx(1000 * 10 ** (wf * top_h + bf_), rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Search: brute force on tiny inputs, invariances, self-search.
+# --------------------------------------------------------------------------
+
+def _tiny_case(seed, mods, max_mods, z_choices=(1, 2, 3, 4), n_spec=12, noise_peaks=(3, 15)):
+    rng = np.random.default_rng(seed)
+    prot = synth.make_proteome(4, seed=seed, len_lo=30, len_hi=70)
+    proteins = [p.decode() for p in prot.as_list()]
+    rows = bf.database(proteins, 1, 4, 25, mods, max_mods)
+    peak_lists, prec, charges = [], [], []
+    for s in range(n_spec):
+        z = int(rng.choice(z_choices))
+        src = rows[int(rng.integers(0, len(rows)))]
+        r = src[5]
+        L = len(r)
+        ions = [sum(r[:i]) + bf.PROTON_UDA for i in range(1, L)] + \
+               [sum(r[L - i:]) + bf.WATER_UDA + bf.PROTON_UDA for i in range(1, L)]
+        pl = [(float(m) * 1e-6 + rng.normal(0, 0.004), float(rng.lognormal())) for m in ions if rng.random() < 0.7]
+        if z >= 3:
+            pl += [((float(m) * 1e-6 + 1.007276) / 2, float(rng.lognormal())) for m in ions if rng.random() < 0.5]
+        pl += [(float(rng.uniform(100, 2000)), float(rng.lognormal())) for _ in range(int(rng.integers(*noise_peaks)))]
+        if s % 5 == 3 and pl:                    # exact duplicate peaks and intensity ties
+            pl += [pl[0], (pl[1][0] + 0.001, pl[1][1])] if len(pl) > 1 else [pl[0]]
+        if s % 7 == 6:
+            pl = []                               # empty spectrum
+        peak_lists.append(pl)
+        prec.append((src[0] * 1e-6 + z * 1.007276) / z)
+        charges.append(z)
+    res = np.frombuffer("".join(proteins).encode(), dtype=np.uint8)
+    off = np.zeros(len(proteins) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in proteins])
+    db = oracle.Database(res, off, 1, 4, 25, list(mods), max_mods)
+    return db, rows, _spectra(peak_lists, prec, charges)
+
+
+@pytest.mark.parametrize("seed,window_is_ppm,window,T,top_b,kmin", [
+    (0, False, 300_000_000, 1, 100, 1),
+    (1, False, 50_000_000, 2, 20, 3),
+    (2, True, 20, 2, 100, 1),
+    (3, False, 10**12, 0, 7, 2),
+])
+def test_search_matches_python_bruteforce(seed, window_is_ppm, window, T, top_b, kmin):
+    mods = [ModSpec("M", 15_994_915), ModSpec("STY", 79_966_331), ModSpec("", 42_010_565, nterm=True)]
+    db, rows, sp = _tiny_case(seed, mods, 2)
+    assert len(db) == len(rows)
+    top_k = 5
+    hits, stats, hist = db.search(sp, window_is_ppm, window, T, top_b, top_k, kmin, threads=3)
+    for s in range(sp.n):
+        a, b = int(sp.peak_off[s]), int(sp.peak_off[s + 1])
+        want = bf.search(rows, sp.mz[a:b], sp.intensity[a:b], sp.precursor_mz[s], int(sp.charge[s]),
+                         window_is_ppm, window, T, top_b, top_k, kmin)
+        st = stats[s]
+        assert int(st["n_window"]) == want["n_window"]
+        if want["n_window"]:
+            assert (int(st["lo"]), int(st["hi"])) == (want["lo"], want["hi"])
+        assert int(st["n_scored"]) == len(want["scored"])
+        assert int(st["pairs_total"]) == want["pairs_total"]
+        assert np.array_equal(hist[s].astype(np.int64), want["hist"])
+        for j in range(top_k):
+            h = hits[s, j]
+            if j < len(want["top"]):
+                pid, (nb, ny, sq, hh) = want["top"][j]
+                assert (int(h["id"]), int(h["n_b"]), int(h["n_y"]), int(h["sum_q"])) == (pid, nb, ny, sq)
+                assert float(h["hyperscore"]) == pytest.approx(hh, rel=1e-12)
+            else:
+                assert int(h["id"]) == 0xFFFFFFFF and h["hyperscore"] == -np.inf
+        assert int(st["status"]) == want["status"]
+        if want["status"] == 0:
+            assert float(st["evalue"]) == pytest.approx(want["evalue"], rel=1e-9)
+        # full scored set
+        ids, nb, ny, sq = db.scored(sp, s, window_is_ppm, window, T, top_b, min_shared=kmin)
+        got = {int(i): (int(x), int(y), int(q)) for i, x, y, q in zip(ids, nb, ny, sq)}
+        assert got == {k: v[:3] for k, v in want["scored"].items()}
+
+
+def _same(a, b):
+    """Bitwise equality of result arrays (NaN e-values compare equal)."""
+    a, b = np.ascontiguousarray(a), np.ascontiguousarray(b)
+    return a.dtype == b.dtype and a.shape == b.shape and a.tobytes() == b.tobytes()
+
+
+def test_search_invariant_under_permutations_and_splits():
+    w = synth.workload("tiny")
+    prot = synth.make_proteome(120, seed=0)
+    sp = w.spectra(prot, n=60, seed=9)
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, [], 0)
+    args = (True, 10, 2, 100, 5, 4)
+    h0, s0, g0 = db.search(sp, *args, threads=4)
+    rng = np.random.default_rng(1)
+    # permute peaks within each spectrum
+    mz, it = sp.mz.copy(), sp.intensity.copy()
+    for s in range(sp.n):
+        a, b = int(sp.peak_off[s]), int(sp.peak_off[s + 1])
+        p = rng.permutation(b - a) + a
+        mz[a:b], it[a:b] = sp.mz[p], sp.intensity[p]
+    sp2 = synth.Spectra(sp.peak_off, mz, it, sp.precursor_mz, sp.charge)
+    h1, s1, g1 = db.search(sp2, *args, threads=2)
+    assert _same(h0, h1) and _same(s0, s1) and _same(g0, g1)
+    # permute spectra within the batch
+    perm = rng.permutation(sp.n)
+    h2, s2, g2 = db.search(sp.subset(perm), *args, threads=1)
+    assert _same(h0[perm], h2) and _same(s0[perm], s2) and _same(g0[perm], g2)
+    # split the batch in two
+    ha, sa, ga = db.search(sp.subset(np.arange(0, 25)), *args)
+    hb, sb, gb = db.search(sp.subset(np.arange(25, sp.n)), *args)
+    assert _same(np.concatenate([ha, hb]), h0) and _same(np.concatenate([sa, sb]), s0)
+
+
+def test_self_search_finds_source_peptide():
+    """A noise-free theoretical spectrum of p shares every b/y ion with p
+    (pairs >= 2(n-1)), and p ranks first unless an isobaric twin with a lower id
+    ties it.  T = 1 bin, because float32 m/z moves a peak by up to ~60 uDa and can
+    cross a bin edge."""
+    prot = synth.make_proteome(40, seed=21)
+    mods = oracle.mods_from_synth([synth.OXIDATION])
+    db = oracle.Database(prot.residues, prot.offsets, 1, 7, 25, mods, 1)
+    rng = np.random.default_rng(2)
+    pids = [int(x) for x in rng.integers(0, len(db), size=25)]
+    peak_lists, prec = [], []
+    for pid in pids:
+        b, y = oracle.ions(db.residue_masses(pid))
+        peak_lists.append([(float(m) * 1e-6, 1.0 + (i % 7)) for i, m in enumerate(np.concatenate([b, y]))])
+        prec.append((db.get(pid)[0] + 2 * bf.PROTON_UDA) * 1e-6 / 2)
+    sp = _spectra(peak_lists, prec, [2] * len(pids))
+    hits, stats, _ = db.search(sp, False, 5_000_000, 1, 1000, 5, 1)
+    for s, pid in enumerate(pids):
+        n = db.get(pid)[3]
+        ids, nb, ny, _ = db.scored(sp, s, False, 5_000_000, 1, 1000, min_shared=1)
+        k = list(ids).index(pid)
+        assert int(nb[k]) + int(ny[k]) >= 2 * (n - 1)
+        top = hits[s, 0]
+        if int(top["id"]) != pid:
+            # only a lower-id candidate with an equal or better score may outrank p
+            mine = [j for j in range(5) if int(hits[s, j]["id"]) == pid]
+            assert int(top["id"]) < pid and (not mine or hits[s, mine[0]]["hyperscore"] == top["hyperscore"])
+
+
+def test_oracle_rejects_invalid_inputs():
+    db = _db(["PEPTIDEKAAR"], missed=1, min_len=3, max_len=20)
+    good = _spectra([[(300.0, 1.0)]], [500.0], [2])
+    with pytest.raises(ValueError):
+        db.search(good, False, 1, 1, 10, 0, 1)          # top_k = 0
+    with pytest.raises(ValueError):
+        db.search(good, False, 1, 1, 10, 5, 0)          # k_min = 0
+    bad = _spectra([[(float("nan"), 1.0)]], [500.0], [2])
+    with pytest.raises(ValueError):
+        db.search(bad, False, 1, 1, 10, 5, 1)
+    bad = _spectra([[(300.0, 1.0)]], [500.0], [0])
+    with pytest.raises(ValueError):
+        db.search(bad, False, 1, 1, 10, 5, 1)
+    with pytest.raises(ValueError):
+        _db(["PEPTIDEXK"])                               # non-standard residue
