@@ -1,0 +1,234 @@
+/*
+ * pepscan.h -- C ABI of the MI355X open-search library.
+ *
+ * The library searches MS/MS spectra against a fragment-ion index of a
+ * digested, modified protein database, as the partial database search of
+ * HiCOPS (arXiv 2102.02286, Superstep 3, Supplementary Algorithm 3) plus the
+ * per-spectrum statistics of Superstep 4 (Supplementary Algorithm 4):
+ *
+ *   precursor-mass window  ->  per-peak fragment-bin postings  ->  shared-peak
+ *   counts and intensity sums per candidate  ->  hyperscore  ->  top-k  ->
+ *   score histogram  ->  smoothed survival function, tail fit, expect value.
+ *
+ * Every step after the index build runs in HIP kernels on one gfx950 GPU.
+ * The index is built on the host (Superstep 1, Supplementary Algorithm 1) and
+ * then lives in device memory the caller provides.
+ *
+ * Conventions (all entry points):
+ *   - Return codes: PS_OK (0) or one of PS_E*.  Nothing throws across the ABI.
+ *     ps_last_error() gives a thread-local message for the last failure.
+ *   - Masses are integer micro-Dalton (uDa, 1e-6 Da) unless a name says
+ *     otherwise.  Fragment bins are 0.01 Da (10000 uDa) wide, rounded half up:
+ *     bin(m) = floor((m + 5000) / 10000).
+ *   - Device memory: the library never allocates device memory.  Every device
+ *     buffer lives inside a caller-provided block (ps_device.base/bytes); the
+ *     caller keeps it alive while any object built in it is in use.
+ *   - Streams: work is enqueued on ps_device.stream (a hipStream_t, NULL = the
+ *     null stream).  Calls are asynchronous unless a comment says "blocks".
+ *   - Thread safety: an index is immutable after build and may be shared by
+ *     concurrent searches; a batch or a server handle is used by one thread
+ *     at a time unless stated.
+ */
+#ifndef PEPSCAN_H
+#define PEPSCAN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define PS_OK        0
+#define PS_EINVAL    1   /* invalid argument; nothing was enqueued */
+#define PS_ENOMEM    2   /* the caller's device block (or host memory) is too small */
+#define PS_EAGAIN    3   /* admission refused for now (serving); retry later */
+#define PS_EDEVICE   4   /* HIP error, or no usable gfx950 device */
+#define PS_EOVERFLOW 5   /* a counter or table bound was exceeded (never silently saturated) */
+
+/* ---- per-spectrum status (ps_stat.status) ------------------------------ */
+#define PS_STATUS_OK          0  /* expect value computed */
+#define PS_STATUS_NO_HITS     1  /* no candidate reached min_shared shared peaks */
+#define PS_STATUS_FEW_POINTS  2  /* tail fit had fewer than 3 points (expect value NaN) */
+#define PS_STATUS_BAD_SLOPE   3  /* fitted survival slope >= 0 (expect value NaN) */
+#define PS_STATUS_INVALID     4  /* invalid spectrum (charge, peaks, precursor or limits) */
+#define PS_STATUS_OVERFLOW    5  /* a shared-peak counter bound was exceeded */
+
+#define PS_HIST_BINS 512         /* score histogram: 512 x int32 = 2048 bytes per spectrum */
+#define PS_MAX_TOP_K 16
+#define PS_MAX_TOP_PEAKS 256
+#define PS_MAX_CHARGE 8
+#define PS_MAX_FRAG_TOL_BINS 4
+#define PS_MAX_PEAKS_IN 4096     /* input peaks per spectrum before top-B selection */
+#define PS_MAX_SEGMENTS 2048     /* top_peaks * max(1, z-1) * (2T+1) per spectrum */
+
+#define PS_SCHED_PLAIN      0    /* one workgroup per spectrum, separate launches */
+#define PS_SCHED_PERSISTENT 1    /* one persistent work-queue launch (hipGraph) */
+
+typedef struct ps_index  ps_index;
+typedef struct ps_batch  ps_batch;
+typedef struct ps_server ps_server;
+
+/* A caller-owned block of device memory and the stream to work on. */
+typedef struct {
+    void*    base;        /* device pointer, 256-byte aligned */
+    uint64_t bytes;
+    void*    stream;      /* hipStream_t; NULL = null stream */
+} ps_device;
+
+/* A variable modification (Experimental Setup: "the number and type of PTMs
+ * ... were varied").  Each residue letter may appear in at most one mod, and at
+ * most one mod may be an N-terminal one; each site carries at most one mod. */
+typedef struct {
+    const char* residues;      /* letters it may sit on, e.g. "STY"; ignored when nterm */
+    int32_t     nterm;         /* 1: protein N-terminus only */
+    int32_t     pad;
+    int64_t     delta_udalton; /* mass shift, uDa */
+} ps_mod;
+
+/* In-silico digestion (Experimental Setup: trypsin, missed cleavages, length
+ * range).  Trypsin cuts after K or R unless the next residue is P. */
+typedef struct {
+    uint32_t      missed_cleavages;
+    uint32_t      min_len, max_len;   /* 2 <= min_len <= max_len <= 62 */
+    uint32_t      n_mods;             /* <= 16 */
+    uint32_t      max_mods;           /* modified sites per peptide */
+    uint32_t      pad;
+    const ps_mod* mods;
+} ps_db_params;
+
+/* A batch of spectra in CSR form (host or device pointers, see each call).
+ * Spectrum i has peaks [peak_off[i], peak_off[i+1]); m/z and intensity are
+ * float32, the precursor m/z float64, the precursor charge int8 in [1, 8]. */
+typedef struct {
+    uint64_t        n;
+    const uint64_t* peak_off;      /* n + 1 */
+    const float*    mz;
+    const float*    intensity;
+    const double*   precursor_mz;
+    const int8_t*   charge;
+} ps_spectra;
+
+typedef struct {
+    int32_t  window_is_ppm;   /* 1: `window` in ppm of the precursor mass; 0: uDa */
+    int32_t  frag_tol_bins;   /* T: a peak matches an ion when |bin difference| <= T */
+    int64_t  window;          /* precursor tolerance: |M_pep - M_q| <= window (inclusive) */
+    uint32_t top_peaks;       /* B most intense peaks kept per spectrum */
+    uint32_t top_k;           /* hits reported per spectrum, 1..PS_MAX_TOP_K */
+    uint32_t min_shared;      /* k_min: candidates need >= k_min shared peaks to be scored */
+    uint32_t max_charge;      /* largest precursor charge in the batch, 1..PS_MAX_CHARGE; sizes
+                                 the workspace (fragment charges 1..max(1, z-1) per spectrum) */
+    int32_t  schedule;        /* PS_SCHED_PLAIN or PS_SCHED_PERSISTENT */
+    int32_t  want_hist;       /* 1: keep per-spectrum histograms for ps_results */
+} ps_search_params;
+
+/* One reported candidate.  id = rank of the peptide in the index's sort order
+ * (mass, protein, start, length, site mask).  Empty slots: id = UINT32_MAX,
+ * hyperscore = -inf. */
+typedef struct {
+    uint32_t id;
+    uint16_t n_b, n_y;        /* shared b- and y-ion pairs */
+    uint32_t sum_q;           /* sum of matched peak intensities (integer 1..100 scale) */
+    uint32_t pad;
+    double   hyperscore;      /* log10(n_b! * n_y! * sum_q) */
+} ps_hit;
+
+typedef struct {
+    uint64_t n_window;        /* candidates in the precursor window */
+    uint64_t n_scored;        /* candidates with >= min_shared shared peaks */
+    double   evalue;          /* expect value of the top hit, NaN unless status == OK */
+    int32_t  status;          /* PS_STATUS_* */
+    int32_t  pad;
+} ps_stat;
+
+/* ---- errors ------------------------------------------------------------ */
+const char* ps_last_error(void);
+
+/* ---- index ------------------------------------------------------------- */
+
+/* Digest the proteins (residues concatenated, protein i = residues[prot_off[i],
+ * prot_off[i+1])), enumerate modified forms, sort them by (mass, protein,
+ * start, length, site mask) and build the CSR fragment-ion index (b/y ions at
+ * charge 1) in host memory (Superstep 1; Supplementary Algorithm 1).  Inputs
+ * are copied; the caller keeps ownership.  Only the 20 standard residue letters
+ * are accepted (PS_EINVAL otherwise).  Needs no GPU. */
+int ps_index_create(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                    uint64_t n_proteins, ps_index** out);
+
+/* Device bytes the index needs (masses, bin offsets, postings, score tables). */
+int ps_index_device_bytes(const ps_index* idx, uint64_t* bytes);
+
+/* Copy the index into dev->base (which must hold ps_index_device_bytes) on
+ * dev->stream.  Blocks until the copy is done.  PS_ENOMEM if the block is too
+ * small; PS_EDEVICE without a usable device. */
+int ps_index_upload(ps_index* idx, const ps_device* dev);
+
+/* ps_index_create + ps_index_upload. */
+int ps_build_index(const ps_device* dev, const ps_db_params* params, const char* residues,
+                   const uint64_t* prot_off, uint64_t n_proteins, ps_index** out);
+
+/* Sizes: peptides (database entries), postings, fragment bins. */
+int ps_index_shape(const ps_index* idx, uint64_t* n_peptides, uint64_t* n_postings, uint64_t* n_bins);
+
+/* Entry `id`: mass (uDa), protein, start, length, site mask.  Mask bit i is
+ * the i-th modifiable site, the protein N-terminus first, then residues by
+ * position. */
+int ps_index_entry(const ps_index* idx, uint64_t id, int64_t* mass, uint32_t* protein,
+                   uint32_t* start, uint32_t* length, uint64_t* site_mask);
+
+/* Peptide string with modifications, e.g. "PEPT[+79.966331]IDEK"; PS_ENOMEM
+ * if cap is too small (the string is truncated and NUL-terminated). */
+int ps_peptide(const ps_index* idx, uint32_t id, char* buf, size_t cap);
+
+/* Host copy of the CSR index, for checks: bin_off[n_bins + 1], postings[n]
+ * (value = id << 1 | is_y, sorted within each bin). Either pointer may be NULL. */
+int ps_index_host_arrays(const ps_index* idx, uint64_t* bin_off, uint32_t* postings);
+
+void ps_index_free(ps_index* idx);
+
+/* ---- one batch --------------------------------------------------------- */
+
+/* Device bytes a batch of n spectra with nnz peaks needs in its workspace,
+ * including a copy of the inputs. */
+int ps_workspace_bytes(const ps_index* idx, uint64_t n, uint64_t nnz, const ps_search_params* params,
+                       uint64_t* bytes);
+
+/* Search host spectra.  Validates them (PS_EINVAL on any invalid spectrum or
+ * parameter), copies them into `work` (which must hold ps_workspace_bytes) and
+ * enqueues the whole search on work->stream; returns without waiting. */
+int ps_search_batch(ps_index* idx, const ps_device* work, const ps_spectra* spectra,
+                    const ps_search_params* params, ps_batch** out);
+
+/* Search spectra already in device memory (every pointer of `spectra` is a
+ * device pointer).  Invalid spectra are reported per spectrum
+ * (PS_STATUS_INVALID) instead of rejected.  Enqueues on work->stream and
+ * returns without waiting; the inputs must stay valid until ps_results. */
+int ps_search_device(ps_index* idx, const ps_device* work, const ps_spectra* spectra,
+                     uint64_t nnz, const ps_search_params* params, ps_batch** out);
+
+/* Blocks until the batch is done, then writes hits[n * top_k], stats[n] and,
+ * when the batch was made with want_hist, hist[n * 512] (hist may be NULL).
+ * Returns PS_EOVERFLOW if any spectrum has PS_STATUS_OVERFLOW (results for the
+ * other spectra are still written). */
+int ps_results(ps_batch* batch, ps_hit* hits, ps_stat* stats, int32_t* hist);
+
+/* Every scored candidate (>= min_shared shared peaks) of every spectrum of a
+ * finished batch, as (spectrum, id, packed counts).  Only for batches searched
+ * with PS_SCHED_PLAIN and `dump` support (ps_search_dump); for parity checks. */
+int ps_search_dump(ps_index* idx, const ps_device* work, const ps_spectra* spectra,
+                   const ps_search_params* params, uint64_t cap, uint32_t* spectrum,
+                   uint32_t* id, uint16_t* n_b, uint16_t* n_y, uint32_t* sum_q, uint64_t* count);
+
+/* Device time of the last batch's dominant kernel (the posting scan), measured
+ * with HIP events on the batch's stream: total milliseconds and launches.  Also
+ * the number of postings it streamed (= sum over window candidates of shared
+ * pairs) and of fragment-bin lookups it made. */
+int ps_batch_timing(ps_batch* batch, double* scan_ms, uint32_t* scan_launches, uint64_t* postings,
+                    uint64_t* bin_lookups);
+
+void ps_batch_free(ps_batch* batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

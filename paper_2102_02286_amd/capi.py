@@ -1,0 +1,151 @@
+"""ctypes binding of libpepscan.so: the C ABI of include/pepscan.h, same names.
+
+Argument marshalling only.  Every step of the search runs in the library's
+HIP kernels; this module never computes results itself and raises if the
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpepscan.so")
+
+PS_OK, PS_EINVAL, PS_ENOMEM, PS_EAGAIN, PS_EDEVICE, PS_EOVERFLOW = 0, 1, 2, 3, 4, 5
+PS_STATUS_OK, PS_STATUS_NO_HITS, PS_STATUS_FEW_POINTS, PS_STATUS_BAD_SLOPE, PS_STATUS_INVALID, \
+    PS_STATUS_OVERFLOW = 0, 1, 2, 3, 4, 5
+PS_HIST_BINS = 512
+PS_SCHED_PLAIN, PS_SCHED_PERSISTENT = 0, 1
+
+_ERR_NAMES = {1: "PS_EINVAL", 2: "PS_ENOMEM", 3: "PS_EAGAIN", 4: "PS_EDEVICE", 5: "PS_EOVERFLOW"}
+
+
+class PsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ps_device(C.Structure):
+    _fields_ = [("base", C.c_void_p), ("bytes", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class ps_mod(C.Structure):
+    _fields_ = [("residues", C.c_char_p), ("nterm", C.c_int32), ("pad", C.c_int32),
+                ("delta_udalton", C.c_int64)]
+
+
+class ps_db_params(C.Structure):
+    _fields_ = [("missed_cleavages", C.c_uint32), ("min_len", C.c_uint32), ("max_len", C.c_uint32),
+                ("n_mods", C.c_uint32), ("max_mods", C.c_uint32), ("pad", C.c_uint32),
+                ("mods", C.POINTER(ps_mod))]
+
+
+class ps_spectra(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("peak_off", C.c_void_p), ("mz", C.c_void_p), ("intensity", C.c_void_p),
+                ("precursor_mz", C.c_void_p), ("charge", C.c_void_p)]
+
+
+class ps_search_params(C.Structure):
+    _fields_ = [("window_is_ppm", C.c_int32), ("frag_tol_bins", C.c_int32), ("window", C.c_int64),
+                ("top_peaks", C.c_uint32), ("top_k", C.c_uint32), ("min_shared", C.c_uint32),
+                ("max_charge", C.c_uint32), ("schedule", C.c_int32), ("want_hist", C.c_int32)]
+
+
+HIT_DTYPE = np.dtype([("id", "<u4"), ("n_b", "<u2"), ("n_y", "<u2"), ("sum_q", "<u4"), ("pad", "<u4"),
+                      ("hyperscore", "<f8")])
+STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8"), ("status", "<i4"),
+                       ("pad", "<i4")])
+assert HIT_DTYPE.itemsize == 24 and STAT_DTYPE.itemsize == 32
+assert C.sizeof(ps_search_params) == 40
+
+_P = C.c_void_p
+_U64P = C.POINTER(C.c_uint64)
+
+# (name, restype, argtypes) for every function the header declares
+_SIGS = [
+    ("ps_last_error", C.c_char_p, []),
+    ("ps_index_create", C.c_int, [C.POINTER(ps_db_params), _P, _P, C.c_uint64, C.POINTER(_P)]),
+    ("ps_index_device_bytes", C.c_int, [_P, _U64P]),
+    ("ps_index_upload", C.c_int, [_P, C.POINTER(ps_device)]),
+    ("ps_build_index", C.c_int, [C.POINTER(ps_device), C.POINTER(ps_db_params), _P, _P, C.c_uint64,
+                                 C.POINTER(_P)]),
+    ("ps_index_shape", C.c_int, [_P, _U64P, _U64P, _U64P]),
+    ("ps_index_entry", C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
+                                 C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), _U64P]),
+    ("ps_peptide", C.c_int, [_P, C.c_uint32, C.c_char_p, C.c_size_t]),
+    ("ps_index_host_arrays", C.c_int, [_P, _P, _P]),
+    ("ps_index_free", None, [_P]),
+    ("ps_workspace_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
+    ("ps_search_batch", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra),
+                                  C.POINTER(ps_search_params), C.POINTER(_P)]),
+    ("ps_search_device", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra), C.c_uint64,
+                                   C.POINTER(ps_search_params), C.POINTER(_P)]),
+    ("ps_results", C.c_int, [_P, _P, _P, _P]),
+    ("ps_search_dump", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra), C.POINTER(ps_search_params),
+                                 C.c_uint64, _P, _P, _P, _P, _P, _U64P]),
+    ("ps_batch_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint32), _U64P, _U64P]),
+    ("ps_batch_free", None, [_P]),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(the search has no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().ps_last_error().decode(errors="replace")
+
+
+def check(rc: int, what: str = ""):
+    if rc != PS_OK:
+        raise PsError(rc, f"{what}: {last_error()}" if what else last_error())
+    return rc
+
+
+def _fn(name):
+    def call(*args):
+        return getattr(lib(), name)(*args)
+    call.__name__ = name
+    return call
+
+
+# raw entry points, same names as the C ABI
+ps_last_error = _fn("ps_last_error")
+ps_index_create = _fn("ps_index_create")
+ps_index_device_bytes = _fn("ps_index_device_bytes")
+ps_index_upload = _fn("ps_index_upload")
+ps_build_index = _fn("ps_build_index")
+ps_index_shape = _fn("ps_index_shape")
+ps_index_entry = _fn("ps_index_entry")
+ps_peptide = _fn("ps_peptide")
+ps_index_host_arrays = _fn("ps_index_host_arrays")
+ps_index_free = _fn("ps_index_free")
+ps_workspace_bytes = _fn("ps_workspace_bytes")
+ps_search_batch = _fn("ps_search_batch")
+ps_search_device = _fn("ps_search_device")
+ps_results = _fn("ps_results")
+ps_search_dump = _fn("ps_search_dump")
+ps_batch_timing = _fn("ps_batch_timing")
+ps_batch_free = _fn("ps_batch_free")
+
+
+def ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)

@@ -1,0 +1,506 @@
+// index.cpp -- host-side database construction and upload of the fragment-ion index.
+//
+// Superstep 1 of HiCOPS (arXiv 2102.02286; Supplementary Algorithm 1): generate
+// every database entry (tryptic peptides and their modified forms, D = zeta*2^m
+// in the paper's notation), sort them, generate b/y model spectra, and build a
+// fragment-ion index.  The paper uses the CFIR-Index without printing its
+// layout; this one is a CSR over 0.01-Da fragment bins whose postings hold the
+// peptide id (= rank in the sorted entry order) and a b/y bit, sorted by id
+// within each bin, so a precursor window is one contiguous sub-range per bin.
+#include "state.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+
+namespace ps {
+
+static const int64_t kResidueUda[26] = {
+    71037114, -1, 103009185, 115026943, 129042593, 147068414, 57021464, 137058912,   // A..H
+    113084064, -1, 128094963, 113084064, 131040485, 114042927, -1, 97052764,         // I..P
+    128058578, 156101111, 87032028, 101047679, -1, 99068414, 186079313, -1,          // Q..X
+    163063329, -1,                                                                     // Y, Z
+};
+
+int64_t residue_uda(char c) {
+    if (c < 'A' || c > 'Z') return -1;
+    return kResidueUda[c - 'A'];
+}
+
+unsigned worker_threads() {
+    unsigned t = std::thread::hardware_concurrency();
+    if (t == 0) t = 4;
+    return std::min(t, 32u);
+}
+
+template <typename F>
+static void parallel_for(uint64_t n, unsigned threads, F&& f) {
+    if (threads <= 1 || n < 2) { f(0, 0, n); return; }
+    std::vector<std::thread> th;
+    uint64_t chunk = (n + threads - 1) / threads;
+    for (unsigned t = 0; t < threads; ++t) {
+        uint64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([&f, t, a, b] { f(t, a, b); });
+    }
+    for (auto& x : th) x.join();
+}
+
+namespace {
+
+struct PepRec {
+    int64_t mass;
+    uint32_t prot, start;
+    uint32_t len, pad;
+    uint64_t mask;
+};
+
+inline bool key_less(const PepRec& x, const PepRec& y) {
+    if (x.mass != y.mass) return x.mass < y.mass;
+    if (x.prot != y.prot) return x.prot < y.prot;
+    if (x.start != y.start) return x.start < y.start;
+    if (x.len != y.len) return x.len < y.len;
+    return x.mask < y.mask;
+}
+
+// Sort in parallel: sorted chunks, then rounds of pairwise merges.
+void parallel_sort(std::vector<PepRec>& v, unsigned threads) {
+    uint64_t n = v.size();
+    if (threads <= 1 || n < (1u << 16)) { std::sort(v.begin(), v.end(), key_less); return; }
+    std::vector<uint64_t> bounds;
+    for (unsigned t = 0; t <= threads; ++t) bounds.push_back(n * t / threads);
+    parallel_for(threads, threads, [&](unsigned, uint64_t a, uint64_t b) {
+        for (uint64_t t = a; t < b; ++t) std::sort(v.begin() + bounds[t], v.begin() + bounds[t + 1], key_less);
+    });
+    std::vector<PepRec> tmp(n);
+    while (bounds.size() > 2) {
+        std::vector<uint64_t> nb;
+        uint64_t pairs = (bounds.size() - 1) / 2;
+        std::vector<std::thread> th;
+        for (uint64_t p = 0; p < pairs; ++p) {
+            uint64_t a = bounds[2 * p], m = bounds[2 * p + 1], b = bounds[2 * p + 2];
+            th.emplace_back([&, a, m, b] {
+                std::merge(v.begin() + a, v.begin() + m, v.begin() + m, v.begin() + b, tmp.begin() + a, key_less);
+            });
+            nb.push_back(a);
+        }
+        for (auto& x : th) x.join();
+        if ((bounds.size() - 1) % 2) {   // odd chunk out: copy it over
+            uint64_t a = bounds[bounds.size() - 2], b = bounds.back();
+            std::copy(v.begin() + a, v.begin() + b, tmp.begin() + a);
+            nb.push_back(a);
+        }
+        nb.push_back(n);
+        v.swap(tmp);
+        bounds.swap(nb);
+    }
+}
+
+}  // namespace
+
+// Mod lookup: which mod (if any) sits on each residue letter; the N-terminal mod.
+struct ModTable {
+    int res_mod[26];
+    int nterm_mod;
+};
+
+static ModTable mod_table(const ps_index* ix) {
+    ModTable t;
+    for (int i = 0; i < 26; ++i) t.res_mod[i] = -1;
+    t.nterm_mod = -1;
+    for (size_t m = 0; m < ix->mods.size(); ++m) {
+        if (ix->mods[m].nterm) t.nterm_mod = (int)m;
+        else for (int i = 0; i < 26; ++i) if (ix->mods[m].res_mask >> i & 1u) t.res_mod[i] = (int)m;
+    }
+    return t;
+}
+
+// Residue masses of entry `id` with its modifications folded in; returns length.
+static uint32_t entry_residues(const ps_index* ix, const ModTable& mt, uint64_t id, int64_t* r) {
+    const char* s = ix->seq.data() + ix->prot_off[ix->prot[id]] + ix->start[id];
+    uint32_t len = ix->len[id];
+    uint64_t mask = ix->mask[id];
+    uint32_t bit = 0;
+    if (ix->start[id] == 0 && mt.nterm_mod >= 0) {
+        r[0] = 0;   // filled below; the N-terminal site is bit 0
+        if (mask & 1ull) r[0] += ix->mods[mt.nterm_mod].delta;
+        bit = 1;
+    } else {
+        r[0] = 0;
+    }
+    for (uint32_t j = 0; j < len; ++j) {
+        int64_t m = kResidueUda[s[j] - 'A'];
+        int mm = mt.res_mod[s[j] - 'A'];
+        if (mm >= 0) {
+            if (mask >> bit & 1ull) m += ix->mods[mm].delta;
+            ++bit;
+        }
+        if (j == 0) r[0] += m; else r[j] = m;
+    }
+    return len;
+}
+
+int index_build_host(ps_index* ix) {
+    const unsigned T = worker_threads();
+    const ModTable mt = mod_table(ix);
+    const uint64_t n_prot = ix->prot_off.size() - 1;
+
+    // 1. generate entries, per protein, in parallel
+    std::vector<std::vector<PepRec>> parts(T);
+    std::atomic<int> too_many{0};
+    parallel_for(n_prot, T, [&](unsigned t, uint64_t pa, uint64_t pb) {
+        auto& out = parts[t];
+        int64_t site_delta[64];
+        for (uint64_t p = pa; p < pb; ++p) {
+            const char* s = ix->seq.data() + ix->prot_off[p];
+            uint64_t n = ix->prot_off[p + 1] - ix->prot_off[p];
+            for (uint64_t a = 0; a < n; ++a) {
+                if (a != 0 && !is_cut(s, n, a - 1)) continue;
+                uint32_t missed = 0;
+                int64_t base = kWaterUda;
+                for (uint64_t e = a + 1; e <= n; ++e) {
+                    uint64_t len = e - a;
+                    if (len > ix->max_len) break;
+                    base += kResidueUda[s[e - 1] - 'A'];
+                    bool end = (e == n) || is_cut(s, n, e - 1);
+                    if (!end) continue;
+                    if (len >= ix->min_len) {
+                        // sites in mask-bit order
+                        uint32_t ns = 0;
+                        if (a == 0 && mt.nterm_mod >= 0) site_delta[ns++] = ix->mods[mt.nterm_mod].delta;
+                        for (uint64_t j = a; j < e; ++j) {
+                            int mm = mt.res_mod[s[j] - 'A'];
+                            if (mm >= 0) site_delta[ns++] = ix->mods[mm].delta;
+                        }
+                        if (ns > 63) { too_many = 1; continue; }
+                        // all subsets with <= max_mods sites: walk combinations by size
+                        uint32_t kmax = std::min<uint32_t>(ix->max_mods, ns);
+                        for (uint32_t k = 0; k <= kmax; ++k) {
+                            uint32_t idx[64];
+                            for (uint32_t i = 0; i < k; ++i) idx[i] = i;
+                            while (true) {
+                                PepRec r;
+                                r.prot = (uint32_t)p; r.start = (uint32_t)a; r.len = (uint32_t)len; r.pad = 0;
+                                r.mask = 0; r.mass = base;
+                                for (uint32_t i = 0; i < k; ++i) { r.mask |= 1ull << idx[i]; r.mass += site_delta[idx[i]]; }
+                                out.push_back(r);
+                                // next combination
+                                int i = (int)k - 1;
+                                while (i >= 0 && idx[i] == ns - k + (uint32_t)i) --i;
+                                if (i < 0) break;
+                                ++idx[i];
+                                for (uint32_t j = (uint32_t)i + 1; j < k; ++j) idx[j] = idx[j - 1] + 1;
+                            }
+                        }
+                    }
+                    if (e < n && ++missed > ix->missed) break;
+                }
+            }
+        }
+    });
+    if (too_many) return fail(PS_EINVAL, "a peptide has more than 63 modifiable sites");
+    uint64_t D = 0;
+    for (auto& v : parts) D += v.size();
+    if (D >= (1ull << 31)) return fail(PS_EOVERFLOW, "%llu database entries exceed the 2^31 id space",
+                                       (unsigned long long)D);
+    std::vector<PepRec> all;
+    all.reserve(D);
+    for (auto& v : parts) { all.insert(all.end(), v.begin(), v.end()); std::vector<PepRec>().swap(v); }
+
+    // 2. sort by (mass, protein, start, length, mask): id = rank
+    parallel_sort(all, T);
+    ix->mass.resize(D); ix->prot.resize(D); ix->start.resize(D); ix->len.resize(D); ix->mask.resize(D);
+    uint32_t max_len_seen = 0;
+    for (uint64_t i = 0; i < D; ++i) {
+        ix->mass[i] = all[i].mass; ix->prot[i] = all[i].prot; ix->start[i] = all[i].start;
+        ix->len[i] = (uint8_t)all[i].len; ix->mask[i] = all[i].mask;
+        max_len_seen = std::max(max_len_seen, all[i].len);
+    }
+    std::vector<PepRec>().swap(all);
+    ix->max_len_seen = max_len_seen;
+
+    // lightest residue including modification deltas (bounds how many ions of one
+    // peptide can share a tolerance window)
+    int64_t nterm_neg = mt.nterm_mod >= 0 ? std::min<int64_t>(0, ix->mods[mt.nterm_mod].delta) : 0;
+    int64_t minres = INT64_MAX;
+    for (int c = 0; c < 26; ++c) {
+        if (kResidueUda[c] < 0) continue;
+        int64_t m = kResidueUda[c] + nterm_neg;
+        if (mt.res_mod[c] >= 0) m += std::min<int64_t>(0, ix->mods[mt.res_mod[c]].delta);
+        minres = std::min(minres, m);
+    }
+    ix->min_residue = minres;
+
+    // 3. b/y ion bins, two passes: count per (thread chunk, bin), then scatter in id order
+    int64_t max_mass = D ? ix->mass[D - 1] : 0;
+    for (uint64_t i = 0; i < D; ++i) max_mass = std::max(max_mass, ix->mass[i]);
+    uint64_t nbins = (uint64_t)((max_mass + kBinWidth / 2) / kBinWidth) + 2;
+    ix->n_bins = nbins;
+    std::vector<std::vector<uint32_t>> cnt(T);
+    std::atomic<int> bad_mass{0};
+    parallel_for(D, T, [&](unsigned t, uint64_t a, uint64_t b) {
+        auto& c = cnt[t];
+        c.assign(nbins, 0);
+        int64_t r[64];
+        for (uint64_t id = a; id < b; ++id) {
+            uint32_t n = entry_residues(ix, mt, id, r);
+            int64_t pre = 0, suf = 0;
+            for (uint32_t i = 1; i < n; ++i) {
+                pre += r[i - 1];
+                suf += r[n - i];
+                int64_t bm = pre + kProtonUda, ym = suf + kWaterUda + kProtonUda;
+                if (bm < 0 || ym < 0) { bad_mass = 1; continue; }
+                c[(uint64_t)((bm + kBinWidth / 2) / kBinWidth)]++;
+                c[(uint64_t)((ym + kBinWidth / 2) / kBinWidth)]++;
+            }
+        }
+    });
+    if (bad_mass) return fail(PS_EINVAL, "a fragment ion has a negative mass (modification deltas too negative)");
+    ix->bin_off.assign(nbins + 1, 0);
+    uint64_t run = 0;
+    std::vector<std::vector<uint64_t>> pos(T);
+    for (unsigned t = 0; t < T; ++t) pos[t].assign(cnt[t].empty() ? 0 : nbins, 0);
+    for (uint64_t bn = 0; bn < nbins; ++bn) {
+        ix->bin_off[bn] = run;
+        for (unsigned t = 0; t < T; ++t) {
+            if (cnt[t].empty()) continue;
+            pos[t][bn] = run;
+            run += cnt[t][bn];
+        }
+    }
+    ix->bin_off[nbins] = run;
+    for (auto& c : cnt) std::vector<uint32_t>().swap(c);
+    ix->post.resize(run);
+    parallel_for(D, T, [&](unsigned t, uint64_t a, uint64_t b) {
+        auto& p = pos[t];
+        int64_t r[64];
+        for (uint64_t id = a; id < b; ++id) {
+            uint32_t n = entry_residues(ix, mt, id, r);
+            int64_t pre = 0;
+            for (uint32_t i = 1; i < n; ++i) {      // b ions (bit 0) first, then y ions
+                pre += r[i - 1];
+                uint64_t bn = (uint64_t)((pre + kProtonUda + kBinWidth / 2) / kBinWidth);
+                ix->post[p[bn]++] = (uint32_t)(id << 1);
+            }
+            int64_t suf = 0;
+            for (uint32_t i = 1; i < n; ++i) {
+                suf += r[n - i];
+                uint64_t bn = (uint64_t)((suf + kWaterUda + kProtonUda + kBinWidth / 2) / kBinWidth);
+                ix->post[p[bn]++] = (uint32_t)(id << 1 | 1u);
+            }
+        }
+    });
+    // Postings of one id in one bin must be ordered b before y; ions of one id are
+    // emitted b-first, so each bin is non-decreasing in (id << 1 | type).
+    return PS_OK;
+}
+
+// Device layout: [mass][bin_off][post][lf][ls], each 256-byte aligned.
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+uint64_t index_device_layout(const ps_index* ix, uint64_t* off_mass, uint64_t* off_bin, uint64_t* off_post,
+                             uint64_t* off_lf, uint64_t* off_ls) {
+    uint64_t o = 0;
+    *off_mass = o; o = align256(o + ix->mass.size() * sizeof(int64_t));
+    *off_bin = o; o = align256(o + ix->bin_off.size() * sizeof(uint64_t));
+    *off_post = o; o = align256(o + ix->post.size() * sizeof(uint32_t));
+    *off_lf = o; o = align256(o + kLfSize * sizeof(double));
+    *off_ls = o; o = align256(o + kLsSize * sizeof(double));
+    return o;
+}
+
+void score_tables(std::vector<double>& lf, std::vector<double>& ls) {
+    // hyperscore terms: lf[n] = sum_{k=2..n} log10 k accumulated left to right;
+    // ls[s] = log10 s (ls[0] is never used: scored candidates have s >= 1)
+    lf.assign(kLfSize, 0.0);
+    double acc = 0.0;
+    for (uint32_t k = 2; k < kLfSize; ++k) { acc += std::log10((double)k); lf[k] = acc; }
+    ls.assign(kLsSize, 0.0);
+    ls[0] = -INFINITY;
+    for (uint32_t s = 1; s < kLsSize; ++s) ls[s] = std::log10((double)s);
+}
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" int ps_index_create(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                               uint64_t n_proteins, ps_index** out) {
+    if (!out) return fail(PS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || !residues || !prot_off) return fail(PS_EINVAL, "NULL argument");
+    if (params->min_len < 2 || params->max_len < params->min_len || params->max_len > 62)
+        return fail(PS_EINVAL, "peptide lengths must satisfy 2 <= min_len <= max_len <= 62");
+    if (params->n_mods > 16) return fail(PS_EINVAL, "at most 16 modifications");
+    if (params->n_mods && !params->mods) return fail(PS_EINVAL, "mods is NULL");
+    if (prot_off[0] != 0) return fail(PS_EINVAL, "prot_off[0] must be 0");
+    for (uint64_t i = 0; i < n_proteins; ++i)
+        if (prot_off[i + 1] < prot_off[i]) return fail(PS_EINVAL, "prot_off must be non-decreasing");
+    uint64_t total = prot_off[n_proteins];
+    for (uint64_t i = 0; i < total; ++i)
+        if (residue_uda(residues[i]) < 0)
+            return fail(PS_EINVAL, "residue %llu ('%c') is not one of the 20 standard amino acids",
+                        (unsigned long long)i, residues[i]);
+    ps_index* ix = new (std::nothrow) ps_index();
+    if (!ix) return fail(PS_ENOMEM, "out of host memory");
+    ix->missed = params->missed_cleavages;
+    ix->min_len = params->min_len;
+    ix->max_len = params->max_len;
+    ix->max_mods = params->max_mods;
+    uint32_t letters_used = 0;
+    int nterm_count = 0;
+    for (uint32_t m = 0; m < params->n_mods; ++m) {
+        const ps_mod& pm = params->mods[m];
+        ps_index::Mod md;
+        md.nterm = pm.nterm != 0;
+        md.delta = pm.delta_udalton;
+        md.res_mask = 0;
+        if (md.nterm) {
+            ++nterm_count;
+        } else {
+            if (!pm.residues || !pm.residues[0]) { delete ix; return fail(PS_EINVAL, "mod %u has no residues", m); }
+            for (const char* c = pm.residues; *c; ++c) {
+                if (residue_uda(*c) < 0) { delete ix; return fail(PS_EINVAL, "mod %u: bad residue '%c'", m, *c); }
+                md.res_mask |= 1u << (*c - 'A');
+            }
+            if (md.res_mask & letters_used) { delete ix; return fail(PS_EINVAL, "a residue appears in two mods"); }
+            letters_used |= md.res_mask;
+            md.residues = pm.residues;
+        }
+        ix->mods.push_back(md);
+    }
+    if (nterm_count > 1) { delete ix; return fail(PS_EINVAL, "at most one N-terminal mod"); }
+    try {
+        ix->seq.assign(residues, residues + total);
+        ix->prot_off.assign(prot_off, prot_off + n_proteins + 1);
+    } catch (...) { delete ix; return fail(PS_ENOMEM, "out of host memory"); }
+    int rc;
+    try { rc = index_build_host(ix); } catch (...) { rc = fail(PS_ENOMEM, "out of host memory building the index"); }
+    if (rc != PS_OK) { delete ix; return rc; }
+    *out = ix;
+    return PS_OK;
+}
+
+extern "C" int ps_index_device_bytes(const ps_index* ix, uint64_t* bytes) {
+    if (!ix || !bytes) return fail(PS_EINVAL, "NULL argument");
+    uint64_t a, b, c, d, e;
+    *bytes = index_device_layout(ix, &a, &b, &c, &d, &e);
+    return PS_OK;
+}
+
+extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
+    if (!ix || !dev) return fail(PS_EINVAL, "NULL argument");
+    int rc = require_device();
+    if (rc != PS_OK) return rc;
+    if (ix->post.size() >= (1ull << 32))
+        return fail(PS_EOVERFLOW, "index holds %llu postings; this build addresses at most 2^32",
+                    (unsigned long long)ix->post.size());
+    uint64_t om, ob, op, olf, ols;
+    uint64_t need = index_device_layout(ix, &om, &ob, &op, &olf, &ols);
+    if (!dev->base || dev->bytes < need)
+        return fail(PS_ENOMEM, "index needs %llu device bytes, block has %llu", (unsigned long long)need,
+                    (unsigned long long)dev->bytes);
+    if (((uintptr_t)dev->base & 255u) != 0) return fail(PS_EINVAL, "device block must be 256-byte aligned");
+    std::vector<double> lf, ls;
+    score_tables(lf, ls);
+    char* base = (char*)dev->base;
+    hipStream_t st = (hipStream_t)dev->stream;
+    hipError_t e = hipSuccess;
+    auto cp = [&](uint64_t off, const void* src, size_t n) {
+        if (e == hipSuccess && n) e = hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, st);
+    };
+    cp(om, ix->mass.data(), ix->mass.size() * sizeof(int64_t));
+    cp(ob, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
+    cp(op, ix->post.data(), ix->post.size() * sizeof(uint32_t));
+    cp(olf, lf.data(), lf.size() * sizeof(double));
+    cp(ols, ls.data(), ls.size() * sizeof(double));
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
+    DevIndex& d = ix->dev;
+    d.mass = (const int64_t*)(base + om);
+    d.bin_off = (const uint64_t*)(base + ob);
+    d.post = (const uint32_t*)(base + op);
+    d.lf = (const double*)(base + olf);
+    d.ls = (const double*)(base + ols);
+    d.n_pep = ix->mass.size();
+    d.n_bins = ix->n_bins;
+    d.n_post = ix->post.size();
+    d.max_len = ix->max_len_seen;
+    d.min_residue = ix->min_residue;
+    ix->on_device = true;
+    return PS_OK;
+}
+
+extern "C" int ps_build_index(const ps_device* dev, const ps_db_params* params, const char* residues,
+                              const uint64_t* prot_off, uint64_t n_proteins, ps_index** out) {
+    int rc = ps_index_create(params, residues, prot_off, n_proteins, out);
+    if (rc != PS_OK) return rc;
+    rc = ps_index_upload(*out, dev);
+    if (rc != PS_OK) { ps_index_free(*out); *out = nullptr; }
+    return rc;
+}
+
+extern "C" int ps_index_shape(const ps_index* ix, uint64_t* n_pep, uint64_t* n_post, uint64_t* n_bins) {
+    if (!ix) return fail(PS_EINVAL, "NULL index");
+    if (n_pep) *n_pep = ix->mass.size();
+    if (n_post) *n_post = ix->post.size();
+    if (n_bins) *n_bins = ix->n_bins;
+    return PS_OK;
+}
+
+extern "C" int ps_index_entry(const ps_index* ix, uint64_t id, int64_t* mass, uint32_t* protein,
+                              uint32_t* start, uint32_t* length, uint64_t* site_mask) {
+    if (!ix) return fail(PS_EINVAL, "NULL index");
+    if (id >= ix->mass.size()) return fail(PS_EINVAL, "id %llu out of range", (unsigned long long)id);
+    if (mass) *mass = ix->mass[id];
+    if (protein) *protein = ix->prot[id];
+    if (start) *start = ix->start[id];
+    if (length) *length = ix->len[id];
+    if (site_mask) *site_mask = ix->mask[id];
+    return PS_OK;
+}
+
+extern "C" int ps_peptide(const ps_index* ix, uint32_t id, char* buf, size_t cap) {
+    if (!ix || !buf || cap == 0) return fail(PS_EINVAL, "NULL argument");
+    if (id >= ix->mass.size()) return fail(PS_EINVAL, "id %u out of range", id);
+    ModTable mt = mod_table(ix);
+    std::string s;
+    const char* seq = ix->seq.data() + ix->prot_off[ix->prot[id]] + ix->start[id];
+    uint64_t mask = ix->mask[id];
+    uint32_t bit = 0;
+    char tmp[48];
+    if (ix->start[id] == 0 && mt.nterm_mod >= 0) {
+        if (mask & 1ull) {
+            snprintf(tmp, sizeof tmp, "n[%+.6f]", ix->mods[mt.nterm_mod].delta * 1e-6);
+            s += tmp;
+        }
+        bit = 1;
+    }
+    for (uint32_t j = 0; j < ix->len[id]; ++j) {
+        s += seq[j];
+        int mm = mt.res_mod[seq[j] - 'A'];
+        if (mm >= 0) {
+            if (mask >> bit & 1ull) {
+                snprintf(tmp, sizeof tmp, "[%+.6f]", ix->mods[mm].delta * 1e-6);
+                s += tmp;
+            }
+            ++bit;
+        }
+    }
+    size_t n = std::min(cap - 1, s.size());
+    memcpy(buf, s.data(), n);
+    buf[n] = 0;
+    return n < s.size() ? fail(PS_ENOMEM, "buffer too small for peptide string") : PS_OK;
+}
+
+extern "C" int ps_index_host_arrays(const ps_index* ix, uint64_t* bin_off, uint32_t* postings) {
+    if (!ix) return fail(PS_EINVAL, "NULL index");
+    if (bin_off) memcpy(bin_off, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
+    if (postings) memcpy(postings, ix->post.data(), ix->post.size() * sizeof(uint32_t));
+    return PS_OK;
+}
+
+extern "C" void ps_index_free(ps_index* ix) { delete ix; }

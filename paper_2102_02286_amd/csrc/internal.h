@@ -1,0 +1,111 @@
+// internal.h -- shared definitions of the pepscan library (host code and kernels).
+//
+// Not part of the public ABI (include/pepscan.h is).  Units: integer
+// micro-Dalton (uDa) masses; fragment bins of 10000 uDa rounded half up.
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/pepscan.h"
+
+namespace ps {
+
+constexpr int64_t kProtonUda = 1007276;     // H+
+constexpr int64_t kWaterUda = 18010565;     // H2O
+constexpr int64_t kBinWidth = 10000;        // 0.01 Da
+constexpr int kHistBins = PS_HIST_BINS;
+constexpr uint32_t kLfSize = 65536;         // log10(n!) table, n < 65536
+constexpr uint32_t kLsSize = 1u << 20;      // log10(s) table, s < 2^20
+constexpr uint32_t kEntryInvalid = 0xFFFFFFFFu;
+constexpr int kBlock = 256;                 // threads per workgroup for every kernel
+
+// Per-spectrum flags written by the prep kernel.
+enum : uint32_t {
+    kFlagInvalid = 1u,      // spectrum rejected (status PS_STATUS_INVALID)
+    kFlagWide = 2u,         // needs 64-bit shared-peak counters
+    kFlagOverflow = 4u,     // even 64-bit counters / tables cannot hold it
+};
+
+// Device view of an uploaded index.
+struct DevIndex {
+    const int64_t* mass;       // [n_pep], ascending
+    const uint64_t* bin_off;   // [n_bins + 1]
+    const uint32_t* post;      // [n_post], value = id << 1 | is_y, sorted within a bin
+    const double* lf;          // [kLfSize]  lf[n] = sum_{k=2..n} log10 k
+    const double* ls;          // [kLsSize]  ls[s] = log10 s
+    uint64_t n_pep, n_bins, n_post;
+    uint32_t max_len;          // longest peptide (residues)
+    int64_t min_residue;       // lightest residue incl. modification deltas (uDa)
+};
+
+// Per-spectrum summary written by the prep kernel.
+struct SpecInfo {
+    uint32_t lo, hi;           // window as id range [lo, hi)
+    uint32_t n_ent;            // entry slots used (kept peaks x fragment charges)
+    uint32_t flags;
+};
+
+// Inputs of one batch, device pointers.
+struct DevSpectra {
+    const uint64_t* peak_off;
+    const float* mz;
+    const float* inten;
+    const double* prec;
+    const int8_t* charge;
+    uint64_t n;
+    uint64_t nnz;              // length of mz / inten; peak_off entries beyond it are invalid
+};
+
+// Search settings as the kernels see them.
+struct KParams {
+    int64_t window;
+    int32_t window_is_ppm;
+    int32_t tol;               // T
+    uint32_t top_peaks;        // B
+    uint32_t top_k;
+    uint32_t min_shared;
+    uint32_t max_charge;
+    uint32_t ent_stride;       // entry slots per spectrum = top_peaks * max(1, max_charge - 1)
+    uint32_t seg_cap;          // LDS segment slots per workgroup
+    uint32_t tile;             // candidates per LDS counter tile
+    uint32_t heavy_min;        // segments longer than this are scanned cooperatively
+};
+
+// Workspace pointers of one batch (all inside the caller's device block).
+struct Work {
+    uint32_t* entries;         // [n * ent_stride] (bin << 8 | q) or kEntryInvalid
+    SpecInfo* info;            // [n]
+    int32_t* hist;             // [n * 512]
+    unsigned long long* n_scored;  // [n]
+    ps_hit* partial;           // [n_items * top_k]
+    uint32_t* item_spec;       // [n_items] (persistent schedule) spectrum of each item
+    uint32_t* item_t0;         // [n_items] first tile
+    uint32_t* spec_item0;      // [n + 1] first item of each spectrum
+    ps_hit* hits;              // [n * top_k]
+    ps_stat* stats;            // [n]
+    unsigned long long* counters;  // [8]: postings, bin lookups, work-queue head, items total, dump count
+    // optional full dump of scored candidates
+    uint32_t* dump_spec; uint32_t* dump_id; uint32_t* dump_cnt_lo; uint32_t* dump_cnt_hi;
+    uint64_t dump_cap;
+};
+
+enum CounterSlot { kCtrPostings = 0, kCtrLookups = 1, kCtrQueue = 2, kCtrItems = 3, kCtrDump = 4 };
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
+hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t stream);
+hipError_t launch_prep(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
+                       hipStream_t stream);
+hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
+                             bool dump, hipStream_t stream);
+hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& w, uint64_t max_items,
+                           hipStream_t stream);
+hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, const KParams& kp,
+                                  const Work& w, uint32_t grid, uint32_t tiles_per_item,
+                                  hipStream_t stream);
+hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
+                        bool per_item, hipStream_t stream);
+size_t scan_lds_bytes(const KParams& kp, bool wide);
+
+}  // namespace ps

@@ -1,0 +1,750 @@
+// kernels.hip -- the search path on gfx950.
+//
+//   k_prep     spectrum pre-processing (top-B peaks, integer intensities, m/z to
+//              uDa, fragment-charge expansion to bin entries) and the precursor
+//              window (filter_1 of Supplementary Algorithm 3)
+//   k_scan     per work item (spectrum, id range): fragment-bin lookups to
+//              posting segments (filter_2), streaming of postings into LDS
+//              shared-peak counters tile by tile, then per tile the candidate
+//              filter (shared peaks >= k), hyperscore, per-thread top-k and the
+//              LDS score histogram (Supplementary Algorithm 3's score/heap)
+//   k_merge    merge of partial top-k lists, Savitzky-Golay smoothed survival
+//              function, linear tail fit and expect value (Superstep 4;
+//              Supplementary Algorithm 4)
+//
+// Integer work is exact: counters are packed integer fields, the histogram is
+// integer, and hyperscores come from host-built fp64 tables, so results do not
+// depend on atomic order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace ps {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// llround for x >= 0: nearest integer, halves away from zero.
+__device__ __forceinline__ int64_t round_half_up_pos(double x) {
+    double t = trunc(x);
+    return (int64_t)t + ((x - t) >= 0.5 ? 1 : 0);
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t v) {
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// First index in [lo, hi) with a[i] >= v, found by one wavefront: each round
+// the 64 lanes probe evenly spaced positions and a ballot narrows the range
+// 64-fold, so a segment of n postings costs ~log64(n) dependent loads.
+// Must be called by all 64 lanes with identical (lo, hi, v).
+__device__ __forceinline__ uint32_t wave_lower_bound(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t v) {
+    const uint32_t lane = threadIdx.x & 63u;
+    while (hi - lo > 64u) {
+        uint32_t stride = (hi - lo + 63u) >> 6;
+        uint32_t p = lo + lane * stride;
+        bool pred = (p < hi) && (a[p] < v);
+        uint32_t c = (uint32_t)__popcll(__ballot(pred));
+        if (c == 0) return lo;
+        uint32_t nlo = lo + (c - 1u) * stride + 1u;
+        uint32_t nhi = min(hi, lo + c * stride);
+        lo = nlo;
+        hi = nhi;
+    }
+    uint32_t p = lo + lane;
+    bool pred = (p < hi) && (a[p] < v);
+    return lo + (uint32_t)__popcll(__ballot(pred));
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch) {
+    // scratch: kBlock/64 slots
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    T r = 0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kBlock / 64; ++i) r += scratch[i];
+        scratch[0] = r;
+    }
+    __syncthreads();
+    r = scratch[0];
+    __syncthreads();
+    return r;
+}
+
+// Packed shared-peak counters.  Narrow: [n_b:8 | n_y:8 | S:16] in 32 bits;
+// wide: [n_b:16 | n_y:16 | S:32] in 64 bits.  The prep kernel proves per
+// spectrum that no field can overflow before choosing the narrow form.
+template <typename C> struct Cnt;
+template <> struct Cnt<uint32_t> {
+    __device__ static uint32_t inc(uint32_t is_y, uint32_t q) { return (is_y ? (1u << 16) : (1u << 24)) + q; }
+    __device__ static uint32_t nb(uint32_t c) { return c >> 24; }
+    __device__ static uint32_t ny(uint32_t c) { return (c >> 16) & 0xFFu; }
+    __device__ static uint32_t s(uint32_t c) { return c & 0xFFFFu; }
+};
+template <> struct Cnt<unsigned long long> {
+    __device__ static unsigned long long inc(uint32_t is_y, uint32_t q) {
+        return (is_y ? (1ull << 32) : (1ull << 48)) + (unsigned long long)q;
+    }
+    __device__ static uint32_t nb(unsigned long long c) { return (uint32_t)(c >> 48); }
+    __device__ static uint32_t ny(unsigned long long c) { return (uint32_t)(c >> 32) & 0xFFFFu; }
+    __device__ static uint32_t s(unsigned long long c) { return (uint32_t)c; }
+};
+
+// Top-K list held in registers, sorted by (hyperscore desc, id asc).  Entries
+// keep the raw packed counter; n_b, n_y and S are decoded only when written out.
+template <int K, typename C>
+struct TopK {
+    double h[K];
+    uint32_t id[K];
+    C c[K];
+    __device__ void init() {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { h[j] = -INFINITY; id[j] = 0xFFFFFFFFu; c[j] = 0; }
+    }
+    __device__ static bool better(double ha, uint32_t ia, double hb, uint32_t ib) {
+        return ha > hb || (ha == hb && ia < ib);
+    }
+    // Insert by bubbling the newcomer down: after the pass the list holds the K
+    // best of (old list + newcomer), still sorted.
+    __device__ void insert(double hh, uint32_t ii, C cc) {
+        if (!better(hh, ii, h[K - 1], id[K - 1])) return;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (better(hh, ii, h[j], id[j])) {
+                double th = h[j]; uint32_t ti = id[j]; C tc = c[j];
+                h[j] = hh; id[j] = ii; c[j] = cc;
+                hh = th; ii = ti; cc = tc;
+            }
+        }
+    }
+};
+
+// Entry of the LDS merge of per-thread lists (16 bytes narrow, 24 wide).
+template <typename C> struct MergeEnt;
+template <> struct MergeEnt<uint32_t> { double h; uint32_t id; uint32_t c; };
+template <> struct MergeEnt<unsigned long long> { double h; uint32_t id; uint32_t pad; unsigned long long c; };
+
+// ---------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    uint64_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, (uint32_t*)p, value, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// prep: one workgroup per spectrum
+// ---------------------------------------------------------------------------
+
+struct PrepArgs {
+    DevIndex ix;
+    DevSpectra sp;
+    KParams kp;
+    Work w;
+};
+
+__global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
+    __shared__ float s_mz[PS_MAX_PEAKS_IN];
+    __shared__ float s_in[PS_MAX_PEAKS_IN];
+    __shared__ uint32_t s_ent[PS_MAX_TOP_PEAKS * (PS_MAX_CHARGE - 1)];
+    __shared__ uint32_t s_flag, s_imax_bits, s_mult;
+    __shared__ unsigned long long s_red[kBlock / 64];
+    const uint32_t tid = threadIdx.x;
+    const KParams& kp = A.kp;
+
+    for (uint64_t s = blockIdx.x; s < A.sp.n; s += gridDim.x) {
+        const uint64_t p0 = A.sp.peak_off[s], p1 = A.sp.peak_off[s + 1];
+        const int z = A.sp.charge[s];
+        const double prec = A.sp.prec[s];
+        if (tid == 0) {
+            uint32_t bad = 0;
+            if (!(p1 >= p0) || p1 - p0 > PS_MAX_PEAKS_IN || p1 > A.sp.nnz) bad = 1;
+            if (z < 1 || z > (int)kp.max_charge) bad = 1;
+            if (!(prec > 0.0) || !(prec <= 1e6)) bad = 1;   // also rejects NaN
+            s_flag = bad;
+            s_imax_bits = 0;
+            s_mult = 0;
+        }
+        __syncthreads();
+        const uint32_t np = s_flag ? 0u : (uint32_t)(p1 - p0);
+        for (uint32_t i = tid; i < np; i += kBlock) {
+            float m = A.sp.mz[p0 + i], v = A.sp.inten[p0 + i];
+            s_mz[i] = m;
+            s_in[i] = v;
+            if (!(m > 0.0f) || !(m <= 3.0e38f) || !(v >= 0.0f) || !(v <= 3.0e38f)) atomicOr(&s_flag, 1u);
+            else atomicMax(&s_imax_bits, __float_as_uint(v));   // ordered like floats for v >= 0
+        }
+        __syncthreads();
+        const bool bad = s_flag != 0;
+        const float imax = __uint_as_float(s_imax_bits);
+        const uint32_t cmax = z > 2 ? (uint32_t)(z - 1) : 1u;
+        const uint32_t keep = min(np, kp.top_peaks);
+        const uint32_t n_ent = bad ? 0u : keep * cmax;
+        uint32_t* gent = A.w.entries + s * (uint64_t)kp.ent_stride;
+        // top-B by (intensity desc, m/z asc, input order asc): rank = number of better peaks
+        if (!bad) {
+            for (uint32_t i = tid; i < np; i += kBlock) {
+                const float mi = s_mz[i], vi = s_in[i];
+                uint32_t rank = 0;
+                for (uint32_t j = 0; j < np; ++j) {
+                    const float mj = s_mz[j], vj = s_in[j];
+                    rank += (vj > vi) || (vj == vi && (mj < mi || (mj == mi && j < i)));
+                }
+                if (rank >= keep) continue;
+                // integer intensity q in [1, 100] relative to the most intense peak
+                uint32_t q = 1;
+                if (imax > 0.0f) {
+                    double t = (double)vi / (double)imax;
+                    t = t * 100.0;
+                    t = t + 0.5;
+                    t = floor(t);
+                    q = t < 1.0 ? 1u : (t > 100.0 ? 100u : (uint32_t)t);
+                }
+                const double x = (double)mi * 1e6;            // exact: float32 * 10^6 fits in fp64
+                // beyond 2^40 uDa no fragment bin exists: such a peak matches nothing
+                const int64_t mz_uda = x < 1099511627776.0 ? round_half_up_pos(x) : (1ll << 40);
+                for (uint32_t c = 1; c <= cmax; ++c) {
+                    // singly charged equivalent of a fragment at charge c
+                    const int64_t m1 = (int64_t)c * mz_uda - (int64_t)(c - 1) * kProtonUda;
+                    uint32_t e = kEntryInvalid;
+                    if (m1 >= 0 && mz_uda < (1ll << 40)) {
+                        const int64_t b = (m1 + kBinWidth / 2) / kBinWidth;
+                        if (b < (1ll << 24)) e = ((uint32_t)b << 8) | q;
+                    }
+                    s_ent[rank * cmax + (c - 1)] = e;
+                    gent[rank * cmax + (c - 1)] = e;
+                }
+            }
+        }
+        __syncthreads();
+        // counter-width bound: M = most entries within one 2T+1-bin span
+        uint32_t sumq = 0, valid = 0;
+        const uint32_t span = 2u * (uint32_t)kp.tol;
+        for (uint32_t i = tid; i < n_ent; i += kBlock) {
+            const uint32_t ei = s_ent[i];
+            if (ei == kEntryInvalid) continue;
+            ++valid;
+            sumq += ei & 0xFFu;
+            const uint32_t bi = ei >> 8;
+            uint32_t m = 0;
+            for (uint32_t j = 0; j < n_ent; ++j) {
+                const uint32_t ej = s_ent[j];
+                if (ej == kEntryInvalid) continue;
+                const uint32_t bj = ej >> 8;
+                m += (bj >= bi && bj - bi <= span);
+            }
+            atomicMax(&s_mult, m);
+        }
+        const unsigned long long tot = block_sum<unsigned long long>(
+            ((unsigned long long)sumq << 32) | valid, s_red);
+        if (tid == 0) {
+            SpecInfo inf;
+            inf.n_ent = n_ent;
+            inf.flags = bad ? kFlagInvalid : 0u;
+            inf.lo = inf.hi = 0;
+            if (!bad) {
+                const int64_t prec_uda = round_half_up_pos(prec * 1e6);
+                const int64_t mq = (int64_t)z * (prec_uda - kProtonUda);
+                if (mq < 0) {
+                    inf.flags = kFlagInvalid;
+                } else {
+                    const int64_t dm = kp.window_is_ppm ? (mq * kp.window) / 1000000 : kp.window;
+                    // filter_1: ids with |M - M_q| <= dM  ->  [lo, hi)
+                    const int64_t lo_m = mq - dm, hi_m = mq + dm;
+                    uint64_t a = 0, b = A.ix.n_pep;
+                    while (a < b) { uint64_t mid = (a + b) >> 1; if (A.ix.mass[mid] < lo_m) a = mid + 1; else b = mid; }
+                    inf.lo = (uint32_t)a;
+                    b = A.ix.n_pep;
+                    while (a < b) { uint64_t mid = (a + b) >> 1; if (A.ix.mass[mid] <= hi_m) a = mid + 1; else b = mid; }
+                    inf.hi = (uint32_t)a;
+                    // worst-case field values for any candidate of this spectrum
+                    const uint64_t nvalid = tot & 0xFFFFFFFFull, sq = tot >> 32;
+                    const uint64_t width = (uint64_t)(2 * kp.tol + 1) * (uint64_t)kBinWidth;
+                    const uint64_t kpe = A.ix.min_residue > 0 ? (width - 1) / (uint64_t)A.ix.min_residue + 1 : (1ull << 20);
+                    uint64_t nbmax = nvalid * kpe;
+                    const uint64_t by_len = (uint64_t)(A.ix.max_len > 0 ? A.ix.max_len - 1 : 0) * (uint64_t)s_mult;
+                    if (by_len < nbmax) nbmax = by_len;
+                    uint64_t smax = sq * 2ull * kpe;
+                    if (200ull * nbmax < smax) smax = 200ull * nbmax;
+                    if (!(nbmax <= 255 && smax <= 65535)) {
+                        inf.flags |= kFlagWide;
+                        if (!(nbmax < kLfSize && smax < kLsSize)) inf.flags |= kFlagOverflow;
+                    }
+                }
+            }
+            A.w.info[s] = inf;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_prep(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
+                       hipStream_t stream) {
+    if (sp.n == 0) return hipSuccess;
+    PrepArgs a{ix, sp, kp, w};
+    uint64_t grid = sp.n < (1u << 20) ? sp.n : (1u << 20);
+    hipLaunchKernelGGL(k_prep, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scan: shared-peak counting in LDS tiles + scoring
+// ---------------------------------------------------------------------------
+
+struct ScanArgs {
+    DevIndex ix;
+    DevSpectra sp;
+    KParams kp;
+    Work w;
+    uint32_t tiles_per_item;   // persistent schedule
+    uint32_t want_wide;        // which counter width this launch handles
+};
+
+struct ScanShared {
+    uint32_t nseg, nlight, nheavy;
+    unsigned long long red[kBlock / 64];
+    uint32_t item;
+};
+
+// LDS layout (dynamic): counters | seg_cur | seg_end | heavy_tend | seg_q | light | heavy | hist
+template <typename C>
+struct ScanLds {
+    C* cnt;
+    uint32_t* seg_cur;
+    uint32_t* seg_end;
+    uint32_t* heavy_tend;
+    uint16_t* seg_q;
+    uint16_t* light;
+    uint16_t* heavy;
+    int32_t* hist;
+    __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap, uint32_t top_k) {
+        size_t o = 0;
+        cnt = (C*)(base + o);
+        const size_t merge = (size_t)(kBlock + kBlock / 2) * top_k * sizeof(MergeEnt<C>);
+        const size_t cbytes = (size_t)tile * sizeof(C);
+        o += ((cbytes > merge ? cbytes : merge) + 15) & ~(size_t)15;
+        seg_cur = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        seg_end = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        heavy_tend = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        seg_q = (uint16_t*)(base + o); o += (size_t)segcap * 2;
+        light = (uint16_t*)(base + o); o += (size_t)segcap * 2;
+        heavy = (uint16_t*)(base + o); o += (size_t)segcap * 2;
+        o = (o + 15) & ~(size_t)15;
+        hist = (int32_t*)(base + o);
+    }
+};
+
+size_t scan_lds_bytes(const KParams& kp, bool wide) {
+    size_t csz = wide ? 8 : 4;
+    // the counter area also holds the top-k merge: 1.5 * kBlock lists of top_k entries
+    size_t merge = (size_t)(kBlock + kBlock / 2) * kp.top_k * (wide ? 24 : 16);
+    size_t o = std::max((size_t)kp.tile * csz, merge);
+    o = (o + 15) & ~(size_t)15;
+    o += (size_t)kp.seg_cap * (4 + 4 + 4 + 2 + 2 + 2);
+    o = (o + 15) & ~(size_t)15;
+    o += (size_t)kHistBins * 4;
+    return o;
+}
+
+// One work item: spectrum s, candidate ids [ida, idb).  Writes the item's top
+// hits to `out` (top_k entries) and adds its histogram and counts to the
+// spectrum's global accumulators.
+template <typename C, int K, bool DUMP>
+__device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint32_t s, uint32_t ida,
+                          uint32_t idb, ps_hit* out) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const KParams& kp = A.kp;
+    const DevIndex& ix = A.ix;
+    const uint32_t n_ent = A.w.info[s].n_ent;
+    const uint32_t* ent = A.w.entries + (uint64_t)s * kp.ent_stride;
+    const int T = kp.tol;
+
+    if (tid == 0) { sh.nseg = 0; sh.nlight = 0; sh.nheavy = 0; }
+    for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) L.hist[i] = 0;
+    __syncthreads();
+
+    // filter_2, part 1: every (entry, bin offset) -> posting segment inside [ida, idb)
+    unsigned long long lookups = 0, postings = 0;
+    const uint32_t npairs = n_ent * (uint32_t)(2 * T + 1);
+    for (uint32_t k = tid; k < npairs; k += kBlock) {
+        const uint32_t e = ent[k / (uint32_t)(2 * T + 1)];
+        if (e == kEntryInvalid) continue;
+        const int64_t bin = (int64_t)(e >> 8) + (int64_t)(k % (uint32_t)(2 * T + 1)) - T;
+        if (bin < 0 || bin >= (int64_t)ix.n_bins) continue;
+        ++lookups;
+        const uint32_t r0 = (uint32_t)ix.bin_off[bin], r1 = (uint32_t)ix.bin_off[bin + 1];
+        if (r0 == r1) continue;
+        const uint32_t s0 = lower_bound_u32(ix.post, r0, r1, ida << 1);
+        const uint32_t s1 = lower_bound_u32(ix.post, s0, r1, idb << 1);
+        if (s1 <= s0) continue;
+        postings += s1 - s0;
+        const uint32_t slot = atomicAdd(&sh.nseg, 1u);
+        if (slot < kp.seg_cap) {
+            L.seg_cur[slot] = s0;
+            L.seg_end[slot] = s1;
+            L.seg_q[slot] = (uint16_t)(e & 0xFFu);
+            if (s1 - s0 > kp.heavy_min) L.heavy[atomicAdd(&sh.nheavy, 1u)] = (uint16_t)slot;
+            else L.light[atomicAdd(&sh.nlight, 1u)] = (uint16_t)slot;
+        }
+    }
+    __syncthreads();
+    const uint32_t nlight = sh.nlight, nheavy = sh.nheavy;
+    // no posting in range: every counter stays 0 < k_min, nothing can be scored
+    const uint32_t id_end = (nlight + nheavy) ? idb : ida;
+
+    TopK<K, C> top;
+    top.init();
+    uint32_t scored = 0;
+    const uint32_t kmin = kp.min_shared;
+    for (uint32_t tb = ida; tb < id_end; tb += kp.tile) {
+        const uint32_t te = min(id_end, tb + kp.tile);
+        const uint32_t nt = te - tb;
+        const uint32_t lim = te << 1;
+        for (uint32_t i = tid; i < nt; i += kBlock) L.cnt[i] = 0;
+        __syncthreads();
+        // light segments: one thread walks each, up to the tile's end
+        for (uint32_t j = tid; j < nlight; j += kBlock) {
+            const uint32_t sg = L.light[j];
+            uint32_t cur = L.seg_cur[sg];
+            const uint32_t end = L.seg_end[sg];
+            const uint32_t q = L.seg_q[sg];
+            while (cur < end) {
+                const uint32_t p = ix.post[cur];
+                if (p >= lim) break;
+                atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
+                ++cur;
+            }
+            L.seg_cur[sg] = cur;
+        }
+        // heavy segments: one wavefront finds each one's end in this tile
+        for (uint32_t h = wave; h < nheavy; h += kBlock / 64) {
+            const uint32_t sg = L.heavy[h];
+            const uint32_t e = wave_lower_bound(ix.post, L.seg_cur[sg], L.seg_end[sg], lim);
+            if (lane == 0) L.heavy_tend[h] = e;
+        }
+        __syncthreads();
+        // ... then the whole workgroup streams each heavy run, coalesced
+        for (uint32_t h = 0; h < nheavy; ++h) {
+            const uint32_t sg = L.heavy[h];
+            const uint32_t c0 = L.seg_cur[sg], c1 = L.heavy_tend[h];
+            const uint32_t q = L.seg_q[sg];
+            for (uint32_t i = c0 + tid; i < c1; i += kBlock) {
+                const uint32_t p = ix.post[i];
+                atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
+            }
+        }
+        __syncthreads();
+        for (uint32_t h = tid; h < nheavy; h += kBlock) L.seg_cur[L.heavy[h]] = L.heavy_tend[h];
+        // candidate filter, hyperscore, histogram, top-k
+        for (uint32_t i = tid; i < nt; i += kBlock) {
+            const C c = L.cnt[i];
+            const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c);
+            if (nb + ny < kmin) continue;
+            const uint32_t sq = Cnt<C>::s(c);
+            const double h = (ix.lf[nb] + ix.lf[ny]) + ix.ls[sq];
+            const double hb = floor(10.0 * h);
+            const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
+            atomicAdd(&L.hist[bin], 1);
+            ++scored;
+            top.insert(h, tb + i, c);
+            if (DUMP) {
+                const unsigned long long slot = atomicAdd(&A.w.counters[kCtrDump], 1ull);
+                if (slot < A.w.dump_cap) {
+                    A.w.dump_spec[slot] = s;
+                    A.w.dump_id[slot] = tb + i;
+                    A.w.dump_cnt_lo[slot] = (nb & 0xFFFFu) | (ny << 16);
+                    A.w.dump_cnt_hi[slot] = sq;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // top-k of the item: every thread's best top_k go to LDS (over the counter
+    // tile), then rounds of pairwise merges, ping-ponging between two regions,
+    // leave the workgroup's list at the front of one of them
+    const uint32_t kk = kp.top_k;
+    MergeEnt<C>* ma = (MergeEnt<C>*)L.cnt;
+    MergeEnt<C>* mb = ma + kBlock * kk;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if ((uint32_t)j < kk) {
+            MergeEnt<C> m; m.h = top.h[j]; m.id = top.id[j]; m.c = top.c[j];
+            ma[tid * kk + j] = m;
+        }
+    }
+    __syncthreads();
+    for (uint32_t half = kBlock / 2; half >= 1; half >>= 1) {
+        if (tid < half) {
+            const MergeEnt<C>* x = ma + tid * kk;
+            const MergeEnt<C>* y = ma + (tid + half) * kk;
+            MergeEnt<C>* o = mb + tid * kk;
+            uint32_t ix_ = 0, iy = 0;
+            for (uint32_t j = 0; j < kk; ++j) {
+                const bool takex = TopK<K, C>::better(x[ix_].h, x[ix_].id, y[iy].h, y[iy].id);
+                o[j] = takex ? x[ix_] : y[iy];
+                if (takex) ++ix_; else ++iy;
+            }
+        }
+        __syncthreads();
+        MergeEnt<C>* t = ma; ma = mb; mb = t;
+    }
+    const MergeEnt<C>* ml = ma;
+    const unsigned long long sc = block_sum<unsigned long long>(scored, sh.red);   // has barriers
+    if (tid < kk) {
+        const MergeEnt<C> m = ml[tid];
+        ps_hit o;
+        o.id = m.id;
+        o.n_b = (uint16_t)(m.id == 0xFFFFFFFFu ? 0 : Cnt<C>::nb(m.c));
+        o.n_y = (uint16_t)(m.id == 0xFFFFFFFFu ? 0 : Cnt<C>::ny(m.c));
+        o.sum_q = m.id == 0xFFFFFFFFu ? 0 : Cnt<C>::s(m.c);
+        o.pad = 0;
+        o.hyperscore = m.h;
+        out[tid] = o;
+    }
+    if (tid == 0 && sc) atomicAdd(&A.w.n_scored[s], sc);
+    for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) {
+        const int32_t v = L.hist[i];
+        if (v) atomicAdd(&A.w.hist[(uint64_t)s * kHistBins + i], v);
+    }
+    const unsigned long long pl = block_sum<unsigned long long>(postings, sh.red);
+    const unsigned long long lk = block_sum<unsigned long long>(lookups, sh.red);
+    if (tid == 0) {
+        if (pl) atomicAdd(&A.w.counters[kCtrPostings], pl);
+        if (lk) atomicAdd(&A.w.counters[kCtrLookups], lk);
+    }
+    __syncthreads();
+}
+
+// Plain schedule: workgroup s searches spectrum s's whole window.
+template <typename C, int K, bool DUMP>
+__global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ ScanShared sh;
+    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap, A.kp.top_k);
+    const uint32_t s = blockIdx.x;
+    const SpecInfo inf = A.w.info[s];
+    ps_hit* out = A.w.partial + (uint64_t)s * A.kp.top_k;
+    const bool wide = (inf.flags & kFlagWide) != 0;
+    const bool skip = (inf.flags & (kFlagInvalid | kFlagOverflow)) || inf.hi <= inf.lo;
+    if (wide != (A.want_wide != 0)) return;            // the other launch handles it
+    if (skip) {
+        if (threadIdx.x < A.kp.top_k) {
+            ps_hit o; o.id = 0xFFFFFFFFu; o.n_b = o.n_y = 0; o.sum_q = 0; o.pad = 0; o.hyperscore = -INFINITY;
+            out[threadIdx.x] = o;
+        }
+        return;
+    }
+    scan_item<C, K, DUMP>(A, sh, L, s, inf.lo, inf.hi, out);
+}
+
+template <typename C, int K, bool DUMP>
+static hipError_t launch_scan_plain_t(const ScanArgs& a, uint64_t n, hipStream_t stream) {
+    const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
+    hipError_t e = hipFuncSetAttribute((const void*)k_scan_plain<C, K, DUMP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_scan_plain<C, K, DUMP>), dim3((uint32_t)n), dim3(kBlock), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
+                             bool dump, hipStream_t stream) {
+    if (sp.n == 0) return hipSuccess;
+    ScanArgs a{ix, sp, kp, w, 1u, 0u};
+    hipError_t e;
+    const bool k8 = kp.top_k <= 8;
+    // narrow counters for every spectrum that proved it can use them, then wide
+    a.want_wide = 0;
+    if (dump) e = k8 ? launch_scan_plain_t<uint32_t, 8, true>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, true>(a, sp.n, stream);
+    else e = k8 ? launch_scan_plain_t<uint32_t, 8, false>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, false>(a, sp.n, stream);
+    if (e != hipSuccess) return e;
+    a.want_wide = 1;
+    if (dump) e = k8 ? launch_scan_plain_t<unsigned long long, 8, true>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, true>(a, sp.n, stream);
+    else e = k8 ? launch_scan_plain_t<unsigned long long, 8, false>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, false>(a, sp.n, stream);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// merge: partial top-k -> hits; histogram -> smoothed survival -> tail fit -> e-value
+// ---------------------------------------------------------------------------
+
+struct MergeArgs {
+    DevIndex ix;
+    DevSpectra sp;
+    KParams kp;
+    Work w;
+    uint32_t per_item;   // 1: partial lists per work item (spec_item0 ranges); 0: one per spectrum
+};
+
+__global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
+    __shared__ long long s_num[kHistBins];
+    __shared__ long long s_tail[kHistBins];
+    __shared__ double s_red[kBlock / 64];
+    __shared__ long long s_redl[kBlock / 64];
+    __shared__ ps_hit s_top[PS_MAX_TOP_K];
+    __shared__ int s_mode;
+    __shared__ unsigned long long s_modekey;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t K = A.kp.top_k;
+    for (uint64_t s = blockIdx.x; s < A.sp.n; s += gridDim.x) {
+        const SpecInfo inf = A.w.info[s];
+        const bool invalid = (inf.flags & kFlagInvalid) != 0;
+        const bool overflow = (inf.flags & kFlagOverflow) != 0;
+        // ---- top-k merge (thread 0, insertion; lists are short)
+        if (tid == 0) {
+            for (uint32_t j = 0; j < K; ++j) {
+                s_top[j].id = 0xFFFFFFFFu; s_top[j].n_b = s_top[j].n_y = 0; s_top[j].sum_q = 0;
+                s_top[j].pad = 0; s_top[j].hyperscore = -INFINITY;
+            }
+            uint64_t i0 = s, i1 = s + 1;
+            if (A.per_item) { i0 = A.w.spec_item0[s]; i1 = A.w.spec_item0[s + 1]; }
+            if (!invalid && !overflow) {
+                for (uint64_t it = i0; it < i1; ++it) {
+                    const ps_hit* src = A.w.partial + it * K;
+                    for (uint32_t j = 0; j < K; ++j) {
+                        ps_hit c = src[j];
+                        if (c.id == 0xFFFFFFFFu) break;
+                        // insert into s_top (sorted by hyperscore desc, id asc)
+                        if (!(c.hyperscore > s_top[K - 1].hyperscore ||
+                              (c.hyperscore == s_top[K - 1].hyperscore && c.id < s_top[K - 1].id)))
+                            continue;
+                        int p = (int)K - 1;
+                        while (p > 0 && (c.hyperscore > s_top[p - 1].hyperscore ||
+                                         (c.hyperscore == s_top[p - 1].hyperscore && c.id < s_top[p - 1].id))) {
+                            s_top[p] = s_top[p - 1];
+                            --p;
+                        }
+                        s_top[p] = c;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const unsigned long long N = (invalid || overflow) ? 0ull : A.w.n_scored[s];
+        const double h1 = s_top[0].hyperscore;
+        // ---- Savitzky-Golay (-3, 12, 17, 12, -3)/35 numerators, exact in integers
+        const int32_t* hg = A.w.hist + s * (uint64_t)kHistBins;
+        long long part = 0;
+        for (int j = tid; j < kHistBins; j += kBlock) {
+            long long acc = 0;
+            const int c[5] = {-3, 12, 17, 12, -3};
+            for (int t = -2; t <= 2; ++t) {
+                int i = j + t;
+                if (i >= 0 && i < kHistBins && N) acc += (long long)c[t + 2] * (long long)hg[i];
+            }
+            if (acc < 0) acc = 0;
+            s_num[j] = acc;
+            part += acc;
+        }
+        // total
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
+        if ((tid & 63) == 0) s_redl[tid >> 6] = part;
+        if (tid == 0) s_modekey = 0;
+        __syncthreads();
+        long long total = 0;
+        for (int i = 0; i < kBlock / 64; ++i) total += s_redl[i];
+        // mode: largest numerator, lowest index on ties -> max of (value << 9 | (511 - j))
+        for (int j = tid; j < kHistBins; j += kBlock)
+            atomicMax(&s_modekey, ((unsigned long long)s_num[j] << 9) | (unsigned long long)(kHistBins - 1 - j));
+        __syncthreads();
+        if (tid == 0) {
+            s_mode = kHistBins - 1 - (int)(s_modekey & 511ull);
+            long long run = 0;
+            for (int j = kHistBins - 1; j >= 0; --j) { run += s_num[j]; s_tail[j] = run; }
+        }
+        __syncthreads();
+        int status = PS_STATUS_OK;
+        double ev = __builtin_nan("");
+        if (invalid) status = PS_STATUS_INVALID;
+        else if (overflow) status = PS_STATUS_OVERFLOW;
+        else if (N == 0) status = PS_STATUS_NO_HITS;
+        // ---- least-squares fit of log10 survival over [mode, bin(H1) - 1]
+        double sx = 0, sy = 0, sxx = 0, sxy = 0, cnt = 0;
+        if (status == PS_STATUS_OK && total > 0) {
+            const double hb = floor(10.0 * h1);
+            const int jh = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
+            for (int j = s_mode + (int)tid; j <= jh - 1; j += kBlock) {
+                const long long t = s_tail[j];
+                if (t <= 0) continue;
+                const double x = 0.1 * (double)j;
+                const double y = log10((double)t / (double)total);
+                sx += x; sy += y; sxx += x * x; sxy += x * y; cnt += 1.0;
+            }
+        }
+        double v[5] = {sx, sy, sxx, sxy, cnt};
+        __shared__ double s_v[5][kBlock / 64];
+        for (int k = 0; k < 5; ++k) {
+            double x = v[k];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+            if ((tid & 63) == 0) s_v[k][tid >> 6] = x;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double t[5];
+            for (int k = 0; k < 5; ++k) { t[k] = 0; for (int i = 0; i < kBlock / 64; ++i) t[k] += s_v[k][i]; }
+            if (status == PS_STATUS_OK) {
+                const double n = t[4];
+                if (n < 3.0) {
+                    status = PS_STATUS_FEW_POINTS;
+                } else {
+                    const double num = n * t[3] - t[0] * t[1];
+                    const double den = n * t[2] - t[0] * t[0];
+                    const double w = num / den;
+                    const double b = (t[1] - w * t[0]) / n;
+                    if (!(w < 0.0)) status = PS_STATUS_BAD_SLOPE;
+                    else ev = (double)N * pow(10.0, w * h1 + b);
+                }
+            }
+            ps_stat st;
+            st.n_window = (invalid) ? 0ull : (unsigned long long)(inf.hi - inf.lo);
+            st.n_scored = N;
+            st.evalue = ev;
+            st.status = status;
+            st.pad = 0;
+            A.w.stats[s] = st;
+        }
+        for (uint32_t j = tid; j < K; j += kBlock) A.w.hits[s * K + j] = s_top[j];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
+                        bool per_item, hipStream_t stream) {
+    if (sp.n == 0) return hipSuccess;
+    MergeArgs a{ix, sp, kp, w, per_item ? 1u : 0u};
+    uint64_t grid = sp.n < (1u << 20) ? sp.n : (1u << 20);
+    hipLaunchKernelGGL(k_merge, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_worklist(const DevSpectra&, const KParams&, const Work&, uint64_t, hipStream_t) {
+    return hipErrorNotSupported;
+}
+hipError_t launch_scan_persistent(const DevIndex&, const DevSpectra&, const KParams&, const Work&, uint32_t,
+                                  uint32_t, hipStream_t) {
+    return hipErrorNotSupported;
+}
+
+}  // namespace ps

@@ -1,0 +1,56 @@
+// state.h -- host-side objects behind the opaque ABI handles.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ps {
+
+// Record a thread-local error message for ps_last_error(); returns `code`.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+// PS_OK when a gfx950-class device is usable, else PS_EDEVICE (message set).
+int require_device();
+unsigned worker_threads();
+int64_t residue_uda(char c);
+
+// Trypsin: cut after K or R unless the next residue is P.
+inline bool is_cut(const char* s, uint64_t n, uint64_t i) {
+    if (s[i] != 'K' && s[i] != 'R') return false;
+    return i + 1 >= n || s[i + 1] != 'P';
+}
+
+void score_tables(std::vector<double>& lf, std::vector<double>& ls);
+
+}  // namespace ps
+
+struct ps_index {
+    struct Mod {
+        uint32_t res_mask;
+        bool nterm;
+        int64_t delta;
+        std::string residues;
+    };
+    uint32_t missed = 0, min_len = 0, max_len = 0, max_mods = 0;
+    std::vector<Mod> mods;
+    std::vector<char> seq;
+    std::vector<uint64_t> prot_off;
+    // entries sorted by (mass, protein, start, length, mask); id = position
+    std::vector<int64_t> mass;
+    std::vector<uint32_t> prot, start;
+    std::vector<uint8_t> len;
+    std::vector<uint64_t> mask;
+    // CSR fragment-ion index
+    uint64_t n_bins = 0;
+    std::vector<uint64_t> bin_off;
+    std::vector<uint32_t> post;
+    uint32_t max_len_seen = 0;
+    int64_t min_residue = 0;
+    // device copy
+    bool on_device = false;
+    ps::DevIndex dev{};
+};
+
+namespace ps {
+int index_build_host(ps_index* ix);
+}

@@ -1,0 +1,195 @@
+"""Python front end: build an index in device memory and search spectra.
+
+Thin layer over the C ABI (capi.py).  PyTorch only supplies device memory
+blocks (uint8 tensors) and HIP streams; the search itself runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import capi
+from .capi import check, ptr
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class Mod:
+    residues: str
+    delta_uda: int
+    nterm: bool = False
+
+
+def mods_from_synth(mods) -> list[Mod]:
+    return [Mod(m.residues, int(round(m.delta_da * 1e6)), m.nterm) for m in mods]
+
+
+def _db_params(missed, min_len, max_len, mods, max_mods):
+    arr = (capi.ps_mod * max(1, len(mods)))()
+    keep = []
+    for i, m in enumerate(mods):
+        b = (m.residues or "").encode()
+        keep.append(b)
+        arr[i].residues = b
+        arr[i].nterm = 1 if m.nterm else 0
+        arr[i].delta_udalton = int(m.delta_uda)
+    p = capi.ps_db_params(missed, min_len, max_len, len(mods), max_mods, 0, arr)
+    return p, (arr, keep)
+
+
+def search_params(window_is_ppm: bool, window: int, frag_tol_bins: int, top_peaks: int, top_k: int = 5,
+                  min_shared: int = 4, max_charge: int = 8, schedule: int = capi.PS_SCHED_PLAIN,
+                  want_hist: bool = True) -> capi.ps_search_params:
+    return capi.ps_search_params(int(window_is_ppm), int(frag_tol_bins), int(window), int(top_peaks), int(top_k),
+                                 int(min_shared), int(max_charge), int(schedule), int(bool(want_hist)))
+
+
+class HostIndex:
+    """The index built on the host (no GPU needed)."""
+
+    def __init__(self, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int, max_len: int,
+                 mods: list, max_mods: int):
+        self._res = np.ascontiguousarray(residues, dtype=np.uint8)
+        self._off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods)
+        h = C.c_void_p()
+        check(capi.ps_index_create(C.byref(p), ptr(self._res), ptr(self._off), self._off.shape[0] - 1,
+                                   C.byref(h)), "ps_index_create")
+        self.handle = h
+        self.arena = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            capi.ps_index_free(h)
+            self.handle = None
+
+    def shape(self):
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        check(capi.ps_index_shape(self.handle, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def __len__(self):
+        return self.shape()[0]
+
+    def entry(self, pid: int):
+        m, p, s, n, k = C.c_int64(), C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint64()
+        check(capi.ps_index_entry(self.handle, pid, C.byref(m), C.byref(p), C.byref(s), C.byref(n), C.byref(k)))
+        return m.value, p.value, s.value, n.value, k.value
+
+    def peptide(self, pid: int) -> str:
+        buf = C.create_string_buffer(512)
+        check(capi.ps_peptide(self.handle, pid, buf, 512))
+        return buf.value.decode()
+
+    def host_arrays(self):
+        _, n_post, n_bins = self.shape()
+        off = np.zeros(n_bins + 1, np.uint64)
+        post = np.zeros(n_post, np.uint32)
+        check(capi.ps_index_host_arrays(self.handle, ptr(off), ptr(post)))
+        return off, post
+
+    def device_bytes(self) -> int:
+        b = C.c_uint64()
+        check(capi.ps_index_device_bytes(self.handle, C.byref(b)))
+        return b.value
+
+    def upload(self, device: str = "cuda:0", stream=None):
+        torch = _torch()
+        nbytes = self.device_bytes()
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        dev = capi.ps_device(self.arena.data_ptr(), nbytes, st.cuda_stream)
+        check(capi.ps_index_upload(self.handle, C.byref(dev)), "ps_index_upload")
+        return self
+
+
+def _spectra_struct(sp):
+    arrs = [np.ascontiguousarray(sp.peak_off, np.uint64), np.ascontiguousarray(sp.mz, np.float32),
+            np.ascontiguousarray(sp.intensity, np.float32), np.ascontiguousarray(sp.precursor_mz, np.float64),
+            np.ascontiguousarray(sp.charge, np.int8)]
+    s = capi.ps_spectra(sp.n, *[a.ctypes.data for a in arrs])
+    return s, arrs
+
+
+class Workspace:
+    """A reusable device block for batches (grown on demand)."""
+
+    def __init__(self, device: str = "cuda:0", stream=None):
+        self.device = device
+        self.stream = stream
+        self.buf = None
+
+    def get(self, nbytes: int):
+        torch = _torch()
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=self.device)
+        st = self.stream if self.stream is not None else torch.cuda.current_stream(self.buf.device)
+        return capi.ps_device(self.buf.data_ptr(), self.buf.numel(), st.cuda_stream)
+
+
+@dataclass
+class Results:
+    hits: np.ndarray       # [n, top_k] HIT_DTYPE
+    stats: np.ndarray      # [n] STAT_DTYPE
+    hist: np.ndarray | None
+    scan_ms: float
+    postings: int
+    lookups: int
+
+
+def search(index: HostIndex, sp, params: capi.ps_search_params, ws: Workspace | None = None) -> Results:
+    """Search host spectra; blocks until results are back on the host."""
+    ws = ws or Workspace()
+    s, keep = _spectra_struct(sp)
+    need = C.c_uint64()
+    nnz = int(sp.peak_off[-1]) if sp.n else 0
+    check(capi.ps_workspace_bytes(index.handle, sp.n, nnz, C.byref(params), C.byref(need)), "ps_workspace_bytes")
+    dev = ws.get(need.value)
+    b = C.c_void_p()
+    check(capi.ps_search_batch(index.handle, C.byref(dev), C.byref(s), C.byref(params), C.byref(b)),
+          "ps_search_batch")
+    try:
+        return collect(b, sp.n, params)
+    finally:
+        capi.ps_batch_free(b)
+
+
+def collect(batch, n: int, params: capi.ps_search_params) -> Results:
+    hits = np.zeros(n * params.top_k, capi.HIT_DTYPE)
+    stats = np.zeros(n, capi.STAT_DTYPE)
+    hist = np.zeros(n * capi.PS_HIST_BINS, np.int32) if params.want_hist else None
+    rc = capi.ps_results(batch, ptr(hits), ptr(stats), ptr(hist) if hist is not None else None)
+    if rc not in (capi.PS_OK, capi.PS_EOVERFLOW):
+        check(rc, "ps_results")
+    ms, la, po, lk = C.c_double(), C.c_uint32(), C.c_uint64(), C.c_uint64()
+    check(capi.ps_batch_timing(batch, C.byref(ms), C.byref(la), C.byref(po), C.byref(lk)), "ps_batch_timing")
+    return Results(hits.reshape(n, params.top_k), stats,
+                   hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, ms.value, po.value, lk.value)
+
+
+def search_dump(index: HostIndex, sp, params: capi.ps_search_params, cap: int = 1 << 22,
+                ws: Workspace | None = None):
+    """Every scored candidate of every spectrum, sorted by (spectrum, id)."""
+    ws = ws or Workspace()
+    s, keep = _spectra_struct(sp)
+    need = C.c_uint64()
+    nnz = int(sp.peak_off[-1]) if sp.n else 0
+    check(capi.ps_workspace_bytes(index.handle, sp.n, nnz, C.byref(params), C.byref(need)))
+    dev = ws.get(need.value + cap * 16 + (1 << 16))
+    a = np.zeros(cap, np.uint32); b = np.zeros(cap, np.uint32)
+    nb = np.zeros(cap, np.uint16); ny = np.zeros(cap, np.uint16); sq = np.zeros(cap, np.uint32)
+    cnt = C.c_uint64()
+    check(capi.ps_search_dump(index.handle, C.byref(dev), C.byref(s), C.byref(params), cap, ptr(a), ptr(b),
+                              ptr(nb), ptr(ny), ptr(sq), C.byref(cnt)), "ps_search_dump")
+    m = cnt.value
+    order = np.lexsort((b[:m], a[:m]))
+    return a[:m][order], b[:m][order], nb[:m][order], ny[:m][order], sq[:m][order]

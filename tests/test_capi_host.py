@@ -1,0 +1,132 @@
+"""C-ABI library checks that need no GPU: exported symbols, the host-built
+index against the oracle's database, and error paths."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_02286_amd import capi, engine, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "pepscan.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ps_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _header_functions()
+    assert len(names) >= 15
+    L = C.CDLL(capi.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    bound = {s[0] for s in capi._SIGS}
+    assert set(names) == bound, set(names) ^ bound
+
+
+def test_struct_layouts_match_header_sizes():
+    assert C.sizeof(capi.ps_device) == 24
+    assert C.sizeof(capi.ps_mod) == 24
+    assert C.sizeof(capi.ps_db_params) == 32
+    assert C.sizeof(capi.ps_spectra) == 48
+    assert C.sizeof(capi.ps_search_params) == 40
+    assert capi.HIT_DTYPE.itemsize == 24 and capi.STAT_DTYPE.itemsize == 32
+
+
+def _both(prot, missed, min_len, max_len, mods, max_mods):
+    o = oracle.Database(prot.residues, prot.offsets, missed, min_len, max_len,
+                        oracle.mods_from_synth(mods), max_mods)
+    h = engine.HostIndex(prot.residues, prot.offsets, missed, min_len, max_len,
+                         engine.mods_from_synth(mods), max_mods)
+    return o, h
+
+
+@pytest.mark.parametrize("mods,max_mods", [([], 0), ([synth.OXIDATION], 2),
+                                           ([synth.OXIDATION, synth.PHOSPHO, synth.ACETYL_NTERM,
+                                             synth.DEAMIDATION], 3)])
+def test_host_index_entries_match_oracle(mods, max_mods):
+    prot = synth.make_proteome(60, seed=3)
+    o, h = _both(prot, 2, 7, 40, mods, max_mods)
+    assert len(o) == len(h)
+    tab = o.table()
+    rng = np.random.default_rng(0)
+    for pid in list(range(min(len(o), 200))) + list(rng.integers(0, len(o), 500)):
+        pid = int(pid)
+        assert h.entry(pid) == tuple(int(x) for x in tab[pid]), pid
+
+
+def test_host_index_postings_match_oracle_ions():
+    """CSR postings equal bins of the oracle's b/y ions, listed in id order."""
+    prot = synth.make_proteome(25, seed=4)
+    mods = [synth.OXIDATION, synth.PHOSPHO]
+    o, h = _both(prot, 1, 7, 30, mods, 2)
+    off, post = h.host_arrays()
+    want = {}
+    for pid in range(len(o)):
+        b, y = oracle.ions(o.residue_masses(pid))
+        for m in b:
+            want.setdefault(int((m + 5000) // 10000), []).append(pid << 1)
+        for m in y:
+            want.setdefault(int((m + 5000) // 10000), []).append(pid << 1 | 1)
+    assert int(off[-1]) == post.shape[0] == sum(len(v) for v in want.values())
+    for bn in range(off.shape[0] - 1):
+        got = post[off[bn]:off[bn + 1]].tolist()
+        assert got == sorted(want.get(bn, [])), bn
+
+
+def test_peptide_strings():
+    prot = synth.Proteome(np.frombuffer(b"MSTKPEPTIDER", np.uint8).copy(), np.array([0, 12], np.uint64))
+    h = engine.HostIndex(prot.residues, prot.offsets, 1, 4, 20,
+                         engine.mods_from_synth([synth.PHOSPHO, synth.ACETYL_NTERM]), 2)
+    strings = {h.peptide(i) for i in range(len(h))}
+    assert "MSTKPEPTIDER" in strings
+    assert "n[+42.010565]MS[+79.966331]TKPEPTIDER" in strings
+    assert "MST[+79.966331]KPEPTIDER" in strings
+
+
+def test_index_create_rejects_bad_input():
+    bad = synth.Proteome(np.frombuffer(b"PEPXIDEK", np.uint8).copy(), np.array([0, 8], np.uint64))
+    with pytest.raises(capi.PsError) as e:
+        engine.HostIndex(bad.residues, bad.offsets, 1, 4, 20, [], 0)
+    assert e.value.code == capi.PS_EINVAL
+    ok = synth.Proteome(np.frombuffer(b"PEPTIDEK", np.uint8).copy(), np.array([0, 8], np.uint64))
+    with pytest.raises(capi.PsError):
+        engine.HostIndex(ok.residues, ok.offsets, 1, 10, 5, [], 0)             # min_len > max_len
+    with pytest.raises(capi.PsError):
+        engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20,
+                         [engine.Mod("ST", 1), engine.Mod("TY", 2)], 1)        # T in two mods
+
+
+def test_no_device_is_reported_not_crashed():
+    """In a container without a GPU, upload and search fail with PS_EDEVICE."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present")
+    ok = synth.Proteome(np.frombuffer(b"PEPTIDEKAAAAR", np.uint8).copy(), np.array([0, 13], np.uint64))
+    h = engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [], 0)
+    dev = capi.ps_device(None, 0, None)
+    rc = capi.ps_index_upload(h.handle, C.byref(dev))
+    assert rc == capi.PS_EDEVICE
+    assert "device" in capi.last_error()
+
+
+def test_search_params_validation_without_device():
+    ok = synth.Proteome(np.frombuffer(b"PEPTIDEKAAAAR", np.uint8).copy(), np.array([0, 13], np.uint64))
+    h = engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [], 0)
+    need = C.c_uint64()
+    for bad in [engine.search_params(False, 1, 1, 100, top_k=0),
+                engine.search_params(False, 1, 1, 100, top_k=17),
+                engine.search_params(False, 1, 9, 100),
+                engine.search_params(False, -1, 1, 100),
+                engine.search_params(False, 1, 1, 100, min_shared=0),
+                engine.search_params(False, 1, 1, 256, max_charge=8),          # too many segments
+                engine.search_params(True, 2_000_000, 1, 100)]:
+        assert capi.ps_workspace_bytes(h.handle, 10, 100, C.byref(bad), C.byref(need)) == capi.PS_EINVAL
+    good = engine.search_params(False, 1, 1, 100, max_charge=3)
+    assert capi.ps_workspace_bytes(h.handle, 10, 100, C.byref(good), C.byref(need)) == capi.PS_OK
+    assert need.value > 10 * 512 * 4

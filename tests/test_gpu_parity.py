@@ -1,0 +1,268 @@
+"""Parity of the HIP search path with the CPU oracle (needs an MI355X).
+
+Integer outputs (window sizes, scored counts, top-k ids, n_b/n_y/S, histograms,
+the full scored set) must be bit-exact.  Hyperscores come from the same fp64
+table values on both sides, so they agree to the last bit; expect values go
+through GPU log10/pow and a differently ordered sum, so they are held to 1e-5
+relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_02286_amd import capi, engine, synth
+
+pytestmark = pytest.mark.gpu
+
+EV_RTOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def assert_parity(res, oh, ost, og, check_hist=True):
+    assert res.hits.shape == oh.shape
+    bad = np.nonzero(np.any(res.hits["id"] != oh["id"], axis=1))[0]
+    assert bad.size == 0, f"top-k ids differ for spectra {bad[:10]}"
+    for f in ("n_b", "n_y", "sum_q"):
+        assert np.array_equal(res.hits[f], oh[f]), f
+    h1, h2 = res.hits["hyperscore"], oh["hyperscore"]
+    assert np.array_equal(np.isinf(h1), np.isinf(h2))
+    fin = np.isfinite(h2)
+    assert np.array_equal(h1[fin], h2[fin])
+    for f in ("n_window", "n_scored", "status"):
+        assert np.array_equal(res.stats[f].astype(np.int64), ost[f].astype(np.int64)), f
+    ok = ost["status"] == 0
+    assert np.all(np.isnan(res.stats["evalue"][~ok]))
+    np.testing.assert_allclose(res.stats["evalue"][ok], ost["evalue"][ok], rtol=EV_RTOL)
+    if check_hist:
+        assert np.array_equal(res.hist, og)
+
+
+# ---------------------------------------------------------------------------
+# tiny closed search: the whole 1000-spectrum batch
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = synth.workload("tiny")
+    prot = w.proteome()
+    sp = w.spectra(prot)
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, [], 0).upload()
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, [], 0)
+    return w, prot, sp, ix, db
+
+
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN])
+def test_tiny_full_batch_parity(tiny, schedule):
+    w, prot, sp, ix, db = tiny
+    _say(f"tiny: {sp.n} spectra, schedule {schedule}")
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=2, schedule=schedule)
+    res = engine.search(ix, sp, prm)
+    oh, ost, og = db.search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared)
+    assert_parity(res, oh, ost, og)
+    assert res.postings == int(ost["pairs_total"].sum())
+
+
+def test_tiny_scored_set_dump(tiny):
+    w, prot, sp, ix, db = tiny
+    sub = sp.subset(np.arange(0, 200))
+    _say("tiny: scored-set dump, 200 spectra")
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, 1, max_charge=2)
+    gs, gi, gb, gy, gq = engine.search_dump(ix, sub, prm)
+    want = []
+    for s in range(sub.n):
+        ids, nb, ny, sq = db.scored(sub, s, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, min_shared=1)
+        want += [(s, int(a), int(b), int(c), int(d)) for a, b, c, d in zip(ids, nb, ny, sq)]
+    got = list(zip(gs.tolist(), gi.tolist(), gb.tolist(), gy.tolist(), gq.tolist()))
+    assert got == want
+
+
+# ---------------------------------------------------------------------------
+# open search on a small proteome: many tiles per window, ragged tails
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def small_open():
+    w = synth.workload("medium")
+    prot = synth.make_proteome(2000, seed=0)
+    sp = w.spectra(prot, n=160, seed=5)
+    mods = w.mods
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
+                          engine.mods_from_synth(mods), w.max_mods).upload()
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
+                         oracle.mods_from_synth(mods), w.max_mods)
+    oh, ost, og = db.search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared)
+    return w, prot, sp, ix, db, (oh, ost, og)
+
+
+def test_small_open_search_parity(small_open):
+    w, prot, sp, ix, db, (oh, ost, og) = small_open
+    _say(f"small open: {len(db)} peptides, {sp.n} spectra")
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3)
+    res = engine.search(ix, sp, prm)
+    assert (ost["n_window"] > 4 * 8192).sum() > 50          # windows span several LDS tiles
+    assert_parity(res, oh, ost, og)
+    assert res.postings == int(ost["pairs_total"].sum())
+
+
+def test_small_open_scored_set_dump(small_open):
+    w, prot, sp, ix, db, _ = small_open
+    sub = sp.subset(np.arange(0, 12))
+    _say("small open: scored-set dump, 12 spectra")
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3)
+    gs, gi, gb, gy, gq = engine.search_dump(ix, sub, prm)
+    want = []
+    for s in range(sub.n):
+        ids, nb, ny, sq = db.scored(sub, s, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks,
+                                    min_shared=w.min_shared)
+        want += [(s, int(a), int(b), int(c), int(d)) for a, b, c, d in zip(ids, nb, ny, sq)]
+    got = list(zip(gs.tolist(), gi.tolist(), gb.tolist(), gy.tolist(), gq.tolist()))
+    assert got == want
+
+
+def test_small_open_permutation_and_split_invariance(small_open):
+    w, prot, sp, ix, db, _ = small_open
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3)
+    _say("small open: permutation / split invariance")
+    r0 = engine.search(ix, sp, prm)
+    perm = np.random.default_rng(7).permutation(sp.n)
+    r1 = engine.search(ix, sp.subset(perm), prm)
+    assert r1.hits.tobytes() == r0.hits[perm].tobytes()
+    assert r1.stats.tobytes() == r0.stats[perm].tobytes()
+    ra = engine.search(ix, sp.subset(np.arange(0, 70)), prm)
+    rb = engine.search(ix, sp.subset(np.arange(70, sp.n)), prm)
+    assert np.concatenate([ra.hits, rb.hits]).tobytes() == r0.hits.tobytes()
+    assert np.concatenate([ra.stats, rb.stats]).tobytes() == r0.stats.tobytes()
+    # the same batch twice: bit-identical
+    r2 = engine.search(ix, sp, prm)
+    assert r2.hits.tobytes() == r0.hits.tobytes() and r2.hist.tobytes() == r0.hist.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def _mk(peak_lists, prec, charges):
+    off = np.zeros(len(peak_lists) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in peak_lists])
+    mz = np.array([m for pl in peak_lists for (m, _) in pl], np.float32)
+    it = np.array([i for pl in peak_lists for (_, i) in pl], np.float32)
+    return synth.Spectra(off, mz, it, np.asarray(prec, np.float64), np.asarray(charges, np.int8))
+
+
+def test_edge_cases_parity(small_open):
+    w, prot, sp, ix, db, _ = small_open
+    rng = np.random.default_rng(11)
+    tab_mass = [db.get(int(i))[0] for i in rng.integers(0, len(db), 8)]
+    b, y = oracle.ions(db.residue_masses(int(rng.integers(0, len(db)))))
+    one_ion = float(b[2]) * 1e-6
+    cases = [
+        ([], 800.0, 2),                                                       # no peaks
+        ([(500.0, 0.0), (600.0, 0.0)], 700.0, 2),                             # zero intensities
+        ([(one_ion, 5.0)] * 120, (tab_mass[0] * 1e-6 + 2 * 1.007276) / 2, 2),  # duplicates: wide counters
+        ([(one_ion + 0.001 * k, 1.0 + k % 3) for k in range(100)], 900.0, 3),  # crowded bins, intensity ties
+        ([(float(m) * 1e-6, 1.0) for m in np.concatenate([b, y])], 650.5, 1),  # charge 1
+        ([(float(m) * 1e-6, 2.0) for m in b], 410.25, 8),                     # charge 8 (7 fragment charges)
+        ([(300.0, 1.0)], 20000.0, 2),                                         # window beyond every peptide
+        ([(300.0 + k, 1.0) for k in range(300)], 1200.0, 3),                  # more peaks than top_peaks
+    ]
+    sp_e = _mk([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases])
+    for top_k, kmin, T, top_b, window, ppm in [(1, 1, 1, 90, 500_000_000, False), (16, 2, 0, 90, 100_000_000, False),
+                                               (5, 4, 4, 20, 500_000_000, False), (3, 1, 2, 50, 30, True),
+                                               (5, 1, 1, 90, 10**15, False)]:
+        _say(f"edge: top_k={top_k} kmin={kmin} T={T} B={top_b} window={window} ppm={ppm}")
+        prm = engine.search_params(ppm, window, T, top_b, top_k, kmin, max_charge=8 if (2 * T + 1) * 7 * top_b <= 2048 else 3)
+        sub = sp_e if prm.max_charge == 8 else sp_e.subset([i for i in range(sp_e.n) if sp_e.charge[i] <= 3])
+        res = engine.search(ix, sub, prm)
+        oh, ost, og = db.search(sub, ppm, window, T, top_b, top_k, kmin)
+        assert_parity(res, oh, ost, og)
+
+
+def test_wide_counters_are_used_and_exact(small_open):
+    """A spectrum whose peaks pile into one bin needs 64-bit counters; the
+    result must still equal the oracle's unbounded counts."""
+    w, prot, sp, ix, db, _ = small_open
+    pid = 1234
+    b, y = oracle.ions(db.residue_masses(pid))
+    ion = float(y[0]) * 1e-6
+    peaks = [(ion, 10.0)] * 200 + [(float(m) * 1e-6, 3.0) for m in b[:5]]
+    sp1 = _mk([peaks], [(db.get(pid)[0] * 1e-6 + 2 * 1.007276) / 2], [2])
+    prm = engine.search_params(False, 500_000_000, 1, 256, 5, 1, max_charge=2)
+    _say("wide counters")
+    res = engine.search(ix, sp1, prm)
+    oh, ost, og = db.search(sp1, False, 500_000_000, 1, 256, 5, 1)
+    assert int(oh["n_y"][0, 0]) > 255 or int(oh["sum_q"][0, 0]) > 65535
+    assert_parity(res, oh, ost, og)
+
+
+def test_device_resident_inputs_and_invalid_spectra(small_open):
+    import torch
+    w, prot, sp, ix, db, _ = small_open
+    sub = sp.subset(np.arange(0, 40))
+    charge = sub.charge.copy()
+    charge[3] = 0                       # invalid charge
+    prec = sub.precursor_mz.copy()
+    prec[5] = np.nan                    # invalid precursor
+    mz = sub.mz.copy()
+    mz[int(sub.peak_off[7])] = -1.0     # invalid peak
+    dev = "cuda:0"
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+         (sub.peak_off.astype(np.uint64).view(np.int64), mz, sub.intensity, prec, charge)]
+    s = capi.ps_spectra(sub.n, *[x.data_ptr() for x in t])
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3)
+    import ctypes as C
+    need = C.c_uint64()
+    capi.check(capi.ps_workspace_bytes(ix.handle, sub.n, int(sub.peak_off[-1]), C.byref(prm), C.byref(need)))
+    ws = engine.Workspace()
+    d = ws.get(need.value)
+    bh = C.c_void_p()
+    _say("device-resident inputs")
+    capi.check(capi.ps_search_device(ix.handle, C.byref(d), C.byref(s), int(sub.peak_off[-1]), C.byref(prm),
+                                     C.byref(bh)))
+    res = engine.collect(bh, sub.n, prm)
+    capi.ps_batch_free(bh)
+    st = res.stats["status"]
+    assert st[3] == capi.PS_STATUS_INVALID and st[5] == capi.PS_STATUS_INVALID and st[7] == capi.PS_STATUS_INVALID
+    good = np.array([i for i in range(sub.n) if i not in (3, 5, 7)])
+    ref = engine.search(ix, sub.subset(good), prm)
+    assert res.hits[good].tobytes() == ref.hits.tobytes()
+    assert res.stats[good].tobytes() == ref.stats.tobytes()
+    # the host path rejects the same batch outright
+    sp_bad = synth.Spectra(sub.peak_off, mz, sub.intensity, prec, charge)
+    with pytest.raises(capi.PsError) as e:
+        engine.search(ix, sp_bad, prm)
+    assert e.value.code == capi.PS_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# full-size medium workload: sampled outputs against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN])
+def test_medium_full_size_sampled_parity(schedule):
+    w = synth.workload("medium")
+    prot = w.proteome()
+    _say("medium: building index")
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
+                          engine.mods_from_synth(w.mods), w.max_mods).upload()
+    sp = w.spectra(prot)
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3, schedule=schedule)
+    _say(f"medium: searching {sp.n} spectra, schedule {schedule}")
+    res = engine.search(ix, sp, prm)
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
+                         oracle.mods_from_synth(w.mods), w.max_mods)
+    idx = np.sort(np.random.default_rng(123).choice(sp.n, 24, replace=False))
+    sub = sp.subset(idx)
+    _say("medium: oracle on 24 sampled spectra")
+    oh, ost, og = db.search(sub, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared)
+    from types import SimpleNamespace
+    part = SimpleNamespace(hits=res.hits[idx], stats=res.stats[idx], hist=res.hist[idx])
+    assert_parity(part, oh, ost, og)
