@@ -101,6 +101,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(the search has no CPU fallback)")
+        # One HIP runtime per process: torch ships its own libamdhip64.so.7, so it
+        # must be loaded first; the library then binds to that runtime by soname
+        # instead of pulling a second copy from /opt/rocm.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             f = getattr(L, name)
