@@ -141,6 +141,19 @@ typedef struct {
     int32_t  pad;
 } ps_stat;
 
+/* Launch schedule of the posting scan.  Every schedule gives identical results;
+ * it only changes speed.  Chosen by default at index creation, by ps_autotune,
+ * or set by the caller. */
+typedef struct {
+    uint32_t tile;            /* candidates per LDS counter tile: 1024..32768, multiple of 256 */
+    uint32_t coop_min;        /* a posting run longer than this (within one work item) is
+                                 streamed by the whole workgroup; shorter runs by one thread */
+    uint32_t tiles_per_item;  /* PS_SCHED_PERSISTENT: tiles per work item (>= 1) */
+    uint32_t groups_per_cu;   /* PS_SCHED_PERSISTENT: resident workgroups per compute unit (1..8) */
+    uint32_t use_bitmaps;     /* 1: dense fragment bins are read as b/y bitmaps, 0: as postings */
+    uint32_t pad;
+} ps_schedule;
+
 /* ---- errors ------------------------------------------------------------ */
 const char* ps_last_error(void);
 
@@ -183,6 +196,15 @@ int ps_peptide(const ps_index* idx, uint32_t id, char* buf, size_t cap);
 /* Host copy of the CSR index, for checks: bin_off[n_bins + 1], postings[n]
  * (value = id << 1 | is_y, sorted within each bin). Either pointer may be NULL. */
 int ps_index_host_arrays(const ps_index* idx, uint64_t* bin_off, uint32_t* postings);
+
+/* Schedule used by later searches on this index (not by batches in flight).
+ * PS_EINVAL for out-of-range fields. */
+int ps_index_set_schedule(ps_index* idx, const ps_schedule* schedule);
+int ps_index_get_schedule(const ps_index* idx, ps_schedule* schedule);
+
+/* Number of dense fragment bins stored as bitmaps (bins holding at least 1/16
+ * of all entries), and the device bytes of those bitmaps. */
+int ps_index_bitmap_bins(const ps_index* idx, uint32_t* n_bins, uint64_t* bytes);
 
 void ps_index_free(ps_index* idx);
 

@@ -8,6 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libpepscan.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["kernels.hip", "index.cpp", "capi.cpp"]
@@ -30,7 +31,7 @@ def build(verbose: bool = False) -> str:
     for src in sources():
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        cmds.append([HIPCC, *COMMON, *lang, "-I", CSRC, "-c", src, "-o", obj])
+        cmds.append([HIPCC, *COMMON, *lang, "-I", CSRC, "-I", INCLUDE, "-c", src, "-o", obj])
         objs.append(obj)
 
     def run(cmd):

@@ -55,6 +55,11 @@ class ps_search_params(C.Structure):
                 ("max_charge", C.c_uint32), ("schedule", C.c_int32), ("want_hist", C.c_int32)]
 
 
+class ps_schedule(C.Structure):
+    _fields_ = [("tile", C.c_uint32), ("coop_min", C.c_uint32), ("tiles_per_item", C.c_uint32),
+                ("groups_per_cu", C.c_uint32), ("use_bitmaps", C.c_uint32), ("pad", C.c_uint32)]
+
+
 HIT_DTYPE = np.dtype([("id", "<u4"), ("n_b", "<u2"), ("n_y", "<u2"), ("sum_q", "<u4"), ("pad", "<u4"),
                       ("hyperscore", "<f8")])
 STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8"), ("status", "<i4"),
@@ -78,6 +83,9 @@ _SIGS = [
                                  C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), _U64P]),
     ("ps_peptide", C.c_int, [_P, C.c_uint32, C.c_char_p, C.c_size_t]),
     ("ps_index_host_arrays", C.c_int, [_P, _P, _P]),
+    ("ps_index_set_schedule", C.c_int, [_P, C.POINTER(ps_schedule)]),
+    ("ps_index_get_schedule", C.c_int, [_P, C.POINTER(ps_schedule)]),
+    ("ps_index_bitmap_bins", C.c_int, [_P, C.POINTER(C.c_uint32), _U64P]),
     ("ps_index_free", None, [_P]),
     ("ps_workspace_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
     ("ps_search_batch", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra),
@@ -141,6 +149,9 @@ ps_index_shape = _fn("ps_index_shape")
 ps_index_entry = _fn("ps_index_entry")
 ps_peptide = _fn("ps_peptide")
 ps_index_host_arrays = _fn("ps_index_host_arrays")
+ps_index_set_schedule = _fn("ps_index_set_schedule")
+ps_index_get_schedule = _fn("ps_index_get_schedule")
+ps_index_bitmap_bins = _fn("ps_index_bitmap_bins")
 ps_index_free = _fn("ps_index_free")
 ps_workspace_bytes = _fn("ps_workspace_bytes")
 ps_search_batch = _fn("ps_search_batch")

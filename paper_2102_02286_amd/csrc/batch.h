@@ -4,14 +4,7 @@
 
 namespace ps {
 
-// Launch shape of the scan (chosen by default or by the autotuner).
-struct Schedule {
-    uint32_t tile;            // candidates per LDS counter tile
-    uint32_t heavy_min;       // segments longer than this are streamed by the whole workgroup
-    uint32_t tiles_per_item;  // persistent schedule: tiles per work item
-    uint32_t grid_per_cu;     // persistent schedule: workgroups per compute unit
-};
-
+using Schedule = ps_schedule;
 Schedule default_schedule();
 int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, const Schedule* sched);
 

@@ -81,7 +81,8 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
     kp->ent_stride = (uint32_t)stride;
     kp->seg_cap = (uint32_t)segs;
     kp->tile = sched->tile;
-    kp->heavy_min = sched->heavy_min;
+    kp->coop_min = sched->coop_min;
+    kp->use_bitmaps = sched->use_bitmaps;
     (void)ix;
     return PS_OK;
 }
@@ -89,10 +90,20 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
 Schedule default_schedule() {
     Schedule s;
     s.tile = 8192;
-    s.heavy_min = 2048;
+    s.coop_min = 1024;
     s.tiles_per_item = 8;
-    s.grid_per_cu = 4;
+    s.groups_per_cu = 4;
+    s.use_bitmaps = 1;
+    s.pad = 0;
     return s;
+}
+
+int check_schedule(const Schedule& s) {
+    if (s.tile < 1024 || s.tile > 32768 || s.tile % 256) return fail(PS_EINVAL, "tile must be 1024..32768, multiple of 256");
+    if (s.tiles_per_item < 1 || s.tiles_per_item > 4096) return fail(PS_EINVAL, "tiles_per_item must be 1..4096");
+    if (s.groups_per_cu < 1 || s.groups_per_cu > 8) return fail(PS_EINVAL, "groups_per_cu must be 1..8");
+    if (s.use_bitmaps > 1) return fail(PS_EINVAL, "use_bitmaps must be 0 or 1");
+    return PS_OK;
 }
 
 // Carve the batch workspace out of the caller's block.  Returns bytes needed.
@@ -230,7 +241,7 @@ int batch_begin(ps_index* ix, const ps_device* work, const ps_spectra* host_sp, 
     int rc = require_device();
     if (rc != PS_OK) return rc;
     if (!ix->on_device) return fail(PS_EINVAL, "index is not uploaded");
-    Schedule sc = default_schedule();
+    Schedule sc = ix->sched;
     KParams kp;
     rc = make_kparams(ix, params, &kp, &sc);
     if (rc != PS_OK) return rc;
@@ -311,7 +322,7 @@ extern "C" const char* ps_last_error(void) { return g_err.c_str(); }
 extern "C" int ps_workspace_bytes(const ps_index* ix, uint64_t n, uint64_t nnz, const ps_search_params* params,
                                   uint64_t* bytes) {
     if (!ix || !bytes) return fail(PS_EINVAL, "NULL argument");
-    Schedule sc = default_schedule();
+    Schedule sc = ix->sched;
     KParams kp;
     int rc = make_kparams(ix, params, &kp, &sc);
     if (rc != PS_OK) return rc;
@@ -399,3 +410,18 @@ extern "C" int ps_search_dump(ps_index* ix, const ps_device* work, const ps_spec
 }
 
 extern "C" void ps_batch_free(ps_batch* B) { batch_destroy(B); }
+
+extern "C" int ps_index_set_schedule(ps_index* ix, const ps_schedule* s) {
+    if (!ix || !s) return fail(PS_EINVAL, "NULL argument");
+    int rc = check_schedule(*s);
+    if (rc != PS_OK) return rc;
+    ix->sched = *s;
+    ix->sched.pad = 0;
+    return PS_OK;
+}
+
+extern "C" int ps_index_get_schedule(const ps_index* ix, ps_schedule* s) {
+    if (!ix || !s) return fail(PS_EINVAL, "NULL argument");
+    *s = ix->sched;
+    return PS_OK;
+}

@@ -8,6 +8,7 @@
 // peptide id (= rank in the sorted entry order) and a b/y bit, sorted by id
 // within each bin, so a precursor window is one contiguous sub-range per bin.
 #include "state.h"
+#include "batch.h"
 
 #include <algorithm>
 #include <atomic>
@@ -295,21 +296,56 @@ int index_build_host(ps_index* ix) {
     });
     // Postings of one id in one bin must be ordered b before y; ions of one id are
     // emitted b-first, so each bin is non-decreasing in (id << 1 | type).
+
+    // 4. dense bins (>= 1/16 of all entries, at most 64 of them) also as b/y
+    // bitmaps over the whole id space: for such a bin a bitmap is cheaper to read
+    // than its postings, and the scan adds them while scoring instead of with atomics
+    ix->heavy_slot.assign(nbins, -1);
+    ix->heavy_bins.clear();
+    ix->bm_words = (D + 31) / 32 + 1;
+    std::vector<std::pair<uint64_t, uint32_t>> dense;
+    const uint64_t min_count = std::max<uint64_t>(64, D / 16);
+    for (uint64_t bn = 0; bn < nbins; ++bn) {
+        uint64_t c = ix->bin_off[bn + 1] - ix->bin_off[bn];
+        if (c >= min_count) dense.push_back({c, (uint32_t)bn});
+    }
+    std::sort(dense.begin(), dense.end(), [](auto& a, auto& b) { return a.first > b.first || (a.first == b.first && a.second < b.second); });
+    if (dense.size() > 64) dense.resize(64);
+    std::sort(dense.begin(), dense.end(), [](auto& a, auto& b) { return a.second < b.second; });
+    ix->bitmaps.assign(dense.size() * 2 * ix->bm_words, 0u);
+    for (size_t h = 0; h < dense.size(); ++h) {
+        const uint32_t bn = dense[h].second;
+        ix->heavy_slot[bn] = (int32_t)h;
+        ix->heavy_bins.push_back(bn);
+        uint32_t* bb = ix->bitmaps.data() + h * 2 * ix->bm_words;
+        uint32_t* yb = bb + ix->bm_words;
+        for (uint64_t i = ix->bin_off[bn]; i < ix->bin_off[bn + 1]; ++i) {
+            const uint32_t p = ix->post[i], id = p >> 1;
+            (p & 1u ? yb : bb)[id >> 5] |= 1u << (id & 31);
+        }
+    }
     return PS_OK;
 }
 
 // Device layout: [mass][bin_off][post][lf][ls], each 256-byte aligned.
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-uint64_t index_device_layout(const ps_index* ix, uint64_t* off_mass, uint64_t* off_bin, uint64_t* off_post,
-                             uint64_t* off_lf, uint64_t* off_ls) {
+struct DevLayout {
+    uint64_t mass, bin, post, lf, ls, slot, bm, total;
+};
+
+static DevLayout index_device_layout(const ps_index* ix) {
+    DevLayout L;
     uint64_t o = 0;
-    *off_mass = o; o = align256(o + ix->mass.size() * sizeof(int64_t));
-    *off_bin = o; o = align256(o + ix->bin_off.size() * sizeof(uint64_t));
-    *off_post = o; o = align256(o + ix->post.size() * sizeof(uint32_t));
-    *off_lf = o; o = align256(o + kLfSize * sizeof(double));
-    *off_ls = o; o = align256(o + kLsSize * sizeof(double));
-    return o;
+    L.mass = o; o = align256(o + ix->mass.size() * sizeof(int64_t));
+    L.bin = o; o = align256(o + ix->bin_off.size() * sizeof(uint64_t));
+    L.post = o; o = align256(o + ix->post.size() * sizeof(uint32_t));
+    L.lf = o; o = align256(o + kLfSize * sizeof(double));
+    L.ls = o; o = align256(o + kLsSize * sizeof(double));
+    L.slot = o; o = align256(o + ix->heavy_slot.size() * sizeof(int32_t));
+    L.bm = o; o = align256(o + ix->bitmaps.size() * sizeof(uint32_t));
+    L.total = o;
+    return L;
 }
 
 void score_tables(std::vector<double>& lf, std::vector<double>& ls) {
@@ -377,6 +413,7 @@ extern "C" int ps_index_create(const ps_db_params* params, const char* residues,
         ix->seq.assign(residues, residues + total);
         ix->prot_off.assign(prot_off, prot_off + n_proteins + 1);
     } catch (...) { delete ix; return fail(PS_ENOMEM, "out of host memory"); }
+    ix->sched = default_schedule();
     int rc;
     try { rc = index_build_host(ix); } catch (...) { rc = fail(PS_ENOMEM, "out of host memory building the index"); }
     if (rc != PS_OK) { delete ix; return rc; }
@@ -386,8 +423,7 @@ extern "C" int ps_index_create(const ps_db_params* params, const char* residues,
 
 extern "C" int ps_index_device_bytes(const ps_index* ix, uint64_t* bytes) {
     if (!ix || !bytes) return fail(PS_EINVAL, "NULL argument");
-    uint64_t a, b, c, d, e;
-    *bytes = index_device_layout(ix, &a, &b, &c, &d, &e);
+    *bytes = index_device_layout(ix).total;
     return PS_OK;
 }
 
@@ -398,8 +434,8 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     if (ix->post.size() >= (1ull << 32))
         return fail(PS_EOVERFLOW, "index holds %llu postings; this build addresses at most 2^32",
                     (unsigned long long)ix->post.size());
-    uint64_t om, ob, op, olf, ols;
-    uint64_t need = index_device_layout(ix, &om, &ob, &op, &olf, &ols);
+    const DevLayout lay = index_device_layout(ix);
+    const uint64_t need = lay.total;
     if (!dev->base || dev->bytes < need)
         return fail(PS_ENOMEM, "index needs %llu device bytes, block has %llu", (unsigned long long)need,
                     (unsigned long long)dev->bytes);
@@ -412,19 +448,25 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     auto cp = [&](uint64_t off, const void* src, size_t n) {
         if (e == hipSuccess && n) e = hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, st);
     };
-    cp(om, ix->mass.data(), ix->mass.size() * sizeof(int64_t));
-    cp(ob, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
-    cp(op, ix->post.data(), ix->post.size() * sizeof(uint32_t));
-    cp(olf, lf.data(), lf.size() * sizeof(double));
-    cp(ols, ls.data(), ls.size() * sizeof(double));
+    cp(lay.mass, ix->mass.data(), ix->mass.size() * sizeof(int64_t));
+    cp(lay.bin, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
+    cp(lay.post, ix->post.data(), ix->post.size() * sizeof(uint32_t));
+    cp(lay.lf, lf.data(), lf.size() * sizeof(double));
+    cp(lay.ls, ls.data(), ls.size() * sizeof(double));
+    cp(lay.slot, ix->heavy_slot.data(), ix->heavy_slot.size() * sizeof(int32_t));
+    cp(lay.bm, ix->bitmaps.data(), ix->bitmaps.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
     DevIndex& d = ix->dev;
-    d.mass = (const int64_t*)(base + om);
-    d.bin_off = (const uint64_t*)(base + ob);
-    d.post = (const uint32_t*)(base + op);
-    d.lf = (const double*)(base + olf);
-    d.ls = (const double*)(base + ols);
+    d.mass = (const int64_t*)(base + lay.mass);
+    d.bin_off = (const uint64_t*)(base + lay.bin);
+    d.post = (const uint32_t*)(base + lay.post);
+    d.lf = (const double*)(base + lay.lf);
+    d.ls = (const double*)(base + lay.ls);
+    d.heavy_slot = (const int32_t*)(base + lay.slot);
+    d.bitmaps = (const uint32_t*)(base + lay.bm);
+    d.bm_words = ix->bm_words;
+    d.n_heavy = (uint32_t)ix->heavy_bins.size();
     d.n_pep = ix->mass.size();
     d.n_bins = ix->n_bins;
     d.n_post = ix->post.size();
@@ -500,6 +542,13 @@ extern "C" int ps_index_host_arrays(const ps_index* ix, uint64_t* bin_off, uint3
     if (!ix) return fail(PS_EINVAL, "NULL index");
     if (bin_off) memcpy(bin_off, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
     if (postings) memcpy(postings, ix->post.data(), ix->post.size() * sizeof(uint32_t));
+    return PS_OK;
+}
+
+extern "C" int ps_index_bitmap_bins(const ps_index* ix, uint32_t* n_bins, uint64_t* bytes) {
+    if (!ix) return fail(PS_EINVAL, "NULL index");
+    if (n_bins) *n_bins = (uint32_t)ix->heavy_bins.size();
+    if (bytes) *bytes = ix->bitmaps.size() * sizeof(uint32_t);
     return PS_OK;
 }
 

@@ -320,22 +320,30 @@ struct ScanArgs {
     uint32_t want_wide;        // which counter width this launch handles
 };
 
+constexpr uint32_t kCoopCap = 32;     // cooperative (long) segments per work item
+constexpr uint32_t kChunkTiles = 16;  // tiles per boundary chunk of the cooperative segments
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+
 struct ScanShared {
-    uint32_t nseg, nlight, nheavy;
+    uint32_t nseg, nlight, ncoop, nhh;
     unsigned long long red[kBlock / 64];
-    uint32_t item;
 };
 
-// LDS layout (dynamic): counters | seg_cur | seg_end | heavy_tend | seg_q | light | heavy | hist
+// LDS layout (dynamic):
+//   counters (also the top-k merge area) | seg_cur | seg_end | seg_next | bitmap-hit slot |
+//   seg_q | light list | bitmap-hit q | coop list | coop tile boundaries | histogram
 template <typename C>
 struct ScanLds {
     C* cnt;
     uint32_t* seg_cur;
     uint32_t* seg_end;
-    uint32_t* heavy_tend;
+    uint32_t* seg_next;   // posting value at seg_cur (kSentinel when exhausted)
+    uint32_t* hh_slot;    // bitmap slot of each dense-bin hit
     uint16_t* seg_q;
     uint16_t* light;
-    uint16_t* heavy;
+    uint16_t* hh_q;
+    uint16_t* coop;
+    uint32_t* bnd;        // [kCoopCap][kChunkTiles + 1]
     int32_t* hist;
     __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap, uint32_t top_k) {
         size_t o = 0;
@@ -345,22 +353,28 @@ struct ScanLds {
         o += ((cbytes > merge ? cbytes : merge) + 15) & ~(size_t)15;
         seg_cur = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         seg_end = (uint32_t*)(base + o); o += (size_t)segcap * 4;
-        heavy_tend = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        seg_next = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        hh_slot = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         seg_q = (uint16_t*)(base + o); o += (size_t)segcap * 2;
         light = (uint16_t*)(base + o); o += (size_t)segcap * 2;
-        heavy = (uint16_t*)(base + o); o += (size_t)segcap * 2;
+        hh_q = (uint16_t*)(base + o); o += (size_t)segcap * 2;
+        coop = (uint16_t*)(base + o); o += (size_t)kCoopCap * 2;
+        o = (o + 15) & ~(size_t)15;
+        bnd = (uint32_t*)(base + o); o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
         o = (o + 15) & ~(size_t)15;
         hist = (int32_t*)(base + o);
     }
 };
 
 size_t scan_lds_bytes(const KParams& kp, bool wide) {
-    size_t csz = wide ? 8 : 4;
+    const size_t csz = wide ? 8 : 4;
     // the counter area also holds the top-k merge: 1.5 * kBlock lists of top_k entries
-    size_t merge = (size_t)(kBlock + kBlock / 2) * kp.top_k * (wide ? 24 : 16);
+    const size_t merge = (size_t)(kBlock + kBlock / 2) * kp.top_k * (wide ? 24 : 16);
     size_t o = std::max((size_t)kp.tile * csz, merge);
     o = (o + 15) & ~(size_t)15;
-    o += (size_t)kp.seg_cap * (4 + 4 + 4 + 2 + 2 + 2);
+    o += (size_t)kp.seg_cap * (4 + 4 + 4 + 4 + 2 + 2 + 2) + kCoopCap * 2;
+    o = (o + 15) & ~(size_t)15;
+    o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
     o = (o + 15) & ~(size_t)15;
     o += (size_t)kHistBins * 4;
     return o;
@@ -373,24 +387,26 @@ template <typename C, int K, bool DUMP>
 __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint32_t s, uint32_t ida,
                           uint32_t idb, ps_hit* out) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
     const KParams& kp = A.kp;
     const DevIndex& ix = A.ix;
     const uint32_t n_ent = A.w.info[s].n_ent;
     const uint32_t* ent = A.w.entries + (uint64_t)s * kp.ent_stride;
     const int T = kp.tol;
+    const uint32_t width = (uint32_t)(2 * T + 1);
 
-    if (tid == 0) { sh.nseg = 0; sh.nlight = 0; sh.nheavy = 0; }
+    if (tid == 0) { sh.nseg = 0; sh.nlight = 0; sh.ncoop = 0; sh.nhh = 0; }
     for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) L.hist[i] = 0;
     __syncthreads();
 
-    // filter_2, part 1: every (entry, bin offset) -> posting segment inside [ida, idb)
+    // filter_2, part 1: every (entry, bin offset) -> posting run inside [ida, idb).
+    // Dense bins become bitmap hits; long runs are streamed cooperatively; the
+    // rest are walked by one thread each.
     unsigned long long lookups = 0, postings = 0;
-    const uint32_t npairs = n_ent * (uint32_t)(2 * T + 1);
+    const uint32_t npairs = n_ent * width;
     for (uint32_t k = tid; k < npairs; k += kBlock) {
-        const uint32_t e = ent[k / (uint32_t)(2 * T + 1)];
+        const uint32_t e = ent[k / width];
         if (e == kEntryInvalid) continue;
-        const int64_t bin = (int64_t)(e >> 8) + (int64_t)(k % (uint32_t)(2 * T + 1)) - T;
+        const int64_t bin = (int64_t)(e >> 8) + (int64_t)(k % width) - T;
         if (bin < 0 || bin >= (int64_t)ix.n_bins) continue;
         ++lookups;
         const uint32_t r0 = (uint32_t)ix.bin_off[bin], r1 = (uint32_t)ix.bin_off[bin + 1];
@@ -399,85 +415,145 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         const uint32_t s1 = lower_bound_u32(ix.post, s0, r1, idb << 1);
         if (s1 <= s0) continue;
         postings += s1 - s0;
-        const uint32_t slot = atomicAdd(&sh.nseg, 1u);
-        if (slot < kp.seg_cap) {
-            L.seg_cur[slot] = s0;
-            L.seg_end[slot] = s1;
-            L.seg_q[slot] = (uint16_t)(e & 0xFFu);
-            if (s1 - s0 > kp.heavy_min) L.heavy[atomicAdd(&sh.nheavy, 1u)] = (uint16_t)slot;
-            else L.light[atomicAdd(&sh.nlight, 1u)] = (uint16_t)slot;
+        const uint16_t q = (uint16_t)(e & 0xFFu);
+        if (kp.use_bitmaps) {
+            const int32_t hs = ix.heavy_slot[bin];
+            if (hs >= 0) {
+                const uint32_t h = atomicAdd(&sh.nhh, 1u);
+                L.hh_slot[h] = (uint32_t)hs;
+                L.hh_q[h] = q;
+                continue;
+            }
         }
+        const uint32_t slot = atomicAdd(&sh.nseg, 1u);
+        L.seg_cur[slot] = s0;
+        L.seg_end[slot] = s1;
+        L.seg_q[slot] = q;
+        if (s1 - s0 > kp.coop_min) {
+            const uint32_t c = atomicAdd(&sh.ncoop, 1u);
+            if (c < kCoopCap) { L.coop[c] = (uint16_t)slot; continue; }
+        }
+        L.seg_next[slot] = ix.post[s0];
+        L.light[atomicAdd(&sh.nlight, 1u)] = (uint16_t)slot;
     }
     __syncthreads();
-    const uint32_t nlight = sh.nlight, nheavy = sh.nheavy;
+    const uint32_t nlight = sh.nlight, nhh = sh.nhh;
+    const uint32_t ncoop = min(sh.ncoop, kCoopCap);
     // no posting in range: every counter stays 0 < k_min, nothing can be scored
-    const uint32_t id_end = (nlight + nheavy) ? idb : ida;
+    const uint32_t id_end = (nlight + ncoop + nhh) ? idb : ida;
 
     TopK<K, C> top;
     top.init();
     uint32_t scored = 0;
     const uint32_t kmin = kp.min_shared;
-    for (uint32_t tb = ida; tb < id_end; tb += kp.tile) {
-        const uint32_t te = min(id_end, tb + kp.tile);
-        const uint32_t nt = te - tb;
-        const uint32_t lim = te << 1;
-        for (uint32_t i = tid; i < nt; i += kBlock) L.cnt[i] = 0;
+    const uint64_t bmw = ix.bm_words;
+    if (id_end > ida)
+        for (uint32_t i = tid; i < kp.tile; i += kBlock) L.cnt[i] = 0;
+    __syncthreads();
+    for (uint32_t tc0 = ida; tc0 < id_end; tc0 += kChunkTiles * kp.tile) {
+        const uint32_t left = id_end - tc0;
+        const uint32_t nch = min(kChunkTiles, (left + kp.tile - 1) / kp.tile);
+        // tile boundaries of every cooperative run in this chunk
+        for (uint32_t q = tid; q < ncoop * nch; q += kBlock) {
+            const uint32_t c = q / nch, k = q - c * nch;
+            const uint32_t sg = L.coop[c];
+            const uint32_t lim = min(id_end, tc0 + (k + 1) * kp.tile) << 1;
+            L.bnd[c * (kChunkTiles + 1) + k + 1] = lower_bound_u32(ix.post, L.seg_cur[sg], L.seg_end[sg], lim);
+        }
+        for (uint32_t c = tid; c < ncoop; c += kBlock) L.bnd[c * (kChunkTiles + 1)] = L.seg_cur[L.coop[c]];
         __syncthreads();
-        // light segments: one thread walks each, up to the tile's end
-        for (uint32_t j = tid; j < nlight; j += kBlock) {
-            const uint32_t sg = L.light[j];
-            uint32_t cur = L.seg_cur[sg];
-            const uint32_t end = L.seg_end[sg];
-            const uint32_t q = L.seg_q[sg];
-            while (cur < end) {
-                const uint32_t p = ix.post[cur];
-                if (p >= lim) break;
-                atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
+        for (uint32_t k = 0; k < nch; ++k) {
+            const uint32_t tb = tc0 + k * kp.tile;
+            const uint32_t te = min(id_end, tb + kp.tile);
+            const uint32_t nt = te - tb;
+            const uint32_t lim = te << 1;
+            // short runs: one thread each; the next posting id is cached in LDS so a
+            // run with nothing in this tile costs no global load
+            for (uint32_t j = tid; j < nlight; j += kBlock) {
+                const uint32_t sg = L.light[j];
+                uint32_t nx = L.seg_next[sg];
+                if (nx >= lim) continue;
+                uint32_t cur = L.seg_cur[sg];
+                const uint32_t end = L.seg_end[sg];
+                const uint32_t q = L.seg_q[sg];
+                atomicAdd(&L.cnt[(nx >> 1) - tb], Cnt<C>::inc(nx & 1u, q));
                 ++cur;
+                while (true) {
+                    if (cur >= end) { nx = kSentinel; break; }
+                    const uint32_t p0 = ix.post[cur];
+                    const uint32_t p1 = cur + 1 < end ? ix.post[cur + 1] : kSentinel;
+                    const uint32_t p2 = cur + 2 < end ? ix.post[cur + 2] : kSentinel;
+                    const uint32_t p3 = cur + 3 < end ? ix.post[cur + 3] : kSentinel;
+                    if (p0 >= lim) { nx = p0; break; }
+                    atomicAdd(&L.cnt[(p0 >> 1) - tb], Cnt<C>::inc(p0 & 1u, q));
+                    ++cur;
+                    if (p1 >= lim) { nx = p1; break; }
+                    atomicAdd(&L.cnt[(p1 >> 1) - tb], Cnt<C>::inc(p1 & 1u, q));
+                    ++cur;
+                    if (p2 >= lim) { nx = p2; break; }
+                    atomicAdd(&L.cnt[(p2 >> 1) - tb], Cnt<C>::inc(p2 & 1u, q));
+                    ++cur;
+                    if (p3 >= lim) { nx = p3; break; }
+                    atomicAdd(&L.cnt[(p3 >> 1) - tb], Cnt<C>::inc(p3 & 1u, q));
+                    ++cur;
+                }
+                L.seg_cur[sg] = cur;
+                L.seg_next[sg] = nx;
             }
-            L.seg_cur[sg] = cur;
-        }
-        // heavy segments: one wavefront finds each one's end in this tile
-        for (uint32_t h = wave; h < nheavy; h += kBlock / 64) {
-            const uint32_t sg = L.heavy[h];
-            const uint32_t e = wave_lower_bound(ix.post, L.seg_cur[sg], L.seg_end[sg], lim);
-            if (lane == 0) L.heavy_tend[h] = e;
-        }
-        __syncthreads();
-        // ... then the whole workgroup streams each heavy run, coalesced
-        for (uint32_t h = 0; h < nheavy; ++h) {
-            const uint32_t sg = L.heavy[h];
-            const uint32_t c0 = L.seg_cur[sg], c1 = L.heavy_tend[h];
-            const uint32_t q = L.seg_q[sg];
-            for (uint32_t i = c0 + tid; i < c1; i += kBlock) {
-                const uint32_t p = ix.post[i];
-                atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
-            }
-        }
-        __syncthreads();
-        for (uint32_t h = tid; h < nheavy; h += kBlock) L.seg_cur[L.heavy[h]] = L.heavy_tend[h];
-        // candidate filter, hyperscore, histogram, top-k
-        for (uint32_t i = tid; i < nt; i += kBlock) {
-            const C c = L.cnt[i];
-            const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c);
-            if (nb + ny < kmin) continue;
-            const uint32_t sq = Cnt<C>::s(c);
-            const double h = (ix.lf[nb] + ix.lf[ny]) + ix.ls[sq];
-            const double hb = floor(10.0 * h);
-            const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
-            atomicAdd(&L.hist[bin], 1);
-            ++scored;
-            top.insert(h, tb + i, c);
-            if (DUMP) {
-                const unsigned long long slot = atomicAdd(&A.w.counters[kCtrDump], 1ull);
-                if (slot < A.w.dump_cap) {
-                    A.w.dump_spec[slot] = s;
-                    A.w.dump_id[slot] = tb + i;
-                    A.w.dump_cnt_lo[slot] = (nb & 0xFFFFu) | (ny << 16);
-                    A.w.dump_cnt_hi[slot] = sq;
+            // long runs: the whole workgroup streams this tile's part, coalesced
+            for (uint32_t c = 0; c < ncoop; ++c) {
+                const uint32_t b0 = L.bnd[c * (kChunkTiles + 1) + k], b1 = L.bnd[c * (kChunkTiles + 1) + k + 1];
+                const uint32_t q = L.seg_q[L.coop[c]];
+                uint32_t i = b0 + tid;
+                for (; i + 3 * kBlock < b1; i += 4 * kBlock) {
+                    const uint32_t p0 = ix.post[i], p1 = ix.post[i + kBlock];
+                    const uint32_t p2 = ix.post[i + 2 * kBlock], p3 = ix.post[i + 3 * kBlock];
+                    atomicAdd(&L.cnt[(p0 >> 1) - tb], Cnt<C>::inc(p0 & 1u, q));
+                    atomicAdd(&L.cnt[(p1 >> 1) - tb], Cnt<C>::inc(p1 & 1u, q));
+                    atomicAdd(&L.cnt[(p2 >> 1) - tb], Cnt<C>::inc(p2 & 1u, q));
+                    atomicAdd(&L.cnt[(p3 >> 1) - tb], Cnt<C>::inc(p3 & 1u, q));
+                }
+                for (; i < b1; i += kBlock) {
+                    const uint32_t p = ix.post[i];
+                    atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
                 }
             }
+            __syncthreads();
+            // dense bins from their bitmaps, then the candidate filter, hyperscore,
+            // histogram and top-k; counters are cleared for the next tile on the way
+            for (uint32_t i = tid; i < nt; i += kBlock) {
+                C c = L.cnt[i];
+                L.cnt[i] = 0;
+                const uint32_t id = tb + i;
+                for (uint32_t h = 0; h < nhh; ++h) {
+                    const uint32_t* bm = ix.bitmaps + (uint64_t)L.hh_slot[h] * 2 * bmw;
+                    const uint32_t q = L.hh_q[h];
+                    const uint32_t wd = id >> 5, sh5 = id & 31u;
+                    if ((bm[wd] >> sh5) & 1u) c += Cnt<C>::inc(0u, q);
+                    if ((bm[bmw + wd] >> sh5) & 1u) c += Cnt<C>::inc(1u, q);
+                }
+                const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c);
+                if (nb + ny < kmin) continue;
+                const uint32_t sq = Cnt<C>::s(c);
+                const double h = (ix.lf[nb] + ix.lf[ny]) + ix.ls[sq];
+                const double hb = floor(10.0 * h);
+                const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
+                atomicAdd(&L.hist[bin], 1);
+                ++scored;
+                top.insert(h, id, c);
+                if (DUMP) {
+                    const unsigned long long slot = atomicAdd(&A.w.counters[kCtrDump], 1ull);
+                    if (slot < A.w.dump_cap) {
+                        A.w.dump_spec[slot] = s;
+                        A.w.dump_id[slot] = id;
+                        A.w.dump_cnt_lo[slot] = (nb & 0xFFFFu) | (ny << 16);
+                        A.w.dump_cnt_hi[slot] = sq;
+                    }
+                }
+            }
+            __syncthreads();
         }
+        for (uint32_t c = tid; c < ncoop; c += kBlock) L.seg_cur[L.coop[c]] = L.bnd[c * (kChunkTiles + 1) + nch];
         __syncthreads();
     }
 
@@ -581,6 +657,8 @@ hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KPa
     else e = k8 ? launch_scan_plain_t<uint32_t, 8, false>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, false>(a, sp.n, stream);
     if (e != hipSuccess) return e;
     a.want_wide = 1;
+    // 64-bit counters take twice the LDS per candidate: halve the tile if needed
+    if (a.kp.tile > 16384) a.kp.tile = 16384;
     if (dump) e = k8 ? launch_scan_plain_t<unsigned long long, 8, true>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, true>(a, sp.n, stream);
     else e = k8 ? launch_scan_plain_t<unsigned long long, 8, false>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, false>(a, sp.n, stream);
     return e;
@@ -601,7 +679,6 @@ struct MergeArgs {
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     __shared__ long long s_num[kHistBins];
     __shared__ long long s_tail[kHistBins];
-    __shared__ double s_red[kBlock / 64];
     __shared__ long long s_redl[kBlock / 64];
     __shared__ ps_hit s_top[PS_MAX_TOP_K];
     __shared__ int s_mode;

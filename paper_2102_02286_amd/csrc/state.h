@@ -46,6 +46,12 @@ struct ps_index {
     std::vector<uint32_t> post;
     uint32_t max_len_seen = 0;
     int64_t min_residue = 0;
+    // dense bins as b/y bitmaps over all ids (slot h: words [2h*W, 2h*W + W) = b, then y)
+    std::vector<int32_t> heavy_slot;      // [n_bins], -1 = postings only
+    std::vector<uint32_t> heavy_bins;     // bin of each slot
+    std::vector<uint32_t> bitmaps;        // [n_heavy * 2 * bm_words]
+    uint64_t bm_words = 0;
+    ps_schedule sched{};
     // device copy
     bool on_device = false;
     ps::DevIndex dev{};

@@ -96,6 +96,23 @@ class HostIndex:
         check(capi.ps_index_host_arrays(self.handle, ptr(off), ptr(post)))
         return off, post
 
+    def schedule(self) -> capi.ps_schedule:
+        sc = capi.ps_schedule()
+        check(capi.ps_index_get_schedule(self.handle, C.byref(sc)))
+        return sc
+
+    def set_schedule(self, **fields) -> capi.ps_schedule:
+        sc = self.schedule()
+        for k, v in fields.items():
+            setattr(sc, k, int(v))
+        check(capi.ps_index_set_schedule(self.handle, C.byref(sc)), "ps_index_set_schedule")
+        return sc
+
+    def bitmap_bins(self):
+        n, b = C.c_uint32(), C.c_uint64()
+        check(capi.ps_index_bitmap_bins(self.handle, C.byref(n), C.byref(b)))
+        return n.value, b.value
+
     def device_bytes(self) -> int:
         b = C.c_uint64()
         check(capi.ps_index_device_bytes(self.handle, C.byref(b)))

@@ -6,6 +6,8 @@ table values on both sides, so they agree to the last bit; expect values go
 through GPU log10/pow and a differently ordered sum, so they are held to 1e-5
 relative.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -142,6 +144,25 @@ def test_small_open_permutation_and_split_invariance(small_open):
     # the same batch twice: bit-identical
     r2 = engine.search(ix, sp, prm)
     assert r2.hits.tobytes() == r0.hits.tobytes() and r2.hist.tobytes() == r0.hist.tobytes()
+
+
+@pytest.mark.parametrize("sched", [dict(use_bitmaps=0), dict(tile=1024, coop_min=64),
+                                   dict(tile=32768, coop_min=100000), dict(tile=4096, coop_min=0)])
+def test_schedules_give_identical_results(small_open, sched):
+    """Tile size, cooperative threshold and dense-bin bitmaps change only speed."""
+    w, prot, sp, ix, db, (oh, ost, og) = small_open
+    assert ix.bitmap_bins()[0] >= 1
+    old = ix.schedule()
+    try:
+        ix.set_schedule(**sched)
+        _say(f"schedule {sched}")
+        prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                                   max_charge=3)
+        res = engine.search(ix, sp, prm)
+        assert_parity(res, oh, ost, og)
+        assert res.postings == int(ost["pairs_total"].sum())
+    finally:
+        capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
 
 
 # ---------------------------------------------------------------------------
