@@ -327,6 +327,8 @@ constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 struct ScanShared {
     uint32_t nseg, nlight, ncoop, nhh;
     unsigned long long red[kBlock / 64];
+    unsigned long long acc[PS_MAX_TOP_K * 3];    // top-k accumulators (24-byte entries)
+    unsigned long long acc2[PS_MAX_TOP_K * 3];
 };
 
 // LDS layout (dynamic):
@@ -348,9 +350,8 @@ struct ScanLds {
     __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap, uint32_t top_k) {
         size_t o = 0;
         cnt = (C*)(base + o);
-        const size_t merge = (size_t)(kBlock + kBlock / 2) * top_k * sizeof(MergeEnt<C>);
-        const size_t cbytes = (size_t)tile * sizeof(C);
-        o += ((cbytes > merge ? cbytes : merge) + 15) & ~(size_t)15;
+        o += ((size_t)tile * sizeof(C) + 15) & ~(size_t)15;
+        (void)top_k;
         seg_cur = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         seg_end = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         seg_next = (uint32_t*)(base + o); o += (size_t)segcap * 4;
@@ -368,10 +369,7 @@ struct ScanLds {
 
 size_t scan_lds_bytes(const KParams& kp, bool wide) {
     const size_t csz = wide ? 8 : 4;
-    // the counter area also holds the top-k merge: 1.5 * kBlock lists of top_k entries
-    const size_t merge = (size_t)(kBlock + kBlock / 2) * kp.top_k * (wide ? 24 : 16);
-    size_t o = std::max((size_t)kp.tile * csz, merge);
-    o = (o + 15) & ~(size_t)15;
+    size_t o = ((size_t)kp.tile * csz + 15) & ~(size_t)15;
     o += (size_t)kp.seg_cap * (4 + 4 + 4 + 4 + 2 + 2 + 2) + kCoopCap * 2;
     o = (o + 15) & ~(size_t)15;
     o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
@@ -557,36 +555,56 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         __syncthreads();
     }
 
-    // top-k of the item: every thread's best top_k go to LDS (over the counter
-    // tile), then rounds of pairwise merges, ping-ponging between two regions,
-    // leave the workgroup's list at the front of one of them
+    // top-k of the item: the threads' lists are merged group by group (a group's
+    // lists and the ping-pong space of its merge tree fit in the counter area),
+    // each group's best list then merged into an accumulator
     const uint32_t kk = kp.top_k;
-    MergeEnt<C>* ma = (MergeEnt<C>*)L.cnt;
-    MergeEnt<C>* mb = ma + kBlock * kk;
+    const uint32_t G = kp.merge_groups, gsz = kBlock / G;
+    MergeEnt<C>* acc = (MergeEnt<C>*)sh.acc;
+    MergeEnt<C>* acc2 = (MergeEnt<C>*)sh.acc2;
+    if (tid < kk) { acc[tid].h = -INFINITY; acc[tid].id = 0xFFFFFFFFu; acc[tid].c = 0; }
+    for (uint32_t g = 0; g < G; ++g) {
+        MergeEnt<C>* ma = (MergeEnt<C>*)L.cnt;
+        MergeEnt<C>* mb = ma + gsz * kk;
+        __syncthreads();
+        if (tid / gsz == g) {
+            const uint32_t r = tid - g * gsz;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if ((uint32_t)j < kk) {
-            MergeEnt<C> m; m.h = top.h[j]; m.id = top.id[j]; m.c = top.c[j];
-            ma[tid * kk + j] = m;
-        }
-    }
-    __syncthreads();
-    for (uint32_t half = kBlock / 2; half >= 1; half >>= 1) {
-        if (tid < half) {
-            const MergeEnt<C>* x = ma + tid * kk;
-            const MergeEnt<C>* y = ma + (tid + half) * kk;
-            MergeEnt<C>* o = mb + tid * kk;
-            uint32_t ix_ = 0, iy = 0;
-            for (uint32_t j = 0; j < kk; ++j) {
-                const bool takex = TopK<K, C>::better(x[ix_].h, x[ix_].id, y[iy].h, y[iy].id);
-                o[j] = takex ? x[ix_] : y[iy];
-                if (takex) ++ix_; else ++iy;
+            for (int j = 0; j < K; ++j) {
+                if ((uint32_t)j < kk) {
+                    MergeEnt<C> m; m.h = top.h[j]; m.id = top.id[j]; m.c = top.c[j];
+                    ma[r * kk + j] = m;
+                }
             }
         }
         __syncthreads();
-        MergeEnt<C>* t = ma; ma = mb; mb = t;
+        for (uint32_t half = gsz / 2; half >= 1; half >>= 1) {
+            if (tid < half) {
+                const MergeEnt<C>* x = ma + tid * kk;
+                const MergeEnt<C>* y = ma + (tid + half) * kk;
+                MergeEnt<C>* o = mb + tid * kk;
+                uint32_t ix_ = 0, iy = 0;
+                for (uint32_t j = 0; j < kk; ++j) {
+                    const bool takex = TopK<K, C>::better(x[ix_].h, x[ix_].id, y[iy].h, y[iy].id);
+                    o[j] = takex ? x[ix_] : y[iy];
+                    if (takex) ++ix_; else ++iy;
+                }
+            }
+            __syncthreads();
+            MergeEnt<C>* t = ma; ma = mb; mb = t;
+        }
+        if (tid == 0) {
+            uint32_t ix_ = 0, iy = 0;
+            for (uint32_t j = 0; j < kk; ++j) {
+                const bool takex = TopK<K, C>::better(acc[ix_].h, acc[ix_].id, ma[iy].h, ma[iy].id);
+                acc2[j] = takex ? acc[ix_] : ma[iy];
+                if (takex) ++ix_; else ++iy;
+            }
+            for (uint32_t j = 0; j < kk; ++j) acc[j] = acc2[j];
+        }
     }
-    const MergeEnt<C>* ml = ma;
+    __syncthreads();
+    const MergeEnt<C>* ml = acc;
     const unsigned long long sc = block_sum<unsigned long long>(scored, sh.red);   // has barriers
     if (tid < kk) {
         const MergeEnt<C> m = ml[tid];
@@ -635,8 +653,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
     scan_item<C, K, DUMP>(A, sh, L, s, inf.lo, inf.hi, out);
 }
 
+// Thread groups for the top-k merge: a group's lists plus the ping-pong half
+// must fit in the counter area.
+static uint32_t merge_groups(const KParams& kp, bool wide) {
+    const size_t area = (size_t)kp.tile * (wide ? 8 : 4);
+    const size_t esz = wide ? 24 : 16;
+    uint32_t g = 1;
+    while (g < (uint32_t)kBlock && (size_t)(kBlock / g + kBlock / g / 2) * kp.top_k * esz > area) g *= 2;
+    return g;
+}
+
 template <typename C, int K, bool DUMP>
-static hipError_t launch_scan_plain_t(const ScanArgs& a, uint64_t n, hipStream_t stream) {
+static hipError_t launch_scan_plain_t(ScanArgs a, uint64_t n, hipStream_t stream) {
+    a.kp.merge_groups = merge_groups(a.kp, sizeof(C) == 8);
     const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
     hipError_t e = hipFuncSetAttribute((const void*)k_scan_plain<C, K, DUMP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
