@@ -89,11 +89,11 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
 
 Schedule default_schedule() {
     Schedule s;
-    s.tile = 8192;
-    s.coop_min = 1024;
-    s.tiles_per_item = 8;
+    s.tile = 4096;
+    s.coop_min = 4096;
+    s.tiles_per_item = 16;
     s.groups_per_cu = 4;
-    s.use_bitmaps = 1;
+    s.use_bitmaps = 0;
     s.pad = 0;
     return s;
 }

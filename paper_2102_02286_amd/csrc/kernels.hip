@@ -323,9 +323,11 @@ struct ScanArgs {
 constexpr uint32_t kCoopCap = 32;     // cooperative (long) segments per work item
 constexpr uint32_t kChunkTiles = 16;  // tiles per boundary chunk of the cooperative segments
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+constexpr uint32_t kBmCap = 4;        // dense-bin bitmap hits per work item (more go the posting route)
+constexpr uint32_t kCandCap = 512;    // scored candidates buffered per tile before scoring
 
 struct ScanShared {
-    uint32_t nseg, nlight, ncoop, nhh;
+    uint32_t nseg, nlight, ncoop, nhh, ncand;
     unsigned long long red[kBlock / 64];
     unsigned long long acc[PS_MAX_TOP_K * 3];    // top-k accumulators (24-byte entries)
     unsigned long long acc2[PS_MAX_TOP_K * 3];
@@ -346,36 +348,62 @@ struct ScanLds {
     uint16_t* hh_q;
     uint16_t* coop;
     uint32_t* bnd;        // [kCoopCap][kChunkTiles + 1]
+    uint32_t* bmw;        // [kBmCap][2][tile/32 + 2] bitmap words of the current tile
+    C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter
+    uint16_t* cand_idx;   // [kCandCap] their positions in the tile
     int32_t* hist;
-    __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap, uint32_t top_k) {
+    __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap) {
         size_t o = 0;
         cnt = (C*)(base + o);
         o += ((size_t)tile * sizeof(C) + 15) & ~(size_t)15;
-        (void)top_k;
+        cand_cnt = (C*)(base + o); o += (size_t)kCandCap * sizeof(C);
         seg_cur = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         seg_end = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         seg_next = (uint32_t*)(base + o); o += (size_t)segcap * 4;
-        hh_slot = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        hh_slot = (uint32_t*)(base + o); o += (size_t)kBmCap * 4;
+        bnd = (uint32_t*)(base + o); o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
+        bmw = (uint32_t*)(base + o); o += (size_t)kBmCap * 2 * (tile / 32 + 2) * 4;
+        hist = (int32_t*)(base + o); o += (size_t)kHistBins * 4;
         seg_q = (uint16_t*)(base + o); o += (size_t)segcap * 2;
         light = (uint16_t*)(base + o); o += (size_t)segcap * 2;
-        hh_q = (uint16_t*)(base + o); o += (size_t)segcap * 2;
+        hh_q = (uint16_t*)(base + o); o += (size_t)kBmCap * 2;
         coop = (uint16_t*)(base + o); o += (size_t)kCoopCap * 2;
-        o = (o + 15) & ~(size_t)15;
-        bnd = (uint32_t*)(base + o); o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
-        o = (o + 15) & ~(size_t)15;
-        hist = (int32_t*)(base + o);
+        cand_idx = (uint16_t*)(base + o);
     }
 };
 
 size_t scan_lds_bytes(const KParams& kp, bool wide) {
     const size_t csz = wide ? 8 : 4;
     size_t o = ((size_t)kp.tile * csz + 15) & ~(size_t)15;
-    o += (size_t)kp.seg_cap * (4 + 4 + 4 + 4 + 2 + 2 + 2) + kCoopCap * 2;
-    o = (o + 15) & ~(size_t)15;
-    o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
-    o = (o + 15) & ~(size_t)15;
-    o += (size_t)kHistBins * 4;
-    return o;
+    o += (size_t)kCandCap * csz;
+    o += (size_t)kp.seg_cap * 12 + (size_t)kBmCap * 4 + (size_t)kCoopCap * (kChunkTiles + 1) * 4;
+    o += (size_t)kBmCap * 2 * (kp.tile / 32 + 2) * 4 + (size_t)kHistBins * 4;
+    o += (size_t)kp.seg_cap * 4 + (size_t)kBmCap * 2 + (size_t)kCoopCap * 2 + (size_t)kCandCap * 2;
+    return (o + 15) & ~(size_t)15;
+}
+
+// Hyperscore of one candidate that passed the filter: log10(n_b! n_y! S) from
+// the fp64 tables, its histogram bin (width 0.1, last bin open), and the
+// thread's top-k list.
+template <typename C, int K, bool DUMP>
+__device__ __forceinline__ void score_one(const ScanArgs& A, ScanLds<C>& L, TopK<K, C>& top, uint32_t s,
+                                          uint32_t id, C c, uint32_t& scored) {
+    const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c), sq = Cnt<C>::s(c);
+    const double h = (A.ix.lf[nb] + A.ix.lf[ny]) + A.ix.ls[sq];
+    const double hb = floor(10.0 * h);
+    const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
+    atomicAdd(&L.hist[bin], 1);
+    ++scored;
+    top.insert(h, id, c);
+    if (DUMP) {
+        const unsigned long long slot = atomicAdd(&A.w.counters[kCtrDump], 1ull);
+        if (slot < A.w.dump_cap) {
+            A.w.dump_spec[slot] = s;
+            A.w.dump_id[slot] = id;
+            A.w.dump_cnt_lo[slot] = (nb & 0xFFFFu) | (ny << 16);
+            A.w.dump_cnt_hi[slot] = sq;
+        }
+    }
 }
 
 // One work item: spectrum s, candidate ids [ida, idb).  Writes the item's top
@@ -418,9 +446,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             const int32_t hs = ix.heavy_slot[bin];
             if (hs >= 0) {
                 const uint32_t h = atomicAdd(&sh.nhh, 1u);
-                L.hh_slot[h] = (uint32_t)hs;
-                L.hh_q[h] = q;
-                continue;
+                if (h < kBmCap) {
+                    L.hh_slot[h] = (uint32_t)hs;
+                    L.hh_q[h] = q;
+                    continue;
+                }
             }
         }
         const uint32_t slot = atomicAdd(&sh.nseg, 1u);
@@ -435,7 +465,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         L.light[atomicAdd(&sh.nlight, 1u)] = (uint16_t)slot;
     }
     __syncthreads();
-    const uint32_t nlight = sh.nlight, nhh = sh.nhh;
+    const uint32_t nlight = sh.nlight, nhh = min(sh.nhh, kBmCap);
     const uint32_t ncoop = min(sh.ncoop, kCoopCap);
     // no posting in range: every counter stays 0 < k_min, nothing can be scored
     const uint32_t id_end = (nlight + ncoop + nhh) ? idb : ida;
@@ -445,8 +475,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     uint32_t scored = 0;
     const uint32_t kmin = kp.min_shared;
     const uint64_t bmw = ix.bm_words;
+    (void)bmw;
     if (id_end > ida)
         for (uint32_t i = tid; i < kp.tile; i += kBlock) L.cnt[i] = 0;
+    if (tid == 0) sh.ncand = 0;
+    const uint32_t wpt = kp.tile / 32 + 2;
     __syncthreads();
     for (uint32_t tc0 = ida; tc0 < id_end; tc0 += kChunkTiles * kp.tile) {
         const uint32_t left = id_end - tc0;
@@ -465,6 +498,14 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             const uint32_t te = min(id_end, tb + kp.tile);
             const uint32_t nt = te - tb;
             const uint32_t lim = te << 1;
+            if (tid == 0) sh.ncand = 0;
+            // this tile's words of the dense-bin bitmaps, staged in LDS
+            for (uint32_t q = tid; q < nhh * 2 * wpt; q += kBlock) {
+                const uint32_t h = q / (2 * wpt), r = q - h * 2 * wpt;
+                const uint32_t half = r / wpt, wi = r - half * wpt;
+                const uint64_t word = (uint64_t)(tb >> 5) + wi;
+                L.bmw[q] = word < bmw ? ix.bitmaps[(uint64_t)L.hh_slot[h] * 2 * bmw + half * bmw + word] : 0u;
+            }
             // short runs: one thread each; the next posting id is cached in LDS so a
             // run with nothing in this tile costs no global load
             for (uint32_t j = tid; j < nlight; j += kBlock) {
@@ -517,38 +558,35 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                 }
             }
             __syncthreads();
-            // dense bins from their bitmaps, then the candidate filter, hyperscore,
-            // histogram and top-k; counters are cleared for the next tile on the way
+            // candidate filter: counters (plus dense bins from the staged bitmap
+            // words) are read and cleared for the next tile; candidates with at
+            // least k_min shared peaks are buffered for scoring
+            const uint32_t w0 = tb >> 5;
             for (uint32_t i = tid; i < nt; i += kBlock) {
                 C c = L.cnt[i];
                 L.cnt[i] = 0;
                 const uint32_t id = tb + i;
                 for (uint32_t h = 0; h < nhh; ++h) {
-                    const uint32_t* bm = ix.bitmaps + (uint64_t)L.hh_slot[h] * 2 * bmw;
+                    const uint32_t* bw = L.bmw + h * 2 * wpt;
+                    const uint32_t wd = (id >> 5) - w0, sh5 = id & 31u;
                     const uint32_t q = L.hh_q[h];
-                    const uint32_t wd = id >> 5, sh5 = id & 31u;
-                    if ((bm[wd] >> sh5) & 1u) c += Cnt<C>::inc(0u, q);
-                    if ((bm[bmw + wd] >> sh5) & 1u) c += Cnt<C>::inc(1u, q);
+                    if ((bw[wd] >> sh5) & 1u) c += Cnt<C>::inc(0u, q);
+                    if ((bw[wpt + wd] >> sh5) & 1u) c += Cnt<C>::inc(1u, q);
                 }
-                const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c);
-                if (nb + ny < kmin) continue;
-                const uint32_t sq = Cnt<C>::s(c);
-                const double h = (ix.lf[nb] + ix.lf[ny]) + ix.ls[sq];
-                const double hb = floor(10.0 * h);
-                const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
-                atomicAdd(&L.hist[bin], 1);
-                ++scored;
-                top.insert(h, id, c);
-                if (DUMP) {
-                    const unsigned long long slot = atomicAdd(&A.w.counters[kCtrDump], 1ull);
-                    if (slot < A.w.dump_cap) {
-                        A.w.dump_spec[slot] = s;
-                        A.w.dump_id[slot] = id;
-                        A.w.dump_cnt_lo[slot] = (nb & 0xFFFFu) | (ny << 16);
-                        A.w.dump_cnt_hi[slot] = sq;
-                    }
+                if (Cnt<C>::nb(c) + Cnt<C>::ny(c) < kmin) continue;
+                const uint32_t slot = atomicAdd(&sh.ncand, 1u);
+                if (slot < kCandCap) {
+                    L.cand_idx[slot] = (uint16_t)i;
+                    L.cand_cnt[slot] = c;
+                } else {
+                    score_one<C, K, DUMP>(A, L, top, s, id, c, scored);   // buffer full: score in place
                 }
             }
+            __syncthreads();
+            // hyperscore, histogram, top-k over the buffered candidates
+            const uint32_t ncand = min(sh.ncand, kCandCap);
+            for (uint32_t j = tid; j < ncand; j += kBlock)
+                score_one<C, K, DUMP>(A, L, top, s, tb + L.cand_idx[j], L.cand_cnt[j], scored);
             __syncthreads();
         }
         for (uint32_t c = tid; c < ncoop; c += kBlock) L.seg_cur[L.coop[c]] = L.bnd[c * (kChunkTiles + 1) + nch];
@@ -636,7 +674,7 @@ template <typename C, int K, bool DUMP>
 __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
-    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap, A.kp.top_k);
+    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap);
     const uint32_t s = blockIdx.x;
     const SpecInfo inf = A.w.info[s];
     ps_hit* out = A.w.partial + (uint64_t)s * A.kp.top_k;
