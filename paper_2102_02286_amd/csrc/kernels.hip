@@ -352,7 +352,7 @@ struct ScanLds {
     C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter
     uint16_t* cand_idx;   // [kCandCap] their positions in the tile
     int32_t* hist;
-    __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap) {
+    __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap, uint32_t bmcap) {
         size_t o = 0;
         cnt = (C*)(base + o);
         o += ((size_t)tile * sizeof(C) + 15) & ~(size_t)15;
@@ -362,7 +362,7 @@ struct ScanLds {
         seg_next = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         hh_slot = (uint32_t*)(base + o); o += (size_t)kBmCap * 4;
         bnd = (uint32_t*)(base + o); o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
-        bmw = (uint32_t*)(base + o); o += (size_t)kBmCap * 2 * (tile / 32 + 2) * 4;
+        bmw = (uint32_t*)(base + o); o += (size_t)bmcap * 2 * (tile / 32 + 2) * 4;
         hist = (int32_t*)(base + o); o += (size_t)kHistBins * 4;
         seg_q = (uint16_t*)(base + o); o += (size_t)segcap * 2;
         light = (uint16_t*)(base + o); o += (size_t)segcap * 2;
@@ -377,7 +377,7 @@ size_t scan_lds_bytes(const KParams& kp, bool wide) {
     size_t o = ((size_t)kp.tile * csz + 15) & ~(size_t)15;
     o += (size_t)kCandCap * csz;
     o += (size_t)kp.seg_cap * 12 + (size_t)kBmCap * 4 + (size_t)kCoopCap * (kChunkTiles + 1) * 4;
-    o += (size_t)kBmCap * 2 * (kp.tile / 32 + 2) * 4 + (size_t)kHistBins * 4;
+    o += (size_t)(kp.use_bitmaps ? kBmCap : 0) * 2 * (kp.tile / 32 + 2) * 4 + (size_t)kHistBins * 4;
     o += (size_t)kp.seg_cap * 4 + (size_t)kBmCap * 2 + (size_t)kCoopCap * 2 + (size_t)kCandCap * 2;
     return (o + 15) & ~(size_t)15;
 }
@@ -674,7 +674,7 @@ template <typename C, int K, bool DUMP>
 __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
-    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap);
+    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap, A.kp.use_bitmaps ? kBmCap : 0);
     const uint32_t s = blockIdx.x;
     const SpecInfo inf = A.w.info[s];
     ps_hit* out = A.w.partial + (uint64_t)s * A.kp.top_k;
@@ -724,8 +724,8 @@ hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KPa
     else e = k8 ? launch_scan_plain_t<uint32_t, 8, false>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, false>(a, sp.n, stream);
     if (e != hipSuccess) return e;
     a.want_wide = 1;
-    // 64-bit counters take twice the LDS per candidate: halve the tile if needed
-    if (a.kp.tile > 16384) a.kp.tile = 16384;
+    // 64-bit counters take twice the LDS per candidate: halve the tile until it fits
+    while (a.kp.tile > 1024 && scan_lds_bytes(a.kp, true) > kMaxLds) a.kp.tile /= 2;
     if (dump) e = k8 ? launch_scan_plain_t<unsigned long long, 8, true>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, true>(a, sp.n, stream);
     else e = k8 ? launch_scan_plain_t<unsigned long long, 8, false>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, false>(a, sp.n, stream);
     return e;
