@@ -250,6 +250,47 @@ int ps_batch_timing(ps_batch* batch, double* scan_ms, uint32_t* scan_launches, u
 
 void ps_batch_free(ps_batch* batch);
 
+/* ---- reusable plans (persistent scan captured as a hipGraph) ------------ */
+
+typedef struct ps_plan ps_plan;
+
+/* Device bytes of a plan for batches of up to n_cap spectra and nnz_cap peaks. */
+int ps_plan_bytes(const ps_index* idx, uint64_t n_cap, uint64_t nnz_cap, const ps_search_params* params,
+                  uint64_t* bytes);
+
+/* Carve a plan out of `work` (which must hold ps_plan_bytes) and capture the
+ * whole kernel sequence of a search -- prep and window, work list, scan,
+ * merge and expect values -- once as a hipGraph on work->stream (a private
+ * non-blocking stream when NULL).  Every later run replays that graph; the
+ * kernels read the batch size from device memory, so any batch up to the
+ * capacity reuses it.  The index's current schedule is baked in. */
+int ps_plan_create(ps_index* idx, const ps_device* work, uint64_t n_cap, uint64_t nnz_cap,
+                   const ps_search_params* params, ps_plan** out);
+
+/* Copy host spectra into the plan (validated as in ps_search_batch) and
+ * replay the graph; returns without waiting.  Waits first if the plan's
+ * previous run is still in flight (one batch per plan at a time). */
+int ps_plan_run(ps_plan* plan, const ps_spectra* spectra);
+
+/* Device pointers of the plan's input buffers (capacity n_cap / nnz_cap), for
+ * callers that place spectra there themselves; then ps_plan_run_device. */
+int ps_plan_inputs(ps_plan* plan, ps_spectra* device_buffers);
+int ps_plan_run_device(ps_plan* plan, uint64_t n, uint64_t nnz);
+
+/* Blocks until the run is done; then as ps_results. */
+int ps_plan_results(ps_plan* plan, ps_hit* hits, ps_stat* stats, int32_t* hist);
+
+/* Device time of the last run: the whole graph, and the scan alone (HIP events
+ * recorded inside the graph; -1 when the runtime does not record them), plus
+ * postings streamed, bin lookups and work items of the persistent scan. */
+int ps_plan_timing(ps_plan* plan, double* graph_ms, double* scan_ms, uint64_t* postings, uint64_t* bin_lookups,
+                   uint64_t* work_items);
+
+/* The stream the plan runs on. */
+int ps_plan_stream(ps_plan* plan, void** stream);
+
+void ps_plan_free(ps_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

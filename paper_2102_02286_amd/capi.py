@@ -97,6 +97,16 @@ _SIGS = [
                                  C.c_uint64, _P, _P, _P, _P, _P, _U64P]),
     ("ps_batch_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint32), _U64P, _U64P]),
     ("ps_batch_free", None, [_P]),
+    ("ps_plan_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
+    ("ps_plan_create", C.c_int, [_P, C.POINTER(ps_device), C.c_uint64, C.c_uint64, C.POINTER(ps_search_params),
+                                 C.POINTER(_P)]),
+    ("ps_plan_run", C.c_int, [_P, C.POINTER(ps_spectra)]),
+    ("ps_plan_inputs", C.c_int, [_P, C.POINTER(ps_spectra)]),
+    ("ps_plan_run_device", C.c_int, [_P, C.c_uint64, C.c_uint64]),
+    ("ps_plan_results", C.c_int, [_P, _P, _P, _P]),
+    ("ps_plan_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _U64P, _U64P, _U64P]),
+    ("ps_plan_stream", C.c_int, [_P, C.POINTER(_P)]),
+    ("ps_plan_free", None, [_P]),
 ]
 
 _lib = None
@@ -160,6 +170,15 @@ ps_results = _fn("ps_results")
 ps_search_dump = _fn("ps_search_dump")
 ps_batch_timing = _fn("ps_batch_timing")
 ps_batch_free = _fn("ps_batch_free")
+ps_plan_bytes = _fn("ps_plan_bytes")
+ps_plan_create = _fn("ps_plan_create")
+ps_plan_run = _fn("ps_plan_run")
+ps_plan_inputs = _fn("ps_plan_inputs")
+ps_plan_run_device = _fn("ps_plan_run_device")
+ps_plan_results = _fn("ps_plan_results")
+ps_plan_timing = _fn("ps_plan_timing")
+ps_plan_stream = _fn("ps_plan_stream")
+ps_plan_free = _fn("ps_plan_free")
 
 
 def ptr(a: np.ndarray):

@@ -7,6 +7,13 @@ namespace ps {
 using Schedule = ps_schedule;
 Schedule default_schedule();
 int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, const Schedule* sched);
+int check_schedule(const Schedule& s);
+hipError_t enqueue_kernels(const ps_index* ix, const DevSpectra& dsp, const KParams& kp, const Schedule& sc,
+                           int schedule, const Work& w, bool dump, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+uint64_t layout_work(uint64_t n, uint64_t nnz, const KParams& kp, bool copy_inputs, uint64_t max_items,
+                     char* base, Work* w, DevSpectra* dsp, uint64_t dump_cap);
+uint64_t max_items_for(const ps_index* ix, uint64_t n, const KParams& kp, const Schedule& sc, int schedule);
+int validate_host_spectra(const ps_spectra* sp, const KParams& kp);
 
 }  // namespace ps
 
@@ -30,4 +37,5 @@ struct ps_batch {
     int32_t* h_hist = nullptr;
     unsigned long long* h_counters = nullptr;
     char* h_stage = nullptr;
+    ps::BatchHdr* h_hdr = nullptr;
 };

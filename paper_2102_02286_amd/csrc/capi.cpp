@@ -23,6 +23,10 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+static int g_cu_count = 0;
+
+int device_cu_count() { return g_cu_count > 0 ? g_cu_count : 256; }
+
 int require_device() {
     static std::once_flag once;
     static int state = PS_EDEVICE;
@@ -41,6 +45,9 @@ int require_device() {
             msg = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950 only";
             return;
         }
+        g_cu_count = prop.multiProcessorCount;
+        hipError_t ea = init_kernel_attributes();
+        if (ea != hipSuccess) { msg = std::string("kernel set-up: ") + hipGetErrorString(ea); return; }
         state = PS_OK;
     });
     if (state != PS_OK) return fail(state, "%s", msg.c_str());
@@ -128,6 +135,7 @@ uint64_t layout_work(uint64_t n, uint64_t nnz, const KParams& kp, bool copy_inpu
     }
     Work t;
     memset(&t, 0, sizeof t);
+    t.hdr = (BatchHdr*)take(sizeof(BatchHdr));
     t.entries = (uint32_t*)take(n * (uint64_t)kp.ent_stride * 4);
     t.info = (SpecInfo*)take(n * sizeof(SpecInfo));
     t.hist = (int32_t*)take(n * (uint64_t)kHistBins * 4);
@@ -160,7 +168,7 @@ uint64_t max_items_for(const ps_index* ix, uint64_t n, const KParams& kp, const 
     return n * per;
 }
 
-static int validate_host_spectra(const ps_spectra* sp, const KParams& kp) {
+int validate_host_spectra(const ps_spectra* sp, const KParams& kp) {
     if (!sp) return fail(PS_EINVAL, "spectra is NULL");
     if (sp->n && (!sp->peak_off || !sp->precursor_mz || !sp->charge)) return fail(PS_EINVAL, "NULL spectra array");
     if (sp->n == 0) return PS_OK;
@@ -190,6 +198,31 @@ static int validate_host_spectra(const ps_spectra* sp, const KParams& kp) {
     return PS_OK;
 }
 
+// Kernel sequence of one search (no host copies): zero the accumulators,
+// prep + window, scan (plain or persistent), merge + expect values.  Reads the
+// batch size from w.hdr, so it can be captured once and replayed.
+hipError_t enqueue_kernels(const ps_index* ix, const DevSpectra& dsp, const KParams& kp, const Schedule& sc,
+                           int schedule, const Work& w, bool dump, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(launch_fill_per_spectrum(w.hist, 0, (uint64_t)kHistBins, dsp.n * (uint64_t)kHistBins, w.hdr, st));
+    chk(launch_fill_per_spectrum(w.n_scored, 0, 2, dsp.n * 2, w.hdr, st));
+    chk(launch_fill_u32(w.counters, 0, 16, st));
+    chk(launch_prep(ix->dev, dsp, kp, w, st));
+    if (ev0) chk(hipEventRecord(ev0, st));
+    const bool per_item = schedule == PS_SCHED_PERSISTENT;
+    if (per_item) {
+        chk(launch_worklist(dsp, kp, w, sc.tiles_per_item, st));
+        const uint32_t grid = (uint32_t)device_cu_count() * sc.groups_per_cu;
+        chk(launch_scan_persistent(ix->dev, dsp, kp, w, grid, sc.tiles_per_item, st));
+    } else {
+        chk(launch_scan_plain(ix->dev, dsp, kp, w, dump, false, false, st));
+    }
+    if (ev1) chk(hipEventRecord(ev1, st));
+    chk(launch_merge(ix->dev, dsp, kp, w, per_item, st));
+    return e;
+}
+
 // Enqueue the whole search for a batch whose inputs are in device memory.
 int enqueue_search(ps_batch* B) {
     hipStream_t st = B->stream;
@@ -197,21 +230,8 @@ int enqueue_search(ps_batch* B) {
     const uint64_t n = B->n;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(launch_fill_u32(w.hist, 0, n * (uint64_t)kHistBins, st));
-    chk(launch_fill_u32(w.n_scored, 0, n * 2, st));
-    chk(launch_fill_u32(w.counters, 0, 16, st));
-    chk(launch_prep(B->ix->dev, B->dsp, B->kp, w, st));
-    chk(hipEventRecord(B->ev_scan0, st));
-    bool per_item = false;
-    if (B->schedule == PS_SCHED_PERSISTENT) {
-        chk(launch_worklist(B->dsp, B->kp, w, B->max_items, st));
-        chk(launch_scan_persistent(B->ix->dev, B->dsp, B->kp, w, B->grid, B->sched.tiles_per_item, st));
-        per_item = true;
-    } else {
-        chk(launch_scan_plain(B->ix->dev, B->dsp, B->kp, w, B->dump, st));
-    }
-    chk(hipEventRecord(B->ev_scan1, st));
-    chk(launch_merge(B->ix->dev, B->dsp, B->kp, w, per_item, st));
+    chk(hipMemcpyAsync(w.hdr, B->h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, st));
+    chk(enqueue_kernels(B->ix, B->dsp, B->kp, B->sched, B->schedule, w, B->dump, st, B->ev_scan0, B->ev_scan1));
     // results to pinned host memory
     chk(hipMemcpyAsync(B->h_hits, w.hits, n * (uint64_t)B->kp.top_k * sizeof(ps_hit), hipMemcpyDeviceToHost, st));
     chk(hipMemcpyAsync(B->h_stats, w.stats, n * sizeof(ps_stat), hipMemcpyDeviceToHost, st));
@@ -219,7 +239,7 @@ int enqueue_search(ps_batch* B) {
     chk(hipMemcpyAsync(B->h_counters, w.counters, 8 * 8, hipMemcpyDeviceToHost, st));
     chk(hipEventRecord(B->ev_done, st));
     if (e != hipSuccess) return fail(PS_EDEVICE, "enqueue: %s", hipGetErrorString(e));
-    B->scan_launches = B->schedule == PS_SCHED_PERSISTENT ? 1 : 2;
+    B->scan_launches = 2;
     return PS_OK;
 }
 
@@ -233,6 +253,7 @@ static void batch_destroy(ps_batch* B) {
     if (B->h_hist) (void)hipHostFree(B->h_hist);
     if (B->h_counters) (void)hipHostFree(B->h_counters);
     if (B->h_stage) (void)hipHostFree(B->h_stage);
+    if (B->h_hdr) (void)hipHostFree(B->h_hdr);
     delete B;
 }
 
@@ -272,6 +293,7 @@ int batch_begin(ps_index* ix, const ps_device* work, const ps_spectra* host_sp, 
         dsp.peak_off = dev_sp->peak_off; dsp.mz = dev_sp->mz; dsp.inten = dev_sp->intensity;
         dsp.prec = dev_sp->precursor_mz; dsp.charge = dev_sp->charge; dsp.n = n; dsp.nnz = nnz;
     }
+    dsp.hdr = B->w.hdr;
     B->dsp = dsp;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
@@ -283,6 +305,8 @@ int batch_begin(ps_index* ix, const ps_device* work, const ps_spectra* host_sp, 
     chk(hipHostMalloc((void**)&B->h_stats, nh * sizeof(ps_stat), hipHostMallocDefault));
     if (B->want_hist) chk(hipHostMalloc((void**)&B->h_hist, nh * (uint64_t)kHistBins * 4, hipHostMallocDefault));
     chk(hipHostMalloc((void**)&B->h_counters, 8 * 8, hipHostMallocDefault));
+    chk(hipHostMalloc((void**)&B->h_hdr, sizeof(BatchHdr), hipHostMallocDefault));
+    if (e == hipSuccess) { B->h_hdr->n = n; B->h_hdr->nnz = nnz; }
     if (e != hipSuccess) { batch_destroy(B); return fail(PS_EDEVICE, "batch set-up: %s", hipGetErrorString(e)); }
     if (host_sp && n) {
         // stage inputs in pinned memory, then copy on the batch's stream

@@ -52,6 +52,13 @@ struct SpecInfo {
     uint32_t flags;
 };
 
+// Actual size of the batch in flight, in device memory, so that one launch
+// sequence (or one captured graph) serves any batch up to its capacity.
+struct BatchHdr {
+    unsigned long long n;      // spectra
+    unsigned long long nnz;    // peaks (length of mz / inten)
+};
+
 // Inputs of one batch, device pointers.
 struct DevSpectra {
     const uint64_t* peak_off;
@@ -59,8 +66,9 @@ struct DevSpectra {
     const float* inten;
     const double* prec;
     const int8_t* charge;
-    uint64_t n;
-    uint64_t nnz;              // length of mz / inten; peak_off entries beyond it are invalid
+    uint64_t n;                // capacity: grids are sized for it
+    uint64_t nnz;              // capacity
+    const BatchHdr* hdr;       // actual n and nnz; peak_off entries beyond nnz are invalid
 };
 
 // Search settings as the kernels see them.
@@ -82,6 +90,7 @@ struct KParams {
 
 // Workspace pointers of one batch (all inside the caller's device block).
 struct Work {
+    BatchHdr* hdr;             // actual batch size
     uint32_t* entries;         // [n * ent_stride] (bin << 8 | q) or kEntryInvalid
     SpecInfo* info;            // [n]
     int32_t* hist;             // [n * 512]
@@ -102,11 +111,18 @@ enum CounterSlot { kCtrPostings = 0, kCtrLookups = 1, kCtrQueue = 2, kCtrItems =
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t stream);
+// fill count_per_spectrum * hdr->n words (grid sized for `cap_count`)
+hipError_t launch_fill_per_spectrum(void* p, uint32_t value, uint64_t count_per_spectrum, uint64_t cap_count,
+                                    const BatchHdr* hdr, hipStream_t stream);
+int device_cu_count();
 hipError_t launch_prep(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
                        hipStream_t stream);
+// per_item: partial lists are laid out per work item (persistent schedule);
+// wide_only: launch only the 64-bit-counter kernel (the persistent kernel
+// handles the narrow spectra)
 hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
-                             bool dump, hipStream_t stream);
-hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& w, uint64_t max_items,
+                             bool dump, bool per_item, bool wide_only, hipStream_t stream);
+hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& w, uint32_t tiles_per_item,
                            hipStream_t stream);
 hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, const KParams& kp,
                                   const Work& w, uint32_t grid, uint32_t tiles_per_item,
@@ -114,5 +130,6 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
 hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
                         bool per_item, hipStream_t stream);
 size_t scan_lds_bytes(const KParams& kp, bool wide);
+hipError_t init_kernel_attributes();
 
 }  // namespace ps

@@ -152,6 +152,23 @@ hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t 
     return hipGetLastError();
 }
 
+__global__ void k_fill_per_spectrum(uint32_t* p, uint32_t v, uint64_t per, const BatchHdr* hdr) {
+    const uint64_t n = hdr->n * per;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_per_spectrum(void* p, uint32_t value, uint64_t per, uint64_t cap_count, const BatchHdr* hdr,
+                                    hipStream_t stream) {
+    if (cap_count == 0) return hipSuccess;
+    uint64_t blocks = (cap_count + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_per_spectrum, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, (uint32_t*)p, value,
+                       per, hdr);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // prep: one workgroup per spectrum
 // ---------------------------------------------------------------------------
@@ -172,13 +189,14 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
     const uint32_t tid = threadIdx.x;
     const KParams& kp = A.kp;
 
-    for (uint64_t s = blockIdx.x; s < A.sp.n; s += gridDim.x) {
+    const uint64_t n_batch = A.sp.hdr->n, nnz_batch = A.sp.hdr->nnz;
+    for (uint64_t s = blockIdx.x; s < n_batch; s += gridDim.x) {
         const uint64_t p0 = A.sp.peak_off[s], p1 = A.sp.peak_off[s + 1];
         const int z = A.sp.charge[s];
         const double prec = A.sp.prec[s];
         if (tid == 0) {
             uint32_t bad = 0;
-            if (!(p1 >= p0) || p1 - p0 > PS_MAX_PEAKS_IN || p1 > A.sp.nnz) bad = 1;
+            if (!(p1 >= p0) || p1 - p0 > PS_MAX_PEAKS_IN || p1 > nnz_batch) bad = 1;
             if (z < 1 || z > (int)kp.max_charge) bad = 1;
             if (!(prec > 0.0) || !(prec <= 1e6)) bad = 1;   // also rejects NaN
             s_flag = bad;
@@ -318,6 +336,7 @@ struct ScanArgs {
     Work w;
     uint32_t tiles_per_item;   // persistent schedule
     uint32_t want_wide;        // which counter width this launch handles
+    uint32_t per_item;         // partial lists indexed by work item (persistent schedule)
 };
 
 constexpr uint32_t kCoopCap = 32;     // cooperative (long) segments per work item
@@ -676,11 +695,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
     __shared__ ScanShared sh;
     ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap, A.kp.use_bitmaps ? kBmCap : 0);
     const uint32_t s = blockIdx.x;
+    if (s >= A.sp.hdr->n) return;
     const SpecInfo inf = A.w.info[s];
-    ps_hit* out = A.w.partial + (uint64_t)s * A.kp.top_k;
     const bool wide = (inf.flags & kFlagWide) != 0;
     const bool skip = (inf.flags & (kFlagInvalid | kFlagOverflow)) || inf.hi <= inf.lo;
     if (wide != (A.want_wide != 0)) return;            // the other launch handles it
+    if (A.per_item && skip) return;                    // no work item: nothing to write
+    ps_hit* out = A.w.partial + (uint64_t)(A.per_item ? A.w.spec_item0[s] : s) * A.kp.top_k;
     if (skip) {
         if (threadIdx.x < A.kp.top_k) {
             ps_hit o; o.id = 0xFFFFFFFFu; o.n_b = o.n_y = 0; o.sum_q = 0; o.pad = 0; o.hyperscore = -INFINITY;
@@ -705,30 +726,135 @@ template <typename C, int K, bool DUMP>
 static hipError_t launch_scan_plain_t(ScanArgs a, uint64_t n, hipStream_t stream) {
     a.kp.merge_groups = merge_groups(a.kp, sizeof(C) == 8);
     const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
-    hipError_t e = hipFuncSetAttribute((const void*)k_scan_plain<C, K, DUMP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_scan_plain<C, K, DUMP>), dim3((uint32_t)n), dim3(kBlock), lds, stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
-                             bool dump, hipStream_t stream) {
+                             bool dump, bool per_item, bool wide_only, hipStream_t stream) {
     if (sp.n == 0) return hipSuccess;
-    ScanArgs a{ix, sp, kp, w, 1u, 0u};
-    hipError_t e;
+    ScanArgs a{ix, sp, kp, w, 1u, 0u, per_item ? 1u : 0u};
+    hipError_t e = hipSuccess;
     const bool k8 = kp.top_k <= 8;
     // narrow counters for every spectrum that proved it can use them, then wide
-    a.want_wide = 0;
-    if (dump) e = k8 ? launch_scan_plain_t<uint32_t, 8, true>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, true>(a, sp.n, stream);
-    else e = k8 ? launch_scan_plain_t<uint32_t, 8, false>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, false>(a, sp.n, stream);
-    if (e != hipSuccess) return e;
+    if (!wide_only) {
+        a.want_wide = 0;
+        if (dump) e = k8 ? launch_scan_plain_t<uint32_t, 8, true>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, true>(a, sp.n, stream);
+        else e = k8 ? launch_scan_plain_t<uint32_t, 8, false>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, false>(a, sp.n, stream);
+        if (e != hipSuccess) return e;
+    }
     a.want_wide = 1;
     // 64-bit counters take twice the LDS per candidate: halve the tile until it fits
     while (a.kp.tile > 1024 && scan_lds_bytes(a.kp, true) > kMaxLds) a.kp.tile /= 2;
     if (dump) e = k8 ? launch_scan_plain_t<unsigned long long, 8, true>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, true>(a, sp.n, stream);
     else e = k8 ? launch_scan_plain_t<unsigned long long, 8, false>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, false>(a, sp.n, stream);
     return e;
+}
+
+// ---------------------------------------------------------------------------
+// persistent schedule: a work list of (spectrum, tile range) items and one
+// resident grid that pops items from a device queue
+// ---------------------------------------------------------------------------
+
+struct ListArgs {
+    DevSpectra sp;
+    KParams kp;
+    Work w;
+    uint32_t tiles_per_item;
+};
+
+// Items per spectrum: ceil(tiles / tiles_per_item) for narrow-counter spectra,
+// one slot for a wide-counter spectrum (filled by the plain wide kernel), none
+// for invalid, overflowing or empty-window spectra.  spec_item0 is their
+// exclusive prefix sum; spec_item0[n] is the total.  One workgroup.
+__device__ __forceinline__ uint32_t items_of(const SpecInfo& inf, uint32_t tile, uint32_t tpi) {
+    if ((inf.flags & (kFlagInvalid | kFlagOverflow)) || inf.hi <= inf.lo) return 0u;
+    if (inf.flags & kFlagWide) return 1u;
+    const uint32_t tiles = (inf.hi - inf.lo + tile - 1) / tile;
+    return (tiles + tpi - 1) / tpi;
+}
+
+__global__ __launch_bounds__(kBlock) void k_worklist(ListArgs A) {
+    __shared__ unsigned long long s_part[kBlock];
+    const uint64_t n = A.sp.hdr->n;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t a = n * tid / kBlock, b = n * (tid + 1) / kBlock;
+    unsigned long long sum = 0;
+    for (uint64_t s = a; s < b; ++s) sum += items_of(A.w.info[s], A.kp.tile, A.tiles_per_item);
+    s_part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long run = 0;
+        for (int i = 0; i < kBlock; ++i) { const unsigned long long t = s_part[i]; s_part[i] = run; run += t; }
+        A.w.spec_item0[n] = (uint32_t)run;
+        A.w.counters[kCtrItems] = run;
+    }
+    __syncthreads();
+    unsigned long long run = s_part[tid];
+    for (uint64_t s = a; s < b; ++s) {
+        A.w.spec_item0[s] = (uint32_t)run;
+        run += items_of(A.w.info[s], A.kp.tile, A.tiles_per_item);
+    }
+}
+
+hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& w, uint32_t tiles_per_item,
+                           hipStream_t stream) {
+    ListArgs a{sp, kp, w, tiles_per_item};
+    hipLaunchKernelGGL(k_worklist, dim3(1), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename C, int K>
+__global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ ScanShared sh;
+    __shared__ uint32_t s_item;
+    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap, A.kp.use_bitmaps ? kBmCap : 0);
+    const uint32_t n = (uint32_t)A.sp.hdr->n;
+    const uint32_t total = A.w.spec_item0[n];
+    const uint32_t tpi = A.tiles_per_item;
+    while (true) {
+        if (threadIdx.x == 0) s_item = (uint32_t)atomicAdd(&A.w.counters[kCtrQueue], 1ull);
+        __syncthreads();
+        const uint32_t g = s_item;
+        __syncthreads();
+        if (g >= total) break;                         // queue drained: every workgroup exits
+        // spectrum of item g: the last s with spec_item0[s] <= g
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (A.w.spec_item0[mid] <= g) lo = mid; else hi = mid;
+        }
+        const uint32_t s = lo;
+        const SpecInfo inf = A.w.info[s];
+        if (inf.flags & kFlagWide) continue;           // its slot is filled by the wide kernel
+        const uint32_t t0 = (g - A.w.spec_item0[s]) * tpi;
+        const uint32_t ida = inf.lo + t0 * A.kp.tile;
+        const uint32_t span = tpi * A.kp.tile;
+        const uint32_t idb = inf.hi - ida > span ? ida + span : inf.hi;
+        scan_item<C, K, false>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
+    }
+}
+
+template <typename C, int K>
+static hipError_t launch_persistent_t(ScanArgs a, uint32_t grid, hipStream_t stream) {
+    a.kp.merge_groups = merge_groups(a.kp, sizeof(C) == 8);
+    const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_scan_persistent<C, K>), dim3(grid), dim3(kBlock), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
+                                  uint32_t grid, uint32_t tiles_per_item, hipStream_t stream) {
+    if (sp.n == 0) return hipSuccess;
+    ScanArgs a{ix, sp, kp, w, tiles_per_item, 0u, 1u};
+    hipError_t e = kp.top_k <= 8 ? launch_persistent_t<uint32_t, 8>(a, grid, stream)
+                                 : launch_persistent_t<uint32_t, 16>(a, grid, stream);
+    if (e != hipSuccess) return e;
+    // spectra that need 64-bit counters: one workgroup per spectrum, slot = its item
+    return launch_scan_plain(ix, sp, kp, w, false, true, true, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -752,7 +878,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     __shared__ unsigned long long s_modekey;
     const uint32_t tid = threadIdx.x;
     const uint32_t K = A.kp.top_k;
-    for (uint64_t s = blockIdx.x; s < A.sp.n; s += gridDim.x) {
+    const uint64_t n_batch = A.sp.hdr->n;
+    for (uint64_t s = blockIdx.x; s < n_batch; s += gridDim.x) {
         const SpecInfo inf = A.w.info[s];
         const bool invalid = (inf.flags & kFlagInvalid) != 0;
         const bool overflow = (inf.flags & kFlagOverflow) != 0;
@@ -883,12 +1010,20 @@ hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams&
     return hipGetLastError();
 }
 
-hipError_t launch_worklist(const DevSpectra&, const KParams&, const Work&, uint64_t, hipStream_t) {
-    return hipErrorNotSupported;
-}
-hipError_t launch_scan_persistent(const DevIndex&, const DevSpectra&, const KParams&, const Work&, uint32_t,
-                                  uint32_t, hipStream_t) {
-    return hipErrorNotSupported;
+// Allow every scan kernel the whole LDS once, before any launch or capture.
+hipError_t init_kernel_attributes() {
+    const void* fns[] = {
+        (const void*)k_scan_plain<uint32_t, 8, false>, (const void*)k_scan_plain<uint32_t, 16, false>,
+        (const void*)k_scan_plain<uint32_t, 8, true>, (const void*)k_scan_plain<uint32_t, 16, true>,
+        (const void*)k_scan_plain<unsigned long long, 8, false>, (const void*)k_scan_plain<unsigned long long, 16, false>,
+        (const void*)k_scan_plain<unsigned long long, 8, true>, (const void*)k_scan_plain<unsigned long long, 16, true>,
+        (const void*)k_scan_persistent<uint32_t, 8>, (const void*)k_scan_persistent<uint32_t, 16>,
+    };
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace ps

@@ -210,3 +210,63 @@ def search_dump(index: HostIndex, sp, params: capi.ps_search_params, cap: int = 
     m = cnt.value
     order = np.lexsort((b[:m], a[:m]))
     return a[:m][order], b[:m][order], nb[:m][order], ny[:m][order], sq[:m][order]
+
+
+class Plan:
+    """A reusable, graph-captured search plan for batches up to a capacity."""
+
+    def __init__(self, index: HostIndex, params: capi.ps_search_params, n_cap: int, nnz_cap: int,
+                 device: str = "cuda:0", stream=None):
+        torch = _torch()
+        self.index, self.params, self.n_cap, self.nnz_cap = index, params, n_cap, nnz_cap
+        need = C.c_uint64()
+        check(capi.ps_plan_bytes(index.handle, n_cap, nnz_cap, C.byref(params), C.byref(need)), "ps_plan_bytes")
+        self.buf = torch.empty(max(need.value, 256), dtype=torch.uint8, device=device)
+        st = None if stream is None else stream.cuda_stream
+        dev = capi.ps_device(self.buf.data_ptr(), self.buf.numel(), st)
+        h = C.c_void_p()
+        check(capi.ps_plan_create(index.handle, C.byref(dev), n_cap, nnz_cap, C.byref(params), C.byref(h)),
+              "ps_plan_create")
+        self.handle = h
+        self.n = 0
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            capi.ps_plan_free(h)
+            self.handle = None
+
+    def run(self, sp):
+        s, self._keep = _spectra_struct(sp)
+        check(capi.ps_plan_run(self.handle, C.byref(s)), "ps_plan_run")
+        self.n = sp.n
+
+    def inputs(self) -> capi.ps_spectra:
+        d = capi.ps_spectra()
+        check(capi.ps_plan_inputs(self.handle, C.byref(d)))
+        return d
+
+    def run_device(self, n: int, nnz: int):
+        check(capi.ps_plan_run_device(self.handle, n, nnz), "ps_plan_run_device")
+        self.n = n
+
+    def results(self) -> Results:
+        n, prm = self.n, self.params
+        hits = np.zeros(n * prm.top_k, capi.HIT_DTYPE)
+        stats = np.zeros(n, capi.STAT_DTYPE)
+        hist = np.zeros(n * capi.PS_HIST_BINS, np.int32) if prm.want_hist else None
+        rc = capi.ps_plan_results(self.handle, ptr(hits), ptr(stats), ptr(hist) if hist is not None else None)
+        if rc not in (capi.PS_OK, capi.PS_EOVERFLOW):
+            check(rc, "ps_plan_results")
+        g, sc = C.c_double(), C.c_double()
+        po, lk, it = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        check(capi.ps_plan_timing(self.handle, C.byref(g), C.byref(sc), C.byref(po), C.byref(lk), C.byref(it)))
+        r = Results(hits.reshape(n, prm.top_k), stats,
+                    hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, sc.value, po.value, lk.value)
+        r.graph_ms = g.value
+        r.items = it.value
+        return r
+
+    def search(self, sp) -> Results:
+        self.run(sp)
+        return self.results()

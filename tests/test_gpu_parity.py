@@ -56,7 +56,7 @@ def tiny():
     return w, prot, sp, ix, db
 
 
-@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN])
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
 def test_tiny_full_batch_parity(tiny, schedule):
     w, prot, sp, ix, db = tiny
     _say(f"tiny: {sp.n} spectra, schedule {schedule}")
@@ -165,6 +165,76 @@ def test_schedules_give_identical_results(small_open, sched):
         capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
 
 
+@pytest.mark.parametrize("sched", [dict(tiles_per_item=1), dict(tiles_per_item=3, tile=2048),
+                                   dict(tiles_per_item=64, groups_per_cu=1)])
+def test_persistent_schedule_parity(small_open, sched):
+    """The work-queue scan splits windows into (spectrum, tile range) items;
+    merged results equal the oracle for any item size."""
+    w, prot, sp, ix, db, (oh, ost, og) = small_open
+    old = ix.schedule()
+    try:
+        ix.set_schedule(**sched)
+        _say(f"persistent {sched}")
+        prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                                   max_charge=3, schedule=capi.PS_SCHED_PERSISTENT)
+        res = engine.search(ix, sp, prm)
+        assert_parity(res, oh, ost, og)
+        assert res.postings == int(ost["pairs_total"].sum())
+    finally:
+        capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
+
+
+def test_plan_graph_replays_match_eager_and_oracle(small_open):
+    """One captured graph, replayed for batches of different sizes with eager
+    searches and synchronisations in between; every replay equals the eager
+    result and the oracle."""
+    import torch
+    w, prot, sp, ix, db, (oh, ost, og) = small_open
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3, schedule=capi.PS_SCHED_PERSISTENT)
+    plan = engine.Plan(ix, prm, n_cap=sp.n, nnz_cap=int(sp.peak_off[-1]))
+    ranges = [(0, sp.n), (10, 50), (0, 1), (100, sp.n), (0, sp.n), (33, 34)]
+    for k, (a, b) in enumerate(ranges):
+        sub = sp.subset(np.arange(a, b))
+        _say(f"plan replay {k}: spectra [{a}, {b})")
+        got = plan.search(sub)
+        eager = engine.search(ix, sub, prm)
+        torch.cuda.synchronize()
+        assert got.hits.tobytes() == eager.hits.tobytes()
+        assert got.stats.tobytes() == eager.stats.tobytes()
+        assert got.hist.tobytes() == eager.hist.tobytes()
+        from types import SimpleNamespace
+        assert_parity(SimpleNamespace(hits=got.hits, stats=got.stats, hist=got.hist), oh[a:b], ost[a:b], og[a:b])
+
+
+class _DevArray:
+    """A raw device buffer seen by torch (no copy)."""
+
+    def __init__(self, p, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (p, False), "version": 2}
+
+
+def test_plan_device_inputs(small_open):
+    import torch
+    w, prot, sp, ix, db, (oh, ost, og) = small_open
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3, schedule=capi.PS_SCHED_PERSISTENT)
+    nnz = int(sp.peak_off[-1])
+    plan = engine.Plan(ix, prm, n_cap=sp.n, nnz_cap=nnz)
+    d = plan.inputs()
+    pairs = [(d.peak_off, sp.peak_off.astype(np.uint64).view(np.int64), "<i8"), (d.mz, sp.mz, "<f4"),
+             (d.intensity, sp.intensity, "<f4"), (d.precursor_mz, sp.precursor_mz, "<f8"), (d.charge, sp.charge, "|i1")]
+    for p, host, ts in pairs:
+        dst = torch.as_tensor(_DevArray(p, host.shape[0], ts), device="cuda")
+        dst.copy_(torch.from_numpy(np.ascontiguousarray(host)).to("cuda"))
+    torch.cuda.synchronize()
+    _say("plan with device inputs")
+    plan.run_device(sp.n, nnz)
+    got = plan.results()
+    from types import SimpleNamespace
+    assert_parity(SimpleNamespace(hits=got.hits, stats=got.stats, hist=got.hist), oh, ost, og)
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
@@ -266,7 +336,7 @@ def test_device_resident_inputs_and_invalid_spectra(small_open):
 # full-size medium workload: sampled outputs against the oracle
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN])
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
 def test_medium_full_size_sampled_parity(schedule):
     w = synth.workload("medium")
     prot = w.proteome()
