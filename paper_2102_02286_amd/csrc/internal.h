@@ -20,7 +20,7 @@ constexpr uint32_t kLfSize = 65536;         // log10(n!) table, n < 65536
 constexpr uint32_t kLsSize = 1u << 20;      // log10(s) table, s < 2^20
 constexpr uint32_t kEntryInvalid = 0xFFFFFFFFu;
 constexpr int kBlock = 256;                 // threads per workgroup for every kernel
-constexpr size_t kMaxLds = 160 * 1024;      // LDS per workgroup on gfx950
+constexpr size_t kMaxLds = 158 * 1024;      // dynamic LDS per workgroup (160 KB on gfx950 less static use)
 
 // Per-spectrum flags written by the prep kernel.
 enum : uint32_t {
