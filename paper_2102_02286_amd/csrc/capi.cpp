@@ -102,7 +102,7 @@ Schedule default_schedule() {
     Schedule s;
     s.tile = 4096;
     s.coop_min = 4096;
-    s.tiles_per_item = 16;
+    s.tiles_per_item = 64;
     s.groups_per_cu = 4;
     s.use_bitmaps = 0;
     s.pad = 0;
@@ -163,8 +163,7 @@ uint64_t layout_work(uint64_t n, uint64_t nnz, const KParams& kp, bool copy_inpu
 uint64_t max_items_for(const ps_index* ix, uint64_t n, const KParams& kp, const Schedule& sc, int schedule) {
     if (schedule == PS_SCHED_PLAIN) return n;
     uint64_t span = (uint64_t)kp.tile * sc.tiles_per_item;
-    uint64_t per = (ix->mass.size() + span - 1) / span;
-    if (per < 1) per = 1;
+    uint64_t per = ix->mass.size() / span + 2;    // grid-aligned items touching one window
     return n * per;
 }
 

@@ -297,7 +297,26 @@ int index_build_host(ps_index* ix) {
     // Postings of one id in one bin must be ordered b before y; ions of one id are
     // emitted b-first, so each bin is non-decreasing in (id << 1 | type).
 
-    // 4. dense bins (>= 1/16 of all entries, at most 64 of them) also as b/y
+    // 4. block directory: for every bin and every block of 2^dir_shift ids, the
+    // first posting at or after the block start, so a range search inside a bin
+    // starts from a block instead of the whole bin
+    ix->dir_nblk = (D >> ix->dir_shift) + 1;
+    const uint64_t stride = ix->dir_nblk + 1;
+    ix->dir.assign(nbins * stride, 0u);
+    parallel_for(nbins, T, [&](unsigned, uint64_t ba, uint64_t bb) {
+        for (uint64_t bn = ba; bn < bb; ++bn) {
+            uint32_t* d = ix->dir.data() + bn * stride;
+            uint64_t i = ix->bin_off[bn];
+            const uint64_t e = ix->bin_off[bn + 1];
+            for (uint64_t k = 0; k <= ix->dir_nblk; ++k) {
+                const uint64_t first_id = k << ix->dir_shift;
+                while (i < e && (uint64_t)(ix->post[i] >> 1) < first_id) ++i;
+                d[k] = (uint32_t)i;
+            }
+        }
+    });
+
+    // 5. dense bins (>= 1/16 of all entries, at most 64 of them) also as b/y
     // bitmaps over the whole id space: for such a bin a bitmap is cheaper to read
     // than its postings, and the scan adds them while scoring instead of with atomics
     ix->heavy_slot.assign(nbins, -1);
@@ -331,7 +350,7 @@ int index_build_host(ps_index* ix) {
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
 struct DevLayout {
-    uint64_t mass, bin, post, lf, ls, slot, bm, total;
+    uint64_t mass, bin, post, lf, ls, slot, bm, dir, total;
 };
 
 static DevLayout index_device_layout(const ps_index* ix) {
@@ -344,6 +363,7 @@ static DevLayout index_device_layout(const ps_index* ix) {
     L.ls = o; o = align256(o + kLsSize * sizeof(double));
     L.slot = o; o = align256(o + ix->heavy_slot.size() * sizeof(int32_t));
     L.bm = o; o = align256(o + ix->bitmaps.size() * sizeof(uint32_t));
+    L.dir = o; o = align256(o + ix->dir.size() * sizeof(uint32_t));
     L.total = o;
     return L;
 }
@@ -455,6 +475,7 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     cp(lay.ls, ls.data(), ls.size() * sizeof(double));
     cp(lay.slot, ix->heavy_slot.data(), ix->heavy_slot.size() * sizeof(int32_t));
     cp(lay.bm, ix->bitmaps.data(), ix->bitmaps.size() * sizeof(uint32_t));
+    cp(lay.dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
     DevIndex& d = ix->dev;
@@ -467,6 +488,9 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     d.bitmaps = (const uint32_t*)(base + lay.bm);
     d.bm_words = ix->bm_words;
     d.n_heavy = (uint32_t)ix->heavy_bins.size();
+    d.dir = (const uint32_t*)(base + lay.dir);
+    d.dir_shift = ix->dir_shift;
+    d.dir_nblk = (uint32_t)ix->dir_nblk;
     d.n_pep = ix->mass.size();
     d.n_bins = ix->n_bins;
     d.n_post = ix->post.size();

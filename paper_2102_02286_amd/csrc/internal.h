@@ -38,6 +38,9 @@ struct DevIndex {
     const double* ls;          // [kLsSize]  ls[s] = log10 s
     const int32_t* heavy_slot; // [n_bins] bitmap slot of a dense bin, or -1
     const uint32_t* bitmaps;   // [n_heavy * 2 * bm_words]: b bitmap, then y bitmap, per slot
+    const uint32_t* dir;       // [n_bins * (dir_nblk + 1)] first posting of a bin at or after each id block
+    uint32_t dir_shift;        // id block = 1 << dir_shift ids
+    uint32_t dir_nblk;
     uint64_t n_pep, n_bins, n_post;
     uint64_t bm_words;
     uint32_t n_heavy;

@@ -454,10 +454,14 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         const int64_t bin = (int64_t)(e >> 8) + (int64_t)(k % width) - T;
         if (bin < 0 || bin >= (int64_t)ix.n_bins) continue;
         ++lookups;
-        const uint32_t r0 = (uint32_t)ix.bin_off[bin], r1 = (uint32_t)ix.bin_off[bin + 1];
-        if (r0 == r1) continue;
-        const uint32_t s0 = lower_bound_u32(ix.post, r0, r1, ida << 1);
-        const uint32_t s1 = lower_bound_u32(ix.post, s0, r1, idb << 1);
+        const uint32_t* d = ix.dir + (uint64_t)bin * (ix.dir_nblk + 1);
+        // first posting with id >= ida / idb: exact when the id is block aligned,
+        // else a search inside one block of the bin
+        const uint32_t ka = ida >> ix.dir_shift, kb = idb >> ix.dir_shift;
+        const uint32_t a0 = d[ka];
+        const uint32_t s0 = (ida & ((1u << ix.dir_shift) - 1)) ? lower_bound_u32(ix.post, a0, d[ka + 1], ida << 1) : a0;
+        const uint32_t b0 = d[kb];
+        const uint32_t s1 = (idb & ((1u << ix.dir_shift) - 1)) ? lower_bound_u32(ix.post, b0, d[kb + 1], idb << 1) : b0;
         if (s1 <= s0) continue;
         postings += s1 - s0;
         const uint16_t q = (uint16_t)(e & 0xFFu);
@@ -768,11 +772,13 @@ struct ListArgs {
 // one slot for a wide-counter spectrum (filled by the plain wide kernel), none
 // for invalid, overflowing or empty-window spectra.  spec_item0 is their
 // exclusive prefix sum; spec_item0[n] is the total.  One workgroup.
+// Items are aligned to the global grid of `span` = tile * tiles_per_item ids,
+// so interior items start on directory blocks when span is a multiple of them.
 __device__ __forceinline__ uint32_t items_of(const SpecInfo& inf, uint32_t tile, uint32_t tpi) {
     if ((inf.flags & (kFlagInvalid | kFlagOverflow)) || inf.hi <= inf.lo) return 0u;
     if (inf.flags & kFlagWide) return 1u;
-    const uint32_t tiles = (inf.hi - inf.lo + tile - 1) / tile;
-    return (tiles + tpi - 1) / tpi;
+    const uint32_t span = tile * tpi;
+    return (inf.hi - 1) / span - inf.lo / span + 1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_worklist(ListArgs A) {
@@ -829,10 +835,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
         const uint32_t s = lo;
         const SpecInfo inf = A.w.info[s];
         if (inf.flags & kFlagWide) continue;           // its slot is filled by the wide kernel
-        const uint32_t t0 = (g - A.w.spec_item0[s]) * tpi;
-        const uint32_t ida = inf.lo + t0 * A.kp.tile;
         const uint32_t span = tpi * A.kp.tile;
-        const uint32_t idb = inf.hi - ida > span ? ida + span : inf.hi;
+        const uint32_t blk = inf.lo / span + (g - A.w.spec_item0[s]);
+        const uint32_t ida = max(inf.lo, blk * span);
+        const uint32_t idb = min(inf.hi, (blk + 1) * span);
         scan_item<C, K, false>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
     }
 }

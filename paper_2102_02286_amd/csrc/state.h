@@ -51,6 +51,10 @@ struct ps_index {
     std::vector<uint32_t> heavy_bins;     // bin of each slot
     std::vector<uint32_t> bitmaps;        // [n_heavy * 2 * bm_words]
     uint64_t bm_words = 0;
+    // block directory: dir[bin * (dir_nblk + 1) + k] = first posting of `bin` with id >= k << dir_shift
+    uint32_t dir_shift = 16;
+    uint64_t dir_nblk = 0;
+    std::vector<uint32_t> dir;
     ps_schedule sched{};
     // device copy
     bool on_device = false;
