@@ -90,7 +90,6 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
     kp->tile = sched->tile;
     kp->coop_min = sched->coop_min;
     kp->use_bitmaps = sched->use_bitmaps;
-    kp->merge_groups = 1;
     if (scan_lds_bytes(*kp, false) > kMaxLds)
         return fail(PS_EINVAL, "tile %u needs %zu bytes of LDS with these parameters (max %zu)", kp->tile,
                     scan_lds_bytes(*kp, false), kMaxLds);

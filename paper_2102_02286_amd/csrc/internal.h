@@ -88,7 +88,6 @@ struct KParams {
     uint32_t tile;             // candidates per LDS counter tile
     uint32_t coop_min;         // segments longer than this are scanned cooperatively
     uint32_t use_bitmaps;      // read dense bins through their bitmaps
-    uint32_t merge_groups;     // thread groups of the top-k merge (set per launch)
 };
 
 // Workspace pointers of one batch (all inside the caller's device block).

@@ -100,39 +100,44 @@ template <> struct Cnt<unsigned long long> {
     __device__ static uint32_t s(unsigned long long c) { return (uint32_t)c; }
 };
 
-// Top-K list held in registers, sorted by (hyperscore desc, id asc).  Entries
-// keep the raw packed counter; n_b, n_y and S are decoded only when written out.
-template <int K, typename C>
-struct TopK {
-    double h[K];
-    uint32_t id[K];
-    C c[K];
-    __device__ void init() {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { h[j] = -INFINITY; id[j] = 0xFFFFFFFFu; c[j] = 0; }
+// Top-k of one wavefront, distributed over its lanes: lane j < k holds the
+// j-th best candidate by (hyperscore desc, id asc).  An insertion is a ballot
+// for the first lane the newcomer beats and a one-lane shift below it, so the
+// list costs each lane one entry of registers instead of k.
+__device__ __forceinline__ bool better_hit(double ha, uint32_t ia, double hb, uint32_t ib) {
+    return ha > hb || (ha == hb && ia < ib);
+}
+
+template <typename C>
+struct WaveTopK {
+    double h;
+    uint32_t id;
+    C c;
+    __device__ void init() { h = -INFINITY; id = 0xFFFFFFFFu; c = 0; }
+    // Insert a wave-uniform candidate; every lane of the wavefront calls this.
+    __device__ void insert(double xh, uint32_t xid, C xc, uint32_t k) {
+        const uint32_t lane = threadIdx.x & 63u;
+        const unsigned long long m = __ballot(lane < k && better_hit(xh, xid, h, id));
+        if (m == 0) return;
+        const uint32_t p = (uint32_t)__ffsll((long long)m) - 1u;
+        const double uh = __shfl_up(h, 1, 64);
+        const uint32_t uid = __shfl_up(id, 1, 64);
+        const C uc = __shfl_up(c, 1, 64);
+        if (lane > p && lane < k) { h = uh; id = uid; c = uc; }
+        if (lane == p) { h = xh; id = xid; c = xc; }
     }
-    __device__ static bool better(double ha, uint32_t ia, double hb, uint32_t ib) {
-        return ha > hb || (ha == hb && ia < ib);
-    }
-    // Insert by bubbling the newcomer down: after the pass the list holds the K
-    // best of (old list + newcomer), still sorted.
-    __device__ void insert(double hh, uint32_t ii, C cc) {
-        if (!better(hh, ii, h[K - 1], id[K - 1])) return;
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (better(hh, ii, h[j], id[j])) {
-                double th = h[j]; uint32_t ti = id[j]; C tc = c[j];
-                h[j] = hh; id[j] = ii; c[j] = cc;
-                hh = th; ii = ti; cc = tc;
-            }
+    // Insert every flagged lane's candidate that beats the current k-th best.
+    __device__ void insert_lanes(bool flag, double ch, uint32_t cid, C cc, uint32_t k) {
+        const double kh = __shfl(h, (int)k - 1, 64);
+        const uint32_t kid = __shfl(id, (int)k - 1, 64);
+        unsigned long long m = __ballot(flag && better_hit(ch, cid, kh, kid));
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            insert(__shfl(ch, l, 64), __shfl(cid, l, 64), __shfl(cc, l, 64), k);
         }
     }
 };
-
-// Entry of the LDS merge of per-thread lists (16 bytes narrow, 24 wide).
-template <typename C> struct MergeEnt;
-template <> struct MergeEnt<uint32_t> { double h; uint32_t id; uint32_t c; };
-template <> struct MergeEnt<unsigned long long> { double h; uint32_t id; uint32_t pad; unsigned long long c; };
 
 // ---------------------------------------------------------------------------
 // fill
@@ -348,8 +353,9 @@ constexpr uint32_t kCandCap = 512;    // scored candidates buffered per tile bef
 struct ScanShared {
     uint32_t nseg, nlight, ncoop, nhh, ncand;
     unsigned long long red[kBlock / 64];
-    unsigned long long acc[PS_MAX_TOP_K * 3];    // top-k accumulators (24-byte entries)
-    unsigned long long acc2[PS_MAX_TOP_K * 3];
+    double wh[kBlock / 64][PS_MAX_TOP_K];          // per-wavefront top-k lists
+    uint32_t wid[kBlock / 64][PS_MAX_TOP_K];
+    unsigned long long wc[kBlock / 64][PS_MAX_TOP_K];
 };
 
 // LDS layout (dynamic):
@@ -402,18 +408,16 @@ size_t scan_lds_bytes(const KParams& kp, bool wide) {
 }
 
 // Hyperscore of one candidate that passed the filter: log10(n_b! n_y! S) from
-// the fp64 tables, its histogram bin (width 0.1, last bin open), and the
-// thread's top-k list.
-template <typename C, int K, bool DUMP>
-__device__ __forceinline__ void score_one(const ScanArgs& A, ScanLds<C>& L, TopK<K, C>& top, uint32_t s,
-                                          uint32_t id, C c, uint32_t& scored) {
+// the fp64 tables, plus its histogram bin (width 0.1, last bin open).
+template <typename C, bool DUMP>
+__device__ __forceinline__ double score_one(const ScanArgs& A, ScanLds<C>& L, uint32_t s, uint32_t id, C c,
+                                            uint32_t& scored) {
     const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c), sq = Cnt<C>::s(c);
     const double h = (A.ix.lf[nb] + A.ix.lf[ny]) + A.ix.ls[sq];
     const double hb = floor(10.0 * h);
     const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
     atomicAdd(&L.hist[bin], 1);
     ++scored;
-    top.insert(h, id, c);
     if (DUMP) {
         const unsigned long long slot = atomicAdd(&A.w.counters[kCtrDump], 1ull);
         if (slot < A.w.dump_cap) {
@@ -423,12 +427,13 @@ __device__ __forceinline__ void score_one(const ScanArgs& A, ScanLds<C>& L, TopK
             A.w.dump_cnt_hi[slot] = sq;
         }
     }
+    return h;
 }
 
 // One work item: spectrum s, candidate ids [ida, idb).  Writes the item's top
 // hits to `out` (top_k entries) and adds its histogram and counts to the
 // spectrum's global accumulators.
-template <typename C, int K, bool DUMP>
+template <typename C, bool DUMP>
 __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint32_t s, uint32_t ida,
                           uint32_t idb, ps_hit* out) {
     const uint32_t tid = threadIdx.x;
@@ -493,8 +498,10 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     // no posting in range: every counter stays 0 < k_min, nothing can be scored
     const uint32_t id_end = (nlight + ncoop + nhh) ? idb : ida;
 
-    TopK<K, C> top;
+    WaveTopK<C> top;
     top.init();
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t kk = kp.top_k;
     uint32_t scored = 0;
     const uint32_t kmin = kp.min_shared;
     const uint64_t bmw = ix.bm_words;
@@ -585,100 +592,82 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             // words) are read and cleared for the next tile; candidates with at
             // least k_min shared peaks are buffered for scoring
             const uint32_t w0 = tb >> 5;
-            for (uint32_t i = tid; i < nt; i += kBlock) {
-                C c = L.cnt[i];
-                L.cnt[i] = 0;
-                const uint32_t id = tb + i;
-                for (uint32_t h = 0; h < nhh; ++h) {
-                    const uint32_t* bw = L.bmw + h * 2 * wpt;
-                    const uint32_t wd = (id >> 5) - w0, sh5 = id & 31u;
-                    const uint32_t q = L.hh_q[h];
-                    if ((bw[wd] >> sh5) & 1u) c += Cnt<C>::inc(0u, q);
-                    if ((bw[wpt + wd] >> sh5) & 1u) c += Cnt<C>::inc(1u, q);
+            for (uint32_t base = wave * 64u; base < nt; base += kBlock) {   // wave-uniform trip count
+                const uint32_t i = base + lane;
+                bool ovf = false;
+                C c = 0;
+                if (i < nt) {
+                    c = L.cnt[i];
+                    L.cnt[i] = 0;
+                    const uint32_t id = tb + i;
+                    for (uint32_t h = 0; h < nhh; ++h) {
+                        const uint32_t* bw = L.bmw + h * 2 * wpt;
+                        const uint32_t wd = (id >> 5) - w0, sh5 = id & 31u;
+                        const uint32_t q = L.hh_q[h];
+                        if ((bw[wd] >> sh5) & 1u) c += Cnt<C>::inc(0u, q);
+                        if ((bw[wpt + wd] >> sh5) & 1u) c += Cnt<C>::inc(1u, q);
+                    }
+                    if (Cnt<C>::nb(c) + Cnt<C>::ny(c) >= kmin) {
+                        const uint32_t slot = atomicAdd(&sh.ncand, 1u);
+                        if (slot < kCandCap) {
+                            L.cand_idx[slot] = (uint16_t)i;
+                            L.cand_cnt[slot] = c;
+                        } else {
+                            ovf = true;                 // buffer full: score in place below
+                        }
+                    }
                 }
-                if (Cnt<C>::nb(c) + Cnt<C>::ny(c) < kmin) continue;
-                const uint32_t slot = atomicAdd(&sh.ncand, 1u);
-                if (slot < kCandCap) {
-                    L.cand_idx[slot] = (uint16_t)i;
-                    L.cand_cnt[slot] = c;
-                } else {
-                    score_one<C, K, DUMP>(A, L, top, s, id, c, scored);   // buffer full: score in place
+                if (__ballot(ovf)) {
+                    const double h = ovf ? score_one<C, DUMP>(A, L, s, tb + i, c, scored) : -INFINITY;
+                    top.insert_lanes(ovf, h, tb + i, c, kk);
                 }
             }
             __syncthreads();
             // hyperscore, histogram, top-k over the buffered candidates
             const uint32_t ncand = min(sh.ncand, kCandCap);
-            for (uint32_t j = tid; j < ncand; j += kBlock)
-                score_one<C, K, DUMP>(A, L, top, s, tb + L.cand_idx[j], L.cand_cnt[j], scored);
+            for (uint32_t base = wave * 64u; base < ncand; base += kBlock) {
+                const uint32_t j = base + lane;
+                const bool ok = j < ncand;
+                const C c = ok ? L.cand_cnt[j] : (C)0;
+                const uint32_t id = ok ? tb + L.cand_idx[j] : 0u;
+                const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
+                top.insert_lanes(ok, h, id, c, kk);
+            }
             __syncthreads();
         }
         for (uint32_t c = tid; c < ncoop; c += kBlock) L.seg_cur[L.coop[c]] = L.bnd[c * (kChunkTiles + 1) + nch];
         __syncthreads();
     }
 
-    // top-k of the item: the threads' lists are merged group by group (a group's
-    // lists and the ping-pong space of its merge tree fit in the counter area),
-    // each group's best list then merged into an accumulator
-    const uint32_t kk = kp.top_k;
-    const uint32_t G = kp.merge_groups, gsz = kBlock / G;
-    MergeEnt<C>* acc = (MergeEnt<C>*)sh.acc;
-    MergeEnt<C>* acc2 = (MergeEnt<C>*)sh.acc2;
-    if (tid < kk) { acc[tid].h = -INFINITY; acc[tid].id = 0xFFFFFFFFu; acc[tid].c = 0; }
-    for (uint32_t g = 0; g < G; ++g) {
-        MergeEnt<C>* ma = (MergeEnt<C>*)L.cnt;
-        MergeEnt<C>* mb = ma + gsz * kk;
-        __syncthreads();
-        if (tid / gsz == g) {
-            const uint32_t r = tid - g * gsz;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                if ((uint32_t)j < kk) {
-                    MergeEnt<C> m; m.h = top.h[j]; m.id = top.id[j]; m.c = top.c[j];
-                    ma[r * kk + j] = m;
-                }
-            }
-        }
-        __syncthreads();
-        for (uint32_t half = gsz / 2; half >= 1; half >>= 1) {
-            if (tid < half) {
-                const MergeEnt<C>* x = ma + tid * kk;
-                const MergeEnt<C>* y = ma + (tid + half) * kk;
-                MergeEnt<C>* o = mb + tid * kk;
-                uint32_t ix_ = 0, iy = 0;
-                for (uint32_t j = 0; j < kk; ++j) {
-                    const bool takex = TopK<K, C>::better(x[ix_].h, x[ix_].id, y[iy].h, y[iy].id);
-                    o[j] = takex ? x[ix_] : y[iy];
-                    if (takex) ++ix_; else ++iy;
-                }
-            }
-            __syncthreads();
-            MergeEnt<C>* t = ma; ma = mb; mb = t;
-        }
-        if (tid == 0) {
-            uint32_t ix_ = 0, iy = 0;
-            for (uint32_t j = 0; j < kk; ++j) {
-                const bool takex = TopK<K, C>::better(acc[ix_].h, acc[ix_].id, ma[iy].h, ma[iy].id);
-                acc2[j] = takex ? acc[ix_] : ma[iy];
-                if (takex) ++ix_; else ++iy;
-            }
-            for (uint32_t j = 0; j < kk; ++j) acc[j] = acc2[j];
-        }
+    // top-k of the item: the wavefronts' lists, merged by one thread
+    if (lane < kk) {
+        sh.wh[wave][lane] = top.h;
+        sh.wid[wave][lane] = top.id;
+        sh.wc[wave][lane] = (unsigned long long)top.c;
     }
-    __syncthreads();
-    const MergeEnt<C>* ml = acc;
     const unsigned long long sc = block_sum<unsigned long long>(scored, sh.red);   // has barriers
-    if (tid < kk) {
-        const MergeEnt<C> m = ml[tid];
-        ps_hit o;
-        o.id = m.id;
-        o.n_b = (uint16_t)(m.id == 0xFFFFFFFFu ? 0 : Cnt<C>::nb(m.c));
-        o.n_y = (uint16_t)(m.id == 0xFFFFFFFFu ? 0 : Cnt<C>::ny(m.c));
-        o.sum_q = m.id == 0xFFFFFFFFu ? 0 : Cnt<C>::s(m.c);
-        o.pad = 0;
-        o.hyperscore = m.h;
-        out[tid] = o;
+    if (tid == 0) {
+        uint32_t head[kBlock / 64];
+        for (int v = 0; v < kBlock / 64; ++v) head[v] = 0;
+        for (uint32_t j = 0; j < kk; ++j) {
+            int best = 0;
+            for (int v = 1; v < kBlock / 64; ++v)
+                if (better_hit(sh.wh[v][head[v]], sh.wid[v][head[v]], sh.wh[best][head[best]], sh.wid[best][head[best]]))
+                    best = v;
+            const uint32_t hh = head[best]++;
+            const C c = (C)sh.wc[best][hh];
+            const uint32_t id = sh.wid[best][hh];
+            ps_hit o;
+            o.id = id;
+            o.n_b = (uint16_t)(id == 0xFFFFFFFFu ? 0 : Cnt<C>::nb(c));
+            o.n_y = (uint16_t)(id == 0xFFFFFFFFu ? 0 : Cnt<C>::ny(c));
+            o.sum_q = id == 0xFFFFFFFFu ? 0 : Cnt<C>::s(c);
+            o.pad = 0;
+            o.hyperscore = sh.wh[best][hh];
+            out[j] = o;
+        }
+        if (sc) atomicAdd(&A.w.n_scored[s], sc);
     }
-    if (tid == 0 && sc) atomicAdd(&A.w.n_scored[s], sc);
     for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) {
         const int32_t v = L.hist[i];
         if (v) atomicAdd(&A.w.hist[(uint64_t)s * kHistBins + i], v);
@@ -693,7 +682,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
 }
 
 // Plain schedule: workgroup s searches spectrum s's whole window.
-template <typename C, int K, bool DUMP>
+template <typename C, bool DUMP>
 __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
@@ -713,25 +702,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
         }
         return;
     }
-    scan_item<C, K, DUMP>(A, sh, L, s, inf.lo, inf.hi, out);
+    scan_item<C, DUMP>(A, sh, L, s, inf.lo, inf.hi, out);
 }
 
-// Thread groups for the top-k merge: a group's lists plus the ping-pong half
-// must fit in the counter area.
-static uint32_t merge_groups(const KParams& kp, bool wide) {
-    const size_t area = (size_t)kp.tile * (wide ? 8 : 4);
-    const size_t esz = wide ? 24 : 16;
-    uint32_t g = 1;
-    while (g < (uint32_t)kBlock && (size_t)(kBlock / g + kBlock / g / 2) * kp.top_k * esz > area) g *= 2;
-    return g;
-}
-
-template <typename C, int K, bool DUMP>
+template <typename C, bool DUMP>
 static hipError_t launch_scan_plain_t(ScanArgs a, uint64_t n, hipStream_t stream) {
-    a.kp.merge_groups = merge_groups(a.kp, sizeof(C) == 8);
     const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_scan_plain<C, K, DUMP>), dim3((uint32_t)n), dim3(kBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_scan_plain<C, DUMP>), dim3((uint32_t)n), dim3(kBlock), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -740,19 +718,17 @@ hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KPa
     if (sp.n == 0) return hipSuccess;
     ScanArgs a{ix, sp, kp, w, 1u, 0u, per_item ? 1u : 0u};
     hipError_t e = hipSuccess;
-    const bool k8 = kp.top_k <= 8;
     // narrow counters for every spectrum that proved it can use them, then wide
     if (!wide_only) {
         a.want_wide = 0;
-        if (dump) e = k8 ? launch_scan_plain_t<uint32_t, 8, true>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, true>(a, sp.n, stream);
-        else e = k8 ? launch_scan_plain_t<uint32_t, 8, false>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, 16, false>(a, sp.n, stream);
+        e = dump ? launch_scan_plain_t<uint32_t, true>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, false>(a, sp.n, stream);
         if (e != hipSuccess) return e;
     }
     a.want_wide = 1;
     // 64-bit counters take twice the LDS per candidate: halve the tile until it fits
     while (a.kp.tile > 1024 && scan_lds_bytes(a.kp, true) > kMaxLds) a.kp.tile /= 2;
-    if (dump) e = k8 ? launch_scan_plain_t<unsigned long long, 8, true>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, true>(a, sp.n, stream);
-    else e = k8 ? launch_scan_plain_t<unsigned long long, 8, false>(a, sp.n, stream) : launch_scan_plain_t<unsigned long long, 16, false>(a, sp.n, stream);
+    e = dump ? launch_scan_plain_t<unsigned long long, true>(a, sp.n, stream)
+             : launch_scan_plain_t<unsigned long long, false>(a, sp.n, stream);
     return e;
 }
 
@@ -811,7 +787,7 @@ hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& 
     return hipGetLastError();
 }
 
-template <typename C, int K>
+template <typename C>
 __global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
@@ -839,16 +815,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
         const uint32_t blk = inf.lo / span + (g - A.w.spec_item0[s]);
         const uint32_t ida = max(inf.lo, blk * span);
         const uint32_t idb = min(inf.hi, (blk + 1) * span);
-        scan_item<C, K, false>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
+        scan_item<C, false>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
     }
 }
 
-template <typename C, int K>
+template <typename C>
 static hipError_t launch_persistent_t(ScanArgs a, uint32_t grid, hipStream_t stream) {
-    a.kp.merge_groups = merge_groups(a.kp, sizeof(C) == 8);
     const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_scan_persistent<C, K>), dim3(grid), dim3(kBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_scan_persistent<C>), dim3(grid), dim3(kBlock), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -856,8 +831,7 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
                                   uint32_t grid, uint32_t tiles_per_item, hipStream_t stream) {
     if (sp.n == 0) return hipSuccess;
     ScanArgs a{ix, sp, kp, w, tiles_per_item, 0u, 1u};
-    hipError_t e = kp.top_k <= 8 ? launch_persistent_t<uint32_t, 8>(a, grid, stream)
-                                 : launch_persistent_t<uint32_t, 16>(a, grid, stream);
+    hipError_t e = launch_persistent_t<uint32_t>(a, grid, stream);
     if (e != hipSuccess) return e;
     // spectra that need 64-bit counters: one workgroup per spectrum, slot = its item
     return launch_scan_plain(ix, sp, kp, w, false, true, true, stream);
@@ -1019,11 +993,9 @@ hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams&
 // Allow every scan kernel the whole LDS once, before any launch or capture.
 hipError_t init_kernel_attributes() {
     const void* fns[] = {
-        (const void*)k_scan_plain<uint32_t, 8, false>, (const void*)k_scan_plain<uint32_t, 16, false>,
-        (const void*)k_scan_plain<uint32_t, 8, true>, (const void*)k_scan_plain<uint32_t, 16, true>,
-        (const void*)k_scan_plain<unsigned long long, 8, false>, (const void*)k_scan_plain<unsigned long long, 16, false>,
-        (const void*)k_scan_plain<unsigned long long, 8, true>, (const void*)k_scan_plain<unsigned long long, 16, true>,
-        (const void*)k_scan_persistent<uint32_t, 8>, (const void*)k_scan_persistent<uint32_t, 16>,
+        (const void*)k_scan_plain<uint32_t, false>, (const void*)k_scan_plain<uint32_t, true>,
+        (const void*)k_scan_plain<unsigned long long, false>, (const void*)k_scan_plain<unsigned long long, true>,
+        (const void*)k_scan_persistent<uint32_t>,
     };
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
