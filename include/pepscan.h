@@ -291,6 +291,49 @@ int ps_plan_stream(ps_plan* plan, void** stream);
 
 void ps_plan_free(ps_plan* plan);
 
+/* ---- serving: continuous batching over a resident index ----------------- */
+
+typedef struct {
+    uint64_t completed;       /* requests finished */
+    uint64_t spectra;         /* spectra in finished requests */
+    uint64_t runs;            /* device runs (each packs one or more requests) */
+    uint64_t refused;         /* submissions refused with PS_EAGAIN */
+    uint64_t max_queue;       /* deepest request queue seen */
+    uint32_t slots;           /* concurrent device runs the pool holds */
+    uint32_t pad;
+    uint64_t slot_bytes;      /* device bytes per slot */
+    double   p50_ms, p99_ms, max_ms, mean_ms;   /* latency from submit to completion */
+    double   elapsed_s;       /* first submit to last completion */
+} ps_serve_stats;
+
+/* A search server over an uploaded index.  The device `pool` is divided into
+ * as many slots as fit (at most max_slots), each a plan for up to
+ * slot_spectra spectra and slot_peaks peaks with its own stream.  A scheduler
+ * thread admits queued requests in arrival order: whenever a slot is free it
+ * packs waiting requests into one run up to the slot's capacity, so requests
+ * that arrive while others run are admitted as slots and memory free up, and
+ * runs on different slots overlap on the device.  params->schedule must be
+ * PS_SCHED_PERSISTENT.  max_pending bounds the host queue (0 = 2^20). */
+int ps_server_create(ps_index* idx, const ps_device* pool, const ps_search_params* params,
+                     uint64_t slot_spectra, uint64_t slot_peaks, uint32_t max_slots, uint64_t max_pending,
+                     ps_server** out);
+
+/* Queue a request (host spectra, copied).  PS_EAGAIN when the queue is full,
+ * PS_EINVAL for invalid spectra or a request larger than a slot.  Thread-safe. */
+int ps_server_submit(ps_server* server, const ps_spectra* spectra, uint64_t* ticket);
+
+/* Block until the request is done; write its results as ps_results does and
+ * its latency (submit to completion, ms).  Each ticket is waited for once.
+ * Thread-safe. */
+int ps_server_wait(ps_server* server, uint64_t ticket, ps_hit* hits, ps_stat* stats, int32_t* hist,
+                   double* latency_ms);
+
+int ps_server_stats(ps_server* server, ps_serve_stats* out);
+int ps_server_reset_stats(ps_server* server);
+
+/* Drains queued and running requests, then frees the server (not the pool). */
+void ps_server_free(ps_server* server);
+
 #ifdef __cplusplus
 }
 #endif

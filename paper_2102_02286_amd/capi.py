@@ -60,6 +60,13 @@ class ps_schedule(C.Structure):
                 ("groups_per_cu", C.c_uint32), ("use_bitmaps", C.c_uint32), ("pad", C.c_uint32)]
 
 
+class ps_serve_stats(C.Structure):
+    _fields_ = [("completed", C.c_uint64), ("spectra", C.c_uint64), ("runs", C.c_uint64), ("refused", C.c_uint64),
+                ("max_queue", C.c_uint64), ("slots", C.c_uint32), ("pad", C.c_uint32), ("slot_bytes", C.c_uint64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double), ("mean_ms", C.c_double),
+                ("elapsed_s", C.c_double)]
+
+
 HIT_DTYPE = np.dtype([("id", "<u4"), ("n_b", "<u2"), ("n_y", "<u2"), ("sum_q", "<u4"), ("pad", "<u4"),
                       ("hyperscore", "<f8")])
 STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8"), ("status", "<i4"),
@@ -107,6 +114,13 @@ _SIGS = [
     ("ps_plan_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _U64P, _U64P, _U64P]),
     ("ps_plan_stream", C.c_int, [_P, C.POINTER(_P)]),
     ("ps_plan_free", None, [_P]),
+    ("ps_server_create", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_search_params), C.c_uint64, C.c_uint64,
+                                   C.c_uint32, C.c_uint64, C.POINTER(_P)]),
+    ("ps_server_submit", C.c_int, [_P, C.POINTER(ps_spectra), _U64P]),
+    ("ps_server_wait", C.c_int, [_P, C.c_uint64, _P, _P, _P, C.POINTER(C.c_double)]),
+    ("ps_server_stats", C.c_int, [_P, C.POINTER(ps_serve_stats)]),
+    ("ps_server_reset_stats", C.c_int, [_P]),
+    ("ps_server_free", None, [_P]),
 ]
 
 _lib = None
@@ -179,6 +193,12 @@ ps_plan_results = _fn("ps_plan_results")
 ps_plan_timing = _fn("ps_plan_timing")
 ps_plan_stream = _fn("ps_plan_stream")
 ps_plan_free = _fn("ps_plan_free")
+ps_server_create = _fn("ps_server_create")
+ps_server_submit = _fn("ps_server_submit")
+ps_server_wait = _fn("ps_server_wait")
+ps_server_stats = _fn("ps_server_stats")
+ps_server_reset_stats = _fn("ps_server_reset_stats")
+ps_server_free = _fn("ps_server_free")
 
 
 def ptr(a: np.ndarray):

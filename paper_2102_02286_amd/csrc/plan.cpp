@@ -256,4 +256,13 @@ extern "C" int ps_plan_stream(ps_plan* P, void** stream) {
     return PS_OK;
 }
 
+// 1 when the plan is idle or its run has finished, 0 while it runs, -1 on error.
+extern "C" int ps_plan_event_query(ps_plan* P) {
+    if (!P || !P->in_flight) return 1;
+    hipError_t e = hipEventQuery(P->ev_done);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return -1;
+}
+
 extern "C" void ps_plan_free(ps_plan* P) { plan_destroy(P); }

@@ -270,3 +270,51 @@ class Plan:
     def search(self, sp) -> Results:
         self.run(sp)
         return self.results()
+
+
+class Server:
+    """Continuous-batching server over a resident index (see ps_server_create)."""
+
+    def __init__(self, index: HostIndex, params: capi.ps_search_params, slot_spectra: int, slot_peaks: int,
+                 pool_bytes: int, max_slots: int = 8, max_pending: int = 0, device: str = "cuda:0"):
+        torch = _torch()
+        self.index, self.params = index, params
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
+        dev = capi.ps_device(self.pool.data_ptr(), pool_bytes, None)
+        h = C.c_void_p()
+        check(capi.ps_server_create(index.handle, C.byref(dev), C.byref(params), slot_spectra, slot_peaks,
+                                    max_slots, max_pending, C.byref(h)), "ps_server_create")
+        self.handle = h
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            capi.ps_server_free(h)
+            self.handle = None
+
+    __del__ = close
+
+    def submit(self, sp) -> int:
+        s, keep = _spectra_struct(sp)
+        t = C.c_uint64()
+        check(capi.ps_server_submit(self.handle, C.byref(s), C.byref(t)), "ps_server_submit")
+        return t.value
+
+    def wait(self, ticket: int, n: int):
+        k = self.params.top_k
+        hits = np.zeros(n * k, capi.HIT_DTYPE)
+        stats = np.zeros(n, capi.STAT_DTYPE)
+        hist = np.zeros(n * capi.PS_HIST_BINS, np.int32) if self.params.want_hist else None
+        lat = C.c_double()
+        check(capi.ps_server_wait(self.handle, ticket, ptr(hits), ptr(stats), ptr(hist) if hist is not None else None,
+                                  C.byref(lat)), "ps_server_wait")
+        return (hits.reshape(n, k), stats, hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None,
+                lat.value)
+
+    def stats(self) -> capi.ps_serve_stats:
+        st = capi.ps_serve_stats()
+        check(capi.ps_server_stats(self.handle, C.byref(st)))
+        return st
+
+    def reset_stats(self):
+        check(capi.ps_server_reset_stats(self.handle))

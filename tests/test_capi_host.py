@@ -130,3 +130,17 @@ def test_search_params_validation_without_device():
     good = engine.search_params(False, 1, 1, 100, max_charge=3)
     assert capi.ps_workspace_bytes(h.handle, 10, 100, C.byref(good), C.byref(need)) == capi.PS_OK
     assert need.value > 10 * 512 * 4
+
+
+def test_server_and_plan_need_an_uploaded_index():
+    ok = synth.Proteome(np.frombuffer(b"PEPTIDEKAAAAR", np.uint8).copy(), np.array([0, 13], np.uint64))
+    h = engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [], 0)
+    prm = engine.search_params(False, 1000, 1, 50, max_charge=3, schedule=capi.PS_SCHED_PERSISTENT)
+    dev = capi.ps_device(None, 0, None)
+    out = C.c_void_p()
+    rc = capi.ps_plan_create(h.handle, C.byref(dev), 10, 100, C.byref(prm), C.byref(out))
+    assert rc in (capi.PS_EDEVICE, capi.PS_EINVAL) and not out.value
+    rc = capi.ps_server_create(h.handle, C.byref(dev), C.byref(prm), 10, 100, 2, 0, C.byref(out))
+    assert rc in (capi.PS_EDEVICE, capi.PS_EINVAL, capi.PS_ENOMEM) and not out.value
+    plain = engine.search_params(False, 1000, 1, 50, max_charge=3)
+    assert capi.ps_server_create(h.handle, C.byref(dev), C.byref(plain), 10, 100, 2, 0, C.byref(out)) == capi.PS_EINVAL
