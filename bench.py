@@ -1,12 +1,16 @@
-"""Benchmark: spectra searched per second on one MI355X.
+"""Benchmark: spectra searched per second on one MI355X (plain batch,
+persistent graph-captured batch, and continuous-batching serving).
 
-One step = the whole search path (prep, window, fragment-bin postings scan,
-shared-peak counting, hyperscore, top-k, histogram, expect value, results back
-to the host) over one batch of synthetic spectra already resident in HBM.
+One step = the whole search path (prep and precursor window, fragment-bin
+posting scan, shared-peak counting, hyperscore, top-k, score histogram,
+expect value, results back to the host) over one batch of synthetic spectra
+already resident in HBM.  `value` is the persistent (hipGraph, work-queue)
+form's throughput; the plain form and the serving loop (Poisson arrivals,
+p50/p99 latency) are reported beside it.
 
-Prints ONE JSON line (rank 0) with the throughput, the roofline figure of the
-dominant kernel (the posting scan) measured with HIP events on its stream, and
-the CPU oracle's rate on a bounded sample of the same workload.
+Prints ONE JSON line with the roofline figure of the dominant kernel (the
+posting scan, timed with HIP events on its stream) and the CPU oracle's rate
+on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -15,6 +19,7 @@ import ctypes as C
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -29,27 +34,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+class _DevArray:
+    def __init__(self, p, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (p, False), "version": 2}
+
+
 def device_spectra(sp, torch):
     dev = "cuda:0"
-    t = [torch.from_numpy(np.ascontiguousarray(sp.peak_off.astype(np.uint64).view(np.int64))).to(dev),
-         torch.from_numpy(np.ascontiguousarray(sp.mz)).to(dev),
-         torch.from_numpy(np.ascontiguousarray(sp.intensity)).to(dev),
-         torch.from_numpy(np.ascontiguousarray(sp.precursor_mz)).to(dev),
-         torch.from_numpy(np.ascontiguousarray(sp.charge)).to(dev)]
-    return t
+    return [torch.from_numpy(np.ascontiguousarray(sp.peak_off.astype(np.uint64).view(np.int64))).to(dev),
+            torch.from_numpy(np.ascontiguousarray(sp.mz)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(sp.intensity)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(sp.precursor_mz)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(sp.charge)).to(dev)]
 
 
-def run_steps(capi, engine, ix, dsp, n, nnz, prm, ws_dev, steps):
-    """Run `steps` searches back to back; returns per-step scan ms and counters."""
-    scan_ms, postings, lookups = [], 0, 0
+def fill_plan_inputs(plan, tens, torch):
+    d = plan.inputs()
+    for p, t, ts in [(d.peak_off, tens[0], "<i8"), (d.mz, tens[1], "<f4"), (d.intensity, tens[2], "<f4"),
+                     (d.precursor_mz, tens[3], "<f8"), (d.charge, tens[4], "|i1")]:
+        torch.as_tensor(_DevArray(p, t.numel(), ts), device="cuda").copy_(t)
+    torch.cuda.synchronize()
+
+
+def eager_steps(capi, engine, ix, dsp, n, nnz, prm, ws_dev, steps):
+    scan_ms, res = [], None
     for _ in range(steps):
         b = C.c_void_p()
         capi.check(capi.ps_search_device(ix.handle, C.byref(ws_dev), C.byref(dsp), nnz, C.byref(prm), C.byref(b)))
         res = engine.collect(b, n, prm)
         capi.ps_batch_free(b)
         scan_ms.append(res.scan_ms)
-        postings, lookups = res.postings, res.lookups
-    return scan_ms, postings, lookups, res
+    return scan_ms, res
 
 
 def cpu_baseline(w, prot, sp, seconds_target=15.0):
@@ -57,7 +72,6 @@ def cpu_baseline(w, prot, sp, seconds_target=15.0):
     threads = os.cpu_count() or 1
     db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
                          oracle.mods_from_synth(w.mods), w.max_mods)
-    # calibrate on a few spectra, then time a sample sized to ~seconds_target
     probe = sp.subset(np.arange(0, min(sp.n, threads)))
     t0 = time.perf_counter()
     db.search(probe, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared, threads=threads)
@@ -69,8 +83,51 @@ def cpu_baseline(w, prot, sp, seconds_target=15.0):
     db.search(sub, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": m / dt, "unit": "spectra/s", "cores": threads, "kind": "oracle",
-            "sample": f"{m} of the {sp.n} spectra (seed 99), full database, all {threads} host threads, "
-                      f"{dt:.1f} s"}
+            "sample": f"{m} of the {sp.n} spectra (seed 99), full database, all {threads} host threads, {dt:.1f} s"}
+
+
+def serve(engine, synth, ix, prm, sp, capacity, load, n_requests, seed, max_peaks):
+    """Poisson arrivals of requests of 1..4096 spectra at `load` x capacity."""
+    mean_size = (1 + 4096) / 2
+    rate = load * capacity / mean_size
+    t_arr, sizes = synth.poisson_arrivals(n_requests, rate, 1, 4096, seed=seed)
+    rng = np.random.default_rng(seed)
+    starts = rng.integers(0, sp.n, size=n_requests)
+    reqs = [sp.subset((np.arange(s, s + k) % sp.n)) for s, k in zip(starts, sizes)]
+    slot_n, slot_p = 4096, 4096 * max_peaks
+    pool = 6 * plan_bytes(engine, ix, prm, slot_n, slot_p)
+    srv = engine.Server(ix, prm, slot_spectra=slot_n, slot_peaks=slot_p, pool_bytes=pool, max_slots=6)
+    tickets = [None] * n_requests
+    lat = [None] * n_requests
+
+    def waiter():
+        for i in range(n_requests):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            lat[i] = srv.wait(tickets[i], reqs[i].n)[3]
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i in range(n_requests):
+        dt = t_arr[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets[i] = srv.submit(reqs[i])
+    th.join()
+    st = srv.stats()
+    srv.close()
+    return {"load": load, "arrival_rate_per_s": rate, "requests": n_requests, "spectra": int(st.spectra),
+            "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "max_ms": st.max_ms,
+            "spectra_per_s": st.spectra / st.elapsed_s if st.elapsed_s > 0 else None,
+            "runs": int(st.runs), "slots": int(st.slots)}
+
+
+def plan_bytes(engine, ix, prm, n, nnz):
+    from paper_2102_02286_amd import capi
+    b = C.c_uint64()
+    capi.check(capi.ps_plan_bytes(ix.handle, n, nnz, C.byref(prm), C.byref(b)))
+    return b.value
 
 
 def main():
@@ -80,8 +137,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--n-spectra", type=int, default=None)
-    ap.add_argument("--schedule", default="plain", choices=["plain", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--only", choices=["plain", "persistent"], default=None,
+                    help="time one form only (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -102,56 +162,123 @@ def main():
     log(f"index: {n_pep} peptides, {n_post} postings, {n_bins} bins, host build {time.perf_counter() - t0:.1f}s")
     ix.upload("cuda:0")
     torch.cuda.synchronize()
-    sched = capi.PS_SCHED_PLAIN if args.schedule == "plain" else capi.PS_SCHED_PERSISTENT
     max_charge = int(sp.charge.max()) if sp.n else 1
-    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
-                               max_charge=max_charge, schedule=sched, want_hist=False)
-    tens = device_spectra(sp, torch)
     nnz = int(sp.peak_off[-1])
+    max_peaks = int(np.diff(sp.peak_off.astype(np.int64)).max())
+    tens = device_spectra(sp, torch)
     dsp = capi.ps_spectra(sp.n, *[x.data_ptr() for x in tens])
-    need = C.c_uint64()
-    capi.check(capi.ps_workspace_bytes(ix.handle, sp.n, nnz, C.byref(prm), C.byref(need)))
+
+    def params(schedule):
+        return engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k,
+                                    w.min_shared, max_charge=max_charge, schedule=schedule, want_hist=False)
+
+    prm_plain, prm_pers = params(capi.PS_SCHED_PLAIN), params(capi.PS_SCHED_PERSISTENT)
+    out = {}
+
+    # ---- schedule: autotuned on a sample (identical results are checked inside)
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        best, trials = engine.autotune(ix, sp.subset(np.arange(0, min(sp.n, 5000))), prm_pers)
+        log(f"autotune: {len(trials)} trials in {time.perf_counter() - t0:.1f}s -> "
+            f"tile {best.tile} coop {best.coop_min} bitmaps {best.use_bitmaps} items {best.tiles_per_item} "
+            f"groups/CU {best.groups_per_cu}")
+    sc = ix.schedule()
+    schedule = {f: getattr(sc, f) for f, _ in capi.ps_schedule._fields_ if f != "pad"}
+
     ws = engine.Workspace()
+    need = C.c_uint64()
+    capi.check(capi.ps_workspace_bytes(ix.handle, sp.n, nnz, C.byref(prm_pers), C.byref(need)))
     ws_dev = ws.get(need.value)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} steps")
-    run_steps(capi, engine, ix, dsp, sp.n, nnz, prm, ws_dev, args.warmup)
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    t0 = time.perf_counter()
-    scan_ms, postings, lookups, res = run_steps(capi, engine, ix, dsp, sp.n, nnz, prm, ws_dev, args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt * 1000.0 / args.steps
-    value = sp.n * args.steps / dt
-    scan_avg = float(np.mean(scan_ms))
+
+    # ---- plain batch
+    plain = None
+    if args.only in (None, "plain"):
+        eager_steps(capi, engine, ix, dsp, sp.n, nnz, prm_plain, ws_dev, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        scan_ms, res_plain = eager_steps(capi, engine, ix, dsp, sp.n, nnz, prm_plain, ws_dev, args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plain = {"spectra_per_s": sp.n * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+                 "scan_ms": float(np.mean(scan_ms))}
+        log(f"plain: {plain['spectra_per_s']:.0f} spectra/s, {plain['ms_per_step']:.1f} ms/step, "
+            f"scan {plain['scan_ms']:.1f} ms")
+
+    # ---- persistent: the scan kernels timed with HIP events on their stream
+    scan_ms, res_eager = eager_steps(capi, engine, ix, dsp, sp.n, nnz, prm_pers, ws_dev, max(2, args.steps))
+    scan_avg = float(np.mean(scan_ms[1:] if len(scan_ms) > 1 else scan_ms))
+    postings, lookups = res_eager.postings, res_eager.lookups
+    if plain is not None:
+        assert res_eager.hits.tobytes() == res_plain.hits.tobytes(), "plain and persistent results differ"
+
+    # ---- persistent graph plan over the resident batch: the headline number
+    persistent = None
+    if args.only in (None, "persistent"):
+        plan = engine.Plan(ix, prm_pers, n_cap=sp.n, nnz_cap=nnz)
+        fill_plan_inputs(plan, tens, torch)
+        for _ in range(args.warmup):
+            plan.run_device(sp.n, nnz)
+            plan.results()
+        torch.cuda.synchronize()
+        log(f"timing {args.steps} persistent steps")
+        t0 = time.perf_counter()
+        graph_ms = []
+        for _ in range(args.steps):
+            plan.run_device(sp.n, nnz)
+            r = plan.results()
+            graph_ms.append(r.graph_ms)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert r.hits.tobytes() == res_eager.hits.tobytes(), "graph replay and eager results differ"
+        persistent = {"spectra_per_s": sp.n * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+                      "graph_ms": float(np.mean(graph_ms)), "scan_ms": scan_avg, "work_items": int(r.items)}
+        log(f"persistent: {persistent['spectra_per_s']:.0f} spectra/s, {persistent['ms_per_step']:.1f} ms/step, "
+            f"graph {persistent['graph_ms']:.1f} ms, scan {scan_avg:.1f} ms, {r.items} work items")
+        del plan
+    st = np.bincount(res_eager.stats["status"], minlength=6)
+    log(f"status counts {st.tolist()}")
+
     alg_bytes = 4.0 * postings + 16.0 * lookups
     achieved = alg_bytes / (scan_avg * 1e-3) / 1e9
-    log(f"{value:.1f} spectra/s, {ms_per_step:.2f} ms/step, scan {scan_avg:.2f} ms, "
-        f"{postings} postings, {lookups} bin lookups, {achieved:.0f} GB/s algorithmic")
-    st = np.bincount(res.stats["status"], minlength=6)
-    log(f"status counts {st.tolist()}")
-    out = {
+    head = persistent or plain
+    out.update({
         "metric": "spectra searched/sec at 1 MI355X (serving vs plain batch), p99 latency, HBM GB/s %",
-        "value": value,
+        "value": head["spectra_per_s"],
         "unit": "spectra/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {prot.n} proteins, {n_pep} peptides, {sp.n} spectra, "
+        "config": {"workload": f"{w.name}: {prot.n} proteins, {n_pep} peptides, {n_post} postings, {sp.n} spectra, "
                                f"window +-{w.window / 1e6:g} Da, fragment tol {w.frag_tol_bins} bin(s), "
-                               f"top {w.top_k}, schedule {args.schedule}"},
+                               f"top {w.top_k}, persistent work-queue scan replayed as a hipGraph"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_scan_plain (posting scan)", "scan_ms": scan_avg,
-                     "bytes_per_launch": alg_bytes},
-    }
+                     "kernel": "k_scan_persistent (posting scan)", "scan_ms": scan_avg,
+                     "bytes_per_launch": alg_bytes, "postings_per_launch": postings,
+                     "bin_lookups_per_launch": lookups},
+        "plain": plain,
+        "persistent": persistent,
+        "schedule": schedule,
+    })
+    log(f"roofline: {alg_bytes / 1e9:.1f} GB algorithmic per step in {scan_avg:.1f} ms = {achieved:.0f} GB/s")
+
+    # ---- serving: continuous batching at two loads
+    if not args.no_serving and persistent is not None:
+        cap = persistent["spectra_per_s"]
+        serving = []
+        for load, nreq, seed in [(0.5, 100, 2), (0.9, 200, 3)]:
+            r = serve(engine, synth, ix, prm_pers, sp, cap, load, nreq, seed, max_peaks)
+            log(f"serving load {load}: p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms, "
+                f"{r['spectra_per_s']:.0f} spectra/s over {r['requests']} requests ({r['runs']} runs)")
+            serving.append(r)
+        out["serving"] = serving
+
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, prot, sp)

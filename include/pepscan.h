@@ -291,6 +291,28 @@ int ps_plan_stream(ps_plan* plan, void** stream);
 
 void ps_plan_free(ps_plan* plan);
 
+/* ---- autotuning --------------------------------------------------------- */
+
+typedef struct {
+    ps_schedule schedule;
+    double      scan_ms;     /* scan time on the sample (HIP events) */
+    int32_t     same;        /* 1: results identical to the baseline schedule's */
+    int32_t     pad;
+} ps_tune_trial;
+
+/* Choose the scan schedule for `params` by measurement: coordinate descent
+ * over tile, coop_min, use_bitmaps and, for PS_SCHED_PERSISTENT,
+ * tiles_per_item and groups_per_cu, each candidate searching the host
+ * `sample` batch in `work` (candidates that do not fit it or the LDS are
+ * skipped).  Every candidate's results must equal the starting schedule's bit
+ * for bit (else PS_EDEVICE).  The fastest is set on the index and returned in
+ * `best`.  With a cache_path, a schedule stored under the same index shape and
+ * parameters is reused without measuring, and a new winner is written there.
+ * `trials` (may be NULL) receives up to max_trials measured candidates. */
+int ps_autotune(ps_index* idx, const ps_device* work, const ps_spectra* sample, const ps_search_params* params,
+                const char* cache_path, ps_tune_trial* trials, uint32_t max_trials, uint32_t* n_trials,
+                ps_schedule* best);
+
 /* ---- serving: continuous batching over a resident index ----------------- */
 
 typedef struct {

@@ -60,6 +60,10 @@ class ps_schedule(C.Structure):
                 ("groups_per_cu", C.c_uint32), ("use_bitmaps", C.c_uint32), ("pad", C.c_uint32)]
 
 
+class ps_tune_trial(C.Structure):
+    _fields_ = [("schedule", ps_schedule), ("scan_ms", C.c_double), ("same", C.c_int32), ("pad", C.c_int32)]
+
+
 class ps_serve_stats(C.Structure):
     _fields_ = [("completed", C.c_uint64), ("spectra", C.c_uint64), ("runs", C.c_uint64), ("refused", C.c_uint64),
                 ("max_queue", C.c_uint64), ("slots", C.c_uint32), ("pad", C.c_uint32), ("slot_bytes", C.c_uint64),
@@ -114,6 +118,9 @@ _SIGS = [
     ("ps_plan_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _U64P, _U64P, _U64P]),
     ("ps_plan_stream", C.c_int, [_P, C.POINTER(_P)]),
     ("ps_plan_free", None, [_P]),
+    ("ps_autotune", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra), C.POINTER(ps_search_params),
+                              C.c_char_p, C.POINTER(ps_tune_trial), C.c_uint32, C.POINTER(C.c_uint32),
+                              C.POINTER(ps_schedule)]),
     ("ps_server_create", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_search_params), C.c_uint64, C.c_uint64,
                                    C.c_uint32, C.c_uint64, C.POINTER(_P)]),
     ("ps_server_submit", C.c_int, [_P, C.POINTER(ps_spectra), _U64P]),
@@ -193,6 +200,7 @@ ps_plan_results = _fn("ps_plan_results")
 ps_plan_timing = _fn("ps_plan_timing")
 ps_plan_stream = _fn("ps_plan_stream")
 ps_plan_free = _fn("ps_plan_free")
+ps_autotune = _fn("ps_autotune")
 ps_server_create = _fn("ps_server_create")
 ps_server_submit = _fn("ps_server_submit")
 ps_server_wait = _fn("ps_server_wait")

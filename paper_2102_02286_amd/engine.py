@@ -180,6 +180,29 @@ def search(index: HostIndex, sp, params: capi.ps_search_params, ws: Workspace | 
         capi.ps_batch_free(b)
 
 
+def autotune(index: HostIndex, sample, params: capi.ps_search_params, cache_path: str | None = None,
+             ws: Workspace | None = None, headroom: int = 4):
+    """Measure candidate schedules on `sample` and set the fastest on the index.
+    Returns (best schedule, list of (schedule dict, scan_ms))."""
+    ws = ws or Workspace()
+    s, keep = _spectra_struct(sample)
+    need = C.c_uint64()
+    nnz = int(sample.peak_off[-1]) if sample.n else 0
+    check(capi.ps_workspace_bytes(index.handle, sample.n, nnz, C.byref(params), C.byref(need)))
+    dev = ws.get(need.value * headroom)
+    trials = (capi.ps_tune_trial * 256)()
+    nt = C.c_uint32()
+    best = capi.ps_schedule()
+    check(capi.ps_autotune(index.handle, C.byref(dev), C.byref(s), C.byref(params),
+                           cache_path.encode() if cache_path else None, trials, 256, C.byref(nt), C.byref(best)),
+          "ps_autotune")
+    out = []
+    for i in range(min(nt.value, 256)):
+        t = trials[i]
+        out.append(({f: getattr(t.schedule, f) for f, _ in capi.ps_schedule._fields_ if f != "pad"}, t.scan_ms))
+    return best, out
+
+
 def collect(batch, n: int, params: capi.ps_search_params) -> Results:
     hits = np.zeros(n * params.top_k, capi.HIT_DTYPE)
     stats = np.zeros(n, capi.STAT_DTYPE)

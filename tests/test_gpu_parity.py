@@ -235,6 +235,27 @@ def test_plan_device_inputs(small_open):
     assert_parity(SimpleNamespace(hits=got.hits, stats=got.stats, hist=got.hist), oh, ost, og)
 
 
+def test_autotune_keeps_results_and_caches(small_open, tmp_path):
+    w, prot, sp, ix, db, (oh, ost, og) = small_open
+    old = ix.schedule()
+    try:
+        prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                                   max_charge=3, schedule=capi.PS_SCHED_PERSISTENT)
+        cache = str(tmp_path / "tune.txt")
+        _say("autotune")
+        best, trials = engine.autotune(ix, sp.subset(np.arange(0, 60)), prm, cache_path=cache)
+        assert len(trials) >= 5
+        res = engine.search(ix, sp, prm)
+        assert_parity(res, oh, ost, og)
+        # a second call finds the cached schedule and measures nothing
+        capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
+        best2, trials2 = engine.autotune(ix, sp.subset(np.arange(0, 60)), prm, cache_path=cache)
+        assert trials2 == [] and bytes(best2) == bytes(best)
+        assert bytes(ix.schedule()) == bytes(best)
+    finally:
+        capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
