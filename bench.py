@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--only", choices=["plain", "persistent"], default=None,
                     help="time one form only (for profiling runs)")
     args = ap.parse_args()
@@ -175,15 +176,22 @@ def main():
     prm_plain, prm_pers = params(capi.PS_SCHED_PLAIN), params(capi.PS_SCHED_PERSISTENT)
     out = {}
 
-    # ---- schedule: autotuned on a sample (identical results are checked inside)
-    if not args.no_tune:
-        t0 = time.perf_counter()
-        best, trials = engine.autotune(ix, sp.subset(np.arange(0, min(sp.n, 5000))), prm_pers)
-        log(f"autotune: {len(trials)} trials in {time.perf_counter() - t0:.1f}s -> "
-            f"tile {best.tile} coop {best.coop_min} bitmaps {best.use_bitmaps} items {best.tiles_per_item} "
-            f"groups/CU {best.groups_per_cu}")
-    sc = ix.schedule()
-    schedule = {f: getattr(sc, f) for f, _ in capi.ps_schedule._fields_ if f != "pad"}
+    # ---- schedules: each form autotuned on a sample (identical results are checked inside)
+    def as_dict(sc):
+        return {f: getattr(sc, f) for f, _ in capi.ps_schedule._fields_ if f != "pad"}
+
+    default = ix.schedule()
+    tuned = {}
+    for name, prm in (("plain", prm_plain), ("persistent", prm_pers)):
+        capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(default)))
+        if not args.no_tune:
+            t0 = time.perf_counter()
+            best, trials = engine.autotune(ix, sp.subset(np.arange(0, min(sp.n, 5000))), prm)
+            log(f"autotune {name}: {len(trials)} trials in {time.perf_counter() - t0:.1f}s -> {as_dict(best)}")
+        tuned[name] = capi.ps_schedule.from_buffer_copy(ix.schedule())
+
+    def use(name):
+        capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(tuned[name])))
 
     ws = engine.Workspace()
     need = C.c_uint64()
@@ -192,6 +200,7 @@ def main():
 
     # ---- plain batch
     plain = None
+    use("plain")
     if args.only in (None, "plain"):
         eager_steps(capi, engine, ix, dsp, sp.n, nnz, prm_plain, ws_dev, args.warmup)
         torch.cuda.synchronize()
@@ -205,6 +214,7 @@ def main():
             f"scan {plain['scan_ms']:.1f} ms")
 
     # ---- persistent: the scan kernels timed with HIP events on their stream
+    use("persistent")
     scan_ms, res_eager = eager_steps(capi, engine, ix, dsp, sp.n, nnz, prm_pers, ws_dev, max(2, args.steps))
     scan_avg = float(np.mean(scan_ms[1:] if len(scan_ms) > 1 else scan_ms))
     postings, lookups = res_eager.postings, res_eager.lookups
@@ -264,7 +274,7 @@ def main():
                      "bin_lookups_per_launch": lookups},
         "plain": plain,
         "persistent": persistent,
-        "schedule": schedule,
+        "schedule": {"plain": as_dict(tuned["plain"]), "persistent": as_dict(tuned["persistent"])},
     })
     log(f"roofline: {alg_bytes / 1e9:.1f} GB algorithmic per step in {scan_avg:.1f} ms = {achieved:.0f} GB/s")
 
@@ -278,6 +288,16 @@ def main():
                 f"{r['spectra_per_s']:.0f} spectra/s over {r['requests']} requests ({r['runs']} runs)")
             serving.append(r)
         out["serving"] = serving
+
+    if args.copy_probe:
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE under
+        # rocprofv3 --pmc scale the scan kernel's counters to bytes
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 1 << 30
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
