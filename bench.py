@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="file caching autotuned schedules")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--only", choices=["plain", "persistent"], default=None,
                     help="time one form only (for profiling runs)")
@@ -186,7 +187,8 @@ def main():
         capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(default)))
         if not args.no_tune:
             t0 = time.perf_counter()
-            best, trials = engine.autotune(ix, sp.subset(np.arange(0, min(sp.n, 5000))), prm)
+            best, trials = engine.autotune(ix, sp.subset(np.arange(0, min(sp.n, 5000))), prm,
+                                           cache_path=args.tune_cache)
             log(f"autotune {name}: {len(trials)} trials in {time.perf_counter() - t0:.1f}s -> {as_dict(best)}")
         tuned[name] = capi.ps_schedule.from_buffer_copy(ix.schedule())
 
