@@ -123,6 +123,26 @@ def serve(engine, synth, ix, prm, sp, capacity, load, n_requests, seed, max_peak
             "runs": int(st.runs), "slots": int(st.slots)}
 
 
+def measured_traffic(workload_name):
+    """HBM bytes per scan launch from the committed rocprofv3 counter summary,
+    valid only while the kernel source is the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "scan_persistent_medium_hbm_counters.md")
+    if workload_name != "medium" or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    ") and line.strip().split(":")[0] in (
+                "traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.strip().split(":", 1)
+            vals[k] = v.strip()
+    src = os.path.join(ROOT, "paper_2102_02286_amd", "csrc", "kernels.hip")
+    now = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != now:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def plan_bytes(engine, ix, prm, n, nnz):
     from paper_2102_02286_amd import capi
     b = C.c_uint64()
@@ -270,7 +290,7 @@ def main():
                                f"window +-{w.window / 1e6:g} Da, fragment tol {w.frag_tol_bins} bin(s), "
                                f"top {w.top_k}, persistent work-queue scan replayed as a hipGraph"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
                      "kernel": "k_scan_persistent (posting scan)", "scan_ms": scan_avg,
                      "bytes_per_launch": alg_bytes, "postings_per_launch": postings,
                      "bin_lookups_per_launch": lookups},

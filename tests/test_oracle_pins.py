@@ -423,3 +423,36 @@ def test_oracle_rejects_invalid_inputs():
         db.search(bad, False, 1, 1, 10, 5, 1)
     with pytest.raises(ValueError):
         _db(["PEPTIDEXK"])                               # non-standard residue
+
+
+@pytest.mark.parametrize("z", [1, 2, 3])
+def test_window_edges_are_inclusive(z):
+    """filter_1 keeps a candidate whose mass differs from the query's by exactly
+    the tolerance, and drops one a micro-dalton further (absolute and ppm)."""
+    db = _db(["PEPTIDEK"], missed=0, min_len=8, max_len=8)
+    assert len(db) == 1
+    pep = sum(bf.RES_UDA[c] for c in "PEPTIDEK") + bf.WATER_UDA
+    peaks = [[(300.0, 1.0)]]
+
+    def window_of(mq, ppm, w):
+        # precursor m/z whose rounded micro-dalton value gives neutral mass mq at charge z
+        assert mq % z == 0
+        prec = (mq // z + bf.PROTON_UDA) / 1e6
+        _, st, _ = db.search(_spectra(peaks, [prec], [z]), ppm, w, 1, 10, 1, 1)
+        return int(st[0]["n_window"])
+
+    # every residue of the query mass modulo z, so both edges are hit exactly for some dm
+    edges = 0
+    for dm in range(1000, 1000 + z):
+        for mq in range(pep - dm - 2 * z - (pep - dm) % z, pep + dm + 2 * z, z):
+            inside = abs(pep - mq) <= dm
+            edges += abs(pep - mq) == dm
+            assert window_of(mq, False, dm) == int(inside), (dm, mq)
+    assert edges >= 2
+    # ppm: the tolerance is floor(M_q * ppm / 1e6) micro-daltons
+    ppm = 10
+    t0 = pep * ppm // 1_000_000
+    near = [m for c in (pep - t0, pep + t0) for m in range(c - 6 * z - c % z, c + 6 * z, z)]
+    for mq in near:
+        tol = mq * ppm // 1_000_000
+        assert window_of(mq, True, ppm) == int(abs(pep - mq) <= tol), mq
