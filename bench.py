@@ -199,7 +199,7 @@ def main():
 
     # ---- schedules: each form autotuned on a sample (identical results are checked inside)
     def as_dict(sc):
-        return {f: getattr(sc, f) for f, _ in capi.ps_schedule._fields_ if f != "pad"}
+        return {f: getattr(sc, f) for f, _ in capi.ps_schedule._fields_ if f != "reserved"}
 
     default = ix.schedule()
     tuned = {}

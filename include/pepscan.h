@@ -145,13 +145,11 @@ typedef struct {
  * it only changes speed.  Chosen by default at index creation, by ps_autotune,
  * or set by the caller. */
 typedef struct {
-    uint32_t tile;            /* candidates per LDS counter tile: 1024..32768, multiple of 256 */
-    uint32_t coop_min;        /* a posting run longer than this (within one work item) is
-                                 streamed by the whole workgroup; shorter runs by one thread */
-    uint32_t tiles_per_item;  /* PS_SCHED_PERSISTENT: tiles per work item (>= 1) */
+    uint32_t tile;            /* candidates per LDS counter tile: a power of two in 1024..32768 and
+                                 at least the index's tile grain (ps_index_directory) */
+    uint32_t tiles_per_item;  /* PS_SCHED_PERSISTENT: tiles per work item (1..4096) */
     uint32_t groups_per_cu;   /* PS_SCHED_PERSISTENT: resident workgroups per compute unit (1..8) */
-    uint32_t use_bitmaps;     /* 1: dense fragment bins are read as b/y bitmaps, 0: as postings */
-    uint32_t pad;
+    uint32_t reserved[3];     /* must be 0 */
 } ps_schedule;
 
 /* ---- errors ------------------------------------------------------------ */
@@ -202,9 +200,15 @@ int ps_index_host_arrays(const ps_index* idx, uint64_t* bin_off, uint32_t* posti
 int ps_index_set_schedule(ps_index* idx, const ps_schedule* schedule);
 int ps_index_get_schedule(const ps_index* idx, ps_schedule* schedule);
 
-/* Number of dense fragment bins stored as bitmaps (bins holding at least 1/16
- * of all entries), and the device bytes of those bitmaps. */
-int ps_index_bitmap_bins(const ps_index* idx, uint32_t* n_bins, uint64_t* bytes);
+/* The tile directory: for every fragment bin and every block of
+ * 2^grain_shift peptide ids, the position of the bin's first posting at or
+ * after the block (Superstep 3's filter_2 reads a bin's postings inside an id
+ * range; the directory turns every tile boundary of that range into one load).
+ * grain_shift is 12 unless the directory would exceed 16 GiB; `bytes` is its
+ * size.  `dir`, if not NULL, receives a host copy of `bytes` bytes laid out as
+ * [n_bins][(n_pep >> grain_shift) + 2] uint32 postings positions.  Any pointer
+ * may be NULL. */
+int ps_index_directory(const ps_index* idx, uint32_t* grain_shift, uint64_t* bytes, uint32_t* dir);
 
 void ps_index_free(ps_index* idx);
 
@@ -301,9 +305,8 @@ typedef struct {
 } ps_tune_trial;
 
 /* Choose the scan schedule for `params` by measurement: coordinate descent
- * over tile, coop_min, use_bitmaps and, for PS_SCHED_PERSISTENT,
- * tiles_per_item and groups_per_cu, each candidate searching the host
- * `sample` batch in `work` (candidates that do not fit it or the LDS are
+ * over tile and, for PS_SCHED_PERSISTENT, tiles_per_item and groups_per_cu,
+ * each candidate searching the host `sample` batch in `work` (candidates that do not fit it or the LDS are
  * skipped).  Every candidate's results must equal the starting schedule's bit
  * for bit (else PS_EDEVICE).  The fastest is set on the index and returned in
  * `best`.  With a cache_path, a schedule stored under the same index shape and

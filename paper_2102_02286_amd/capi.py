@@ -56,8 +56,8 @@ class ps_search_params(C.Structure):
 
 
 class ps_schedule(C.Structure):
-    _fields_ = [("tile", C.c_uint32), ("coop_min", C.c_uint32), ("tiles_per_item", C.c_uint32),
-                ("groups_per_cu", C.c_uint32), ("use_bitmaps", C.c_uint32), ("pad", C.c_uint32)]
+    _fields_ = [("tile", C.c_uint32), ("tiles_per_item", C.c_uint32), ("groups_per_cu", C.c_uint32),
+                ("reserved", C.c_uint32 * 3)]
 
 
 class ps_tune_trial(C.Structure):
@@ -96,7 +96,7 @@ _SIGS = [
     ("ps_index_host_arrays", C.c_int, [_P, _P, _P]),
     ("ps_index_set_schedule", C.c_int, [_P, C.POINTER(ps_schedule)]),
     ("ps_index_get_schedule", C.c_int, [_P, C.POINTER(ps_schedule)]),
-    ("ps_index_bitmap_bins", C.c_int, [_P, C.POINTER(C.c_uint32), _U64P]),
+    ("ps_index_directory", C.c_int, [_P, C.POINTER(C.c_uint32), _U64P, C.c_void_p]),
     ("ps_index_free", None, [_P]),
     ("ps_workspace_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
     ("ps_search_batch", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra),
@@ -182,7 +182,7 @@ ps_peptide = _fn("ps_peptide")
 ps_index_host_arrays = _fn("ps_index_host_arrays")
 ps_index_set_schedule = _fn("ps_index_set_schedule")
 ps_index_get_schedule = _fn("ps_index_get_schedule")
-ps_index_bitmap_bins = _fn("ps_index_bitmap_bins")
+ps_index_directory = _fn("ps_index_directory")
 ps_index_free = _fn("ps_index_free")
 ps_workspace_bytes = _fn("ps_workspace_bytes")
 ps_search_batch = _fn("ps_search_batch")

@@ -1,8 +1,7 @@
 // autotune.cpp -- pick the scan schedule by measurement.
 //
-// Coordinate descent over the schedule fields (tile, cooperative threshold,
-// dense-bin bitmaps, and for the persistent schedule the work-item size and
-// resident workgroups per CU): each candidate searches a sample batch, its
+// Coordinate descent over the schedule fields (tile, and for the persistent
+// schedule the work-item size and resident workgroups per CU): each candidate searches a sample batch, its
 // scan is timed with HIP events, and its results must equal the baseline's
 // bit for bit (a schedule only changes speed).  The winner is set on the index
 // and, if a cache file is given, stored under a key made of the index shape
@@ -47,7 +46,7 @@ bool cache_lookup(const char* path, const std::string& key, ps_schedule* out) {
         std::istringstream is(line);
         std::string k;
         ps_schedule s{};
-        if (is >> k >> s.tile >> s.coop_min >> s.tiles_per_item >> s.groups_per_cu >> s.use_bitmaps && k == key) {
+        if (is >> k >> s.tile >> s.tiles_per_item >> s.groups_per_cu && k == key) {
             *out = s;
             return true;
         }
@@ -69,8 +68,7 @@ void cache_store(const char* path, const std::string& key, const ps_schedule& s)
     }
     std::ofstream f(path, std::ios::trunc);
     for (auto& l : keep) f << l << "\n";
-    f << key << " " << s.tile << " " << s.coop_min << " " << s.tiles_per_item << " " << s.groups_per_cu << " "
-      << s.use_bitmaps << "\n";
+    f << key << " " << s.tile << " " << s.tiles_per_item << " " << s.groups_per_cu << "\n";
 }
 
 struct Outcome {
@@ -135,7 +133,6 @@ extern "C" int ps_autotune(ps_index* ix, const ps_device* work, const ps_spectra
         record(s, o.ms, ok);
         if (!ok) return fail(PS_EDEVICE, "schedule (tile %u) changed the results", s.tile);
         *ms_out = o.ms;
-        if (!ref) return PS_OK;
         return PS_OK;
     };
     Outcome ref = run_once(ix, work, sample, params);
@@ -147,22 +144,19 @@ extern "C" int ps_autotune(ps_index* ix, const ps_device* work, const ps_spectra
     const bool persistent = params->schedule == PS_SCHED_PERSISTENT;
     for (int pass = 0; pass < 2; ++pass) {
         bool improved = false;
-        for (int field = 0; field < 5; ++field) {
+        for (int field = 0; field < 3; ++field) {
             std::vector<uint32_t> vals;
             switch (field) {
-                case 0: vals = {2048, 4096, 8192}; break;
-                case 1: vals = {1024, 2048, 4096, 8192, 16384}; break;
-                case 2: vals = {0, 1}; break;
-                case 3: if (persistent) vals = {64, 128, 256, 512}; break;
-                case 4: if (persistent) vals = {4, 6, 8}; break;
+                case 0: vals = {4096, 8192, 16384}; break;
+                case 1: if (persistent) vals = {8, 16, 32, 64, 128, 256}; break;
+                case 2: if (persistent) vals = {3, 4, 5, 6, 8}; break;
             }
             for (uint32_t v : vals) {
                 ps_schedule s = cur;
-                uint32_t* f = field == 0 ? &s.tile : field == 1 ? &s.coop_min : field == 2 ? &s.use_bitmaps
-                            : field == 3 ? &s.tiles_per_item : &s.groups_per_cu;
+                uint32_t* f = field == 0 ? &s.tile : field == 1 ? &s.tiles_per_item : &s.groups_per_cu;
                 if (*f == v) continue;
                 *f = v;
-                if (check_schedule(s) != PS_OK) continue;
+                if (check_schedule(s) != PS_OK || s.tile < (1u << ix->dir_shift)) continue;
                 double ms = 0;
                 rc = measure(s, &ref, &ms);
                 if (rc == PS_ENOMEM || rc == PS_EINVAL) continue;   // does not fit this block / LDS

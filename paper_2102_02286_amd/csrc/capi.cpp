@@ -87,32 +87,34 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
     kp->max_charge = p->max_charge;
     kp->ent_stride = (uint32_t)stride;
     kp->seg_cap = (uint32_t)segs;
+    int rc = check_schedule(*sched);
+    if (rc != PS_OK) return rc;
+    if (ix && sched->tile < (1u << ix->dir_shift))
+        return fail(PS_EINVAL, "tile %u is smaller than this index's tile grain %u", sched->tile,
+                    1u << ix->dir_shift);
     kp->tile = sched->tile;
-    kp->coop_min = sched->coop_min;
-    kp->use_bitmaps = sched->use_bitmaps;
+    kp->tile_shift = (uint32_t)__builtin_ctz(sched->tile);
     if (scan_lds_bytes(*kp, false) > kMaxLds)
         return fail(PS_EINVAL, "tile %u needs %zu bytes of LDS with these parameters (max %zu)", kp->tile,
                     scan_lds_bytes(*kp, false), kMaxLds);
-    (void)ix;
     return PS_OK;
 }
 
 Schedule default_schedule() {
-    Schedule s;
+    Schedule s{};
     s.tile = 4096;
-    s.coop_min = 4096;
     s.tiles_per_item = 64;
     s.groups_per_cu = 4;
-    s.use_bitmaps = 0;
-    s.pad = 0;
     return s;
 }
 
 int check_schedule(const Schedule& s) {
-    if (s.tile < 1024 || s.tile > 32768 || s.tile % 256) return fail(PS_EINVAL, "tile must be 1024..32768, multiple of 256");
+    if (s.tile < 1024 || s.tile > 32768 || (s.tile & (s.tile - 1)))
+        return fail(PS_EINVAL, "tile must be a power of two in 1024..32768");
     if (s.tiles_per_item < 1 || s.tiles_per_item > 4096) return fail(PS_EINVAL, "tiles_per_item must be 1..4096");
     if (s.groups_per_cu < 1 || s.groups_per_cu > 8) return fail(PS_EINVAL, "groups_per_cu must be 1..8");
-    if (s.use_bitmaps > 1) return fail(PS_EINVAL, "use_bitmaps must be 0 or 1");
+    for (uint32_t r : s.reserved)
+        if (r) return fail(PS_EINVAL, "reserved schedule fields must be 0");
     return PS_OK;
 }
 
@@ -441,8 +443,9 @@ extern "C" int ps_index_set_schedule(ps_index* ix, const ps_schedule* s) {
     if (!ix || !s) return fail(PS_EINVAL, "NULL argument");
     int rc = check_schedule(*s);
     if (rc != PS_OK) return rc;
+    if (s->tile < (1u << ix->dir_shift))
+        return fail(PS_EINVAL, "tile %u is smaller than this index's tile grain %u", s->tile, 1u << ix->dir_shift);
     ix->sched = *s;
-    ix->sched.pad = 0;
     return PS_OK;
 }
 

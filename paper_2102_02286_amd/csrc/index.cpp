@@ -297,9 +297,13 @@ int index_build_host(ps_index* ix) {
     // Postings of one id in one bin must be ordered b before y; ions of one id are
     // emitted b-first, so each bin is non-decreasing in (id << 1 | type).
 
-    // 4. block directory: for every bin and every block of 2^dir_shift ids, the
-    // first posting at or after the block start, so a range search inside a bin
-    // starts from a block instead of the whole bin
+    // 4. tile directory: for every bin and every block of 2^dir_shift ids, the
+    // first posting at or after the block start.  A scan tile is a whole number
+    // of blocks, so every posting run's tile boundaries are direct lookups.  The
+    // grain is 4096 ids unless the directory would pass kDirBudget bytes.
+    constexpr uint64_t kDirBudget = 16ull << 30;
+    ix->dir_shift = 12;
+    while (ix->dir_shift < 16 && nbins * ((D >> ix->dir_shift) + 2) * 4 > kDirBudget) ++ix->dir_shift;
     ix->dir_nblk = (D >> ix->dir_shift) + 1;
     const uint64_t stride = ix->dir_nblk + 1;
     ix->dir.assign(nbins * stride, 0u);
@@ -315,42 +319,14 @@ int index_build_host(ps_index* ix) {
             }
         }
     });
-
-    // 5. dense bins (>= 1/16 of all entries, at most 64 of them) also as b/y
-    // bitmaps over the whole id space: for such a bin a bitmap is cheaper to read
-    // than its postings, and the scan adds them while scoring instead of with atomics
-    ix->heavy_slot.assign(nbins, -1);
-    ix->heavy_bins.clear();
-    ix->bm_words = (D + 31) / 32 + 1;
-    std::vector<std::pair<uint64_t, uint32_t>> dense;
-    const uint64_t min_count = std::max<uint64_t>(64, D / 16);
-    for (uint64_t bn = 0; bn < nbins; ++bn) {
-        uint64_t c = ix->bin_off[bn + 1] - ix->bin_off[bn];
-        if (c >= min_count) dense.push_back({c, (uint32_t)bn});
-    }
-    std::sort(dense.begin(), dense.end(), [](auto& a, auto& b) { return a.first > b.first || (a.first == b.first && a.second < b.second); });
-    if (dense.size() > 64) dense.resize(64);
-    std::sort(dense.begin(), dense.end(), [](auto& a, auto& b) { return a.second < b.second; });
-    ix->bitmaps.assign(dense.size() * 2 * ix->bm_words, 0u);
-    for (size_t h = 0; h < dense.size(); ++h) {
-        const uint32_t bn = dense[h].second;
-        ix->heavy_slot[bn] = (int32_t)h;
-        ix->heavy_bins.push_back(bn);
-        uint32_t* bb = ix->bitmaps.data() + h * 2 * ix->bm_words;
-        uint32_t* yb = bb + ix->bm_words;
-        for (uint64_t i = ix->bin_off[bn]; i < ix->bin_off[bn + 1]; ++i) {
-            const uint32_t p = ix->post[i], id = p >> 1;
-            (p & 1u ? yb : bb)[id >> 5] |= 1u << (id & 31);
-        }
-    }
     return PS_OK;
 }
 
-// Device layout: [mass][bin_off][post][lf][ls], each 256-byte aligned.
+// Device layout: [mass][bin_off][post][lf][ls][dir], each 256-byte aligned.
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
 struct DevLayout {
-    uint64_t mass, bin, post, lf, ls, slot, bm, dir, total;
+    uint64_t mass, bin, post, lf, ls, dir, total;
 };
 
 static DevLayout index_device_layout(const ps_index* ix) {
@@ -361,8 +337,6 @@ static DevLayout index_device_layout(const ps_index* ix) {
     L.post = o; o = align256(o + ix->post.size() * sizeof(uint32_t));
     L.lf = o; o = align256(o + kLfSize * sizeof(double));
     L.ls = o; o = align256(o + kLsSize * sizeof(double));
-    L.slot = o; o = align256(o + ix->heavy_slot.size() * sizeof(int32_t));
-    L.bm = o; o = align256(o + ix->bitmaps.size() * sizeof(uint32_t));
     L.dir = o; o = align256(o + ix->dir.size() * sizeof(uint32_t));
     L.total = o;
     return L;
@@ -437,6 +411,7 @@ extern "C" int ps_index_create(const ps_db_params* params, const char* residues,
     int rc;
     try { rc = index_build_host(ix); } catch (...) { rc = fail(PS_ENOMEM, "out of host memory building the index"); }
     if (rc != PS_OK) { delete ix; return rc; }
+    if (ix->sched.tile < (1u << ix->dir_shift)) ix->sched.tile = 1u << ix->dir_shift;
     *out = ix;
     return PS_OK;
 }
@@ -473,8 +448,6 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     cp(lay.post, ix->post.data(), ix->post.size() * sizeof(uint32_t));
     cp(lay.lf, lf.data(), lf.size() * sizeof(double));
     cp(lay.ls, ls.data(), ls.size() * sizeof(double));
-    cp(lay.slot, ix->heavy_slot.data(), ix->heavy_slot.size() * sizeof(int32_t));
-    cp(lay.bm, ix->bitmaps.data(), ix->bitmaps.size() * sizeof(uint32_t));
     cp(lay.dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
@@ -484,10 +457,6 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     d.post = (const uint32_t*)(base + lay.post);
     d.lf = (const double*)(base + lay.lf);
     d.ls = (const double*)(base + lay.ls);
-    d.heavy_slot = (const int32_t*)(base + lay.slot);
-    d.bitmaps = (const uint32_t*)(base + lay.bm);
-    d.bm_words = ix->bm_words;
-    d.n_heavy = (uint32_t)ix->heavy_bins.size();
     d.dir = (const uint32_t*)(base + lay.dir);
     d.dir_shift = ix->dir_shift;
     d.dir_nblk = (uint32_t)ix->dir_nblk;
@@ -569,10 +538,11 @@ extern "C" int ps_index_host_arrays(const ps_index* ix, uint64_t* bin_off, uint3
     return PS_OK;
 }
 
-extern "C" int ps_index_bitmap_bins(const ps_index* ix, uint32_t* n_bins, uint64_t* bytes) {
+extern "C" int ps_index_directory(const ps_index* ix, uint32_t* grain_shift, uint64_t* bytes, uint32_t* dir) {
     if (!ix) return fail(PS_EINVAL, "NULL index");
-    if (n_bins) *n_bins = (uint32_t)ix->heavy_bins.size();
-    if (bytes) *bytes = ix->bitmaps.size() * sizeof(uint32_t);
+    if (grain_shift) *grain_shift = ix->dir_shift;
+    if (bytes) *bytes = ix->dir.size() * sizeof(uint32_t);
+    if (dir) memcpy(dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
     return PS_OK;
 }
 

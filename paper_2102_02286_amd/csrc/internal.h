@@ -36,14 +36,10 @@ struct DevIndex {
     const uint32_t* post;      // [n_post], value = id << 1 | is_y, sorted within a bin
     const double* lf;          // [kLfSize]  lf[n] = sum_{k=2..n} log10 k
     const double* ls;          // [kLsSize]  ls[s] = log10 s
-    const int32_t* heavy_slot; // [n_bins] bitmap slot of a dense bin, or -1
-    const uint32_t* bitmaps;   // [n_heavy * 2 * bm_words]: b bitmap, then y bitmap, per slot
     const uint32_t* dir;       // [n_bins * (dir_nblk + 1)] first posting of a bin at or after each id block
-    uint32_t dir_shift;        // id block = 1 << dir_shift ids
+    uint32_t dir_shift;        // id block = 1 << dir_shift ids (the tile grain)
     uint32_t dir_nblk;
     uint64_t n_pep, n_bins, n_post;
-    uint64_t bm_words;
-    uint32_t n_heavy;
     uint32_t max_len;          // longest peptide (residues)
     int64_t min_residue;       // lightest residue incl. modification deltas (uDa)
 };
@@ -84,10 +80,9 @@ struct KParams {
     uint32_t min_shared;
     uint32_t max_charge;
     uint32_t ent_stride;       // entry slots per spectrum = top_peaks * max(1, max_charge - 1)
-    uint32_t seg_cap;          // LDS segment slots per workgroup
-    uint32_t tile;             // candidates per LDS counter tile
-    uint32_t coop_min;         // segments longer than this are scanned cooperatively
-    uint32_t use_bitmaps;      // read dense bins through their bitmaps
+    uint32_t seg_cap;          // probe slots per workgroup (entries x bin offsets)
+    uint32_t tile;             // candidates per LDS counter tile: a power of two, >= 1 << dir_shift
+    uint32_t tile_shift;       // log2(tile)
 };
 
 // Workspace pointers of one batch (all inside the caller's device block).

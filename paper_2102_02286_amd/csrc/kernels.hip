@@ -4,10 +4,11 @@
 //              uDa, fragment-charge expansion to bin entries) and the precursor
 //              window (filter_1 of Supplementary Algorithm 3)
 //   k_scan     per work item (spectrum, id range): fragment-bin lookups to
-//              posting segments (filter_2), streaming of postings into LDS
-//              shared-peak counters tile by tile, then per tile the candidate
-//              filter (shared peaks >= k), hyperscore, per-thread top-k and the
-//              LDS score histogram (Supplementary Algorithm 3's score/heap)
+//              posting runs (filter_2), a load-balanced gather of each tile's
+//              postings into LDS shared-peak counters, then per tile the
+//              candidate filter (shared peaks >= k), hyperscore, wavefront
+//              top-k and the LDS score histogram (Supplementary Algorithm 3's
+//              score/heap)
 //   k_merge    merge of partial top-k lists, Savitzky-Golay smoothed survival
 //              function, linear tail fit and expect value (Superstep 4;
 //              Supplementary Algorithm 4)
@@ -39,28 +40,6 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t 
         if (a[mid] < v) lo = mid + 1; else hi = mid;
     }
     return lo;
-}
-
-// First index in [lo, hi) with a[i] >= v, found by one wavefront: each round
-// the 64 lanes probe evenly spaced positions and a ballot narrows the range
-// 64-fold, so a segment of n postings costs ~log64(n) dependent loads.
-// Must be called by all 64 lanes with identical (lo, hi, v).
-__device__ __forceinline__ uint32_t wave_lower_bound(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t v) {
-    const uint32_t lane = threadIdx.x & 63u;
-    while (hi - lo > 64u) {
-        uint32_t stride = (hi - lo + 63u) >> 6;
-        uint32_t p = lo + lane * stride;
-        bool pred = (p < hi) && (a[p] < v);
-        uint32_t c = (uint32_t)__popcll(__ballot(pred));
-        if (c == 0) return lo;
-        uint32_t nlo = lo + (c - 1u) * stride + 1u;
-        uint32_t nhi = min(hi, lo + c * stride);
-        lo = nlo;
-        hi = nhi;
-    }
-    uint32_t p = lo + lane;
-    bool pred = (p < hi) && (a[p] < v);
-    return lo + (uint32_t)__popcll(__ballot(pred));
 }
 
 template <typename T>
@@ -344,66 +323,77 @@ struct ScanArgs {
     uint32_t per_item;         // partial lists indexed by work item (persistent schedule)
 };
 
-constexpr uint32_t kCoopCap = 32;     // cooperative (long) segments per work item
-constexpr uint32_t kChunkTiles = 16;  // tiles per boundary chunk of the cooperative segments
-constexpr uint32_t kSentinel = 0xFFFFFFFFu;
-constexpr uint32_t kBmCap = 4;        // dense-bin bitmap hits per work item (more go the posting route)
+constexpr uint32_t kRounds = 8;       // gather rounds of 64 postings a wavefront keeps in flight
 constexpr uint32_t kCandCap = 512;    // scored candidates buffered per tile before scoring
+constexpr uint32_t kMapCap = 8192;    // flat posting positions mapped to slots at a time
 
 struct ScanShared {
-    uint32_t nseg, nlight, ncoop, nhh, ncand;
+    uint32_t nact, ncand;
+    unsigned long long wsum[kBlock / 64];
     unsigned long long red[kBlock / 64];
     double wh[kBlock / 64][PS_MAX_TOP_K];          // per-wavefront top-k lists
     uint32_t wid[kBlock / 64][PS_MAX_TOP_K];
     unsigned long long wc[kBlock / 64][PS_MAX_TOP_K];
 };
 
+// What the lookup pass finds for one fragment-bin probe with postings in the
+// item: its bin, its posting run [s0, s1) inside the item, the peak's integer
+// intensity and the ends of the run's first two tiles.
+struct SlotInit {
+    uint32_t bin, s0, s1, q, e0, e1;
+};
+
+// A slot with postings in the current tile, by rank among such slots: flat
+// position f of its range reads post[base + f]; q is its peak's intensity.
+struct SegBase {
+    uint32_t base, q;
+};
+
 // LDS layout (dynamic):
-//   counters (also the top-k merge area) | seg_cur | seg_end | seg_next | bitmap-hit slot |
-//   seg_q | light list | bitmap-hit q | coop list | coop tile boundaries | histogram
+//   counters (the SlotInit array before the first tile) | SegBase[seg_cap] |
+//   range starts [seg_cap] | map bits [kMapCap / 64] (u64) | map ranks [kMapCap / 64] |
+//   candidate counters | histogram | candidate positions
+//
+// The map of a chunk of kMapCap flat positions: bit b of mbits[R] is set when
+// a slot's range starts at position 64 R + b, and mrank[R] is the rank of the
+// slot holding position 64 R, so the slot of any position is one popcount away.
 template <typename C>
 struct ScanLds {
     C* cnt;
-    uint32_t* seg_cur;
-    uint32_t* seg_end;
-    uint32_t* seg_next;   // posting value at seg_cur (kSentinel when exhausted)
-    uint32_t* hh_slot;    // bitmap slot of each dense-bin hit
-    uint16_t* seg_q;
-    uint16_t* light;
-    uint16_t* hh_q;
-    uint16_t* coop;
-    uint32_t* bnd;        // [kCoopCap][kChunkTiles + 1]
-    uint32_t* bmw;        // [kBmCap][2][tile/32 + 2] bitmap words of the current tile
+    SlotInit* init;
+    SegBase* sbase;
+    uint32_t* sstart;
+    unsigned long long* mbits;
+    uint32_t* mrank;
     C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter
-    uint16_t* cand_idx;   // [kCandCap] their positions in the tile
     int32_t* hist;
-    __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap, uint32_t bmcap) {
+    uint16_t* cand_idx;   // [kCandCap] their positions in the tile
+    __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap) {
         size_t o = 0;
-        cnt = (C*)(base + o);
-        o += ((size_t)tile * sizeof(C) + 15) & ~(size_t)15;
+        cnt = (C*)base;
+        init = (SlotInit*)base;
+        const size_t head = max((size_t)tile * sizeof(C), (size_t)segcap * sizeof(SlotInit));
+        o += (head + 15) & ~(size_t)15;
+        sbase = (SegBase*)(base + o); o += (size_t)segcap * sizeof(SegBase);
+        mbits = (unsigned long long*)(base + o); o += (size_t)(kMapCap / 64) * 8;
+        sstart = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        mrank = (uint32_t*)(base + o); o += (size_t)(kMapCap / 64) * 4;
+        o = (o + 15) & ~(size_t)15;
         cand_cnt = (C*)(base + o); o += (size_t)kCandCap * sizeof(C);
-        seg_cur = (uint32_t*)(base + o); o += (size_t)segcap * 4;
-        seg_end = (uint32_t*)(base + o); o += (size_t)segcap * 4;
-        seg_next = (uint32_t*)(base + o); o += (size_t)segcap * 4;
-        hh_slot = (uint32_t*)(base + o); o += (size_t)kBmCap * 4;
-        bnd = (uint32_t*)(base + o); o += (size_t)kCoopCap * (kChunkTiles + 1) * 4;
-        bmw = (uint32_t*)(base + o); o += (size_t)bmcap * 2 * (tile / 32 + 2) * 4;
         hist = (int32_t*)(base + o); o += (size_t)kHistBins * 4;
-        seg_q = (uint16_t*)(base + o); o += (size_t)segcap * 2;
-        light = (uint16_t*)(base + o); o += (size_t)segcap * 2;
-        hh_q = (uint16_t*)(base + o); o += (size_t)kBmCap * 2;
-        coop = (uint16_t*)(base + o); o += (size_t)kCoopCap * 2;
         cand_idx = (uint16_t*)(base + o);
     }
 };
 
 size_t scan_lds_bytes(const KParams& kp, bool wide) {
     const size_t csz = wide ? 8 : 4;
-    size_t o = ((size_t)kp.tile * csz + 15) & ~(size_t)15;
+    const size_t head = std::max((size_t)kp.tile * csz, (size_t)kp.seg_cap * sizeof(SlotInit));
+    size_t o = (head + 15) & ~(size_t)15;
+    o += (size_t)kp.seg_cap * (sizeof(SegBase) + 4) + (size_t)(kMapCap / 64) * 12;
+    o = (o + 15) & ~(size_t)15;
     o += (size_t)kCandCap * csz;
-    o += (size_t)kp.seg_cap * 12 + (size_t)kBmCap * 4 + (size_t)kCoopCap * (kChunkTiles + 1) * 4;
-    o += (size_t)(kp.use_bitmaps ? kBmCap : 0) * 2 * (kp.tile / 32 + 2) * 4 + (size_t)kHistBins * 4;
-    o += (size_t)kp.seg_cap * 4 + (size_t)kBmCap * 2 + (size_t)kCoopCap * 2 + (size_t)kCandCap * 2;
+    o += (size_t)kHistBins * 4;
+    o += (size_t)kCandCap * 2;
     return (o + 15) & ~(size_t)15;
 }
 
@@ -430,213 +420,311 @@ __device__ __forceinline__ double score_one(const ScanArgs& A, ScanLds<C>& L, ui
     return h;
 }
 
+// Exclusive prefix sum over the workgroup in thread order; *total gets the sum.
+// Contains one barrier; `wsum` must not be in use by another pass.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* wsum, T* total) {
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    T x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63u) wsum[wave] = x;
+    __syncthreads();
+    T before = 0, all = 0;
+    for (uint32_t w = 0; w < kBlock / 64; ++w) {
+        const T t = wsum[w];
+        before += w < wave ? t : (T)0;
+        all += t;
+    }
+    *total = all;
+    return before + x - v;
+}
+
+// Enter the slot of rank k, whose range is [a, b), into the map of the chunk
+// [c0, c0 + kMapCap): its start bit, and the rank of every 64-position round
+// that begins inside it.
+template <typename C>
+__device__ __forceinline__ void map_slot(const ScanLds<C>& L, uint32_t k, uint32_t a, uint32_t b, uint32_t c0) {
+    const uint32_t ce = c0 + kMapCap;
+    if (b <= c0 || a >= ce) return;
+    if (a >= c0) atomicOr(&L.mbits[(a - c0) >> 6], 1ull << ((a - c0) & 63u));
+    const uint32_t lo = max(a, c0), hi = min(b, ce);
+    for (uint32_t r = (lo - c0 + 63u) >> 6; (r << 6) < hi - c0; ++r) L.mrank[r] = k;
+}
+
+// Gather state of one wavefront in the current chunk: its share [next, fe)
+// of the chunk's flat posting positions, and up to kRounds x 64 postings
+// already loaded.
+struct Gather {
+    uint32_t c0, fe, next;
+    uint32_t p[kRounds];
+    uint32_t q[kRounds];   // 0: no posting in this round
+};
+
+// Map flat positions [g.next, g.next + 64 * kRounds) of this wavefront to
+// slots through the chunk map and issue their posting loads.  A round is 64
+// aligned positions, so its map word and round rank are broadcast reads; the
+// rounds are independent and their reads issue back to back.
+template <typename C>
+__device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C>& L, Gather& g) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        const uint32_t f = g.next + 64u * r + lane;
+        const bool valid = f < g.fe;
+        const uint32_t R = min((g.next - g.c0) / 64u + r, kMapCap / 64u - 1u);   // clamped: rounds past fe
+        const unsigned long long bits = L.mbits[R];
+        const uint32_t k = L.mrank[R] + (uint32_t)__popcll(bits & ((2ull << lane) - 2ull));
+        const SegBase sb = L.sbase[valid ? k : 0u];
+        g.p[r] = valid ? ix.post[sb.base + f] : 0u;
+        g.q[r] = valid ? sb.q : 0u;
+    }
+    g.next += 64u * kRounds;
+}
+
+template <typename C>
+__device__ __forceinline__ void gather_consume(const ScanLds<C>& L, const Gather& g, uint32_t tb) {
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        if (g.q[r]) {
+            const uint32_t p = g.p[r];
+            atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, g.q[r]));
+        }
+    }
+}
+
 // One work item: spectrum s, candidate ids [ida, idb).  Writes the item's top
 // hits to `out` (top_k entries) and adds its histogram and counts to the
 // spectrum's global accumulators.
-template <typename C, bool DUMP>
+//
+// Lookup (filter_2): every (entry, bin offset) probe gives the bin's posting
+// run inside [ida, idb) from the tile directory (a search inside one
+// directory block only where ida or idb is not on a block edge).  Runs that
+// are not empty become probe slots, held in registers by their owner threads.
+//
+// Tiles: candidates [t * tile, (t + 1) * tile) share one LDS counter array.
+// The directory gives every run's tile boundaries directly, so the postings
+// of tile t + 1 are mapped and loaded while tile t is filtered and scored,
+// and the boundaries of tile t + 2 are loaded one tile earlier still.
+template <typename C, bool DUMP, uint32_t U>
 __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint32_t s, uint32_t ida,
                           uint32_t idb, ps_hit* out) {
     const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
     const KParams& kp = A.kp;
     const DevIndex& ix = A.ix;
     const uint32_t n_ent = A.w.info[s].n_ent;
     const uint32_t* ent = A.w.entries + (uint64_t)s * kp.ent_stride;
     const int T = kp.tol;
     const uint32_t width = (uint32_t)(2 * T + 1);
+    const uint32_t gsh = ix.dir_shift, tsh = kp.tile_shift;
+    const uint64_t stride = (uint64_t)ix.dir_nblk + 1;
+    const uint32_t t0 = ida >> tsh, t_last = (idb - 1) >> tsh;
 
-    if (tid == 0) { sh.nseg = 0; sh.nlight = 0; sh.ncoop = 0; sh.nhh = 0; }
+    if (tid == 0) { sh.nact = 0; sh.ncand = 0; }
     for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) L.hist[i] = 0;
     __syncthreads();
 
-    // filter_2, part 1: every (entry, bin offset) -> posting run inside [ida, idb).
-    // Dense bins become bitmap hits; long runs are streamed cooperatively; the
-    // rest are walked by one thread each.
+    // end of tile u's part of a run that ends at s1
+    auto tile_end = [&](const uint32_t* row, uint32_t u, uint32_t s1) -> uint32_t {
+        const uint64_t edge = (uint64_t)(u + 1) << tsh;
+        return edge >= idb ? s1 : min(s1, row[edge >> gsh]);
+    };
+
     unsigned long long lookups = 0, postings = 0;
     const uint32_t npairs = n_ent * width;
+    const uint32_t gmask = (1u << gsh) - 1u;
     for (uint32_t k = tid; k < npairs; k += kBlock) {
         const uint32_t e = ent[k / width];
         if (e == kEntryInvalid) continue;
         const int64_t bin = (int64_t)(e >> 8) + (int64_t)(k % width) - T;
         if (bin < 0 || bin >= (int64_t)ix.n_bins) continue;
         ++lookups;
-        const uint32_t* d = ix.dir + (uint64_t)bin * (ix.dir_nblk + 1);
-        // first posting with id >= ida / idb: exact when the id is block aligned,
-        // else a search inside one block of the bin
-        const uint32_t ka = ida >> ix.dir_shift, kb = idb >> ix.dir_shift;
-        const uint32_t a0 = d[ka];
-        const uint32_t s0 = (ida & ((1u << ix.dir_shift) - 1)) ? lower_bound_u32(ix.post, a0, d[ka + 1], ida << 1) : a0;
-        const uint32_t b0 = d[kb];
-        const uint32_t s1 = (idb & ((1u << ix.dir_shift) - 1)) ? lower_bound_u32(ix.post, b0, d[kb + 1], idb << 1) : b0;
+        const uint32_t* row = ix.dir + (uint64_t)bin * stride;
+        const uint32_t ka = ida >> gsh, kb = idb >> gsh;
+        const uint32_t s0 = (ida & gmask) ? lower_bound_u32(ix.post, row[ka], row[ka + 1], ida << 1) : row[ka];
+        const uint32_t s1 = (idb & gmask) ? lower_bound_u32(ix.post, row[kb], row[kb + 1], idb << 1) : row[kb];
         if (s1 <= s0) continue;
         postings += s1 - s0;
-        const uint16_t q = (uint16_t)(e & 0xFFu);
-        if (kp.use_bitmaps) {
-            const int32_t hs = ix.heavy_slot[bin];
-            if (hs >= 0) {
-                const uint32_t h = atomicAdd(&sh.nhh, 1u);
-                if (h < kBmCap) {
-                    L.hh_slot[h] = (uint32_t)hs;
-                    L.hh_q[h] = q;
-                    continue;
-                }
-            }
-        }
-        const uint32_t slot = atomicAdd(&sh.nseg, 1u);
-        L.seg_cur[slot] = s0;
-        L.seg_end[slot] = s1;
-        L.seg_q[slot] = q;
-        if (s1 - s0 > kp.coop_min) {
-            const uint32_t c = atomicAdd(&sh.ncoop, 1u);
-            if (c < kCoopCap) { L.coop[c] = (uint16_t)slot; continue; }
-        }
-        L.seg_next[slot] = ix.post[s0];
-        L.light[atomicAdd(&sh.nlight, 1u)] = (uint16_t)slot;
+        const uint32_t slot = atomicAdd(&sh.nact, 1u);
+        SlotInit si;
+        si.bin = (uint32_t)bin;
+        si.s0 = s0;
+        si.s1 = s1;
+        si.q = e & 0xFFu;
+        si.e0 = tile_end(row, t0, s1);
+        si.e1 = t0 < t_last ? tile_end(row, t0 + 1, s1) : s1;
+        L.init[slot] = si;
     }
     __syncthreads();
-    const uint32_t nlight = sh.nlight, nhh = min(sh.nhh, kBmCap);
-    const uint32_t ncoop = min(sh.ncoop, kCoopCap);
-    // no posting in range: every counter stays 0 < k_min, nothing can be scored
-    const uint32_t id_end = (nlight + ncoop + nhh) ? idb : ida;
+    const uint32_t nact = sh.nact;
+    // slots [tid * us, tid * us + us) belong to this thread
+    const uint32_t us = nact > kBlock ? (nact + kBlock - 1) / kBlock : 1u;
+    uint32_t o_bin[U], o_s1[U], o_q[U], o_cur[U], o_end[U], o_nxt[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t j = tid * us + u;
+        o_bin[u] = 0; o_s1[u] = 0; o_q[u] = 0; o_cur[u] = 0; o_end[u] = 0; o_nxt[u] = 0;
+        if (u < us && j < nact) {
+            const SlotInit si = L.init[j];
+            o_bin[u] = si.bin; o_s1[u] = si.s1; o_q[u] = si.q;
+            o_cur[u] = si.s0; o_end[u] = si.e0; o_nxt[u] = si.e1;
+        }
+    }
+    __syncthreads();                                   // SlotInit area becomes the counters
 
     WaveTopK<C> top;
     top.init();
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
     const uint32_t kk = kp.top_k;
-    uint32_t scored = 0;
     const uint32_t kmin = kp.min_shared;
-    const uint64_t bmw = ix.bm_words;
-    (void)bmw;
-    if (id_end > ida)
-        for (uint32_t i = tid; i < kp.tile; i += kBlock) L.cnt[i] = 0;
-    if (tid == 0) sh.ncand = 0;
-    const uint32_t wpt = kp.tile / 32 + 2;
-    __syncthreads();
-    for (uint32_t tc0 = ida; tc0 < id_end; tc0 += kChunkTiles * kp.tile) {
-        const uint32_t left = id_end - tc0;
-        const uint32_t nch = min(kChunkTiles, (left + kp.tile - 1) / kp.tile);
-        // tile boundaries of every cooperative run in this chunk
-        for (uint32_t q = tid; q < ncoop * nch; q += kBlock) {
-            const uint32_t c = q / nch, k = q - c * nch;
-            const uint32_t sg = L.coop[c];
-            const uint32_t lim = min(id_end, tc0 + (k + 1) * kp.tile) << 1;
-            L.bnd[c * (kChunkTiles + 1) + k + 1] = lower_bound_u32(ix.post, L.seg_cur[sg], L.seg_end[sg], lim);
+    uint32_t scored = 0;
+    Gather g;
+    uint32_t ptot = 0;
+
+    // flat map of tile t's postings from the owned slots' [cur, end) runs, then
+    // this wavefront's first gather batch
+    uint32_t nne = 0;                                   // slots with postings in the prepared tile
+
+    // this wavefront's share of the chunk [c0, c0 + kMapCap) of a tile with
+    // `total` flat positions
+    auto share = [&](uint32_t c0, uint32_t total) {
+        const uint32_t n = min(kMapCap, total - c0);
+        const uint32_t per = ((n + kBlock - 1) / kBlock) * 64u;
+        g.c0 = c0;
+        g.next = c0 + min(n, wave * per);
+        g.fe = c0 + min(n, wave * per + per);
+    };
+
+    // ranks, flat ranges and the map of the first chunk of the tile whose
+    // slots hold [o_cur, o_end), then this wavefront's first gather batch
+    auto prepare = [&]() {
+        for (uint32_t i = tid; i < kMapCap / 64u; i += kBlock) L.mbits[i] = 0ull;
+        unsigned long long mine = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {                 // unowned slots are 0 - 0
+            const uint32_t n = o_end[u] - o_cur[u];
+            mine += (unsigned long long)n | ((unsigned long long)(n != 0u) << 32);
         }
-        for (uint32_t c = tid; c < ncoop; c += kBlock) L.bnd[c * (kChunkTiles + 1)] = L.seg_cur[L.coop[c]];
+        unsigned long long total;
+        const unsigned long long ex = block_exclusive_scan<unsigned long long>(mine, sh.wsum, &total);
+        uint32_t run = (uint32_t)ex, rank = (uint32_t)(ex >> 32);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t n = o_end[u] - o_cur[u];
+            if (n) {
+                SegBase sb;
+                sb.base = o_cur[u] - run;
+                sb.q = o_q[u];
+                L.sbase[rank] = sb;
+                L.sstart[rank] = run;
+                map_slot<C>(L, rank, run, run + n, 0u);
+                run += n;
+                ++rank;
+            }
+        }
+        ptot = (uint32_t)total;
+        nne = (uint32_t)(total >> 32);
         __syncthreads();
-        for (uint32_t k = 0; k < nch; ++k) {
-            const uint32_t tb = tc0 + k * kp.tile;
-            const uint32_t te = min(id_end, tb + kp.tile);
-            const uint32_t nt = te - tb;
-            const uint32_t lim = te << 1;
-            if (tid == 0) sh.ncand = 0;
-            // this tile's words of the dense-bin bitmaps, staged in LDS
-            for (uint32_t q = tid; q < nhh * 2 * wpt; q += kBlock) {
-                const uint32_t h = q / (2 * wpt), r = q - h * 2 * wpt;
-                const uint32_t half = r / wpt, wi = r - half * wpt;
-                const uint64_t word = (uint64_t)(tb >> 5) + wi;
-                L.bmw[q] = word < bmw ? ix.bitmaps[(uint64_t)L.hh_slot[h] * 2 * bmw + half * bmw + word] : 0u;
-            }
-            // short runs: one thread each; the next posting id is cached in LDS so a
-            // run with nothing in this tile costs no global load
-            for (uint32_t j = tid; j < nlight; j += kBlock) {
-                const uint32_t sg = L.light[j];
-                uint32_t nx = L.seg_next[sg];
-                if (nx >= lim) continue;
-                uint32_t cur = L.seg_cur[sg];
-                const uint32_t end = L.seg_end[sg];
-                const uint32_t q = L.seg_q[sg];
-                atomicAdd(&L.cnt[(nx >> 1) - tb], Cnt<C>::inc(nx & 1u, q));
-                ++cur;
-                while (true) {
-                    if (cur >= end) { nx = kSentinel; break; }
-                    const uint32_t p0 = ix.post[cur];
-                    const uint32_t p1 = cur + 1 < end ? ix.post[cur + 1] : kSentinel;
-                    const uint32_t p2 = cur + 2 < end ? ix.post[cur + 2] : kSentinel;
-                    const uint32_t p3 = cur + 3 < end ? ix.post[cur + 3] : kSentinel;
-                    if (p0 >= lim) { nx = p0; break; }
-                    atomicAdd(&L.cnt[(p0 >> 1) - tb], Cnt<C>::inc(p0 & 1u, q));
-                    ++cur;
-                    if (p1 >= lim) { nx = p1; break; }
-                    atomicAdd(&L.cnt[(p1 >> 1) - tb], Cnt<C>::inc(p1 & 1u, q));
-                    ++cur;
-                    if (p2 >= lim) { nx = p2; break; }
-                    atomicAdd(&L.cnt[(p2 >> 1) - tb], Cnt<C>::inc(p2 & 1u, q));
-                    ++cur;
-                    if (p3 >= lim) { nx = p3; break; }
-                    atomicAdd(&L.cnt[(p3 >> 1) - tb], Cnt<C>::inc(p3 & 1u, q));
-                    ++cur;
-                }
-                L.seg_cur[sg] = cur;
-                L.seg_next[sg] = nx;
-            }
-            // long runs: the whole workgroup streams this tile's part, coalesced
-            for (uint32_t c = 0; c < ncoop; ++c) {
-                const uint32_t b0 = L.bnd[c * (kChunkTiles + 1) + k], b1 = L.bnd[c * (kChunkTiles + 1) + k + 1];
-                const uint32_t q = L.seg_q[L.coop[c]];
-                uint32_t i = b0 + tid;
-                for (; i + 3 * kBlock < b1; i += 4 * kBlock) {
-                    const uint32_t p0 = ix.post[i], p1 = ix.post[i + kBlock];
-                    const uint32_t p2 = ix.post[i + 2 * kBlock], p3 = ix.post[i + 3 * kBlock];
-                    atomicAdd(&L.cnt[(p0 >> 1) - tb], Cnt<C>::inc(p0 & 1u, q));
-                    atomicAdd(&L.cnt[(p1 >> 1) - tb], Cnt<C>::inc(p1 & 1u, q));
-                    atomicAdd(&L.cnt[(p2 >> 1) - tb], Cnt<C>::inc(p2 & 1u, q));
-                    atomicAdd(&L.cnt[(p3 >> 1) - tb], Cnt<C>::inc(p3 & 1u, q));
-                }
-                for (; i < b1; i += kBlock) {
-                    const uint32_t p = ix.post[i];
-                    atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
-                }
-            }
+        share(0u, ptot);
+        gather_issue<C>(ix, L, g);
+    };
+
+    if (nact > 0) {
+        for (uint32_t i = tid; i < kp.tile; i += kBlock) L.cnt[i] = (C)0;
+        prepare();
+    }
+    const uint32_t t_end = nact > 0 ? t_last + 1 : t0;
+    for (uint32_t t = t0; t < t_end; ++t) {
+        const uint32_t tb = t << tsh;
+        // counters of tile t: the batch loaded last, then any further batches,
+        // then any further chunks
+        gather_consume<C>(L, g, tb);
+        while (g.next < g.fe) {
+            gather_issue<C>(ix, L, g);
+            gather_consume<C>(L, g, tb);
+        }
+        const uint32_t p_t = ptot;
+        for (uint32_t c0 = kMapCap; c0 < p_t; c0 += kMapCap) {
+            __syncthreads();                            // every wavefront is done with the last map
+            for (uint32_t i = tid; i < kMapCap / 64u; i += kBlock) L.mbits[i] = 0ull;
             __syncthreads();
-            // candidate filter: counters (plus dense bins from the staged bitmap
-            // words) are read and cleared for the next tile; candidates with at
-            // least k_min shared peaks are buffered for scoring
-            const uint32_t w0 = tb >> 5;
-            for (uint32_t base = wave * 64u; base < nt; base += kBlock) {   // wave-uniform trip count
-                const uint32_t i = base + lane;
+            for (uint32_t k = tid; k < nne; k += kBlock)
+                map_slot<C>(L, k, L.sstart[k], k + 1 < nne ? L.sstart[k + 1] : p_t, c0);
+            __syncthreads();
+            share(c0, p_t);
+            while (g.next < g.fe) {
+                gather_issue<C>(ix, L, g);
+                gather_consume<C>(L, g, tb);
+            }
+        }
+        __syncthreads();
+        if (t < t_last) {
+            // slots move to tile t + 1; the end of their tile t + 2 is loaded now
+            // and first needed one tile later
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                o_cur[u] = o_end[u];
+                o_end[u] = o_nxt[u];
+                const uint32_t j = tid * us + u;
+                if (u < us && j < nact && t + 2 <= t_last)
+                    o_nxt[u] = tile_end(ix.dir + (uint64_t)o_bin[u] * stride, t + 2, o_s1[u]);
+                else
+                    o_nxt[u] = o_end[u];
+            }
+            prepare();
+        }
+        if (p_t == 0) continue;                         // no posting in this tile: counters are all 0
+        // candidate filter: counters are read and cleared four (narrow) or two
+        // (wide) at a time; candidates with at least k_min shared peaks are
+        // buffered for scoring
+        constexpr uint32_t kPer = 16 / sizeof(C);
+        const uint32_t nvec = kp.tile / kPer;
+        uint4* cv = (uint4*)L.cnt;
+        for (uint32_t base = wave * 64u; base < nvec; base += kBlock) {   // nvec is a multiple of kBlock
+            const uint32_t i = base + lane;
+            const uint4 v = cv[i];
+            cv[i] = make_uint4(0u, 0u, 0u, 0u);
+            C c[kPer];
+            if constexpr (kPer == 4) {
+                c[0] = (C)v.x; c[1] = (C)v.y; c[2] = (C)v.z; c[3] = (C)v.w;
+            } else {
+                c[0] = (C)(((unsigned long long)v.y << 32) | v.x);
+                c[1] = (C)(((unsigned long long)v.w << 32) | v.z);
+            }
+#pragma unroll
+            for (uint32_t e = 0; e < kPer; ++e) {
+                const uint32_t pos = i * kPer + e;
                 bool ovf = false;
-                C c = 0;
-                if (i < nt) {
-                    c = L.cnt[i];
-                    L.cnt[i] = 0;
-                    const uint32_t id = tb + i;
-                    for (uint32_t h = 0; h < nhh; ++h) {
-                        const uint32_t* bw = L.bmw + h * 2 * wpt;
-                        const uint32_t wd = (id >> 5) - w0, sh5 = id & 31u;
-                        const uint32_t q = L.hh_q[h];
-                        if ((bw[wd] >> sh5) & 1u) c += Cnt<C>::inc(0u, q);
-                        if ((bw[wpt + wd] >> sh5) & 1u) c += Cnt<C>::inc(1u, q);
-                    }
-                    if (Cnt<C>::nb(c) + Cnt<C>::ny(c) >= kmin) {
-                        const uint32_t slot = atomicAdd(&sh.ncand, 1u);
-                        if (slot < kCandCap) {
-                            L.cand_idx[slot] = (uint16_t)i;
-                            L.cand_cnt[slot] = c;
-                        } else {
-                            ovf = true;                 // buffer full: score in place below
-                        }
+                if (Cnt<C>::nb(c[e]) + Cnt<C>::ny(c[e]) >= kmin) {
+                    const uint32_t slot = atomicAdd(&sh.ncand, 1u);
+                    if (slot < kCandCap) {
+                        L.cand_idx[slot] = (uint16_t)pos;
+                        L.cand_cnt[slot] = c[e];
+                    } else {
+                        ovf = true;                     // buffer full: score in place
                     }
                 }
                 if (__ballot(ovf)) {
-                    const double h = ovf ? score_one<C, DUMP>(A, L, s, tb + i, c, scored) : -INFINITY;
-                    top.insert_lanes(ovf, h, tb + i, c, kk);
+                    const double h = ovf ? score_one<C, DUMP>(A, L, s, tb + pos, c[e], scored) : -INFINITY;
+                    top.insert_lanes(ovf, h, tb + pos, c[e], kk);
                 }
             }
-            __syncthreads();
-            // hyperscore, histogram, top-k over the buffered candidates
-            const uint32_t ncand = min(sh.ncand, kCandCap);
-            for (uint32_t base = wave * 64u; base < ncand; base += kBlock) {
-                const uint32_t j = base + lane;
-                const bool ok = j < ncand;
-                const C c = ok ? L.cand_cnt[j] : (C)0;
-                const uint32_t id = ok ? tb + L.cand_idx[j] : 0u;
-                const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
-                top.insert_lanes(ok, h, id, c, kk);
-            }
-            __syncthreads();
         }
-        for (uint32_t c = tid; c < ncoop; c += kBlock) L.seg_cur[L.coop[c]] = L.bnd[c * (kChunkTiles + 1) + nch];
         __syncthreads();
+        // hyperscore, histogram, top-k over the buffered candidates
+        const uint32_t ncand = min(sh.ncand, kCandCap);
+        for (uint32_t base = wave * 64u; base < ncand; base += kBlock) {
+            const uint32_t j = base + lane;
+            const bool ok = j < ncand;
+            const C c = ok ? L.cand_cnt[j] : (C)0;
+            const uint32_t id = ok ? tb + L.cand_idx[j] : 0u;
+            const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
+            top.insert_lanes(ok, h, id, c, kk);
+        }
+        __syncthreads();
+        if (tid == 0) sh.ncand = 0;
     }
 
     // top-k of the item: the wavefronts' lists, merged by one thread
@@ -682,11 +770,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
 }
 
 // Plain schedule: workgroup s searches spectrum s's whole window.
-template <typename C, bool DUMP>
+template <typename C, bool DUMP, uint32_t U>
 __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
-    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap, A.kp.use_bitmaps ? kBmCap : 0);
+    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap);
     const uint32_t s = blockIdx.x;
     if (s >= A.sp.hdr->n) return;
     const SpecInfo inf = A.w.info[s];
@@ -702,15 +790,40 @@ __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
         }
         return;
     }
-    scan_item<C, DUMP>(A, sh, L, s, inf.lo, inf.hi, out);
+    scan_item<C, DUMP, U>(A, sh, L, s, inf.lo, inf.hi, out);
+}
+
+// Register slots per thread for a workgroup that may hold seg_cap probe slots.
+static uint32_t slots_per_thread(uint32_t seg_cap) {
+    const uint32_t u = (seg_cap + kBlock - 1) / kBlock;
+    return u <= 2 ? 2u : (u <= 4 ? 4u : 8u);
+}
+
+template <typename C, bool DUMP, uint32_t U>
+static hipError_t launch_scan_plain_u(ScanArgs a, uint64_t n, hipStream_t stream) {
+    const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_scan_plain<C, DUMP, U>), dim3((uint32_t)n), dim3(kBlock), lds, stream, a);
+    return hipGetLastError();
 }
 
 template <typename C, bool DUMP>
 static hipError_t launch_scan_plain_t(ScanArgs a, uint64_t n, hipStream_t stream) {
-    const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
-    if (lds > kMaxLds) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_scan_plain<C, DUMP>), dim3((uint32_t)n), dim3(kBlock), lds, stream, a);
-    return hipGetLastError();
+    switch (slots_per_thread(a.kp.seg_cap)) {
+        case 2: return launch_scan_plain_u<C, DUMP, 2>(a, n, stream);
+        case 4: return launch_scan_plain_u<C, DUMP, 4>(a, n, stream);
+        default: return launch_scan_plain_u<C, DUMP, 8>(a, n, stream);
+    }
+}
+
+// 64-bit counters take twice the LDS per candidate: halve the tile (down to
+// one directory block) until the workgroup fits.
+static KParams wide_params(const DevIndex& ix, KParams kp) {
+    while (kp.tile > (1u << ix.dir_shift) && scan_lds_bytes(kp, true) > kMaxLds) {
+        kp.tile /= 2;
+        kp.tile_shift -= 1;
+    }
+    return kp;
 }
 
 hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
@@ -725,8 +838,7 @@ hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KPa
         if (e != hipSuccess) return e;
     }
     a.want_wide = 1;
-    // 64-bit counters take twice the LDS per candidate: halve the tile until it fits
-    while (a.kp.tile > 1024 && scan_lds_bytes(a.kp, true) > kMaxLds) a.kp.tile /= 2;
+    a.kp = wide_params(ix, kp);
     e = dump ? launch_scan_plain_t<unsigned long long, true>(a, sp.n, stream)
              : launch_scan_plain_t<unsigned long long, false>(a, sp.n, stream);
     return e;
@@ -787,12 +899,12 @@ hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& 
     return hipGetLastError();
 }
 
-template <typename C>
+template <typename C, uint32_t U>
 __global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
     __shared__ uint32_t s_item;
-    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap, A.kp.use_bitmaps ? kBmCap : 0);
+    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap);
     const uint32_t n = (uint32_t)A.sp.hdr->n;
     const uint32_t total = A.w.spec_item0[n];
     const uint32_t tpi = A.tiles_per_item;
@@ -815,15 +927,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
         const uint32_t blk = inf.lo / span + (g - A.w.spec_item0[s]);
         const uint32_t ida = max(inf.lo, blk * span);
         const uint32_t idb = min(inf.hi, (blk + 1) * span);
-        scan_item<C, false>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
+        scan_item<C, false, U>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
     }
 }
 
-template <typename C>
+template <typename C, uint32_t U>
 static hipError_t launch_persistent_t(ScanArgs a, uint32_t grid, hipStream_t stream) {
     const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_scan_persistent<C>), dim3(grid), dim3(kBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_scan_persistent<C, U>), dim3(grid), dim3(kBlock), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -831,7 +943,10 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
                                   uint32_t grid, uint32_t tiles_per_item, hipStream_t stream) {
     if (sp.n == 0) return hipSuccess;
     ScanArgs a{ix, sp, kp, w, tiles_per_item, 0u, 1u};
-    hipError_t e = launch_persistent_t<uint32_t>(a, grid, stream);
+    const uint32_t u = slots_per_thread(kp.seg_cap);
+    hipError_t e = u == 2 ? launch_persistent_t<uint32_t, 2>(a, grid, stream)
+                 : u == 4 ? launch_persistent_t<uint32_t, 4>(a, grid, stream)
+                          : launch_persistent_t<uint32_t, 8>(a, grid, stream);
     if (e != hipSuccess) return e;
     // spectra that need 64-bit counters: one workgroup per spectrum, slot = its item
     return launch_scan_plain(ix, sp, kp, w, false, true, true, stream);
@@ -992,11 +1107,12 @@ hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams&
 
 // Allow every scan kernel the whole LDS once, before any launch or capture.
 hipError_t init_kernel_attributes() {
-    const void* fns[] = {
-        (const void*)k_scan_plain<uint32_t, false>, (const void*)k_scan_plain<uint32_t, true>,
-        (const void*)k_scan_plain<unsigned long long, false>, (const void*)k_scan_plain<unsigned long long, true>,
-        (const void*)k_scan_persistent<uint32_t>,
-    };
+#define PS_PLAIN_FNS(U)                                                                             \
+        (const void*)k_scan_plain<uint32_t, false, U>, (const void*)k_scan_plain<uint32_t, true, U>,  \
+        (const void*)k_scan_plain<unsigned long long, false, U>,                                       \
+        (const void*)k_scan_plain<unsigned long long, true, U>, (const void*)k_scan_persistent<uint32_t, U>
+    const void* fns[] = {PS_PLAIN_FNS(2), PS_PLAIN_FNS(4), PS_PLAIN_FNS(8)};
+#undef PS_PLAIN_FNS
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
         if (e != hipSuccess) return e;

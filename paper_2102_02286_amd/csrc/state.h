@@ -46,13 +46,8 @@ struct ps_index {
     std::vector<uint32_t> post;
     uint32_t max_len_seen = 0;
     int64_t min_residue = 0;
-    // dense bins as b/y bitmaps over all ids (slot h: words [2h*W, 2h*W + W) = b, then y)
-    std::vector<int32_t> heavy_slot;      // [n_bins], -1 = postings only
-    std::vector<uint32_t> heavy_bins;     // bin of each slot
-    std::vector<uint32_t> bitmaps;        // [n_heavy * 2 * bm_words]
-    uint64_t bm_words = 0;
-    // block directory: dir[bin * (dir_nblk + 1) + k] = first posting of `bin` with id >= k << dir_shift
-    uint32_t dir_shift = 16;
+    // tile directory: dir[bin * (dir_nblk + 1) + k] = first posting of `bin` with id >= k << dir_shift
+    uint32_t dir_shift = 12;
     uint64_t dir_nblk = 0;
     std::vector<uint32_t> dir;
     ps_schedule sched{};

@@ -108,10 +108,19 @@ class HostIndex:
         check(capi.ps_index_set_schedule(self.handle, C.byref(sc)), "ps_index_set_schedule")
         return sc
 
-    def bitmap_bins(self):
-        n, b = C.c_uint32(), C.c_uint64()
-        check(capi.ps_index_bitmap_bins(self.handle, C.byref(n), C.byref(b)))
-        return n.value, b.value
+    def directory(self):
+        """(grain_shift, device bytes) of the tile directory."""
+        g, b = C.c_uint32(), C.c_uint64()
+        check(capi.ps_index_directory(self.handle, C.byref(g), C.byref(b), None))
+        return g.value, b.value
+
+    def directory_array(self) -> np.ndarray:
+        """Host copy of the tile directory, [n_bins, (n_pep >> grain) + 2]."""
+        g, nbytes = self.directory()
+        n_pep, _, n_bins = self.shape()
+        d = np.zeros(nbytes // 4, np.uint32)
+        check(capi.ps_index_directory(self.handle, None, None, ptr(d)))
+        return d.reshape(n_bins, (n_pep >> g) + 2)
 
     def device_bytes(self) -> int:
         b = C.c_uint64()

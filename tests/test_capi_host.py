@@ -132,6 +132,43 @@ def test_search_params_validation_without_device():
     assert need.value > 10 * 512 * 4
 
 
+def test_schedule_validation_and_tile_directory():
+    prot = synth.make_proteome(30, seed=5)
+    h = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, [], 0)
+    grain, nbytes = h.directory()
+    assert grain == 12
+    n_pep, n_post, n_bins = h.shape()
+    assert nbytes == n_bins * ((n_pep >> 12) + 2) * 4
+    assert h.schedule().tile >= 1 << grain
+    for bad in [dict(tile=2048), dict(tile=6144), dict(tile=65536), dict(tiles_per_item=0), dict(groups_per_cu=9)]:
+        with pytest.raises(capi.PsError) as e:
+            h.set_schedule(**bad)
+        assert e.value.code == capi.PS_EINVAL
+    sc = h.schedule()
+    sc.reserved[1] = 7
+    assert capi.ps_index_set_schedule(h.handle, C.byref(sc)) == capi.PS_EINVAL
+    h.set_schedule(tile=8192, tiles_per_item=7, groups_per_cu=3)
+    got = h.schedule()
+    assert (got.tile, got.tiles_per_item, got.groups_per_cu) == (8192, 7, 3)
+
+
+def test_tile_directory_matches_postings():
+    """dir[bin][k] is the first posting of the bin whose id is >= k * 4096."""
+    prot = synth.make_proteome(400, seed=6)
+    h = engine.HostIndex(prot.residues, prot.offsets, 2, 7, 30, engine.mods_from_synth([synth.OXIDATION]), 2)
+    n_pep, _, n_bins = h.shape()
+    assert n_pep > 3 * 4096
+    off, post = h.host_arrays()
+    d = h.directory_array()
+    nblk = (n_pep >> 12) + 1
+    assert d.shape == (n_bins, nblk + 1)
+    rng = np.random.default_rng(1)
+    for bn in list(rng.integers(0, n_bins, 300)) + [int(np.argmax(np.diff(off.astype(np.int64))))]:
+        ids = post[off[bn]:off[bn + 1]] >> 1
+        want = off[bn] + np.searchsorted(ids, np.arange(nblk + 1) * 4096, side="left")
+        assert np.array_equal(d[bn].astype(np.uint64), want.astype(np.uint64)), bn
+
+
 def test_server_and_plan_need_an_uploaded_index():
     ok = synth.Proteome(np.frombuffer(b"PEPTIDEKAAAAR", np.uint8).copy(), np.array([0, 13], np.uint64))
     h = engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [], 0)

@@ -146,12 +146,11 @@ def test_small_open_permutation_and_split_invariance(small_open):
     assert r2.hits.tobytes() == r0.hits.tobytes() and r2.hist.tobytes() == r0.hist.tobytes()
 
 
-@pytest.mark.parametrize("sched", [dict(use_bitmaps=0), dict(tile=1024, coop_min=64),
-                                   dict(tile=32768, coop_min=100000), dict(tile=4096, coop_min=0)])
+@pytest.mark.parametrize("sched", [dict(tile=4096), dict(tile=8192), dict(tile=16384), dict(tile=32768)])
 def test_schedules_give_identical_results(small_open, sched):
-    """Tile size, cooperative threshold and dense-bin bitmaps change only speed."""
+    """The tile size changes only speed."""
     w, prot, sp, ix, db, (oh, ost, og) = small_open
-    assert ix.bitmap_bins()[0] >= 1
+    assert ix.directory()[0] == 12
     old = ix.schedule()
     try:
         ix.set_schedule(**sched)
@@ -165,8 +164,8 @@ def test_schedules_give_identical_results(small_open, sched):
         capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
 
 
-@pytest.mark.parametrize("sched", [dict(tiles_per_item=1), dict(tiles_per_item=3, tile=2048),
-                                   dict(tiles_per_item=64, groups_per_cu=1)])
+@pytest.mark.parametrize("sched", [dict(tiles_per_item=1), dict(tiles_per_item=3, tile=8192),
+                                   dict(tiles_per_item=64, groups_per_cu=1), dict(tiles_per_item=5, groups_per_cu=8)])
 def test_persistent_schedule_parity(small_open, sched):
     """The work-queue scan splits windows into (spectrum, tile range) items;
     merged results equal the oracle for any item size."""
@@ -378,3 +377,49 @@ def test_medium_full_size_sampled_parity(schedule):
     from types import SimpleNamespace
     part = SimpleNamespace(hits=res.hits[idx], stats=res.stats[idx], hist=res.hist[idx])
     assert_parity(part, oh, ost, og)
+
+
+def test_dense_tiles_use_several_map_chunks(small_open):
+    """Spectra whose peaks sit on the densest fragment bins (b1 and y1 of every
+    residue): with 32768-candidate tiles a tile holds more than 8192 postings,
+    so its postings are mapped to probes in several chunks."""
+    from tests import bruteforce as bf
+    w, prot, sp, ix, db, _ = small_open
+    H, W = bf.PROTON_UDA, bf.WATER_UDA
+    letters = "GASPVTCLINDQKEMHFRYW"
+    peaks = [((bf.RES_UDA[c] + H) * 1e-6, 50.0 + i) for i, c in enumerate(letters)]
+    peaks += [((bf.RES_UDA[c] + W + H) * 1e-6, 80.0 + i) for i, c in enumerate(letters)]
+    lists = [peaks, peaks[::2], peaks[1::2] + peaks[:5]]
+    prec = [(1400.0 + 1.007276 * 2) / 2, (1700.0 + 1.007276 * 2) / 2, (1100.0 + 1.007276 * 2) / 2]
+    off = np.zeros(len(lists) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in lists])
+    dense = synth.Spectra(off, np.array([m for p in lists for m, _ in p], np.float32),
+                          np.array([v for p in lists for _, v in p], np.float32), np.array(prec, np.float64),
+                          np.array([2, 2, 2], np.int8))
+    tol = 2
+    oh, ost, og = db.search(dense, w.window_is_ppm, w.window, tol, w.top_peaks, w.top_k, w.min_shared)
+    # postings per 32768-candidate tile of the first spectrum, counted on the host
+    boff, post = ix.host_arrays()
+    ids = post >> 1
+    lo, hi = int(ost["lo"][0]), int(ost["hi"][0])
+    per_tile = np.zeros((hi >> 15) + 1, np.int64)
+    for m, _ in peaks:
+        b = int((int(round(float(np.float32(m)) * 1e6)) + 5000) // 10000)
+        for d in range(-tol, tol + 1):
+            r = ids[boff[b + d]:boff[b + d + 1]]
+            r = r[(r >= lo) & (r < hi)]
+            np.add.at(per_tile, r >> 15, 1)
+    assert per_tile.max() > 8192, per_tile.max()
+    old = ix.schedule()
+    try:
+        for sched in (dict(tile=32768), dict(tile=4096)):
+            for schedule in (capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT):
+                ix.set_schedule(**sched)
+                _say(f"dense tiles {sched} schedule {schedule}")
+                prm = engine.search_params(w.window_is_ppm, w.window, tol, w.top_peaks, w.top_k, w.min_shared,
+                                           max_charge=3, schedule=schedule)
+                res = engine.search(ix, dense, prm)
+                assert_parity(res, oh, ost, og)
+                assert res.postings == int(ost["pairs_total"].sum())
+    finally:
+        capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
