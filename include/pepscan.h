@@ -206,8 +206,9 @@ int ps_index_get_schedule(const ps_index* idx, ps_schedule* schedule);
  * range; the directory turns every tile boundary of that range into one load).
  * grain_shift is 12 unless the directory would exceed 16 GiB; `bytes` is its
  * size.  `dir`, if not NULL, receives a host copy of `bytes` bytes laid out as
- * [n_bins][(n_pep >> grain_shift) + 2] uint32 postings positions.  Any pointer
- * may be NULL. */
+ * [n_bins][stride] uint32 postings positions, stride = (n_pep >> grain_shift)
+ * + 2 rounded up to a multiple of 4 (the padding repeats the bin's end).  Any
+ * pointer may be NULL. */
 int ps_index_directory(const ps_index* idx, uint32_t* grain_shift, uint64_t* bytes, uint32_t* dir);
 
 void ps_index_free(ps_index* idx);

@@ -239,6 +239,9 @@ int index_build_host(ps_index* ix) {
     int64_t max_mass = D ? ix->mass[D - 1] : 0;
     for (uint64_t i = 0; i < D; ++i) max_mass = std::max(max_mass, ix->mass[i]);
     uint64_t nbins = (uint64_t)((max_mass + kBinWidth / 2) / kBinWidth) + 2;
+    // a fragment bin is carried in 24 bits by the search kernels (167 kDa)
+    if (nbins >= (1ull << 24)) return fail(PS_EOVERFLOW, "peptide masses need %llu fragment bins (limit 2^24)",
+                                           (unsigned long long)nbins);
     ix->n_bins = nbins;
     std::vector<std::vector<uint32_t>> cnt(T);
     std::atomic<int> bad_mass{0};
@@ -303,16 +306,19 @@ int index_build_host(ps_index* ix) {
     // grain is 4096 ids unless the directory would pass kDirBudget bytes.
     constexpr uint64_t kDirBudget = 16ull << 30;
     ix->dir_shift = 12;
-    while (ix->dir_shift < 16 && nbins * ((D >> ix->dir_shift) + 2) * 4 > kDirBudget) ++ix->dir_shift;
+    while (ix->dir_shift < 16 && nbins * ((D >> ix->dir_shift) + 6) * 4 > kDirBudget) ++ix->dir_shift;
+    // Rows are padded to a multiple of four entries (16 bytes), so a row can be
+    // read four tile boundaries at a time; padding repeats the bin's end.
     ix->dir_nblk = (D >> ix->dir_shift) + 1;
-    const uint64_t stride = ix->dir_nblk + 1;
+    ix->dir_stride = (ix->dir_nblk + 1 + 3) & ~3ull;
+    const uint64_t stride = ix->dir_stride;
     ix->dir.assign(nbins * stride, 0u);
     parallel_for(nbins, T, [&](unsigned, uint64_t ba, uint64_t bb) {
         for (uint64_t bn = ba; bn < bb; ++bn) {
             uint32_t* d = ix->dir.data() + bn * stride;
             uint64_t i = ix->bin_off[bn];
             const uint64_t e = ix->bin_off[bn + 1];
-            for (uint64_t k = 0; k <= ix->dir_nblk; ++k) {
+            for (uint64_t k = 0; k < stride; ++k) {
                 const uint64_t first_id = k << ix->dir_shift;
                 while (i < e && (uint64_t)(ix->post[i] >> 1) < first_id) ++i;
                 d[k] = (uint32_t)i;
@@ -460,6 +466,7 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     d.dir = (const uint32_t*)(base + lay.dir);
     d.dir_shift = ix->dir_shift;
     d.dir_nblk = (uint32_t)ix->dir_nblk;
+    d.dir_stride = (uint32_t)ix->dir_stride;
     d.n_pep = ix->mass.size();
     d.n_bins = ix->n_bins;
     d.n_post = ix->post.size();

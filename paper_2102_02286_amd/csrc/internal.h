@@ -36,9 +36,10 @@ struct DevIndex {
     const uint32_t* post;      // [n_post], value = id << 1 | is_y, sorted within a bin
     const double* lf;          // [kLfSize]  lf[n] = sum_{k=2..n} log10 k
     const double* ls;          // [kLsSize]  ls[s] = log10 s
-    const uint32_t* dir;       // [n_bins * (dir_nblk + 1)] first posting of a bin at or after each id block
+    const uint32_t* dir;       // [n_bins * dir_stride] first posting of a bin at or after each id block
     uint32_t dir_shift;        // id block = 1 << dir_shift ids (the tile grain)
     uint32_t dir_nblk;
+    uint32_t dir_stride;       // row length, a multiple of 4 (rows are 16-byte aligned)
     uint64_t n_pep, n_bins, n_post;
     uint32_t max_len;          // longest peptide (residues)
     int64_t min_residue;       // lightest residue incl. modification deltas (uDa)

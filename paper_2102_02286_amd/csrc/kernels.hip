@@ -325,10 +325,14 @@ struct ScanArgs {
 
 constexpr uint32_t kRounds = 8;       // gather rounds of 64 postings a wavefront keeps in flight
 constexpr uint32_t kCandCap = 512;    // scored candidates buffered per tile before scoring
+constexpr uint32_t kWaveCand = kCandCap / (kBlock / 64);   // each wavefront's share of the buffer
 constexpr uint32_t kMapCap = 8192;    // flat posting positions mapped to slots at a time
+constexpr uint32_t kLfLds = 256;      // log10(n!) entries kept in LDS
+// s_waitcnt operand (gfx9 encoding): vmcnt(0), expcnt and lgkmcnt left at their maxima
+constexpr int kWaitVmem0 = 0x0F70;
 
 struct ScanShared {
-    uint32_t nact, ncand;
+    uint32_t nact;
     unsigned long long wsum[kBlock / 64];
     unsigned long long red[kBlock / 64];
     double wh[kBlock / 64][PS_MAX_TOP_K];          // per-wavefront top-k lists
@@ -365,8 +369,9 @@ struct ScanLds {
     uint32_t* sstart;
     unsigned long long* mbits;
     uint32_t* mrank;
-    C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter
+    C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter, kWaveCand per wavefront
     int32_t* hist;
+    double* lf;           // [kLfLds] log10(n!) for the narrow counters' n_b, n_y <= 255
     uint16_t* cand_idx;   // [kCandCap] their positions in the tile
     __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap) {
         size_t o = 0;
@@ -381,6 +386,7 @@ struct ScanLds {
         o = (o + 15) & ~(size_t)15;
         cand_cnt = (C*)(base + o); o += (size_t)kCandCap * sizeof(C);
         hist = (int32_t*)(base + o); o += (size_t)kHistBins * 4;
+        lf = (double*)(base + o); o += (size_t)kLfLds * 8;
         cand_idx = (uint16_t*)(base + o);
     }
 };
@@ -393,17 +399,22 @@ size_t scan_lds_bytes(const KParams& kp, bool wide) {
     o = (o + 15) & ~(size_t)15;
     o += (size_t)kCandCap * csz;
     o += (size_t)kHistBins * 4;
+    o += (size_t)kLfLds * 8;
     o += (size_t)kCandCap * 2;
     return (o + 15) & ~(size_t)15;
 }
 
 // Hyperscore of one candidate that passed the filter: log10(n_b! n_y! S) from
-// the fp64 tables, plus its histogram bin (width 0.1, last bin open).
+// the fp64 tables (log10 S passed in, so that its load can be issued early),
+// plus its histogram bin (width 0.1, last bin open).
 template <typename C, bool DUMP>
-__device__ __forceinline__ double score_one(const ScanArgs& A, ScanLds<C>& L, uint32_t s, uint32_t id, C c,
-                                            uint32_t& scored) {
+__device__ __forceinline__ double score_finish(const ScanArgs& A, ScanLds<C>& L, uint32_t s, uint32_t id, C c,
+                                               double ls_sq, uint32_t& scored) {
     const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c), sq = Cnt<C>::s(c);
-    const double h = (A.ix.lf[nb] + A.ix.lf[ny]) + A.ix.ls[sq];
+    double lfb, lfy;
+    if constexpr (sizeof(C) == 4) { lfb = L.lf[nb]; lfy = L.lf[ny]; }   // narrow: n_b, n_y <= 255
+    else { lfb = A.ix.lf[nb]; lfy = A.ix.lf[ny]; }
+    const double h = (lfb + lfy) + ls_sq;
     const double hb = floor(10.0 * h);
     const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
     atomicAdd(&L.hist[bin], 1);
@@ -418,6 +429,12 @@ __device__ __forceinline__ double score_one(const ScanArgs& A, ScanLds<C>& L, ui
         }
     }
     return h;
+}
+
+template <typename C, bool DUMP>
+__device__ __forceinline__ double score_one(const ScanArgs& A, ScanLds<C>& L, uint32_t s, uint32_t id, C c,
+                                            uint32_t& scored) {
+    return score_finish<C, DUMP>(A, L, s, id, c, A.ix.ls[Cnt<C>::s(c)], scored);
 }
 
 // Exclusive prefix sum over the workgroup in thread order; *total gets the sum.
@@ -460,7 +477,7 @@ __device__ __forceinline__ void map_slot(const ScanLds<C>& L, uint32_t k, uint32
 struct Gather {
     uint32_t c0, fe, next;
     uint32_t p[kRounds];
-    uint32_t q[kRounds];   // 0: no posting in this round
+    uint32_t q4[kRounds / 4];   // intensity of round r in byte r % 4 of q4[r / 4]; 0: no posting
 };
 
 // Map flat positions [g.next, g.next + 64 * kRounds) of this wavefront to
@@ -471,6 +488,8 @@ template <typename C>
 __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C>& L, Gather& g) {
     const uint32_t lane = threadIdx.x & 63u;
 #pragma unroll
+    for (uint32_t r = 0; r < kRounds / 4; ++r) g.q4[r] = 0;
+#pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t f = g.next + 64u * r + lane;
         const bool valid = f < g.fe;
@@ -479,7 +498,7 @@ __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C
         const uint32_t k = L.mrank[R] + (uint32_t)__popcll(bits & ((2ull << lane) - 2ull));
         const SegBase sb = L.sbase[valid ? k : 0u];
         g.p[r] = valid ? ix.post[sb.base + f] : 0u;
-        g.q[r] = valid ? sb.q : 0u;
+        g.q4[r / 4] |= (valid ? sb.q : 0u) << (8u * (r % 4u));
     }
     g.next += 64u * kRounds;
 }
@@ -488,9 +507,10 @@ template <typename C>
 __device__ __forceinline__ void gather_consume(const ScanLds<C>& L, const Gather& g, uint32_t tb) {
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
-        if (g.q[r]) {
+        const uint32_t q = (g.q4[r / 4] >> (8u * (r % 4u))) & 0xFFu;
+        if (q) {
             const uint32_t p = g.p[r];
-            atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, g.q[r]));
+            atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
         }
     }
 }
@@ -520,10 +540,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     const int T = kp.tol;
     const uint32_t width = (uint32_t)(2 * T + 1);
     const uint32_t gsh = ix.dir_shift, tsh = kp.tile_shift;
-    const uint64_t stride = (uint64_t)ix.dir_nblk + 1;
+    const uint64_t stride = ix.dir_stride;
+    const uint32_t m = kp.tile >> gsh;                 // directory entries per tile
     const uint32_t t0 = ida >> tsh, t_last = (idb - 1) >> tsh;
 
-    if (tid == 0) { sh.nact = 0; sh.ncand = 0; }
+    if (tid == 0) sh.nact = 0;
     for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) L.hist[i] = 0;
     __syncthreads();
 
@@ -562,15 +583,27 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     const uint32_t nact = sh.nact;
     // slots [tid * us, tid * us + us) belong to this thread
     const uint32_t us = nact > kBlock ? (nact + kBlock - 1) / kBlock : 1u;
-    uint32_t o_bin[U], o_s1[U], o_q[U], o_cur[U], o_end[U], o_nxt[U];
+    // Each slot also holds the aligned quad of its directory row that contains
+    // the entry for the end of tile t + 2 (needed when moving to tile t + 1):
+    // a quad serves four tiles (one tile = m entries), and the next quad is
+    // loaded one tile before its first use.
+    auto needs_dir = [&](uint32_t u) { return ((uint64_t)(u + 1) << tsh) < (uint64_t)idb; };   // end(u) < s1?
+    auto quad_at = [&](uint32_t bin, uint32_t idx) {
+        return *(const uint4*)(ix.dir + (uint64_t)bin * stride + (idx & ~3u));
+    };
+    uint32_t o_bq[U], o_s1[U], o_cur[U], o_end[U], o_nxt[U];   // o_bq = bin | q << 24
+    uint4 o_quad[U];
+    const bool quad0 = t0 + 2 <= t_last && needs_dir(t0 + 2);
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
         const uint32_t j = tid * us + u;
-        o_bin[u] = 0; o_s1[u] = 0; o_q[u] = 0; o_cur[u] = 0; o_end[u] = 0; o_nxt[u] = 0;
+        o_bq[u] = 0; o_s1[u] = 0; o_cur[u] = 0; o_end[u] = 0; o_nxt[u] = 0;
+        o_quad[u] = make_uint4(0u, 0u, 0u, 0u);
         if (u < us && j < nact) {
             const SlotInit si = L.init[j];
-            o_bin[u] = si.bin; o_s1[u] = si.s1; o_q[u] = si.q;
+            o_bq[u] = si.bin | (si.q << 24); o_s1[u] = si.s1;
             o_cur[u] = si.s0; o_end[u] = si.e0; o_nxt[u] = si.e1;
+            if (quad0) o_quad[u] = quad_at(si.bin, (t0 + 3) * m);
         }
     }
     __syncthreads();                                   // SlotInit area becomes the counters
@@ -616,7 +649,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             if (n) {
                 SegBase sb;
                 sb.base = o_cur[u] - run;
-                sb.q = o_q[u];
+                sb.q = o_bq[u] >> 24;
                 L.sbase[rank] = sb;
                 L.sstart[rank] = run;
                 map_slot<C>(L, rank, run, run + n, 0u);
@@ -635,6 +668,34 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         for (uint32_t i = tid; i < kp.tile; i += kBlock) L.cnt[i] = (C)0;
         prepare();
     }
+    // Every register loaded in one tile is first used right after the next
+    // tile's posting batch is consumed, where the wavefront waits for its loads
+    // anyway: the deferred scoring of the previous tile's candidates, and the
+    // boundary taken from a directory quad.
+    // Each wavefront buffers its own candidates (kWaveCand slots from wbuf) and
+    // scores them itself, so the filter needs no shared counter or barrier.
+    const uint32_t wbuf = wave * kWaveCand;
+    bool pf_ok = false;                                 // a buffered candidate of the previous tile
+    C pf_c = 0;
+    uint32_t pf_id = 0;
+    double pf_ls = 0.0;
+    uint32_t pf_n = 0, pf_tb = 0;                       // this wavefront's candidates of the previous tile, its base
+    auto score_buffered = [&]() {
+        if (pf_n) {
+            const double h = pf_ok ? score_finish<C, DUMP>(A, L, s, pf_id, pf_c, pf_ls, scored) : -INFINITY;
+            top.insert_lanes(pf_ok, h, pf_id, pf_c, kk);
+        }
+        for (uint32_t base = 64u; base < pf_n; base += 64u) {   // beyond the prefetched ones
+            const uint32_t j = base + lane;
+            const bool ok = j < pf_n;
+            const C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
+            const uint32_t id = ok ? pf_tb + L.cand_idx[wbuf + j] : 0u;
+            const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
+            top.insert_lanes(ok, h, id, c, kk);
+        }
+        pf_n = 0;
+        pf_ok = false;
+    };
     const uint32_t t_end = nact > 0 ? t_last + 1 : t0;
     for (uint32_t t = t0; t < t_end; ++t) {
         const uint32_t tb = t << tsh;
@@ -659,73 +720,89 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                 gather_consume<C>(L, g, tb);
             }
         }
+        score_buffered();                               // the previous tile's candidates
+        // end of tile t + 2 from the quad holding directory entry (t + 3) m
+        const bool use = t + 2 <= t_last && needs_dir(t + 2);
+        const uint32_t idx = (t + 3) * m;
+        uint32_t nxt2[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint4 qd = o_quad[u];
+            const uint32_t e = (idx & 3u) == 0u ? qd.x : (idx & 3u) == 1u ? qd.y : (idx & 3u) == 2u ? qd.z : qd.w;
+            nxt2[u] = use ? min(o_s1[u], e) : o_s1[u];
+        }
+        // Everything loaded so far has arrived (the batch above needed it).  Say
+        // so explicitly: the compiler's load scoreboard then starts clean, so
+        // registers reused below never wait for the loads issued next.
+        __builtin_amdgcn_s_waitcnt(kWaitVmem0);
         __syncthreads();
+        // candidate filter: counters are read and cleared four (narrow) or two
+        // (wide) at a time; candidates with at least k_min shared peaks are
+        // buffered for scoring
+        if (p_t != 0) {                                 // else the counters are all 0
+            constexpr uint32_t kPer = 16 / sizeof(C);
+            const uint32_t nvec = kp.tile / kPer;
+            uint4* cv = (uint4*)L.cnt;
+            uint32_t wn = 0;                            // wave-uniform: candidates buffered so far
+            for (uint32_t base = wave * 64u; base < nvec; base += kBlock) {   // nvec is a multiple of kBlock
+                const uint32_t i = base + lane;
+                const uint4 v = cv[i];
+                cv[i] = make_uint4(0u, 0u, 0u, 0u);
+                C c[kPer];
+                if constexpr (kPer == 4) {
+                    c[0] = (C)v.x; c[1] = (C)v.y; c[2] = (C)v.z; c[3] = (C)v.w;
+                } else {
+                    c[0] = (C)(((unsigned long long)v.y << 32) | v.x);
+                    c[1] = (C)(((unsigned long long)v.w << 32) | v.z);
+                }
+#pragma unroll
+                for (uint32_t e = 0; e < kPer; ++e) {
+                    const bool pass = Cnt<C>::nb(c[e]) + Cnt<C>::ny(c[e]) >= kmin;
+                    const unsigned long long msk = __ballot(pass);
+                    if (msk == 0) continue;             // wave-uniform
+                    const uint32_t pos = i * kPer + e;
+                    const uint32_t off = wn + __builtin_amdgcn_mbcnt_hi((uint32_t)(msk >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0u));
+                    const bool fits = off < kWaveCand;
+                    if (pass && fits) {
+                        L.cand_idx[wbuf + off] = (uint16_t)pos;
+                        L.cand_cnt[wbuf + off] = c[e];
+                    }
+                    const bool ovf = pass && !fits;     // buffer full: score in place
+                    if (__ballot(ovf)) {
+                        const double h = ovf ? score_one<C, DUMP>(A, L, s, tb + pos, c[e], scored) : -INFINITY;
+                        top.insert_lanes(ovf, h, tb + pos, c[e], kk);
+                    }
+                    wn = min(wn + (uint32_t)__popcll(msk), kWaveCand);
+                }
+            }
+            pf_n = wn;
+            pf_tb = tb;
+            pf_ok = lane < pf_n;
+        }
         if (t < t_last) {
-            // slots move to tile t + 1; the end of their tile t + 2 is loaded now
-            // and first needed one tile later
+            // slots move to tile t + 1, and the quad for the next tile's boundary
+            // is requested when it differs from the one just used
+            const bool fetch = t + 3 <= t_last && needs_dir(t + 3) && (((t + 4) * m) >> 2) != (idx >> 2);
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 o_cur[u] = o_end[u];
                 o_end[u] = o_nxt[u];
+                o_nxt[u] = nxt2[u];
                 const uint32_t j = tid * us + u;
-                if (u < us && j < nact && t + 2 <= t_last)
-                    o_nxt[u] = tile_end(ix.dir + (uint64_t)o_bin[u] * stride, t + 2, o_s1[u]);
-                else
-                    o_nxt[u] = o_end[u];
+                if (fetch && u < us && j < nact) o_quad[u] = quad_at(o_bq[u] & 0xFFFFFFu, (t + 4) * m);
             }
             prepare();
         }
-        if (p_t == 0) continue;                         // no posting in this tile: counters are all 0
-        // candidate filter: counters are read and cleared four (narrow) or two
-        // (wide) at a time; candidates with at least k_min shared peaks are
-        // buffered for scoring
-        constexpr uint32_t kPer = 16 / sizeof(C);
-        const uint32_t nvec = kp.tile / kPer;
-        uint4* cv = (uint4*)L.cnt;
-        for (uint32_t base = wave * 64u; base < nvec; base += kBlock) {   // nvec is a multiple of kBlock
-            const uint32_t i = base + lane;
-            const uint4 v = cv[i];
-            cv[i] = make_uint4(0u, 0u, 0u, 0u);
-            C c[kPer];
-            if constexpr (kPer == 4) {
-                c[0] = (C)v.x; c[1] = (C)v.y; c[2] = (C)v.z; c[3] = (C)v.w;
-            } else {
-                c[0] = (C)(((unsigned long long)v.y << 32) | v.x);
-                c[1] = (C)(((unsigned long long)v.w << 32) | v.z);
-            }
-#pragma unroll
-            for (uint32_t e = 0; e < kPer; ++e) {
-                const uint32_t pos = i * kPer + e;
-                bool ovf = false;
-                if (Cnt<C>::nb(c[e]) + Cnt<C>::ny(c[e]) >= kmin) {
-                    const uint32_t slot = atomicAdd(&sh.ncand, 1u);
-                    if (slot < kCandCap) {
-                        L.cand_idx[slot] = (uint16_t)pos;
-                        L.cand_cnt[slot] = c[e];
-                    } else {
-                        ovf = true;                     // buffer full: score in place
-                    }
-                }
-                if (__ballot(ovf)) {
-                    const double h = ovf ? score_one<C, DUMP>(A, L, s, tb + pos, c[e], scored) : -INFINITY;
-                    top.insert_lanes(ovf, h, tb + pos, c[e], kk);
-                }
-            }
+        // the first kBlock buffered candidates request log10 S last, and are
+        // scored after the next tile's batch is consumed
+        if (pf_ok) {
+            pf_c = L.cand_cnt[wbuf + lane];
+            pf_id = pf_tb + L.cand_idx[wbuf + lane];
+            pf_ls = ix.ls[Cnt<C>::s(pf_c)];
         }
-        __syncthreads();
-        // hyperscore, histogram, top-k over the buffered candidates
-        const uint32_t ncand = min(sh.ncand, kCandCap);
-        for (uint32_t base = wave * 64u; base < ncand; base += kBlock) {
-            const uint32_t j = base + lane;
-            const bool ok = j < ncand;
-            const C c = ok ? L.cand_cnt[j] : (C)0;
-            const uint32_t id = ok ? tb + L.cand_idx[j] : 0u;
-            const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
-            top.insert_lanes(ok, h, id, c, kk);
-        }
-        __syncthreads();
-        if (tid == 0) sh.ncand = 0;
     }
+    score_buffered();                                   // the last tile's candidates
 
     // top-k of the item: the wavefronts' lists, merged by one thread
     if (lane < kk) {
@@ -790,13 +867,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
         }
         return;
     }
+    for (uint32_t i = threadIdx.x; i < kLfLds; i += kBlock) L.lf[i] = A.ix.lf[i];   // read after a barrier
     scan_item<C, DUMP, U>(A, sh, L, s, inf.lo, inf.hi, out);
 }
 
 // Register slots per thread for a workgroup that may hold seg_cap probe slots.
 static uint32_t slots_per_thread(uint32_t seg_cap) {
     const uint32_t u = (seg_cap + kBlock - 1) / kBlock;
-    return u <= 2 ? 2u : (u <= 4 ? 4u : 8u);
+    return u <= 2 ? 2u : u == 3 ? 3u : u == 4 ? 4u : 8u;
 }
 
 template <typename C, bool DUMP, uint32_t U>
@@ -811,6 +889,7 @@ template <typename C, bool DUMP>
 static hipError_t launch_scan_plain_t(ScanArgs a, uint64_t n, hipStream_t stream) {
     switch (slots_per_thread(a.kp.seg_cap)) {
         case 2: return launch_scan_plain_u<C, DUMP, 2>(a, n, stream);
+        case 3: return launch_scan_plain_u<C, DUMP, 3>(a, n, stream);
         case 4: return launch_scan_plain_u<C, DUMP, 4>(a, n, stream);
         default: return launch_scan_plain_u<C, DUMP, 8>(a, n, stream);
     }
@@ -908,6 +987,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
     const uint32_t n = (uint32_t)A.sp.hdr->n;
     const uint32_t total = A.w.spec_item0[n];
     const uint32_t tpi = A.tiles_per_item;
+    for (uint32_t i = threadIdx.x; i < kLfLds; i += kBlock) L.lf[i] = A.ix.lf[i];   // read after a barrier
     while (true) {
         if (threadIdx.x == 0) s_item = (uint32_t)atomicAdd(&A.w.counters[kCtrQueue], 1ull);
         __syncthreads();
@@ -945,6 +1025,7 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
     ScanArgs a{ix, sp, kp, w, tiles_per_item, 0u, 1u};
     const uint32_t u = slots_per_thread(kp.seg_cap);
     hipError_t e = u == 2 ? launch_persistent_t<uint32_t, 2>(a, grid, stream)
+                 : u == 3 ? launch_persistent_t<uint32_t, 3>(a, grid, stream)
                  : u == 4 ? launch_persistent_t<uint32_t, 4>(a, grid, stream)
                           : launch_persistent_t<uint32_t, 8>(a, grid, stream);
     if (e != hipSuccess) return e;
@@ -1111,7 +1192,7 @@ hipError_t init_kernel_attributes() {
         (const void*)k_scan_plain<uint32_t, false, U>, (const void*)k_scan_plain<uint32_t, true, U>,  \
         (const void*)k_scan_plain<unsigned long long, false, U>,                                       \
         (const void*)k_scan_plain<unsigned long long, true, U>, (const void*)k_scan_persistent<uint32_t, U>
-    const void* fns[] = {PS_PLAIN_FNS(2), PS_PLAIN_FNS(4), PS_PLAIN_FNS(8)};
+    const void* fns[] = {PS_PLAIN_FNS(2), PS_PLAIN_FNS(3), PS_PLAIN_FNS(4), PS_PLAIN_FNS(8)};
 #undef PS_PLAIN_FNS
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);

@@ -46,9 +46,10 @@ struct ps_index {
     std::vector<uint32_t> post;
     uint32_t max_len_seen = 0;
     int64_t min_residue = 0;
-    // tile directory: dir[bin * (dir_nblk + 1) + k] = first posting of `bin` with id >= k << dir_shift
+    // tile directory: dir[bin * dir_stride + k] = first posting of `bin` with id >= k << dir_shift
     uint32_t dir_shift = 12;
-    uint64_t dir_nblk = 0;
+    uint64_t dir_nblk = 0;       // blocks: entries 0..dir_nblk are meaningful
+    uint64_t dir_stride = 0;     // row length, dir_nblk + 1 rounded up to a multiple of 4
     std::vector<uint32_t> dir;
     ps_schedule sched{};
     // device copy

@@ -115,12 +115,13 @@ class HostIndex:
         return g.value, b.value
 
     def directory_array(self) -> np.ndarray:
-        """Host copy of the tile directory, [n_bins, (n_pep >> grain) + 2]."""
+        """Host copy of the tile directory, [n_bins, stride] with stride =
+        (n_pep >> grain) + 2 rounded up to a multiple of 4."""
         g, nbytes = self.directory()
         n_pep, _, n_bins = self.shape()
         d = np.zeros(nbytes // 4, np.uint32)
         check(capi.ps_index_directory(self.handle, None, None, ptr(d)))
-        return d.reshape(n_bins, (n_pep >> g) + 2)
+        return d.reshape(n_bins, ((n_pep >> g) + 2 + 3) // 4 * 4)
 
     def device_bytes(self) -> int:
         b = C.c_uint64()

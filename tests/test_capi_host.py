@@ -138,7 +138,7 @@ def test_schedule_validation_and_tile_directory():
     grain, nbytes = h.directory()
     assert grain == 12
     n_pep, n_post, n_bins = h.shape()
-    assert nbytes == n_bins * ((n_pep >> 12) + 2) * 4
+    assert nbytes == n_bins * (((n_pep >> 12) + 2 + 3) // 4 * 4) * 4
     assert h.schedule().tile >= 1 << grain
     for bad in [dict(tile=2048), dict(tile=6144), dict(tile=65536), dict(tiles_per_item=0), dict(groups_per_cu=9)]:
         with pytest.raises(capi.PsError) as e:
@@ -153,7 +153,8 @@ def test_schedule_validation_and_tile_directory():
 
 
 def test_tile_directory_matches_postings():
-    """dir[bin][k] is the first posting of the bin whose id is >= k * 4096."""
+    """dir[bin][k] is the first posting of the bin whose id is >= k * 4096
+    (rows padded to a multiple of four entries, the padding repeating the end)."""
     prot = synth.make_proteome(400, seed=6)
     h = engine.HostIndex(prot.residues, prot.offsets, 2, 7, 30, engine.mods_from_synth([synth.OXIDATION]), 2)
     n_pep, _, n_bins = h.shape()
@@ -161,11 +162,12 @@ def test_tile_directory_matches_postings():
     off, post = h.host_arrays()
     d = h.directory_array()
     nblk = (n_pep >> 12) + 1
-    assert d.shape == (n_bins, nblk + 1)
+    stride = (nblk + 1 + 3) // 4 * 4
+    assert d.shape == (n_bins, stride)
     rng = np.random.default_rng(1)
     for bn in list(rng.integers(0, n_bins, 300)) + [int(np.argmax(np.diff(off.astype(np.int64))))]:
         ids = post[off[bn]:off[bn + 1]] >> 1
-        want = off[bn] + np.searchsorted(ids, np.arange(nblk + 1) * 4096, side="left")
+        want = off[bn] + np.searchsorted(ids, np.arange(stride) * 4096, side="left")
         assert np.array_equal(d[bn].astype(np.uint64), want.astype(np.uint64)), bn
 
 
