@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None, help="file caching autotuned schedules")
+    ap.add_argument("--classic-index", action="store_true",
+                    help="one posting list per fragment bin (default: lists merge the 2T+1 neighbouring bins)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--only", choices=["plain", "persistent"], default=None,
                     help="time one form only (for profiling runs)")
@@ -178,10 +180,12 @@ def main():
     sp = w.spectra(prot, n=args.n_spectra)
     log(f"workload {w.name}: {prot.n} proteins, {sp.n} spectra generated in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
+    merge = 0 if args.classic_index else w.frag_tol_bins
     ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
-                          engine.mods_from_synth(w.mods), w.max_mods)
+                          engine.mods_from_synth(w.mods), w.max_mods, merge_tol=merge)
     n_pep, n_post, n_bins = ix.shape()
-    log(f"index: {n_pep} peptides, {n_post} postings, {n_bins} bins, host build {time.perf_counter() - t0:.1f}s")
+    log(f"index: {n_pep} peptides, {n_post} postings (lists of {2 * merge + 1} bin(s) each), {n_bins} bins, "
+        f"directory {ix.directory()[1] / 1e9:.2f} GB, host build {time.perf_counter() - t0:.1f}s")
     ix.upload("cuda:0")
     torch.cuda.synchronize()
     max_charge = int(sp.charge.max()) if sp.n else 1
@@ -286,7 +290,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {prot.n} proteins, {n_pep} peptides, {n_post} postings, {sp.n} spectra, "
+        "config": {"workload": f"{w.name}: {prot.n} proteins, {n_pep} peptides, {n_post} postings "
+                               f"(lists merging {2 * merge + 1} neighbouring bin(s)), {sp.n} spectra, "
                                f"window +-{w.window / 1e6:g} Da, fragment tol {w.frag_tol_bins} bin(s), "
                                f"top {w.top_k}, persistent work-queue scan replayed as a hipGraph"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

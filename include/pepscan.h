@@ -60,7 +60,8 @@ extern "C" {
 #define PS_MAX_CHARGE 8
 #define PS_MAX_FRAG_TOL_BINS 4
 #define PS_MAX_PEAKS_IN 4096     /* input peaks per spectrum before top-B selection */
-#define PS_MAX_SEGMENTS 2048     /* top_peaks * max(1, z-1) * (2T+1) per spectrum */
+#define PS_MAX_SEGMENTS 2048     /* top_peaks * max(1, z-1) * probes per peak (2T+1, or 1 on an
+                                    index with merged lists) per spectrum */
 
 #define PS_SCHED_PLAIN      0    /* one workgroup per spectrum, separate launches */
 #define PS_SCHED_PERSISTENT 1    /* one persistent work-queue launch (hipGraph) */
@@ -93,7 +94,11 @@ typedef struct {
     uint32_t      min_len, max_len;   /* 2 <= min_len <= max_len <= 62 */
     uint32_t      n_mods;             /* <= 16 */
     uint32_t      max_mods;           /* modified sites per peptide */
-    uint32_t      pad;
+    uint32_t      merge_tol_bins;     /* 0: one posting list per fragment bin.  T in 1..PS_MAX_FRAG_TOL_BINS:
+                                         the list of bin b holds the postings of bins b-T..b+T, so a
+                                         search probes one list per peak instead of 2T+1 (same pairs,
+                                         Supplementary Text 4); searches on such an index must use
+                                         frag_tol_bins == T (else PS_EINVAL).  Postings grow (2T+1)-fold. */
     const ps_mod* mods;
 } ps_db_params;
 

@@ -40,7 +40,7 @@ class ps_mod(C.Structure):
 
 class ps_db_params(C.Structure):
     _fields_ = [("missed_cleavages", C.c_uint32), ("min_len", C.c_uint32), ("max_len", C.c_uint32),
-                ("n_mods", C.c_uint32), ("max_mods", C.c_uint32), ("pad", C.c_uint32),
+                ("n_mods", C.c_uint32), ("max_mods", C.c_uint32), ("merge_tol_bins", C.c_uint32),
                 ("mods", C.POINTER(ps_mod))]
 
 

@@ -74,9 +74,14 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
         return fail(PS_EINVAL, "unknown schedule %d", p->schedule);
     const uint32_t cmax = p->max_charge > 2 ? p->max_charge - 1 : 1;
     const uint64_t stride = (uint64_t)p->top_peaks * cmax;
-    const uint64_t segs = stride * (uint64_t)(2 * p->frag_tol_bins + 1);
+    if (ix && ix->merge_tol && (uint32_t)p->frag_tol_bins != ix->merge_tol)
+        return fail(PS_EINVAL, "this index merges the lists of %u neighbouring bins; search with frag_tol_bins = %u",
+                    ix->merge_tol, ix->merge_tol);
+    // probes per entry: 2T+1 bins, or the one merged list
+    const uint64_t width = (ix && ix->merge_tol) ? 1 : (uint64_t)(2 * p->frag_tol_bins + 1);
+    const uint64_t segs = stride * width;
     if (segs > PS_MAX_SEGMENTS)
-        return fail(PS_EINVAL, "top_peaks * max(1, max_charge-1) * (2*frag_tol_bins+1) = %llu exceeds %d",
+        return fail(PS_EINVAL, "top_peaks * max(1, max_charge-1) * probes per peak = %llu exceeds %d",
                     (unsigned long long)segs, PS_MAX_SEGMENTS);
     kp->window = p->window;
     kp->window_is_ppm = p->window_is_ppm ? 1 : 0;

@@ -300,7 +300,44 @@ int index_build_host(ps_index* ix) {
     // Postings of one id in one bin must be ordered b before y; ions of one id are
     // emitted b-first, so each bin is non-decreasing in (id << 1 | type).
 
-    // 4. tile directory: for every bin and every block of 2^dir_shift ids, the
+    // 4. with a merge width T, the list of bin b becomes the id-ordered merge of
+    // the lists of bins b-T..b+T: a peak then probes one list and still meets
+    // every ion within T bins once
+    if (ix->merge_tol > 0) {
+        const int64_t mt = ix->merge_tol;
+        std::vector<uint64_t> off2(nbins + 1, 0);
+        for (uint64_t bn = 0; bn < nbins; ++bn) {
+            const uint64_t a = (uint64_t)std::max<int64_t>(0, (int64_t)bn - mt);
+            const uint64_t b = std::min<uint64_t>(nbins, bn + mt + 1);
+            off2[bn + 1] = off2[bn] + (ix->bin_off[b] - ix->bin_off[a]);
+        }
+        if (off2[nbins] >= (1ull << 32))
+            return fail(PS_EOVERFLOW, "merged lists hold %llu postings; this build addresses at most 2^32",
+                        (unsigned long long)off2[nbins]);
+        std::vector<uint32_t> post2(off2[nbins]);
+        parallel_for(nbins, T, [&](unsigned, uint64_t ba, uint64_t bb) {
+            std::vector<uint32_t> tmp;
+            for (uint64_t bn = ba; bn < bb; ++bn) {
+                const uint64_t a = (uint64_t)std::max<int64_t>(0, (int64_t)bn - mt);
+                const uint64_t b = std::min<uint64_t>(nbins, bn + mt + 1);
+                uint32_t* dst = post2.data() + off2[bn];
+                // each source list is sorted; merge them pairwise in order
+                uint64_t filled = 0;
+                for (uint64_t src = a; src < b; ++src) {
+                    const uint32_t* p0 = ix->post.data() + ix->bin_off[src];
+                    const uint64_t n0 = ix->bin_off[src + 1] - ix->bin_off[src];
+                    tmp.resize(filled + n0);
+                    std::merge(dst, dst + filled, p0, p0 + n0, tmp.begin());
+                    std::copy(tmp.begin(), tmp.end(), dst);
+                    filled += n0;
+                }
+            }
+        });
+        ix->bin_off.swap(off2);
+        ix->post.swap(post2);
+    }
+
+    // 5. tile directory: for every bin and every block of 2^dir_shift ids, the
     // first posting at or after the block start.  A scan tile is a whole number
     // of blocks, so every posting run's tile boundaries are direct lookups.  The
     // grain is 4096 ids unless the directory would pass kDirBudget bytes.
@@ -382,6 +419,9 @@ extern "C" int ps_index_create(const ps_db_params* params, const char* residues,
                         (unsigned long long)i, residues[i]);
     ps_index* ix = new (std::nothrow) ps_index();
     if (!ix) return fail(PS_ENOMEM, "out of host memory");
+    if (params->merge_tol_bins > PS_MAX_FRAG_TOL_BINS)
+        return fail(PS_EINVAL, "merge_tol_bins must be 0..%d", PS_MAX_FRAG_TOL_BINS);
+    ix->merge_tol = params->merge_tol_bins;
     ix->missed = params->missed_cleavages;
     ix->min_len = params->min_len;
     ix->max_len = params->max_len;
@@ -467,6 +507,7 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     d.dir_shift = ix->dir_shift;
     d.dir_nblk = (uint32_t)ix->dir_nblk;
     d.dir_stride = (uint32_t)ix->dir_stride;
+    d.merge_tol = ix->merge_tol;
     d.n_pep = ix->mass.size();
     d.n_bins = ix->n_bins;
     d.n_post = ix->post.size();

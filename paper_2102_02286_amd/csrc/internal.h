@@ -40,6 +40,7 @@ struct DevIndex {
     uint32_t dir_shift;        // id block = 1 << dir_shift ids (the tile grain)
     uint32_t dir_nblk;
     uint32_t dir_stride;       // row length, a multiple of 4 (rows are 16-byte aligned)
+    uint32_t merge_tol;        // T > 0: the list of bin b holds bins b-T..b+T (one probe per peak)
     uint64_t n_pep, n_bins, n_post;
     uint32_t max_len;          // longest peptide (residues)
     int64_t min_residue;       // lightest residue incl. modification deltas (uDa)

@@ -537,7 +537,8 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     const DevIndex& ix = A.ix;
     const uint32_t n_ent = A.w.info[s].n_ent;
     const uint32_t* ent = A.w.entries + (uint64_t)s * kp.ent_stride;
-    const int T = kp.tol;
+    // probes per entry: the 2T+1 bins around it, or its one merged list
+    const int T = ix.merge_tol ? 0 : kp.tol;
     const uint32_t width = (uint32_t)(2 * T + 1);
     const uint32_t gsh = ix.dir_shift, tsh = kp.tile_shift;
     const uint64_t stride = ix.dir_stride;
@@ -874,7 +875,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
 // Register slots per thread for a workgroup that may hold seg_cap probe slots.
 static uint32_t slots_per_thread(uint32_t seg_cap) {
     const uint32_t u = (seg_cap + kBlock - 1) / kBlock;
-    return u <= 2 ? 2u : u == 3 ? 3u : u == 4 ? 4u : 8u;
+    return u <= 1 ? 1u : u == 2 ? 2u : u == 3 ? 3u : u == 4 ? 4u : 8u;
 }
 
 template <typename C, bool DUMP, uint32_t U>
@@ -888,6 +889,7 @@ static hipError_t launch_scan_plain_u(ScanArgs a, uint64_t n, hipStream_t stream
 template <typename C, bool DUMP>
 static hipError_t launch_scan_plain_t(ScanArgs a, uint64_t n, hipStream_t stream) {
     switch (slots_per_thread(a.kp.seg_cap)) {
+        case 1: return launch_scan_plain_u<C, DUMP, 1>(a, n, stream);
         case 2: return launch_scan_plain_u<C, DUMP, 2>(a, n, stream);
         case 3: return launch_scan_plain_u<C, DUMP, 3>(a, n, stream);
         case 4: return launch_scan_plain_u<C, DUMP, 4>(a, n, stream);
@@ -1024,7 +1026,8 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
     if (sp.n == 0) return hipSuccess;
     ScanArgs a{ix, sp, kp, w, tiles_per_item, 0u, 1u};
     const uint32_t u = slots_per_thread(kp.seg_cap);
-    hipError_t e = u == 2 ? launch_persistent_t<uint32_t, 2>(a, grid, stream)
+    hipError_t e = u == 1 ? launch_persistent_t<uint32_t, 1>(a, grid, stream)
+                 : u == 2 ? launch_persistent_t<uint32_t, 2>(a, grid, stream)
                  : u == 3 ? launch_persistent_t<uint32_t, 3>(a, grid, stream)
                  : u == 4 ? launch_persistent_t<uint32_t, 4>(a, grid, stream)
                           : launch_persistent_t<uint32_t, 8>(a, grid, stream);
@@ -1192,7 +1195,7 @@ hipError_t init_kernel_attributes() {
         (const void*)k_scan_plain<uint32_t, false, U>, (const void*)k_scan_plain<uint32_t, true, U>,  \
         (const void*)k_scan_plain<unsigned long long, false, U>,                                       \
         (const void*)k_scan_plain<unsigned long long, true, U>, (const void*)k_scan_persistent<uint32_t, U>
-    const void* fns[] = {PS_PLAIN_FNS(2), PS_PLAIN_FNS(3), PS_PLAIN_FNS(4), PS_PLAIN_FNS(8)};
+    const void* fns[] = {PS_PLAIN_FNS(1), PS_PLAIN_FNS(2), PS_PLAIN_FNS(3), PS_PLAIN_FNS(4), PS_PLAIN_FNS(8)};
 #undef PS_PLAIN_FNS
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);

@@ -32,6 +32,7 @@ struct ps_index {
         std::string residues;
     };
     uint32_t missed = 0, min_len = 0, max_len = 0, max_mods = 0;
+    uint32_t merge_tol = 0;      // lists of bin b hold the postings of bins b-T..b+T
     std::vector<Mod> mods;
     std::vector<char> seq;
     std::vector<uint64_t> prot_off;

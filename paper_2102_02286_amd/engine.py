@@ -31,7 +31,7 @@ def mods_from_synth(mods) -> list[Mod]:
     return [Mod(m.residues, int(round(m.delta_da * 1e6)), m.nterm) for m in mods]
 
 
-def _db_params(missed, min_len, max_len, mods, max_mods):
+def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0):
     arr = (capi.ps_mod * max(1, len(mods)))()
     keep = []
     for i, m in enumerate(mods):
@@ -40,7 +40,7 @@ def _db_params(missed, min_len, max_len, mods, max_mods):
         arr[i].residues = b
         arr[i].nterm = 1 if m.nterm else 0
         arr[i].delta_udalton = int(m.delta_uda)
-    p = capi.ps_db_params(missed, min_len, max_len, len(mods), max_mods, 0, arr)
+    p = capi.ps_db_params(missed, min_len, max_len, len(mods), max_mods, merge_tol, arr)
     return p, (arr, keep)
 
 
@@ -55,10 +55,13 @@ class HostIndex:
     """The index built on the host (no GPU needed)."""
 
     def __init__(self, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int, max_len: int,
-                 mods: list, max_mods: int):
+                 mods: list, max_mods: int, merge_tol: int = 0):
+        """merge_tol = T >= 1 stores, for each bin, the postings of bins b-T..b+T
+        (searches must then use frag_tol_bins == T)."""
         self._res = np.ascontiguousarray(residues, dtype=np.uint8)
         self._off = np.ascontiguousarray(offsets, dtype=np.uint64)
-        p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods)
+        self.merge_tol = int(merge_tol)
+        p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods, self.merge_tol)
         h = C.c_void_p()
         check(capi.ps_index_create(C.byref(p), ptr(self._res), ptr(self._off), self._off.shape[0] - 1,
                                    C.byref(h)), "ps_index_create")

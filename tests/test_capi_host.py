@@ -183,3 +183,34 @@ def test_server_and_plan_need_an_uploaded_index():
     assert rc in (capi.PS_EDEVICE, capi.PS_EINVAL, capi.PS_ENOMEM) and not out.value
     plain = engine.search_params(False, 1000, 1, 50, max_charge=3)
     assert capi.ps_server_create(h.handle, C.byref(dev), C.byref(plain), 10, 100, 2, 0, C.byref(out)) == capi.PS_EINVAL
+
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_merged_lists_are_neighbour_unions(T):
+    """With merge width T the list of bin b is the id-ordered union of the
+    classic lists of bins b-T..b+T; searches must use that tolerance."""
+    prot = synth.make_proteome(40, seed=7)
+    mods = engine.mods_from_synth([synth.OXIDATION])
+    classic = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, mods, 2)
+    merged = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, mods, 2, merge_tol=T)
+    oc, pc = classic.host_arrays()
+    om, pm = merged.host_arrays()
+    nb = oc.shape[0] - 1
+    assert om.shape == oc.shape and pm.shape[0] <= (2 * T + 1) * pc.shape[0]
+    for bn in range(nb):
+        parts = [pc[oc[b]:oc[b + 1]] for b in range(max(0, bn - T), min(nb, bn + T + 1))]
+        want = np.sort(np.concatenate(parts)) if parts else np.zeros(0, np.uint32)
+        assert np.array_equal(pm[om[bn]:om[bn + 1]], want), bn
+    # the tile directory indexes the merged lists
+    d = merged.directory_array()
+    for bn in range(0, nb, 97):
+        ids = pm[om[bn]:om[bn + 1]] >> 1
+        assert np.array_equal(d[bn], om[bn] + np.searchsorted(ids, np.arange(d.shape[1]) * 4096).astype(np.uint64))
+    need = C.c_uint64()
+    wrong = engine.search_params(False, 1000, T + 1, 100, max_charge=3)
+    assert capi.ps_workspace_bytes(merged.handle, 10, 100, C.byref(wrong), C.byref(need)) == capi.PS_EINVAL
+    assert "frag_tol_bins" in capi.last_error()
+    right = engine.search_params(False, 1000, T, 100, max_charge=3)
+    assert capi.ps_workspace_bytes(merged.handle, 10, 100, C.byref(right), C.byref(need)) == capi.PS_OK
+    with pytest.raises(capi.PsError):
+        engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, mods, 2, merge_tol=5)

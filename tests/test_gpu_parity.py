@@ -423,3 +423,51 @@ def test_dense_tiles_use_several_map_chunks(small_open):
                 assert res.postings == int(ost["pairs_total"].sum())
     finally:
         capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(old)))
+
+
+# ---------------------------------------------------------------------------
+# indexes whose lists merge the 2T+1 neighbouring bins: one probe per peak
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
+def test_tiny_merged_lists_parity(tiny, schedule):
+    w, prot, sp, _, db = tiny
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, [], 0,
+                          merge_tol=w.frag_tol_bins).upload()
+    _say(f"tiny merged T={w.frag_tol_bins}: {sp.n} spectra, schedule {schedule}")
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=2, schedule=schedule)
+    res = engine.search(ix, sp, prm)
+    oh, ost, og = db.search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared)
+    assert_parity(res, oh, ost, og)
+    assert res.postings == int(ost["pairs_total"].sum())
+    sub = sp.subset(np.arange(0, 100))
+    prm1 = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, 1, max_charge=2)
+    gs, gi, gb, gy, gq = engine.search_dump(ix, sub, prm1)
+    want = []
+    for s in range(sub.n):
+        ids, nb, ny, sq = db.scored(sub, s, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, min_shared=1)
+        want += [(s, int(a), int(b), int(c), int(d)) for a, b, c, d in zip(ids, nb, ny, sq)]
+    assert list(zip(gs.tolist(), gi.tolist(), gb.tolist(), gy.tolist(), gq.tolist())) == want
+
+
+@pytest.fixture(scope="module")
+def small_open_merged(small_open):
+    w, prot, sp, _, db, expect = small_open
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
+                          engine.mods_from_synth(w.mods), w.max_mods, merge_tol=w.frag_tol_bins).upload()
+    return w, prot, sp, ix, db, expect
+
+
+@pytest.mark.parametrize("sched", [dict(tile=4096, tiles_per_item=64), dict(tile=8192, tiles_per_item=3),
+                                   dict(tile=4096, tiles_per_item=1, groups_per_cu=8)])
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
+def test_small_open_merged_lists_parity(small_open_merged, sched, schedule):
+    w, prot, sp, ix, db, (oh, ost, og) = small_open_merged
+    ix.set_schedule(**sched)
+    _say(f"small open merged: {sched} schedule {schedule}")
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3, schedule=schedule)
+    res = engine.search(ix, sp, prm)
+    assert_parity(res, oh, ost, og)
+    assert res.postings == int(ost["pairs_total"].sum())
