@@ -69,6 +69,8 @@ template <> struct Cnt<uint32_t> {
     __device__ static uint32_t nb(uint32_t c) { return c >> 24; }
     __device__ static uint32_t ny(uint32_t c) { return (c >> 16) & 0xFFu; }
     __device__ static uint32_t s(uint32_t c) { return c & 0xFFFFu; }
+    // n_b + n_y: one byte dot product with weights (1, 1, 0, 0) on the two high bytes
+    __device__ static uint32_t shared(uint32_t c) { return __builtin_amdgcn_udot4(c, 0x01010000u, 0u, false); }
 };
 template <> struct Cnt<unsigned long long> {
     __device__ static unsigned long long inc(uint32_t is_y, uint32_t q) {
@@ -77,6 +79,7 @@ template <> struct Cnt<unsigned long long> {
     __device__ static uint32_t nb(unsigned long long c) { return (uint32_t)(c >> 48); }
     __device__ static uint32_t ny(unsigned long long c) { return (uint32_t)(c >> 32) & 0xFFFFu; }
     __device__ static uint32_t s(unsigned long long c) { return (uint32_t)c; }
+    __device__ static uint32_t shared(unsigned long long c) { return nb(c) + ny(c); }
 };
 
 // Top-k of one wavefront, distributed over its lanes: lane j < k holds the
@@ -87,33 +90,44 @@ __device__ __forceinline__ bool better_hit(double ha, uint32_t ia, double hb, ui
     return ha > hb || (ha == hb && ia < ib);
 }
 
+// Top-k of one wavefront kept in LDS (rows of k entries sorted by hyperscore
+// desc, id asc), so that no registers stay allocated to it across the scan;
+// insertions are rare once the list holds good hits.  Lane j < k handles
+// entry j.  Every call is made by all 64 lanes of the wavefront.
 template <typename C>
 struct WaveTopK {
-    double h;
-    uint32_t id;
-    C c;
-    __device__ void init() { h = -INFINITY; id = 0xFFFFFFFFu; c = 0; }
-    // Insert a wave-uniform candidate; every lane of the wavefront calls this.
+    double* h;
+    uint32_t* id;
+    unsigned long long* c;
+    __device__ void init(uint32_t k) {
+        const uint32_t lane = threadIdx.x & 63u;
+        if (lane < k) { h[lane] = -INFINITY; id[lane] = 0xFFFFFFFFu; c[lane] = 0; }
+    }
+    // Insert a wave-uniform candidate.
     __device__ void insert(double xh, uint32_t xid, C xc, uint32_t k) {
         const uint32_t lane = threadIdx.x & 63u;
-        const unsigned long long m = __ballot(lane < k && better_hit(xh, xid, h, id));
+        const bool in = lane < k;
+        const double hj = in ? h[lane] : 0.0;
+        const uint32_t ij = in ? id[lane] : 0u;
+        const unsigned long long m = __ballot(in && better_hit(xh, xid, hj, ij));
         if (m == 0) return;
         const uint32_t p = (uint32_t)__ffsll((long long)m) - 1u;
-        const double uh = __shfl_up(h, 1, 64);
-        const uint32_t uid = __shfl_up(id, 1, 64);
-        const C uc = __shfl_up(c, 1, 64);
-        if (lane > p && lane < k) { h = uh; id = uid; c = uc; }
-        if (lane == p) { h = xh; id = xid; c = xc; }
+        const bool shift = in && lane > p;
+        const double ph = shift ? h[lane - 1] : 0.0;
+        const uint32_t pi = shift ? id[lane - 1] : 0u;
+        const unsigned long long pc = shift ? c[lane - 1] : 0ull;
+        if (shift) { h[lane] = ph; id[lane] = pi; c[lane] = pc; }
+        if (lane == p) { h[lane] = xh; id[lane] = xid; c[lane] = (unsigned long long)xc; }
     }
     // Insert every flagged lane's candidate that beats the current k-th best.
     __device__ void insert_lanes(bool flag, double ch, uint32_t cid, C cc, uint32_t k) {
-        const double kh = __shfl(h, (int)k - 1, 64);
-        const uint32_t kid = __shfl(id, (int)k - 1, 64);
+        const double kh = h[k - 1];
+        const uint32_t kid = id[k - 1];
         unsigned long long m = __ballot(flag && better_hit(ch, cid, kh, kid));
         while (m) {
             const int l = __ffsll((long long)m) - 1;
             m &= m - 1;
-            insert(__shfl(ch, l, 64), __shfl(cid, l, 64), __shfl(cc, l, 64), k);
+            insert(__shfl(ch, l, 64), __shfl(cid, l, 64), (C)__shfl((unsigned long long)cc, l, 64), k);
         }
     }
 };
@@ -477,7 +491,7 @@ __device__ __forceinline__ void map_slot(const ScanLds<C>& L, uint32_t k, uint32
 struct Gather {
     uint32_t c0, fe, next;
     uint32_t p[kRounds];
-    uint32_t q4[kRounds / 4];   // intensity of round r in byte r % 4 of q4[r / 4]; 0: no posting
+    uint32_t q4[(kRounds + 3) / 4];   // intensity of round r in byte r % 4 of q4[r / 4]; 0: no posting
 };
 
 // Map flat positions [g.next, g.next + 64 * kRounds) of this wavefront to
@@ -487,15 +501,16 @@ struct Gather {
 template <typename C>
 __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C>& L, Gather& g) {
     const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below = (2ull << lane) - 2ull;   // positions 1..lane of a round
 #pragma unroll
-    for (uint32_t r = 0; r < kRounds / 4; ++r) g.q4[r] = 0;
+    for (uint32_t r = 0; r < (kRounds + 3) / 4; ++r) g.q4[r] = 0;
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t f = g.next + 64u * r + lane;
         const bool valid = f < g.fe;
         const uint32_t R = min((g.next - g.c0) / 64u + r, kMapCap / 64u - 1u);   // clamped: rounds past fe
         const unsigned long long bits = L.mbits[R];
-        const uint32_t k = L.mrank[R] + (uint32_t)__popcll(bits & ((2ull << lane) - 2ull));
+        const uint32_t k = L.mrank[R] + (uint32_t)__popcll(bits & below);
         const SegBase sb = L.sbase[valid ? k : 0u];
         g.p[r] = valid ? ix.post[sb.base + f] : 0u;
         g.q4[r / 4] |= (valid ? sb.q : 0u) << (8u * (r % 4u));
@@ -609,8 +624,8 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     }
     __syncthreads();                                   // SlotInit area becomes the counters
 
-    WaveTopK<C> top;
-    top.init();
+    WaveTopK<C> top{sh.wh[wave], sh.wid[wave], sh.wc[wave]};
+    top.init(kp.top_k);
     const uint32_t kk = kp.top_k;
     const uint32_t kmin = kp.min_shared;
     uint32_t scored = 0;
@@ -669,34 +684,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         for (uint32_t i = tid; i < kp.tile; i += kBlock) L.cnt[i] = (C)0;
         prepare();
     }
-    // Every register loaded in one tile is first used right after the next
+    // The directory quad loaded in one tile is first used right after the next
     // tile's posting batch is consumed, where the wavefront waits for its loads
-    // anyway: the deferred scoring of the previous tile's candidates, and the
-    // boundary taken from a directory quad.
-    // Each wavefront buffers its own candidates (kWaveCand slots from wbuf) and
+    // anyway.  Each wavefront buffers its own candidates (kWaveCand slots from wbuf) and
     // scores them itself, so the filter needs no shared counter or barrier.
     const uint32_t wbuf = wave * kWaveCand;
-    bool pf_ok = false;                                 // a buffered candidate of the previous tile
-    C pf_c = 0;
-    uint32_t pf_id = 0;
-    double pf_ls = 0.0;
-    uint32_t pf_n = 0, pf_tb = 0;                       // this wavefront's candidates of the previous tile, its base
-    auto score_buffered = [&]() {
-        if (pf_n) {
-            const double h = pf_ok ? score_finish<C, DUMP>(A, L, s, pf_id, pf_c, pf_ls, scored) : -INFINITY;
-            top.insert_lanes(pf_ok, h, pf_id, pf_c, kk);
-        }
-        for (uint32_t base = 64u; base < pf_n; base += 64u) {   // beyond the prefetched ones
-            const uint32_t j = base + lane;
-            const bool ok = j < pf_n;
-            const C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
-            const uint32_t id = ok ? pf_tb + L.cand_idx[wbuf + j] : 0u;
-            const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
-            top.insert_lanes(ok, h, id, c, kk);
-        }
-        pf_n = 0;
-        pf_ok = false;
-    };
     const uint32_t t_end = nact > 0 ? t_last + 1 : t0;
     for (uint32_t t = t0; t < t_end; ++t) {
         const uint32_t tb = t << tsh;
@@ -721,7 +713,6 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                 gather_consume<C>(L, g, tb);
             }
         }
-        score_buffered();                               // the previous tile's candidates
         // end of tile t + 2 from the quad holding directory entry (t + 3) m
         const bool use = t + 2 <= t_last && needs_dir(t + 2);
         const uint32_t idx = (t + 3) * m;
@@ -758,7 +749,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                 }
 #pragma unroll
                 for (uint32_t e = 0; e < kPer; ++e) {
-                    const bool pass = Cnt<C>::nb(c[e]) + Cnt<C>::ny(c[e]) >= kmin;
+                    const bool pass = Cnt<C>::shared(c[e]) >= kmin;
                     const unsigned long long msk = __ballot(pass);
                     if (msk == 0) continue;             // wave-uniform
                     const uint32_t pos = i * kPer + e;
@@ -777,9 +768,15 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                     wn = min(wn + (uint32_t)__popcll(msk), kWaveCand);
                 }
             }
-            pf_n = wn;
-            pf_tb = tb;
-            pf_ok = lane < pf_n;
+            // hyperscore, histogram, top-k over this wavefront's candidates
+            for (uint32_t base = 0; base < wn; base += 64u) {
+                const uint32_t j = base + lane;
+                const bool ok = j < wn;
+                const C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
+                const uint32_t id = ok ? tb + L.cand_idx[wbuf + j] : 0u;
+                const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
+                top.insert_lanes(ok, h, id, c, kk);
+            }
         }
         if (t < t_last) {
             // slots move to tile t + 1, and the quad for the next tile's boundary
@@ -795,22 +792,9 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             }
             prepare();
         }
-        // the first kBlock buffered candidates request log10 S last, and are
-        // scored after the next tile's batch is consumed
-        if (pf_ok) {
-            pf_c = L.cand_cnt[wbuf + lane];
-            pf_id = pf_tb + L.cand_idx[wbuf + lane];
-            pf_ls = ix.ls[Cnt<C>::s(pf_c)];
-        }
     }
-    score_buffered();                                   // the last tile's candidates
 
-    // top-k of the item: the wavefronts' lists, merged by one thread
-    if (lane < kk) {
-        sh.wh[wave][lane] = top.h;
-        sh.wid[wave][lane] = top.id;
-        sh.wc[wave][lane] = (unsigned long long)top.c;
-    }
+    // top-k of the item: the wavefronts' lists (in LDS), merged by one thread
     const unsigned long long sc = block_sum<unsigned long long>(scored, sh.red);   // has barriers
     if (tid == 0) {
         uint32_t head[kBlock / 64];
