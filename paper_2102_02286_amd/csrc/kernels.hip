@@ -386,7 +386,7 @@ struct ScanLds {
     C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter, kWaveCand per wavefront
     int32_t* hist;
     double* lf;           // [kLfLds] log10(n!) for the narrow counters' n_b, n_y <= 255
-    uint16_t* cand_idx;   // [kCandCap] their positions in the tile
+    uint32_t* cand_id;    // [kCandCap] their peptide ids
     __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap) {
         size_t o = 0;
         cnt = (C*)base;
@@ -401,7 +401,7 @@ struct ScanLds {
         cand_cnt = (C*)(base + o); o += (size_t)kCandCap * sizeof(C);
         hist = (int32_t*)(base + o); o += (size_t)kHistBins * 4;
         lf = (double*)(base + o); o += (size_t)kLfLds * 8;
-        cand_idx = (uint16_t*)(base + o);
+        cand_id = (uint32_t*)(base + o);
     }
 };
 
@@ -414,7 +414,7 @@ size_t scan_lds_bytes(const KParams& kp, bool wide) {
     o += (size_t)kCandCap * csz;
     o += (size_t)kHistBins * 4;
     o += (size_t)kLfLds * 8;
-    o += (size_t)kCandCap * 2;
+    o += (size_t)kCandCap * 4;
     return (o + 15) & ~(size_t)15;
 }
 
@@ -689,6 +689,20 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     // anyway.  Each wavefront buffers its own candidates (kWaveCand slots from wbuf) and
     // scores them itself, so the filter needs no shared counter or barrier.
     const uint32_t wbuf = wave * kWaveCand;
+    // Candidates collect over tiles and are scored 64 at a time (full rounds),
+    // when the buffer passes a round, when it could overflow, and at the end.
+    uint32_t wn = 0;                                    // wave-uniform: candidates buffered
+    auto score_buffer = [&]() {
+        for (uint32_t base = 0; base < wn; base += 64u) {
+            const uint32_t j = base + lane;
+            const bool ok = j < wn;
+            const C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
+            const uint32_t id = ok ? L.cand_id[wbuf + j] : 0u;
+            const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
+            top.insert_lanes(ok, h, id, c, kk);
+        }
+        wn = 0;
+    };
     const uint32_t t_end = nact > 0 ? t_last + 1 : t0;
     for (uint32_t t = t0; t < t_end; ++t) {
         const uint32_t tb = t << tsh;
@@ -735,7 +749,6 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             constexpr uint32_t kPer = 16 / sizeof(C);
             const uint32_t nvec = kp.tile / kPer;
             uint4* cv = (uint4*)L.cnt;
-            uint32_t wn = 0;                            // wave-uniform: candidates buffered so far
             for (uint32_t base = wave * 64u; base < nvec; base += kBlock) {   // nvec is a multiple of kBlock
                 const uint32_t i = base + lane;
                 const uint4 v = cv[i];
@@ -752,31 +765,17 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                     const bool pass = Cnt<C>::shared(c[e]) >= kmin;
                     const unsigned long long msk = __ballot(pass);
                     if (msk == 0) continue;             // wave-uniform
-                    const uint32_t pos = i * kPer + e;
+                    if (wn > kWaveCand - 64u) score_buffer();   // room for a whole wavefront
                     const uint32_t off = wn + __builtin_amdgcn_mbcnt_hi((uint32_t)(msk >> 32),
                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0u));
-                    const bool fits = off < kWaveCand;
-                    if (pass && fits) {
-                        L.cand_idx[wbuf + off] = (uint16_t)pos;
+                    if (pass) {
+                        L.cand_id[wbuf + off] = tb + i * kPer + e;
                         L.cand_cnt[wbuf + off] = c[e];
                     }
-                    const bool ovf = pass && !fits;     // buffer full: score in place
-                    if (__ballot(ovf)) {
-                        const double h = ovf ? score_one<C, DUMP>(A, L, s, tb + pos, c[e], scored) : -INFINITY;
-                        top.insert_lanes(ovf, h, tb + pos, c[e], kk);
-                    }
-                    wn = min(wn + (uint32_t)__popcll(msk), kWaveCand);
+                    wn += (uint32_t)__popcll(msk);
                 }
             }
-            // hyperscore, histogram, top-k over this wavefront's candidates
-            for (uint32_t base = 0; base < wn; base += 64u) {
-                const uint32_t j = base + lane;
-                const bool ok = j < wn;
-                const C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
-                const uint32_t id = ok ? tb + L.cand_idx[wbuf + j] : 0u;
-                const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
-                top.insert_lanes(ok, h, id, c, kk);
-            }
+            if (wn >= 64u) score_buffer();
         }
         if (t < t_last) {
             // slots move to tile t + 1, and the quad for the next tile's boundary
@@ -794,6 +793,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         }
     }
 
+    score_buffer();                                     // what is left of the item's candidates
     // top-k of the item: the wavefronts' lists (in LDS), merged by one thread
     const unsigned long long sc = block_sum<unsigned long long>(scored, sh.red);   // has barriers
     if (tid == 0) {
