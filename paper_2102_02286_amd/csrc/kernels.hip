@@ -473,6 +473,53 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* wsum, T* total) {
     return before + x - v;
 }
 
+// Inclusive prefix sum over one wavefront: DPP row shifts within each 16-lane
+// row, then row broadcasts (each step adds only where the lane condition holds,
+// so out-of-row sources never matter).
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false); if ((lane & 15u) >= 1u) x += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false); if ((lane & 15u) >= 2u) x += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false); if ((lane & 15u) >= 4u) x += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false); if ((lane & 15u) >= 8u) x += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xF, 0xF, false); if ((lane & 31u) >= 16u) x += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xF, 0xF, false); if (lane >= 32u) x += t;
+    return x;
+}
+
+// Exclusive prefix sums over the workgroup (thread order) of a count n and of a
+// small number e <= U, with their totals.  One barrier; `wsum` must be free.
+template <uint32_t U>
+__device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsigned long long* wsum, uint32_t* n_ex,
+                                                  uint32_t* e_ex, uint32_t* n_all, uint32_t* e_all) {
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_inclusive_sum(n);
+    uint32_t ex = 0, et = 0;
+#pragma unroll
+    for (uint32_t b = 0; (1u << b) <= U; ++b) {        // e bit by bit: ballot + mbcnt
+        const unsigned long long m = __ballot((e >> b) & 1u);
+        ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+        et += (uint32_t)__popcll(m) << b;
+    }
+    const uint32_t ntot = __shfl(incl, 63, 64);
+    if (lane == 0) wsum[wave] = ((unsigned long long)et << 32) | ntot;
+    __syncthreads();
+    uint32_t nb = 0, eb = 0, na = 0, ea = 0;
+    for (uint32_t w = 0; w < kBlock / 64; ++w) {
+        const unsigned long long v = wsum[w];
+        const uint32_t vn = (uint32_t)v, ve = (uint32_t)(v >> 32);
+        nb += w < wave ? vn : 0u;
+        eb += w < wave ? ve : 0u;
+        na += vn;
+        ea += ve;
+    }
+    *n_ex = nb + incl - n;
+    *e_ex = eb + ex;
+    *n_all = na;
+    *e_all = ea;
+}
+
 // Enter the slot of rank k, whose range is [a, b), into the map of the chunk
 // [c0, c0 + kMapCap): its start bit, and the rank of every 64-position round
 // that begins inside it.
@@ -650,15 +697,15 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     // slots hold [o_cur, o_end), then this wavefront's first gather batch
     auto prepare = [&]() {
         for (uint32_t i = tid; i < kMapCap / 64u; i += kBlock) L.mbits[i] = 0ull;
-        unsigned long long mine = 0;
+        uint32_t mine = 0, mine_ne = 0;
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {                 // unowned slots are 0 - 0
             const uint32_t n = o_end[u] - o_cur[u];
-            mine += (unsigned long long)n | ((unsigned long long)(n != 0u) << 32);
+            mine += n;
+            mine_ne += n != 0u;
         }
-        unsigned long long total;
-        const unsigned long long ex = block_exclusive_scan<unsigned long long>(mine, sh.wsum, &total);
-        uint32_t run = (uint32_t)ex, rank = (uint32_t)(ex >> 32);
+        uint32_t run, rank, total_n, total_ne;
+        block_scan_counts<U>(mine, mine_ne, sh.wsum, &run, &rank, &total_n, &total_ne);
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
             const uint32_t n = o_end[u] - o_cur[u];
@@ -673,8 +720,8 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                 ++rank;
             }
         }
-        ptot = (uint32_t)total;
-        nne = (uint32_t)(total >> 32);
+        ptot = total_n;
+        nne = total_ne;
         __syncthreads();
         share(0u, ptot);
         gather_issue<C>(ix, L, g);
