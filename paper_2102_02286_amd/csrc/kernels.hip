@@ -60,14 +60,20 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
     return r;
 }
 
-// Packed shared-peak counters.  Narrow: [n_b:8 | n_y:8 | S:16] in 32 bits;
+// Packed shared-peak counters.  Narrow: [n_y:8 | n_b:8 | S:16] in 32 bits;
 // wide: [n_b:16 | n_y:16 | S:32] in 64 bits.  The prep kernel proves per
 // spectrum that no field can overflow before choosing the narrow form.
 template <typename C> struct Cnt;
 template <> struct Cnt<uint32_t> {
-    __device__ static uint32_t inc(uint32_t is_y, uint32_t q) { return (is_y ? (1u << 16) : (1u << 24)) + q; }
-    __device__ static uint32_t nb(uint32_t c) { return c >> 24; }
-    __device__ static uint32_t ny(uint32_t c) { return (c >> 16) & 0xFFu; }
+    __device__ static uint32_t inc(uint32_t is_y, uint32_t q) { return (is_y ? (1u << 24) : (1u << 16)) + q; }
+    // the same from byte `byte` of a packed intensity word: (q | 1 << 16) from one
+    // byte permute, plus 0xFF0000 for a y ion
+    __device__ static uint32_t inc_packed(uint32_t is_y, uint32_t q4, uint32_t byte) {
+        const uint32_t qb = __builtin_amdgcn_perm(0x00010000u, q4, 0x0C060C00u | byte);
+        return is_y * 0xFF0000u + qb;                   // is_y is 0 or 1: one 24-bit multiply-add
+    }
+    __device__ static uint32_t nb(uint32_t c) { return (c >> 16) & 0xFFu; }
+    __device__ static uint32_t ny(uint32_t c) { return c >> 24; }
     __device__ static uint32_t s(uint32_t c) { return c & 0xFFFFu; }
     // n_b + n_y: one byte dot product with weights (1, 1, 0, 0) on the two high bytes
     __device__ static uint32_t shared(uint32_t c) { return __builtin_amdgcn_udot4(c, 0x01010000u, 0u, false); }
@@ -80,6 +86,9 @@ template <> struct Cnt<unsigned long long> {
     __device__ static uint32_t ny(unsigned long long c) { return (uint32_t)(c >> 32) & 0xFFFFu; }
     __device__ static uint32_t s(unsigned long long c) { return (uint32_t)c; }
     __device__ static uint32_t shared(unsigned long long c) { return nb(c) + ny(c); }
+    __device__ static unsigned long long inc_packed(uint32_t is_y, uint32_t q4, uint32_t byte) {
+        return inc(is_y, (q4 >> (8u * byte)) & 0xFFu);
+    }
 };
 
 // Top-k of one wavefront, distributed over its lanes: lane j < k holds the
@@ -566,13 +575,13 @@ __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C
 }
 
 template <typename C>
-__device__ __forceinline__ void gather_consume(const ScanLds<C>& L, const Gather& g, uint32_t tb) {
+__device__ __forceinline__ void gather_consume(const ScanLds<C>& L, const Gather& g, uint32_t tsh) {
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
-        const uint32_t q = (g.q4[r / 4] >> (8u * (r % 4u))) & 0xFFu;
-        if (q) {
+        if ((g.q4[r / 4] >> (8u * (r % 4u))) & 0xFFu) {
+            // tiles are aligned to their size: the counter is the id modulo the tile
             const uint32_t p = g.p[r];
-            atomicAdd(&L.cnt[(p >> 1) - tb], Cnt<C>::inc(p & 1u, q));
+            atomicAdd(&L.cnt[__builtin_amdgcn_ubfe(p, 1u, tsh)], Cnt<C>::inc_packed(p & 1u, g.q4[r / 4], r % 4u));
         }
     }
 }
@@ -594,7 +603,8 @@ template <typename C, bool DUMP, uint32_t U>
 __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint32_t s, uint32_t ida,
                           uint32_t idb, ps_hit* out) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar addressing
     const KParams& kp = A.kp;
     const DevIndex& ix = A.ix;
     const uint32_t n_ent = A.w.info[s].n_ent;
@@ -755,10 +765,10 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         const uint32_t tb = t << tsh;
         // counters of tile t: the batch loaded last, then any further batches,
         // then any further chunks
-        gather_consume<C>(L, g, tb);
+        gather_consume<C>(L, g, tsh);
         while (g.next < g.fe) {
             gather_issue<C>(ix, L, g);
-            gather_consume<C>(L, g, tb);
+            gather_consume<C>(L, g, tsh);
         }
         const uint32_t p_t = ptot;
         for (uint32_t c0 = kMapCap; c0 < p_t; c0 += kMapCap) {
@@ -771,7 +781,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             share(c0, p_t);
             while (g.next < g.fe) {
                 gather_issue<C>(ix, L, g);
-                gather_consume<C>(L, g, tb);
+                gather_consume<C>(L, g, tsh);
             }
         }
         // end of tile t + 2 from the quad holding directory entry (t + 3) m
