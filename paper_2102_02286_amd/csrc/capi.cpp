@@ -109,7 +109,7 @@ Schedule default_schedule() {
     Schedule s{};
     s.tile = 4096;
     s.tiles_per_item = 64;
-    s.groups_per_cu = 4;
+    s.groups_per_cu = 6;
     return s;
 }
 

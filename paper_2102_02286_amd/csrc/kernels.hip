@@ -347,10 +347,9 @@ struct ScanArgs {
 };
 
 constexpr uint32_t kRounds = 8;       // gather rounds of 64 postings a wavefront keeps in flight
-constexpr uint32_t kCandCap = 512;    // scored candidates buffered per tile before scoring
+constexpr uint32_t kCandCap = 384;    // candidates buffered per workgroup before scoring
 constexpr uint32_t kWaveCand = kCandCap / (kBlock / 64);   // each wavefront's share of the buffer
-constexpr uint32_t kMapCap = 8192;    // flat posting positions mapped to slots at a time
-constexpr uint32_t kLfLds = 256;      // log10(n!) entries kept in LDS
+constexpr uint32_t kMapCap = 4096;    // flat posting positions mapped to slots at a time
 // s_waitcnt operand (gfx9 encoding): vmcnt(0), expcnt and lgkmcnt left at their maxima
 constexpr int kWaitVmem0 = 0x0F70;
 
@@ -394,7 +393,6 @@ struct ScanLds {
     uint32_t* mrank;
     C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter, kWaveCand per wavefront
     int32_t* hist;
-    double* lf;           // [kLfLds] log10(n!) for the narrow counters' n_b, n_y <= 255
     uint32_t* cand_id;    // [kCandCap] their peptide ids
     __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap) {
         size_t o = 0;
@@ -409,7 +407,6 @@ struct ScanLds {
         o = (o + 15) & ~(size_t)15;
         cand_cnt = (C*)(base + o); o += (size_t)kCandCap * sizeof(C);
         hist = (int32_t*)(base + o); o += (size_t)kHistBins * 4;
-        lf = (double*)(base + o); o += (size_t)kLfLds * 8;
         cand_id = (uint32_t*)(base + o);
     }
 };
@@ -422,22 +419,18 @@ size_t scan_lds_bytes(const KParams& kp, bool wide) {
     o = (o + 15) & ~(size_t)15;
     o += (size_t)kCandCap * csz;
     o += (size_t)kHistBins * 4;
-    o += (size_t)kLfLds * 8;
     o += (size_t)kCandCap * 4;
     return (o + 15) & ~(size_t)15;
 }
 
 // Hyperscore of one candidate that passed the filter: log10(n_b! n_y! S) from
-// the fp64 tables (log10 S passed in, so that its load can be issued early),
-// plus its histogram bin (width 0.1, last bin open).
+// the fp64 tables (log10 S passed in), plus its histogram bin (width 0.1,
+// last bin open).
 template <typename C, bool DUMP>
 __device__ __forceinline__ double score_finish(const ScanArgs& A, ScanLds<C>& L, uint32_t s, uint32_t id, C c,
                                                double ls_sq, uint32_t& scored) {
     const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c), sq = Cnt<C>::s(c);
-    double lfb, lfy;
-    if constexpr (sizeof(C) == 4) { lfb = L.lf[nb]; lfy = L.lf[ny]; }   // narrow: n_b, n_y <= 255
-    else { lfb = A.ix.lf[nb]; lfy = A.ix.lf[ny]; }
-    const double h = (lfb + lfy) + ls_sq;
+    const double h = (A.ix.lf[nb] + A.ix.lf[ny]) + ls_sq;
     const double hb = floor(10.0 * h);
     const int bin = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
     atomicAdd(&L.hist[bin], 1);
@@ -909,7 +902,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
         }
         return;
     }
-    for (uint32_t i = threadIdx.x; i < kLfLds; i += kBlock) L.lf[i] = A.ix.lf[i];   // read after a barrier
     scan_item<C, DUMP, U>(A, sh, L, s, inf.lo, inf.hi, out);
 }
 
@@ -1021,8 +1013,12 @@ hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& 
     return hipGetLastError();
 }
 
+// With one probe slot per thread, ask for six resident wavefronts per SIMD
+// (at most 80 VGPRs): with the LDS of six workgroups per CU this is the
+// occupancy the work-queue scan runs best at.
 template <typename C, uint32_t U>
-__global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(U == 1 ? 6 : 1, 8)))
+void k_scan_persistent(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
     __shared__ uint32_t s_item;
@@ -1030,7 +1026,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_persistent(ScanArgs A) {
     const uint32_t n = (uint32_t)A.sp.hdr->n;
     const uint32_t total = A.w.spec_item0[n];
     const uint32_t tpi = A.tiles_per_item;
-    for (uint32_t i = threadIdx.x; i < kLfLds; i += kBlock) L.lf[i] = A.ix.lf[i];   // read after a barrier
     while (true) {
         if (threadIdx.x == 0) s_item = (uint32_t)atomicAdd(&A.w.counters[kCtrQueue], 1ull);
         __syncthreads();
