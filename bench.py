@@ -123,24 +123,25 @@ def serve(engine, synth, ix, prm, sp, capacity, load, n_requests, seed, max_peak
             "runs": int(st.runs), "slots": int(st.slots)}
 
 
-def measured_traffic(workload_name):
-    """HBM bytes per scan launch from the committed rocprofv3 counter summary,
-    valid only while the kernel source is the one the counters were taken on."""
+def measured_traffic(workload_name, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, valid only while the kernel source is the one the counters were
+    taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "scan_persistent_medium_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", "scan_medium_hbm_counters.md")
     if workload_name != "medium" or not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and line.startswith("    ") and line.strip().split(":")[0] in (
-                "traffic_bytes_per_launch", "kernel_source_sha256"):
+        if line.startswith("    ") and ":" in line:
             k, v = line.strip().split(":", 1)
-            vals[k] = v.strip()
+            vals[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_2102_02286_amd", "csrc", "kernels.hip")
     now = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256") != now:
+    key = f"traffic_bytes_per_launch {kernel}"
+    if vals.get("kernel_source_sha256") != now or key not in vals:
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return float(vals[key])
 
 
 def plan_bytes(engine, ix, prm, n, nnz):
@@ -247,16 +248,15 @@ def main():
     if plain is not None:
         assert res_eager.hits.tobytes() == res_plain.hits.tobytes(), "plain and persistent results differ"
 
-    # ---- persistent graph plan over the resident batch: the headline number
-    persistent = None
-    if args.only in (None, "persistent"):
-        plan = engine.Plan(ix, prm_pers, n_cap=sp.n, nnz_cap=nnz)
+    # ---- graph plans over the resident batch (both schedules); the faster is the headline
+    def graph_steps(name, prm, eager_ref):
+        plan = engine.Plan(ix, prm, n_cap=sp.n, nnz_cap=nnz)
         fill_plan_inputs(plan, tens, torch)
         for _ in range(args.warmup):
             plan.run_device(sp.n, nnz)
             plan.results()
         torch.cuda.synchronize()
-        log(f"timing {args.steps} persistent steps")
+        log(f"timing {args.steps} {name} graph steps")
         t0 = time.perf_counter()
         graph_ms = []
         for _ in range(args.steps):
@@ -265,26 +265,47 @@ def main():
             graph_ms.append(r.graph_ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        assert r.hits.tobytes() == res_eager.hits.tobytes(), "graph replay and eager results differ"
-        persistent = {"spectra_per_s": sp.n * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
-                      "graph_ms": float(np.mean(graph_ms)), "scan_ms": scan_avg, "work_items": int(r.items)}
-        log(f"persistent: {persistent['spectra_per_s']:.0f} spectra/s, {persistent['ms_per_step']:.1f} ms/step, "
-            f"graph {persistent['graph_ms']:.1f} ms, scan {scan_avg:.1f} ms, {r.items} work items")
+        assert r.hits.tobytes() == eager_ref.hits.tobytes(), f"{name} graph replay and eager results differ"
+        out = {"spectra_per_s": sp.n * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+               "graph_ms": float(np.mean(graph_ms)), "work_items": int(r.items)}
+        log(f"{name} graph: {out['spectra_per_s']:.0f} spectra/s, {out['ms_per_step']:.1f} ms/step, "
+            f"graph {out['graph_ms']:.1f} ms")
         del plan
+        return out
+
+    persistent = None
+    if args.only in (None, "persistent"):
+        use("persistent")
+        persistent = graph_steps("persistent", prm_pers, res_eager)
+        persistent["scan_ms"] = scan_avg
+    if plain is not None:
+        use("plain")
+        g = graph_steps("plain", prm_plain, res_plain)
+        plain.update({"graph_spectra_per_s": g["spectra_per_s"], "graph_ms_per_step": g["ms_per_step"],
+                      "graph_ms": g["graph_ms"]})
+        use("persistent")
     st = np.bincount(res_eager.stats["status"], minlength=6)
     log(f"status counts {st.tolist()}")
 
+    # headline: the faster graph form; its scan kernel's HIP-event time gives the roofline
+    forms = []
+    if persistent is not None:
+        forms.append(("persistent", persistent["spectra_per_s"], persistent["ms_per_step"], scan_avg,
+                      res_eager.postings, res_eager.lookups, "k_scan_persistent"))
+    if plain is not None:
+        forms.append(("plain", plain["graph_spectra_per_s"], plain["graph_ms_per_step"], plain["scan_ms"],
+                      res_plain.postings, res_plain.lookups, "k_scan_plain"))
+    form, value, ms_step, head_scan, postings, lookups, kernel = max(forms, key=lambda f: f[1])
     alg_bytes = 4.0 * postings + 16.0 * lookups
-    achieved = alg_bytes / (scan_avg * 1e-3) / 1e9
-    head = persistent or plain
+    achieved = alg_bytes / (head_scan * 1e-3) / 1e9
     out.update({
         "metric": "spectra searched/sec at 1 MI355X (serving vs plain batch), p99 latency, HBM GB/s %",
-        "value": head["spectra_per_s"],
+        "value": value,
         "unit": "spectra/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -293,17 +314,19 @@ def main():
         "config": {"workload": f"{w.name}: {prot.n} proteins, {n_pep} peptides, {n_post} postings "
                                f"(lists merging {2 * merge + 1} neighbouring bin(s)), {sp.n} spectra, "
                                f"window +-{w.window / 1e6:g} Da, fragment tol {w.frag_tol_bins} bin(s), "
-                               f"top {w.top_k}, persistent work-queue scan replayed as a hipGraph"},
+                               f"top {w.top_k}, whole search replayed as a hipGraph, {form} scan schedule",
+                   "schedule": form},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
-                     "kernel": "k_scan_persistent (posting scan)", "scan_ms": scan_avg,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, kernel),
+                     "kernel": f"{kernel} (posting scan)", "scan_ms": head_scan,
                      "bytes_per_launch": alg_bytes, "postings_per_launch": postings,
                      "bin_lookups_per_launch": lookups},
         "plain": plain,
         "persistent": persistent,
         "schedule": {"plain": as_dict(tuned["plain"]), "persistent": as_dict(tuned["persistent"])},
     })
-    log(f"roofline: {alg_bytes / 1e9:.1f} GB algorithmic per step in {scan_avg:.1f} ms = {achieved:.0f} GB/s")
+    log(f"headline: {form} graph; roofline: {alg_bytes / 1e9:.1f} GB algorithmic per step in {head_scan:.1f} ms "
+        f"= {achieved:.0f} GB/s")
 
     # ---- serving: continuous batching at two loads
     if not args.no_serving and persistent is not None:
