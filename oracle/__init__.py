@@ -68,6 +68,10 @@ def lib():
         L.orc_scored.restype = C.c_int64
         L.orc_scored.argtypes = [P, P, P, P, C.c_double, C.c_int8, C.POINTER(Params), P, P, P, P,
                                  C.c_uint64]
+        L.orc_db_shard.restype = P
+        L.orc_db_shard.argtypes = [P, C.c_uint32, C.c_uint32]
+        L.orc_assemble.restype = C.c_int
+        L.orc_assemble.argtypes = [C.c_uint32, C.c_uint64, C.c_uint32, P, P, P, P, P, P]
         L.orc_hyperscore.restype = C.c_double
         L.orc_hyperscore.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
         L.orc_sg_smooth.argtypes = [P, P]
@@ -114,6 +118,15 @@ class Database:
                                   _ptr(delta), max_mods)
         if not self._h:
             raise ValueError("oracle rejected the database parameters")
+
+    def shard(self, n_shards: int, shard: int) -> "Database":
+        """Partition `shard` of `n_shards`: entries with rank r % G == g, in order."""
+        h = lib().orc_db_shard(self._h, int(n_shards), int(shard))
+        if not h:
+            raise ValueError("invalid shard")
+        out = Database.__new__(Database)
+        out._res, out._off, out._h = self._res, self._off, h
+        return out
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -175,6 +188,24 @@ class Database:
         if k > cap:
             raise OverflowError("scored set larger than cap")
         return ids[:k].copy(), nb[:k].copy(), ny[:k].copy(), sq[:k].copy()
+
+
+def assemble(part_hits, part_stats, part_hist):
+    """Assemble G partition results (lists indexed by partition g, each as
+    returned by Database.search on Database.shard(G, g)) into whole-database
+    results: (hits[n, k], stats[n], hist[n, 512])."""
+    G = len(part_hits)
+    n, k = part_hits[0].shape
+    ph = np.ascontiguousarray(np.stack(part_hits), dtype=HIT_DTYPE)
+    ps = np.ascontiguousarray(np.stack(part_stats), dtype=STAT_DTYPE)
+    pg = np.ascontiguousarray(np.stack(part_hist), dtype=np.int32)
+    hits = np.zeros(n * k, HIT_DTYPE)
+    stats = np.zeros(n, STAT_DTYPE)
+    hist = np.zeros(n * HIST_BINS, np.int32)
+    rc = lib().orc_assemble(G, n, k, _ptr(ph), _ptr(ps), _ptr(pg), _ptr(hits), _ptr(stats), _ptr(hist))
+    if rc != 0:
+        raise ValueError("oracle rejected the assembly arguments")
+    return hits.reshape(n, k), stats, hist.reshape(n, HIST_BINS)
 
 
 def ions(residue_uda: np.ndarray) -> tuple[np.ndarray, np.ndarray]:

@@ -547,3 +547,100 @@ int64_t orc_scored(const orc_db* db, const uint64_t* peak_off_2, const float* mz
     free(hits);
     return rc ? -1 : J.d_n;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Partitions and result assembly (Superstep 1 is_mine; Superstep 4;          */
+/* Supplementary Algorithm 4).                                                */
+/* ------------------------------------------------------------------------ */
+
+/* The entries a process keeps in a partitioned search.  Reading: the sorted
+ * database is scattered round robin (Supplementary Fig. 3 allows round robin or
+ * random), so entry r of the whole database is entry r / G of partition r % G
+ * and every partition keeps the global sort order. */
+orc_db* orc_db_shard(const orc_db* src, uint32_t n_shards, uint32_t shard) {
+    if (n_shards == 0 || shard >= n_shards) return NULL;
+    orc_db* db = (orc_db*)calloc(1, sizeof(orc_db));
+    uint64_t total = src->off[src->n_prot];
+    db->seq = (char*)malloc(total + 1);
+    memcpy(db->seq, src->seq, total);
+    db->off = (uint64_t*)malloc((src->n_prot + 1) * sizeof(uint64_t));
+    memcpy(db->off, src->off, (src->n_prot + 1) * sizeof(uint64_t));
+    db->n_prot = src->n_prot;
+    db->n_mods = src->n_mods;
+    memcpy(db->mod_res_mask, src->mod_res_mask, sizeof db->mod_res_mask);
+    memcpy(db->mod_nterm, src->mod_nterm, sizeof db->mod_nterm);
+    memcpy(db->mod_delta, src->mod_delta, sizeof db->mod_delta);
+    for (uint64_t r = shard; r < src->n_pep; r += n_shards) push_peptide(db, src->pep[r]);
+    return db;
+}
+
+static int hit_order_cmp(const void* a, const void* b) {
+    const orc_hit* x = (const orc_hit*)a;
+    const orc_hit* y = (const orc_hit*)b;
+    if (better(x->hyperscore, x->id, y->hyperscore, y->id)) return -1;
+    if (better(y->hyperscore, y->id, x->hyperscore, x->id)) return 1;
+    return 0;
+}
+
+/* Assemble the partial results of G partitions into complete ones, per
+ * spectrum, in the order of Supplementary Algorithm 4:
+ *   1. the null distribution is the bin-wise sum of the partial histograms
+ *      (the "addition" of Superstep 4; the partial histograms here are not
+ *      sampled, so they share bin 0 and no shift is needed);
+ *   2. every partial top hit, with its id turned back into the global id
+ *      (local * G + g), goes into one list ordered by (hyperscore desc,
+ *      id asc), of which the first k are kept (the max-heap);
+ *   3. the fit and expect value of orc_evalue run on the assembled histogram
+ *      with the best hit's hyperscore and N = the summed scored counts.
+ * Window sizes and shared-pair totals add; the window id range is recovered
+ * from the partitions' ranges.  Inputs are laid out [G][n][...]. */
+int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, const orc_hit* part_hits,
+                 const orc_stat* part_stats, const int32_t* part_hist, orc_hit* hits,
+                 orc_stat* stats, int32_t* hist) {
+    if (n_shards == 0 || top_k < 1 || top_k > 64) return -1;
+    const uint64_t G = n_shards;
+    orc_hit* pool = (orc_hit*)malloc((size_t)G * top_k * sizeof(orc_hit));
+    int32_t dist[ORC_HIST_BINS];
+    for (uint64_t s = 0; s < n; ++s) {
+        memset(dist, 0, sizeof dist);
+        orc_stat st;
+        memset(&st, 0, sizeof st);
+        uint64_t lo = UINT64_MAX, hi = 0;
+        uint64_t m = 0;
+        for (uint64_t g = 0; g < G; ++g) {
+            const orc_stat* ps = part_stats + g * n + s;
+            st.n_window += ps->n_window;
+            st.n_scored += ps->n_scored;
+            st.pairs_total += ps->pairs_total;
+            if (ps->hi > ps->lo) {
+                uint64_t a = ps->lo * G + g, b = (ps->hi - 1) * G + g + 1;
+                if (a < lo) lo = a;
+                if (b > hi) hi = b;
+            }
+            for (int j = 0; j < ORC_HIST_BINS; ++j) dist[j] += part_hist[(g * n + s) * ORC_HIST_BINS + j];
+            const orc_hit* ph = part_hits + (g * n + s) * top_k;
+            for (uint32_t i = 0; i < top_k; ++i) {
+                if (ph[i].id == UINT32_MAX) continue;
+                pool[m] = ph[i];
+                pool[m].id = (uint32_t)((uint64_t)ph[i].id * G + g);
+                ++m;
+            }
+        }
+        if (hi == 0) lo = 0;
+        st.lo = lo; st.hi = hi;
+        qsort(pool, (size_t)m, sizeof(orc_hit), hit_order_cmp);
+        orc_hit* out = hits + s * top_k;
+        for (uint32_t i = 0; i < top_k; ++i) {
+            if (i < m) { out[i] = pool[i]; continue; }
+            out[i].id = UINT32_MAX; out[i].n_b = 0; out[i].n_y = 0;
+            out[i].sum_q = 0; out[i].pad = 0; out[i].hyperscore = -INFINITY;
+        }
+        double w, b; int32_t npts;
+        double top = st.n_scored ? out[0].hyperscore : 0.0;
+        st.status = orc_evalue(dist, top, st.n_scored, &st.evalue, &w, &b, &npts);
+        stats[s] = st;
+        if (hist) memcpy(hist + s * ORC_HIST_BINS, dist, sizeof dist);
+    }
+    free(pool);
+    return 0;
+}

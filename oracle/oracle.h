@@ -16,7 +16,10 @@
  *     per Supplementary Text 4), hyperscore, top hits (Supplementary Algorithm 3),
  *     a score histogram (Sampling section: the 2048-byte local null
  *     distribution), Savitzky-Golay smoothing, linear tail fit and expect value
- *     (Superstep 4; Supplementary Algorithm 4).
+ *     (Superstep 4; Supplementary Algorithm 4);
+ *   - partitions and result assembly: round-robin database partitions and the
+ *     histogram addition plus top-hit merge of Superstep 4 (Supplementary
+ *     Algorithm 4).
  * Readings where the paper is silent are stated at each function in oracle.c.
  *
  * Everything floating-point is IEEE fp64; masses are exact int64 micro-Dalton.
@@ -89,6 +92,19 @@ int64_t orc_scored(const orc_db*, const uint64_t* peak_off_2, const float* mz,
                    const float* intensity, double precursor_mz, int8_t charge,
                    const orc_params*, uint32_t* ids, uint16_t* n_b, uint16_t* n_y,
                    uint32_t* sum_q, uint64_t cap);
+
+/* Partition g of G: the entries whose rank r in the whole database has
+ * r % G == g, in the same order (entry r is entry r / G of its partition).
+ * Returns NULL when g >= G or G == 0. */
+orc_db* orc_db_shard(const orc_db*, uint32_t n_shards, uint32_t shard);
+
+/* Assemble the results of G partition searches of the same n spectra: inputs
+ * part_hits[G][n][top_k] (partition-local ids), part_stats[G][n],
+ * part_hist[G][n][512]; outputs as orc_search (global ids).  Returns 0, or -1
+ * on invalid arguments. */
+int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, const orc_hit* part_hits,
+                 const orc_stat* part_stats, const int32_t* part_hist, orc_hit* hits,
+                 orc_stat* stats, int32_t* hist);
 
 /* Pieces exposed for pin tests. */
 double orc_hyperscore(uint32_t n_b, uint32_t n_y, uint32_t sum_q);

@@ -456,3 +456,75 @@ def test_window_edges_are_inclusive(z):
     for mq in near:
         tol = mq * ppm // 1_000_000
         assert window_of(mq, True, ppm) == int(abs(pep - mq) <= tol), mq
+
+
+# --------------------------------------------------------------------------
+# Partitions and result assembly (Superstep 4; Supplementary Algorithm 4).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("G", [1, 2, 3, 4])
+def test_shards_are_round_robin_slices(G):
+    prot = synth.make_proteome(30, seed=4)
+    mods = oracle.mods_from_synth([synth.OXIDATION])
+    db = oracle.Database(prot.residues, prot.offsets, 1, 6, 25, mods, 1)
+    whole = db.table()
+    parts = [db.shard(G, g).table() for g in range(G)]
+    assert sum(len(p) for p in parts) == len(whole)
+    for g, p in enumerate(parts):
+        assert _same(p, whole[g::G])
+    with pytest.raises(ValueError):
+        db.shard(G, G)
+
+
+def test_assembly_orders_ties_by_global_id_and_adds_counts():
+    """Two hand-made partition results of one spectrum whose whole-database
+    window is ids [1, 7): partition 0 holds the even ids (local 1..3), partition
+    1 the odd ones (local 0..2).  The expected merge is written out by hand: ids
+    map back as local * G + g, equal hyperscores order by the global id, and
+    histograms and counts add bin by bin."""
+    empty = (np.uint32(0xFFFFFFFF), 0, 0, 0, 0, -np.inf)
+    h0 = np.array([[(1, 3, 4, 50, 0, 5.0), (2, 2, 2, 30, 0, 4.0), empty]], oracle.HIT_DTYPE)
+    h1 = np.array([[(0, 4, 3, 60, 0, 5.0), (1, 1, 3, 20, 0, 4.0), (2, 1, 3, 10, 0, 3.0)]], oracle.HIT_DTYPE)
+    s0 = np.zeros(1, oracle.STAT_DTYPE); s1 = np.zeros(1, oracle.STAT_DTYPE)
+    s0["n_window"], s0["n_scored"], s0["lo"], s0["hi"], s0["pairs_total"] = 3, 2, 1, 4, 11
+    s1["n_window"], s1["n_scored"], s1["lo"], s1["hi"], s1["pairs_total"] = 3, 3, 0, 3, 17
+    g0 = np.zeros((1, oracle.HIST_BINS), np.int32); g1 = np.zeros((1, oracle.HIST_BINS), np.int32)
+    g0[0, 40], g0[0, 50] = 1, 1
+    g1[0, 30], g1[0, 40], g1[0, 50] = 1, 1, 1
+    hits, stats, hist = oracle.assemble([h0, h1], [s0, s1], [g0, g1])
+    # (5.0, global 1), (5.0, global 2), (4.0, global 3) beat (4.0, global 4) and (3.0, global 5)
+    assert [int(x) for x in hits[0]["id"]] == [1, 2, 3]
+    assert list(hits[0]["hyperscore"]) == [5.0, 5.0, 4.0]
+    assert [int(x) for x in hits[0]["sum_q"]] == [60, 50, 20]
+    assert int(stats[0]["n_window"]) == 6 and int(stats[0]["n_scored"]) == 5
+    assert int(stats[0]["pairs_total"]) == 28
+    assert (int(stats[0]["lo"]), int(stats[0]["hi"])) == (1, 7)
+    assert int(hist[0, 30]) == 1 and int(hist[0, 40]) == 2 and int(hist[0, 50]) == 2
+    assert int(hist.sum()) == 5
+    # one partition with nothing scored anywhere: no hits, no expect value
+    z = np.zeros(1, oracle.STAT_DTYPE)
+    e = np.array([[empty] * 3], oracle.HIT_DTYPE)
+    g = np.zeros((1, oracle.HIST_BINS), np.int32)
+    hits, stats, _ = oracle.assemble([e, e], [z, z], [g, g])
+    assert int(stats[0]["status"]) == 1 and np.isnan(stats[0]["evalue"])
+    assert all(int(x) == 0xFFFFFFFF for x in hits[0]["id"])
+
+
+@pytest.mark.parametrize("G", [1, 2, 3, 5])
+def test_partitioned_search_assembles_to_the_whole_search(G):
+    """A candidate's shared peaks, hyperscore and histogram bin depend on that
+    candidate alone, and the partitions split the database into disjoint sets, so
+    searching every partition and assembling must reproduce the whole-database
+    search exactly: hits, counts, window ranges, histograms, fit and expect
+    values (the correctness claim behind Superstep 4)."""
+    w = synth.workload("tiny")
+    prot = synth.make_proteome(150, seed=0)
+    mods = oracle.mods_from_synth([synth.OXIDATION])
+    sp = w.spectra(prot, n=40, seed=12)
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, mods, 1)
+    args = (False, 300_000_000, 2, 100, 6, 3)        # +-300 Da open window
+    h, s, g = db.search(sp, *args, threads=4)
+    assert (s["status"] == 0).sum() >= 30            # the fit runs for most spectra
+    parts = [db.shard(G, i).search(sp, *args, threads=4) for i in range(G)]
+    ha, sa, ga = oracle.assemble([p[0] for p in parts], [p[1] for p in parts], [p[2] for p in parts])
+    assert _same(h, ha) and _same(s, sa) and _same(g, ga)
