@@ -63,6 +63,8 @@ extern "C" {
 #define PS_MAX_SEGMENTS 2048     /* top_peaks * max(1, z-1) * probes per peak (2T+1, or 1 on an
                                     index with merged lists) per spectrum */
 
+#define PS_MAX_SHARDS 64          /* database partitions one ps_assemble call merges */
+
 #define PS_SCHED_PLAIN      0    /* one workgroup per spectrum, separate launches */
 #define PS_SCHED_PERSISTENT 1    /* one persistent work-queue launch (hipGraph) */
 
@@ -99,6 +101,12 @@ typedef struct {
                                          search probes one list per peak instead of 2T+1 (same pairs,
                                          Supplementary Text 4); searches on such an index must use
                                          frag_tol_bins == T (else PS_EINVAL).  Postings grow (2T+1)-fold. */
+    uint32_t      n_shards;           /* database partitions G, 1..PS_MAX_SHARDS (0 means 1: the whole database) */
+    uint32_t      shard;              /* this index's partition g < G.  The sorted database is scattered round
+                                         robin (Superstep 1's is_mine, Supplementary Fig. 3): partition g holds
+                                         the entries of whole-database rank r with r % G == g, in order, so its
+                                         id i is whole-database id i * G + g.  Searches of a partition report
+                                         partition ids; ps_assemble turns G partition results into whole ones. */
     const ps_mod* mods;
 } ps_db_params;
 
@@ -244,6 +252,14 @@ int ps_search_device(ps_index* idx, const ps_device* work, const ps_spectra* spe
  * other spectra are still written). */
 int ps_results(ps_batch* batch, ps_hit* hits, ps_stat* stats, int32_t* hist);
 
+/* Device pointers of the batch's results inside its workspace, laid out as
+ * ps_results writes them: hits[n * top_k], stats[n], hist[n * 512] (the
+ * histogram is always kept on the device, whatever want_hist says).  They are
+ * written by the batch's work on its stream, stay valid while the batch and its
+ * device block live, and are the inputs ps_assemble takes.  Any argument may be
+ * NULL. */
+int ps_batch_device_results(ps_batch* batch, ps_hit** hits, ps_stat** stats, int32_t** hist);
+
 /* Every scored candidate (>= min_shared shared peaks) of every spectrum of a
  * finished batch, as (spectrum, id, packed counts).  Only for batches searched
  * with PS_SCHED_PLAIN and `dump` support (ps_search_dump); for parity checks. */
@@ -259,6 +275,35 @@ int ps_batch_timing(ps_batch* batch, double* scan_ms, uint32_t* scan_launches, u
                     uint64_t* bin_lookups);
 
 void ps_batch_free(ps_batch* batch);
+
+/* ---- result assembly over database partitions --------------------------- */
+
+/* The results of one partition's search (all device pointers, partition ids). */
+typedef struct {
+    const ps_hit*  hits;      /* [n * top_k] */
+    const ps_stat* stats;     /* [n] */
+    const int32_t* hist;      /* [n * 512] */
+} ps_part;
+
+/* Result assembly of Superstep 4 (Supplementary Algorithm 4) on the device.
+ * parts[g] holds the results of the same n spectra searched with the same
+ * parameters (top_k included) against partition g of G (ps_db_params.n_shards,
+ * .shard).  Per spectrum, on `stream` (a hipStream_t, NULL = null stream):
+ *   - hist = the bin-wise sum of the partition histograms (the histograms are
+ *     not sampled, so addition needs no shift);
+ *   - hits = the best top_k of all partition hits by (hyperscore desc, id asc),
+ *     ids turned into whole-database ids (i * G + g);
+ *   - stats: n_window and n_scored are the sums; the expect value is fitted on
+ *     the assembled histogram with the best hit's hyperscore, exactly as a search
+ *     of the whole database does; a spectrum any partition reports INVALID or
+ *     OVERFLOW keeps that status with no hits (n_scored 0).
+ * The result equals a whole-database search bit for bit.  Outputs hits[n *
+ * top_k], stats[n] and hist[n * 512] (hist may be NULL) are device memory that
+ * must not overlap the inputs.  Nothing is allocated; returns without waiting.
+ * PS_EINVAL for G outside 1..PS_MAX_SHARDS, top_k outside 1..PS_MAX_TOP_K, or a
+ * NULL input pointer when n > 0. */
+int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts, uint64_t n, uint32_t top_k,
+                ps_hit* hits, ps_stat* stats, int32_t* hist);
 
 /* ---- reusable plans (persistent scan captured as a hipGraph) ------------ */
 
@@ -295,6 +340,10 @@ int ps_plan_results(ps_plan* plan, ps_hit* hits, ps_stat* stats, int32_t* hist);
  * postings streamed, bin lookups and work items of the persistent scan. */
 int ps_plan_timing(ps_plan* plan, double* graph_ms, double* scan_ms, uint64_t* postings, uint64_t* bin_lookups,
                    uint64_t* work_items);
+
+/* Device pointers of the plan's results (as ps_batch_device_results), valid
+ * for the last run once it is done on the plan's stream, until the next run. */
+int ps_plan_device_results(ps_plan* plan, ps_hit** hits, ps_stat** stats, int32_t** hist);
 
 /* The stream the plan runs on. */
 int ps_plan_stream(ps_plan* plan, void** stream);

@@ -41,7 +41,7 @@ class ps_mod(C.Structure):
 class ps_db_params(C.Structure):
     _fields_ = [("missed_cleavages", C.c_uint32), ("min_len", C.c_uint32), ("max_len", C.c_uint32),
                 ("n_mods", C.c_uint32), ("max_mods", C.c_uint32), ("merge_tol_bins", C.c_uint32),
-                ("mods", C.POINTER(ps_mod))]
+                ("n_shards", C.c_uint32), ("shard", C.c_uint32), ("mods", C.POINTER(ps_mod))]
 
 
 class ps_spectra(C.Structure):
@@ -58,6 +58,10 @@ class ps_search_params(C.Structure):
 class ps_schedule(C.Structure):
     _fields_ = [("tile", C.c_uint32), ("tiles_per_item", C.c_uint32), ("groups_per_cu", C.c_uint32),
                 ("reserved", C.c_uint32 * 3)]
+
+
+class ps_part(C.Structure):
+    _fields_ = [("hits", C.c_void_p), ("stats", C.c_void_p), ("hist", C.c_void_p)]
 
 
 class ps_tune_trial(C.Structure):
@@ -77,6 +81,8 @@ STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8
                        ("pad", "<i4")])
 assert HIT_DTYPE.itemsize == 24 and STAT_DTYPE.itemsize == 32
 assert C.sizeof(ps_search_params) == 40
+assert C.sizeof(ps_db_params) == 40
+PS_MAX_SHARDS = 64
 
 _P = C.c_void_p
 _U64P = C.POINTER(C.c_uint64)
@@ -106,6 +112,8 @@ _SIGS = [
     ("ps_results", C.c_int, [_P, _P, _P, _P]),
     ("ps_search_dump", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra), C.POINTER(ps_search_params),
                                  C.c_uint64, _P, _P, _P, _P, _P, _U64P]),
+    ("ps_batch_device_results", C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]),
+    ("ps_assemble", C.c_int, [_P, C.c_uint32, C.POINTER(ps_part), C.c_uint64, C.c_uint32, _P, _P, _P]),
     ("ps_batch_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint32), _U64P, _U64P]),
     ("ps_batch_free", None, [_P]),
     ("ps_plan_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
@@ -116,6 +124,7 @@ _SIGS = [
     ("ps_plan_run_device", C.c_int, [_P, C.c_uint64, C.c_uint64]),
     ("ps_plan_results", C.c_int, [_P, _P, _P, _P]),
     ("ps_plan_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _U64P, _U64P, _U64P]),
+    ("ps_plan_device_results", C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]),
     ("ps_plan_stream", C.c_int, [_P, C.POINTER(_P)]),
     ("ps_plan_free", None, [_P]),
     ("ps_autotune", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra), C.POINTER(ps_search_params),
@@ -189,6 +198,8 @@ ps_search_batch = _fn("ps_search_batch")
 ps_search_device = _fn("ps_search_device")
 ps_results = _fn("ps_results")
 ps_search_dump = _fn("ps_search_dump")
+ps_batch_device_results = _fn("ps_batch_device_results")
+ps_assemble = _fn("ps_assemble")
 ps_batch_timing = _fn("ps_batch_timing")
 ps_batch_free = _fn("ps_batch_free")
 ps_plan_bytes = _fn("ps_plan_bytes")
@@ -198,6 +209,7 @@ ps_plan_inputs = _fn("ps_plan_inputs")
 ps_plan_run_device = _fn("ps_plan_run_device")
 ps_plan_results = _fn("ps_plan_results")
 ps_plan_timing = _fn("ps_plan_timing")
+ps_plan_device_results = _fn("ps_plan_device_results")
 ps_plan_stream = _fn("ps_plan_stream")
 ps_plan_free = _fn("ps_plan_free")
 ps_autotune = _fn("ps_autotune")

@@ -391,6 +391,31 @@ extern "C" int ps_results(ps_batch* B, ps_hit* hits, ps_stat* stats, int32_t* hi
     return PS_OK;
 }
 
+extern "C" int ps_batch_device_results(ps_batch* B, ps_hit** hits, ps_stat** stats, int32_t** hist) {
+    if (!B) return fail(PS_EINVAL, "NULL batch");
+    if (hits) *hits = B->w.hits;
+    if (stats) *stats = B->w.stats;
+    if (hist) *hist = B->w.hist;
+    return PS_OK;
+}
+
+extern "C" int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts, uint64_t n, uint32_t top_k,
+                           ps_hit* hits, ps_stat* stats, int32_t* hist) {
+    if (n_shards < 1 || n_shards > PS_MAX_SHARDS)
+        return fail(PS_EINVAL, "n_shards must be 1..%d", PS_MAX_SHARDS);
+    if (top_k < 1 || top_k > PS_MAX_TOP_K) return fail(PS_EINVAL, "top_k must be 1..%d", PS_MAX_TOP_K);
+    if (n == 0) return PS_OK;
+    if (!parts || !hits || !stats) return fail(PS_EINVAL, "NULL argument");
+    for (uint32_t g = 0; g < n_shards; ++g)
+        if (!parts[g].hits || !parts[g].stats || !parts[g].hist)
+            return fail(PS_EINVAL, "partition %u has a NULL result pointer", g);
+    int rc = require_device();
+    if (rc != PS_OK) return rc;
+    hipError_t e = launch_assemble(parts, n_shards, n, top_k, hits, stats, hist, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(PS_EDEVICE, "assemble: %s", hipGetErrorString(e));
+    return PS_OK;
+}
+
 extern "C" int ps_batch_timing(ps_batch* B, double* scan_ms, uint32_t* launches, uint64_t* postings,
                                uint64_t* lookups) {
     if (!B) return fail(PS_EINVAL, "NULL batch");

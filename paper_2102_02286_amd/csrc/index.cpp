@@ -211,14 +211,26 @@ int index_build_host(ps_index* ix) {
     all.reserve(D);
     for (auto& v : parts) { all.insert(all.end(), v.begin(), v.end()); std::vector<PepRec>().swap(v); }
 
-    // 2. sort by (mass, protein, start, length, mask): id = rank
+    // 2. sort by (mass, protein, start, length, mask): id = rank.  A partition
+    //    keeps the ranks r with r % G == g (round-robin scatter of the sorted
+    //    database); its entry r / G is entry r of the whole.  The longest
+    //    peptide and the heaviest mass are taken over the whole database, so
+    //    counter bounds and bin ranges match an unpartitioned index.
     parallel_sort(all, T);
-    ix->mass.resize(D); ix->prot.resize(D); ix->start.resize(D); ix->len.resize(D); ix->mask.resize(D);
     uint32_t max_len_seen = 0;
+    int64_t max_mass = 0;
     for (uint64_t i = 0; i < D; ++i) {
-        ix->mass[i] = all[i].mass; ix->prot[i] = all[i].prot; ix->start[i] = all[i].start;
-        ix->len[i] = (uint8_t)all[i].len; ix->mask[i] = all[i].mask;
         max_len_seen = std::max(max_len_seen, all[i].len);
+        max_mass = std::max(max_mass, all[i].mass);
+    }
+    const uint64_t G = ix->n_shards, g = ix->shard;
+    const uint64_t D_all = D;
+    D = D_all > g ? (D_all - g + G - 1) / G : 0;
+    ix->mass.resize(D); ix->prot.resize(D); ix->start.resize(D); ix->len.resize(D); ix->mask.resize(D);
+    for (uint64_t i = 0; i < D; ++i) {
+        const PepRec& r = all[i * G + g];
+        ix->mass[i] = r.mass; ix->prot[i] = r.prot; ix->start[i] = r.start;
+        ix->len[i] = (uint8_t)r.len; ix->mask[i] = r.mask;
     }
     std::vector<PepRec>().swap(all);
     ix->max_len_seen = max_len_seen;
@@ -236,8 +248,6 @@ int index_build_host(ps_index* ix) {
     ix->min_residue = minres;
 
     // 3. b/y ion bins, two passes: count per (thread chunk, bin), then scatter in id order
-    int64_t max_mass = D ? ix->mass[D - 1] : 0;
-    for (uint64_t i = 0; i < D; ++i) max_mass = std::max(max_mass, ix->mass[i]);
     uint64_t nbins = (uint64_t)((max_mass + kBinWidth / 2) / kBinWidth) + 2;
     // a fragment bin is carried in 24 bits by the search kernels (167 kDa)
     if (nbins >= (1ull << 24)) return fail(PS_EOVERFLOW, "peptide masses need %llu fragment bins (limit 2^24)",
@@ -417,10 +427,16 @@ extern "C" int ps_index_create(const ps_db_params* params, const char* residues,
         if (residue_uda(residues[i]) < 0)
             return fail(PS_EINVAL, "residue %llu ('%c') is not one of the 20 standard amino acids",
                         (unsigned long long)i, residues[i]);
-    ps_index* ix = new (std::nothrow) ps_index();
-    if (!ix) return fail(PS_ENOMEM, "out of host memory");
     if (params->merge_tol_bins > PS_MAX_FRAG_TOL_BINS)
         return fail(PS_EINVAL, "merge_tol_bins must be 0..%d", PS_MAX_FRAG_TOL_BINS);
+    const uint32_t n_shards = params->n_shards ? params->n_shards : 1u;
+    if (n_shards > PS_MAX_SHARDS || params->shard >= n_shards)
+        return fail(PS_EINVAL, "need shard < n_shards <= %d (got shard %u of %u)", PS_MAX_SHARDS,
+                    params->shard, n_shards);
+    ps_index* ix = new (std::nothrow) ps_index();
+    if (!ix) return fail(PS_ENOMEM, "out of host memory");
+    ix->n_shards = n_shards;
+    ix->shard = params->shard;
     ix->merge_tol = params->merge_tol_bins;
     ix->missed = params->missed_cleavages;
     ix->min_len = params->min_len;

@@ -12,6 +12,8 @@
 //   k_merge    merge of partial top-k lists, Savitzky-Golay smoothed survival
 //              function, linear tail fit and expect value (Superstep 4;
 //              Supplementary Algorithm 4)
+//   k_assemble the same statistics over the results of G database partitions:
+//              histogram addition and a G-way top-k merge first (Superstep 4)
 //
 // Integer work is exact: counters are packed integer fields, the histogram is
 // integer, and hyperscores come from host-built fp64 tables, so results do not
@@ -19,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "internal.h"
 
@@ -1084,13 +1087,103 @@ struct MergeArgs {
     uint32_t per_item;   // 1: partial lists per work item (spec_item0 ranges); 0: one per spectrum
 };
 
+// LDS of the expect-value stage.
+struct EvShared {
+    long long num[kHistBins];
+    long long tail[kHistBins];
+    long long redl[kBlock / 64];
+    double v[5][kBlock / 64];
+    int mode;
+    unsigned long long modekey;
+};
+
+// Expect value of one spectrum (Superstep 4): the histogram hg[512] is smoothed
+// with Savitzky-Golay (-3, 12, 17, 12, -3)/35 (numerators kept exact in
+// integers), turned into a survival function, fitted by least squares in log10
+// from the smoothed mode to the bin below the top hit, and ev = N * 10^(w h1 + b).
+// `status` enters as OK, INVALID, OVERFLOW or NO_HITS; only OK is refined (to
+// FEW_POINTS or BAD_SLOPE).  Every thread of the block calls it; the result is
+// valid in thread 0.  Ends with the block synchronised.
+__device__ void expect_value(const int32_t* hg, unsigned long long N, double h1, int& status, double& ev,
+                             EvShared& S) {
+    const uint32_t tid = threadIdx.x;
+    long long part = 0;
+    for (int j = tid; j < kHistBins; j += kBlock) {
+        long long acc = 0;
+        const int c[5] = {-3, 12, 17, 12, -3};
+        for (int t = -2; t <= 2; ++t) {
+            int i = j + t;
+            if (i >= 0 && i < kHistBins && N) acc += (long long)c[t + 2] * (long long)hg[i];
+        }
+        if (acc < 0) acc = 0;
+        S.num[j] = acc;
+        part += acc;
+    }
+    // total
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
+    if ((tid & 63) == 0) S.redl[tid >> 6] = part;
+    if (tid == 0) S.modekey = 0;
+    __syncthreads();
+    long long total = 0;
+    for (int i = 0; i < kBlock / 64; ++i) total += S.redl[i];
+    // mode: largest numerator, lowest index on ties -> max of (value << 9 | (511 - j))
+    for (int j = tid; j < kHistBins; j += kBlock)
+        atomicMax(&S.modekey, ((unsigned long long)S.num[j] << 9) | (unsigned long long)(kHistBins - 1 - j));
+    __syncthreads();
+    if (tid == 0) {
+        S.mode = kHistBins - 1 - (int)(S.modekey & 511ull);
+        long long run = 0;
+        for (int j = kHistBins - 1; j >= 0; --j) { run += S.num[j]; S.tail[j] = run; }
+    }
+    __syncthreads();
+    ev = __builtin_nan("");
+    // ---- least-squares fit of log10 survival over [mode, bin(H1) - 1]
+    double sx = 0, sy = 0, sxx = 0, sxy = 0, cnt = 0;
+    if (status == PS_STATUS_OK && total > 0) {
+        const double hb = floor(10.0 * h1);
+        const int jh = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
+        for (int j = S.mode + (int)tid; j <= jh - 1; j += kBlock) {
+            const long long t = S.tail[j];
+            if (t <= 0) continue;
+            const double x = 0.1 * (double)j;
+            const double y = log10((double)t / (double)total);
+            sx += x; sy += y; sxx += x * x; sxy += x * y; cnt += 1.0;
+        }
+    }
+    double v[5] = {sx, sy, sxx, sxy, cnt};
+    for (int k = 0; k < 5; ++k) {
+        double x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if ((tid & 63) == 0) S.v[k][tid >> 6] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t[5];
+        for (int k = 0; k < 5; ++k) { t[k] = 0; for (int i = 0; i < kBlock / 64; ++i) t[k] += S.v[k][i]; }
+        if (status == PS_STATUS_OK) {
+            const double n = t[4];
+            if (n < 3.0) {
+                status = PS_STATUS_FEW_POINTS;
+            } else {
+                const double num = n * t[3] - t[0] * t[1];
+                const double den = n * t[2] - t[0] * t[0];
+                const double w = num / den;
+                const double b = (t[1] - w * t[0]) / n;
+                if (!(w < 0.0)) status = PS_STATUS_BAD_SLOPE;
+                else ev = (double)N * pow(10.0, w * h1 + b);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void empty_hit(ps_hit& h) {
+    h.id = 0xFFFFFFFFu; h.n_b = h.n_y = 0; h.sum_q = 0; h.pad = 0; h.hyperscore = -INFINITY;
+}
+
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
-    __shared__ long long s_num[kHistBins];
-    __shared__ long long s_tail[kHistBins];
-    __shared__ long long s_redl[kBlock / 64];
+    __shared__ EvShared S;
     __shared__ ps_hit s_top[PS_MAX_TOP_K];
-    __shared__ int s_mode;
-    __shared__ unsigned long long s_modekey;
     const uint32_t tid = threadIdx.x;
     const uint32_t K = A.kp.top_k;
     const uint64_t n_batch = A.sp.hdr->n;
@@ -1100,10 +1193,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         const bool overflow = (inf.flags & kFlagOverflow) != 0;
         // ---- top-k merge (thread 0, insertion; lists are short)
         if (tid == 0) {
-            for (uint32_t j = 0; j < K; ++j) {
-                s_top[j].id = 0xFFFFFFFFu; s_top[j].n_b = s_top[j].n_y = 0; s_top[j].sum_q = 0;
-                s_top[j].pad = 0; s_top[j].hyperscore = -INFINITY;
-            }
+            for (uint32_t j = 0; j < K; ++j) empty_hit(s_top[j]);
             uint64_t i0 = s, i1 = s + 1;
             if (A.per_item) { i0 = A.w.spec_item0[s]; i1 = A.w.spec_item0[s + 1]; }
             if (!invalid && !overflow) {
@@ -1129,80 +1219,11 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         }
         __syncthreads();
         const unsigned long long N = (invalid || overflow) ? 0ull : A.w.n_scored[s];
-        const double h1 = s_top[0].hyperscore;
-        // ---- Savitzky-Golay (-3, 12, 17, 12, -3)/35 numerators, exact in integers
-        const int32_t* hg = A.w.hist + s * (uint64_t)kHistBins;
-        long long part = 0;
-        for (int j = tid; j < kHistBins; j += kBlock) {
-            long long acc = 0;
-            const int c[5] = {-3, 12, 17, 12, -3};
-            for (int t = -2; t <= 2; ++t) {
-                int i = j + t;
-                if (i >= 0 && i < kHistBins && N) acc += (long long)c[t + 2] * (long long)hg[i];
-            }
-            if (acc < 0) acc = 0;
-            s_num[j] = acc;
-            part += acc;
-        }
-        // total
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
-        if ((tid & 63) == 0) s_redl[tid >> 6] = part;
-        if (tid == 0) s_modekey = 0;
-        __syncthreads();
-        long long total = 0;
-        for (int i = 0; i < kBlock / 64; ++i) total += s_redl[i];
-        // mode: largest numerator, lowest index on ties -> max of (value << 9 | (511 - j))
-        for (int j = tid; j < kHistBins; j += kBlock)
-            atomicMax(&s_modekey, ((unsigned long long)s_num[j] << 9) | (unsigned long long)(kHistBins - 1 - j));
-        __syncthreads();
+        int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
+                   : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
+        double ev;
+        expect_value(A.w.hist + s * (uint64_t)kHistBins, N, s_top[0].hyperscore, status, ev, S);
         if (tid == 0) {
-            s_mode = kHistBins - 1 - (int)(s_modekey & 511ull);
-            long long run = 0;
-            for (int j = kHistBins - 1; j >= 0; --j) { run += s_num[j]; s_tail[j] = run; }
-        }
-        __syncthreads();
-        int status = PS_STATUS_OK;
-        double ev = __builtin_nan("");
-        if (invalid) status = PS_STATUS_INVALID;
-        else if (overflow) status = PS_STATUS_OVERFLOW;
-        else if (N == 0) status = PS_STATUS_NO_HITS;
-        // ---- least-squares fit of log10 survival over [mode, bin(H1) - 1]
-        double sx = 0, sy = 0, sxx = 0, sxy = 0, cnt = 0;
-        if (status == PS_STATUS_OK && total > 0) {
-            const double hb = floor(10.0 * h1);
-            const int jh = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
-            for (int j = s_mode + (int)tid; j <= jh - 1; j += kBlock) {
-                const long long t = s_tail[j];
-                if (t <= 0) continue;
-                const double x = 0.1 * (double)j;
-                const double y = log10((double)t / (double)total);
-                sx += x; sy += y; sxx += x * x; sxy += x * y; cnt += 1.0;
-            }
-        }
-        double v[5] = {sx, sy, sxx, sxy, cnt};
-        __shared__ double s_v[5][kBlock / 64];
-        for (int k = 0; k < 5; ++k) {
-            double x = v[k];
-            for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-            if ((tid & 63) == 0) s_v[k][tid >> 6] = x;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double t[5];
-            for (int k = 0; k < 5; ++k) { t[k] = 0; for (int i = 0; i < kBlock / 64; ++i) t[k] += s_v[k][i]; }
-            if (status == PS_STATUS_OK) {
-                const double n = t[4];
-                if (n < 3.0) {
-                    status = PS_STATUS_FEW_POINTS;
-                } else {
-                    const double num = n * t[3] - t[0] * t[1];
-                    const double den = n * t[2] - t[0] * t[0];
-                    const double w = num / den;
-                    const double b = (t[1] - w * t[0]) / n;
-                    if (!(w < 0.0)) status = PS_STATUS_BAD_SLOPE;
-                    else ev = (double)N * pow(10.0, w * h1 + b);
-                }
-            }
             ps_stat st;
             st.n_window = (invalid) ? 0ull : (unsigned long long)(inf.hi - inf.lo);
             st.n_scored = N;
@@ -1222,6 +1243,120 @@ hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams&
     MergeArgs a{ix, sp, kp, w, per_item ? 1u : 0u};
     uint64_t grid = sp.n < (1u << 20) ? sp.n : (1u << 20);
     hipLaunchKernelGGL(k_merge, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// result assembly over database partitions (Superstep 4; Supplementary
+// Algorithm 4): histogram addition, G-way top-k merge, expect value
+// ---------------------------------------------------------------------------
+
+struct AssembleArgs {
+    ps_part parts[PS_MAX_SHARDS];
+    uint32_t G, K;
+    uint64_t n;
+    ps_hit* hits;
+    ps_stat* stats;
+    int32_t* hist;   // may be NULL
+};
+
+// (h, id) ranks before (h2, id2): hyperscore descending, id ascending
+__device__ __forceinline__ bool ranks_before(double h, uint32_t id, double h2, uint32_t id2) {
+    return h > h2 || (h == h2 && id < id2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
+    __shared__ EvShared S;
+    __shared__ int32_t s_hist[kHistBins];
+    __shared__ ps_hit s_top[PS_MAX_TOP_K];
+    __shared__ unsigned long long s_scored, s_window;
+    __shared__ uint32_t s_flags;
+    const uint32_t tid = threadIdx.x, G = A.G, K = A.K;
+    for (uint64_t s = blockIdx.x; s < A.n; s += gridDim.x) {
+        if (tid == 0) { s_scored = 0; s_window = 0; s_flags = 0; }
+        __syncthreads();
+        for (uint32_t g = tid; g < G; g += kBlock) {
+            const ps_stat st = A.parts[g].stats[s];
+            atomicAdd(&s_scored, st.n_scored);
+            atomicAdd(&s_window, st.n_window);
+            if (st.status == PS_STATUS_INVALID) atomicOr(&s_flags, 1u);
+            if (st.status == PS_STATUS_OVERFLOW) atomicOr(&s_flags, 2u);
+        }
+        // histogram addition: partition histograms share bin 0, so bins add one to one
+        for (uint32_t j = tid; j < (uint32_t)kHistBins; j += kBlock) {
+            int32_t acc = 0;
+            for (uint32_t g = 0; g < G; ++g) acc += A.parts[g].hist[s * (uint64_t)kHistBins + j];
+            s_hist[j] = acc;
+            if (A.hist) A.hist[s * (uint64_t)kHistBins + j] = acc;
+        }
+        __syncthreads();
+        const bool invalid = (s_flags & 1u) != 0, overflow = (s_flags & 2u) != 0;
+        // G-way merge in wavefront 0: lane g holds the head of partition g's list
+        // (already ordered); each round the best head across lanes is taken.
+        if (tid < 64) {
+            const uint32_t g = tid;
+            uint32_t pos = 0;
+            ps_hit head;
+            empty_hit(head);
+            auto load_head = [&]() {
+                empty_hit(head);
+                if (g < G && pos < K && !invalid && !overflow) {
+                    const ps_hit c = A.parts[g].hits[s * K + pos];
+                    if (c.id != 0xFFFFFFFFu) {
+                        head = c;
+                        head.id = (uint32_t)((uint64_t)c.id * G + g);
+                    }
+                }
+            };
+            load_head();
+            for (uint32_t j = 0; j < K; ++j) {
+                double bh = head.hyperscore;
+                uint32_t bid = head.id;
+                uint32_t blane = g;
+                for (int o = 32; o > 0; o >>= 1) {
+                    const double oh = __shfl_xor(bh, o, 64);
+                    const uint32_t oid = __shfl_xor(bid, o, 64);
+                    const uint32_t ol = __shfl_xor(blane, o, 64);
+                    if (ranks_before(oh, oid, bh, bid) || (oh == bh && oid == bid && ol < blane)) {
+                        bh = oh; bid = oid; blane = ol;
+                    }
+                }
+                if (g == blane) {
+                    s_top[j] = head;
+                    ++pos;
+                    load_head();
+                }
+            }
+        }
+        __syncthreads();
+        const unsigned long long N = (invalid || overflow) ? 0ull : s_scored;
+        int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
+                   : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
+        double ev;
+        expect_value(s_hist, N, s_top[0].hyperscore, status, ev, S);
+        if (tid == 0) {
+            ps_stat st;
+            st.n_window = invalid ? 0ull : s_window;
+            st.n_scored = N;
+            st.evalue = ev;
+            st.status = status;
+            st.pad = 0;
+            A.stats[s] = st;
+        }
+        for (uint32_t j = tid; j < K; j += kBlock) A.hits[s * K + j] = s_top[j];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_assemble(const ps_part* parts, uint32_t G, uint64_t n, uint32_t K, ps_hit* hits,
+                           ps_stat* stats, int32_t* hist, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    AssembleArgs a;
+    memset(&a, 0, sizeof a);
+    for (uint32_t g = 0; g < G; ++g) a.parts[g] = parts[g];
+    a.G = G; a.K = K; a.n = n; a.hits = hits; a.stats = stats; a.hist = hist;
+    const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
+    hipLaunchKernelGGL(k_assemble, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

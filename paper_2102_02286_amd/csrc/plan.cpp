@@ -250,6 +250,14 @@ extern "C" int ps_plan_timing(ps_plan* P, double* graph_ms, double* scan_ms, uin
     return PS_OK;
 }
 
+extern "C" int ps_plan_device_results(ps_plan* P, ps_hit** hits, ps_stat** stats, int32_t** hist) {
+    if (!P) return fail(PS_EINVAL, "NULL plan");
+    if (hits) *hits = P->w.hits;
+    if (stats) *stats = P->w.stats;
+    if (hist) *hist = P->w.hist;
+    return PS_OK;
+}
+
 extern "C" int ps_plan_stream(ps_plan* P, void** stream) {
     if (!P || !stream) return fail(PS_EINVAL, "NULL argument");
     *stream = P->stream;

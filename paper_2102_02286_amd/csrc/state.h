@@ -33,10 +33,11 @@ struct ps_index {
     };
     uint32_t missed = 0, min_len = 0, max_len = 0, max_mods = 0;
     uint32_t merge_tol = 0;      // lists of bin b hold the postings of bins b-T..b+T
+    uint32_t n_shards = 1, shard = 0;   // this index holds whole-database ranks r % n_shards == shard
     std::vector<Mod> mods;
     std::vector<char> seq;
     std::vector<uint64_t> prot_off;
-    // entries sorted by (mass, protein, start, length, mask); id = position
+    // entries sorted by (mass, protein, start, length, mask); id = position (in the partition)
     std::vector<int64_t> mass;
     std::vector<uint32_t> prot, start;
     std::vector<uint8_t> len;

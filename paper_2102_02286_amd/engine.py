@@ -31,7 +31,7 @@ def mods_from_synth(mods) -> list[Mod]:
     return [Mod(m.residues, int(round(m.delta_da * 1e6)), m.nterm) for m in mods]
 
 
-def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0):
+def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0, n_shards=1, shard=0):
     arr = (capi.ps_mod * max(1, len(mods)))()
     keep = []
     for i, m in enumerate(mods):
@@ -40,7 +40,7 @@ def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0):
         arr[i].residues = b
         arr[i].nterm = 1 if m.nterm else 0
         arr[i].delta_udalton = int(m.delta_uda)
-    p = capi.ps_db_params(missed, min_len, max_len, len(mods), max_mods, merge_tol, arr)
+    p = capi.ps_db_params(missed, min_len, max_len, len(mods), max_mods, merge_tol, n_shards, shard, arr)
     return p, (arr, keep)
 
 
@@ -55,13 +55,16 @@ class HostIndex:
     """The index built on the host (no GPU needed)."""
 
     def __init__(self, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int, max_len: int,
-                 mods: list, max_mods: int, merge_tol: int = 0):
+                 mods: list, max_mods: int, merge_tol: int = 0, n_shards: int = 1, shard: int = 0):
         """merge_tol = T >= 1 stores, for each bin, the postings of bins b-T..b+T
-        (searches must then use frag_tol_bins == T)."""
+        (searches must then use frag_tol_bins == T).  n_shards = G > 1 keeps only
+        partition `shard` of the sorted database (ranks r with r % G == shard)."""
         self._res = np.ascontiguousarray(residues, dtype=np.uint8)
         self._off = np.ascontiguousarray(offsets, dtype=np.uint64)
         self.merge_tol = int(merge_tol)
-        p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods, self.merge_tol)
+        self.n_shards, self.shard = int(n_shards), int(shard)
+        p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods, self.merge_tol, self.n_shards,
+                                   self.shard)
         h = C.c_void_p()
         check(capi.ps_index_create(C.byref(p), ptr(self._res), ptr(self._off), self._off.shape[0] - 1,
                                    C.byref(h)), "ps_index_create")
@@ -227,6 +230,85 @@ def collect(batch, n: int, params: capi.ps_search_params) -> Results:
     check(capi.ps_batch_timing(batch, C.byref(ms), C.byref(la), C.byref(po), C.byref(lk)), "ps_batch_timing")
     return Results(hits.reshape(n, params.top_k), stats,
                    hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, ms.value, po.value, lk.value)
+
+
+def _device_results(batch):
+    h, st, hg = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    check(capi.ps_batch_device_results(batch, C.byref(h), C.byref(st), C.byref(hg)), "ps_batch_device_results")
+    return capi.ps_part(h.value, st.value, hg.value)
+
+
+class AssembleOut:
+    """Device buffers for assembled results of n spectra (one block, three regions)."""
+
+    def __init__(self, n: int, top_k: int, device: str = "cuda:0"):
+        torch = _torch()
+        self.n, self.k = n, top_k
+        a = lambda b: (b + 255) // 256 * 256
+        self.o_stats = a(n * top_k * capi.HIT_DTYPE.itemsize)
+        self.o_hist = self.o_stats + a(n * capi.STAT_DTYPE.itemsize)
+        self.buf = torch.empty(max(self.o_hist + n * capi.PS_HIST_BINS * 4, 256), dtype=torch.uint8, device=device)
+
+    def pointers(self):
+        b = self.buf.data_ptr()
+        return b, b + self.o_stats, b + self.o_hist
+
+    def to_host(self):
+        n, k = self.n, self.k
+        raw = self.buf.cpu().numpy()
+        hits = raw[:n * k * 24].view(capi.HIT_DTYPE).reshape(n, k).copy()
+        stats = raw[self.o_stats:self.o_stats + n * 32].view(capi.STAT_DTYPE).copy()
+        hist = raw[self.o_hist:self.o_hist + n * capi.PS_HIST_BINS * 4].view(np.int32).reshape(n, capi.PS_HIST_BINS).copy()
+        return hits, stats, hist
+
+
+def assemble(parts, n: int, top_k: int, out: AssembleOut, stream=None):
+    """Enqueue ps_assemble over the partition results `parts` (ps_part list)."""
+    torch = _torch()
+    G = len(parts)
+    arr = (capi.ps_part * max(1, G))(*parts)
+    st = stream if stream is not None else torch.cuda.current_stream(out.buf.device)
+    h, s, g = out.pointers()
+    check(capi.ps_assemble(st.cuda_stream, G, arr, n, top_k, h, s, g), "ps_assemble")
+
+
+def search_partitioned(indexes: list, sp, params: capi.ps_search_params, device: str = "cuda:0") -> Results:
+    """Search each partition index (HostIndex with n_shards = G, shard = g, in
+    order g = 0..G-1) on the same stream, then assemble whole-database results
+    on the device (ps_assemble); blocks until they are on the host."""
+    torch = _torch()
+    G = len(indexes)
+    for g, ix in enumerate(indexes):
+        if ix.n_shards != G or ix.shard != g:
+            raise ValueError(f"index {g} is partition {ix.shard} of {ix.n_shards}, expected {g} of {G}")
+    s, keep = _spectra_struct(sp)
+    nnz = int(sp.peak_off[-1]) if sp.n else 0
+    batches, spaces, parts = [], [], []
+    try:
+        for ix in indexes:
+            need = C.c_uint64()
+            check(capi.ps_workspace_bytes(ix.handle, sp.n, nnz, C.byref(params), C.byref(need)))
+            ws = Workspace(device)
+            dev = ws.get(need.value)
+            b = C.c_void_p()
+            check(capi.ps_search_batch(ix.handle, C.byref(dev), C.byref(s), C.byref(params), C.byref(b)),
+                  "ps_search_batch")
+            batches.append(b)
+            spaces.append(ws)
+            parts.append(_device_results(b))
+        out = AssembleOut(sp.n, params.top_k, device)
+        assemble(parts, sp.n, params.top_k, out)
+        torch.cuda.current_stream(out.buf.device).synchronize()
+        hits, stats, hist = out.to_host()
+        scan_ms = postings = lookups = 0
+        for b in batches:
+            ms, la, po, lk = C.c_double(), C.c_uint32(), C.c_uint64(), C.c_uint64()
+            check(capi.ps_batch_timing(b, C.byref(ms), C.byref(la), C.byref(po), C.byref(lk)))
+            scan_ms += ms.value; postings += po.value; lookups += lk.value
+        return Results(hits, stats, hist, scan_ms, postings, lookups)
+    finally:
+        for b in batches:
+            capi.ps_batch_free(b)
 
 
 def search_dump(index: HostIndex, sp, params: capi.ps_search_params, cap: int = 1 << 22,

@@ -32,7 +32,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     assert C.sizeof(capi.ps_device) == 24
     assert C.sizeof(capi.ps_mod) == 24
-    assert C.sizeof(capi.ps_db_params) == 32
+    assert C.sizeof(capi.ps_db_params) == 40
+    assert C.sizeof(capi.ps_part) == 24
     assert C.sizeof(capi.ps_spectra) == 48
     assert C.sizeof(capi.ps_search_params) == 40
     assert capi.HIT_DTYPE.itemsize == 24 and capi.STAT_DTYPE.itemsize == 32
@@ -214,3 +215,50 @@ def test_merged_lists_are_neighbour_unions(T):
     assert capi.ps_workspace_bytes(merged.handle, 10, 100, C.byref(right), C.byref(need)) == capi.PS_OK
     with pytest.raises(capi.PsError):
         engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, mods, 2, merge_tol=5)
+
+
+@pytest.mark.parametrize("G,T", [(2, 0), (3, 0), (3, 2)])
+def test_partition_index_is_a_round_robin_slice(G, T):
+    """Partition g of G holds whole-database entries g, g + G, ... in order; its
+    postings are the whole index's postings of those entries with ids divided by
+    G, bin by bin, over the same bin range (merged lists included)."""
+    prot = synth.make_proteome(40, seed=5)
+    mods = engine.mods_from_synth([synth.OXIDATION])
+    whole = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, mods, 1, merge_tol=T)
+    ow, pw = whole.host_arrays()
+    n_whole = len(whole)
+    total_post = 0
+    for g in range(G):
+        part = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, mods, 1, merge_tol=T, n_shards=G, shard=g)
+        n_pep, n_post, n_bins = part.shape()
+        assert n_pep == len(range(g, n_whole, G)) and n_bins == whole.shape()[2]
+        for i in list(range(min(n_pep, 50))) + [n_pep - 1]:
+            assert part.entry(i) == whole.entry(i * G + g)
+        op, pp = part.host_arrays()
+        total_post += n_post
+        for bn in range(0, n_bins, 7):
+            w = pw[ow[bn]:ow[bn + 1]]
+            ids = w >> 1
+            keep = w[ids % G == g]
+            want = ((keep >> 1) // G) << 1 | (keep & 1)
+            assert np.array_equal(pp[op[bn]:op[bn + 1]], want.astype(np.uint32)), (g, bn)
+    assert total_post == pw.shape[0]
+
+
+def test_partition_and_assemble_argument_checks_without_device():
+    ok = synth.Proteome(np.frombuffer(b"PEPTIDEKAAAAR", np.uint8).copy(), np.array([0, 13], np.uint64))
+    for G, g in [(2, 2), (65, 0)]:
+        with pytest.raises(capi.PsError) as e:
+            engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [], 0, n_shards=G, shard=g)
+        assert e.value.code == capi.PS_EINVAL
+    # a partition with no entries at all is valid
+    empty = engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [], 0, n_shards=64, shard=63)
+    assert len(empty) == 0
+    parts = (capi.ps_part * 2)()
+    assert capi.ps_assemble(None, 0, parts, 1, 5, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 65, parts, 1, 5, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 2, parts, 1, 0, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 2, parts, 1, 17, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 2, parts, 1, 5, 1, 1, 1) == capi.PS_EINVAL     # NULL partition pointers
+    assert "partition 0" in capi.last_error()
+    assert capi.ps_assemble(None, 2, parts, 0, 5, None, None, None) == capi.PS_OK  # nothing to do
