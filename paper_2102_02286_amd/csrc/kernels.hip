@@ -1089,72 +1089,90 @@ struct MergeArgs {
 
 // LDS of the expect-value stage.
 struct EvShared {
-    long long num[kHistBins];
-    long long tail[kHistBins];
-    long long redl[kBlock / 64];
-    double v[5][kBlock / 64];
-    int mode;
-    unsigned long long modekey;
+    long long wsum[kBlock / 64];            // per wavefront: sum of smoothed numerators
+    unsigned long long wkey[kBlock / 64];   // per wavefront: best mode key
+    double v[5][kBlock / 64];               // per wavefront: least-squares sums
 };
 
 // Expect value of one spectrum (Superstep 4): the histogram hg[512] is smoothed
 // with Savitzky-Golay (-3, 12, 17, 12, -3)/35 (numerators kept exact in
-// integers), turned into a survival function, fitted by least squares in log10
-// from the smoothed mode to the bin below the top hit, and ev = N * 10^(w h1 + b).
-// `status` enters as OK, INVALID, OVERFLOW or NO_HITS; only OK is refined (to
-// FEW_POINTS or BAD_SLOPE).  Every thread of the block calls it; the result is
-// valid in thread 0.  Ends with the block synchronised.
+// integers, negatives set to 0), turned into a survival function, fitted by
+// least squares in log10 from the smoothed mode (lowest bin on ties) to the bin
+// below the top hit, and ev = N * 10^(w h1 + b).  Thread t owns bins 2t and
+// 2t + 1; the survival sums come from a suffix scan across the block.  `status`
+// enters as OK, INVALID, OVERFLOW or NO_HITS; only OK is refined (to FEW_POINTS
+// or BAD_SLOPE).  Every thread of the block calls it; the result is valid in
+// thread 0.  Ends with the block synchronised.
 __device__ void expect_value(const int32_t* hg, unsigned long long N, double h1, int& status, double& ev,
                              EvShared& S) {
-    const uint32_t tid = threadIdx.x;
-    long long part = 0;
-    for (int j = tid; j < kHistBins; j += kBlock) {
+    static_assert(kHistBins == 2 * kBlock, "two histogram bins per thread");
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    long long num[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int j = 2 * (int)tid + u;
         long long acc = 0;
-        const int c[5] = {-3, 12, 17, 12, -3};
-        for (int t = -2; t <= 2; ++t) {
-            int i = j + t;
-            if (i >= 0 && i < kHistBins && N) acc += (long long)c[t + 2] * (long long)hg[i];
+        if (N) {
+            const int c[5] = {-3, 12, 17, 12, -3};
+#pragma unroll
+            for (int t = -2; t <= 2; ++t) {
+                const int i = j + t;
+                if (i >= 0 && i < kHistBins) acc += (long long)c[t + 2] * (long long)hg[i];
+            }
         }
-        if (acc < 0) acc = 0;
-        S.num[j] = acc;
-        part += acc;
+        num[u] = acc < 0 ? 0 : acc;
     }
-    // total
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
-    if ((tid & 63) == 0) S.redl[tid >> 6] = part;
-    if (tid == 0) S.modekey = 0;
-    __syncthreads();
-    long long total = 0;
-    for (int i = 0; i < kBlock / 64; ++i) total += S.redl[i];
-    // mode: largest numerator, lowest index on ties -> max of (value << 9 | (511 - j))
-    for (int j = tid; j < kHistBins; j += kBlock)
-        atomicMax(&S.modekey, ((unsigned long long)S.num[j] << 9) | (unsigned long long)(kHistBins - 1 - j));
-    __syncthreads();
-    if (tid == 0) {
-        S.mode = kHistBins - 1 - (int)(S.modekey & 511ull);
-        long long run = 0;
-        for (int j = kHistBins - 1; j >= 0; --j) { run += S.num[j]; S.tail[j] = run; }
+    const long long pair = num[0] + num[1];
+    // suffix sum over the lanes of this wavefront: lanes >= lane
+    long long suf = pair;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long v = __shfl_down(suf, o, 64);
+        if (lane + (uint32_t)o < 64u) suf += v;
     }
+    // mode: largest numerator, lowest bin on ties -> max of (value << 9 | (511 - j))
+    const unsigned long long k0 = ((unsigned long long)num[0] << 9) | (unsigned long long)(kHistBins - 1 - 2 * (int)tid);
+    const unsigned long long k1 = ((unsigned long long)num[1] << 9) | (unsigned long long)(kHistBins - 2 - 2 * (int)tid);
+    unsigned long long key = k0 > k1 ? k0 : k1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long v = __shfl_xor(key, o, 64);
+        key = v > key ? v : key;
+    }
+    if (lane == 0) { S.wsum[wv] = suf; S.wkey[wv] = key; }
     __syncthreads();
+    long long total = 0, later = 0;
+    unsigned long long mkey = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        total += S.wsum[w];
+        if (w > (int)wv) later += S.wsum[w];
+        mkey = S.wkey[w] > mkey ? S.wkey[w] : mkey;
+    }
+    const int mode = kHistBins - 1 - (int)(mkey & 511ull);
+    const long long above = suf - pair + later;              // smoothed mass of bins > 2t + 1
+    const long long tail[2] = {pair + above, num[1] + above};
     ev = __builtin_nan("");
     // ---- least-squares fit of log10 survival over [mode, bin(H1) - 1]
     double sx = 0, sy = 0, sxx = 0, sxy = 0, cnt = 0;
     if (status == PS_STATUS_OK && total > 0) {
         const double hb = floor(10.0 * h1);
         const int jh = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
-        for (int j = S.mode + (int)tid; j <= jh - 1; j += kBlock) {
-            const long long t = S.tail[j];
-            if (t <= 0) continue;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int j = 2 * (int)tid + u;
+            if (j < mode || j > jh - 1 || tail[u] <= 0) continue;
             const double x = 0.1 * (double)j;
-            const double y = log10((double)t / (double)total);
+            const double y = log10((double)tail[u] / (double)total);
             sx += x; sy += y; sxx += x * x; sxy += x * y; cnt += 1.0;
         }
     }
     double v[5] = {sx, sy, sxx, sxy, cnt};
+#pragma unroll
     for (int k = 0; k < 5; ++k) {
         double x = v[k];
         for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-        if ((tid & 63) == 0) S.v[k][tid >> 6] = x;
+        if (lane == 0) S.v[k][wv] = x;
     }
     __syncthreads();
     if (tid == 0) {
@@ -1165,9 +1183,9 @@ __device__ void expect_value(const int32_t* hg, unsigned long long N, double h1,
             if (n < 3.0) {
                 status = PS_STATUS_FEW_POINTS;
             } else {
-                const double num = n * t[3] - t[0] * t[1];
+                const double num_w = n * t[3] - t[0] * t[1];
                 const double den = n * t[2] - t[0] * t[0];
-                const double w = num / den;
+                const double w = num_w / den;
                 const double b = (t[1] - w * t[0]) / n;
                 if (!(w < 0.0)) status = PS_STATUS_BAD_SLOPE;
                 else ev = (double)N * pow(10.0, w * h1 + b);
@@ -1181,9 +1199,59 @@ __device__ __forceinline__ void empty_hit(ps_hit& h) {
     h.id = 0xFFFFFFFFu; h.n_b = h.n_y = 0; h.sum_q = 0; h.pad = 0; h.hyperscore = -INFINITY;
 }
 
+// Keys of the lists being merged, staged in LDS (up to kMergeCap entries).
+constexpr uint32_t kMergeCap = 1024;
+struct TopShared {
+    double h[kMergeCap];
+    uint32_t id[kMergeCap];
+    ps_hit top[PS_MAX_TOP_K];
+};
+
+// Top k of the union of L lists of k entries, each ordered by (hyperscore
+// desc, id asc) with empty entries (id UINT32_MAX) last, into T.top.  An
+// entry's place in the union is its position in its own list plus, for every
+// other list, the number of entries there that rank before it (a binary
+// search); ids are distinct, so places are distinct.  key(c) gives (hyperscore,
+// id) of entry c = list * k + position; emit(c, place) writes entry c to
+// T.top[place].  Every thread calls it; ends with the block synchronised.
+template <typename Key, typename Emit>
+__device__ void merge_sorted_lists(uint32_t L, uint32_t k, TopShared& T, Key key, Emit emit) {
+    const uint32_t tid = threadIdx.x, M = L * k;
+    const bool staged = M <= kMergeCap;
+    if (tid < k) empty_hit(T.top[tid]);
+    if (staged)
+        for (uint32_t c = tid; c < M; c += kBlock) key(c, T.h[c], T.id[c]);
+    __syncthreads();
+    auto get = [&](uint32_t c, double& h, uint32_t& id) {
+        if (staged) { h = T.h[c]; id = T.id[c]; } else { key(c, h, id); }
+    };
+    for (uint32_t c = tid; c < M; c += kBlock) {
+        double h;
+        uint32_t id;
+        get(c, h, id);
+        if (id == 0xFFFFFFFFu) continue;
+        const uint32_t a = c / k;
+        uint32_t place = c - a * k;
+        for (uint32_t b = 0; b < L && place < k; ++b) {
+            if (b == a) continue;
+            uint32_t lo = 0, hi = k;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                double xh;
+                uint32_t xid;
+                get(b * k + mid, xh, xid);
+                if (better_hit(xh, xid, h, id)) lo = mid + 1; else hi = mid;
+            }
+            place += lo;
+        }
+        if (place < k) emit(c, place);
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     __shared__ EvShared S;
-    __shared__ ps_hit s_top[PS_MAX_TOP_K];
+    __shared__ TopShared T;
     const uint32_t tid = threadIdx.x;
     const uint32_t K = A.kp.top_k;
     const uint64_t n_batch = A.sp.hdr->n;
@@ -1191,38 +1259,19 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         const SpecInfo inf = A.w.info[s];
         const bool invalid = (inf.flags & kFlagInvalid) != 0;
         const bool overflow = (inf.flags & kFlagOverflow) != 0;
-        // ---- top-k merge (thread 0, insertion; lists are short)
-        if (tid == 0) {
-            for (uint32_t j = 0; j < K; ++j) empty_hit(s_top[j]);
-            uint64_t i0 = s, i1 = s + 1;
-            if (A.per_item) { i0 = A.w.spec_item0[s]; i1 = A.w.spec_item0[s + 1]; }
-            if (!invalid && !overflow) {
-                for (uint64_t it = i0; it < i1; ++it) {
-                    const ps_hit* src = A.w.partial + it * K;
-                    for (uint32_t j = 0; j < K; ++j) {
-                        ps_hit c = src[j];
-                        if (c.id == 0xFFFFFFFFu) break;
-                        // insert into s_top (sorted by hyperscore desc, id asc)
-                        if (!(c.hyperscore > s_top[K - 1].hyperscore ||
-                              (c.hyperscore == s_top[K - 1].hyperscore && c.id < s_top[K - 1].id)))
-                            continue;
-                        int p = (int)K - 1;
-                        while (p > 0 && (c.hyperscore > s_top[p - 1].hyperscore ||
-                                         (c.hyperscore == s_top[p - 1].hyperscore && c.id < s_top[p - 1].id))) {
-                            s_top[p] = s_top[p - 1];
-                            --p;
-                        }
-                        s_top[p] = c;
-                    }
-                }
-            }
-        }
-        __syncthreads();
+        // ---- top-k of the spectrum's partial lists (one per work item, each sorted)
+        uint64_t i0 = s, i1 = s + 1;
+        if (A.per_item) { i0 = A.w.spec_item0[s]; i1 = A.w.spec_item0[s + 1]; }
+        const uint32_t L = (invalid || overflow) ? 0u : (uint32_t)(i1 - i0);
+        const ps_hit* src = A.w.partial + i0 * K;
+        merge_sorted_lists(L, K, T,
+            [&](uint32_t c, double& h, uint32_t& id) { h = src[c].hyperscore; id = src[c].id; },
+            [&](uint32_t c, uint32_t place) { T.top[place] = src[c]; });
         const unsigned long long N = (invalid || overflow) ? 0ull : A.w.n_scored[s];
         int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
                    : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
         double ev;
-        expect_value(A.w.hist + s * (uint64_t)kHistBins, N, s_top[0].hyperscore, status, ev, S);
+        expect_value(A.w.hist + s * (uint64_t)kHistBins, N, T.top[0].hyperscore, status, ev, S);
         if (tid == 0) {
             ps_stat st;
             st.n_window = (invalid) ? 0ull : (unsigned long long)(inf.hi - inf.lo);
@@ -1232,7 +1281,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
             st.pad = 0;
             A.w.stats[s] = st;
         }
-        for (uint32_t j = tid; j < K; j += kBlock) A.w.hits[s * K + j] = s_top[j];
+        for (uint32_t j = tid; j < K; j += kBlock) A.w.hits[s * K + j] = T.top[j];
         __syncthreads();
     }
 }
@@ -1260,15 +1309,10 @@ struct AssembleArgs {
     int32_t* hist;   // may be NULL
 };
 
-// (h, id) ranks before (h2, id2): hyperscore descending, id ascending
-__device__ __forceinline__ bool ranks_before(double h, uint32_t id, double h2, uint32_t id2) {
-    return h > h2 || (h == h2 && id < id2);
-}
-
 __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
     __shared__ EvShared S;
+    __shared__ TopShared T;
     __shared__ int32_t s_hist[kHistBins];
-    __shared__ ps_hit s_top[PS_MAX_TOP_K];
     __shared__ unsigned long long s_scored, s_window;
     __shared__ uint32_t s_flags;
     const uint32_t tid = threadIdx.x, G = A.G, K = A.K;
@@ -1291,49 +1335,22 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
         }
         __syncthreads();
         const bool invalid = (s_flags & 1u) != 0, overflow = (s_flags & 2u) != 0;
-        // G-way merge in wavefront 0: lane g holds the head of partition g's list
-        // (already ordered); each round the best head across lanes is taken.
-        if (tid < 64) {
-            const uint32_t g = tid;
-            uint32_t pos = 0;
-            ps_hit head;
-            empty_hit(head);
-            auto load_head = [&]() {
-                empty_hit(head);
-                if (g < G && pos < K && !invalid && !overflow) {
-                    const ps_hit c = A.parts[g].hits[s * K + pos];
-                    if (c.id != 0xFFFFFFFFu) {
-                        head = c;
-                        head.id = (uint32_t)((uint64_t)c.id * G + g);
-                    }
-                }
-            };
-            load_head();
-            for (uint32_t j = 0; j < K; ++j) {
-                double bh = head.hyperscore;
-                uint32_t bid = head.id;
-                uint32_t blane = g;
-                for (int o = 32; o > 0; o >>= 1) {
-                    const double oh = __shfl_xor(bh, o, 64);
-                    const uint32_t oid = __shfl_xor(bid, o, 64);
-                    const uint32_t ol = __shfl_xor(blane, o, 64);
-                    if (ranks_before(oh, oid, bh, bid) || (oh == bh && oid == bid && ol < blane)) {
-                        bh = oh; bid = oid; blane = ol;
-                    }
-                }
-                if (g == blane) {
-                    s_top[j] = head;
-                    ++pos;
-                    load_head();
-                }
-            }
-        }
-        __syncthreads();
+        // top-k of the partitions' lists, ids turned into whole-database ids
+        auto hit_at = [&](uint32_t c) -> const ps_hit& {
+            const uint32_t g = c / K;
+            return A.parts[g].hits[s * K + (c - g * K)];
+        };
+        auto whole_id = [&](uint32_t c, uint32_t id) -> uint32_t {
+            return id == 0xFFFFFFFFu ? id : (uint32_t)((uint64_t)id * G + c / K);
+        };
+        merge_sorted_lists((invalid || overflow) ? 0u : G, K, T,
+            [&](uint32_t c, double& h, uint32_t& id) { const ps_hit& x = hit_at(c); h = x.hyperscore; id = whole_id(c, x.id); },
+            [&](uint32_t c, uint32_t place) { ps_hit x = hit_at(c); x.id = whole_id(c, x.id); T.top[place] = x; });
         const unsigned long long N = (invalid || overflow) ? 0ull : s_scored;
         int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
                    : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
         double ev;
-        expect_value(s_hist, N, s_top[0].hyperscore, status, ev, S);
+        expect_value(s_hist, N, T.top[0].hyperscore, status, ev, S);
         if (tid == 0) {
             ps_stat st;
             st.n_window = invalid ? 0ull : s_window;
@@ -1343,7 +1360,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
             st.pad = 0;
             A.stats[s] = st;
         }
-        for (uint32_t j = tid; j < K; j += kBlock) A.hits[s * K + j] = s_top[j];
+        for (uint32_t j = tid; j < K; j += kBlock) A.hits[s * K + j] = T.top[j];
         __syncthreads();
     }
 }
