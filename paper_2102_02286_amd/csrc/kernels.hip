@@ -183,6 +183,32 @@ hipError_t launch_fill_per_spectrum(void* p, uint32_t value, uint64_t per, uint6
 // prep: one workgroup per spectrum
 // ---------------------------------------------------------------------------
 
+// First index i in [0, n) with mass[i] >= v (upper = false) or mass[i] > v
+// (upper = true), n if none: a 64-ary search by one wavefront.  Each round the
+// 64 lanes probe evenly spaced positions of the remaining range [a, b) and the
+// ballot of "still below" narrows it about 64-fold, so a few dependent loads
+// replace the ~22 of a binary search.  Call with the whole wavefront active.
+__device__ uint64_t wave_bound(const int64_t* mass, uint64_t n, int64_t v, bool upper) {
+    const uint64_t lane = threadIdx.x & 63u;
+    uint64_t a = 0, b = n;
+    while (a < b) {
+        const uint64_t step = (b - a + 63) / 64;
+        const uint64_t i = a + (lane + 1) * step - 1;
+        bool below = false;
+        if (i < b) {
+            const int64_t m = mass[i];
+            below = upper ? (m <= v) : (m < v);
+        }
+        const uint64_t c = (uint64_t)__popcll(__ballot(below));
+        const uint64_t na = a + c * step;
+        if (step == 1) return na;                       // every position was probed
+        const uint64_t cap = a + (c + 1) * step - 1;    // probe c failed (or lies beyond b)
+        a = na;
+        b = cap < b ? cap : b;
+    }
+    return a;
+}
+
 struct PrepArgs {
     DevIndex ix;
     DevSpectra sp;
@@ -196,6 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
     __shared__ uint32_t s_ent[PS_MAX_TOP_PEAKS * (PS_MAX_CHARGE - 1)];
     __shared__ uint32_t s_flag, s_imax_bits, s_mult;
     __shared__ unsigned long long s_red[kBlock / 64];
+    __shared__ uint64_t s_win[2];
     const uint32_t tid = threadIdx.x;
     const KParams& kp = A.kp;
 
@@ -204,6 +231,16 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         const uint64_t p0 = A.sp.peak_off[s], p1 = A.sp.peak_off[s + 1];
         const int z = A.sp.charge[s];
         const double prec = A.sp.prec[s];
+        // filter_1: ids with |M - M_q| <= dM  ->  [lo, hi), searched by wavefronts 0 and 1
+        // while the others start on the peaks
+        const bool prec_ok = z >= 1 && z <= (int)kp.max_charge && prec > 0.0 && prec <= 1e6;
+        const int64_t mq = prec_ok ? (int64_t)z * (round_half_up_pos(prec * 1e6) - kProtonUda) : -1;
+        const int64_t dm = mq < 0 ? 0 : kp.window_is_ppm ? (mq * kp.window) / 1000000 : kp.window;
+        if ((tid >> 6) < 2) {
+            const bool hi_side = (tid >> 6) == 1;
+            const uint64_t r = mq < 0 ? 0 : wave_bound(A.ix.mass, A.ix.n_pep, hi_side ? mq + dm : mq - dm, hi_side);
+            if ((tid & 63u) == 0) s_win[hi_side ? 1 : 0] = r;
+        }
         if (tid == 0) {
             uint32_t bad = 0;
             if (!(p1 >= p0) || p1 - p0 > PS_MAX_PEAKS_IN || p1 > nnz_batch) bad = 1;
@@ -291,20 +328,11 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
             inf.flags = bad ? kFlagInvalid : 0u;
             inf.lo = inf.hi = 0;
             if (!bad) {
-                const int64_t prec_uda = round_half_up_pos(prec * 1e6);
-                const int64_t mq = (int64_t)z * (prec_uda - kProtonUda);
                 if (mq < 0) {
                     inf.flags = kFlagInvalid;
                 } else {
-                    const int64_t dm = kp.window_is_ppm ? (mq * kp.window) / 1000000 : kp.window;
-                    // filter_1: ids with |M - M_q| <= dM  ->  [lo, hi)
-                    const int64_t lo_m = mq - dm, hi_m = mq + dm;
-                    uint64_t a = 0, b = A.ix.n_pep;
-                    while (a < b) { uint64_t mid = (a + b) >> 1; if (A.ix.mass[mid] < lo_m) a = mid + 1; else b = mid; }
-                    inf.lo = (uint32_t)a;
-                    b = A.ix.n_pep;
-                    while (a < b) { uint64_t mid = (a + b) >> 1; if (A.ix.mass[mid] <= hi_m) a = mid + 1; else b = mid; }
-                    inf.hi = (uint32_t)a;
+                    inf.lo = (uint32_t)s_win[0];
+                    inf.hi = (uint32_t)s_win[1];
                     // worst-case field values for any candidate of this spectrum
                     const uint64_t nvalid = tot & 0xFFFFFFFFull, sq = tot >> 32;
                     const uint64_t width = (uint64_t)(2 * kp.tol + 1) * (uint64_t)kBinWidth;
