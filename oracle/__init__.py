@@ -34,7 +34,11 @@ def build(force: bool = True) -> str:
 
 class Params(C.Structure):
     _fields_ = [("window_is_ppm", C.c_int32), ("window", C.c_int64), ("frag_tol_bins", C.c_int32),
-                ("top_peaks", C.c_uint32), ("top_k", C.c_uint32), ("min_shared", C.c_uint32)]
+                ("top_peaks", C.c_uint32), ("top_k", C.c_uint32), ("min_shared", C.c_uint32),
+                ("fit", C.c_int32)]
+
+
+FIT_TAIL, FIT_GUMBEL = 0, 1
 
 
 HIT_DTYPE = np.dtype([("id", "<u4"), ("n_b", "<u2"), ("n_y", "<u2"), ("sum_q", "<u4"),
@@ -71,12 +75,14 @@ def lib():
         L.orc_db_shard.restype = P
         L.orc_db_shard.argtypes = [P, C.c_uint32, C.c_uint32]
         L.orc_assemble.restype = C.c_int
-        L.orc_assemble.argtypes = [C.c_uint32, C.c_uint64, C.c_uint32, P, P, P, P, P, P]
+        L.orc_assemble.argtypes = [C.c_uint32, C.c_uint64, C.c_uint32, C.c_int32, P, P, P, P, P, P]
         L.orc_hyperscore.restype = C.c_double
         L.orc_hyperscore.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
         L.orc_sg_smooth.argtypes = [P, P]
         L.orc_evalue.restype = C.c_int
         L.orc_evalue.argtypes = [P, C.c_double, C.c_uint64, P, P, P, P]
+        L.orc_evalue_gumbel.restype = C.c_int
+        L.orc_evalue_gumbel.argtypes = [P, C.c_double, C.c_uint64, P, P, P, P]
         _lib = L
     return _lib
 
@@ -155,10 +161,11 @@ class Database:
         return buf[:n].copy()
 
     def search(self, sp, window_is_ppm: bool, window: int, frag_tol_bins: int, top_peaks: int,
-               top_k: int = 5, min_shared: int = 4, threads: int | None = None, want_hist=True):
+               top_k: int = 5, min_shared: int = 4, threads: int | None = None, want_hist=True,
+               fit: int = FIT_TAIL):
         n = sp.n
         prm = Params(int(window_is_ppm), int(window), int(frag_tol_bins), int(top_peaks), int(top_k),
-                     int(min_shared))
+                     int(min_shared), int(fit))
         hits = np.zeros(n * top_k, dtype=HIT_DTYPE)
         stats = np.zeros(n, dtype=STAT_DTYPE)
         hist = np.zeros(n * HIST_BINS, dtype=np.int32) if want_hist else None
@@ -175,7 +182,7 @@ class Database:
     def scored(self, sp, s: int, window_is_ppm: bool, window: int, frag_tol_bins: int,
                top_peaks: int, min_shared: int = 4, cap: int = 1 << 22):
         prm = Params(int(window_is_ppm), int(window), int(frag_tol_bins), int(top_peaks), 1,
-                     int(min_shared))
+                     int(min_shared), FIT_TAIL)
         ids = np.zeros(cap, np.uint32); nb = np.zeros(cap, np.uint16)
         ny = np.zeros(cap, np.uint16); sq = np.zeros(cap, np.uint32)
         off2 = np.ascontiguousarray(sp.peak_off[s:s + 2], np.uint64)
@@ -190,7 +197,7 @@ class Database:
         return ids[:k].copy(), nb[:k].copy(), ny[:k].copy(), sq[:k].copy()
 
 
-def assemble(part_hits, part_stats, part_hist):
+def assemble(part_hits, part_stats, part_hist, fit: int = FIT_TAIL):
     """Assemble G partition results (lists indexed by partition g, each as
     returned by Database.search on Database.shard(G, g)) into whole-database
     results: (hits[n, k], stats[n], hist[n, 512])."""
@@ -202,7 +209,8 @@ def assemble(part_hits, part_stats, part_hist):
     hits = np.zeros(n * k, HIT_DTYPE)
     stats = np.zeros(n, STAT_DTYPE)
     hist = np.zeros(n * HIST_BINS, np.int32)
-    rc = lib().orc_assemble(G, n, k, _ptr(ph), _ptr(ps), _ptr(pg), _ptr(hits), _ptr(stats), _ptr(hist))
+    rc = lib().orc_assemble(G, n, k, int(fit), _ptr(ph), _ptr(ps), _ptr(pg), _ptr(hits), _ptr(stats),
+                            _ptr(hist))
     if rc != 0:
         raise ValueError("oracle rejected the assembly arguments")
     return hits.reshape(n, k), stats, hist.reshape(n, HIST_BINS)
@@ -227,6 +235,15 @@ def sg_smooth(hist: np.ndarray) -> np.ndarray:
     out = np.zeros(HIST_BINS, np.float64)
     lib().orc_sg_smooth(_ptr(h), _ptr(out))
     return out
+
+
+def evalue_gumbel(hist: np.ndarray, top_h: float, n_scored: int):
+    h = np.ascontiguousarray(hist, dtype=np.int32)
+    ev, mu, beta = C.c_double(), C.c_double(), C.c_double()
+    npts = C.c_int32()
+    st = lib().orc_evalue_gumbel(_ptr(h), float(top_h), int(n_scored), C.byref(ev), C.byref(mu), C.byref(beta),
+                                 C.byref(npts))
+    return st, ev.value, mu.value, beta.value, npts.value
 
 
 def evalue(hist: np.ndarray, top_h: float, n_scored: int):

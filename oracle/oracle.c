@@ -314,6 +314,51 @@ int orc_evalue(const int32_t* hist, double top_h, uint64_t n_scored,
     return 0;
 }
 
+/* log-Weibull (Gumbel) fit (Superstep 4; Supplementary Algorithm 4 names it
+ * next to the tail fit) and expect value.  Reading: the Gumbel location mu and
+ * scale beta come from the moments of the smoothed histogram hs, each bin j
+ * standing at its centre x_j = 0.1 j + 0.05: mean m = sum hs x / sum hs, variance
+ * v = sum hs (x - m)^2 / sum hs, beta = sqrt(6 v) / pi, mu = m - gamma * beta
+ * (gamma = Euler-Mascheroni).  ev = N * S(H1) with the Gumbel survival
+ * S(h) = 1 - exp(-exp(-(h - mu) / beta)).  Returns 0 ok, 1 nothing scored, 2
+ * fewer than 3 bins of hs above zero. */
+int orc_evalue_gumbel(const int32_t* hist, double top_h, uint64_t n_scored,
+                      double* evalue, double* mu, double* beta, int32_t* n_points) {
+    static const double kEulerGamma = 0.57721566490153286061;
+    static const double kPi = 3.14159265358979323846;
+    *evalue = NAN; *mu = NAN; *beta = NAN; *n_points = 0;
+    if (n_scored == 0) return 1;
+    double hs[ORC_HIST_BINS];
+    orc_sg_smooth(hist, hs);
+    double w = 0.0, wx = 0.0;
+    int n = 0;
+    for (int j = 0; j < ORC_HIST_BINS; ++j) {
+        if (hs[j] > 0.0) ++n;
+        w += hs[j];
+        wx += hs[j] * (0.1 * (double)j + 0.05);
+    }
+    *n_points = n;
+    if (n < 3) return 2;
+    double m = wx / w;
+    double v = 0.0;
+    for (int j = 0; j < ORC_HIST_BINS; ++j) {
+        double d = (0.1 * (double)j + 0.05) - m;
+        v += hs[j] * d * d;
+    }
+    v = v / w;
+    double b = sqrt(6.0 * v) / kPi;
+    *beta = b;
+    *mu = m - kEulerGamma * b;
+    *evalue = (double)n_scored * -expm1(-exp(-(top_h - *mu) / b));
+    return 0;
+}
+
+static int expect_value(int32_t fit, const int32_t* hist, double top_h, uint64_t n_scored, double* ev) {
+    double a, b; int32_t npts;
+    if (fit == ORC_FIT_GUMBEL) return orc_evalue_gumbel(hist, top_h, n_scored, ev, &a, &b, &npts);
+    return orc_evalue(hist, top_h, n_scored, ev, &a, &b, &npts);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Search (Supplementary Algorithm 3).                                        */
 /* ------------------------------------------------------------------------ */
@@ -477,9 +522,8 @@ static int search_one(job* J) {
     J->stat->n_scored = n_scored;
     J->stat->pairs_total = pairs_total;
     if (J->hist) memcpy(J->hist, local_hist, sizeof local_hist);
-    double w, b; int32_t npts;
     double top = n_scored ? J->hits[0].hyperscore : 0.0;     /* k >= 1 is enforced */
-    J->stat->status = orc_evalue(local_hist, top, n_scored, &J->stat->evalue, &w, &b, &npts);
+    J->stat->status = expect_value(P->fit, local_hist, top, n_scored, &J->stat->evalue);
     return 0;
 }
 
@@ -508,6 +552,7 @@ static void* work_loop(void* arg) {
 
 static int params_ok(const orc_params* P) {
     return P->top_k >= 1 && P->top_k <= 64 && P->min_shared >= 1 && P->frag_tol_bins >= 0 &&
+           (P->fit == ORC_FIT_TAIL || P->fit == ORC_FIT_GUMBEL) &&
            P->window >= 0 && P->top_peaks >= 1;
 }
 
@@ -590,14 +635,14 @@ static int hit_order_cmp(const void* a, const void* b) {
  *   2. every partial top hit, with its id turned back into the global id
  *      (local * G + g), goes into one list ordered by (hyperscore desc,
  *      id asc), of which the first k are kept (the max-heap);
- *   3. the fit and expect value of orc_evalue run on the assembled histogram
+ *   3. the fit and expect value (orc_evalue or orc_evalue_gumbel) run on the assembled histogram
  *      with the best hit's hyperscore and N = the summed scored counts.
  * Window sizes and shared-pair totals add; the window id range is recovered
  * from the partitions' ranges.  Inputs are laid out [G][n][...]. */
-int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, const orc_hit* part_hits,
+int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, int32_t fit, const orc_hit* part_hits,
                  const orc_stat* part_stats, const int32_t* part_hist, orc_hit* hits,
                  orc_stat* stats, int32_t* hist) {
-    if (n_shards == 0 || top_k < 1 || top_k > 64) return -1;
+    if (n_shards == 0 || top_k < 1 || top_k > 64 || (fit != ORC_FIT_TAIL && fit != ORC_FIT_GUMBEL)) return -1;
     const uint64_t G = n_shards;
     orc_hit* pool = (orc_hit*)malloc((size_t)G * top_k * sizeof(orc_hit));
     int32_t dist[ORC_HIST_BINS];
@@ -635,9 +680,8 @@ int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, const orc_hit* p
             out[i].id = UINT32_MAX; out[i].n_b = 0; out[i].n_y = 0;
             out[i].sum_q = 0; out[i].pad = 0; out[i].hyperscore = -INFINITY;
         }
-        double w, b; int32_t npts;
         double top = st.n_scored ? out[0].hyperscore : 0.0;
-        st.status = orc_evalue(dist, top, st.n_scored, &st.evalue, &w, &b, &npts);
+        st.status = expect_value(fit, dist, top, st.n_scored, &st.evalue);
         stats[s] = st;
         if (hist) memcpy(hist + s * ORC_HIST_BINS, dist, sizeof dist);
     }

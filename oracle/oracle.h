@@ -16,7 +16,8 @@
  *     per Supplementary Text 4), hyperscore, top hits (Supplementary Algorithm 3),
  *     a score histogram (Sampling section: the 2048-byte local null
  *     distribution), Savitzky-Golay smoothing, linear tail fit and expect value
- *     (Superstep 4; Supplementary Algorithm 4);
+ *     (Superstep 4; Supplementary Algorithm 4), or a log-Weibull (Gumbel) fit
+ *     by moments in its place (Superstep 4 names both);
  *   - partitions and result assembly: round-robin database partitions and the
  *     histogram addition plus top-hit merge of Superstep 4 (Supplementary
  *     Algorithm 4).
@@ -57,6 +58,9 @@ uint32_t orc_db_residue_masses(const orc_db*, uint64_t id, int64_t* out, uint32_
 /* b_i and y_i, i = 1..n-1, of a residue-mass sequence (uDa). */
 void orc_ions(const int64_t* res_uda, uint32_t n, int64_t* b_out, int64_t* y_out);
 
+#define ORC_FIT_TAIL   0   /* linear tail fit of the log survival function */
+#define ORC_FIT_GUMBEL 1   /* log-Weibull (Gumbel) fit */
+
 typedef struct {
     int32_t  window_is_ppm;   /* 1: window in ppm of the precursor mass; 0: uDa */
     int64_t  window;
@@ -64,6 +68,7 @@ typedef struct {
     uint32_t top_peaks;       /* B */
     uint32_t top_k;           /* k <= 64 */
     uint32_t min_shared;      /* k_min */
+    int32_t  fit;             /* ORC_FIT_TAIL or ORC_FIT_GUMBEL */
 } orc_params;
 
 typedef struct {
@@ -102,7 +107,7 @@ orc_db* orc_db_shard(const orc_db*, uint32_t n_shards, uint32_t shard);
  * part_hits[G][n][top_k] (partition-local ids), part_stats[G][n],
  * part_hist[G][n][512]; outputs as orc_search (global ids).  Returns 0, or -1
  * on invalid arguments. */
-int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, const orc_hit* part_hits,
+int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, int32_t fit, const orc_hit* part_hits,
                  const orc_stat* part_stats, const int32_t* part_hist, orc_hit* hits,
                  orc_stat* stats, int32_t* hist);
 
@@ -111,6 +116,8 @@ double orc_hyperscore(uint32_t n_b, uint32_t n_y, uint32_t sum_q);
 void   orc_sg_smooth(const int32_t* hist, double* out);          /* 512 -> 512 */
 int    orc_evalue(const int32_t* hist, double top_h, uint64_t n_scored,
                   double* evalue, double* slope, double* intercept, int32_t* n_points);
+int    orc_evalue_gumbel(const int32_t* hist, double top_h, uint64_t n_scored,
+                         double* evalue, double* mu, double* beta, int32_t* n_points);
 
 #ifdef __cplusplus
 }

@@ -528,3 +528,95 @@ def test_partitioned_search_assembles_to_the_whole_search(G):
     parts = [db.shard(G, i).search(sp, *args, threads=4) for i in range(G)]
     ha, sa, ga = oracle.assemble([p[0] for p in parts], [p[1] for p in parts], [p[2] for p in parts])
     assert _same(h, ha) and _same(s, sa) and _same(g, ga)
+
+
+# --------------------------------------------------------------------------
+# log-Weibull (Gumbel) fit (Superstep 4; Supplementary Algorithm 4).
+# --------------------------------------------------------------------------
+
+def _gumbel_hist(mu, beta, total):
+    """Counts of `total` scores drawn exactly from Gumbel(mu, beta), binned as
+    the search bins hyperscores: bin j = [0.1 j, 0.1 (j + 1)), the last bin open."""
+    from scipy.stats import gumbel_r
+    edges = 0.1 * np.arange(oracle.HIST_BINS + 1)
+    cdf = gumbel_r.cdf(edges, loc=mu, scale=beta)
+    cdf[-1] = 1.0
+    return np.round(total * np.diff(cdf)).astype(np.int32)
+
+
+@pytest.mark.parametrize("mu,beta", [(20.0, 2.0), (12.5, 0.8), (24.0, 3.0)])
+def test_gumbel_fit_recovers_location_and_scale(mu, beta):
+    """On a histogram of an exact Gumbel(mu, beta) the moment fit returns mu and
+    beta up to binning (a few 1e-3), and the expect value is N times the Gumbel
+    survival function of scipy at the fitted parameters."""
+    from scipy.stats import gumbel_r
+    h = _gumbel_hist(mu, beta, 10**8)
+    N = int(h.sum())
+    top = mu + 6 * beta
+    st, ev, m, b, npts = oracle.evalue_gumbel(h, top, N)
+    assert st == 0 and npts > 30
+    assert abs(m - mu) < 5e-3 and abs(b - beta) < 5e-3 * beta
+    assert ev == pytest.approx(N * gumbel_r.sf(top, loc=m, scale=b), rel=1e-12)
+    # far tail: the survival still carries full relative precision
+    st, ev_far, _, _, _ = oracle.evalue_gumbel(h, mu + 40 * beta, N)
+    assert ev_far == pytest.approx(N * gumbel_r.sf(mu + 40 * beta, loc=m, scale=b), rel=1e-12)
+
+
+def test_gumbel_moments_equal_numpy_moments_of_the_smoothed_histogram():
+    """The fit is the moment fit of the (independently pinned) smoothed
+    histogram: compare with numpy moments over bin centres.  Mass at bin 0 makes
+    the zero padding and the clamping of the smoothing matter, and because the
+    quadratic Savitzky-Golay window keeps the first two moments, the raw
+    histogram of a smooth interior distribution gives the same answer."""
+    k_gamma = 0.5772156649015329
+    x = 0.1 * np.arange(oracle.HIST_BINS) + 0.05
+    for h in [np.bincount([0, 0, 0, 1, 1, 5, 5, 9], minlength=oracle.HIST_BINS).astype(np.int32) * 10,
+              _gumbel_hist(25.0, 3.0, 10**7)]:
+        hs = oracle.sg_smooth(h)
+        m = np.sum(hs * x) / np.sum(hs)
+        v = np.sum(hs * (x - m) ** 2) / np.sum(hs)
+        beta = np.sqrt(6 * v) / np.pi
+        st, ev, mu_f, beta_f, _ = oracle.evalue_gumbel(h, 3.0, 1000)
+        assert st == 0
+        assert mu_f == pytest.approx(m - k_gamma * beta, rel=1e-12) and beta_f == pytest.approx(beta, rel=1e-12)
+    # interior (no mass near either end): smoothing keeps the moments of the raw histogram
+    h = _gumbel_hist(20.0, 2.0, 10**7)
+    m0 = np.sum(h * x) / h.sum()
+    v0 = np.sum(h * (x - m0) ** 2) / h.sum()
+    _, _, mu_f, beta_f, _ = oracle.evalue_gumbel(h, 30.0, int(h.sum()))
+    # (up to the few sparse tail bins where smoothing goes negative and is clamped)
+    assert beta_f == pytest.approx(np.sqrt(6 * v0) / np.pi, rel=2e-5)
+    assert mu_f == pytest.approx(m0 - k_gamma * np.sqrt(6 * v0) / np.pi, rel=2e-5)
+
+
+def test_gumbel_special_cases():
+    h = np.zeros(oracle.HIST_BINS, np.int32)
+    assert oracle.evalue_gumbel(h, 1.0, 0)[0] == 1                       # nothing scored
+    h[0] = 5                                                             # smoothed: bins 0 and 1 only
+    st, ev, _, _, npts = oracle.evalue_gumbel(h, 1.0, 5)
+    assert st == 2 and npts == 2 and np.isnan(ev)
+    h[0], h[100] = 0, 7                                                  # one bin spreads to three
+    st, ev, mu, beta, npts = oracle.evalue_gumbel(h, 10.05, 7)
+    assert st == 0 and npts == 3 and mu < 10.05 < mu + 3 * beta and 0 < ev < 7
+
+
+def test_search_and_assembly_with_the_gumbel_fit():
+    """The fit is chosen per search; both fits see the same histogram, and the
+    partitioned search assembles to the whole one with either."""
+    w = synth.workload("tiny")
+    prot = synth.make_proteome(150, seed=0)
+    sp = w.spectra(prot, n=30, seed=12)
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, [], 0)
+    args = (False, 300_000_000, 2, 100, 6, 3)
+    ht, st, gt = db.search(sp, *args, threads=4)
+    hg, sg, gg = db.search(sp, *args, threads=4, fit=oracle.FIT_GUMBEL)
+    assert _same(ht, hg) and _same(gt, gg)
+    ok = sg["status"] == 0
+    assert ok.sum() >= 25
+    for s in np.nonzero(ok)[0][:10]:
+        want = oracle.evalue_gumbel(gg[s], ht[s, 0]["hyperscore"], int(st[s]["n_scored"]))[1]
+        assert sg[s]["evalue"] == want
+    parts = [db.shard(3, i).search(sp, *args, threads=4, fit=oracle.FIT_GUMBEL) for i in range(3)]
+    ha, sa, ga = oracle.assemble([p[0] for p in parts], [p[1] for p in parts], [p[2] for p in parts],
+                                 fit=oracle.FIT_GUMBEL)
+    assert _same(hg, ha) and _same(sg, sa) and _same(gg, ga)
