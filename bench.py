@@ -178,7 +178,7 @@ def assembly_leg(capi, engine, torch, w, prot, merge, G, dsp, n, nnz, prm, ref, 
         pp = [engine._device_results(b) for b in batches]
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        engine.assemble(pp, n, prm.top_k, out, stream)
+        engine.assemble(pp, n, prm.top_k, out, stream, fit=prm.fit)
         e1.record(stream)
         for b in batches:
             capi.ps_batch_free(b)

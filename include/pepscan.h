@@ -65,6 +65,9 @@ extern "C" {
 
 #define PS_MAX_SHARDS 64          /* database partitions one ps_assemble call merges */
 
+#define PS_FIT_TAIL   0          /* linear fit of the log survival function's tail (Superstep 4) */
+#define PS_FIT_GUMBEL 1          /* log-Weibull (Gumbel) fit by moments (Superstep 4) */
+
 #define PS_SCHED_PLAIN      0    /* one workgroup per spectrum, separate launches */
 #define PS_SCHED_PERSISTENT 1    /* one persistent work-queue launch (hipGraph) */
 
@@ -133,6 +136,14 @@ typedef struct {
                                  the workspace (fragment charges 1..max(1, z-1) per spectrum) */
     int32_t  schedule;        /* PS_SCHED_PLAIN or PS_SCHED_PERSISTENT */
     int32_t  want_hist;       /* 1: keep per-spectrum histograms for ps_results */
+    int32_t  fit;             /* expect-value model on the smoothed histogram (Superstep 4 names both):
+                                 PS_FIT_TAIL: least-squares line through log10 of the survival function
+                                 from the mode to the bin below the top hit, ev = N * 10^(w H1 + b);
+                                 PS_FIT_GUMBEL: Gumbel location and scale from the mean and variance of
+                                 the histogram (bin centres 0.1 j + 0.05), ev = N * S(H1) with
+                                 S(h) = 1 - exp(-exp(-(h - mu) / beta)); fewer than 3 non-zero smoothed
+                                 bins gives PS_STATUS_FEW_POINTS */
+    int32_t  reserved;        /* must be 0 */
 } ps_search_params;
 
 /* One reported candidate.  id = rank of the peptide in the index's sort order
@@ -301,8 +312,9 @@ typedef struct {
  * top_k], stats[n] and hist[n * 512] (hist may be NULL) are device memory that
  * must not overlap the inputs.  Nothing is allocated; returns without waiting.
  * PS_EINVAL for G outside 1..PS_MAX_SHARDS, top_k outside 1..PS_MAX_TOP_K, or a
- * NULL input pointer when n > 0. */
-int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts, uint64_t n, uint32_t top_k,
+ * NULL input pointer when n > 0.  `fit` is the ps_search_params.fit of the
+ * partition searches. */
+int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts, uint64_t n, uint32_t top_k, int32_t fit,
                 ps_hit* hits, ps_stat* stats, int32_t* hist);
 
 /* ---- reusable plans (persistent scan captured as a hipGraph) ------------ */

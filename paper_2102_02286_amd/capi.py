@@ -19,6 +19,7 @@ PS_STATUS_OK, PS_STATUS_NO_HITS, PS_STATUS_FEW_POINTS, PS_STATUS_BAD_SLOPE, PS_S
     PS_STATUS_OVERFLOW = 0, 1, 2, 3, 4, 5
 PS_HIST_BINS = 512
 PS_SCHED_PLAIN, PS_SCHED_PERSISTENT = 0, 1
+PS_FIT_TAIL, PS_FIT_GUMBEL = 0, 1
 
 _ERR_NAMES = {1: "PS_EINVAL", 2: "PS_ENOMEM", 3: "PS_EAGAIN", 4: "PS_EDEVICE", 5: "PS_EOVERFLOW"}
 
@@ -52,7 +53,8 @@ class ps_spectra(C.Structure):
 class ps_search_params(C.Structure):
     _fields_ = [("window_is_ppm", C.c_int32), ("frag_tol_bins", C.c_int32), ("window", C.c_int64),
                 ("top_peaks", C.c_uint32), ("top_k", C.c_uint32), ("min_shared", C.c_uint32),
-                ("max_charge", C.c_uint32), ("schedule", C.c_int32), ("want_hist", C.c_int32)]
+                ("max_charge", C.c_uint32), ("schedule", C.c_int32), ("want_hist", C.c_int32),
+                ("fit", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ps_schedule(C.Structure):
@@ -80,7 +82,7 @@ HIT_DTYPE = np.dtype([("id", "<u4"), ("n_b", "<u2"), ("n_y", "<u2"), ("sum_q", "
 STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8"), ("status", "<i4"),
                        ("pad", "<i4")])
 assert HIT_DTYPE.itemsize == 24 and STAT_DTYPE.itemsize == 32
-assert C.sizeof(ps_search_params) == 40
+assert C.sizeof(ps_search_params) == 48
 assert C.sizeof(ps_db_params) == 40
 PS_MAX_SHARDS = 64
 
@@ -113,7 +115,7 @@ _SIGS = [
     ("ps_search_dump", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra), C.POINTER(ps_search_params),
                                  C.c_uint64, _P, _P, _P, _P, _P, _U64P]),
     ("ps_batch_device_results", C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]),
-    ("ps_assemble", C.c_int, [_P, C.c_uint32, C.POINTER(ps_part), C.c_uint64, C.c_uint32, _P, _P, _P]),
+    ("ps_assemble", C.c_int, [_P, C.c_uint32, C.POINTER(ps_part), C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P]),
     ("ps_batch_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint32), _U64P, _U64P]),
     ("ps_batch_free", None, [_P]),
     ("ps_plan_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),

@@ -72,6 +72,8 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
         return fail(PS_EINVAL, "max_charge must be 1..%d", PS_MAX_CHARGE);
     if (p->schedule != PS_SCHED_PLAIN && p->schedule != PS_SCHED_PERSISTENT)
         return fail(PS_EINVAL, "unknown schedule %d", p->schedule);
+    if (p->fit != PS_FIT_TAIL && p->fit != PS_FIT_GUMBEL) return fail(PS_EINVAL, "unknown fit %d", p->fit);
+    if (p->reserved != 0) return fail(PS_EINVAL, "reserved must be 0");
     const uint32_t cmax = p->max_charge > 2 ? p->max_charge - 1 : 1;
     const uint64_t stride = (uint64_t)p->top_peaks * cmax;
     if (ix && ix->merge_tol && (uint32_t)p->frag_tol_bins != ix->merge_tol)
@@ -92,6 +94,7 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
     kp->max_charge = p->max_charge;
     kp->ent_stride = (uint32_t)stride;
     kp->seg_cap = (uint32_t)segs;
+    kp->fit = p->fit;
     int rc = check_schedule(*sched);
     if (rc != PS_OK) return rc;
     if (ix && sched->tile < (1u << ix->dir_shift))
@@ -400,10 +403,11 @@ extern "C" int ps_batch_device_results(ps_batch* B, ps_hit** hits, ps_stat** sta
 }
 
 extern "C" int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts, uint64_t n, uint32_t top_k,
-                           ps_hit* hits, ps_stat* stats, int32_t* hist) {
+                           int32_t fit, ps_hit* hits, ps_stat* stats, int32_t* hist) {
     if (n_shards < 1 || n_shards > PS_MAX_SHARDS)
         return fail(PS_EINVAL, "n_shards must be 1..%d", PS_MAX_SHARDS);
     if (top_k < 1 || top_k > PS_MAX_TOP_K) return fail(PS_EINVAL, "top_k must be 1..%d", PS_MAX_TOP_K);
+    if (fit != PS_FIT_TAIL && fit != PS_FIT_GUMBEL) return fail(PS_EINVAL, "unknown fit %d", fit);
     if (n == 0) return PS_OK;
     if (!parts || !hits || !stats) return fail(PS_EINVAL, "NULL argument");
     for (uint32_t g = 0; g < n_shards; ++g)
@@ -411,7 +415,7 @@ extern "C" int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts
             return fail(PS_EINVAL, "partition %u has a NULL result pointer", g);
     int rc = require_device();
     if (rc != PS_OK) return rc;
-    hipError_t e = launch_assemble(parts, n_shards, n, top_k, hits, stats, hist, (hipStream_t)stream);
+    hipError_t e = launch_assemble(parts, n_shards, n, top_k, fit, hits, stats, hist, (hipStream_t)stream);
     if (e != hipSuccess) return fail(PS_EDEVICE, "assemble: %s", hipGetErrorString(e));
     return PS_OK;
 }

@@ -85,6 +85,7 @@ struct KParams {
     uint32_t seg_cap;          // probe slots per workgroup (entries x bin offsets)
     uint32_t tile;             // candidates per LDS counter tile: a power of two, >= 1 << dir_shift
     uint32_t tile_shift;       // log2(tile)
+    int32_t fit;               // PS_FIT_TAIL or PS_FIT_GUMBEL
 };
 
 // Workspace pointers of one batch (all inside the caller's device block).
@@ -128,7 +129,7 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
                                   hipStream_t stream);
 hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
                         bool per_item, hipStream_t stream);
-hipError_t launch_assemble(const ps_part* parts, uint32_t n_shards, uint64_t n, uint32_t top_k, ps_hit* hits,
+hipError_t launch_assemble(const ps_part* parts, uint32_t n_shards, uint64_t n, uint32_t top_k, int32_t fit, ps_hit* hits,
                            ps_stat* stats, int32_t* hist, hipStream_t stream);
 size_t scan_lds_bytes(const KParams& kp, bool wide);
 hipError_t init_kernel_attributes();

@@ -1119,8 +1119,55 @@ struct MergeArgs {
 struct EvShared {
     long long wsum[kBlock / 64];            // per wavefront: sum of smoothed numerators
     unsigned long long wkey[kBlock / 64];   // per wavefront: best mode key
-    double v[5][kBlock / 64];               // per wavefront: least-squares sums
+    double v[5][kBlock / 64];               // per wavefront: least-squares sums (Gumbel: moments)
 };
+
+// Sum of x over the block, valid in every thread; uses S.v[k].  Has barriers.
+__device__ __forceinline__ double block_sum_f64(double x, int k, EvShared& S) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if ((threadIdx.x & 63u) == 0) S.v[k][threadIdx.x >> 6] = x;
+    __syncthreads();
+    double t = 0;
+    for (int i = 0; i < kBlock / 64; ++i) t += S.v[k][i];
+    return t;
+}
+
+// log-Weibull (Gumbel) fit by moments of the smoothed histogram (numerators
+// num[u] of bins 2t + u; the common factor 1/35 cancels): mean m and variance v
+// over bin centres x_j = 0.1 j + 0.05, beta = sqrt(6 v) / pi,
+// mu = m - gamma beta, ev = N * (1 - exp(-exp(-(h1 - mu) / beta))).  Fewer than
+// 3 non-zero bins: FEW_POINTS.  Result valid in thread 0.
+__device__ void gumbel_fit(const long long num[2], long long total, unsigned long long N, double h1, int& status,
+                           double& ev, EvShared& S) {
+    const uint32_t tid = threadIdx.x;
+    double wx = 0, pts = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const double x = 0.1 * (double)(2 * (int)tid + u) + 0.05;
+        wx += (double)num[u] * x;
+        pts += num[u] > 0 ? 1.0 : 0.0;
+    }
+    const double swx = block_sum_f64(wx, 0, S);
+    const double n_pts = block_sum_f64(pts, 1, S);
+    const double m = swx / (double)total;
+    double d2 = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const double d = (0.1 * (double)(2 * (int)tid + u) + 0.05) - m;
+        d2 += (double)num[u] * d * d;
+    }
+    const double sd2 = block_sum_f64(d2, 2, S);
+    if (tid == 0 && status == PS_STATUS_OK) {
+        if (n_pts < 3.0) {
+            status = PS_STATUS_FEW_POINTS;
+        } else {
+            const double v = sd2 / (double)total;
+            const double beta = sqrt(6.0 * v) / 3.14159265358979323846;
+            const double mu = m - 0.57721566490153286061 * beta;
+            ev = (double)N * -expm1(-exp(-(h1 - mu) / beta));
+        }
+    }
+}
 
 // Expect value of one spectrum (Superstep 4): the histogram hg[512] is smoothed
 // with Savitzky-Golay (-3, 12, 17, 12, -3)/35 (numerators kept exact in
@@ -1131,7 +1178,7 @@ struct EvShared {
 // enters as OK, INVALID, OVERFLOW or NO_HITS; only OK is refined (to FEW_POINTS
 // or BAD_SLOPE).  Every thread of the block calls it; the result is valid in
 // thread 0.  Ends with the block synchronised.
-__device__ void expect_value(const int32_t* hg, unsigned long long N, double h1, int& status, double& ev,
+__device__ void expect_value(const int32_t* hg, unsigned long long N, double h1, int fit, int& status, double& ev,
                              EvShared& S) {
     static_assert(kHistBins == 2 * kBlock, "two histogram bins per thread");
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
@@ -1181,6 +1228,14 @@ __device__ void expect_value(const int32_t* hg, unsigned long long N, double h1,
     const long long above = suf - pair + later;              // smoothed mass of bins > 2t + 1
     const long long tail[2] = {pair + above, num[1] + above};
     ev = __builtin_nan("");
+    if (fit == PS_FIT_GUMBEL) {
+        if (status == PS_STATUS_OK) {                   // uniform: status and total are block-wide
+            if (total > 0) gumbel_fit(num, total, N, h1, status, ev, S);
+            else status = PS_STATUS_FEW_POINTS;
+        }
+        __syncthreads();
+        return;
+    }
     // ---- least-squares fit of log10 survival over [mode, bin(H1) - 1]
     double sx = 0, sy = 0, sxx = 0, sxy = 0, cnt = 0;
     if (status == PS_STATUS_OK && total > 0) {
@@ -1299,7 +1354,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
                    : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
         double ev;
-        expect_value(A.w.hist + s * (uint64_t)kHistBins, N, T.top[0].hyperscore, status, ev, S);
+        expect_value(A.w.hist + s * (uint64_t)kHistBins, N, T.top[0].hyperscore, A.kp.fit, status, ev, S);
         if (tid == 0) {
             ps_stat st;
             st.n_window = (invalid) ? 0ull : (unsigned long long)(inf.hi - inf.lo);
@@ -1331,6 +1386,7 @@ hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams&
 struct AssembleArgs {
     ps_part parts[PS_MAX_SHARDS];
     uint32_t G, K;
+    int32_t fit;
     uint64_t n;
     ps_hit* hits;
     ps_stat* stats;
@@ -1378,7 +1434,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
         int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
                    : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
         double ev;
-        expect_value(s_hist, N, T.top[0].hyperscore, status, ev, S);
+        expect_value(s_hist, N, T.top[0].hyperscore, A.fit, status, ev, S);
         if (tid == 0) {
             ps_stat st;
             st.n_window = invalid ? 0ull : s_window;
@@ -1393,13 +1449,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
     }
 }
 
-hipError_t launch_assemble(const ps_part* parts, uint32_t G, uint64_t n, uint32_t K, ps_hit* hits,
+hipError_t launch_assemble(const ps_part* parts, uint32_t G, uint64_t n, uint32_t K, int32_t fit, ps_hit* hits,
                            ps_stat* stats, int32_t* hist, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     AssembleArgs a;
     memset(&a, 0, sizeof a);
     for (uint32_t g = 0; g < G; ++g) a.parts[g] = parts[g];
-    a.G = G; a.K = K; a.n = n; a.hits = hits; a.stats = stats; a.hist = hist;
+    a.G = G; a.K = K; a.fit = fit; a.n = n; a.hits = hits; a.stats = stats; a.hist = hist;
     const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
     hipLaunchKernelGGL(k_assemble, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();

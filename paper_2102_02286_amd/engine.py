@@ -46,9 +46,9 @@ def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0, n_shards=1
 
 def search_params(window_is_ppm: bool, window: int, frag_tol_bins: int, top_peaks: int, top_k: int = 5,
                   min_shared: int = 4, max_charge: int = 8, schedule: int = capi.PS_SCHED_PLAIN,
-                  want_hist: bool = True) -> capi.ps_search_params:
+                  want_hist: bool = True, fit: int = capi.PS_FIT_TAIL) -> capi.ps_search_params:
     return capi.ps_search_params(int(window_is_ppm), int(frag_tol_bins), int(window), int(top_peaks), int(top_k),
-                                 int(min_shared), int(max_charge), int(schedule), int(bool(want_hist)))
+                                 int(min_shared), int(max_charge), int(schedule), int(bool(want_hist)), int(fit), 0)
 
 
 class HostIndex:
@@ -262,14 +262,14 @@ class AssembleOut:
         return hits, stats, hist
 
 
-def assemble(parts, n: int, top_k: int, out: AssembleOut, stream=None):
+def assemble(parts, n: int, top_k: int, out: AssembleOut, stream=None, fit: int = capi.PS_FIT_TAIL):
     """Enqueue ps_assemble over the partition results `parts` (ps_part list)."""
     torch = _torch()
     G = len(parts)
     arr = (capi.ps_part * max(1, G))(*parts)
     st = stream if stream is not None else torch.cuda.current_stream(out.buf.device)
     h, s, g = out.pointers()
-    check(capi.ps_assemble(st.cuda_stream, G, arr, n, top_k, h, s, g), "ps_assemble")
+    check(capi.ps_assemble(st.cuda_stream, G, arr, n, top_k, int(fit), h, s, g), "ps_assemble")
 
 
 def search_partitioned(indexes: list, sp, params: capi.ps_search_params, device: str = "cuda:0") -> Results:
@@ -297,7 +297,7 @@ def search_partitioned(indexes: list, sp, params: capi.ps_search_params, device:
             spaces.append(ws)
             parts.append(_device_results(b))
         out = AssembleOut(sp.n, params.top_k, device)
-        assemble(parts, sp.n, params.top_k, out)
+        assemble(parts, sp.n, params.top_k, out, fit=params.fit)
         torch.cuda.current_stream(out.buf.device).synchronize()
         hits, stats, hist = out.to_host()
         scan_ms = postings = lookups = 0

@@ -35,7 +35,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(capi.ps_db_params) == 40
     assert C.sizeof(capi.ps_part) == 24
     assert C.sizeof(capi.ps_spectra) == 48
-    assert C.sizeof(capi.ps_search_params) == 40
+    assert C.sizeof(capi.ps_search_params) == 48
     assert capi.HIT_DTYPE.itemsize == 24 and capi.STAT_DTYPE.itemsize == 32
 
 
@@ -126,7 +126,8 @@ def test_search_params_validation_without_device():
                 engine.search_params(False, -1, 1, 100),
                 engine.search_params(False, 1, 1, 100, min_shared=0),
                 engine.search_params(False, 1, 1, 256, max_charge=8),          # too many segments
-                engine.search_params(True, 2_000_000, 1, 100)]:
+                engine.search_params(True, 2_000_000, 1, 100),
+                engine.search_params(False, 1, 1, 100, fit=2)]:
         assert capi.ps_workspace_bytes(h.handle, 10, 100, C.byref(bad), C.byref(need)) == capi.PS_EINVAL
     good = engine.search_params(False, 1, 1, 100, max_charge=3)
     assert capi.ps_workspace_bytes(h.handle, 10, 100, C.byref(good), C.byref(need)) == capi.PS_OK
@@ -255,10 +256,11 @@ def test_partition_and_assemble_argument_checks_without_device():
     empty = engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [], 0, n_shards=64, shard=63)
     assert len(empty) == 0
     parts = (capi.ps_part * 2)()
-    assert capi.ps_assemble(None, 0, parts, 1, 5, 1, 1, 1) == capi.PS_EINVAL
-    assert capi.ps_assemble(None, 65, parts, 1, 5, 1, 1, 1) == capi.PS_EINVAL
-    assert capi.ps_assemble(None, 2, parts, 1, 0, 1, 1, 1) == capi.PS_EINVAL
-    assert capi.ps_assemble(None, 2, parts, 1, 17, 1, 1, 1) == capi.PS_EINVAL
-    assert capi.ps_assemble(None, 2, parts, 1, 5, 1, 1, 1) == capi.PS_EINVAL     # NULL partition pointers
+    assert capi.ps_assemble(None, 0, parts, 1, 5, 0, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 65, parts, 1, 5, 0, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 2, parts, 1, 0, 0, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 2, parts, 1, 17, 0, 1, 1, 1) == capi.PS_EINVAL
+    assert capi.ps_assemble(None, 2, parts, 1, 5, 2, 1, 1, 1) == capi.PS_EINVAL     # unknown fit
+    assert capi.ps_assemble(None, 2, parts, 1, 5, 0, 1, 1, 1) == capi.PS_EINVAL     # NULL partition pointers
     assert "partition 0" in capi.last_error()
-    assert capi.ps_assemble(None, 2, parts, 0, 5, None, None, None) == capi.PS_OK  # nothing to do
+    assert capi.ps_assemble(None, 2, parts, 0, 5, 0, None, None, None) == capi.PS_OK  # nothing to do

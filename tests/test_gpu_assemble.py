@@ -153,7 +153,7 @@ def test_assembly_keeps_invalid_spectra_invalid(open_parts):
             spaces.append(ws)
             pp.append(engine._device_results(bh))
         out = engine.AssembleOut(sub.n, prm.top_k)
-        engine.assemble(pp, sub.n, prm.top_k, out)
+        engine.assemble(pp, sub.n, prm.top_k, out, fit=prm.fit)
         torch.cuda.synchronize()
         hits, stats, hist = out.to_host()
     finally:
@@ -185,8 +185,24 @@ def test_assembly_of_graph_plan_results(open_parts):
             capi.check(capi.ps_plan_device_results(p.handle, C.byref(h), C.byref(st), C.byref(hg)))
             pp.append(capi.ps_part(h.value, st.value, hg.value))
         out = engine.AssembleOut(batch.n, prm.top_k)
-        engine.assemble(pp, batch.n, prm.top_k, out)
+        engine.assemble(pp, batch.n, prm.top_k, out, fit=prm.fit)
         torch.cuda.synchronize()
         hits, stats, hist = out.to_host()
         ref = engine.search(whole, batch, prm)
         assert _same(hits, ref.hits) and _same(stats, ref.stats) and _same(hist, ref.hist)
+
+
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
+def test_gumbel_fit_parity_whole_and_partitioned(open_parts, schedule):
+    """The log-Weibull (Gumbel) expect value: whole-database search against the
+    oracle's, and 3 partitions assembled against the whole search bit for bit."""
+    w, prot, sp, whole, parts, db, _ = open_parts
+    _say(f"gumbel fit: schedule {schedule}")
+    prm = _params(w, schedule, fit=capi.PS_FIT_GUMBEL)
+    ref = engine.search(whole, sp, prm)
+    oh, ost, og = db.search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                            fit=oracle.FIT_GUMBEL)
+    assert (ost["status"] == 0).sum() > 60
+    assert_parity(ref, oh, ost, og)
+    res = engine.search_partitioned(parts[3], sp, prm)
+    _assert_identical(res, ref)

@@ -287,12 +287,14 @@ def test_edge_cases_parity(small_open):
     for top_k, kmin, T, top_b, window, ppm in [(1, 1, 1, 90, 500_000_000, False), (16, 2, 0, 90, 100_000_000, False),
                                                (5, 4, 4, 20, 500_000_000, False), (3, 1, 2, 50, 30, True),
                                                (5, 1, 1, 90, 10**15, False)]:
-        _say(f"edge: top_k={top_k} kmin={kmin} T={T} B={top_b} window={window} ppm={ppm}")
-        prm = engine.search_params(ppm, window, T, top_b, top_k, kmin, max_charge=8 if (2 * T + 1) * 7 * top_b <= 2048 else 3)
-        sub = sp_e if prm.max_charge == 8 else sp_e.subset([i for i in range(sp_e.n) if sp_e.charge[i] <= 3])
-        res = engine.search(ix, sub, prm)
-        oh, ost, og = db.search(sub, ppm, window, T, top_b, top_k, kmin)
-        assert_parity(res, oh, ost, og)
+        for fit in (capi.PS_FIT_TAIL, capi.PS_FIT_GUMBEL):
+            _say(f"edge: top_k={top_k} kmin={kmin} T={T} B={top_b} window={window} ppm={ppm} fit={fit}")
+            prm = engine.search_params(ppm, window, T, top_b, top_k, kmin,
+                                       max_charge=8 if (2 * T + 1) * 7 * top_b <= 2048 else 3, fit=fit)
+            sub = sp_e if prm.max_charge == 8 else sp_e.subset([i for i in range(sp_e.n) if sp_e.charge[i] <= 3])
+            res = engine.search(ix, sub, prm)
+            oh, ost, og = db.search(sub, ppm, window, T, top_b, top_k, kmin, fit=fit)
+            assert_parity(res, oh, ost, og)
 
 
 def test_wide_counters_are_used_and_exact(small_open):
