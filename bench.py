@@ -202,7 +202,9 @@ def assembly_leg(capi, engine, torch, w, prot, merge, G, dsp, n, nnz, prm, ref, 
     res = {"shards": G, "spectra_per_s": n * steps / dt, "ms_per_step": dt * 1e3 / steps,
            "assemble_ms": ms, "identical_to_whole": bool(same),
            "roofline": {"bound": "hbm", "kernel": "k_assemble", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": alg_bytes}}
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": measured_traffic(w.name, "k_assemble") if G == 4 else None,
+                        "bytes_per_launch": alg_bytes}}
     log(f"partitions: {res['spectra_per_s']:.0f} spectra/s over {G} partitions ({res['ms_per_step']:.1f} ms/step); "
         f"assembly {ms:.3f} ms = {achieved:.0f} GB/s of {alg_bytes / 1e9:.2f} GB")
     return res

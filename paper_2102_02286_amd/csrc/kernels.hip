@@ -1137,9 +1137,10 @@ __device__ __forceinline__ double block_sum_f64(double x, int k, EvShared& S) {
 // over bin centres x_j = 0.1 j + 0.05, beta = sqrt(6 v) / pi,
 // mu = m - gamma beta, ev = N * (1 - exp(-exp(-(h1 - mu) / beta))).  Fewer than
 // 3 non-zero bins: FEW_POINTS.  Result valid in thread 0.
-__device__ void gumbel_fit(const long long num[2], long long total, unsigned long long N, double h1, int& status,
-                           double& ev, EvShared& S) {
+__device__ void gumbel_fit(long long num0, long long num1, long long total, unsigned long long N, double h1,
+                           int& status, double& ev, EvShared& S) {
     const uint32_t tid = threadIdx.x;
+    const long long num[2] = {num0, num1};
     double wx = 0, pts = 0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -1226,11 +1227,11 @@ __device__ void expect_value(const int32_t* hg, unsigned long long N, double h1,
     }
     const int mode = kHistBins - 1 - (int)(mkey & 511ull);
     const long long above = suf - pair + later;              // smoothed mass of bins > 2t + 1
-    const long long tail[2] = {pair + above, num[1] + above};
+    const long long tail0 = pair + above, tail1 = num[1] + above;
     ev = __builtin_nan("");
     if (fit == PS_FIT_GUMBEL) {
         if (status == PS_STATUS_OK) {                   // uniform: status and total are block-wide
-            if (total > 0) gumbel_fit(num, total, N, h1, status, ev, S);
+            if (total > 0) gumbel_fit(num[0], num[1], total, N, h1, status, ev, S);
             else status = PS_STATUS_FEW_POINTS;
         }
         __syncthreads();
@@ -1241,12 +1242,13 @@ __device__ void expect_value(const int32_t* hg, unsigned long long N, double h1,
     if (status == PS_STATUS_OK && total > 0) {
         const double hb = floor(10.0 * h1);
         const int jh = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
+#pragma unroll 1
+        for (int u = 0; u < 2; ++u) {                   // one log10 live at a time
             const int j = 2 * (int)tid + u;
-            if (j < mode || j > jh - 1 || tail[u] <= 0) continue;
+            const long long tu = u ? tail1 : tail0;
+            if (j < mode || j > jh - 1 || tu <= 0) continue;
             const double x = 0.1 * (double)j;
-            const double y = log10((double)tail[u] / (double)total);
+            const double y = log10((double)tu / (double)total);
             sx += x; sy += y; sxx += x * x; sxy += x * y; cnt += 1.0;
         }
     }
