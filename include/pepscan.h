@@ -205,11 +205,40 @@ int ps_build_index(const ps_device* dev, const ps_db_params* params, const char*
 /* Sizes: peptides (database entries), postings, fragment bins. */
 int ps_index_shape(const ps_index* idx, uint64_t* n_peptides, uint64_t* n_postings, uint64_t* n_bins);
 
+/* The same index built on the GPU (Superstep 1; Supplementary Algorithm 1): the
+ * host only counts each protein's entries (binomial sums over modification
+ * sites); the GPU writes the entries, sorts them by mass (stable radix sort, so
+ * ties keep the (protein, start, length, site mask) order), generates the b/y
+ * ions and fills the CSR lists with a counting sort done in chunks of at most
+ * 2^27 (bin, posting) pairs, then the tile directory.  The result is identical
+ * to ps_index_create + ps_index_upload (every array bit for bit), already on the
+ * device.  Its postings and directory stay on the device; ps_index_host_arrays
+ * and ps_index_directory copy them back on request.
+ *
+ * ps_index_build_device_bytes: device bytes of the index block (kept for the
+ * index's lifetime; postings sized to an upper bound that is exact for a whole
+ * database and, for a partition, its entries times the longest peptide's
+ * postings) and of the scratch block (only during the build).  Needs a device
+ * (it sizes the library sorts' workspace).
+ * ps_index_build_device: builds into `index_block` (256-byte aligned) using
+ * `scratch`; blocks until done, on index_block->stream.  Errors as
+ * ps_index_create, plus PS_ENOMEM when a block is too small. */
+int ps_index_build_device_bytes(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                                uint64_t n_proteins, uint64_t* index_bytes, uint64_t* scratch_bytes);
+int ps_index_build_device(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                          uint64_t n_proteins, const ps_device* index_block, const ps_device* scratch,
+                          ps_index** out);
+
 /* Entry `id`: mass (uDa), protein, start, length, site mask.  Mask bit i is
  * the i-th modifiable site, the protein N-terminus first, then residues by
  * position. */
 int ps_index_entry(const ps_index* idx, uint64_t id, int64_t* mass, uint32_t* protein,
                    uint32_t* start, uint32_t* length, uint64_t* site_mask);
+
+/* Entries [first, first + count) as arrays (any pointer may be NULL); ids past
+ * the end are PS_EINVAL. */
+int ps_index_entries(const ps_index* idx, uint64_t first, uint64_t count, int64_t* mass, uint32_t* protein,
+                     uint32_t* start, uint8_t* length, uint64_t* site_mask);
 
 /* Peptide string with modifications, e.g. "PEPT[+79.966331]IDEK"; PS_ENOMEM
  * if cap is too small (the string is truncated and NUL-terminated). */

@@ -98,8 +98,12 @@ _SIGS = [
     ("ps_build_index", C.c_int, [C.POINTER(ps_device), C.POINTER(ps_db_params), _P, _P, C.c_uint64,
                                  C.POINTER(_P)]),
     ("ps_index_shape", C.c_int, [_P, _U64P, _U64P, _U64P]),
+    ("ps_index_build_device_bytes", C.c_int, [C.POINTER(ps_db_params), _P, _P, C.c_uint64, _U64P, _U64P]),
+    ("ps_index_build_device", C.c_int, [C.POINTER(ps_db_params), _P, _P, C.c_uint64, C.POINTER(ps_device),
+                                        C.POINTER(ps_device), C.POINTER(_P)]),
     ("ps_index_entry", C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                                  C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), _U64P]),
+    ("ps_index_entries", C.c_int, [_P, C.c_uint64, C.c_uint64, _P, _P, _P, _P, _P]),
     ("ps_peptide", C.c_int, [_P, C.c_uint32, C.c_char_p, C.c_size_t]),
     ("ps_index_host_arrays", C.c_int, [_P, _P, _P]),
     ("ps_index_set_schedule", C.c_int, [_P, C.POINTER(ps_schedule)]),
@@ -188,7 +192,10 @@ ps_index_device_bytes = _fn("ps_index_device_bytes")
 ps_index_upload = _fn("ps_index_upload")
 ps_build_index = _fn("ps_build_index")
 ps_index_shape = _fn("ps_index_shape")
+ps_index_build_device_bytes = _fn("ps_index_build_device_bytes")
+ps_index_build_device = _fn("ps_index_build_device")
 ps_index_entry = _fn("ps_index_entry")
+ps_index_entries = _fn("ps_index_entries")
 ps_peptide = _fn("ps_peptide")
 ps_index_host_arrays = _fn("ps_index_host_arrays")
 ps_index_set_schedule = _fn("ps_index_set_schedule")

@@ -1,0 +1,747 @@
+// build.hip -- the fragment-ion index built on the device.
+//
+// Superstep 1 of HiCOPS (arXiv 2102.02286; Supplementary Algorithm 1): generate
+// every database entry, sort the entries, generate their b/y ions and index
+// them.  The same index as index_build_host, bit for bit, made on the GPU:
+//   1. host: count each protein's entries (peptides x modification subsets) with
+//      binomial sums, which fixes where each protein's entries go (no
+//      materialisation on the host);
+//   2. k_gen_entries: one thread per protein writes its entries in (start,
+//      length, site mask) order, so generation order is the tie order of the
+//      key (mass, protein, start, length, mask);
+//   3. a stable radix sort by mass then gives the id order; a partition keeps
+//      every G-th rank;
+//   4. ions: per entry 2(n-1) b/y ions, each posted to the 2T+1 bins of a
+//      merged list (T = 0: one bin).  In chunks of entries the (bin, posting)
+//      pairs are generated in id order and stably sorted by bin.  One chunk:
+//      the sorted postings are the lists and each bin's offset is a binary
+//      search of the sorted bins.  Several chunks: a first pass adds each
+//      chunk's per-bin run lengths, an exclusive scan gives the offsets, and a
+//      second pass scatters every chunk's runs behind each bin's cursor -- a
+//      chunked counting sort, so every list is in id order and the scratch
+//      memory is bounded by the chunk;
+//   5. k_dir: the tile directory, one binary search per (bin, block).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "batch.h"
+#include "state.h"
+
+namespace ps {
+
+namespace {
+
+constexpr uint64_t kChunkPairs = 1ull << 27;   // (bin, posting) pairs sorted at a time
+
+__constant__ int64_t c_residue[26] = {
+    71037114, -1, 103009185, 115026943, 129042593, 147068414, 57021464, 137058912,   // A..H
+    113084064, -1, 128094963, 113084064, 131040485, 114042927, -1, 97052764,         // I..P
+    128058578, 156101111, 87032028, 101047679, -1, 99068414, 186079313, -1,          // Q..X
+    163063329, -1,                                                                     // Y, Z
+};
+
+struct ModArgs {
+    int32_t res_mod[26];
+    int32_t nterm_mod;
+    int32_t pad;
+    int64_t delta[16];
+};
+
+__device__ __forceinline__ bool cut_after(const char* s, uint64_t n, uint64_t i) {
+    if (s[i] != 'K' && s[i] != 'R') return false;
+    return i + 1 >= n || s[i + 1] != 'P';
+}
+
+// Mass shift of the modification sites selected by `mask` (bit order: the
+// protein N-terminus first when the peptide starts the protein, then residues by
+// position).
+__device__ int64_t site_shift(const char* s, uint32_t a, uint32_t len, uint64_t mask, const ModArgs& M) {
+    int64_t d = 0;
+    uint32_t bit = 0;
+    if (a == 0 && M.nterm_mod >= 0) {
+        if (mask & 1ull) d += M.delta[M.nterm_mod];
+        bit = 1;
+    }
+    for (uint32_t j = 0; j < len; ++j) {
+        const int mm = M.res_mod[s[a + j] - 'A'];
+        if (mm >= 0) {
+            if (mask >> bit & 1ull) d += M.delta[mm];
+            ++bit;
+        }
+    }
+    return d;
+}
+
+struct GenArgs {
+    const char* seq;
+    const uint64_t* prot_off;
+    const uint64_t* ent_off;     // first entry of each protein (host count)
+    uint64_t n_prot;
+    uint32_t missed, min_len, max_len, max_mods;
+    ModArgs mods;
+    int64_t min_mass;
+    int64_t* mass;
+    uint32_t* prot;
+    uint32_t* start;
+    uint8_t* len;
+    uint64_t* mask;
+    uint64_t* key;               // mass - min_mass, the sort key
+    uint32_t* idx;               // generation index, the sort payload
+};
+
+// One thread per protein: every peptide (trypsin, missed cleavages, length
+// range), and for each every subset of <= max_mods sites in increasing mask
+// order.  The walk is the host count's walk, so entry k of protein p lands at
+// ent_off[p] + k.
+__global__ void k_gen_entries(GenArgs A) {
+    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < A.n_prot;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const char* s = A.seq + A.prot_off[p];
+        const uint64_t n = A.prot_off[p + 1] - A.prot_off[p];
+        uint64_t o = A.ent_off[p];
+        for (uint64_t a = 0; a < n; ++a) {
+            if (a != 0 && !cut_after(s, n, a - 1)) continue;
+            uint32_t missed = 0;
+            int64_t base = kWaterUda;
+            for (uint64_t e = a + 1; e <= n; ++e) {
+                const uint64_t len = e - a;
+                if (len > A.max_len) break;
+                base += c_residue[s[e - 1] - 'A'];
+                const bool end = (e == n) || cut_after(s, n, e - 1);
+                if (!end) continue;
+                if (len >= A.min_len) {
+                    uint32_t ns = (a == 0 && A.mods.nterm_mod >= 0) ? 1u : 0u;
+                    for (uint64_t j = a; j < e; ++j) ns += A.mods.res_mod[s[j] - 'A'] >= 0 ? 1u : 0u;
+                    const uint64_t full = ns >= 64 ? ~0ull : (1ull << ns) - 1ull;   // ns <= 63 (checked)
+                    uint64_t mask = 0;
+                    while (true) {
+                        const int64_t m = base + site_shift(s, (uint32_t)a, (uint32_t)len, mask, A.mods);
+                        A.mass[o] = m;
+                        A.prot[o] = (uint32_t)p;
+                        A.start[o] = (uint32_t)a;
+                        A.len[o] = (uint8_t)len;
+                        A.mask[o] = mask;
+                        A.key[o] = (uint64_t)(m - A.min_mass);
+                        A.idx[o] = (uint32_t)o;
+                        ++o;
+                        // next mask in increasing order with at most max_mods bits: a mask with
+                        // too many bits is skipped together with every mask that only adds
+                        // bits below its lowest one
+                        uint64_t y = mask + 1;
+                        while (y != 0 && y <= full && (uint32_t)__popcll(y) > A.max_mods) y += y & (~y + 1);
+                        if (y == 0 || y > full) break;
+                        mask = y;
+                    }
+                }
+                if (e < n && ++missed > A.missed) break;
+            }
+        }
+    }
+}
+
+struct TakeArgs {
+    const uint32_t* order;       // generation index of each sorted rank
+    uint64_t n_local, G, g;
+    const int64_t* mass_in;
+    const uint32_t* prot_in;
+    const uint32_t* start_in;
+    const uint8_t* len_in;
+    const uint64_t* mask_in;
+    int64_t* mass;               // index block
+    uint32_t* prot;
+    uint32_t* start;
+    uint8_t* len;
+    uint64_t* mask;
+    uint64_t* pair_cnt;          // [n_local + 1] pairs of each entry (last = 0)
+    uint32_t pairs_per_ion;      // 2T + 1
+};
+
+// Ranks r * G + g of the sorted database become this partition's ids r.
+__global__ void k_take(TakeArgs A) {
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r <= A.n_local;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        if (r == A.n_local) { A.pair_cnt[r] = 0; continue; }
+        const uint32_t src = A.order[r * A.G + A.g];
+        A.mass[r] = A.mass_in[src];
+        A.prot[r] = A.prot_in[src];
+        A.start[r] = A.start_in[src];
+        A.len[r] = A.len_in[src];
+        A.mask[r] = A.mask_in[src];
+        A.pair_cnt[r] = 2ull * (uint64_t)(A.len_in[src] - 1) * A.pairs_per_ion;
+    }
+}
+
+struct IonArgs {
+    const char* seq;
+    const uint64_t* prot_off;
+    const uint32_t* prot;
+    const uint32_t* start;
+    const uint8_t* len;
+    const uint64_t* mask;
+    ModArgs mods;
+    int32_t T;                   // merge width (0: classic lists)
+    uint64_t n_bins;
+    uint64_t r0, r1;             // entries of this pass
+    const uint64_t* pair_off;    // [n + 1] first pair of each entry
+    uint32_t* key;               // bin, posting (chunk-relative positions)
+    uint32_t* val;
+    int* bad;                    // set when an ion has a negative mass or leaves the bin range
+};
+
+// Residue j of an entry with its modification folded in (the N-terminal shift
+// goes to residue 0).  `bit` is the site counter, advanced past residue j.
+__device__ __forceinline__ int64_t residue_at(const char* s, uint32_t j, uint64_t mask, uint32_t& bit,
+                                              const ModArgs& M) {
+    int64_t m = c_residue[s[j] - 'A'];
+    const int mm = M.res_mod[s[j] - 'A'];
+    if (mm >= 0) {
+        if (mask >> bit & 1ull) m += M.delta[mm];
+        ++bit;
+    }
+    return m;
+}
+
+// One thread per entry: b ions (residues 1..i) then y ions (residues n-i+1..n),
+// i = 1..n-1, each to bins bin-T..bin+T, written as (bin, posting) pairs in
+// this order, so a stable sort by bin keeps every list in (id, b before y) order.
+__global__ void k_ions(IonArgs A) {
+    for (uint64_t r = A.r0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < A.r1;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const char* s = A.seq + A.prot_off[A.prot[r]] + A.start[r];
+        const uint32_t n = A.len[r];
+        const uint64_t mask = A.mask[r];
+        const bool nt = A.start[r] == 0 && A.mods.nterm_mod >= 0;
+        const int64_t nshift = (nt && (mask & 1ull)) ? A.mods.delta[A.mods.nterm_mod] : 0;
+        uint64_t w = A.pair_off[r] - A.pair_off[A.r0];
+        for (int y = 0; y < 2; ++y) {
+            uint32_t bit = nt ? 1u : 0u;
+            uint32_t nsites = 0;
+            if (y) {   // sites before residue j are needed walking backwards: count them all first
+                uint32_t b2 = bit;
+                for (uint32_t j = 0; j < n; ++j) (void)residue_at(s, j, mask, b2, A.mods);
+                nsites = b2;
+            }
+            int64_t acc = 0;
+            uint32_t bit_back = nsites;
+            for (uint32_t i = 1; i < n; ++i) {
+                int64_t ion;
+                if (!y) {
+                    acc += residue_at(s, i - 1, mask, bit, A.mods) + (i == 1 ? nshift : 0);
+                    ion = acc + kProtonUda;
+                } else {
+                    // residue n-i: its site bit is the number of sites before it
+                    const uint32_t j = n - i;
+                    const int mm = A.mods.res_mod[s[j] - 'A'];
+                    if (mm >= 0) --bit_back;
+                    int64_t m = c_residue[s[j] - 'A'];
+                    if (mm >= 0 && (mask >> bit_back & 1ull)) m += A.mods.delta[mm];
+                    acc += m + (j == 0 ? nshift : 0);
+                    ion = acc + kWaterUda + kProtonUda;
+                }
+                if (ion < 0) { atomicOr(A.bad, 1); continue; }
+                const int64_t bn = (ion + kBinWidth / 2) / kBinWidth;
+                for (int d = -A.T; d <= A.T; ++d) {
+                    const int64_t b2 = bn + d;
+                    if (b2 < 0 || b2 >= (int64_t)A.n_bins) { atomicOr(A.bad, 2); continue; }
+                    A.key[w] = (uint32_t)b2;
+                    A.val[w] = (uint32_t)(r << 1) | (uint32_t)y;
+                    ++w;
+                }
+            }
+        }
+    }
+}
+
+struct ScatterArgs {
+    const uint32_t* key;         // sorted chunk
+    const uint32_t* val;
+    uint64_t m;
+    uint32_t* run_start;         // [n_bins] first position of each bin's run in the chunk
+    uint32_t* run_end;
+    const uint64_t* bin_off;
+    unsigned long long* cursor;  // [n_bins] postings of the bin written so far
+    uint32_t* post;
+};
+
+__global__ void k_runs(ScatterArgs A) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = A.key[i];
+        if (i == 0 || A.key[i - 1] != b) A.run_start[b] = (uint32_t)i;
+        if (i + 1 == A.m || A.key[i + 1] != b) A.run_end[b] = (uint32_t)(i + 1);
+    }
+}
+
+__global__ void k_scatter(ScatterArgs A) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = A.key[i];
+        A.post[A.bin_off[b] + A.cursor[b] + (i - A.run_start[b])] = A.val[i];
+    }
+}
+
+__global__ void k_advance(ScatterArgs A) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = A.key[i];
+        if (i == 0 || A.key[i - 1] != b) A.cursor[b] += A.run_end[b] - A.run_start[b];
+    }
+}
+
+// Postings of each bin in a sorted chunk: cnt[b] += (first position > b) -
+// (first position >= b), by binary search, for b < n_bins.  With `off` set
+// (one chunk), off[b] = first position >= b for b <= n_bins instead.
+__global__ void k_bin_runs(const uint32_t* key, uint64_t m, uint64_t n_bins, unsigned long long* cnt,
+                           uint64_t* off) {
+    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b <= n_bins;
+         b += (uint64_t)gridDim.x * blockDim.x) {
+        auto first_ge = [&](uint64_t v) {
+            uint64_t lo = 0, hi = m;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if ((uint64_t)key[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            return lo;
+        };
+        const uint64_t a = first_ge(b);
+        if (off) off[b] = a;
+        else if (b < n_bins) cnt[b] += first_ge(b + 1) - a;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Entry k of bin b: the first posting of b with id >= k << shift.
+__global__ void k_dir(const uint64_t* bin_off, const uint32_t* post, uint64_t n_bins, uint64_t stride,
+                      uint32_t shift, uint32_t* dir) {
+    const uint64_t total = n_bins * stride;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = t / stride, k = t - b * stride;
+        const uint64_t target = (k << shift) << 1;          // posting = id << 1 | y
+        uint64_t lo = bin_off[b], hi = bin_off[b + 1];
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if ((uint64_t)post[mid] < target) lo = mid + 1; else hi = mid;
+        }
+        dir[t] = (uint32_t)lo;
+    }
+}
+
+uint32_t grid_for(uint64_t n, uint32_t block = 256) {
+    uint64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (uint32_t)g;
+}
+
+uint32_t bit_length(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 1u; }
+
+// Host count: entries per protein and the quantities the layout needs.
+struct Census {
+    std::vector<uint64_t> ent_off;   // [n_prot + 1]
+    uint64_t D_all = 0;
+    int64_t min_mass = 0, max_mass = 0;
+    uint32_t max_len = 0;
+    uint64_t D = 0, n_bins = 0, post_cap = 0, dir_stride = 0, dir_nblk = 0;
+    uint32_t dir_shift = 12;
+};
+
+int census(const ps_index* ix, Census& C) {
+    const ModTable mt = mod_table(ix);
+    const uint64_t n_prot = ix->prot_off.size() - 1;
+    uint64_t binom[64][64];
+    for (int a = 0; a < 64; ++a)
+        for (int b = 0; b < 64; ++b) binom[a][b] = b == 0 ? 1 : (a == 0 ? 0 : binom[a - 1][b - 1] + binom[a - 1][b]);
+    const unsigned T = worker_threads();
+    std::vector<uint64_t> cnt(n_prot, 0);
+    struct Part { int64_t lo = INT64_MAX, hi = INT64_MIN; uint32_t max_len = 0; uint64_t pairs = 0; };
+    std::vector<Part> parts(T);
+    std::atomic<int> bad{0};
+    const uint64_t chunk = (n_prot + T - 1) / std::max<uint64_t>(T, 1);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < T; ++t) {
+        const uint64_t pa = t * chunk, pb = std::min(n_prot, pa + chunk);
+        if (pa >= pb) break;
+        th.emplace_back([&, t, pa, pb] {
+            Part& P = parts[t];
+            int64_t site[64];
+            for (uint64_t p = pa; p < pb; ++p) {
+                const char* s = ix->seq.data() + ix->prot_off[p];
+                const uint64_t n = ix->prot_off[p + 1] - ix->prot_off[p];
+                uint64_t c = 0;
+                for (uint64_t a = 0; a < n; ++a) {
+                    if (a != 0 && !is_cut(s, n, a - 1)) continue;
+                    uint32_t missed = 0;
+                    int64_t base = kWaterUda;
+                    for (uint64_t e = a + 1; e <= n; ++e) {
+                        const uint64_t len = e - a;
+                        if (len > ix->max_len) break;
+                        base += residue_uda(s[e - 1]);
+                        const bool end = (e == n) || is_cut(s, n, e - 1);
+                        if (!end) continue;
+                        if (len >= ix->min_len) {
+                            uint32_t ns = 0;
+                            if (a == 0 && mt.nterm_mod >= 0) site[ns++] = ix->mods[mt.nterm_mod].delta;
+                            for (uint64_t j = a; j < e && ns <= 63; ++j) {
+                                const int mm = mt.res_mod[s[j] - 'A'];
+                                if (mm >= 0) site[ns++] = ix->mods[mm].delta;
+                            }
+                            if (ns > 63) { bad = 1; continue; }
+                            const uint32_t k = std::min<uint32_t>(ix->max_mods, ns);
+                            uint64_t v = 0;
+                            for (uint32_t i = 0; i <= k; ++i) v += binom[ns][i];
+                            if (v >= (1ull << 31)) { bad = 2; continue; }
+                            c += v;
+                            // lightest and heaviest variant: the k most negative / positive shifts
+                            std::sort(site, site + ns);
+                            int64_t lo = base, hi = base;
+                            for (uint32_t i = 0; i < k && site[i] < 0; ++i) lo += site[i];
+                            for (uint32_t i = 0; i < k && site[ns - 1 - i] > 0; ++i) hi += site[ns - 1 - i];
+                            P.lo = std::min(P.lo, lo);
+                            P.hi = std::max(P.hi, hi);
+                            P.max_len = std::max(P.max_len, (uint32_t)len);
+                            P.pairs += v * 2ull * (len - 1);
+                        }
+                        if (e < n && ++missed > ix->missed) break;
+                    }
+                }
+                cnt[p] = c;
+            }
+        });
+    }
+    for (auto& x : th) x.join();
+    if (bad == 1) return fail(PS_EINVAL, "a peptide has more than 63 modifiable sites");
+    if (bad == 2) return fail(PS_EOVERFLOW, "one peptide has 2^31 or more modified forms");
+    C.ent_off.assign(n_prot + 1, 0);
+    for (uint64_t p = 0; p < n_prot; ++p) {
+        C.ent_off[p + 1] = C.ent_off[p] + cnt[p];
+        if (C.ent_off[p + 1] >= (1ull << 31))
+            return fail(PS_EOVERFLOW, "more than 2^31 database entries");
+    }
+    C.D_all = C.ent_off[n_prot];
+    C.min_mass = INT64_MAX;
+    C.max_mass = INT64_MIN;
+    uint64_t pairs_all = 0;
+    for (const Part& P : parts) {
+        C.min_mass = std::min(C.min_mass, P.lo);
+        C.max_mass = std::max(C.max_mass, P.hi);
+        C.max_len = std::max(C.max_len, P.max_len);
+        pairs_all += P.pairs;
+    }
+    if (C.D_all == 0) { C.min_mass = 0; C.max_mass = 0; }
+    const uint64_t G = ix->n_shards, g = ix->shard;
+    C.D = C.D_all > g ? (C.D_all - g + G - 1) / G : 0;
+    C.n_bins = (uint64_t)((std::max<int64_t>(C.max_mass, 0) + kBinWidth / 2) / kBinWidth) + 2;
+    if (C.n_bins >= (1ull << 24))
+        return fail(PS_EOVERFLOW, "peptide masses need %llu fragment bins (limit 2^24)", (unsigned long long)C.n_bins);
+    const uint64_t width = 2ull * ix->merge_tol + 1;
+    // postings: exact for the whole database; a partition's share is bounded by
+    // its entry count times the longest peptide's ions
+    uint64_t cap = pairs_all * width;
+    if (G > 1) cap = std::min<uint64_t>(cap, C.D * 2ull * (C.max_len > 0 ? C.max_len - 1 : 0) * width);
+    C.post_cap = cap;
+    C.dir_shift = directory_shift(C.n_bins, C.D);
+    C.dir_nblk = (C.D >> C.dir_shift) + 1;
+    C.dir_stride = (C.dir_nblk + 1 + 3) & ~3ull;
+    return PS_OK;
+}
+
+uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Scratch layout of a build; sizes only when base is NULL.
+struct Scratch {
+    char* seq; uint64_t* prot_off; uint64_t* ent_off;
+    int64_t* g_mass; uint32_t* g_prot; uint32_t* g_start; uint8_t* g_len; uint64_t* g_mask;
+    uint64_t* key0; uint64_t* key1; uint32_t* idx0; uint32_t* idx1;
+    uint32_t* l_prot; uint32_t* l_start; uint8_t* l_len; uint64_t* l_mask;
+    uint64_t* pair_cnt; uint64_t* pair_off;
+    unsigned long long* bin_cnt; unsigned long long* cursor; uint32_t* run_start; uint32_t* run_end;
+    uint32_t* pk0; uint32_t* pk1; uint32_t* pv0; uint32_t* pv1;
+    int* bad;
+    void* temp; uint64_t temp_bytes;
+    uint64_t total;
+};
+
+Scratch layout_scratch(char* base, const ps_index* ix, const Census& C, uint64_t chunk, uint64_t temp_bytes) {
+    Scratch S{};
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) { uint64_t at = o; o = a256(o + bytes); return base ? base + at : nullptr; };
+    const uint64_t np = ix->prot_off.size();
+    const uint64_t Da = std::max<uint64_t>(C.D_all, 1), D = std::max<uint64_t>(C.D, 1);
+    S.seq = (char*)take(ix->seq.size() + 1);
+    S.prot_off = (uint64_t*)take(np * 8);
+    S.ent_off = (uint64_t*)take(np * 8);
+    S.g_mass = (int64_t*)take(Da * 8);
+    S.g_prot = (uint32_t*)take(Da * 4);
+    S.g_start = (uint32_t*)take(Da * 4);
+    S.g_len = (uint8_t*)take(Da);
+    S.g_mask = (uint64_t*)take(Da * 8);
+    S.key0 = (uint64_t*)take(Da * 8);
+    S.key1 = (uint64_t*)take(Da * 8);
+    S.idx0 = (uint32_t*)take(Da * 4);
+    S.idx1 = (uint32_t*)take(Da * 4);
+    S.l_prot = (uint32_t*)take(D * 4);
+    S.l_start = (uint32_t*)take(D * 4);
+    S.l_len = (uint8_t*)take(D);
+    S.l_mask = (uint64_t*)take(D * 8);
+    S.pair_cnt = (uint64_t*)take((D + 1) * 8);
+    S.pair_off = (uint64_t*)take((D + 1) * 8);
+    S.bin_cnt = (unsigned long long*)take((C.n_bins + 1) * 8);
+    S.cursor = (unsigned long long*)take(C.n_bins * 8);
+    S.run_start = (uint32_t*)take(C.n_bins * 4);
+    S.run_end = (uint32_t*)take(C.n_bins * 4);
+    S.pk0 = (uint32_t*)take(chunk * 4);
+    S.pk1 = (uint32_t*)take(chunk * 4);
+    S.pv0 = (uint32_t*)take(chunk * 4);
+    S.pv1 = (uint32_t*)take(chunk * 4);
+    S.bad = (int*)take(256);
+    S.temp = take(temp_bytes);
+    S.temp_bytes = temp_bytes;
+    S.total = o;
+    return S;
+}
+
+// Workspace of the library sorts and scans at these sizes (no launch).
+uint64_t temp_bytes_for(const Census& C, uint64_t chunk, hipStream_t st, hipError_t* err) {
+    size_t a = 0, b = 0, c = 0, d = 0;
+    hipcub::DoubleBuffer<uint64_t> k64(nullptr, nullptr);
+    hipcub::DoubleBuffer<uint32_t> v32(nullptr, nullptr);
+    hipcub::DoubleBuffer<uint32_t> k32(nullptr, nullptr);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, a, k64, v32, (int)std::max<uint64_t>(C.D_all, 1), 0,
+                                                      64, st);
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(nullptr, b, k32, v32, (int)std::max<uint64_t>(chunk, 1), 0, 32, st);
+    if (e == hipSuccess)
+        e = hipcub::DeviceScan::ExclusiveSum(nullptr, c, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                             (int)(std::max<uint64_t>(C.D, 1) + 1), st);
+    if (e == hipSuccess)
+        e = hipcub::DeviceScan::ExclusiveSum(nullptr, d, (const unsigned long long*)nullptr,
+                                             (unsigned long long*)nullptr, (int)(C.n_bins + 1), st);
+    *err = e;
+    return std::max(std::max(a, b), std::max(c, d)) + 4096;
+}
+
+uint64_t chunk_pairs(const Census& C) { return std::max<uint64_t>(1, std::min<uint64_t>(C.post_cap, kChunkPairs)); }
+
+}  // namespace
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                                           uint64_t n_proteins, uint64_t* index_bytes, uint64_t* scratch_bytes) {
+    if (!index_bytes || !scratch_bytes) return fail(PS_EINVAL, "NULL argument");
+    ps_index* ix = nullptr;
+    int rc = index_prepare(params, residues, prot_off, n_proteins, &ix);
+    if (rc != PS_OK) return rc;
+    Census C;
+    rc = census(ix, C);
+    if (rc == PS_OK) rc = require_device();
+    if (rc == PS_OK) {
+        hipError_t e;
+        const uint64_t chunk = chunk_pairs(C);
+        const uint64_t tb = temp_bytes_for(C, chunk, nullptr, &e);
+        if (e != hipSuccess) rc = fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e));
+        *index_bytes = index_layout(C.D, C.n_bins, C.post_cap, C.n_bins * C.dir_stride).total;
+        *scratch_bytes = layout_scratch(nullptr, ix, C, chunk, tb).total;
+    }
+    delete ix;
+    return rc;
+}
+
+extern "C" int ps_index_build_device(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                                     uint64_t n_proteins, const ps_device* index_block, const ps_device* scratch,
+                                     ps_index** out) {
+    if (!out) return fail(PS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!index_block || !scratch) return fail(PS_EINVAL, "NULL device block");
+    ps_index* ix = nullptr;
+    int rc = index_prepare(params, residues, prot_off, n_proteins, &ix);
+    if (rc != PS_OK) return rc;
+    auto bail = [&](int code) { delete ix; return code; };
+    rc = require_device();
+    if (rc != PS_OK) return bail(rc);
+    Census C;
+    rc = census(ix, C);
+    if (rc != PS_OK) return bail(rc);
+    hipStream_t st = (hipStream_t)index_block->stream;
+    hipError_t e = hipSuccess;
+    const uint64_t chunk = chunk_pairs(C);
+    const uint64_t tb = temp_bytes_for(C, chunk, st, &e);
+    if (e != hipSuccess) return bail(fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e)));
+    const DevLayout lay = index_layout(C.D, C.n_bins, C.post_cap, C.n_bins * C.dir_stride);
+    const Scratch need = layout_scratch(nullptr, ix, C, chunk, tb);
+    if (!index_block->base || index_block->bytes < lay.total)
+        return bail(fail(PS_ENOMEM, "index needs %llu device bytes, block has %llu", (unsigned long long)lay.total,
+                         (unsigned long long)index_block->bytes));
+    if (!scratch->base || scratch->bytes < need.total)
+        return bail(fail(PS_ENOMEM, "index build needs %llu scratch bytes, block has %llu",
+                         (unsigned long long)need.total, (unsigned long long)scratch->bytes));
+    if (((uintptr_t)index_block->base & 255u) || ((uintptr_t)scratch->base & 255u))
+        return bail(fail(PS_EINVAL, "device blocks must be 256-byte aligned"));
+    char* base = (char*)index_block->base;
+    const Scratch S = layout_scratch((char*)scratch->base, ix, C, chunk, tb);
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    const ModTable mt = mod_table(ix);
+    ModArgs M{};
+    for (int i = 0; i < 26; ++i) M.res_mod[i] = mt.res_mod[i];
+    M.nterm_mod = mt.nterm_mod;
+    for (size_t m = 0; m < ix->mods.size(); ++m) M.delta[m] = ix->mods[m].delta;
+    int64_t* mass = (int64_t*)(base + lay.mass);
+    uint64_t* bin_off = (uint64_t*)(base + lay.bin);
+    uint32_t* post = (uint32_t*)(base + lay.post);
+    uint32_t* dir = (uint32_t*)(base + lay.dir);
+    const uint64_t n_prot = ix->prot_off.size() - 1;
+
+    // inputs
+    chk(hipMemcpyAsync(S.seq, ix->seq.data(), ix->seq.size(), hipMemcpyHostToDevice, st));
+    chk(hipMemcpyAsync(S.prot_off, ix->prot_off.data(), (n_prot + 1) * 8, hipMemcpyHostToDevice, st));
+    chk(hipMemcpyAsync(S.ent_off, C.ent_off.data(), (n_prot + 1) * 8, hipMemcpyHostToDevice, st));
+    chk(hipMemsetAsync(S.bad, 0, sizeof(int), st));
+    // 2. entries
+    if (e == hipSuccess && C.D_all > 0) {
+        GenArgs g{S.seq, S.prot_off, S.ent_off, n_prot, ix->missed, ix->min_len, ix->max_len, ix->max_mods, M,
+                  C.min_mass, S.g_mass, S.g_prot, S.g_start, S.g_len, S.g_mask, S.key0, S.idx0};
+        hipLaunchKernelGGL(k_gen_entries, dim3(grid_for(n_prot, 64)), dim3(64), 0, st, g);
+        chk(hipGetLastError());
+    }
+    // 3. stable sort by mass; the partition takes every G-th rank
+    const uint32_t* order = S.idx0;
+    if (e == hipSuccess && C.D_all > 1) {
+        hipcub::DoubleBuffer<uint64_t> keys(S.key0, S.key1);
+        hipcub::DoubleBuffer<uint32_t> vals(S.idx0, S.idx1);
+        size_t tbytes = S.temp_bytes;
+        chk(hipcub::DeviceRadixSort::SortPairs(S.temp, tbytes, keys, vals, (int)C.D_all, 0,
+                                               (int)bit_length((uint64_t)(C.max_mass - C.min_mass)), st));
+        order = vals.Current();
+    }
+    const uint32_t width = 2u * ix->merge_tol + 1u;
+    if (e == hipSuccess) {
+        TakeArgs t{order, C.D, ix->n_shards, ix->shard, S.g_mass, S.g_prot, S.g_start, S.g_len, S.g_mask,
+                   mass, S.l_prot, S.l_start, S.l_len, S.l_mask, S.pair_cnt, width};
+        hipLaunchKernelGGL(k_take, dim3(grid_for(C.D + 1)), dim3(256), 0, st, t);
+        chk(hipGetLastError());
+    }
+    // 4. ions: entry pair offsets, then chunks of (bin, posting) pairs
+    IonArgs io{S.seq, S.prot_off, S.l_prot, S.l_start, S.l_len, S.l_mask, M, (int32_t)ix->merge_tol, C.n_bins,
+               0, C.D, S.pair_off, nullptr, nullptr, S.bad};
+    if (e == hipSuccess) {
+        size_t tbytes = S.temp_bytes;
+        chk(hipcub::DeviceScan::ExclusiveSum(S.temp, tbytes, S.pair_cnt, S.pair_off, (int)(C.D + 1), st));
+    }
+    std::vector<uint64_t> poff(C.D + 1);
+    chk(hipMemcpyAsync(poff.data(), S.pair_off, (C.D + 1) * 8, hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    if (e != hipSuccess) return bail(fail(PS_EDEVICE, "index build: %s", hipGetErrorString(e)));
+    const uint64_t n_post = poff[C.D];
+    if (n_post >= (1ull << 32))
+        return bail(fail(PS_EOVERFLOW, "index holds %llu postings; this build addresses at most 2^32",
+                         (unsigned long long)n_post));
+    if (n_post > C.post_cap)
+        return bail(fail(PS_EOVERFLOW, "postings exceed the computed bound (%llu > %llu)",
+                         (unsigned long long)n_post, (unsigned long long)C.post_cap));
+    // chunks of whole entries holding at most `chunk` pairs each
+    std::vector<uint64_t> cuts{0};
+    while (cuts.back() < C.D) {
+        const uint64_t r0 = cuts.back();
+        uint64_t r1 = (uint64_t)(std::upper_bound(poff.begin() + r0, poff.end(), poff[r0] + chunk) - poff.begin()) - 1;
+        if (r1 <= r0) r1 = r0 + 1;                       // one entry never exceeds a chunk
+        cuts.push_back(r1);
+    }
+    const size_t n_chunks = cuts.size() - 1;
+    // generate and stably sort one chunk's pairs; returns the sorted buffers
+    auto sorted_chunk = [&](size_t c, uint64_t& m) {
+        const uint64_t r0 = cuts[c], r1 = cuts[c + 1];
+        m = poff[r1] - poff[r0];
+        io.r0 = r0; io.r1 = r1; io.key = S.pk0; io.val = S.pv0;
+        hipLaunchKernelGGL(k_ions, dim3(grid_for(r1 - r0)), dim3(256), 0, st, io);
+        chk(hipGetLastError());
+        hipcub::DoubleBuffer<uint32_t> keys(S.pk0, S.pk1);
+        hipcub::DoubleBuffer<uint32_t> vals(S.pv0, S.pv1);
+        size_t tbytes = S.temp_bytes;
+        if (m > 1) chk(hipcub::DeviceRadixSort::SortPairs(S.temp, tbytes, keys, vals, (int)m, 0,
+                                                        (int)bit_length(C.n_bins), st));
+        return std::make_pair(keys.Current(), vals.Current());
+    };
+    if (n_chunks <= 1) {
+        uint64_t m = 0;
+        const uint32_t* k = S.pk0;
+        const uint32_t* v = S.pv0;
+        if (n_chunks == 1) { auto kv = sorted_chunk(0, m); k = kv.first; v = kv.second; }
+        hipLaunchKernelGGL(k_bin_runs, dim3(grid_for(C.n_bins + 1)), dim3(256), 0, st, k, m, C.n_bins,
+                           (unsigned long long*)nullptr, bin_off);
+        chk(hipGetLastError());
+        if (m) chk(hipMemcpyAsync(post, v, m * 4, hipMemcpyDeviceToDevice, st));
+    } else {
+        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(C.n_bins + 1)), dim3(256), 0, st, S.bin_cnt, C.n_bins + 1);
+        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(C.n_bins)), dim3(256), 0, st, S.cursor, C.n_bins);
+        for (size_t c = 0; c < n_chunks && e == hipSuccess; ++c) {       // pass 1: postings per bin
+            uint64_t m = 0;
+            auto kv = sorted_chunk(c, m);
+            hipLaunchKernelGGL(k_bin_runs, dim3(grid_for(C.n_bins + 1)), dim3(256), 0, st, kv.first, m, C.n_bins,
+                               S.bin_cnt, (uint64_t*)nullptr);
+            chk(hipGetLastError());
+        }
+        size_t tbytes = S.temp_bytes;
+        chk(hipcub::DeviceScan::ExclusiveSum(S.temp, tbytes, S.bin_cnt, (unsigned long long*)bin_off,
+                                             (int)(C.n_bins + 1), st));
+        for (size_t c = 0; c < n_chunks && e == hipSuccess; ++c) {       // pass 2: scatter
+            uint64_t m = 0;
+            auto kv = sorted_chunk(c, m);
+            ScatterArgs sa{kv.first, kv.second, m, S.run_start, S.run_end, bin_off, S.cursor, post};
+            hipLaunchKernelGGL(k_runs, dim3(grid_for(m)), dim3(256), 0, st, sa);
+            hipLaunchKernelGGL(k_scatter, dim3(grid_for(m)), dim3(256), 0, st, sa);
+            hipLaunchKernelGGL(k_advance, dim3(grid_for(m)), dim3(256), 0, st, sa);
+            chk(hipGetLastError());
+        }
+    }
+    int bad = 0;
+    chk(hipMemcpyAsync(&bad, S.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    if (e != hipSuccess) return bail(fail(PS_EDEVICE, "index build: %s", hipGetErrorString(e)));
+    if (bad & 1) return bail(fail(PS_EINVAL, "a fragment ion has a negative mass (modification deltas too negative)"));
+    if (bad & 2) return bail(fail(PS_EINVAL, "a fragment ion lies outside the bin range"));
+    // 5. directory
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_dir, dim3(grid_for(C.n_bins * C.dir_stride)), dim3(256), 0, st, bin_off, post,
+                           C.n_bins, C.dir_stride, C.dir_shift, dir);
+        chk(hipGetLastError());
+    }
+    // score tables; host copies of the per-entry arrays and the bin offsets
+    std::vector<double> lf, ls;
+    score_tables(lf, ls);
+    chk(hipMemcpyAsync(base + lay.lf, lf.data(), lf.size() * 8, hipMemcpyHostToDevice, st));
+    chk(hipMemcpyAsync(base + lay.ls, ls.data(), ls.size() * 8, hipMemcpyHostToDevice, st));
+    try {
+        ix->mass.resize(C.D); ix->prot.resize(C.D); ix->start.resize(C.D); ix->len.resize(C.D); ix->mask.resize(C.D);
+        ix->bin_off.resize(C.n_bins + 1);
+    } catch (...) { return bail(fail(PS_ENOMEM, "out of host memory")); }
+    chk(hipMemcpyAsync(ix->mass.data(), mass, C.D * 8, hipMemcpyDeviceToHost, st));
+    chk(hipMemcpyAsync(ix->prot.data(), S.l_prot, C.D * 4, hipMemcpyDeviceToHost, st));
+    chk(hipMemcpyAsync(ix->start.data(), S.l_start, C.D * 4, hipMemcpyDeviceToHost, st));
+    chk(hipMemcpyAsync(ix->len.data(), S.l_len, C.D, hipMemcpyDeviceToHost, st));
+    chk(hipMemcpyAsync(ix->mask.data(), S.l_mask, C.D * 8, hipMemcpyDeviceToHost, st));
+    chk(hipMemcpyAsync(ix->bin_off.data(), bin_off, (C.n_bins + 1) * 8, hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    if (e != hipSuccess) return bail(fail(PS_EDEVICE, "index build: %s", hipGetErrorString(e)));
+    ix->n_bins = C.n_bins;
+    ix->max_len_seen = C.max_len;
+    ix->min_residue = lightest_residue(ix, mt);
+    ix->dir_shift = C.dir_shift;
+    ix->dir_nblk = C.dir_nblk;
+    ix->dir_stride = C.dir_stride;
+    ix->device_built = true;
+    ix->dev_n_post = n_post;
+    ix->dev_dir_entries = C.n_bins * C.dir_stride;
+    bind_device_index(ix, base, lay);
+    if (ix->sched.tile < (1u << ix->dir_shift)) ix->sched.tile = 1u << ix->dir_shift;
+    *out = ix;
+    return PS_OK;
+}

@@ -102,13 +102,7 @@ void parallel_sort(std::vector<PepRec>& v, unsigned threads) {
 
 }  // namespace
 
-// Mod lookup: which mod (if any) sits on each residue letter; the N-terminal mod.
-struct ModTable {
-    int res_mod[26];
-    int nterm_mod;
-};
-
-static ModTable mod_table(const ps_index* ix) {
+ModTable mod_table(const ps_index* ix) {
     ModTable t;
     for (int i = 0; i < 26; ++i) t.res_mod[i] = -1;
     t.nterm_mod = -1;
@@ -235,17 +229,7 @@ int index_build_host(ps_index* ix) {
     std::vector<PepRec>().swap(all);
     ix->max_len_seen = max_len_seen;
 
-    // lightest residue including modification deltas (bounds how many ions of one
-    // peptide can share a tolerance window)
-    int64_t nterm_neg = mt.nterm_mod >= 0 ? std::min<int64_t>(0, ix->mods[mt.nterm_mod].delta) : 0;
-    int64_t minres = INT64_MAX;
-    for (int c = 0; c < 26; ++c) {
-        if (kResidueUda[c] < 0) continue;
-        int64_t m = kResidueUda[c] + nterm_neg;
-        if (mt.res_mod[c] >= 0) m += std::min<int64_t>(0, ix->mods[mt.res_mod[c]].delta);
-        minres = std::min(minres, m);
-    }
-    ix->min_residue = minres;
+    ix->min_residue = lightest_residue(ix, mt);
 
     // 3. b/y ion bins, two passes: count per (thread chunk, bin), then scatter in id order
     uint64_t nbins = (uint64_t)((max_mass + kBinWidth / 2) / kBinWidth) + 2;
@@ -351,9 +335,7 @@ int index_build_host(ps_index* ix) {
     // first posting at or after the block start.  A scan tile is a whole number
     // of blocks, so every posting run's tile boundaries are direct lookups.  The
     // grain is 4096 ids unless the directory would pass kDirBudget bytes.
-    constexpr uint64_t kDirBudget = 16ull << 30;
-    ix->dir_shift = 12;
-    while (ix->dir_shift < 16 && nbins * ((D >> ix->dir_shift) + 6) * 4 > kDirBudget) ++ix->dir_shift;
+    ix->dir_shift = directory_shift(nbins, D);
     // Rows are padded to a multiple of four entries (16 bytes), so a row can be
     // read four tile boundaries at a time; padding repeats the bin's end.
     ix->dir_nblk = (D >> ix->dir_shift) + 1;
@@ -375,24 +357,64 @@ int index_build_host(ps_index* ix) {
     return PS_OK;
 }
 
-// Device layout: [mass][bin_off][post][lf][ls][dir], each 256-byte aligned.
+// lightest residue including modification deltas (bounds how many ions of one
+// peptide can share a tolerance window)
+int64_t lightest_residue(const ps_index* ix, const ModTable& mt) {
+    int64_t nterm_neg = mt.nterm_mod >= 0 ? std::min<int64_t>(0, ix->mods[mt.nterm_mod].delta) : 0;
+    int64_t minres = INT64_MAX;
+    for (int c = 0; c < 26; ++c) {
+        if (kResidueUda[c] < 0) continue;
+        int64_t m = kResidueUda[c] + nterm_neg;
+        if (mt.res_mod[c] >= 0) m += std::min<int64_t>(0, ix->mods[mt.res_mod[c]].delta);
+        minres = std::min(minres, m);
+    }
+    return minres;
+}
+
+uint32_t directory_shift(uint64_t nbins, uint64_t D) {
+    constexpr uint64_t kDirBudget = 16ull << 30;
+    uint32_t sh = 12;
+    while (sh < 16 && nbins * ((D >> sh) + 6) * 4 > kDirBudget) ++sh;
+    return sh;
+}
+
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-struct DevLayout {
-    uint64_t mass, bin, post, lf, ls, dir, total;
-};
-
-static DevLayout index_device_layout(const ps_index* ix) {
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_post, uint64_t n_dir) {
     DevLayout L;
     uint64_t o = 0;
-    L.mass = o; o = align256(o + ix->mass.size() * sizeof(int64_t));
-    L.bin = o; o = align256(o + ix->bin_off.size() * sizeof(uint64_t));
-    L.post = o; o = align256(o + ix->post.size() * sizeof(uint32_t));
+    L.mass = o; o = align256(o + n_pep * sizeof(int64_t));
+    L.bin = o; o = align256(o + (n_bins + 1) * sizeof(uint64_t));
+    L.post = o; o = align256(o + n_post * sizeof(uint32_t));
     L.lf = o; o = align256(o + kLfSize * sizeof(double));
     L.ls = o; o = align256(o + kLsSize * sizeof(double));
-    L.dir = o; o = align256(o + ix->dir.size() * sizeof(uint32_t));
+    L.dir = o; o = align256(o + n_dir * sizeof(uint32_t));
     L.total = o;
     return L;
+}
+
+static DevLayout index_device_layout(const ps_index* ix) {
+    return index_layout(ix->mass.size(), ix->n_bins, n_postings(ix), dir_entries(ix));
+}
+
+void bind_device_index(ps_index* ix, char* base, const DevLayout& lay) {
+    DevIndex& d = ix->dev;
+    d.mass = (const int64_t*)(base + lay.mass);
+    d.bin_off = (const uint64_t*)(base + lay.bin);
+    d.post = (const uint32_t*)(base + lay.post);
+    d.lf = (const double*)(base + lay.lf);
+    d.ls = (const double*)(base + lay.ls);
+    d.dir = (const uint32_t*)(base + lay.dir);
+    d.dir_shift = ix->dir_shift;
+    d.dir_nblk = (uint32_t)ix->dir_nblk;
+    d.dir_stride = (uint32_t)ix->dir_stride;
+    d.merge_tol = ix->merge_tol;
+    d.n_pep = ix->mass.size();
+    d.n_bins = ix->n_bins;
+    d.n_post = n_postings(ix);
+    d.max_len = ix->max_len_seen;
+    d.min_residue = ix->min_residue;
+    ix->on_device = true;
 }
 
 void score_tables(std::vector<double>& lf, std::vector<double>& ls) {
@@ -410,8 +432,12 @@ void score_tables(std::vector<double>& lf, std::vector<double>& ls) {
 
 using namespace ps;
 
-extern "C" int ps_index_create(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
-                               uint64_t n_proteins, ps_index** out) {
+namespace ps {
+
+// Validate the database parameters and make an index object holding them and the
+// proteins, with nothing built yet.
+int index_prepare(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                  uint64_t n_proteins, ps_index** out) {
     if (!out) return fail(PS_EINVAL, "out is NULL");
     *out = nullptr;
     if (!params || !residues || !prot_off) return fail(PS_EINVAL, "NULL argument");
@@ -465,14 +491,32 @@ extern "C" int ps_index_create(const ps_db_params* params, const char* residues,
         ix->mods.push_back(md);
     }
     if (nterm_count > 1) { delete ix; return fail(PS_EINVAL, "at most one N-terminal mod"); }
+    // every residue, modified or not, must stay heavier than a proton plus the widest
+    // fragment tolerance, so every b/y ion and its tolerance window lie inside the
+    // bin range of the database's masses
+    if (lightest_residue(ix, mod_table(ix)) <= kProtonUda + kBinWidth * (PS_MAX_FRAG_TOL_BINS + 1)) {
+        delete ix;
+        return fail(PS_EINVAL, "a modification makes a residue lighter than %.3f Da",
+                    (kProtonUda + kBinWidth * (PS_MAX_FRAG_TOL_BINS + 1)) * 1e-6);
+    }
     try {
         ix->seq.assign(residues, residues + total);
         ix->prot_off.assign(prot_off, prot_off + n_proteins + 1);
     } catch (...) { delete ix; return fail(PS_ENOMEM, "out of host memory"); }
     ix->sched = default_schedule();
-    int rc;
+    *out = ix;
+    return PS_OK;
+}
+
+}  // namespace ps
+
+extern "C" int ps_index_create(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
+                               uint64_t n_proteins, ps_index** out) {
+    ps_index* ix = nullptr;
+    int rc = index_prepare(params, residues, prot_off, n_proteins, &ix);
+    if (rc != PS_OK) { if (out) *out = nullptr; return rc; }
     try { rc = index_build_host(ix); } catch (...) { rc = fail(PS_ENOMEM, "out of host memory building the index"); }
-    if (rc != PS_OK) { delete ix; return rc; }
+    if (rc != PS_OK) { delete ix; *out = nullptr; return rc; }
     if (ix->sched.tile < (1u << ix->dir_shift)) ix->sched.tile = 1u << ix->dir_shift;
     *out = ix;
     return PS_OK;
@@ -486,6 +530,7 @@ extern "C" int ps_index_device_bytes(const ps_index* ix, uint64_t* bytes) {
 
 extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     if (!ix || !dev) return fail(PS_EINVAL, "NULL argument");
+    if (ix->device_built) return fail(PS_EINVAL, "this index was built on the device and is already there");
     int rc = require_device();
     if (rc != PS_OK) return rc;
     if (ix->post.size() >= (1ull << 32))
@@ -513,23 +558,7 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     cp(lay.dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
-    DevIndex& d = ix->dev;
-    d.mass = (const int64_t*)(base + lay.mass);
-    d.bin_off = (const uint64_t*)(base + lay.bin);
-    d.post = (const uint32_t*)(base + lay.post);
-    d.lf = (const double*)(base + lay.lf);
-    d.ls = (const double*)(base + lay.ls);
-    d.dir = (const uint32_t*)(base + lay.dir);
-    d.dir_shift = ix->dir_shift;
-    d.dir_nblk = (uint32_t)ix->dir_nblk;
-    d.dir_stride = (uint32_t)ix->dir_stride;
-    d.merge_tol = ix->merge_tol;
-    d.n_pep = ix->mass.size();
-    d.n_bins = ix->n_bins;
-    d.n_post = ix->post.size();
-    d.max_len = ix->max_len_seen;
-    d.min_residue = ix->min_residue;
-    ix->on_device = true;
+    bind_device_index(ix, base, lay);
     return PS_OK;
 }
 
@@ -545,7 +574,7 @@ extern "C" int ps_build_index(const ps_device* dev, const ps_db_params* params, 
 extern "C" int ps_index_shape(const ps_index* ix, uint64_t* n_pep, uint64_t* n_post, uint64_t* n_bins) {
     if (!ix) return fail(PS_EINVAL, "NULL index");
     if (n_pep) *n_pep = ix->mass.size();
-    if (n_post) *n_post = ix->post.size();
+    if (n_post) *n_post = n_postings(ix);
     if (n_bins) *n_bins = ix->n_bins;
     return PS_OK;
 }
@@ -559,6 +588,21 @@ extern "C" int ps_index_entry(const ps_index* ix, uint64_t id, int64_t* mass, ui
     if (start) *start = ix->start[id];
     if (length) *length = ix->len[id];
     if (site_mask) *site_mask = ix->mask[id];
+    return PS_OK;
+}
+
+extern "C" int ps_index_entries(const ps_index* ix, uint64_t first, uint64_t count, int64_t* mass, uint32_t* protein,
+                                uint32_t* start, uint8_t* length, uint64_t* site_mask) {
+    if (!ix) return fail(PS_EINVAL, "NULL index");
+    const uint64_t D = ix->mass.size();
+    if (first > D || count > D - first)
+        return fail(PS_EINVAL, "entries [%llu, %llu) out of range (%llu)", (unsigned long long)first,
+                    (unsigned long long)(first + count), (unsigned long long)D);
+    if (mass) memcpy(mass, ix->mass.data() + first, count * sizeof(int64_t));
+    if (protein) memcpy(protein, ix->prot.data() + first, count * sizeof(uint32_t));
+    if (start) memcpy(start, ix->start.data() + first, count * sizeof(uint32_t));
+    if (length) memcpy(length, ix->len.data() + first, count);
+    if (site_mask) memcpy(site_mask, ix->mask.data() + first, count * sizeof(uint64_t));
     return PS_OK;
 }
 
@@ -598,15 +642,25 @@ extern "C" int ps_peptide(const ps_index* ix, uint32_t id, char* buf, size_t cap
 extern "C" int ps_index_host_arrays(const ps_index* ix, uint64_t* bin_off, uint32_t* postings) {
     if (!ix) return fail(PS_EINVAL, "NULL index");
     if (bin_off) memcpy(bin_off, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
-    if (postings) memcpy(postings, ix->post.data(), ix->post.size() * sizeof(uint32_t));
+    if (postings && ix->device_built) {
+        hipError_t e = hipMemcpy(postings, ix->dev.post, ix->dev_n_post * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(PS_EDEVICE, "postings to host: %s", hipGetErrorString(e));
+    } else if (postings) {
+        memcpy(postings, ix->post.data(), ix->post.size() * sizeof(uint32_t));
+    }
     return PS_OK;
 }
 
 extern "C" int ps_index_directory(const ps_index* ix, uint32_t* grain_shift, uint64_t* bytes, uint32_t* dir) {
     if (!ix) return fail(PS_EINVAL, "NULL index");
     if (grain_shift) *grain_shift = ix->dir_shift;
-    if (bytes) *bytes = ix->dir.size() * sizeof(uint32_t);
-    if (dir) memcpy(dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
+    if (bytes) *bytes = dir_entries(ix) * sizeof(uint32_t);
+    if (dir && ix->device_built) {
+        hipError_t e = hipMemcpy(dir, ix->dev.dir, ix->dev_dir_entries * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(PS_EDEVICE, "directory to host: %s", hipGetErrorString(e));
+    } else if (dir) {
+        memcpy(dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
+    }
     return PS_OK;
 }
 

@@ -57,8 +57,33 @@ struct ps_index {
     // device copy
     bool on_device = false;
     ps::DevIndex dev{};
+    // built on the device: postings and directory exist only there
+    bool device_built = false;
+    uint64_t dev_n_post = 0, dev_dir_entries = 0;
 };
 
 namespace ps {
+int index_prepare(const ps_db_params* params, const char* residues, const uint64_t* prot_off, uint64_t n_proteins,
+                  ps_index** out);
 int index_build_host(ps_index* ix);
+
+inline uint64_t n_postings(const ps_index* ix) { return ix->device_built ? ix->dev_n_post : ix->post.size(); }
+inline uint64_t dir_entries(const ps_index* ix) { return ix->device_built ? ix->dev_dir_entries : ix->dir.size(); }
+
+// Device layout of an index block: [mass][bin_off][post][lf][ls][dir], each 256-byte aligned.
+struct DevLayout {
+    uint64_t mass, bin, post, lf, ls, dir, total;
+};
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_post, uint64_t n_dir);
+// Point ix->dev at an index block laid out by `lay` and mark the index on the device.
+void bind_device_index(ps_index* ix, char* base, const DevLayout& lay);
+// Modification lookup: which mod (if any) sits on each residue letter; the N-terminal mod.
+struct ModTable {
+    int res_mod[26];
+    int nterm_mod;
+};
+ModTable mod_table(const ps_index* ix);
+int64_t lightest_residue(const ps_index* ix, const ModTable& mt);
+// Directory grain for n_pep ids over n_bins bins (4096 ids unless the directory would pass 16 GiB).
+uint32_t directory_shift(uint64_t n_bins, uint64_t n_pep);
 }

@@ -71,6 +71,37 @@ class HostIndex:
         self.handle = h
         self.arena = None
 
+    @classmethod
+    def build_on_device(cls, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int, max_len: int,
+                        mods: list, max_mods: int, merge_tol: int = 0, n_shards: int = 1, shard: int = 0,
+                        device: str = "cuda:0", stream=None) -> "HostIndex":
+        """The same index built on the GPU (ps_index_build_device), already resident:
+        no upload() needed.  The build's scratch block is freed on return."""
+        torch = _torch()
+        self = cls.__new__(cls)
+        self._res = np.ascontiguousarray(residues, dtype=np.uint8)
+        self._off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        self.merge_tol = int(merge_tol)
+        self.n_shards, self.shard = int(n_shards), int(shard)
+        p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods, self.merge_tol, self.n_shards,
+                                   self.shard)
+        ib, sb = C.c_uint64(), C.c_uint64()
+        n_prot = self._off.shape[0] - 1
+        check(capi.ps_index_build_device_bytes(C.byref(p), ptr(self._res), ptr(self._off), n_prot, C.byref(ib),
+                                               C.byref(sb)), "ps_index_build_device_bytes")
+        self.arena = torch.empty(max(ib.value, 256), dtype=torch.uint8, device=device)
+        scratch = torch.empty(max(sb.value, 256), dtype=torch.uint8, device=device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        dev = capi.ps_device(self.arena.data_ptr(), self.arena.numel(), st.cuda_stream)
+        scr = capi.ps_device(scratch.data_ptr(), scratch.numel(), st.cuda_stream)
+        h = C.c_void_p()
+        self.handle = None
+        check(capi.ps_index_build_device(C.byref(p), ptr(self._res), ptr(self._off), n_prot, C.byref(dev),
+                                         C.byref(scr), C.byref(h)), "ps_index_build_device")
+        self.handle = h
+        del scratch
+        return self
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
@@ -89,6 +120,17 @@ class HostIndex:
         m, p, s, n, k = C.c_int64(), C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint64()
         check(capi.ps_index_entry(self.handle, pid, C.byref(m), C.byref(p), C.byref(s), C.byref(n), C.byref(k)))
         return m.value, p.value, s.value, n.value, k.value
+
+    def entries(self):
+        """Every entry as a structured array (mass, prot, start, len, mask)."""
+        n = len(self)
+        out = np.zeros(n, dtype=[("mass", "<i8"), ("prot", "<u4"), ("start", "<u4"), ("len", "<u4"),
+                                 ("mask", "<u8")])
+        m = np.zeros(n, np.int64); p = np.zeros(n, np.uint32); s = np.zeros(n, np.uint32)
+        ln = np.zeros(n, np.uint8); k = np.zeros(n, np.uint64)
+        check(capi.ps_index_entries(self.handle, 0, n, ptr(m), ptr(p), ptr(s), ptr(ln), ptr(k)))
+        out["mass"], out["prot"], out["start"], out["len"], out["mask"] = m, p, s, ln, k
+        return out
 
     def peptide(self, pid: int) -> str:
         buf = C.create_string_buffer(512)

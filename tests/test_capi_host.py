@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 from paper_2102_02286_amd import capi, engine, synth
+from paper_2102_02286_amd.capi import ptr
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -101,6 +102,9 @@ def test_index_create_rejects_bad_input():
     with pytest.raises(capi.PsError):
         engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20,
                          [engine.Mod("ST", 1), engine.Mod("TY", 2)], 1)        # T in two mods
+    with pytest.raises(capi.PsError) as e:
+        engine.HostIndex(ok.residues, ok.offsets, 1, 4, 20, [engine.Mod("G", -56_500_000)], 1)   # G -> 0.5 Da
+    assert "lighter" in str(e.value)
 
 
 def test_no_device_is_reported_not_crashed():
@@ -264,3 +268,33 @@ def test_partition_and_assemble_argument_checks_without_device():
     assert capi.ps_assemble(None, 2, parts, 1, 5, 0, 1, 1, 1) == capi.PS_EINVAL     # NULL partition pointers
     assert "partition 0" in capi.last_error()
     assert capi.ps_assemble(None, 2, parts, 0, 5, 0, None, None, None) == capi.PS_OK  # nothing to do
+
+
+def test_bulk_entries_match_single_entries():
+    prot = synth.make_proteome(20, seed=8)
+    h = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, engine.mods_from_synth([synth.OXIDATION]), 2)
+    tab = h.entries()
+    for pid in range(0, len(h), 37):
+        assert h.entry(pid) == tuple(int(x) for x in tab[pid])
+    assert capi.ps_index_entries(h.handle, len(h), 1, None, None, None, None, None) == capi.PS_EINVAL
+    assert capi.ps_index_entries(h.handle, len(h), 0, None, None, None, None, None) == capi.PS_OK
+
+
+def test_device_build_without_device():
+    """The device build checks its arguments like ps_index_create, then needs a GPU."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present")
+    ok = synth.Proteome(np.frombuffer(b"PEPTIDEKAAAAR", np.uint8).copy(), np.array([0, 13], np.uint64))
+    p, keep = engine._db_params(1, 4, 20, [], 0)
+    a, b = C.c_uint64(), C.c_uint64()
+    assert capi.ps_index_build_device_bytes(C.byref(p), ptr(ok.residues), ptr(ok.offsets), 1, C.byref(a),
+                                            C.byref(b)) == capi.PS_EDEVICE
+    bad, keep2 = engine._db_params(1, 10, 5, [], 0)            # min_len > max_len
+    assert capi.ps_index_build_device_bytes(C.byref(bad), ptr(ok.residues), ptr(ok.offsets), 1, C.byref(a),
+                                            C.byref(b)) == capi.PS_EINVAL
+    dev = capi.ps_device(None, 0, None)
+    out = C.c_void_p()
+    assert capi.ps_index_build_device(C.byref(p), ptr(ok.residues), ptr(ok.offsets), 1, C.byref(dev), C.byref(dev),
+                                      C.byref(out)) == capi.PS_EDEVICE
+    assert not out.value
