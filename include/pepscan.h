@@ -210,7 +210,9 @@ int ps_index_shape(const ps_index* idx, uint64_t* n_peptides, uint64_t* n_postin
  * sites); the GPU writes the entries, sorts them by mass (stable radix sort, so
  * ties keep the (protein, start, length, site mask) order), generates the b/y
  * ions and fills the CSR lists with a counting sort done in chunks of at most
- * 2^27 (bin, posting) pairs, then the tile directory.  The result is identical
+ * chunk_pairs_cap (bin, posting) pairs (0: 2^29; a chunk always holds at least
+ * one peptide's postings), then the tile directory.  More than one chunk costs
+ * a second pass over the pairs but bounds the scratch memory.  The result is identical
  * to ps_index_create + ps_index_upload (every array bit for bit), already on the
  * device.  Its postings and directory stay on the device; ps_index_host_arrays
  * and ps_index_directory copy them back on request.
@@ -224,10 +226,11 @@ int ps_index_shape(const ps_index* idx, uint64_t* n_peptides, uint64_t* n_postin
  * `scratch`; blocks until done, on index_block->stream.  Errors as
  * ps_index_create, plus PS_ENOMEM when a block is too small. */
 int ps_index_build_device_bytes(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
-                                uint64_t n_proteins, uint64_t* index_bytes, uint64_t* scratch_bytes);
+                                uint64_t n_proteins, uint64_t chunk_pairs_cap, uint64_t* index_bytes,
+                                uint64_t* scratch_bytes);
 int ps_index_build_device(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
-                          uint64_t n_proteins, const ps_device* index_block, const ps_device* scratch,
-                          ps_index** out);
+                          uint64_t n_proteins, uint64_t chunk_pairs_cap, const ps_device* index_block,
+                          const ps_device* scratch, ps_index** out);
 
 /* Entry `id`: mass (uDa), protein, start, length, site mask.  Mask bit i is
  * the i-th modifiable site, the protein N-terminus first, then residues by

@@ -98,9 +98,10 @@ _SIGS = [
     ("ps_build_index", C.c_int, [C.POINTER(ps_device), C.POINTER(ps_db_params), _P, _P, C.c_uint64,
                                  C.POINTER(_P)]),
     ("ps_index_shape", C.c_int, [_P, _U64P, _U64P, _U64P]),
-    ("ps_index_build_device_bytes", C.c_int, [C.POINTER(ps_db_params), _P, _P, C.c_uint64, _U64P, _U64P]),
-    ("ps_index_build_device", C.c_int, [C.POINTER(ps_db_params), _P, _P, C.c_uint64, C.POINTER(ps_device),
-                                        C.POINTER(ps_device), C.POINTER(_P)]),
+    ("ps_index_build_device_bytes", C.c_int, [C.POINTER(ps_db_params), _P, _P, C.c_uint64, C.c_uint64, _U64P,
+                                              _U64P]),
+    ("ps_index_build_device", C.c_int, [C.POINTER(ps_db_params), _P, _P, C.c_uint64, C.c_uint64,
+                                        C.POINTER(ps_device), C.POINTER(ps_device), C.POINTER(_P)]),
     ("ps_index_entry", C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                                  C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), _U64P]),
     ("ps_index_entries", C.c_int, [_P, C.c_uint64, C.c_uint64, _P, _P, _P, _P, _P]),

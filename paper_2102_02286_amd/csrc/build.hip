@@ -3,12 +3,12 @@
 // Superstep 1 of HiCOPS (arXiv 2102.02286; Supplementary Algorithm 1): generate
 // every database entry, sort the entries, generate their b/y ions and index
 // them.  The same index as index_build_host, bit for bit, made on the GPU:
-//   1. host: count each protein's entries (peptides x modification subsets) with
-//      binomial sums, which fixes where each protein's entries go (no
-//      materialisation on the host);
-//   2. k_gen_entries: one thread per protein writes its entries in (start,
-//      length, site mask) order, so generation order is the tie order of the
-//      key (mass, protein, start, length, mask);
+//   1. host: count the entries (peptides x modification subsets) of every
+//      cleavage start with binomial sums, which fixes where each start's entries
+//      go (no materialisation on the host);
+//   2. k_gen_entries: one thread per start writes its entries in (length, site
+//      mask) order; starts are in (protein, position) order, so generation order
+//      is the tie order of the key (mass, protein, start, length, mask);
 //   3. a stable radix sort by mass then gives the id order; a partition keeps
 //      every G-th rank;
 //   4. ions: per entry 2(n-1) b/y ions, each posted to the 2T+1 bins of a
@@ -37,7 +37,7 @@ namespace ps {
 
 namespace {
 
-constexpr uint64_t kChunkPairs = 1ull << 27;   // (bin, posting) pairs sorted at a time
+constexpr uint64_t kChunkPairs = 1ull << 29;   // (bin, posting) pairs sorted at a time (8.6 GB of buffers)
 
 __constant__ int64_t c_residue[26] = {
     71037114, -1, 103009185, 115026943, 129042593, 147068414, 57021464, 137058912,   // A..H
@@ -81,8 +81,10 @@ __device__ int64_t site_shift(const char* s, uint32_t a, uint32_t len, uint64_t 
 struct GenArgs {
     const char* seq;
     const uint64_t* prot_off;
-    const uint64_t* ent_off;     // first entry of each protein (host count)
-    uint64_t n_prot;
+    const uint32_t* st_prot;     // cleavage starts with entries: protein, position, first entry
+    const uint32_t* st_pos;
+    const uint64_t* st_off;
+    uint64_t n_starts;
     uint32_t missed, min_len, max_len, max_mods;
     ModArgs mods;
     int64_t min_mass;
@@ -95,52 +97,51 @@ struct GenArgs {
     uint32_t* idx;               // generation index, the sort payload
 };
 
-// One thread per protein: every peptide (trypsin, missed cleavages, length
-// range), and for each every subset of <= max_mods sites in increasing mask
-// order.  The walk is the host count's walk, so entry k of protein p lands at
-// ent_off[p] + k.
+// One thread per cleavage start: every peptide from it (trypsin, missed
+// cleavages, length range), and for each every subset of <= max_mods sites in
+// increasing mask order.  The walk is the host census's walk, so entry k of
+// start i lands at st_off[i] + k.
 __global__ void k_gen_entries(GenArgs A) {
-    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < A.n_prot;
-         p += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n_starts;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = A.st_prot[i];
+        const uint64_t a = A.st_pos[i];
         const char* s = A.seq + A.prot_off[p];
         const uint64_t n = A.prot_off[p + 1] - A.prot_off[p];
-        uint64_t o = A.ent_off[p];
-        for (uint64_t a = 0; a < n; ++a) {
-            if (a != 0 && !cut_after(s, n, a - 1)) continue;
-            uint32_t missed = 0;
-            int64_t base = kWaterUda;
-            for (uint64_t e = a + 1; e <= n; ++e) {
-                const uint64_t len = e - a;
-                if (len > A.max_len) break;
-                base += c_residue[s[e - 1] - 'A'];
-                const bool end = (e == n) || cut_after(s, n, e - 1);
-                if (!end) continue;
-                if (len >= A.min_len) {
-                    uint32_t ns = (a == 0 && A.mods.nterm_mod >= 0) ? 1u : 0u;
-                    for (uint64_t j = a; j < e; ++j) ns += A.mods.res_mod[s[j] - 'A'] >= 0 ? 1u : 0u;
-                    const uint64_t full = ns >= 64 ? ~0ull : (1ull << ns) - 1ull;   // ns <= 63 (checked)
-                    uint64_t mask = 0;
-                    while (true) {
-                        const int64_t m = base + site_shift(s, (uint32_t)a, (uint32_t)len, mask, A.mods);
-                        A.mass[o] = m;
-                        A.prot[o] = (uint32_t)p;
-                        A.start[o] = (uint32_t)a;
-                        A.len[o] = (uint8_t)len;
-                        A.mask[o] = mask;
-                        A.key[o] = (uint64_t)(m - A.min_mass);
-                        A.idx[o] = (uint32_t)o;
-                        ++o;
-                        // next mask in increasing order with at most max_mods bits: a mask with
-                        // too many bits is skipped together with every mask that only adds
-                        // bits below its lowest one
-                        uint64_t y = mask + 1;
-                        while (y != 0 && y <= full && (uint32_t)__popcll(y) > A.max_mods) y += y & (~y + 1);
-                        if (y == 0 || y > full) break;
-                        mask = y;
-                    }
+        uint64_t o = A.st_off[i];
+        uint32_t missed = 0;
+        int64_t base = kWaterUda;
+        for (uint64_t e = a + 1; e <= n; ++e) {
+            const uint64_t len = e - a;
+            if (len > A.max_len) break;
+            base += c_residue[s[e - 1] - 'A'];
+            const bool end = (e == n) || cut_after(s, n, e - 1);
+            if (!end) continue;
+            if (len >= A.min_len) {
+                uint32_t ns = (a == 0 && A.mods.nterm_mod >= 0) ? 1u : 0u;
+                for (uint64_t j = a; j < e; ++j) ns += A.mods.res_mod[s[j] - 'A'] >= 0 ? 1u : 0u;
+                const uint64_t full = ns >= 64 ? ~0ull : (1ull << ns) - 1ull;   // ns <= 63 (checked)
+                uint64_t mask = 0;
+                while (true) {
+                    const int64_t m = base + site_shift(s, (uint32_t)a, (uint32_t)len, mask, A.mods);
+                    A.mass[o] = m;
+                    A.prot[o] = p;
+                    A.start[o] = (uint32_t)a;
+                    A.len[o] = (uint8_t)len;
+                    A.mask[o] = mask;
+                    A.key[o] = (uint64_t)(m - A.min_mass);
+                    A.idx[o] = (uint32_t)o;
+                    ++o;
+                    // next mask in increasing order with at most max_mods bits: a mask with
+                    // too many bits is skipped together with every mask that only adds
+                    // bits below its lowest one
+                    uint64_t y = mask + 1;
+                    while (y != 0 && y <= full && (uint32_t)__popcll(y) > A.max_mods) y += y & (~y + 1);
+                    if (y == 0 || y > full) break;
+                    mask = y;
                 }
-                if (e < n && ++missed > A.missed) break;
             }
+            if (e < n && ++missed > A.missed) break;
         }
     }
 }
@@ -344,7 +345,8 @@ uint32_t bit_length(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) 
 
 // Host count: entries per protein and the quantities the layout needs.
 struct Census {
-    std::vector<uint64_t> ent_off;   // [n_prot + 1]
+    std::vector<uint32_t> st_prot, st_pos;   // cleavage starts with at least one entry
+    std::vector<uint64_t> st_off;            // [starts + 1] first entry of each start
     uint64_t D_all = 0;
     int64_t min_mass = 0, max_mass = 0;
     uint32_t max_len = 0;
@@ -359,8 +361,10 @@ int census(const ps_index* ix, Census& C) {
     for (int a = 0; a < 64; ++a)
         for (int b = 0; b < 64; ++b) binom[a][b] = b == 0 ? 1 : (a == 0 ? 0 : binom[a - 1][b - 1] + binom[a - 1][b]);
     const unsigned T = worker_threads();
-    std::vector<uint64_t> cnt(n_prot, 0);
-    struct Part { int64_t lo = INT64_MAX, hi = INT64_MIN; uint32_t max_len = 0; uint64_t pairs = 0; };
+    struct Part {
+        int64_t lo = INT64_MAX, hi = INT64_MIN; uint32_t max_len = 0; uint64_t pairs = 0;
+        std::vector<uint32_t> prot, pos; std::vector<uint64_t> cnt;
+    };
     std::vector<Part> parts(T);
     std::atomic<int> bad{0};
     const uint64_t chunk = (n_prot + T - 1) / std::max<uint64_t>(T, 1);
@@ -374,9 +378,9 @@ int census(const ps_index* ix, Census& C) {
             for (uint64_t p = pa; p < pb; ++p) {
                 const char* s = ix->seq.data() + ix->prot_off[p];
                 const uint64_t n = ix->prot_off[p + 1] - ix->prot_off[p];
-                uint64_t c = 0;
                 for (uint64_t a = 0; a < n; ++a) {
                     if (a != 0 && !is_cut(s, n, a - 1)) continue;
+                    uint64_t c = 0;
                     uint32_t missed = 0;
                     int64_t base = kWaterUda;
                     for (uint64_t e = a + 1; e <= n; ++e) {
@@ -410,21 +414,25 @@ int census(const ps_index* ix, Census& C) {
                         }
                         if (e < n && ++missed > ix->missed) break;
                     }
+                    if (c) { P.prot.push_back((uint32_t)p); P.pos.push_back((uint32_t)a); P.cnt.push_back(c); }
                 }
-                cnt[p] = c;
             }
         });
     }
     for (auto& x : th) x.join();
     if (bad == 1) return fail(PS_EINVAL, "a peptide has more than 63 modifiable sites");
     if (bad == 2) return fail(PS_EOVERFLOW, "one peptide has 2^31 or more modified forms");
-    C.ent_off.assign(n_prot + 1, 0);
-    for (uint64_t p = 0; p < n_prot; ++p) {
-        C.ent_off[p + 1] = C.ent_off[p] + cnt[p];
-        if (C.ent_off[p + 1] >= (1ull << 31))
-            return fail(PS_EOVERFLOW, "more than 2^31 database entries");
+    C.st_off.assign(1, 0);
+    for (Part& P : parts) {                   // threads hold consecutive protein ranges
+        C.st_prot.insert(C.st_prot.end(), P.prot.begin(), P.prot.end());
+        C.st_pos.insert(C.st_pos.end(), P.pos.begin(), P.pos.end());
+        for (uint64_t c : P.cnt) {
+            C.st_off.push_back(C.st_off.back() + c);
+            if (C.st_off.back() >= (1ull << 31)) return fail(PS_EOVERFLOW, "more than 2^31 database entries");
+        }
+        std::vector<uint32_t>().swap(P.prot); std::vector<uint32_t>().swap(P.pos); std::vector<uint64_t>().swap(P.cnt);
     }
-    C.D_all = C.ent_off[n_prot];
+    C.D_all = C.st_off.back();
     C.min_mass = INT64_MAX;
     C.max_mass = INT64_MIN;
     uint64_t pairs_all = 0;
@@ -456,7 +464,7 @@ uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
 
 // Scratch layout of a build; sizes only when base is NULL.
 struct Scratch {
-    char* seq; uint64_t* prot_off; uint64_t* ent_off;
+    char* seq; uint64_t* prot_off; uint32_t* st_prot; uint32_t* st_pos; uint64_t* st_off;
     int64_t* g_mass; uint32_t* g_prot; uint32_t* g_start; uint8_t* g_len; uint64_t* g_mask;
     uint64_t* key0; uint64_t* key1; uint32_t* idx0; uint32_t* idx1;
     uint32_t* l_prot; uint32_t* l_start; uint8_t* l_len; uint64_t* l_mask;
@@ -476,7 +484,10 @@ Scratch layout_scratch(char* base, const ps_index* ix, const Census& C, uint64_t
     const uint64_t Da = std::max<uint64_t>(C.D_all, 1), D = std::max<uint64_t>(C.D, 1);
     S.seq = (char*)take(ix->seq.size() + 1);
     S.prot_off = (uint64_t*)take(np * 8);
-    S.ent_off = (uint64_t*)take(np * 8);
+    const uint64_t ns = std::max<uint64_t>(C.st_prot.size(), 1);
+    S.st_prot = (uint32_t*)take(ns * 4);
+    S.st_pos = (uint32_t*)take(ns * 4);
+    S.st_off = (uint64_t*)take((ns + 1) * 8);
     S.g_mass = (int64_t*)take(Da * 8);
     S.g_prot = (uint32_t*)take(Da * 4);
     S.g_start = (uint32_t*)take(Da * 4);
@@ -527,7 +538,14 @@ uint64_t temp_bytes_for(const Census& C, uint64_t chunk, hipStream_t st, hipErro
     return std::max(std::max(a, b), std::max(c, d)) + 4096;
 }
 
-uint64_t chunk_pairs(const Census& C) { return std::max<uint64_t>(1, std::min<uint64_t>(C.post_cap, kChunkPairs)); }
+// Pairs per chunk: the caller's cap (0: the default), at least one entry's
+// worth, at most what the database has.
+uint64_t chunk_pairs(const Census& C, uint64_t cap, uint32_t width) {
+    const uint64_t one = 2ull * (C.max_len > 0 ? C.max_len - 1 : 0) * width;
+    uint64_t c = cap ? cap : kChunkPairs;
+    c = std::max<uint64_t>(c, one);
+    return std::max<uint64_t>(1, std::min<uint64_t>(C.post_cap, c));
+}
 
 }  // namespace
 
@@ -536,7 +554,8 @@ uint64_t chunk_pairs(const Census& C) { return std::max<uint64_t>(1, std::min<ui
 using namespace ps;
 
 extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
-                                           uint64_t n_proteins, uint64_t* index_bytes, uint64_t* scratch_bytes) {
+                                           uint64_t n_proteins, uint64_t chunk_pairs_cap, uint64_t* index_bytes,
+                                           uint64_t* scratch_bytes) {
     if (!index_bytes || !scratch_bytes) return fail(PS_EINVAL, "NULL argument");
     ps_index* ix = nullptr;
     int rc = index_prepare(params, residues, prot_off, n_proteins, &ix);
@@ -546,7 +565,7 @@ extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const cha
     if (rc == PS_OK) rc = require_device();
     if (rc == PS_OK) {
         hipError_t e;
-        const uint64_t chunk = chunk_pairs(C);
+        const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
         const uint64_t tb = temp_bytes_for(C, chunk, nullptr, &e);
         if (e != hipSuccess) rc = fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e));
         *index_bytes = index_layout(C.D, C.n_bins, C.post_cap, C.n_bins * C.dir_stride).total;
@@ -557,8 +576,8 @@ extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const cha
 }
 
 extern "C" int ps_index_build_device(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
-                                     uint64_t n_proteins, const ps_device* index_block, const ps_device* scratch,
-                                     ps_index** out) {
+                                     uint64_t n_proteins, uint64_t chunk_pairs_cap, const ps_device* index_block,
+                                     const ps_device* scratch, ps_index** out) {
     if (!out) return fail(PS_EINVAL, "out is NULL");
     *out = nullptr;
     if (!index_block || !scratch) return fail(PS_EINVAL, "NULL device block");
@@ -573,7 +592,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     if (rc != PS_OK) return bail(rc);
     hipStream_t st = (hipStream_t)index_block->stream;
     hipError_t e = hipSuccess;
-    const uint64_t chunk = chunk_pairs(C);
+    const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
     const uint64_t tb = temp_bytes_for(C, chunk, st, &e);
     if (e != hipSuccess) return bail(fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e)));
     const DevLayout lay = index_layout(C.D, C.n_bins, C.post_cap, C.n_bins * C.dir_stride);
@@ -603,13 +622,18 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     // inputs
     chk(hipMemcpyAsync(S.seq, ix->seq.data(), ix->seq.size(), hipMemcpyHostToDevice, st));
     chk(hipMemcpyAsync(S.prot_off, ix->prot_off.data(), (n_prot + 1) * 8, hipMemcpyHostToDevice, st));
-    chk(hipMemcpyAsync(S.ent_off, C.ent_off.data(), (n_prot + 1) * 8, hipMemcpyHostToDevice, st));
+    const uint64_t n_starts = C.st_prot.size();
+    if (n_starts) {
+        chk(hipMemcpyAsync(S.st_prot, C.st_prot.data(), n_starts * 4, hipMemcpyHostToDevice, st));
+        chk(hipMemcpyAsync(S.st_pos, C.st_pos.data(), n_starts * 4, hipMemcpyHostToDevice, st));
+        chk(hipMemcpyAsync(S.st_off, C.st_off.data(), (n_starts + 1) * 8, hipMemcpyHostToDevice, st));
+    }
     chk(hipMemsetAsync(S.bad, 0, sizeof(int), st));
     // 2. entries
     if (e == hipSuccess && C.D_all > 0) {
-        GenArgs g{S.seq, S.prot_off, S.ent_off, n_prot, ix->missed, ix->min_len, ix->max_len, ix->max_mods, M,
-                  C.min_mass, S.g_mass, S.g_prot, S.g_start, S.g_len, S.g_mask, S.key0, S.idx0};
-        hipLaunchKernelGGL(k_gen_entries, dim3(grid_for(n_prot, 64)), dim3(64), 0, st, g);
+        GenArgs g{S.seq, S.prot_off, S.st_prot, S.st_pos, S.st_off, n_starts, ix->missed, ix->min_len, ix->max_len,
+                  ix->max_mods, M, C.min_mass, S.g_mass, S.g_prot, S.g_start, S.g_len, S.g_mask, S.key0, S.idx0};
+        hipLaunchKernelGGL(k_gen_entries, dim3(grid_for(n_starts, 64)), dim3(64), 0, st, g);
         chk(hipGetLastError());
     }
     // 3. stable sort by mass; the partition takes every G-th rank

@@ -74,9 +74,10 @@ class HostIndex:
     @classmethod
     def build_on_device(cls, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int, max_len: int,
                         mods: list, max_mods: int, merge_tol: int = 0, n_shards: int = 1, shard: int = 0,
-                        device: str = "cuda:0", stream=None) -> "HostIndex":
+                        device: str = "cuda:0", stream=None, chunk_pairs: int = 0) -> "HostIndex":
         """The same index built on the GPU (ps_index_build_device), already resident:
-        no upload() needed.  The build's scratch block is freed on return."""
+        no upload() needed.  The build's scratch block is freed on return;
+        chunk_pairs caps the (bin, posting) pairs sorted at a time (0: default)."""
         torch = _torch()
         self = cls.__new__(cls)
         self._res = np.ascontiguousarray(residues, dtype=np.uint8)
@@ -87,8 +88,8 @@ class HostIndex:
                                    self.shard)
         ib, sb = C.c_uint64(), C.c_uint64()
         n_prot = self._off.shape[0] - 1
-        check(capi.ps_index_build_device_bytes(C.byref(p), ptr(self._res), ptr(self._off), n_prot, C.byref(ib),
-                                               C.byref(sb)), "ps_index_build_device_bytes")
+        check(capi.ps_index_build_device_bytes(C.byref(p), ptr(self._res), ptr(self._off), n_prot, int(chunk_pairs),
+                                               C.byref(ib), C.byref(sb)), "ps_index_build_device_bytes")
         self.arena = torch.empty(max(ib.value, 256), dtype=torch.uint8, device=device)
         scratch = torch.empty(max(sb.value, 256), dtype=torch.uint8, device=device)
         st = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
@@ -96,8 +97,8 @@ class HostIndex:
         scr = capi.ps_device(scratch.data_ptr(), scratch.numel(), st.cuda_stream)
         h = C.c_void_p()
         self.handle = None
-        check(capi.ps_index_build_device(C.byref(p), ptr(self._res), ptr(self._off), n_prot, C.byref(dev),
-                                         C.byref(scr), C.byref(h)), "ps_index_build_device")
+        check(capi.ps_index_build_device(C.byref(p), ptr(self._res), ptr(self._off), n_prot, int(chunk_pairs),
+                                         C.byref(dev), C.byref(scr), C.byref(h)), "ps_index_build_device")
         self.handle = h
         del scratch
         return self

@@ -288,13 +288,13 @@ def test_device_build_without_device():
     ok = synth.Proteome(np.frombuffer(b"PEPTIDEKAAAAR", np.uint8).copy(), np.array([0, 13], np.uint64))
     p, keep = engine._db_params(1, 4, 20, [], 0)
     a, b = C.c_uint64(), C.c_uint64()
-    assert capi.ps_index_build_device_bytes(C.byref(p), ptr(ok.residues), ptr(ok.offsets), 1, C.byref(a),
+    assert capi.ps_index_build_device_bytes(C.byref(p), ptr(ok.residues), ptr(ok.offsets), 1, 0, C.byref(a),
                                             C.byref(b)) == capi.PS_EDEVICE
     bad, keep2 = engine._db_params(1, 10, 5, [], 0)            # min_len > max_len
-    assert capi.ps_index_build_device_bytes(C.byref(bad), ptr(ok.residues), ptr(ok.offsets), 1, C.byref(a),
+    assert capi.ps_index_build_device_bytes(C.byref(bad), ptr(ok.residues), ptr(ok.offsets), 1, 0, C.byref(a),
                                             C.byref(b)) == capi.PS_EINVAL
     dev = capi.ps_device(None, 0, None)
     out = C.c_void_p()
-    assert capi.ps_index_build_device(C.byref(p), ptr(ok.residues), ptr(ok.offsets), 1, C.byref(dev), C.byref(dev),
-                                      C.byref(out)) == capi.PS_EDEVICE
+    assert capi.ps_index_build_device(C.byref(p), ptr(ok.residues), ptr(ok.offsets), 1, 0, C.byref(dev),
+                                      C.byref(dev), C.byref(out)) == capi.PS_EDEVICE
     assert not out.value

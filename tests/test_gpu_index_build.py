@@ -21,10 +21,11 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _both(prot, missed, min_len, max_len, mods, max_mods, **kw):
+def _both(prot, missed, min_len, max_len, mods, max_mods, chunk_pairs=0, **kw):
     m = engine.mods_from_synth(mods)
     host = engine.HostIndex(prot.residues, prot.offsets, missed, min_len, max_len, m, max_mods, **kw)
-    dev = engine.HostIndex.build_on_device(prot.residues, prot.offsets, missed, min_len, max_len, m, max_mods, **kw)
+    dev = engine.HostIndex.build_on_device(prot.residues, prot.offsets, missed, min_len, max_len, m, max_mods,
+                                           chunk_pairs=chunk_pairs, **kw)
     return host, dev
 
 
@@ -40,12 +41,15 @@ def _assert_same_index(host, dev):
     assert host.schedule().tile == dev.schedule().tile
 
 
-@pytest.mark.parametrize("mods,max_mods,T", [([], 0, 0), ([synth.OXIDATION], 2, 1), (ALL_MODS, 3, 2)])
-def test_device_build_equals_host_build(mods, max_mods, T):
-    prot = synth.make_proteome(300, seed=3)
-    _say(f"device build: {len(mods)} mods, max {max_mods}, merge {T}")
-    host, dev = _both(prot, 2, 6, 40, mods, max_mods, merge_tol=T)
-    assert len(host) > 10000
+@pytest.mark.parametrize("mods,max_mods,T,chunk", [([], 0, 0, 0), ([synth.OXIDATION], 2, 1, 0), (ALL_MODS, 3, 2, 0),
+                                                   (ALL_MODS, 2, 1, 1 << 22), ([synth.OXIDATION], 2, 0, 1000)])
+def test_device_build_equals_host_build(mods, max_mods, T, chunk):
+    """chunk > 0 forces the chunked counting sort (many chunks; 1000 pairs is
+    raised to one peptide's worth)."""
+    prot = synth.make_proteome(300 if chunk != 1000 else 20, seed=3)
+    _say(f"device build: {len(mods)} mods, max {max_mods}, merge {T}, chunk {chunk}")
+    host, dev = _both(prot, 2, 6, 40, mods, max_mods, chunk_pairs=chunk, merge_tol=T)
+    assert len(host) > (10000 if chunk != 1000 else 500)
     _assert_same_index(host, dev)
 
 
@@ -54,7 +58,8 @@ def test_device_build_partitions(G):
     prot = synth.make_proteome(200, seed=11)
     for g in range(G):
         _say(f"device build: partition {g} of {G}")
-        host, dev = _both(prot, 1, 7, 30, [synth.OXIDATION, synth.PHOSPHO], 2, merge_tol=1, n_shards=G, shard=g)
+        host, dev = _both(prot, 1, 7, 30, [synth.OXIDATION, synth.PHOSPHO], 2, chunk_pairs=1 << 20, merge_tol=1,
+                          n_shards=G, shard=g)
         _assert_same_index(host, dev)
         # the partition's postings fit the bound the block was sized for
         assert dev.shape()[1] * 4 <= dev.arena.numel()
