@@ -388,8 +388,15 @@ static int64_t bin_of(int64_t m) { return (m + kBinWidth / 2) / kBinWidth; }
 /* Superstep 2 pre-processing and sub-task R's top-B selection, then the peak
  * list expanded over fragment charges.  Returns the number of entries, or -1
  * on invalid input. */
+/* Pre-processing (Superstep 2 names normalising and clearing noise; sub-task R
+ * keeps the B most intense peaks).  Readings: noise clearing drops the peaks
+ * with I < Imax * p / 1000 before the top-B selection (p = noise_permille; the
+ * comparison I * 1000 >= Imax * p is exact in fp64); intensities become integer
+ * q in [1, 100] relative to the most intense peak, linearly or through the
+ * square root: q = round half up of 100 * sqrt(I / Imax), taken as the largest
+ * k with (k - 1/2)^2 <= 10^4 * I / Imax so that no square root is rounded. */
 static int64_t prepare_spectrum(const float* mz, const float* in, uint64_t np, int z,
-                                uint32_t top_b, entry* out) {
+                                const orc_params* P, entry* out) {
     if (z < 1 || z > 8) return -1;
     peak_ref* r = (peak_ref*)malloc((np ? np : 1) * sizeof(peak_ref));
     float imax = 0.0f;
@@ -397,17 +404,29 @@ static int64_t prepare_spectrum(const float* mz, const float* in, uint64_t np, i
         if (!(mz[i] > 0.0f) || !isfinite(mz[i]) || !(in[i] >= 0.0f) || !isfinite(in[i])) {
             free(r); return -1;
         }
-        r[i].idx = i; r[i].mz = mz[i]; r[i].in = in[i];
         if (in[i] > imax) imax = in[i];
     }
-    qsort(r, np, sizeof(peak_ref), peak_rank_cmp);
-    uint64_t keep = np < top_b ? np : top_b;
+    uint64_t alive = 0;
+    for (uint64_t i = 0; i < np; ++i) {
+        if ((double)in[i] * 1000.0 < (double)imax * (double)P->noise_permille) continue;   /* noise */
+        r[alive].idx = i; r[alive].mz = mz[i]; r[alive].in = in[i];
+        ++alive;
+    }
+    qsort(r, alive, sizeof(peak_ref), peak_rank_cmp);
+    uint64_t keep = alive < P->top_peaks ? alive : P->top_peaks;
     int cmax = z - 1 > 1 ? z - 1 : 1;
     int64_t n = 0;
     for (uint64_t k = 0; k < keep; ++k) {
         /* normalise to the most intense peak: integer q in [1, 100] */
         uint32_t q = 1;
-        if (imax > 0.0f) {
+        if (imax > 0.0f && P->intensity == ORC_INTENSITY_SQRT) {
+            double t = (double)r[k].in / (double)imax;
+            t = t * 10000.0;
+            q = 1;
+            for (uint32_t c = 100; c >= 1; --c) {
+                if (((double)c - 0.5) * ((double)c - 0.5) <= t) { q = c; break; }
+            }
+        } else if (imax > 0.0f) {
             double t = (double)r[k].in / (double)imax;
             t = t * 100.0;
             t = t + 0.5;
@@ -468,7 +487,7 @@ static int search_one(job* J) {
     memset(J->stat, 0, sizeof *J->stat);
 
     entry* ent = (entry*)malloc((J->np * 8 + 1) * sizeof(entry));
-    int64_t ne = prepare_spectrum(J->mz, J->in, J->np, J->z, P->top_peaks, ent);
+    int64_t ne = prepare_spectrum(J->mz, J->in, J->np, J->z, P, ent);
     if (ne < 0 || !isfinite(J->prec) || J->prec <= 0.0) { free(ent); return -1; }
 
     /* filter_1: precursor mass window, |M_pep - M_q| <= dM, inclusive. */
@@ -552,7 +571,8 @@ static void* work_loop(void* arg) {
 
 static int params_ok(const orc_params* P) {
     return P->top_k >= 1 && P->top_k <= 64 && P->min_shared >= 1 && P->frag_tol_bins >= 0 &&
-           (P->fit == ORC_FIT_TAIL || P->fit == ORC_FIT_GUMBEL) &&
+           (P->fit == ORC_FIT_TAIL || P->fit == ORC_FIT_GUMBEL) && P->noise_permille <= 1000 &&
+           (P->intensity == ORC_INTENSITY_LINEAR || P->intensity == ORC_INTENSITY_SQRT) &&
            P->window >= 0 && P->top_peaks >= 1;
 }
 

@@ -60,6 +60,8 @@ void orc_ions(const int64_t* res_uda, uint32_t n, int64_t* b_out, int64_t* y_out
 
 #define ORC_FIT_TAIL   0   /* linear tail fit of the log survival function */
 #define ORC_FIT_GUMBEL 1   /* log-Weibull (Gumbel) fit */
+#define ORC_INTENSITY_LINEAR 0   /* q = round(100 I / Imax) */
+#define ORC_INTENSITY_SQRT   1   /* q = round(100 sqrt(I / Imax)) */
 
 typedef struct {
     int32_t  window_is_ppm;   /* 1: window in ppm of the precursor mass; 0: uDa */
@@ -69,6 +71,8 @@ typedef struct {
     uint32_t top_k;           /* k <= 64 */
     uint32_t min_shared;      /* k_min */
     int32_t  fit;             /* ORC_FIT_TAIL or ORC_FIT_GUMBEL */
+    uint32_t noise_permille;  /* peaks below this many thousandths of the most intense are dropped */
+    int32_t  intensity;       /* ORC_INTENSITY_LINEAR or ORC_INTENSITY_SQRT */
 } orc_params;
 
 typedef struct {

@@ -152,15 +152,33 @@ def evalue_numpy(hist: np.ndarray, top_h: float, n_scored: int):
     return 0, n_scored * 10.0 ** (w * top_h + b)
 
 
-def search(db_rows, mz, inten, prec_mz, z, window_is_ppm, window, T, top_b, top_k, kmin):
-    """One spectrum.  Returns dict with window, scored set, top hits, hist, e-value."""
+def _q_sqrt(v, imax):
+    """round(100 * sqrt(v / imax)) half up, in 50-digit decimal arithmetic."""
+    from decimal import ROUND_FLOOR, Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 50
+        x = (Decimal(v) / Decimal(imax)).sqrt() * 100 + Decimal("0.5")
+        return int(x.to_integral_value(rounding=ROUND_FLOOR))
+
+
+def search(db_rows, mz, inten, prec_mz, z, window_is_ppm, window, T, top_b, top_k, kmin, noise_permille=0,
+           intensity="linear"):
+    """One spectrum.  Returns dict with window, scored set, top hits, hist, e-value.
+    noise_permille: peaks below that many thousandths of the most intense one are
+    dropped before the top-B selection; intensity "sqrt": q from the square root
+    of the relative intensity."""
+    from fractions import Fraction
     n = len(mz)
-    order = sorted(range(n), key=lambda i: (-float(inten[i]), float(mz[i]), i))[:top_b]
     imax = max((float(v) for v in inten), default=0.0)
+    alive = [i for i in range(n) if Fraction(float(inten[i])) * 1000 >= Fraction(imax) * noise_permille]
+    order = sorted(alive, key=lambda i: (-float(inten[i]), float(mz[i]), i))[:top_b]
     peaks = []
     for i in order:
         if imax > 0:
-            t = math.floor(float(inten[i]) / imax * 100.0 + 0.5)
+            if intensity == "sqrt":
+                t = _q_sqrt(float(inten[i]), imax)
+            else:
+                t = math.floor(float(inten[i]) / imax * 100.0 + 0.5)
             q = min(100, max(1, t))
         else:
             q = 1

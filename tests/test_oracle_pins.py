@@ -306,22 +306,27 @@ def _tiny_case(seed, mods, max_mods, z_choices=(1, 2, 3, 4), n_spec=12, noise_pe
     return db, rows, _spectra(peak_lists, prec, charges)
 
 
-@pytest.mark.parametrize("seed,window_is_ppm,window,T,top_b,kmin", [
-    (0, False, 300_000_000, 1, 100, 1),
-    (1, False, 50_000_000, 2, 20, 3),
-    (2, True, 20, 2, 100, 1),
-    (3, False, 10**12, 0, 7, 2),
+@pytest.mark.parametrize("seed,window_is_ppm,window,T,top_b,kmin,noise,inten", [
+    (0, False, 300_000_000, 1, 100, 1, 0, "linear"),
+    (1, False, 50_000_000, 2, 20, 3, 0, "linear"),
+    (2, True, 20, 2, 100, 1, 0, "linear"),
+    (3, False, 10**12, 0, 7, 2, 0, "linear"),
+    (4, False, 300_000_000, 1, 100, 1, 150, "linear"),     # noise clearing before top-B
+    (5, False, 300_000_000, 1, 10, 1, 400, "sqrt"),        # noise clearing, square-root intensities
+    (6, False, 10**12, 2, 100, 2, 0, "sqrt"),
 ])
-def test_search_matches_python_bruteforce(seed, window_is_ppm, window, T, top_b, kmin):
+def test_search_matches_python_bruteforce(seed, window_is_ppm, window, T, top_b, kmin, noise, inten):
     mods = [ModSpec("M", 15_994_915), ModSpec("STY", 79_966_331), ModSpec("", 42_010_565, nterm=True)]
     db, rows, sp = _tiny_case(seed, mods, 2)
     assert len(db) == len(rows)
     top_k = 5
-    hits, stats, hist = db.search(sp, window_is_ppm, window, T, top_b, top_k, kmin, threads=3)
+    imode = oracle.INTENSITY_SQRT if inten == "sqrt" else oracle.INTENSITY_LINEAR
+    hits, stats, hist = db.search(sp, window_is_ppm, window, T, top_b, top_k, kmin, threads=3,
+                                  noise_permille=noise, intensity=imode)
     for s in range(sp.n):
         a, b = int(sp.peak_off[s]), int(sp.peak_off[s + 1])
         want = bf.search(rows, sp.mz[a:b], sp.intensity[a:b], sp.precursor_mz[s], int(sp.charge[s]),
-                         window_is_ppm, window, T, top_b, top_k, kmin)
+                         window_is_ppm, window, T, top_b, top_k, kmin, noise_permille=noise, intensity=inten)
         st = stats[s]
         assert int(st["n_window"]) == want["n_window"]
         if want["n_window"]:
@@ -341,7 +346,8 @@ def test_search_matches_python_bruteforce(seed, window_is_ppm, window, T, top_b,
         if want["status"] == 0:
             assert float(st["evalue"]) == pytest.approx(want["evalue"], rel=1e-9)
         # full scored set
-        ids, nb, ny, sq = db.scored(sp, s, window_is_ppm, window, T, top_b, min_shared=kmin)
+        ids, nb, ny, sq = db.scored(sp, s, window_is_ppm, window, T, top_b, min_shared=kmin, noise_permille=noise,
+                                    intensity=imode)
         got = {int(i): (int(x), int(y), int(q)) for i, x, y, q in zip(ids, nb, ny, sq)}
         assert got == {k: v[:3] for k, v in want["scored"].items()}
 
@@ -620,3 +626,37 @@ def test_search_and_assembly_with_the_gumbel_fit():
     ha, sa, ga = oracle.assemble([p[0] for p in parts], [p[1] for p in parts], [p[2] for p in parts],
                                  fit=oracle.FIT_GUMBEL)
     assert _same(hg, ha) and _same(sg, sa) and _same(gg, ga)
+
+
+def test_preprocessing_special_cases():
+    """Noise threshold 0 keeps every peak; a threshold of 1000 keeps only the
+    most intense peak(s); square-root q of exact squares: I / Imax = (k/100)^2
+    gives q = k, and the rounding edge (k - 1/2)^2 is rounded up."""
+    db = _db(["MPEPTIDEKAAGLR"], missed=1, min_len=3, max_len=20)
+    pep = db.residue_masses(0)
+    b, y = oracle.ions(pep)
+    mz = [float(m) * 1e-6 for m in np.concatenate([b, y])]
+    prec = (db.get(0)[0] + 2 * bf.PROTON_UDA) * 1e-6 / 2
+    ints = [1.0 + i for i in range(len(mz))]
+    sp = _spectra([list(zip(mz, ints))], [prec], [2])
+    full = db.search(sp, False, 10**9, 0, 100, 5, 1)
+    zero = db.search(sp, False, 10**9, 0, 100, 5, 1, noise_permille=0)
+    assert _same(full[0], zero[0]) and _same(full[1], zero[1])
+    top = db.search(sp, False, 10**9, 0, 100, 5, 1, noise_permille=1000)
+    pairs = int(top[1][0]["pairs_total"])
+    assert 0 < pairs < int(full[1][0]["pairs_total"])
+    # square-root intensities: only the intensity sums change
+    imax = 10000.0
+    for k in [1, 7, 50, 99, 100]:
+        v = imax * (k / 100.0) ** 2
+        assert bf._q_sqrt(v, imax) == k
+    edge = imax * (6.5 / 100.0) ** 2                 # sqrt = 0.065 exactly: rounds half up to 7
+    assert bf._q_sqrt(edge, imax) == 7
+    # (exact ties like this one are decided on the fp64 value 10^4 * I / Imax, so the
+    # spectrum below stays off them)
+    sp2 = _spectra([[(mz[0], imax), (mz[1], imax * 0.00423), (mz[2], imax * 0.0049)]], [prec], [2])
+    ids, nb, ny, sq = db.scored(sp2, 0, False, 10**9, 0, 100, min_shared=1, intensity=oracle.INTENSITY_SQRT)
+    k = list(ids).index(0)
+    assert int(sq[k]) == 100 + 7 + 7                  # sqrt(0.00423) = 0.06504, sqrt(0.0049) = 0.07
+    ids, nb, ny, sq = db.scored(sp2, 0, False, 10**9, 0, 100, min_shared=1)
+    assert int(sq[list(ids).index(0)]) == 100 + 1 + 1  # linear: 0.423 and 0.49 both round to 0, clamped to 1
