@@ -68,6 +68,9 @@ extern "C" {
 #define PS_FIT_TAIL   0          /* linear fit of the log survival function's tail (Superstep 4) */
 #define PS_FIT_GUMBEL 1          /* log-Weibull (Gumbel) fit by moments (Superstep 4) */
 
+#define PS_INTENSITY_LINEAR 0
+#define PS_INTENSITY_SQRT   1
+
 #define PS_SCHED_PLAIN      0    /* one workgroup per spectrum, separate launches */
 #define PS_SCHED_PERSISTENT 1    /* one persistent work-queue launch (hipGraph) */
 
@@ -143,6 +146,13 @@ typedef struct {
                                  the histogram (bin centres 0.1 j + 0.05), ev = N * S(H1) with
                                  S(h) = 1 - exp(-exp(-(h - mu) / beta)); fewer than 3 non-zero smoothed
                                  bins gives PS_STATUS_FEW_POINTS */
+    uint32_t noise_permille;  /* pre-processing (Superstep 2 names noise clearing): peaks with
+                                 I < Imax * noise_permille / 1000 are dropped before the top-B
+                                 selection; 0..1000, 0 keeps every peak */
+    int32_t  intensity;       /* integer intensities q in [1, 100] relative to the most intense peak:
+                                 PS_INTENSITY_LINEAR q = round half up of 100 I / Imax;
+                                 PS_INTENSITY_SQRT q = the largest k with (k - 1/2)^2 <= 10^4 I / Imax
+                                 (round half up of 100 sqrt(I / Imax), decided in fp64) */
     int32_t  reserved;        /* must be 0 */
 } ps_search_params;
 

@@ -20,6 +20,7 @@ PS_STATUS_OK, PS_STATUS_NO_HITS, PS_STATUS_FEW_POINTS, PS_STATUS_BAD_SLOPE, PS_S
 PS_HIST_BINS = 512
 PS_SCHED_PLAIN, PS_SCHED_PERSISTENT = 0, 1
 PS_FIT_TAIL, PS_FIT_GUMBEL = 0, 1
+PS_INTENSITY_LINEAR, PS_INTENSITY_SQRT = 0, 1
 
 _ERR_NAMES = {1: "PS_EINVAL", 2: "PS_ENOMEM", 3: "PS_EAGAIN", 4: "PS_EDEVICE", 5: "PS_EOVERFLOW"}
 
@@ -54,7 +55,8 @@ class ps_search_params(C.Structure):
     _fields_ = [("window_is_ppm", C.c_int32), ("frag_tol_bins", C.c_int32), ("window", C.c_int64),
                 ("top_peaks", C.c_uint32), ("top_k", C.c_uint32), ("min_shared", C.c_uint32),
                 ("max_charge", C.c_uint32), ("schedule", C.c_int32), ("want_hist", C.c_int32),
-                ("fit", C.c_int32), ("reserved", C.c_int32)]
+                ("fit", C.c_int32), ("noise_permille", C.c_uint32), ("intensity", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ps_schedule(C.Structure):
@@ -82,7 +84,7 @@ HIT_DTYPE = np.dtype([("id", "<u4"), ("n_b", "<u2"), ("n_y", "<u2"), ("sum_q", "
 STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8"), ("status", "<i4"),
                        ("pad", "<i4")])
 assert HIT_DTYPE.itemsize == 24 and STAT_DTYPE.itemsize == 32
-assert C.sizeof(ps_search_params) == 48
+assert C.sizeof(ps_search_params) == 56
 assert C.sizeof(ps_db_params) == 40
 PS_MAX_SHARDS = 64
 

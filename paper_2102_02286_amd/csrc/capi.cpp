@@ -73,6 +73,9 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
     if (p->schedule != PS_SCHED_PLAIN && p->schedule != PS_SCHED_PERSISTENT)
         return fail(PS_EINVAL, "unknown schedule %d", p->schedule);
     if (p->fit != PS_FIT_TAIL && p->fit != PS_FIT_GUMBEL) return fail(PS_EINVAL, "unknown fit %d", p->fit);
+    if (p->noise_permille > 1000) return fail(PS_EINVAL, "noise_permille must be 0..1000");
+    if (p->intensity != PS_INTENSITY_LINEAR && p->intensity != PS_INTENSITY_SQRT)
+        return fail(PS_EINVAL, "unknown intensity normalisation %d", p->intensity);
     if (p->reserved != 0) return fail(PS_EINVAL, "reserved must be 0");
     const uint32_t cmax = p->max_charge > 2 ? p->max_charge - 1 : 1;
     const uint64_t stride = (uint64_t)p->top_peaks * cmax;
@@ -95,6 +98,8 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
     kp->ent_stride = (uint32_t)stride;
     kp->seg_cap = (uint32_t)segs;
     kp->fit = p->fit;
+    kp->noise_permille = p->noise_permille;
+    kp->intensity = p->intensity;
     int rc = check_schedule(*sched);
     if (rc != PS_OK) return rc;
     if (ix && sched->tile < (1u << ix->dir_shift))

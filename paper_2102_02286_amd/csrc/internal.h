@@ -86,6 +86,8 @@ struct KParams {
     uint32_t tile;             // candidates per LDS counter tile: a power of two, >= 1 << dir_shift
     uint32_t tile_shift;       // log2(tile)
     int32_t fit;               // PS_FIT_TAIL or PS_FIT_GUMBEL
+    uint32_t noise_permille;   // peaks below Imax * noise_permille / 1000 are dropped before top-B
+    int32_t intensity;         // PS_INTENSITY_LINEAR or PS_INTENSITY_SQRT
 };
 
 // Workspace pointers of one batch (all inside the caller's device block).

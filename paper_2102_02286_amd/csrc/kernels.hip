@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
     __shared__ float s_mz[PS_MAX_PEAKS_IN];
     __shared__ float s_in[PS_MAX_PEAKS_IN];
     __shared__ uint32_t s_ent[PS_MAX_TOP_PEAKS * (PS_MAX_CHARGE - 1)];
-    __shared__ uint32_t s_flag, s_imax_bits, s_mult;
+    __shared__ uint32_t s_flag, s_imax_bits, s_mult, s_alive;
     __shared__ unsigned long long s_red[kBlock / 64];
     __shared__ uint64_t s_win[2];
     const uint32_t tid = threadIdx.x;
@@ -249,6 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
             s_flag = bad;
             s_imax_bits = 0;
             s_mult = 0;
+            s_alive = 0;
         }
         __syncthreads();
         const uint32_t np = s_flag ? 0u : (uint32_t)(p1 - p0);
@@ -263,7 +264,19 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         const bool bad = s_flag != 0;
         const float imax = __uint_as_float(s_imax_bits);
         const uint32_t cmax = z > 2 ? (uint32_t)(z - 1) : 1u;
-        const uint32_t keep = min(np, kp.top_peaks);
+        // noise clearing: peaks with I * 1000 < Imax * p (exact in fp64) are dropped.  They
+        // are weaker than every peak that stays, so the ranks below are unchanged; only
+        // the number kept is limited by the survivors.
+        uint32_t alive = np;
+        if (kp.noise_permille) {
+            uint32_t mine = 0;
+            for (uint32_t i = tid; i < np; i += kBlock)
+                mine += (double)s_in[i] * 1000.0 >= (double)imax * (double)kp.noise_permille ? 1u : 0u;
+            if (mine) atomicAdd(&s_alive, mine);
+            __syncthreads();
+            alive = s_alive;
+        }
+        const uint32_t keep = min(alive, kp.top_peaks);
         const uint32_t n_ent = bad ? 0u : keep * cmax;
         uint32_t* gent = A.w.entries + s * (uint64_t)kp.ent_stride;
         // top-B by (intensity desc, m/z asc, input order asc): rank = number of better peaks
@@ -278,7 +291,15 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
                 if (rank >= keep) continue;
                 // integer intensity q in [1, 100] relative to the most intense peak
                 uint32_t q = 1;
-                if (imax > 0.0f) {
+                if (imax > 0.0f && kp.intensity == PS_INTENSITY_SQRT) {
+                    // the largest k with (k - 1/2)^2 <= 10^4 I / Imax; the comparisons are exact
+                    const double t = ((double)vi / (double)imax) * 10000.0;
+                    int k = (int)(sqrt(t) + 0.5);
+                    k = k < 1 ? 1 : (k > 100 ? 100 : k);
+                    while (k < 100 && ((double)k + 0.5) * ((double)k + 0.5) <= t) ++k;
+                    while (k > 1 && ((double)k - 0.5) * ((double)k - 0.5) > t) --k;
+                    q = (uint32_t)k;
+                } else if (imax > 0.0f) {
                     double t = (double)vi / (double)imax;
                     t = t * 100.0;
                     t = t + 0.5;

@@ -46,9 +46,11 @@ def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0, n_shards=1
 
 def search_params(window_is_ppm: bool, window: int, frag_tol_bins: int, top_peaks: int, top_k: int = 5,
                   min_shared: int = 4, max_charge: int = 8, schedule: int = capi.PS_SCHED_PLAIN,
-                  want_hist: bool = True, fit: int = capi.PS_FIT_TAIL) -> capi.ps_search_params:
+                  want_hist: bool = True, fit: int = capi.PS_FIT_TAIL, noise_permille: int = 0,
+                  intensity: int = capi.PS_INTENSITY_LINEAR) -> capi.ps_search_params:
     return capi.ps_search_params(int(window_is_ppm), int(frag_tol_bins), int(window), int(top_peaks), int(top_k),
-                                 int(min_shared), int(max_charge), int(schedule), int(bool(want_hist)), int(fit), 0)
+                                 int(min_shared), int(max_charge), int(schedule), int(bool(want_hist)), int(fit),
+                                 int(noise_permille), int(intensity), 0)
 
 
 class HostIndex:

@@ -36,7 +36,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(capi.ps_db_params) == 40
     assert C.sizeof(capi.ps_part) == 24
     assert C.sizeof(capi.ps_spectra) == 48
-    assert C.sizeof(capi.ps_search_params) == 48
+    assert C.sizeof(capi.ps_search_params) == 56
     assert capi.HIT_DTYPE.itemsize == 24 and capi.STAT_DTYPE.itemsize == 32
 
 
@@ -131,7 +131,9 @@ def test_search_params_validation_without_device():
                 engine.search_params(False, 1, 1, 100, min_shared=0),
                 engine.search_params(False, 1, 1, 256, max_charge=8),          # too many segments
                 engine.search_params(True, 2_000_000, 1, 100),
-                engine.search_params(False, 1, 1, 100, fit=2)]:
+                engine.search_params(False, 1, 1, 100, fit=2),
+                engine.search_params(False, 1, 1, 100, noise_permille=1001),
+                engine.search_params(False, 1, 1, 100, intensity=2)]:
         assert capi.ps_workspace_bytes(h.handle, 10, 100, C.byref(bad), C.byref(need)) == capi.PS_EINVAL
     good = engine.search_params(False, 1, 1, 100, max_charge=3)
     assert capi.ps_workspace_bytes(h.handle, 10, 100, C.byref(good), C.byref(need)) == capi.PS_OK

@@ -473,3 +473,21 @@ def test_small_open_merged_lists_parity(small_open_merged, sched, schedule):
     res = engine.search(ix, sp, prm)
     assert_parity(res, oh, ost, og)
     assert res.postings == int(ost["pairs_total"].sum())
+
+
+@pytest.mark.parametrize("noise,inten", [(150, capi.PS_INTENSITY_LINEAR), (0, capi.PS_INTENSITY_SQRT),
+                                         (400, capi.PS_INTENSITY_SQRT), (1000, capi.PS_INTENSITY_LINEAR)])
+def test_preprocessing_variants_parity(small_open, noise, inten):
+    """Noise clearing before the top-B selection and square-root intensities,
+    against the oracle with the same options (both schedules)."""
+    w, prot, sp, ix, db, _ = small_open
+    sub = sp.subset(np.arange(0, 64))
+    oh, ost, og = db.search(sub, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                            noise_permille=noise, intensity=inten)
+    for schedule in (capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT):
+        _say(f"pre-processing: noise {noise} intensity {inten} schedule {schedule}")
+        prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                                   max_charge=3, schedule=schedule, noise_permille=noise, intensity=inten)
+        res = engine.search(ix, sub, prm)
+        assert_parity(res, oh, ost, og)
+        assert res.postings == int(ost["pairs_total"].sum())
