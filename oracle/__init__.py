@@ -35,11 +35,13 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("window_is_ppm", C.c_int32), ("window", C.c_int64), ("frag_tol_bins", C.c_int32),
                 ("top_peaks", C.c_uint32), ("top_k", C.c_uint32), ("min_shared", C.c_uint32),
-                ("fit", C.c_int32), ("noise_permille", C.c_uint32), ("intensity", C.c_int32)]
+                ("fit", C.c_int32), ("noise_permille", C.c_uint32), ("intensity", C.c_int32),
+                ("ion_types", C.c_uint32)]
 
 
 FIT_TAIL, FIT_GUMBEL = 0, 1
 INTENSITY_LINEAR, INTENSITY_SQRT = 0, 1
+ION_A, ION_B, ION_C, ION_X, ION_Y, ION_Z = 1, 2, 4, 8, 16, 32
 
 
 HIT_DTYPE = np.dtype([("id", "<u4"), ("n_b", "<u2"), ("n_y", "<u2"), ("sum_q", "<u4"),
@@ -163,10 +165,11 @@ class Database:
 
     def search(self, sp, window_is_ppm: bool, window: int, frag_tol_bins: int, top_peaks: int,
                top_k: int = 5, min_shared: int = 4, threads: int | None = None, want_hist=True,
-               fit: int = FIT_TAIL, noise_permille: int = 0, intensity: int = INTENSITY_LINEAR):
+               fit: int = FIT_TAIL, noise_permille: int = 0, intensity: int = INTENSITY_LINEAR,
+               ion_types: int = 0):
         n = sp.n
         prm = Params(int(window_is_ppm), int(window), int(frag_tol_bins), int(top_peaks), int(top_k),
-                     int(min_shared), int(fit), int(noise_permille), int(intensity))
+                     int(min_shared), int(fit), int(noise_permille), int(intensity), int(ion_types))
         hits = np.zeros(n * top_k, dtype=HIT_DTYPE)
         stats = np.zeros(n, dtype=STAT_DTYPE)
         hist = np.zeros(n * HIST_BINS, dtype=np.int32) if want_hist else None
@@ -182,9 +185,9 @@ class Database:
 
     def scored(self, sp, s: int, window_is_ppm: bool, window: int, frag_tol_bins: int,
                top_peaks: int, min_shared: int = 4, cap: int = 1 << 22, noise_permille: int = 0,
-               intensity: int = INTENSITY_LINEAR):
+               intensity: int = INTENSITY_LINEAR, ion_types: int = 0):
         prm = Params(int(window_is_ppm), int(window), int(frag_tol_bins), int(top_peaks), 1,
-                     int(min_shared), FIT_TAIL, int(noise_permille), int(intensity))
+                     int(min_shared), FIT_TAIL, int(noise_permille), int(intensity), int(ion_types))
         ids = np.zeros(cap, np.uint32); nb = np.zeros(cap, np.uint16)
         ny = np.zeros(cap, np.uint16); sq = np.zeros(cap, np.uint32)
         off2 = np.ascontiguousarray(sp.peak_off[s:s + 2], np.uint64)

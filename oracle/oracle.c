@@ -42,6 +42,12 @@ static const int64_t kResidue[26] = {
 };
 static const int64_t kWater = 18010565;
 static const int64_t kProton = 1007276;
+/* Other ion series (the Mod Distance text says the method generalises to a, c,
+ * x and z ions): a = b - CO, c = b + NH3, x = y + CO - H2, z = y - NH3.  Masses
+ * from the elements: CO 27.994915, NH3 17.026549, H2 2.015650 Da. */
+static const int64_t kCO = 27994915;
+static const int64_t kNH3 = 17026549;
+static const int64_t kH2 = 2015650;
 static const int64_t kBinWidth = 10000;   /* 0.01 Da */
 
 /* ------------------------------------------------------------------------ */
@@ -502,7 +508,11 @@ static int search_one(job* J) {
     if (hi == 0) lo = hi = 0;
     J->stat->lo = lo; J->stat->hi = hi; J->stat->n_window = hi - lo;
 
-    /* filter_2 + score: generate each candidate's ions, count shared peaks. */
+    /* filter_2 + score: generate each candidate's ions, count shared peaks.
+     * Reading for other ion series: matches of N-terminal ions (a, b, c) count
+     * in n_b and of C-terminal ions (x, y, z) in n_y, so the hyperscore keeps
+     * its two factorials. */
+    const uint32_t types = P->ion_types ? P->ion_types : (ORC_ION_B | ORC_ION_Y);
     int64_t res[64], bi[64], yi[64];
     uint64_t n_scored = 0, pairs_total = 0;
     for (uint64_t id = lo; id < hi; ++id) {
@@ -510,8 +520,12 @@ static int search_one(job* J) {
         orc_ions(res, n, bi, yi);
         uint32_t nb = 0, ny = 0, sq = 0;
         for (uint32_t i = 0; i + 1 < n; ++i) {
-            match_ion(ent, ne, bin_of(bi[i]), P->frag_tol_bins, &nb, &sq);
-            match_ion(ent, ne, bin_of(yi[i]), P->frag_tol_bins, &ny, &sq);
+            if (types & ORC_ION_A) match_ion(ent, ne, bin_of(bi[i] - kCO), P->frag_tol_bins, &nb, &sq);
+            if (types & ORC_ION_B) match_ion(ent, ne, bin_of(bi[i]), P->frag_tol_bins, &nb, &sq);
+            if (types & ORC_ION_C) match_ion(ent, ne, bin_of(bi[i] + kNH3), P->frag_tol_bins, &nb, &sq);
+            if (types & ORC_ION_X) match_ion(ent, ne, bin_of(yi[i] + kCO - kH2), P->frag_tol_bins, &ny, &sq);
+            if (types & ORC_ION_Y) match_ion(ent, ne, bin_of(yi[i]), P->frag_tol_bins, &ny, &sq);
+            if (types & ORC_ION_Z) match_ion(ent, ne, bin_of(yi[i] - kNH3), P->frag_tol_bins, &ny, &sq);
         }
         pairs_total += nb + ny;
         if (nb + ny < P->min_shared) continue;        /* shared peaks >= k */
@@ -572,7 +586,7 @@ static void* work_loop(void* arg) {
 static int params_ok(const orc_params* P) {
     return P->top_k >= 1 && P->top_k <= 64 && P->min_shared >= 1 && P->frag_tol_bins >= 0 &&
            (P->fit == ORC_FIT_TAIL || P->fit == ORC_FIT_GUMBEL) && P->noise_permille <= 1000 &&
-           (P->intensity == ORC_INTENSITY_LINEAR || P->intensity == ORC_INTENSITY_SQRT) &&
+           (P->intensity == ORC_INTENSITY_LINEAR || P->intensity == ORC_INTENSITY_SQRT) && P->ion_types < 64u &&
            P->window >= 0 && P->top_peaks >= 1;
 }
 

@@ -60,6 +60,12 @@ void orc_ions(const int64_t* res_uda, uint32_t n, int64_t* b_out, int64_t* y_out
 
 #define ORC_FIT_TAIL   0   /* linear tail fit of the log survival function */
 #define ORC_FIT_GUMBEL 1   /* log-Weibull (Gumbel) fit */
+#define ORC_ION_A 1u
+#define ORC_ION_B 2u
+#define ORC_ION_C 4u
+#define ORC_ION_X 8u
+#define ORC_ION_Y 16u
+#define ORC_ION_Z 32u
 #define ORC_INTENSITY_LINEAR 0   /* q = round(100 I / Imax) */
 #define ORC_INTENSITY_SQRT   1   /* q = round(100 sqrt(I / Imax)) */
 
@@ -73,6 +79,7 @@ typedef struct {
     int32_t  fit;             /* ORC_FIT_TAIL or ORC_FIT_GUMBEL */
     uint32_t noise_permille;  /* peaks below this many thousandths of the most intense are dropped */
     int32_t  intensity;       /* ORC_INTENSITY_LINEAR or ORC_INTENSITY_SQRT */
+    uint32_t ion_types;       /* ORC_ION_* bits; 0 means b and y */
 } orc_params;
 
 typedef struct {

@@ -55,6 +55,11 @@ _UDA = _uda_table()
 RES_UDA = {k: v for k, v in _UDA.items() if len(k) == 1}
 WATER_UDA = _UDA["water"]
 PROTON_UDA = _UDA["proton"]
+# neutral losses and gains of the other ion series, from the elements
+CO_UDA = round((EL["C"] + EL["O"]) * 1e6)
+NH3_UDA = round((EL["N"] + 3 * EL["H"]) * 1e6)
+H2_UDA = round(2 * EL["H"] * 1e6)
+ION_SHIFT = {"a": -CO_UDA, "b": 0, "c": NH3_UDA, "x": CO_UDA - H2_UDA, "y": 0, "z": -NH3_UDA}
 
 
 def is_cleavage_boundary(seq: str, pos: int) -> bool:
@@ -162,7 +167,7 @@ def _q_sqrt(v, imax):
 
 
 def search(db_rows, mz, inten, prec_mz, z, window_is_ppm, window, T, top_b, top_k, kmin, noise_permille=0,
-           intensity="linear"):
+           intensity="linear", ions="by"):
     """One spectrum.  Returns dict with window, scored set, top hits, hist, e-value.
     noise_permille: peaks below that many thousandths of the most intense one are
     dropped before the top-B selection; intensity "sqrt": q from the square root
@@ -192,8 +197,8 @@ def search(db_rows, mz, inten, prec_mz, z, window_is_ppm, window, T, top_b, top_
     for pid in window_ids:
         r = db_rows[pid][5]
         L = len(r)
-        bs = [sum(r[:i]) + PROTON_UDA for i in range(1, L)]
-        ys = [sum(r[L - i:]) + WATER_UDA + PROTON_UDA for i in range(1, L)]
+        bs = [sum(r[:i]) + PROTON_UDA + ION_SHIFT[t] for t in ions if t in "abc" for i in range(1, L)]
+        ys = [sum(r[L - i:]) + WATER_UDA + PROTON_UDA + ION_SHIFT[t] for t in ions if t in "xyz" for i in range(1, L)]
         nb = ny = s = 0
         for (pm, q) in peaks:
             for c in range(1, cmax + 1):

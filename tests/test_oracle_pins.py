@@ -306,27 +306,35 @@ def _tiny_case(seed, mods, max_mods, z_choices=(1, 2, 3, 4), n_spec=12, noise_pe
     return db, rows, _spectra(peak_lists, prec, charges)
 
 
-@pytest.mark.parametrize("seed,window_is_ppm,window,T,top_b,kmin,noise,inten", [
-    (0, False, 300_000_000, 1, 100, 1, 0, "linear"),
-    (1, False, 50_000_000, 2, 20, 3, 0, "linear"),
-    (2, True, 20, 2, 100, 1, 0, "linear"),
-    (3, False, 10**12, 0, 7, 2, 0, "linear"),
-    (4, False, 300_000_000, 1, 100, 1, 150, "linear"),     # noise clearing before top-B
-    (5, False, 300_000_000, 1, 10, 1, 400, "sqrt"),        # noise clearing, square-root intensities
-    (6, False, 10**12, 2, 100, 2, 0, "sqrt"),
+_ION_BITS = {"a": 1, "b": 2, "c": 4, "x": 8, "y": 16, "z": 32}
+
+
+@pytest.mark.parametrize("seed,window_is_ppm,window,T,top_b,kmin,noise,inten,ions", [
+    (0, False, 300_000_000, 1, 100, 1, 0, "linear", "by"),
+    (1, False, 50_000_000, 2, 20, 3, 0, "linear", "by"),
+    (2, True, 20, 2, 100, 1, 0, "linear", "by"),
+    (3, False, 10**12, 0, 7, 2, 0, "linear", "by"),
+    (4, False, 300_000_000, 1, 100, 1, 150, "linear", "by"),     # noise clearing before top-B
+    (5, False, 300_000_000, 1, 10, 1, 400, "sqrt", "by"),        # noise clearing, square-root intensities
+    (6, False, 10**12, 2, 100, 2, 0, "sqrt", "by"),
+    (7, False, 300_000_000, 1, 100, 1, 0, "linear", "abcxyz"),   # every ion series
+    (8, False, 10**12, 0, 100, 1, 0, "linear", "cz"),            # c and z only
+    (9, True, 50, 2, 60, 2, 100, "sqrt", "axy"),
 ])
-def test_search_matches_python_bruteforce(seed, window_is_ppm, window, T, top_b, kmin, noise, inten):
+def test_search_matches_python_bruteforce(seed, window_is_ppm, window, T, top_b, kmin, noise, inten, ions):
     mods = [ModSpec("M", 15_994_915), ModSpec("STY", 79_966_331), ModSpec("", 42_010_565, nterm=True)]
     db, rows, sp = _tiny_case(seed, mods, 2)
     assert len(db) == len(rows)
     top_k = 5
     imode = oracle.INTENSITY_SQRT if inten == "sqrt" else oracle.INTENSITY_LINEAR
+    itypes = sum(_ION_BITS[c] for c in ions)
     hits, stats, hist = db.search(sp, window_is_ppm, window, T, top_b, top_k, kmin, threads=3,
-                                  noise_permille=noise, intensity=imode)
+                                  noise_permille=noise, intensity=imode, ion_types=itypes)
     for s in range(sp.n):
         a, b = int(sp.peak_off[s]), int(sp.peak_off[s + 1])
         want = bf.search(rows, sp.mz[a:b], sp.intensity[a:b], sp.precursor_mz[s], int(sp.charge[s]),
-                         window_is_ppm, window, T, top_b, top_k, kmin, noise_permille=noise, intensity=inten)
+                         window_is_ppm, window, T, top_b, top_k, kmin, noise_permille=noise, intensity=inten,
+                         ions=ions)
         st = stats[s]
         assert int(st["n_window"]) == want["n_window"]
         if want["n_window"]:
@@ -347,7 +355,7 @@ def test_search_matches_python_bruteforce(seed, window_is_ppm, window, T, top_b,
             assert float(st["evalue"]) == pytest.approx(want["evalue"], rel=1e-9)
         # full scored set
         ids, nb, ny, sq = db.scored(sp, s, window_is_ppm, window, T, top_b, min_shared=kmin, noise_permille=noise,
-                                    intensity=imode)
+                                    intensity=imode, ion_types=itypes)
         got = {int(i): (int(x), int(y), int(q)) for i, x, y, q in zip(ids, nb, ny, sq)}
         assert got == {k: v[:3] for k, v in want["scored"].items()}
 
@@ -660,3 +668,57 @@ def test_preprocessing_special_cases():
     assert int(sq[k]) == 100 + 7 + 7                  # sqrt(0.00423) = 0.06504, sqrt(0.0049) = 0.07
     ids, nb, ny, sq = db.scored(sp2, 0, False, 10**9, 0, 100, min_shared=1)
     assert int(sq[list(ids).index(0)]) == 100 + 1 + 1  # linear: 0.423 and 0.49 both round to 0, clamped to 1
+
+
+def test_other_ion_series_closed_forms():
+    """From the element masses: c_i + z_(n-i) = M + 2 H+ and a_i + x_(n-i) =
+    M + 2 H+ - H2; a single peak placed on each series' first ion of a peptide
+    matches it through the oracle only when that series is switched on."""
+    assert bf.CO_UDA == 27994915 and bf.NH3_UDA == 17026549 and bf.H2_UDA == 2015650
+    db = _db(["MPEPTIDEKAAGLR"], missed=1, min_len=3, max_len=20)
+    pid = 0
+    r = [int(x) for x in db.residue_masses(pid)]
+    M, n = db.get(pid)[0], len(r)
+    for i in range(1, n):
+        pre, suf = sum(r[:i]), sum(r[i:])
+        c = pre + bf.PROTON_UDA + bf.NH3_UDA
+        z = suf + bf.WATER_UDA + bf.PROTON_UDA - bf.NH3_UDA
+        a = pre + bf.PROTON_UDA - bf.CO_UDA
+        x = suf + bf.WATER_UDA + bf.PROTON_UDA + bf.CO_UDA - bf.H2_UDA
+        assert c + z == M + 2 * bf.PROTON_UDA
+        assert a + x == M + 2 * bf.PROTON_UDA - bf.H2_UDA
+    prec = (M + 2 * bf.PROTON_UDA) * 1e-6 / 2
+    firsts = {"a": r[0] + bf.PROTON_UDA - bf.CO_UDA, "c": r[0] + bf.PROTON_UDA + bf.NH3_UDA,
+              "x": r[-1] + bf.WATER_UDA + bf.PROTON_UDA + bf.CO_UDA - bf.H2_UDA,
+              "z": r[-1] + bf.WATER_UDA + bf.PROTON_UDA - bf.NH3_UDA}
+    for t, m in firsts.items():
+        sp = _spectra([[(m * 1e-6, 1.0)]], [prec], [2])
+        ids, nb, ny, sq = db.scored(sp, 0, False, 10**9, 0, 10, min_shared=1, ion_types=_ION_BITS[t])
+        got = dict(zip(ids.tolist(), zip(nb.tolist(), ny.tolist())))
+        # N-terminal series count in n_b, C-terminal ones in n_y
+        assert pid in got and (got[pid][0] if t in "ac" else got[pid][1]) >= 1
+        assert (got[pid][1] if t in "ac" else got[pid][0]) == 0
+
+
+def test_ion_series_offsets_at_bin_edges():
+    """Modification shifts chosen so that the doubly modified GAK has its c1 ion
+    at 4999 and its z1 ion at 5000 uDa past a multiple of 10000, the two sides
+    of a bin edge: a 1-uDa error in NH3 (or CO) moves them to the other bin, and
+    with T = 0 a peak at the centre of the right bin then no longer matches."""
+    mods = [ModSpec("", 42_009_710, nterm=True), ModSpec("K", 15_998_745)]
+    db = _db(["GAK"], missed=0, min_len=3, max_len=3, mods=mods, max_mods=2)
+    tab = db.table()
+    pid = int(np.nonzero(tab["mask"] == 3)[0][0])
+    r = [int(x) for x in db.residue_masses(pid)]
+    c1 = r[0] + bf.PROTON_UDA + bf.NH3_UDA
+    z1 = r[-1] + bf.WATER_UDA + bf.PROTON_UDA - bf.NH3_UDA
+    assert c1 % 10000 == 4999 and z1 % 10000 == 5000
+    peaks = [(bf.bin_of(c1) * 0.01, 1.0), (bf.bin_of(z1) * 0.01, 1.0)]
+    prec = (int(tab["mass"][pid]) + 2 * bf.PROTON_UDA) * 1e-6 / 2
+    sp = _spectra([peaks], [prec], [2])
+    ids, nb, ny, sq = db.scored(sp, 0, False, 10**9, 0, 10, min_shared=1, ion_types=4 | 32)
+    k = list(ids).index(pid)
+    assert (int(nb[k]), int(ny[k])) == (1, 1)
+    want = bf.search([(int(t["mass"]), 0, 0, 0, 0, db.residue_masses(i).tolist()) for i, t in enumerate(tab)],
+                     sp.mz, sp.intensity, prec, 2, False, 10**9, 0, 10, 5, 1, ions="cz")
+    assert want["scored"][pid][:2] == (1, 1)
