@@ -63,6 +63,13 @@ extern "C" {
 #define PS_MAX_SEGMENTS 2048     /* top_peaks * max(1, z-1) * probes per peak (2T+1, or 1 on an
                                     index with merged lists) per spectrum */
 
+#define PS_ION_A 1u               /* a = b - CO */
+#define PS_ION_B 2u
+#define PS_ION_C 4u               /* c = b + NH3 */
+#define PS_ION_X 8u               /* x = y + CO - H2 */
+#define PS_ION_Y 16u
+#define PS_ION_Z 32u              /* z = y - NH3 */
+
 #define PS_MAX_SHARDS 64          /* database partitions one ps_assemble call merges */
 
 #define PS_FIT_TAIL   0          /* linear fit of the log survival function's tail (Superstep 4) */
@@ -113,6 +120,11 @@ typedef struct {
                                          the entries of whole-database rank r with r % G == g, in order, so its
                                          id i is whole-database id i * G + g.  Searches of a partition report
                                          partition ids; ps_assemble turns G partition results into whole ones. */
+    uint32_t      ion_types;          /* fragment ion series indexed, PS_ION_* bits; 0 = b and y (the paper's
+                                         choice; its Mod Distance text says a, c, x, z generalise).  Matches of
+                                         N-terminal series (a, b, c) count in n_b, C-terminal (x, y, z) in n_y.
+                                         With a or x ions every residue must weigh more than 28.05 Da. */
+    uint32_t      reserved;           /* must be 0 */
     const ps_mod* mods;
 } ps_db_params;
 

@@ -43,7 +43,8 @@ class ps_mod(C.Structure):
 class ps_db_params(C.Structure):
     _fields_ = [("missed_cleavages", C.c_uint32), ("min_len", C.c_uint32), ("max_len", C.c_uint32),
                 ("n_mods", C.c_uint32), ("max_mods", C.c_uint32), ("merge_tol_bins", C.c_uint32),
-                ("n_shards", C.c_uint32), ("shard", C.c_uint32), ("mods", C.POINTER(ps_mod))]
+                ("n_shards", C.c_uint32), ("shard", C.c_uint32), ("ion_types", C.c_uint32), ("reserved", C.c_uint32),
+                ("mods", C.POINTER(ps_mod))]
 
 
 class ps_spectra(C.Structure):
@@ -85,7 +86,8 @@ STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8
                        ("pad", "<i4")])
 assert HIT_DTYPE.itemsize == 24 and STAT_DTYPE.itemsize == 32
 assert C.sizeof(ps_search_params) == 56
-assert C.sizeof(ps_db_params) == 40
+assert C.sizeof(ps_db_params) == 48
+PS_ION_A, PS_ION_B, PS_ION_C, PS_ION_X, PS_ION_Y, PS_ION_Z = 1, 2, 4, 8, 16, 32
 PS_MAX_SHARDS = 64
 
 _P = C.c_void_p

@@ -160,7 +160,7 @@ struct TakeArgs {
     uint8_t* len;
     uint64_t* mask;
     uint64_t* pair_cnt;          // [n_local + 1] pairs of each entry (last = 0)
-    uint32_t pairs_per_ion;      // 2T + 1
+    uint32_t pairs_per_ion;      // (2T + 1) x enabled ion series
 };
 
 // Ranks r * G + g of the sorted database become this partition's ids r.
@@ -174,7 +174,7 @@ __global__ void k_take(TakeArgs A) {
         A.start[r] = A.start_in[src];
         A.len[r] = A.len_in[src];
         A.mask[r] = A.mask_in[src];
-        A.pair_cnt[r] = 2ull * (uint64_t)(A.len_in[src] - 1) * A.pairs_per_ion;
+        A.pair_cnt[r] = (uint64_t)(A.len_in[src] - 1) * A.pairs_per_ion;
     }
 }
 
@@ -186,6 +186,7 @@ struct IonArgs {
     const uint8_t* len;
     const uint64_t* mask;
     ModArgs mods;
+    IonSeries ions;              // enabled series, N-terminal first
     int32_t T;                   // merge width (0: classic lists)
     uint64_t n_bins;
     uint64_t r0, r1;             // entries of this pass
@@ -208,9 +209,10 @@ __device__ __forceinline__ int64_t residue_at(const char* s, uint32_t j, uint64_
     return m;
 }
 
-// One thread per entry: b ions (residues 1..i) then y ions (residues n-i+1..n),
-// i = 1..n-1, each to bins bin-T..bin+T, written as (bin, posting) pairs in
-// this order, so a stable sort by bin keeps every list in (id, b before y) order.
+// One thread per entry: for every enabled series, N-terminal ones first, the
+// ions i = 1..n-1 (residues 1..i, or n-i+1..n for C-terminal series), each to
+// bins bin-T..bin+T, written as (bin, posting) pairs in this order, so a stable
+// sort by bin keeps every list in (id, N-terminal before C-terminal) order.
 __global__ void k_ions(IonArgs A) {
     for (uint64_t r = A.r0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < A.r1;
          r += (uint64_t)gridDim.x * blockDim.x) {
@@ -219,22 +221,19 @@ __global__ void k_ions(IonArgs A) {
         const uint64_t mask = A.mask[r];
         const bool nt = A.start[r] == 0 && A.mods.nterm_mod >= 0;
         const int64_t nshift = (nt && (mask & 1ull)) ? A.mods.delta[A.mods.nterm_mod] : 0;
+        uint32_t nsites = nt ? 1u : 0u;                  // every site, for the backward walks
+        for (uint32_t j = 0; j < n; ++j) nsites += A.mods.res_mod[s[j] - 'A'] >= 0 ? 1u : 0u;
         uint64_t w = A.pair_off[r] - A.pair_off[A.r0];
-        for (int y = 0; y < 2; ++y) {
+        for (int t = 0; t < A.ions.n; ++t) {
+            const bool y = A.ions.cterm[t] != 0;
             uint32_t bit = nt ? 1u : 0u;
-            uint32_t nsites = 0;
-            if (y) {   // sites before residue j are needed walking backwards: count them all first
-                uint32_t b2 = bit;
-                for (uint32_t j = 0; j < n; ++j) (void)residue_at(s, j, mask, b2, A.mods);
-                nsites = b2;
-            }
-            int64_t acc = 0;
             uint32_t bit_back = nsites;
+            int64_t acc = 0;
             for (uint32_t i = 1; i < n; ++i) {
                 int64_t ion;
                 if (!y) {
                     acc += residue_at(s, i - 1, mask, bit, A.mods) + (i == 1 ? nshift : 0);
-                    ion = acc + kProtonUda;
+                    ion = acc + kProtonUda + A.ions.shift[t];
                 } else {
                     // residue n-i: its site bit is the number of sites before it
                     const uint32_t j = n - i;
@@ -242,8 +241,8 @@ __global__ void k_ions(IonArgs A) {
                     if (mm >= 0) --bit_back;
                     int64_t m = c_residue[s[j] - 'A'];
                     if (mm >= 0 && (mask >> bit_back & 1ull)) m += A.mods.delta[mm];
-                    acc += m + (j == 0 ? nshift : 0);
-                    ion = acc + kWaterUda + kProtonUda;
+                    acc += m;
+                    ion = acc + kWaterUda + kProtonUda + A.ions.shift[t];
                 }
                 if (ion < 0) { atomicOr(A.bad, 1); continue; }
                 const int64_t bn = (ion + kBinWidth / 2) / kBinWidth;
@@ -357,6 +356,7 @@ struct Census {
 int census(const ps_index* ix, Census& C) {
     const ModTable mt = mod_table(ix);
     const uint64_t n_prot = ix->prot_off.size() - 1;
+    const uint32_t series = (uint32_t)__builtin_popcount(ix->ion_types);
     uint64_t binom[64][64];
     for (int a = 0; a < 64; ++a)
         for (int b = 0; b < 64; ++b) binom[a][b] = b == 0 ? 1 : (a == 0 ? 0 : binom[a - 1][b - 1] + binom[a - 1][b]);
@@ -410,7 +410,7 @@ int census(const ps_index* ix, Census& C) {
                             P.lo = std::min(P.lo, lo);
                             P.hi = std::max(P.hi, hi);
                             P.max_len = std::max(P.max_len, (uint32_t)len);
-                            P.pairs += v * 2ull * (len - 1);
+                            P.pairs += v * (uint64_t)series * (len - 1);
                         }
                         if (e < n && ++missed > ix->missed) break;
                     }
@@ -452,7 +452,7 @@ int census(const ps_index* ix, Census& C) {
     // postings: exact for the whole database; a partition's share is bounded by
     // its entry count times the longest peptide's ions
     uint64_t cap = pairs_all * width;
-    if (G > 1) cap = std::min<uint64_t>(cap, C.D * 2ull * (C.max_len > 0 ? C.max_len - 1 : 0) * width);
+    if (G > 1) cap = std::min<uint64_t>(cap, C.D * (uint64_t)series * (C.max_len > 0 ? C.max_len - 1 : 0) * width);
     C.post_cap = cap;
     C.dir_shift = directory_shift(C.n_bins, C.D);
     C.dir_nblk = (C.D >> C.dir_shift) + 1;
@@ -541,7 +541,7 @@ uint64_t temp_bytes_for(const Census& C, uint64_t chunk, hipStream_t st, hipErro
 // Pairs per chunk: the caller's cap (0: the default), at least one entry's
 // worth, at most what the database has.
 uint64_t chunk_pairs(const Census& C, uint64_t cap, uint32_t width) {
-    const uint64_t one = 2ull * (C.max_len > 0 ? C.max_len - 1 : 0) * width;
+    const uint64_t one = 6ull * (C.max_len > 0 ? C.max_len - 1 : 0) * width;   // six series at most
     uint64_t c = cap ? cap : kChunkPairs;
     c = std::max<uint64_t>(c, one);
     return std::max<uint64_t>(1, std::min<uint64_t>(C.post_cap, c));
@@ -649,13 +649,14 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     const uint32_t width = 2u * ix->merge_tol + 1u;
     if (e == hipSuccess) {
         TakeArgs t{order, C.D, ix->n_shards, ix->shard, S.g_mass, S.g_prot, S.g_start, S.g_len, S.g_mask,
-                   mass, S.l_prot, S.l_start, S.l_len, S.l_mask, S.pair_cnt, width};
+                   mass, S.l_prot, S.l_start, S.l_len, S.l_mask, S.pair_cnt,
+                   width * (uint32_t)__builtin_popcount(ix->ion_types)};
         hipLaunchKernelGGL(k_take, dim3(grid_for(C.D + 1)), dim3(256), 0, st, t);
         chk(hipGetLastError());
     }
     // 4. ions: entry pair offsets, then chunks of (bin, posting) pairs
-    IonArgs io{S.seq, S.prot_off, S.l_prot, S.l_start, S.l_len, S.l_mask, M, (int32_t)ix->merge_tol, C.n_bins,
-               0, C.D, S.pair_off, nullptr, nullptr, S.bad};
+    IonArgs io{S.seq, S.prot_off, S.l_prot, S.l_start, S.l_len, S.l_mask, M, ion_series(ix->ion_types),
+               (int32_t)ix->merge_tol, C.n_bins, 0, C.D, S.pair_off, nullptr, nullptr, S.bad};
     if (e == hipSuccess) {
         size_t tbytes = S.temp_bytes;
         chk(hipcub::DeviceScan::ExclusiveSum(S.temp, tbytes, S.pair_cnt, S.pair_off, (int)(C.D + 1), st));

@@ -239,6 +239,7 @@ int index_build_host(ps_index* ix) {
     ix->n_bins = nbins;
     std::vector<std::vector<uint32_t>> cnt(T);
     std::atomic<int> bad_mass{0};
+    const IonSeries ions = ion_series(ix->ion_types);
     parallel_for(D, T, [&](unsigned t, uint64_t a, uint64_t b) {
         auto& c = cnt[t];
         c.assign(nbins, 0);
@@ -249,10 +250,11 @@ int index_build_host(ps_index* ix) {
             for (uint32_t i = 1; i < n; ++i) {
                 pre += r[i - 1];
                 suf += r[n - i];
-                int64_t bm = pre + kProtonUda, ym = suf + kWaterUda + kProtonUda;
-                if (bm < 0 || ym < 0) { bad_mass = 1; continue; }
-                c[(uint64_t)((bm + kBinWidth / 2) / kBinWidth)]++;
-                c[(uint64_t)((ym + kBinWidth / 2) / kBinWidth)]++;
+                for (int t = 0; t < ions.n; ++t) {
+                    const int64_t m = (ions.cterm[t] ? suf + kWaterUda : pre) + kProtonUda + ions.shift[t];
+                    if (m < 0) { bad_mass = 1; continue; }
+                    c[(uint64_t)((m + kBinWidth / 2) / kBinWidth)]++;
+                }
             }
         }
     });
@@ -277,22 +279,19 @@ int index_build_host(ps_index* ix) {
         int64_t r[64];
         for (uint64_t id = a; id < b; ++id) {
             uint32_t n = entry_residues(ix, mt, id, r);
-            int64_t pre = 0;
-            for (uint32_t i = 1; i < n; ++i) {      // b ions (bit 0) first, then y ions
-                pre += r[i - 1];
-                uint64_t bn = (uint64_t)((pre + kProtonUda + kBinWidth / 2) / kBinWidth);
-                ix->post[p[bn]++] = (uint32_t)(id << 1);
-            }
-            int64_t suf = 0;
-            for (uint32_t i = 1; i < n; ++i) {
-                suf += r[n - i];
-                uint64_t bn = (uint64_t)((suf + kWaterUda + kProtonUda + kBinWidth / 2) / kBinWidth);
-                ix->post[p[bn]++] = (uint32_t)(id << 1 | 1u);
+            for (int t = 0; t < ions.n; ++t) {      // N-terminal series (bit 0) first, then C-terminal
+                int64_t acc = 0;
+                for (uint32_t i = 1; i < n; ++i) {
+                    acc += ions.cterm[t] ? r[n - i] : r[i - 1];
+                    const int64_t m = (ions.cterm[t] ? acc + kWaterUda : acc) + kProtonUda + ions.shift[t];
+                    uint64_t bn = (uint64_t)((m + kBinWidth / 2) / kBinWidth);
+                    ix->post[p[bn]++] = (uint32_t)(id << 1 | ions.cterm[t]);
+                }
             }
         }
     });
-    // Postings of one id in one bin must be ordered b before y; ions of one id are
-    // emitted b-first, so each bin is non-decreasing in (id << 1 | type).
+    // Postings of one id in one bin must be ordered N-terminal before C-terminal; ions
+    // of one id are emitted that way, so each bin is non-decreasing in (id << 1 | type).
 
     // 4. with a merge width T, the list of bin b becomes the id-ordered merge of
     // the lists of bins b-T..b+T: a peak then probes one list and still meets
@@ -413,6 +412,8 @@ void bind_device_index(ps_index* ix, char* base, const DevLayout& lay) {
     d.n_bins = ix->n_bins;
     d.n_post = n_postings(ix);
     d.max_len = ix->max_len_seen;
+    d.ion_mult = ion_mult(ix->ion_types);
+    d.ion_series = (uint32_t)__builtin_popcount(ix->ion_types);
     d.min_residue = ix->min_residue;
     ix->on_device = true;
 }
@@ -459,8 +460,11 @@ int index_prepare(const ps_db_params* params, const char* residues, const uint64
     if (n_shards > PS_MAX_SHARDS || params->shard >= n_shards)
         return fail(PS_EINVAL, "need shard < n_shards <= %d (got shard %u of %u)", PS_MAX_SHARDS,
                     params->shard, n_shards);
+    if (params->ion_types > 63) return fail(PS_EINVAL, "ion_types must be a set of PS_ION_* bits");
+    if (params->reserved != 0) return fail(PS_EINVAL, "reserved must be 0");
     ps_index* ix = new (std::nothrow) ps_index();
     if (!ix) return fail(PS_ENOMEM, "out of host memory");
+    ix->ion_types = params->ion_types ? params->ion_types : (PS_ION_B | PS_ION_Y);
     ix->n_shards = n_shards;
     ix->shard = params->shard;
     ix->merge_tol = params->merge_tol_bins;
@@ -494,10 +498,12 @@ int index_prepare(const ps_db_params* params, const char* residues, const uint64
     // every residue, modified or not, must stay heavier than a proton plus the widest
     // fragment tolerance, so every b/y ion and its tolerance window lie inside the
     // bin range of the database's masses
-    if (lightest_residue(ix, mod_table(ix)) <= kProtonUda + kBinWidth * (PS_MAX_FRAG_TOL_BINS + 1)) {
+    // (a and x ions lose or gain CO at the ends, so they need residues heavier than CO)
+    const int64_t floor_uda = ((ix->ion_types & (PS_ION_A | PS_ION_X)) ? kCOUda : kProtonUda) +
+                              kBinWidth * (PS_MAX_FRAG_TOL_BINS + 1);
+    if (lightest_residue(ix, mod_table(ix)) <= floor_uda) {
         delete ix;
-        return fail(PS_EINVAL, "a modification makes a residue lighter than %.3f Da",
-                    (kProtonUda + kBinWidth * (PS_MAX_FRAG_TOL_BINS + 1)) * 1e-6);
+        return fail(PS_EINVAL, "a modification makes a residue lighter than %.3f Da", floor_uda * 1e-6);
     }
     try {
         ix->seq.assign(residues, residues + total);

@@ -15,6 +15,30 @@ namespace ps {
 constexpr int64_t kProtonUda = 1007276;     // H+
 constexpr int64_t kWaterUda = 18010565;     // H2O
 constexpr int64_t kBinWidth = 10000;        // 0.01 Da
+constexpr int64_t kCOUda = 27994915;        // CO, the a/b and x/y ion offset
+constexpr int64_t kNH3Uda = 17026549;       // NH3, the c/b and z/y ion offset
+constexpr int64_t kH2Uda = 2015650;         // H2
+
+// Fragment ion series of an index, in posting order: N-terminal series first.
+struct IonSeries {
+    int n;                     // enabled series
+    int64_t shift[6];          // added to b (N-terminal) or y (C-terminal) mass
+    uint32_t cterm[6];         // 1: C-terminal (posting bit 1)
+};
+inline IonSeries ion_series(uint32_t types) {
+    IonSeries s{};
+    const uint32_t bit[6] = {PS_ION_A, PS_ION_B, PS_ION_C, PS_ION_X, PS_ION_Y, PS_ION_Z};
+    const int64_t sh[6] = {-kCOUda, 0, kNH3Uda, kCOUda - kH2Uda, 0, -kNH3Uda};
+    for (int t = 0; t < 6; ++t)
+        if (types & bit[t]) { s.shift[s.n] = sh[t]; s.cterm[s.n] = t >= 3 ? 1u : 0u; ++s.n; }
+    return s;
+}
+// Largest number of enabled series on one terminus.
+inline uint32_t ion_mult(uint32_t types) {
+    const uint32_t n = __builtin_popcount(types & (PS_ION_A | PS_ION_B | PS_ION_C));
+    const uint32_t c = __builtin_popcount(types & (PS_ION_X | PS_ION_Y | PS_ION_Z));
+    return n > c ? n : c;
+}
 constexpr int kHistBins = PS_HIST_BINS;
 constexpr uint32_t kLfSize = 65536;         // log10(n!) table, n < 65536
 constexpr uint32_t kLsSize = 1u << 20;      // log10(s) table, s < 2^20
@@ -43,6 +67,8 @@ struct DevIndex {
     uint32_t merge_tol;        // T > 0: the list of bin b holds bins b-T..b+T (one probe per peak)
     uint64_t n_pep, n_bins, n_post;
     uint32_t max_len;          // longest peptide (residues)
+    uint32_t ion_mult;         // most ion series on one terminus (counter bounds)
+    uint32_t ion_series;       // enabled ion series
     int64_t min_residue;       // lightest residue incl. modification deltas (uDa)
 };
 

@@ -357,11 +357,13 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
                     // worst-case field values for any candidate of this spectrum
                     const uint64_t nvalid = tot & 0xFFFFFFFFull, sq = tot >> 32;
                     const uint64_t width = (uint64_t)(2 * kp.tol + 1) * (uint64_t)kBinWidth;
+                    // (each ion series of a terminus adds at most kpe ions per window)
                     const uint64_t kpe = A.ix.min_residue > 0 ? (width - 1) / (uint64_t)A.ix.min_residue + 1 : (1ull << 20);
-                    uint64_t nbmax = nvalid * kpe;
-                    const uint64_t by_len = (uint64_t)(A.ix.max_len > 0 ? A.ix.max_len - 1 : 0) * (uint64_t)s_mult;
+                    uint64_t nbmax = nvalid * kpe * A.ix.ion_mult;
+                    const uint64_t by_len = (uint64_t)(A.ix.max_len > 0 ? A.ix.max_len - 1 : 0) * (uint64_t)s_mult *
+                                            A.ix.ion_mult;
                     if (by_len < nbmax) nbmax = by_len;
-                    uint64_t smax = sq * 2ull * kpe;
+                    uint64_t smax = sq * (uint64_t)A.ix.ion_series * kpe;
                     if (200ull * nbmax < smax) smax = 200ull * nbmax;
                     if (!(nbmax <= 255 && smax <= 65535)) {
                         inf.flags |= kFlagWide;

@@ -34,6 +34,7 @@ struct ps_index {
     uint32_t missed = 0, min_len = 0, max_len = 0, max_mods = 0;
     uint32_t merge_tol = 0;      // lists of bin b hold the postings of bins b-T..b+T
     uint32_t n_shards = 1, shard = 0;   // this index holds whole-database ranks r % n_shards == shard
+    uint32_t ion_types = PS_ION_B | PS_ION_Y;
     std::vector<Mod> mods;
     std::vector<char> seq;
     std::vector<uint64_t> prot_off;

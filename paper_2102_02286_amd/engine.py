@@ -31,7 +31,7 @@ def mods_from_synth(mods) -> list[Mod]:
     return [Mod(m.residues, int(round(m.delta_da * 1e6)), m.nterm) for m in mods]
 
 
-def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0, n_shards=1, shard=0):
+def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0, n_shards=1, shard=0, ion_types=0):
     arr = (capi.ps_mod * max(1, len(mods)))()
     keep = []
     for i, m in enumerate(mods):
@@ -40,7 +40,7 @@ def _db_params(missed, min_len, max_len, mods, max_mods, merge_tol=0, n_shards=1
         arr[i].residues = b
         arr[i].nterm = 1 if m.nterm else 0
         arr[i].delta_udalton = int(m.delta_uda)
-    p = capi.ps_db_params(missed, min_len, max_len, len(mods), max_mods, merge_tol, n_shards, shard, arr)
+    p = capi.ps_db_params(missed, min_len, max_len, len(mods), max_mods, merge_tol, n_shards, shard, ion_types, 0, arr)
     return p, (arr, keep)
 
 
@@ -57,16 +57,18 @@ class HostIndex:
     """The index built on the host (no GPU needed)."""
 
     def __init__(self, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int, max_len: int,
-                 mods: list, max_mods: int, merge_tol: int = 0, n_shards: int = 1, shard: int = 0):
+                 mods: list, max_mods: int, merge_tol: int = 0, n_shards: int = 1, shard: int = 0,
+                 ion_types: int = 0):
         """merge_tol = T >= 1 stores, for each bin, the postings of bins b-T..b+T
         (searches must then use frag_tol_bins == T).  n_shards = G > 1 keeps only
-        partition `shard` of the sorted database (ranks r with r % G == shard)."""
+        partition `shard` of the sorted database (ranks r with r % G == shard).
+        ion_types: PS_ION_* bits of the indexed fragment series (0: b and y)."""
         self._res = np.ascontiguousarray(residues, dtype=np.uint8)
         self._off = np.ascontiguousarray(offsets, dtype=np.uint64)
         self.merge_tol = int(merge_tol)
         self.n_shards, self.shard = int(n_shards), int(shard)
         p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods, self.merge_tol, self.n_shards,
-                                   self.shard)
+                                   self.shard, int(ion_types))
         h = C.c_void_p()
         check(capi.ps_index_create(C.byref(p), ptr(self._res), ptr(self._off), self._off.shape[0] - 1,
                                    C.byref(h)), "ps_index_create")
@@ -76,7 +78,8 @@ class HostIndex:
     @classmethod
     def build_on_device(cls, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int, max_len: int,
                         mods: list, max_mods: int, merge_tol: int = 0, n_shards: int = 1, shard: int = 0,
-                        device: str = "cuda:0", stream=None, chunk_pairs: int = 0) -> "HostIndex":
+                        device: str = "cuda:0", stream=None, chunk_pairs: int = 0,
+                        ion_types: int = 0) -> "HostIndex":
         """The same index built on the GPU (ps_index_build_device), already resident:
         no upload() needed.  The build's scratch block is freed on return;
         chunk_pairs caps the (bin, posting) pairs sorted at a time (0: default)."""
@@ -87,7 +90,7 @@ class HostIndex:
         self.merge_tol = int(merge_tol)
         self.n_shards, self.shard = int(n_shards), int(shard)
         p, self._keep = _db_params(missed, min_len, max_len, list(mods), max_mods, self.merge_tol, self.n_shards,
-                                   self.shard)
+                                   self.shard, int(ion_types))
         ib, sb = C.c_uint64(), C.c_uint64()
         n_prot = self._off.shape[0] - 1
         check(capi.ps_index_build_device_bytes(C.byref(p), ptr(self._res), ptr(self._off), n_prot, int(chunk_pairs),

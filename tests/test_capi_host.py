@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     assert C.sizeof(capi.ps_device) == 24
     assert C.sizeof(capi.ps_mod) == 24
-    assert C.sizeof(capi.ps_db_params) == 40
+    assert C.sizeof(capi.ps_db_params) == 48
     assert C.sizeof(capi.ps_part) == 24
     assert C.sizeof(capi.ps_spectra) == 48
     assert C.sizeof(capi.ps_search_params) == 56
@@ -300,3 +300,29 @@ def test_device_build_without_device():
     assert capi.ps_index_build_device(C.byref(p), ptr(ok.residues), ptr(ok.offsets), 1, 0, C.byref(dev),
                                       C.byref(dev), C.byref(out)) == capi.PS_EDEVICE
     assert not out.value
+
+
+@pytest.mark.parametrize("types,label", [(63, "abcxyz"), (4 | 32, "cz"), (1 | 8, "ax")])
+def test_host_index_postings_other_ion_series(types, label):
+    """Postings of the a, c, x, z series: the oracle's b/y ions shifted by the
+    element-derived offsets; N-terminal series carry bit 0, C-terminal bit 1."""
+    from tests import bruteforce as bf
+    prot = synth.make_proteome(20, seed=9)
+    mods = [synth.OXIDATION, synth.ACETYL_NTERM]
+    o = oracle.Database(prot.residues, prot.offsets, 1, 7, 30, oracle.mods_from_synth(mods), 1)
+    h = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, engine.mods_from_synth(mods), 1, ion_types=types)
+    off, post = h.host_arrays()
+    want = {}
+    for pid in range(len(o)):
+        b, y = oracle.ions(o.residue_masses(pid))
+        for t in label:
+            base, flag = (b, 0) if t in "abc" else (y, 1)
+            for m in base:
+                want.setdefault(int((m + bf.ION_SHIFT[t] + 5000) // 10000), []).append(pid << 1 | flag)
+    assert int(off[-1]) == post.shape[0] == sum(len(v) for v in want.values())
+    for bn in range(off.shape[0] - 1):
+        assert post[off[bn]:off[bn + 1]].tolist() == sorted(want.get(bn, [])), bn
+    with pytest.raises(capi.PsError):
+        engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, [], 0, ion_types=64)
+    with pytest.raises(capi.PsError):     # a ions need residues heavier than CO
+        engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, [engine.Mod("G", -30_000_000)], 1, ion_types=1)

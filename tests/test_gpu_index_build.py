@@ -53,6 +53,14 @@ def test_device_build_equals_host_build(mods, max_mods, T, chunk):
     _assert_same_index(host, dev)
 
 
+@pytest.mark.parametrize("types,T", [(63, 1), (4 | 32, 0), (1 | 2 | 16, 2)])
+def test_device_build_other_ion_series(types, T):
+    prot = synth.make_proteome(150, seed=13)
+    _say(f"device build: ion series {types}, merge {T}")
+    host, dev = _both(prot, 2, 6, 40, [synth.OXIDATION, synth.ACETYL_NTERM], 2, merge_tol=T, ion_types=types)
+    _assert_same_index(host, dev)
+
+
 @pytest.mark.parametrize("G", [2, 3])
 def test_device_build_partitions(G):
     prot = synth.make_proteome(200, seed=11)

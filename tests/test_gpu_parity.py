@@ -491,3 +491,24 @@ def test_preprocessing_variants_parity(small_open, noise, inten):
         res = engine.search(ix, sub, prm)
         assert_parity(res, oh, ost, og)
         assert res.postings == int(ost["pairs_total"].sum())
+
+
+@pytest.mark.parametrize("types,T", [(63, 1), (4 | 32, 2)])
+def test_other_ion_series_parity(types, T):
+    """Indexes of the a, c, x and z series (N-terminal matches in n_b,
+    C-terminal in n_y) against the oracle with the same series, both schedules."""
+    w = synth.workload("medium")
+    prot = synth.make_proteome(600, seed=2)
+    sp = w.spectra(prot, n=48, seed=8)
+    mods = [synth.OXIDATION, synth.ACETYL_NTERM]
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, engine.mods_from_synth(mods),
+                          2, merge_tol=T, ion_types=types).upload()
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, oracle.mods_from_synth(mods), 2)
+    oh, ost, og = db.search(sp, False, 300_000_000, T, w.top_peaks, w.top_k, 3, ion_types=types)
+    assert (ost["status"] == 0).sum() > 20
+    for schedule in (capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT):
+        _say(f"ion series {types}, merge {T}, schedule {schedule}")
+        prm = engine.search_params(False, 300_000_000, T, w.top_peaks, w.top_k, 3, max_charge=3, schedule=schedule)
+        res = engine.search(ix, sp, prm)
+        assert_parity(res, oh, ost, og)
+        assert res.postings == int(ost["pairs_total"].sum())
