@@ -864,9 +864,15 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                     c[0] = (C)(((unsigned long long)v.y << 32) | v.x);
                     c[1] = (C)(((unsigned long long)v.w << 32) | v.z);
                 }
+                // most counter groups hold no candidate: one test for the group first
+                uint32_t sh4[kPer];
+                uint32_t top = 0;
+#pragma unroll
+                for (uint32_t e = 0; e < kPer; ++e) { sh4[e] = Cnt<C>::shared(c[e]); top = max(top, sh4[e]); }
+                if (__ballot(top >= kmin) == 0ull) continue;   // wave-uniform
 #pragma unroll
                 for (uint32_t e = 0; e < kPer; ++e) {
-                    const bool pass = Cnt<C>::shared(c[e]) >= kmin;
+                    const bool pass = sh4[e] >= kmin;
                     const unsigned long long msk = __ballot(pass);
                     if (msk == 0) continue;             // wave-uniform
                     if (wn > kWaveCand - 64u) score_buffer();   // room for a whole wavefront
