@@ -210,6 +210,43 @@ def assembly_leg(capi, engine, torch, w, prot, merge, G, dsp, n, nnz, prm, ref, 
     return res
 
 
+def small_batch_leg(capi, engine, torch, ix, sp, params, use, sizes=(256, 1024, 4096, 16384), reps=10):
+    """Graph-replayed searches of small batches (the serving regime): one
+    workgroup per spectrum leaves most of the GPU idle when a batch holds fewer
+    spectra than the GPU holds workgroups, while the persistent work queue
+    splits every window into items.  Spectra/s of both schedules, same results."""
+    out = []
+    for n in sizes:
+        sub = sp.subset(np.arange(0, n))
+        tens = device_spectra(sub, torch)
+        nnz = int(sub.peak_off[-1])
+        row = {"spectra": n}
+        ref = None
+        for name, prm in params:
+            use(name)
+            plan = engine.Plan(ix, prm, n_cap=n, nnz_cap=nnz)
+            fill_plan_inputs(plan, tens, torch)
+            plan.run_device(n, nnz)
+            r = plan.results()
+            torch.cuda.synchronize()
+            dt = float("inf")
+            for _ in range(3):                      # best of three groups: the batches are short
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    plan.run_device(n, nnz)
+                    r = plan.results()
+                dt = min(dt, (time.perf_counter() - t0) / reps)
+            if ref is None:
+                ref = r.hits.tobytes()
+            assert r.hits.tobytes() == ref, "schedules disagree on a small batch"
+            row[name] = {"spectra_per_s": n / dt, "ms_per_batch": dt * 1e3}
+            del plan
+        log(f"small batch {n}: " + ", ".join(f"{k} {v['spectra_per_s']:.0f} spectra/s" for k, v in row.items()
+                                               if isinstance(v, dict)))
+        out.append(row)
+    return out
+
+
 def index_build_leg(engine, torch, w, prot, merge, host_s):
     """The same index built on the GPU (ps_index_build_device): wall time of the
     whole call (host census, entry generation, sorts, lists, directory, copies
@@ -426,6 +463,12 @@ def main():
     if args.shards > 1:
         out["assembly"] = assembly_leg(capi, engine, torch, w, prot, merge, args.shards, dsp, sp.n, nnz,
                                        prm_plain, res_eager, args.steps, args.warmup)
+
+    # ---- small batches: where the persistent work queue pays
+    if plain is not None and persistent is not None:
+        out["small_batches"] = small_batch_leg(capi, engine, torch, ix, sp,
+                                               [("plain", prm_plain), ("persistent", prm_pers)], use)
+        use("persistent")
 
     # ---- the index built on the GPU
     if not args.no_build_leg:
