@@ -293,6 +293,7 @@ def main():
                     help="one posting list per fragment bin (default: lists merge the 2T+1 neighbouring bins)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--no-build-leg", action="store_true", help="skip timing the GPU index build")
+    ap.add_argument("--no-small-batches", action="store_true", help="skip the small-batch plain/persistent leg")
     ap.add_argument("--shards", type=int, default=4,
                     help="also search G round-robin database partitions and assemble them (0: skip)")
     ap.add_argument("--only", choices=["plain", "persistent"], default=None,
@@ -465,7 +466,7 @@ def main():
                                        prm_plain, res_eager, args.steps, args.warmup)
 
     # ---- small batches: where the persistent work queue pays
-    if plain is not None and persistent is not None:
+    if plain is not None and persistent is not None and not args.no_small_batches:
         out["small_batches"] = small_batch_leg(capi, engine, torch, ix, sp,
                                                [("plain", prm_plain), ("persistent", prm_pers)], use)
         use("persistent")
