@@ -50,6 +50,11 @@ STAT_DTYPE = np.dtype([("n_window", "<u8"), ("n_scored", "<u8"), ("evalue", "<f8
                        ("status", "<i4"), ("pad", "<i4"), ("lo", "<u8"), ("hi", "<u8"),
                        ("pairs_total", "<u8")])
 
+SAMPLE_BINS, SAMPLE_HEAD = 120, 60
+SAMPLED_DTYPE = np.dtype([("lo", "<u2"), ("flags", "<u2"), ("pad", "<u4"), ("n_scored", "<u8"),
+                          ("count", "<u2", (SAMPLE_BINS,))])
+assert SAMPLED_DTYPE.itemsize == 256
+
 _lib = None
 
 
@@ -86,6 +91,8 @@ def lib():
         L.orc_evalue.argtypes = [P, C.c_double, C.c_uint64, P, P, P, P]
         L.orc_evalue_gumbel.restype = C.c_int
         L.orc_evalue_gumbel.argtypes = [P, C.c_double, C.c_uint64, P, P, P, P]
+        L.orc_sample.argtypes = [P, C.c_uint64, P]
+        L.orc_unsample.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -219,6 +226,27 @@ def assemble(part_hits, part_stats, part_hist, fit: int = FIT_TAIL):
     if rc != 0:
         raise ValueError("oracle rejected the assembly arguments")
     return hits.reshape(n, k), stats, hist.reshape(n, HIST_BINS)
+
+
+def sample(hist: np.ndarray, n_scored) -> np.ndarray:
+    """Sampled 256-byte records (oracle.h: orc_sample) of histograms [n, 512]
+    with their scored-candidate counts [n]."""
+    h = np.ascontiguousarray(np.asarray(hist, dtype=np.int32).reshape(-1, HIST_BINS))
+    ns = np.asarray(n_scored, dtype=np.uint64).reshape(-1)
+    assert ns.shape[0] == h.shape[0]
+    out = np.zeros(h.shape[0], SAMPLED_DTYPE)
+    for i in range(h.shape[0]):
+        lib().orc_sample(_ptr(h[i]), int(ns[i]), _ptr(out[i:i + 1]))
+    return out
+
+
+def unsample(rec: np.ndarray) -> np.ndarray:
+    """The histograms [n, 512] the records stand for (the shift of the assembly)."""
+    r = np.ascontiguousarray(np.asarray(rec, dtype=SAMPLED_DTYPE).reshape(-1))
+    out = np.zeros((r.shape[0], HIST_BINS), np.int32)
+    for i in range(r.shape[0]):
+        lib().orc_unsample(_ptr(r[i:i + 1]), _ptr(out[i]))
+    return out
 
 
 def ions(residue_uda: np.ndarray) -> tuple[np.ndarray, np.ndarray]:

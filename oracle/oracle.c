@@ -722,3 +722,52 @@ int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, int32_t fit, con
     free(pool);
     return 0;
 }
+
+/* Sampling section and its figure: locate the mean of the score distribution
+ * from its three most intense samples, then keep ORC_SAMPLE_BINS samples
+ * around it, giving up the tail before the head. */
+void orc_sample(const int32_t* hist, uint64_t n_scored, orc_sampled* out) {
+    memset(out, 0, sizeof *out);
+    out->n_scored = n_scored;
+    /* the three most intense samples (largest counts; ties go to the lower bin) */
+    int top[3];
+    int t = 0;
+    for (int r = 0; r < 3; ++r) {
+        int best = -1;
+        for (int j = 0; j < ORC_HIST_BINS; ++j) {
+            if (hist[j] <= 0) continue;
+            int used = 0;
+            for (int u = 0; u < t; ++u) used |= top[u] == j;
+            if (used) continue;
+            if (best < 0 || hist[j] > hist[best]) best = j;
+        }
+        if (best < 0) break;
+        top[t++] = best;
+    }
+    if (t == 0) return;                       /* empty distribution: nothing to keep */
+    int sum = 0;
+    for (int u = 0; u < t; ++u) sum += top[u];
+    const int mean = sum / t;                 /* average location, floored */
+    int first = 0;
+    while (hist[first] <= 0) ++first;
+    /* the window reaches down to the head's start, but no further than
+     * ORC_SAMPLE_HEAD bins below the mean; what does not fit is tail */
+    int lo = first > mean - ORC_SAMPLE_HEAD ? first : mean - ORC_SAMPLE_HEAD;
+    if (lo > ORC_HIST_BINS - ORC_SAMPLE_BINS) lo = ORC_HIST_BINS - ORC_SAMPLE_BINS;
+    out->lo = (uint16_t)lo;
+    for (int j = 0; j < ORC_HIST_BINS; ++j) {
+        const int32_t v = hist[j] > 0 ? hist[j] : 0;
+        if (j >= lo && j < lo + ORC_SAMPLE_BINS) {
+            if (v > 65535) out->flags |= 1;
+            out->count[j - lo] = (uint16_t)(v > 65535 ? 65535 : v);
+        } else if (v > 0) {
+            out->flags |= 2;
+        }
+    }
+}
+
+void orc_unsample(const orc_sampled* in, int32_t* hist) {
+    memset(hist, 0, ORC_HIST_BINS * sizeof(int32_t));
+    if (in->lo > ORC_HIST_BINS - ORC_SAMPLE_BINS) return;   /* not a record orc_sample writes */
+    for (int i = 0; i < ORC_SAMPLE_BINS; ++i) hist[in->lo + i] = in->count[i];
+}

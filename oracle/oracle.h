@@ -122,6 +122,30 @@ int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, int32_t fit, con
                  const orc_stat* part_stats, const int32_t* part_hist, orc_hit* hits,
                  orc_stat* stats, int32_t* hist);
 
+/* Sampled intermediate result (Sampling section and its figure): the score
+ * histogram cut to ORC_SAMPLE_BINS consecutive bins around its mean, so that
+ * one spectrum's partial result fits 256 bytes.  Reading: the mean is the
+ * average location (floored) of the three bins with the largest counts (ties:
+ * lower bin; only nonzero bins); the window starts at the first nonzero bin,
+ * or ORC_SAMPLE_HEAD bins below the mean if the head reaches further, so that
+ * the far tail is what gets dropped first; it is clamped to end at bin 511.
+ * Counts above 65535 saturate.  flags: bit 0 a count saturated, bit 1 a
+ * nonzero bin fell outside the window. */
+#define ORC_SAMPLE_BINS 120
+#define ORC_SAMPLE_HEAD 60
+typedef struct {
+    uint16_t lo;               /* histogram bin of count[0] */
+    uint16_t flags;
+    uint32_t pad;
+    uint64_t n_scored;         /* the spectrum's scored candidates (all of them) */
+    uint16_t count[ORC_SAMPLE_BINS];
+} orc_sampled;                 /* 256 bytes */
+
+void orc_sample(const int32_t* hist, uint64_t n_scored, orc_sampled* out);
+/* The shift of Superstep 4's "addition and shift": the 512-bin histogram a
+ * record stands for (zero outside its window). */
+void orc_unsample(const orc_sampled* in, int32_t* hist);
+
 /* Pieces exposed for pin tests. */
 double orc_hyperscore(uint32_t n_b, uint32_t n_y, uint32_t sum_q);
 void   orc_sg_smooth(const int32_t* hist, double* out);          /* 512 -> 512 */

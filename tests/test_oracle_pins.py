@@ -722,3 +722,122 @@ def test_ion_series_offsets_at_bin_edges():
     want = bf.search([(int(t["mass"]), 0, 0, 0, 0, db.residue_masses(i).tolist()) for i, t in enumerate(tab)],
                      sp.mz, sp.intensity, prec, 2, False, 10**9, 0, 10, 5, 1, ions="cz")
     assert want["scored"][pid][:2] == (1, 1)
+
+
+# --------------------------------------------------------------------------
+# Sampled intermediate results (Sampling section and its figure; the shift of
+# Superstep 4's "addition and shift").
+# --------------------------------------------------------------------------
+
+def _sample_bruteforce(h):
+    """The reading written as a search: the mean from the three most intense
+    nonzero bins (sorted by count desc, bin asc), then the first window
+    placement that starts no earlier than the head and no more than 60 bins
+    below the mean; placements end at bin 511."""
+    nz = [j for j in range(oracle.HIST_BINS) if h[j] > 0]
+    if not nz:
+        return 0
+    top = sorted(nz, key=lambda j: (-int(h[j]), j))[:3]
+    mean = sum(top) // len(top)
+    for lo in range(0, oracle.HIST_BINS - oracle.SAMPLE_BINS + 1):
+        if lo >= nz[0] and lo >= mean - oracle.SAMPLE_HEAD:
+            return lo
+    return oracle.HIST_BINS - oracle.SAMPLE_BINS
+
+
+def _hand_hist(pairs, n=oracle.HIST_BINS):
+    h = np.zeros(n, np.int32)
+    for j, v in pairs:
+        h[j] = v
+    return h
+
+
+def test_sampling_hand_worked_cases():
+    """Cases worked out by hand from the reading (window of 120 bins; mean =
+    floor of the average bin of the three largest counts)."""
+    # narrow distribution: everything fits, the window starts at the head
+    h = _hand_hist([(j, 5) for j in range(20, 40)] + [(30, 100), (31, 90), (35, 80)])
+    r = oracle.sample(h[None], [7])[0]
+    assert int(r["lo"]) == 20 and int(r["flags"]) == 0 and int(r["n_scored"]) == 7
+    assert np.array_equal(oracle.unsample(r[None])[0], h)
+    # long head: mean (150 + 151 + 152) / 3 = 151, window [91, 211): bins 0..90 are cut
+    h = _hand_hist([(j, 1) for j in range(0, 201)] + [(150, 1000), (151, 900), (152, 800)])
+    r = oracle.sample(h[None], [0])[0]
+    assert int(r["lo"]) == 91 and int(r["flags"]) == 2
+    u = oracle.unsample(r[None])[0]
+    assert u[:91].sum() == 0 and np.array_equal(u[91:201], h[91:201]) and u[201:].sum() == 0
+    # four equal counts: the three lowest bins are the most intense, mean 200, window [140, 260)
+    h = _hand_hist([(100, 10), (200, 10), (300, 10), (400, 10)])
+    r = oracle.sample(h[None], [40])[0]
+    assert int(r["lo"]) == 140 and int(r["flags"]) == 2
+    assert oracle.unsample(r[None])[0].sum() == 10
+    # distribution against the top of the range: the window ends at bin 511
+    h = _hand_hist([(j, 3) for j in range(450, 512)])
+    r = oracle.sample(h[None], [186])[0]
+    assert int(r["lo"]) == 392 and int(r["flags"]) == 0
+    assert np.array_equal(oracle.unsample(r[None])[0], h)
+    # saturation of a 16-bit sample
+    h = _hand_hist([(5, 70000), (6, 3)])
+    r = oracle.sample(h[None], [70003])[0]
+    assert int(r["lo"]) == 5 and int(r["count"][0]) == 65535 and int(r["count"][1]) == 3
+    assert int(r["flags"]) == 1
+    # empty distribution
+    r = oracle.sample(np.zeros((1, oracle.HIST_BINS), np.int32), [0])[0]
+    assert int(r["lo"]) == 0 and int(r["flags"]) == 0 and int(r["count"].sum()) == 0
+
+
+def test_sampling_matches_bruteforce_and_loses_only_outside_the_window():
+    """Random histograms of every shape (narrow, wide, long heads, long tails,
+    ties, edges): the window matches the brute-force search, kept counts equal
+    the histogram inside it (saturated), and the flags say exactly whether
+    anything was lost."""
+    rng = np.random.default_rng(5)
+    hs = []
+    for _ in range(400):
+        h = np.zeros(oracle.HIST_BINS, np.int32)
+        kind = rng.integers(0, 4)
+        a = int(rng.integers(0, oracle.HIST_BINS))
+        b = min(oracle.HIST_BINS, a + int(rng.integers(1, [30, 121, 300, 512][kind])))
+        h[a:b] = rng.integers(0, [3, 50, 1000, 80000][int(rng.integers(0, 4))], b - a)
+        if rng.random() < 0.3:                      # ties among the largest counts
+            h[rng.integers(a, b, 3)] = h.max()
+        hs.append(h)
+    hs = np.stack(hs)
+    recs = oracle.sample(hs, np.arange(len(hs)))
+    back = oracle.unsample(recs)
+    for h, r, u in zip(hs, recs, back):
+        lo = _sample_bruteforce(h)
+        assert int(r["lo"]) == lo
+        w = slice(lo, lo + oracle.SAMPLE_BINS)
+        assert np.array_equal(u[w], np.minimum(h[w], 65535))
+        assert u.sum() == np.minimum(h[w], 65535).sum()
+        assert bool(r["flags"] & 1) == bool((h[w] > 65535).any())
+        outside = h.copy()
+        outside[w] = 0
+        assert bool(r["flags"] & 2) == bool((outside > 0).any())
+    assert int(recs["n_scored"][17]) == 17
+
+
+def test_sampled_assembly_equals_full_assembly_when_lossless():
+    """Partition results sampled to 256 bytes, shifted back and added give the
+    same assembled results as the full histograms whenever no sample was lost
+    (the usual case: hyperscores of one spectrum span well under 12 units)."""
+    w = synth.workload("tiny")
+    prot = synth.make_proteome(150, seed=0)
+    mods = oracle.mods_from_synth([synth.OXIDATION])
+    sp = w.spectra(prot, n=40, seed=12)
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, mods, 1)
+    args = (False, 300_000_000, 2, 100, 6, 3)
+    G = 3
+    parts = [db.shard(G, i).search(sp, *args, threads=4) for i in range(G)]
+    recs = [oracle.sample(p[2], p[1]["n_scored"]) for p in parts]
+    lossless = np.all([r["flags"] == 0 for r in recs], axis=0)
+    assert lossless.sum() >= 20                      # a lone far-out top hit is the usual loss
+    full = oracle.assemble([p[0] for p in parts], [p[1] for p in parts], [p[2] for p in parts])
+    samp = oracle.assemble([p[0] for p in parts], [p[1] for p in parts], [oracle.unsample(r) for r in recs])
+    assert _same(full[0], samp[0])                   # hits never depend on the histogram
+    assert np.array_equal(full[1]["n_scored"], samp[1]["n_scored"])
+    assert _same(full[1][lossless], samp[1][lossless]) and _same(full[2][lossless], samp[2][lossless])
+    # where samples were lost, the assembled histogram is the full one cut to the windows
+    for i in np.nonzero(~lossless)[0]:
+        assert (samp[2][i] <= full[2][i]).all() and samp[2][i].sum() < full[2][i].sum()
