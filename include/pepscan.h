@@ -71,6 +71,8 @@ extern "C" {
 #define PS_ION_Z 32u              /* z = y - NH3 */
 
 #define PS_MAX_SHARDS 64          /* database partitions one ps_assemble call merges */
+#define PS_SAMPLE_BINS 120        /* histogram bins a sampled partial result keeps (Sampling: s = 120) */
+#define PS_SAMPLE_HEAD 60         /* bins below the mean a sampled result keeps at most */
 
 #define PS_FIT_TAIL   0          /* linear fit of the log survival function's tail (Superstep 4) */
 #define PS_FIT_GUMBEL 1          /* log-Weibull (Gumbel) fit by moments (Superstep 4) */
@@ -343,30 +345,61 @@ void ps_batch_free(ps_batch* batch);
 
 /* ---- result assembly over database partitions --------------------------- */
 
-/* The results of one partition's search (all device pointers, partition ids). */
+/* Sampled partial histogram of one spectrum: the 256-byte intermediate result
+ * of the Sampling section (Superstep 3) and its figure.  The histogram keeps
+ * PS_SAMPLE_BINS consecutive bins [lo, lo + 120) around its mean, where the
+ * mean is the average location (floored) of the three bins with the largest
+ * counts (ties to the lower bin, nonzero bins only), and lo is the first
+ * nonzero bin, or mean - PS_SAMPLE_HEAD when the head reaches further down, at
+ * most 392 (the window ends by bin 511).  What does not fit is the far tail
+ * first, which a fit recovers.  Counts above 65535 saturate. */
 typedef struct {
-    const ps_hit*  hits;      /* [n * top_k] */
-    const ps_stat* stats;     /* [n] */
-    const int32_t* hist;      /* [n * 512] */
+    uint16_t lo;              /* histogram bin of count[0]; 0..392 */
+    uint16_t flags;           /* bit 0: a count saturated; bit 1: a nonzero bin lay outside the window */
+    uint32_t pad;             /* 0 */
+    uint64_t n_scored;        /* the spectrum's scored candidates, all of them (ps_stat.n_scored) */
+    uint16_t count[PS_SAMPLE_BINS];
+} ps_sampled;                 /* 256 bytes */
+
+/* Sample n partial histograms on the device (the Sampling section's step
+ * before results leave a partition).  hist[n * 512] and stats[n] are a
+ * search's device results (ps_batch_device_results, ps_plan_device_results);
+ * out[n] is device memory.  Runs on `stream` (a hipStream_t, NULL = null
+ * stream), allocates nothing and returns without waiting.  PS_EINVAL for a NULL
+ * pointer when n > 0. */
+int ps_sample(void* stream, uint64_t n, const int32_t* hist, const ps_stat* stats, ps_sampled* out);
+
+/* The results of one partition's search (all device pointers, partition ids).
+ * Exactly one of hist and sampled is given: the full histograms, or their
+ * 256-byte samples from ps_sample. */
+typedef struct {
+    const ps_hit*     hits;      /* [n * top_k] */
+    const ps_stat*    stats;     /* [n] */
+    const int32_t*    hist;      /* [n * 512], or NULL */
+    const ps_sampled* sampled;   /* [n], or NULL */
 } ps_part;
 
 /* Result assembly of Superstep 4 (Supplementary Algorithm 4) on the device.
  * parts[g] holds the results of the same n spectra searched with the same
  * parameters (top_k included) against partition g of G (ps_db_params.n_shards,
  * .shard).  Per spectrum, on `stream` (a hipStream_t, NULL = null stream):
- *   - hist = the bin-wise sum of the partition histograms (the histograms are
- *     not sampled, so addition needs no shift);
+ *   - hist = the sum of the partition histograms: full histograms add bin by
+ *     bin; a sampled one is shifted to its window first (the "addition and
+ *     shift" of Superstep 4), with zeros outside it;
  *   - hits = the best top_k of all partition hits by (hyperscore desc, id asc),
  *     ids turned into whole-database ids (i * G + g);
  *   - stats: n_window and n_scored are the sums; the expect value is fitted on
  *     the assembled histogram with the best hit's hyperscore, exactly as a search
  *     of the whole database does; a spectrum any partition reports INVALID or
  *     OVERFLOW keeps that status with no hits (n_scored 0).
- * The result equals a whole-database search bit for bit.  Outputs hits[n *
+ * With full histograms, or samples that lost nothing (flags 0), the result
+ * equals a whole-database search bit for bit; lossy samples change only the
+ * histogram and the expect value.  Outputs hits[n *
  * top_k], stats[n] and hist[n * 512] (hist may be NULL) are device memory that
  * must not overlap the inputs.  Nothing is allocated; returns without waiting.
- * PS_EINVAL for G outside 1..PS_MAX_SHARDS, top_k outside 1..PS_MAX_TOP_K, or a
- * NULL input pointer when n > 0.  `fit` is the ps_search_params.fit of the
+ * PS_EINVAL for G outside 1..PS_MAX_SHARDS, top_k outside 1..PS_MAX_TOP_K, a
+ * NULL input pointer when n > 0, or a partition giving both or neither of hist
+ * and sampled.  `fit` is the ps_search_params.fit of the
  * partition searches. */
 int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts, uint64_t n, uint32_t top_k, int32_t fit,
                 ps_hit* hits, ps_stat* stats, int32_t* hist);

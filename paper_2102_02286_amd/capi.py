@@ -66,7 +66,7 @@ class ps_schedule(C.Structure):
 
 
 class ps_part(C.Structure):
-    _fields_ = [("hits", C.c_void_p), ("stats", C.c_void_p), ("hist", C.c_void_p)]
+    _fields_ = [("hits", C.c_void_p), ("stats", C.c_void_p), ("hist", C.c_void_p), ("sampled", C.c_void_p)]
 
 
 class ps_tune_trial(C.Structure):
@@ -89,6 +89,9 @@ assert C.sizeof(ps_search_params) == 56
 assert C.sizeof(ps_db_params) == 48
 PS_ION_A, PS_ION_B, PS_ION_C, PS_ION_X, PS_ION_Y, PS_ION_Z = 1, 2, 4, 8, 16, 32
 PS_MAX_SHARDS = 64
+PS_SAMPLE_BINS, PS_SAMPLE_HEAD = 120, 60
+SAMPLED_DTYPE = np.dtype([("lo", "<u2"), ("flags", "<u2"), ("pad", "<u4"), ("n_scored", "<u8"),
+                          ("count", "<u2", (PS_SAMPLE_BINS,))])
 
 _P = C.c_void_p
 _U64P = C.POINTER(C.c_uint64)
@@ -125,6 +128,7 @@ _SIGS = [
                                  C.c_uint64, _P, _P, _P, _P, _P, _U64P]),
     ("ps_batch_device_results", C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]),
     ("ps_assemble", C.c_int, [_P, C.c_uint32, C.POINTER(ps_part), C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P]),
+    ("ps_sample", C.c_int, [_P, C.c_uint64, _P, _P, _P]),
     ("ps_batch_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint32), _U64P, _U64P]),
     ("ps_batch_free", None, [_P]),
     ("ps_plan_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
@@ -214,6 +218,7 @@ ps_results = _fn("ps_results")
 ps_search_dump = _fn("ps_search_dump")
 ps_batch_device_results = _fn("ps_batch_device_results")
 ps_assemble = _fn("ps_assemble")
+ps_sample = _fn("ps_sample")
 ps_batch_timing = _fn("ps_batch_timing")
 ps_batch_free = _fn("ps_batch_free")
 ps_plan_bytes = _fn("ps_plan_bytes")

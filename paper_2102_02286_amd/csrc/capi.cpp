@@ -415,13 +415,28 @@ extern "C" int ps_assemble(void* stream, uint32_t n_shards, const ps_part* parts
     if (fit != PS_FIT_TAIL && fit != PS_FIT_GUMBEL) return fail(PS_EINVAL, "unknown fit %d", fit);
     if (n == 0) return PS_OK;
     if (!parts || !hits || !stats) return fail(PS_EINVAL, "NULL argument");
-    for (uint32_t g = 0; g < n_shards; ++g)
-        if (!parts[g].hits || !parts[g].stats || !parts[g].hist)
+    for (uint32_t g = 0; g < n_shards; ++g) {
+        if (!parts[g].hits || !parts[g].stats)
             return fail(PS_EINVAL, "partition %u has a NULL result pointer", g);
+        if ((parts[g].hist == nullptr) == (parts[g].sampled == nullptr))
+            return fail(PS_EINVAL, "partition %u must give exactly one of hist and sampled", g);
+    }
     int rc = require_device();
     if (rc != PS_OK) return rc;
     hipError_t e = launch_assemble(parts, n_shards, n, top_k, fit, hits, stats, hist, (hipStream_t)stream);
     if (e != hipSuccess) return fail(PS_EDEVICE, "assemble: %s", hipGetErrorString(e));
+    return PS_OK;
+}
+
+static_assert(sizeof(ps_sampled) == 256, "a sampled partial result is 256 bytes");
+
+extern "C" int ps_sample(void* stream, uint64_t n, const int32_t* hist, const ps_stat* stats, ps_sampled* out) {
+    if (n == 0) return PS_OK;
+    if (!hist || !stats || !out) return fail(PS_EINVAL, "NULL argument");
+    int rc = require_device();
+    if (rc != PS_OK) return rc;
+    hipError_t e = launch_sample(hist, stats, out, n, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(PS_EDEVICE, "sample: %s", hipGetErrorString(e));
     return PS_OK;
 }
 

@@ -157,6 +157,7 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
                                   hipStream_t stream);
 hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
                         bool per_item, hipStream_t stream);
+hipError_t launch_sample(const int32_t* hist, const ps_stat* stats, ps_sampled* out, uint64_t n, hipStream_t stream);
 hipError_t launch_assemble(const ps_part* parts, uint32_t n_shards, uint64_t n, uint32_t top_k, int32_t fit, ps_hit* hits,
                            ps_stat* stats, int32_t* hist, hipStream_t stream);
 size_t scan_lds_bytes(const KParams& kp, bool wide);

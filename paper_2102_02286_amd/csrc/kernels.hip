@@ -1441,10 +1441,19 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
             if (st.status == PS_STATUS_INVALID) atomicOr(&s_flags, 1u);
             if (st.status == PS_STATUS_OVERFLOW) atomicOr(&s_flags, 2u);
         }
-        // histogram addition: partition histograms share bin 0, so bins add one to one
+        // histogram addition: full partition histograms share bin 0 and add one to
+        // one; a sampled one is shifted to its window [lo, lo + 120) first
         for (uint32_t j = tid; j < (uint32_t)kHistBins; j += kBlock) {
             int32_t acc = 0;
-            for (uint32_t g = 0; g < G; ++g) acc += A.parts[g].hist[s * (uint64_t)kHistBins + j];
+            for (uint32_t g = 0; g < G; ++g) {
+                if (A.parts[g].hist) {
+                    acc += A.parts[g].hist[s * (uint64_t)kHistBins + j];
+                } else {
+                    const ps_sampled* r = A.parts[g].sampled + s;
+                    const uint32_t i = j - (uint32_t)r->lo;      // wraps above 120 below the window
+                    if (i < (uint32_t)PS_SAMPLE_BINS) acc += r->count[i];
+                }
+            }
             s_hist[j] = acc;
             if (A.hist) A.hist[s * (uint64_t)kHistBins + j] = acc;
         }
@@ -1489,6 +1498,120 @@ hipError_t launch_assemble(const ps_part* parts, uint32_t G, uint64_t n, uint32_
     a.G = G; a.K = K; a.fit = fit; a.n = n; a.hits = hits; a.stats = stats; a.hist = hist;
     const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
     hipLaunchKernelGGL(k_assemble, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sampling: one wavefront per spectrum turns its 512-bin histogram into the
+// 256-byte record of the Sampling section
+// ---------------------------------------------------------------------------
+
+struct SampleArgs {
+    const int32_t* hist;
+    const ps_stat* stats;
+    ps_sampled* out;
+    uint64_t n;
+};
+
+// Wave-wide maximum of a 64-bit key.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+constexpr uint32_t kSampleWaves = kBlock / 64;
+
+__global__ __launch_bounds__(kBlock) void k_sample(SampleArgs A) {
+    __shared__ int32_t s_h[kSampleWaves][kHistBins];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    int32_t* h = s_h[wave];
+    for (uint64_t s = (uint64_t)blockIdx.x * kSampleWaves + wave; s < A.n; s += (uint64_t)gridDim.x * kSampleWaves) {
+        // lane l holds bins 8 l .. 8 l + 7 (negative counts, which a search never
+        // writes, count as empty)
+        const int4* src = (const int4*)(A.hist + s * (uint64_t)kHistBins) + 2u * lane;
+        const int4 a = src[0], b = src[1];
+        int32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            v[i] = v[i] > 0 ? v[i] : 0;
+            h[8u * lane + i] = v[i];
+        }
+        // the three most intense bins: key = count, then the lower bin
+        uint32_t used = 0, sum = 0, t = 0;
+        for (int r = 0; r < 3; ++r) {
+            unsigned long long best = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const unsigned long long key =
+                    ((unsigned long long)(uint32_t)v[i] << 32) | (uint32_t)(kHistBins - 1 - (8u * lane + i));
+                if (v[i] > 0 && !((used >> i) & 1u) && key > best) best = key;
+            }
+            best = wave_max_u64(best);
+            if (best == 0) break;                                   // wave-uniform
+            const uint32_t bin = (uint32_t)(kHistBins - 1) - (uint32_t)(best & 0xFFFFFFFFull);
+            if (bin / 8u == lane) used |= 1u << (bin % 8u);
+            sum += bin;
+            ++t;
+        }
+        uint32_t first = kHistBins;
+#pragma unroll
+        for (int i = 7; i >= 0; --i)
+            if (v[i] > 0) first = 8u * lane + i;
+        first = wave_min_u32(first);
+        int lo = 0;
+        if (t) {
+            const int mean = (int)(sum / t);
+            lo = (int)first > mean - PS_SAMPLE_HEAD ? (int)first : mean - PS_SAMPLE_HEAD;
+            lo = min(lo, kHistBins - PS_SAMPLE_BINS);
+        }
+        // flags from this lane's bins
+        bool sat = false, lost = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = (int)(8u * lane) + i;
+            const bool inside = j >= lo && j < lo + PS_SAMPLE_BINS;
+            sat |= inside && v[i] > 65535;
+            lost |= !inside && v[i] > 0;
+        }
+        const uint32_t flags = (__ballot(sat) ? 1u : 0u) | (__ballot(lost) ? 2u : 0u);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the wave's LDS writes are visible to it
+        // 64 words of the record: header, then count pairs
+        uint32_t word;
+        if (lane == 0) {
+            word = (uint32_t)lo | (flags << 16);
+        } else if (lane == 1) {
+            word = 0;
+        } else if (lane < 4) {
+            const uint64_t ns = A.stats[s].n_scored;
+            word = lane == 2 ? (uint32_t)ns : (uint32_t)(ns >> 32);
+        } else {
+            const int i = 2 * (int)(lane - 4);
+            const int32_t c0 = h[lo + i], c1 = h[lo + i + 1];
+            word = (uint32_t)min(c0, 65535) | ((uint32_t)min(c1, 65535) << 16);
+        }
+        ((uint32_t*)(A.out + s))[lane] = word;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // reads done before the next spectrum's writes
+    }
+}
+
+hipError_t launch_sample(const int32_t* hist, const ps_stat* stats, ps_sampled* out, uint64_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    SampleArgs a{hist, stats, out, n};
+    const uint64_t blocks = (n + kSampleWaves - 1) / kSampleWaves;
+    const uint32_t grid = (uint32_t)(blocks < (1u << 20) ? blocks : (1u << 20));
+    hipLaunchKernelGGL(k_sample, dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

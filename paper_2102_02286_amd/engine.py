@@ -283,7 +283,7 @@ def collect(batch, n: int, params: capi.ps_search_params) -> Results:
 def _device_results(batch):
     h, st, hg = C.c_void_p(), C.c_void_p(), C.c_void_p()
     check(capi.ps_batch_device_results(batch, C.byref(h), C.byref(st), C.byref(hg)), "ps_batch_device_results")
-    return capi.ps_part(h.value, st.value, hg.value)
+    return capi.ps_part(h.value, st.value, hg.value, None)
 
 
 class AssembleOut:
@@ -308,6 +308,25 @@ class AssembleOut:
         stats = raw[self.o_stats:self.o_stats + n * 32].view(capi.STAT_DTYPE).copy()
         hist = raw[self.o_hist:self.o_hist + n * capi.PS_HIST_BINS * 4].view(np.int32).reshape(n, capi.PS_HIST_BINS).copy()
         return hits, stats, hist
+
+
+def sample(part, n: int, stream=None, device: str = "cuda:0", rec=None):
+    """Enqueue ps_sample on a partition result `part` (ps_part with full
+    histograms).  Returns (the ps_part that gives the 256-byte records instead
+    of the histograms, the device tensor holding the records; `rec` reuses one
+    of at least n * 256 bytes)."""
+    torch = _torch()
+    if rec is None:
+        rec = torch.empty(max(n, 1) * capi.SAMPLED_DTYPE.itemsize, dtype=torch.uint8, device=device)
+    elif rec.numel() < n * capi.SAMPLED_DTYPE.itemsize:
+        raise ValueError("record buffer too small")
+    st = stream if stream is not None else torch.cuda.current_stream(rec.device)
+    check(capi.ps_sample(st.cuda_stream, n, part.hist, part.stats, rec.data_ptr()), "ps_sample")
+    return capi.ps_part(part.hits, part.stats, None, rec.data_ptr()), rec
+
+
+def sampled_to_host(rec, n: int) -> np.ndarray:
+    return rec.cpu().numpy()[:n * capi.SAMPLED_DTYPE.itemsize].view(capi.SAMPLED_DTYPE).copy()
 
 
 def assemble(parts, n: int, top_k: int, out: AssembleOut, stream=None, fit: int = capi.PS_FIT_TAIL):

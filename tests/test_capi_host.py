@@ -34,7 +34,8 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(capi.ps_device) == 24
     assert C.sizeof(capi.ps_mod) == 24
     assert C.sizeof(capi.ps_db_params) == 48
-    assert C.sizeof(capi.ps_part) == 24
+    assert C.sizeof(capi.ps_part) == 32
+    assert capi.SAMPLED_DTYPE.itemsize == 256
     assert C.sizeof(capi.ps_spectra) == 48
     assert C.sizeof(capi.ps_search_params) == 56
     assert capi.HIT_DTYPE.itemsize == 24 and capi.STAT_DTYPE.itemsize == 32
@@ -269,7 +270,20 @@ def test_partition_and_assemble_argument_checks_without_device():
     assert capi.ps_assemble(None, 2, parts, 1, 5, 2, 1, 1, 1) == capi.PS_EINVAL     # unknown fit
     assert capi.ps_assemble(None, 2, parts, 1, 5, 0, 1, 1, 1) == capi.PS_EINVAL     # NULL partition pointers
     assert "partition 0" in capi.last_error()
+    # exactly one of the full and the sampled histograms
+    parts[0] = capi.ps_part(8, 8, 8, 8)
+    parts[1] = capi.ps_part(8, 8, 8, None)
+    assert capi.ps_assemble(None, 2, parts, 1, 5, 0, 1, 1, 1) == capi.PS_EINVAL
+    assert "exactly one of hist and sampled" in capi.last_error()
+    parts[0] = capi.ps_part(8, 8, None, None)
+    assert capi.ps_assemble(None, 2, parts, 1, 5, 0, 1, 1, 1) == capi.PS_EINVAL
+    assert "exactly one of hist and sampled" in capi.last_error()
     assert capi.ps_assemble(None, 2, parts, 0, 5, 0, None, None, None) == capi.PS_OK  # nothing to do
+    # sampling: NULL pointers are rejected before any device work; nothing to do is fine
+    assert capi.ps_sample(None, 1, None, 8, 8) == capi.PS_EINVAL
+    assert capi.ps_sample(None, 1, 8, None, 8) == capi.PS_EINVAL
+    assert capi.ps_sample(None, 1, 8, 8, None) == capi.PS_EINVAL
+    assert capi.ps_sample(None, 0, None, None, None) == capi.PS_OK
 
 
 def test_bulk_entries_match_single_entries():

@@ -183,7 +183,7 @@ def test_assembly_of_graph_plan_results(open_parts):
             p.results()                                 # waits for the run
             h, st, hg = C.c_void_p(), C.c_void_p(), C.c_void_p()
             capi.check(capi.ps_plan_device_results(p.handle, C.byref(h), C.byref(st), C.byref(hg)))
-            pp.append(capi.ps_part(h.value, st.value, hg.value))
+            pp.append(capi.ps_part(h.value, st.value, hg.value, None))
         out = engine.AssembleOut(batch.n, prm.top_k)
         engine.assemble(pp, batch.n, prm.top_k, out, fit=prm.fit)
         torch.cuda.synchronize()
@@ -206,3 +206,114 @@ def test_gumbel_fit_parity_whole_and_partitioned(open_parts, schedule):
     assert_parity(ref, oh, ost, og)
     res = engine.search_partitioned(parts[3], sp, prm)
     _assert_identical(res, ref)
+
+
+# ---------------------------------------------------------------------------
+# sampled partial results (Sampling section; the shift of Superstep 4)
+# ---------------------------------------------------------------------------
+
+def _synthetic_histograms(n, seed):
+    """Histograms of every shape: narrow, wide, long heads and tails, ties
+    among the largest counts, counts past 16 bits, at both ends of the range,
+    and empty ones."""
+    rng = np.random.default_rng(seed)
+    hs = np.zeros((n, capi.PS_HIST_BINS), np.int32)
+    for i in range(n):
+        kind = i % 6
+        if kind == 5:
+            continue                                    # empty
+        a = int(rng.integers(0, capi.PS_HIST_BINS)) if kind != 4 else int(rng.integers(430, 500))
+        b = min(capi.PS_HIST_BINS, a + int(rng.integers(1, [30, 121, 300, 512, 200][kind])))
+        hs[i, a:b] = rng.integers(0, [3, 50, 1000, 80000, 9][int(rng.integers(0, 5))], b - a)
+        if rng.random() < 0.3:
+            hs[i, rng.integers(a, b, 3)] = hs[i].max()
+    return hs
+
+
+@pytest.mark.parametrize("n", [1, 5, 1027])
+def test_sampling_matches_oracle_records(n):
+    """ps_sample against the oracle's records, byte for byte, on histograms of
+    every shape (n ragged against the four spectra a workgroup samples)."""
+    import torch
+    _say(f"sampling: {n} synthetic histograms")
+    hs = _synthetic_histograms(n, seed=n)
+    ns = np.random.default_rng(1).integers(0, 1 << 40, n).astype(np.uint64)
+    stats = np.zeros(n, capi.STAT_DTYPE)
+    stats["n_scored"] = ns
+    d_hist = torch.from_numpy(hs).cuda()
+    d_stats = torch.from_numpy(stats.view(np.uint8)).cuda()
+    part = capi.ps_part(None, d_stats.data_ptr(), d_hist.data_ptr(), None)
+    _, rec = engine.sample(part, n)
+    torch.cuda.synchronize()
+    got = engine.sampled_to_host(rec, n)
+    want = oracle.sample(hs, ns)
+    assert got.tobytes() == want.tobytes()
+    assert (got["flags"] & 1).any() and (got["flags"] & 2).any() if n > 100 else True
+
+
+def _oracle_sampled_assembly(db, sp, w, G, sampled_parts, fit=oracle.FIT_TAIL):
+    parts = [db.shard(G, g).search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k,
+                                   w.min_shared, fit=fit) for g in range(G)]
+    recs = [oracle.sample(p[2], p[1]["n_scored"]) for p in parts]
+    hists = [oracle.unsample(recs[g]) if g in sampled_parts else parts[g][2] for g in range(G)]
+    return recs, oracle.assemble([p[0] for p in parts], [p[1] for p in parts], hists, fit=fit)
+
+
+class _Res:
+    def __init__(self, hits, stats, hist):
+        self.hits, self.stats, self.hist = hits, stats, hist
+
+
+@pytest.mark.parametrize("fit", [capi.PS_FIT_TAIL, capi.PS_FIT_GUMBEL])
+@pytest.mark.parametrize("sampled_parts", [(0, 1, 2), (1,)])
+def test_sampled_assembly_matches_oracle(open_parts, fit, sampled_parts):
+    """Three partitions searched on the GPU, their histograms sampled on the
+    device (all, or only partition 1), assembled from the samples: equal to the
+    oracle's assembly of its own sampled partition results (records byte for
+    byte, hits and histograms exact, expect values 1e-5 relative).  Spectra
+    whose samples lost nothing equal the full assembly bit for bit."""
+    import torch
+    w, prot, sp, whole, parts, db, _ = open_parts
+    G = 3
+    _say(f"sampled assembly: fit {fit}, sampled partitions {sampled_parts}")
+    prm = _params(w, capi.PS_SCHED_PLAIN, fit=fit)
+    s, keep = engine._spectra_struct(sp)
+    ws = [engine.Workspace() for _ in range(G)]
+    batches, pp, recs = [], [], []
+    try:
+        for g, ix in enumerate(parts[G]):
+            need = C.c_uint64()
+            nnz = int(sp.peak_off[-1])
+            capi.check(capi.ps_workspace_bytes(ix.handle, sp.n, nnz, C.byref(prm), C.byref(need)))
+            dev = ws[g].get(need.value)
+            bh = C.c_void_p()
+            capi.check(capi.ps_search_batch(ix.handle, C.byref(dev), C.byref(s), C.byref(prm), C.byref(bh)))
+            batches.append(bh)
+            full = engine._device_results(bh)
+            if g in sampled_parts:
+                part, rec = engine.sample(full, sp.n)
+                recs.append((g, rec))
+                pp.append(part)
+            else:
+                pp.append(full)
+        for bh in batches:
+            engine.collect(bh, sp.n, prm)               # waits for the searches
+        out = engine.AssembleOut(sp.n, prm.top_k)
+        engine.assemble(pp, sp.n, prm.top_k, out, fit=fit)
+        full_out = engine.AssembleOut(sp.n, prm.top_k)
+        engine.assemble([engine._device_results(bh) for bh in batches], sp.n, prm.top_k, full_out, fit=fit)
+        torch.cuda.synchronize()
+        hits, stats, hist = out.to_host()
+        fh, fst, fhist = full_out.to_host()
+        got_recs = {g: engine.sampled_to_host(r, sp.n) for g, r in recs}
+    finally:
+        for bh in batches:
+            capi.ps_batch_free(bh)
+    orecs, (oh, ost, og) = _oracle_sampled_assembly(db, sp, w, G, sampled_parts, fit=fit)
+    for g, r in got_recs.items():
+        assert r.tobytes() == orecs[g].tobytes(), f"records of partition {g} differ"
+    assert_parity(_Res(hits, stats, hist), oh, ost, og)
+    lossless = np.all([got_recs[g]["flags"] == 0 for g in got_recs], axis=0)
+    assert lossless.sum() > 40
+    for f, a, b in (("hits", hits, fh), ("stats", stats, fst), ("hist", hist, fhist)):
+        assert a[lossless].tobytes() == b[lossless].tobytes(), f
