@@ -384,7 +384,7 @@ DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_post, uint64_
     uint64_t o = 0;
     L.mass = o; o = align256(o + n_pep * sizeof(int64_t));
     L.bin = o; o = align256(o + (n_bins + 1) * sizeof(uint64_t));
-    L.post = o; o = align256(o + n_post * sizeof(uint32_t));
+    L.post = o; o = align256(o + n_post * sizeof(uint32_t) + 16);   // the scan reads whole aligned quads
     L.lf = o; o = align256(o + kLfSize * sizeof(double));
     L.ls = o; o = align256(o + kLsSize * sizeof(double));
     L.dir = o; o = align256(o + n_dir * sizeof(uint32_t));

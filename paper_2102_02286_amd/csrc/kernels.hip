@@ -400,10 +400,12 @@ struct ScanArgs {
     uint32_t per_item;         // partial lists indexed by work item (persistent schedule)
 };
 
-constexpr uint32_t kRounds = 8;       // gather rounds of 64 postings a wavefront keeps in flight
+constexpr uint32_t kRounds = 2;       // gather rounds of 64 posting quads a wavefront keeps in flight
 constexpr uint32_t kCandCap = 384;    // candidates buffered per workgroup before scoring
 constexpr uint32_t kWaveCand = kCandCap / (kBlock / 64);   // each wavefront's share of the buffer
-constexpr uint32_t kMapCap = 4096;    // flat posting positions mapped to slots at a time
+constexpr uint32_t kMapCap = 1024;    // flat quad positions mapped to slots at a time
+// map words: one per 64 quads, plus one for the start bit just past the chunk
+constexpr uint32_t kMapWords = kMapCap / 64 + 1;
 // s_waitcnt operand (gfx9 encoding): vmcnt(0), expcnt and lgkmcnt left at their maxima
 constexpr int kWaitVmem0 = 0x0F70;
 
@@ -423,15 +425,18 @@ struct SlotInit {
     uint32_t bin, s0, s1, q, e0, e1;
 };
 
-// A slot with postings in the current tile, by rank among such slots: flat
-// position f of its range reads post[base + f]; q is its peak's intensity.
+// A slot with postings in the current tile, by rank among such slots.  Its run
+// [cur, end) is read in aligned quads of postings: flat quad position f of its
+// range reads post[base + 4 f .. base + 4 f + 3].  qx = q (its peak's
+// intensity) | lead << 8 (postings before cur in its first quad) | (tail - 1)
+// << 10 (postings of the run in its last quad, 1..4).
 struct SegBase {
-    uint32_t base, q;
+    uint32_t base, qx;
 };
 
 // LDS layout (dynamic):
 //   counters (the SlotInit array before the first tile) | SegBase[seg_cap] |
-//   range starts [seg_cap] | map bits [kMapCap / 64] (u64) | map ranks [kMapCap / 64] |
+//   range starts [seg_cap] | map bits [kMapWords] (u64) | map ranks [kMapCap / 64] |
 //   candidate counters | histogram | candidate positions
 //
 // The map of a chunk of kMapCap flat positions: bit b of mbits[R] is set when
@@ -455,7 +460,7 @@ struct ScanLds {
         const size_t head = max((size_t)tile * sizeof(C), (size_t)segcap * sizeof(SlotInit));
         o += (head + 15) & ~(size_t)15;
         sbase = (SegBase*)(base + o); o += (size_t)segcap * sizeof(SegBase);
-        mbits = (unsigned long long*)(base + o); o += (size_t)(kMapCap / 64) * 8;
+        mbits = (unsigned long long*)(base + o); o += (size_t)kMapWords * 8;
         sstart = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         mrank = (uint32_t*)(base + o); o += (size_t)(kMapCap / 64) * 4;
         o = (o + 15) & ~(size_t)15;
@@ -469,7 +474,7 @@ size_t scan_lds_bytes(const KParams& kp, bool wide) {
     const size_t csz = wide ? 8 : 4;
     const size_t head = std::max((size_t)kp.tile * csz, (size_t)kp.seg_cap * sizeof(SlotInit));
     size_t o = (head + 15) & ~(size_t)15;
-    o += (size_t)kp.seg_cap * (sizeof(SegBase) + 4) + (size_t)(kMapCap / 64) * 12;
+    o += (size_t)kp.seg_cap * (sizeof(SegBase) + 4) + (size_t)kMapWords * 8 + (size_t)(kMapCap / 64) * 4;
     o = (o + 15) & ~(size_t)15;
     o += (size_t)kCandCap * csz;
     o += (size_t)kHistBins * 4;
@@ -579,11 +584,13 @@ __device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsign
 // Enter the slot of rank k, whose range is [a, b), into the map of the chunk
 // [c0, c0 + kMapCap): its start bit, and the rank of every 64-position round
 // that begins inside it.
+// A start exactly at the chunk's end is entered too (word kMapCap / 64): it
+// ends the chunk's last slot.
 template <typename C>
 __device__ __forceinline__ void map_slot(const ScanLds<C>& L, uint32_t k, uint32_t a, uint32_t b, uint32_t c0) {
     const uint32_t ce = c0 + kMapCap;
+    if (a >= c0 && a <= ce) atomicOr(&L.mbits[(a - c0) >> 6], 1ull << ((a - c0) & 63u));
     if (b <= c0 || a >= ce) return;
-    if (a >= c0) atomicOr(&L.mbits[(a - c0) >> 6], 1ull << ((a - c0) & 63u));
     const uint32_t lo = max(a, c0), hi = min(b, ce);
     for (uint32_t r = (lo - c0 + 63u) >> 6; (r << 6) < hi - c0; ++r) L.mrank[r] = k;
 }
@@ -592,31 +599,40 @@ __device__ __forceinline__ void map_slot(const ScanLds<C>& L, uint32_t k, uint32
 // of the chunk's flat posting positions, and up to kRounds x 64 postings
 // already loaded.
 struct Gather {
-    uint32_t c0, fe, next;
-    uint32_t p[kRounds];
-    uint32_t q4[(kRounds + 3) / 4];   // intensity of round r in byte r % 4 of q4[r / 4]; 0: no posting
+    uint32_t c0, fe, next;             // quad positions
+    uint4 p[kRounds];
+    uint32_t mq[(kRounds + 1) / 2];    // round r in half r % 2: elements of the run (bits 0-3) | q << 4
 };
 
-// Map flat positions [g.next, g.next + 64 * kRounds) of this wavefront to
-// slots through the chunk map and issue their posting loads.  A round is 64
-// aligned positions, so its map word and round rank are broadcast reads; the
-// rounds are independent and their reads issue back to back.
+// Map flat quad positions [g.next, g.next + 64 * kRounds) of this wavefront
+// to slots through the chunk map and issue their posting loads (16 aligned
+// bytes per lane).  A round is 64 aligned positions, so its map word and round
+// rank are broadcast reads.  A quad is the first of its slot when its own
+// start bit is set and the last when the next position's is (the bit past
+// the chunk, or the end marker after the last slot): only there do postings
+// outside the run share the quad.
 template <typename C>
 __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C>& L, Gather& g) {
     const uint32_t lane = threadIdx.x & 63u;
     const unsigned long long below = (2ull << lane) - 2ull;   // positions 1..lane of a round
 #pragma unroll
-    for (uint32_t r = 0; r < (kRounds + 3) / 4; ++r) g.q4[r] = 0;
+    for (uint32_t r = 0; r < (kRounds + 1) / 2; ++r) g.mq[r] = 0;
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t f = g.next + 64u * r + lane;
         const bool valid = f < g.fe;
         const uint32_t R = min((g.next - g.c0) / 64u + r, kMapCap / 64u - 1u);   // clamped: rounds past fe
         const unsigned long long bits = L.mbits[R];
+        const unsigned long long after = L.mbits[R + 1];
         const uint32_t k = L.mrank[R] + (uint32_t)__popcll(bits & below);
         const SegBase sb = L.sbase[valid ? k : 0u];
-        g.p[r] = valid ? ix.post[sb.base + f] : 0u;
-        g.q4[r / 4] |= (valid ? sb.q : 0u) << (8u * (r % 4u));
+        g.p[r] = valid ? *(const uint4*)(ix.post + (sb.base + 4u * f)) : make_uint4(0u, 0u, 0u, 0u);
+        const bool first = (bits >> lane) & 1ull;
+        const bool last = (lane < 63u ? (bits >> (lane + 1u)) : after) & 1ull;
+        const uint32_t lead = first ? (sb.qx >> 8) & 3u : 0u;
+        const uint32_t keep = last ? ((sb.qx >> 10) & 3u) + 1u : 4u;
+        const uint32_t m4 = valid ? (0xFu << lead) & (0xFu >> (4u - keep)) : 0u;
+        g.mq[r / 2] |= (m4 | (sb.qx & 0xFFu) << 4) << (16u * (r % 2u));
     }
     g.next += 64u * kRounds;
 }
@@ -625,10 +641,18 @@ template <typename C>
 __device__ __forceinline__ void gather_consume(const ScanLds<C>& L, const Gather& g, uint32_t tsh) {
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
-        if ((g.q4[r / 4] >> (8u * (r % 4u))) & 0xFFu) {
-            // tiles are aligned to their size: the counter is the id modulo the tile
-            const uint32_t p = g.p[r];
-            atomicAdd(&L.cnt[__builtin_amdgcn_ubfe(p, 1u, tsh)], Cnt<C>::inc_packed(p & 1u, g.q4[r / 4], r % 4u));
+        const uint32_t w = g.mq[r / 2] >> (16u * (r % 2u));
+        if (w & 0xFu) {
+            const uint32_t q = (w >> 4) & 0xFFu;
+            const uint32_t e4[4] = {g.p[r].x, g.p[r].y, g.p[r].z, g.p[r].w};
+#pragma unroll
+            for (uint32_t e = 0; e < 4; ++e) {
+                if ((w >> e) & 1u) {
+                    // tiles are aligned to their size: the counter is the id modulo the tile
+                    const uint32_t p = e4[e];
+                    atomicAdd(&L.cnt[__builtin_amdgcn_ubfe(p, 1u, tsh)], Cnt<C>::inc(p & 1u, q));
+                }
+            }
         }
     }
 }
@@ -752,12 +776,14 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
 
     // ranks, flat ranges and the map of the first chunk of the tile whose
     // slots hold [o_cur, o_end), then this wavefront's first gather batch
+    // quads of postings a run [cur, end) covers (0 when empty)
+    auto quads = [](uint32_t cur, uint32_t end) { return end > cur ? ((cur & 3u) + (end - cur) + 3u) >> 2 : 0u; };
     auto prepare = [&]() {
-        for (uint32_t i = tid; i < kMapCap / 64u; i += kBlock) L.mbits[i] = 0ull;
+        for (uint32_t i = tid; i < kMapWords; i += kBlock) L.mbits[i] = 0ull;
         uint32_t mine = 0, mine_ne = 0;
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {                 // unowned slots are 0 - 0
-            const uint32_t n = o_end[u] - o_cur[u];
+            const uint32_t n = quads(o_cur[u], o_end[u]);
             mine += n;
             mine_ne += n != 0u;
         }
@@ -765,11 +791,12 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         block_scan_counts<U>(mine, mine_ne, sh.wsum, &run, &rank, &total_n, &total_ne);
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t n = o_end[u] - o_cur[u];
+            const uint32_t n = quads(o_cur[u], o_end[u]);
             if (n) {
+                const uint32_t a = o_cur[u] & ~3u;      // the run's first aligned quad
                 SegBase sb;
-                sb.base = o_cur[u] - run;
-                sb.q = o_bq[u] >> 24;
+                sb.base = a - 4u * run;
+                sb.qx = (o_bq[u] >> 24) | (o_cur[u] & 3u) << 8 | (o_end[u] - a - 4u * (n - 1u) - 1u) << 10;
                 L.sbase[rank] = sb;
                 L.sstart[rank] = run;
                 map_slot<C>(L, rank, run, run + n, 0u);
@@ -779,6 +806,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         }
         ptot = total_n;
         nne = total_ne;
+        if (tid == 0 && total_n <= kMapCap) atomicOr(&L.mbits[total_n >> 6], 1ull << (total_n & 63u));   // end marker
         __syncthreads();
         share(0u, ptot);
         gather_issue<C>(ix, L, g);
@@ -820,10 +848,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         const uint32_t p_t = ptot;
         for (uint32_t c0 = kMapCap; c0 < p_t; c0 += kMapCap) {
             __syncthreads();                            // every wavefront is done with the last map
-            for (uint32_t i = tid; i < kMapCap / 64u; i += kBlock) L.mbits[i] = 0ull;
+            for (uint32_t i = tid; i < kMapWords; i += kBlock) L.mbits[i] = 0ull;
             __syncthreads();
             for (uint32_t k = tid; k < nne; k += kBlock)
                 map_slot<C>(L, k, L.sstart[k], k + 1 < nne ? L.sstart[k + 1] : p_t, c0);
+            if (tid == 0 && p_t - c0 <= kMapCap) atomicOr(&L.mbits[(p_t - c0) >> 6], 1ull << ((p_t - c0) & 63u));
             __syncthreads();
             share(c0, p_t);
             while (g.next < g.fe) {
@@ -943,7 +972,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
 
 // Plain schedule: workgroup s searches spectrum s's whole window.
 template <typename C, bool DUMP, uint32_t U>
-__global__ __launch_bounds__(kBlock) void k_scan_plain(ScanArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(U == 1 ? 6 : 1, 8))) void k_scan_plain(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ ScanShared sh;
     ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap);
