@@ -405,7 +405,7 @@ def main():
         capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(default)))
         if not args.no_tune:
             t0 = time.perf_counter()
-            best, trials = engine.autotune(ix, sp.subset(np.arange(0, min(sp.n, 5000))), prm,
+            best, trials = engine.autotune(ix, sp.subset(np.arange(0, min(sp.n, 20000))), prm,
                                            cache_path=args.tune_cache)
             log(f"autotune {name}: {len(trials)} trials in {time.perf_counter() - t0:.1f}s -> {as_dict(best)}")
         tuned[name] = capi.ps_schedule.from_buffer_copy(ix.schedule())
