@@ -216,9 +216,13 @@ struct PrepArgs {
     Work w;
 };
 
+// Peaks a spectrum may have for k_prep to stage them in LDS; larger spectra are
+// read from global memory.  Small enough that five workgroups fit a CU.
+constexpr uint32_t kPrepLdsPeaks = 1024;
+
 __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
-    __shared__ float s_mz[PS_MAX_PEAKS_IN];
-    __shared__ float s_in[PS_MAX_PEAKS_IN];
+    __shared__ float s_mz[kPrepLdsPeaks];
+    __shared__ float s_in[kPrepLdsPeaks];
     __shared__ uint32_t s_ent[PS_MAX_TOP_PEAKS * (PS_MAX_CHARGE - 1)];
     __shared__ uint32_t s_flag, s_imax_bits, s_mult, s_alive;
     __shared__ unsigned long long s_red[kBlock / 64];
@@ -255,12 +259,20 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         const uint32_t np = s_flag ? 0u : (uint32_t)(p1 - p0);
         for (uint32_t i = tid; i < np; i += kBlock) {
             float m = A.sp.mz[p0 + i], v = A.sp.inten[p0 + i];
-            s_mz[i] = m;
-            s_in[i] = v;
+            if (np <= kPrepLdsPeaks) {
+                s_mz[i] = m;
+                s_in[i] = v;
+            }
             if (!(m > 0.0f) || !(m <= 3.0e38f) || !(v >= 0.0f) || !(v <= 3.0e38f)) atomicOr(&s_flag, 1u);
             else atomicMax(&s_imax_bits, __float_as_uint(v));   // ordered like floats for v >= 0
         }
         __syncthreads();
+        // the peaks: staged in LDS, or read where they are when there are more
+        const bool lds = np <= kPrepLdsPeaks;
+        const float* gmz = A.sp.mz + p0;
+        const float* gin = A.sp.inten + p0;
+        auto mz_at = [&](uint32_t i) { return lds ? s_mz[i] : gmz[i]; };
+        auto in_at = [&](uint32_t i) { return lds ? s_in[i] : gin[i]; };
         const bool bad = s_flag != 0;
         const float imax = __uint_as_float(s_imax_bits);
         const uint32_t cmax = z > 2 ? (uint32_t)(z - 1) : 1u;
@@ -271,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         if (kp.noise_permille) {
             uint32_t mine = 0;
             for (uint32_t i = tid; i < np; i += kBlock)
-                mine += (double)s_in[i] * 1000.0 >= (double)imax * (double)kp.noise_permille ? 1u : 0u;
+                mine += (double)in_at(i) * 1000.0 >= (double)imax * (double)kp.noise_permille ? 1u : 0u;
             if (mine) atomicAdd(&s_alive, mine);
             __syncthreads();
             alive = s_alive;
@@ -282,11 +294,18 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         // top-B by (intensity desc, m/z asc, input order asc): rank = number of better peaks
         if (!bad) {
             for (uint32_t i = tid; i < np; i += kBlock) {
-                const float mi = s_mz[i], vi = s_in[i];
+                const float mi = mz_at(i), vi = in_at(i);
                 uint32_t rank = 0;
-                for (uint32_t j = 0; j < np; ++j) {
-                    const float mj = s_mz[j], vj = s_in[j];
-                    rank += (vj > vi) || (vj == vi && (mj < mi || (mj == mi && j < i)));
+                if (lds) {
+                    for (uint32_t j = 0; j < np; ++j) {
+                        const float mj = s_mz[j], vj = s_in[j];
+                        rank += (vj > vi) || (vj == vi && (mj < mi || (mj == mi && j < i)));
+                    }
+                } else {
+                    for (uint32_t j = 0; j < np; ++j) {
+                        const float mj = gmz[j], vj = gin[j];
+                        rank += (vj > vi) || (vj == vi && (mj < mi || (mj == mi && j < i)));
+                    }
                 }
                 if (rank >= keep) continue;
                 // integer intensity q in [1, 100] relative to the most intense peak

@@ -297,6 +297,39 @@ def test_edge_cases_parity(small_open):
             assert_parity(res, oh, ost, og)
 
 
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
+def test_spectra_with_many_peaks_parity(small_open, schedule):
+    """Spectra with more peaks than the prep stages in LDS (up to the 4096
+    allowed), with intensity ties broken by m/z and by input order, next to
+    small ones: top-B selection and everything after it against the oracle."""
+    w, prot, sp, ix, db, _ = small_open
+    rng = np.random.default_rng(21)
+    lists, prec, ch = [], [], []
+    for n_peaks in (1023, 1024, 1025, 2000, 4096, 60):
+        pid = int(rng.integers(0, len(db)))
+        b, y = oracle.ions(db.residue_masses(pid))
+        ions = [float(m) * 1e-6 for m in np.concatenate([b, y])]
+        mz = np.concatenate([ions, rng.uniform(150.0, 2000.0, max(0, n_peaks - len(ions)))])[:n_peaks]
+        inten = rng.integers(1, 40, n_peaks).astype(np.float64)      # many equal intensities
+        inten[:min(len(ions), n_peaks)] += 20.0                       # the true ions among the strongest
+        mz[5::97] = mz[4::97][:len(mz[5::97])]                        # equal m/z and intensity: input order decides
+        inten[5::97] = inten[4::97][:len(inten[5::97])]
+        lists.append(list(zip(mz.tolist(), inten.tolist())))
+        prec.append((db.get(pid)[0] * 1e-6 + 2 * 1.007276) / 2)
+        ch.append(2 + (n_peaks % 2))
+    sp_m = _mk(lists, prec, ch)
+    for top_b, noise, inten_mode in ((100, 0, capi.PS_INTENSITY_LINEAR), (256, 50, capi.PS_INTENSITY_SQRT)):
+        _say(f"many peaks: schedule {schedule}, B={top_b}, noise {noise}, intensity {inten_mode}")
+        prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, top_b, w.top_k, w.min_shared,
+                                   max_charge=3, schedule=schedule, noise_permille=noise, intensity=inten_mode)
+        res = engine.search(ix, sp_m, prm)
+        oh, ost, og = db.search(sp_m, w.window_is_ppm, w.window, w.frag_tol_bins, top_b, w.top_k, w.min_shared,
+                                noise_permille=noise, intensity=oracle.INTENSITY_SQRT if inten_mode else
+                                oracle.INTENSITY_LINEAR)
+        assert_parity(res, oh, ost, og)
+        assert (ost["status"] == 0).sum() >= 5
+
+
 def test_wide_counters_are_used_and_exact(small_open):
     """A spectrum whose peaks pile into one bin needs 64-bit counters; the
     result must still equal the oracle's unbounded counts."""
