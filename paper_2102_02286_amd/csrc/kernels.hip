@@ -615,8 +615,8 @@ __device__ __forceinline__ void map_slot(const ScanLds<C>& L, uint32_t k, uint32
 }
 
 // Gather state of one wavefront in the current chunk: its share [next, fe)
-// of the chunk's flat posting positions, and up to kRounds x 64 postings
-// already loaded.
+// of the chunk's flat quad positions, and up to kRounds x 64 quads of
+// postings already loaded.
 struct Gather {
     uint32_t c0, fe, next;             // quad positions
     uint4 p[kRounds];
