@@ -110,8 +110,11 @@ class HostIndex:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            capi.ps_index_free(h)
+        if h is not None and h.value and capi is not None:   # module globals are gone at interpreter exit
+            try:
+                capi.ps_index_free(h)
+            except (AttributeError, TypeError):
+                return
             self.handle = None
 
     def shape(self):
@@ -417,8 +420,11 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            capi.ps_plan_free(h)
+        if h is not None and h.value and capi is not None:   # module globals are gone at interpreter exit
+            try:
+                capi.ps_plan_free(h)
+            except (AttributeError, TypeError):
+                return
             self.handle = None
 
     def run(self, sp):
