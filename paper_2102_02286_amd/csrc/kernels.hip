@@ -220,9 +220,16 @@ struct PrepArgs {
 // read from global memory.  Small enough that five workgroups fit a CU.
 constexpr uint32_t kPrepLdsPeaks = 1024;
 
+// Ranking key of a peak: intensity bits over inverted m/z bits.  For finite
+// m/z > 0 and intensity >= 0 (-0 taken as +0) a larger key is a more intense
+// peak, or an equally intense one at lower m/z; equal keys are equal peaks.
+__device__ __forceinline__ unsigned long long peak_key(float mz, float in) {
+    const uint32_t vb = in == 0.0f ? 0u : __float_as_uint(in);
+    return ((unsigned long long)vb << 32) | (uint32_t)~__float_as_uint(mz);
+}
+
 __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
-    __shared__ float s_mz[kPrepLdsPeaks];
-    __shared__ float s_in[kPrepLdsPeaks];
+    __shared__ unsigned long long s_key[kPrepLdsPeaks];
     __shared__ uint32_t s_ent[PS_MAX_TOP_PEAKS * (PS_MAX_CHARGE - 1)];
     __shared__ uint32_t s_flag, s_imax_bits, s_mult, s_alive;
     __shared__ unsigned long long s_red[kBlock / 64];
@@ -259,10 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         const uint32_t np = s_flag ? 0u : (uint32_t)(p1 - p0);
         for (uint32_t i = tid; i < np; i += kBlock) {
             float m = A.sp.mz[p0 + i], v = A.sp.inten[p0 + i];
-            if (np <= kPrepLdsPeaks) {
-                s_mz[i] = m;
-                s_in[i] = v;
-            }
+            if (np <= kPrepLdsPeaks) s_key[i] = peak_key(m, v);
             if (!(m > 0.0f) || !(m <= 3.0e38f) || !(v >= 0.0f) || !(v <= 3.0e38f)) atomicOr(&s_flag, 1u);
             else atomicMax(&s_imax_bits, __float_as_uint(v));   // ordered like floats for v >= 0
         }
@@ -271,8 +275,9 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         const bool lds = np <= kPrepLdsPeaks;
         const float* gmz = A.sp.mz + p0;
         const float* gin = A.sp.inten + p0;
-        auto mz_at = [&](uint32_t i) { return lds ? s_mz[i] : gmz[i]; };
-        auto in_at = [&](uint32_t i) { return lds ? s_in[i] : gin[i]; };
+        auto key_at = [&](uint32_t i) { return lds ? s_key[i] : peak_key(gmz[i], gin[i]); };
+        auto mz_at = [&](uint32_t i) { return lds ? __uint_as_float(~(uint32_t)s_key[i]) : gmz[i]; };
+        auto in_at = [&](uint32_t i) { return lds ? __uint_as_float((uint32_t)(s_key[i] >> 32)) : gin[i]; };
         const bool bad = s_flag != 0;
         const float imax = __uint_as_float(s_imax_bits);
         const uint32_t cmax = z > 2 ? (uint32_t)(z - 1) : 1u;
@@ -295,16 +300,17 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         if (!bad) {
             for (uint32_t i = tid; i < np; i += kBlock) {
                 const float mi = mz_at(i), vi = in_at(i);
+                const unsigned long long ki = key_at(i);
                 uint32_t rank = 0;
                 if (lds) {
                     for (uint32_t j = 0; j < np; ++j) {
-                        const float mj = s_mz[j], vj = s_in[j];
-                        rank += (vj > vi) || (vj == vi && (mj < mi || (mj == mi && j < i)));
+                        const unsigned long long kj = s_key[j];
+                        rank += kj > ki || (kj == ki && j < i);
                     }
                 } else {
                     for (uint32_t j = 0; j < np; ++j) {
-                        const float mj = gmz[j], vj = gin[j];
-                        rank += (vj > vi) || (vj == vi && (mj < mi || (mj == mi && j < i)));
+                        const unsigned long long kj = peak_key(gmz[j], gin[j]);
+                        rank += kj > ki || (kj == ki && j < i);
                     }
                 }
                 if (rank >= keep) continue;
