@@ -579,7 +579,8 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
 template <uint32_t U>
 __device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsigned long long* wsum, uint32_t* n_ex,
                                                   uint32_t* e_ex, uint32_t* n_all, uint32_t* e_all) {
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar selects below
     const uint32_t incl = wave_inclusive_sum(n);
     uint32_t ex = 0, et = 0;
 #pragma unroll
