@@ -908,7 +908,10 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             constexpr uint32_t kPer = 16 / sizeof(C);
             const uint32_t nvec = kp.tile / kPer;
             uint4* cv = (uint4*)L.cnt;
-            for (uint32_t base = wave * 64u; base < nvec; base += kBlock) {   // nvec is a multiple of kBlock
+            // nvec is a multiple of 4 kBlock: four steps per pass, at fixed offsets
+            for (uint32_t base0 = wave * 64u; base0 < nvec; base0 += 4u * kBlock)
+#pragma unroll
+            for (uint32_t base = base0; base < base0 + 4u * kBlock; base += kBlock) {
                 const uint32_t i = base + lane;
                 const uint4 v = cv[i];
                 cv[i] = make_uint4(0u, 0u, 0u, 0u);
