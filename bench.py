@@ -275,7 +275,9 @@ def small_batch_leg(capi, engine, torch, ix, sp, params, use, sizes=(256, 1024, 
     """Graph-replayed searches of small batches (the serving regime): one
     workgroup per spectrum leaves most of the GPU idle when a batch holds fewer
     spectra than the GPU holds workgroups, while the persistent work queue
-    splits every window into items.  Spectra/s of both schedules, same results."""
+    splits every window into items.  Spectra/s of both schedules, same results;
+    the persistent schedule is autotuned for each batch size (its item size
+    matters most when batches are small)."""
     out = []
     for n in sizes:
         sub = sp.subset(np.arange(0, n))
@@ -285,6 +287,10 @@ def small_batch_leg(capi, engine, torch, ix, sp, params, use, sizes=(256, 1024, 
         ref = None
         for name, prm in params:
             use(name)
+            if name == "persistent":
+                best, _ = engine.autotune(ix, sub, prm)      # sets the index's schedule
+                row["persistent_schedule"] = {"tile": best.tile, "tiles_per_item": best.tiles_per_item,
+                                              "groups_per_cu": best.groups_per_cu}
             plan = engine.Plan(ix, prm, n_cap=n, nnz_cap=nnz)
             fill_plan_inputs(plan, tens, torch)
             plan.run_device(n, nnz)
@@ -303,7 +309,7 @@ def small_batch_leg(capi, engine, torch, ix, sp, params, use, sizes=(256, 1024, 
             row[name] = {"spectra_per_s": n / dt, "ms_per_batch": dt * 1e3}
             del plan
         log(f"small batch {n}: " + ", ".join(f"{k} {v['spectra_per_s']:.0f} spectra/s" for k, v in row.items()
-                                               if isinstance(v, dict)))
+                                               if isinstance(v, dict) and "spectra_per_s" in v))
         out.append(row)
     return out
 
