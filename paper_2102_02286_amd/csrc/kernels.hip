@@ -69,12 +69,6 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
 template <typename C> struct Cnt;
 template <> struct Cnt<uint32_t> {
     __device__ static uint32_t inc(uint32_t is_y, uint32_t q) { return (is_y ? (1u << 24) : (1u << 16)) + q; }
-    // the same from byte `byte` of a packed intensity word: (q | 1 << 16) from one
-    // byte permute, plus 0xFF0000 for a y ion
-    __device__ static uint32_t inc_packed(uint32_t is_y, uint32_t q4, uint32_t byte) {
-        const uint32_t qb = __builtin_amdgcn_perm(0x00010000u, q4, 0x0C060C00u | byte);
-        return is_y * 0xFF0000u + qb;                   // is_y is 0 or 1: one 24-bit multiply-add
-    }
     __device__ static uint32_t nb(uint32_t c) { return (c >> 16) & 0xFFu; }
     __device__ static uint32_t ny(uint32_t c) { return c >> 24; }
     __device__ static uint32_t s(uint32_t c) { return c & 0xFFFFu; }
@@ -89,9 +83,6 @@ template <> struct Cnt<unsigned long long> {
     __device__ static uint32_t ny(unsigned long long c) { return (uint32_t)(c >> 32) & 0xFFFFu; }
     __device__ static uint32_t s(unsigned long long c) { return (uint32_t)c; }
     __device__ static uint32_t shared(unsigned long long c) { return nb(c) + ny(c); }
-    __device__ static unsigned long long inc_packed(uint32_t is_y, uint32_t q4, uint32_t byte) {
-        return inc(is_y, (q4 >> (8u * byte)) & 0xFFu);
-    }
 };
 
 // Top-k of one wavefront, distributed over its lanes: lane j < k holds the
