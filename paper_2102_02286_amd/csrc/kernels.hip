@@ -1257,8 +1257,10 @@ __device__ void gumbel_fit(long long num0, long long num1, long long total, unsi
 // enters as OK, INVALID, OVERFLOW or NO_HITS; only OK is refined (to FEW_POINTS
 // or BAD_SLOPE).  Every thread of the block calls it; the result is valid in
 // thread 0.  Ends with the block synchronised.
-__device__ void expect_value(const int32_t* hg, unsigned long long N, double h1, int fit, int& status, double& ev,
-                             EvShared& S) {
+// Kept out of line: inlined into k_merge and k_assemble it took their register
+// count past 150 and their occupancy down to three workgroups per CU.
+__device__ __attribute__((noinline)) void expect_value(const int32_t* hg, unsigned long long N, double h1, int fit,
+                                                      int& status, double& ev, EvShared& S) {
     static_assert(kHistBins == 2 * kBlock, "two histogram bins per thread");
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     long long num[2];
