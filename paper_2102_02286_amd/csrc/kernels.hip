@@ -1258,7 +1258,8 @@ __device__ void gumbel_fit(long long num0, long long num1, long long total, unsi
 // or BAD_SLOPE).  Every thread of the block calls it; the result is valid in
 // thread 0.  Ends with the block synchronised.
 // Kept out of line: inlined into k_merge and k_assemble it took their register
-// count past 150 and their occupancy down to three workgroups per CU.
+// count past 150 and their occupancy down to three workgroups per CU (they now
+// ask for five, at 88-94 VGPRs; six would spill to scratch and add HBM traffic).
 __device__ __attribute__((noinline)) void expect_value(const int32_t* hg, unsigned long long N, double h1, int fit,
                                                       int& status, double& ev, EvShared& S) {
     static_assert(kHistBins == 2 * kBlock, "two histogram bins per thread");
@@ -1414,7 +1415,7 @@ __device__ void merge_sorted_lists(uint32_t L, uint32_t k, TopShared& T, Key key
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_merge(MergeArgs A) {
     __shared__ EvShared S;
     __shared__ TopShared T;
     const uint32_t tid = threadIdx.x;
@@ -1475,7 +1476,7 @@ struct AssembleArgs {
     int32_t* hist;   // may be NULL
 };
 
-__global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_assemble(AssembleArgs A) {
     __shared__ EvShared S;
     __shared__ TopShared T;
     __shared__ int32_t s_hist[kHistBins];
