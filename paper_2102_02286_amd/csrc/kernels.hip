@@ -221,7 +221,7 @@ __device__ __forceinline__ unsigned long long peak_key(float mz, float in) {
 
 __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
     __shared__ unsigned long long s_key[kPrepLdsPeaks];
-    __shared__ uint32_t s_ent[PS_MAX_TOP_PEAKS * (PS_MAX_CHARGE - 1)];
+    __shared__ __align__(16) uint32_t s_ent[PS_MAX_TOP_PEAKS * (PS_MAX_CHARGE - 1)];
     __shared__ uint32_t s_flag, s_imax_bits, s_mult, s_alive;
     __shared__ unsigned long long s_red[kBlock / 64];
     __shared__ uint64_t s_win[2];
@@ -348,13 +348,15 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
             ++valid;
             sumq += ei & 0xFFu;
             const uint32_t bi = ei >> 8;
-            uint32_t m = 0;
-            for (uint32_t j = 0; j < n_ent; ++j) {
-                const uint32_t ej = s_ent[j];
-                if (ej == kEntryInvalid) continue;
-                const uint32_t bj = ej >> 8;
-                m += (bj >= bi && bj - bi <= span);
+            // entries with a bin in [bi, bi + span]: the unsigned difference wraps
+            // for bins below bi; four entries per LDS read
+            auto near = [&](uint32_t ej) { return (uint32_t)(ej != kEntryInvalid && (ej >> 8) - bi <= span); };
+            uint32_t m = 0, j = 0;
+            for (; j + 4u <= n_ent; j += 4u) {
+                const uint4 e = *(const uint4*)&s_ent[j];
+                m += near(e.x) + near(e.y) + near(e.z) + near(e.w);
             }
+            for (; j < n_ent; ++j) m += near(s_ent[j]);
             atomicMax(&s_mult, m);
         }
         const unsigned long long tot = block_sum<unsigned long long>(
