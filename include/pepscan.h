@@ -281,14 +281,15 @@ int ps_index_set_schedule(ps_index* idx, const ps_schedule* schedule);
 int ps_index_get_schedule(const ps_index* idx, ps_schedule* schedule);
 
 /* The tile directory: for every fragment bin and every block of
- * 2^grain_shift peptide ids, the position of the bin's first posting at or
- * after the block (Superstep 3's filter_2 reads a bin's postings inside an id
- * range; the directory turns every tile boundary of that range into one load).
- * grain_shift is 12 unless the directory would exceed 16 GiB; `bytes` is its
- * size.  `dir`, if not NULL, receives a host copy of `bytes` bytes laid out as
- * [n_bins][stride] uint32 postings positions, stride = (n_pep >> grain_shift)
- * + 2 rounded up to a multiple of 4 (the padding repeats the bin's end).  Any
- * pointer may be NULL. */
+ * 2^grain_shift peptide ids, the position inside the bin's list of its first
+ * posting at or after the block (Superstep 3's filter_2 reads a bin's postings
+ * inside an id range; the directory turns every tile boundary of that range
+ * into one load).  Positions are relative to the list's start, so they stay
+ * 32-bit however many postings the index holds.  grain_shift is 12 unless the
+ * directory would exceed 32 GiB; `bytes` is its size.  `dir`, if not NULL,
+ * receives a host copy of `bytes` bytes laid out as [n_bins][stride] uint32
+ * positions, stride = (n_pep >> grain_shift) + 2 rounded up to a multiple of 4
+ * (the padding repeats the list's length).  Any pointer may be NULL. */
 int ps_index_directory(const ps_index* idx, uint32_t* grain_shift, uint64_t* bytes, uint32_t* dir);
 
 void ps_index_free(ps_index* idx);
@@ -478,32 +479,49 @@ typedef struct {
     uint64_t runs;            /* device runs (each packs one or more requests) */
     uint64_t refused;         /* submissions refused with PS_EAGAIN */
     uint64_t max_queue;       /* deepest request queue seen */
-    uint32_t slots;           /* concurrent device runs the pool holds */
+    uint32_t streams;         /* concurrent device runs */
     uint32_t pad;
-    uint64_t slot_bytes;      /* device bytes per slot */
+    uint64_t pool_bytes;      /* device bytes runs are admitted into */
+    uint64_t peak_bytes;      /* most pool bytes reserved at once since the last reset */
+    uint64_t committed_bytes; /* device bytes of the requests queued or running now */
+    uint64_t samples;         /* latencies behind the percentiles */
     double   p50_ms, p99_ms, max_ms, mean_ms;   /* latency from submit to completion */
     double   elapsed_s;       /* first submit to last completion */
 } ps_serve_stats;
 
-/* A search server over an uploaded index.  The device `pool` is divided into
- * as many slots as fit (at most max_slots), each a plan for up to
- * slot_spectra spectra and slot_peaks peaks with its own stream.  A scheduler
- * thread admits queued requests in arrival order: whenever a slot is free it
- * packs waiting requests into one run up to the slot's capacity, so requests
- * that arrive while others run are admitted as slots and memory free up, and
- * runs on different slots overlap on the device.  params->schedule must be
- * PS_SCHED_PERSISTENT.  max_pending bounds the host queue (0 = 2^20). */
+/* A search server over an uploaded index (BASELINE's serving loop; the paper's
+ * analogue is Superstep 3's Buffering: a producer/consumer pipeline over
+ * recycled buffers, and Supplementary Algorithm 5's memory guard).  The device
+ * `pool` (256-byte aligned, owned by the caller, kept alive until
+ * ps_server_free) is an arena: every run reserves exactly the workspace its
+ * batch needs (as ps_workspace_bytes counts it) and gives it back when done.
+ * A scheduler thread admits queued requests in arrival order: whenever one of
+ * max_runs streams (1..64, each non-blocking at the default priority) is free,
+ * it packs waiting requests into one run, up to run_spectra spectra and
+ * run_peaks peaks (a single larger request runs alone), reserves the run's
+ * bytes and enqueues the whole search.  So requests that arrive while others
+ * run are admitted as streams and memory free up, and runs overlap on the
+ * device.  A request that does not fit the free memory waits at the head of
+ * the queue.  Memory guard: a submission is refused with PS_EAGAIN while the
+ * device bytes of the queued and running requests plus its own would exceed
+ * max_committed_bytes (0: the pool size).  params->schedule may be either
+ * schedule.  Errors: PS_EINVAL (bad argument, index not on the device),
+ * PS_ENOMEM (pool too small for a one-spectrum search), PS_EDEVICE. */
 int ps_server_create(ps_index* idx, const ps_device* pool, const ps_search_params* params,
-                     uint64_t slot_spectra, uint64_t slot_peaks, uint32_t max_slots, uint64_t max_pending,
+                     uint64_t run_spectra, uint64_t run_peaks, uint32_t max_runs, uint64_t max_committed_bytes,
                      ps_server** out);
 
-/* Queue a request (host spectra, copied).  PS_EAGAIN when the queue is full,
- * PS_EINVAL for invalid spectra or a request larger than a slot.  Thread-safe. */
+/* Queue a request (host spectra, copied before returning).  Thread-safe.
+ * PS_EAGAIN when the memory guard is closed (retry after requests finish; a
+ * refused request leaves no trace), PS_ENOMEM when the request alone needs
+ * more device bytes than the server holds, PS_EINVAL for invalid or empty
+ * spectra.  *ticket identifies the request for ps_server_wait. */
 int ps_server_submit(ps_server* server, const ps_spectra* spectra, uint64_t* ticket);
 
 /* Block until the request is done; write its results as ps_results does and
- * its latency (submit to completion, ms).  Each ticket is waited for once.
- * Thread-safe. */
+ * its latency (submit to completion, ms).  Thread-safe; each ticket is waited
+ * for by one caller: a second wait on a ticket already claimed, or an unknown
+ * ticket, returns PS_EINVAL. */
 int ps_server_wait(ps_server* server, uint64_t ticket, ps_hit* hits, ps_stat* stats, int32_t* hist,
                    double* latency_ms);
 

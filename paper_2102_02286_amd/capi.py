@@ -18,6 +18,7 @@ PS_OK, PS_EINVAL, PS_ENOMEM, PS_EAGAIN, PS_EDEVICE, PS_EOVERFLOW = 0, 1, 2, 3, 4
 PS_STATUS_OK, PS_STATUS_NO_HITS, PS_STATUS_FEW_POINTS, PS_STATUS_BAD_SLOPE, PS_STATUS_INVALID, \
     PS_STATUS_OVERFLOW = 0, 1, 2, 3, 4, 5
 PS_HIST_BINS = 512
+PS_MAX_PEAKS_IN = 4096
 PS_SCHED_PLAIN, PS_SCHED_PERSISTENT = 0, 1
 PS_FIT_TAIL, PS_FIT_GUMBEL = 0, 1
 PS_INTENSITY_LINEAR, PS_INTENSITY_SQRT = 0, 1
@@ -75,7 +76,8 @@ class ps_tune_trial(C.Structure):
 
 class ps_serve_stats(C.Structure):
     _fields_ = [("completed", C.c_uint64), ("spectra", C.c_uint64), ("runs", C.c_uint64), ("refused", C.c_uint64),
-                ("max_queue", C.c_uint64), ("slots", C.c_uint32), ("pad", C.c_uint32), ("slot_bytes", C.c_uint64),
+                ("max_queue", C.c_uint64), ("streams", C.c_uint32), ("pad", C.c_uint32), ("pool_bytes", C.c_uint64),
+                ("peak_bytes", C.c_uint64), ("committed_bytes", C.c_uint64), ("samples", C.c_uint64),
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double), ("mean_ms", C.c_double),
                 ("elapsed_s", C.c_double)]
 

@@ -13,14 +13,14 @@
 //      every G-th rank;
 //   4. ions: per entry 2(n-1) b/y ions, each posted to the 2T+1 bins of a
 //      merged list (T = 0: one bin).  In chunks of entries the (bin, posting)
-//      pairs are generated in id order and stably sorted by bin.  One chunk:
-//      the sorted postings are the lists and each bin's offset is a binary
-//      search of the sorted bins.  Several chunks: a first pass adds each
-//      chunk's per-bin run lengths, an exclusive scan gives the offsets, and a
-//      second pass scatters every chunk's runs behind each bin's cursor -- a
-//      chunked counting sort, so every list is in id order and the scratch
-//      memory is bounded by the chunk;
-//   5. k_dir: the tile directory, one binary search per (bin, block).
+//      pairs are generated in id order and stably sorted by bin.  A first pass
+//      adds each chunk's per-bin run lengths; the host turns the counts into
+//      list offsets, each list padded to whole 16-byte quads; a second pass
+//      scatters every chunk's runs behind each bin's cursor (a single chunk
+//      stays sorted between the passes) -- a chunked counting sort, so every
+//      list is in id order and the scratch memory is bounded by the chunk;
+//   5. k_dir: the tile directory, one binary search per (bin, block), as
+//      positions inside the bin's list.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -264,7 +264,7 @@ struct ScatterArgs {
     uint64_t m;
     uint32_t* run_start;         // [n_bins] first position of each bin's run in the chunk
     uint32_t* run_end;
-    const uint64_t* bin_off;
+    const uint32_t* bin_q;       // [n_bins] first quad of each bin's list
     unsigned long long* cursor;  // [n_bins] postings of the bin written so far
     uint32_t* post;
 };
@@ -280,7 +280,7 @@ __global__ void k_runs(ScatterArgs A) {
 __global__ void k_scatter(ScatterArgs A) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.m; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t b = A.key[i];
-        A.post[A.bin_off[b] + A.cursor[b] + (i - A.run_start[b])] = A.val[i];
+        A.post[4ull * A.bin_q[b] + A.cursor[b] + (i - A.run_start[b])] = A.val[i];
     }
 }
 
@@ -292,11 +292,9 @@ __global__ void k_advance(ScatterArgs A) {
 }
 
 // Postings of each bin in a sorted chunk: cnt[b] += (first position > b) -
-// (first position >= b), by binary search, for b < n_bins.  With `off` set
-// (one chunk), off[b] = first position >= b for b <= n_bins instead.
-__global__ void k_bin_runs(const uint32_t* key, uint64_t m, uint64_t n_bins, unsigned long long* cnt,
-                           uint64_t* off) {
-    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b <= n_bins;
+// (first position >= b), by binary search, for b < n_bins.
+__global__ void k_bin_runs(const uint32_t* key, uint64_t m, uint64_t n_bins, unsigned long long* cnt) {
+    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < n_bins;
          b += (uint64_t)gridDim.x * blockDim.x) {
         auto first_ge = [&](uint64_t v) {
             uint64_t lo = 0, hi = m;
@@ -306,10 +304,13 @@ __global__ void k_bin_runs(const uint32_t* key, uint64_t m, uint64_t n_bins, uns
             }
             return lo;
         };
-        const uint64_t a = first_ge(b);
-        if (off) off[b] = a;
-        else if (b < n_bins) cnt[b] += first_ge(b + 1) - a;
+        cnt[b] += first_ge(b + 1) - first_ge(b);
     }
+}
+
+__global__ void k_fill_post(uint32_t* p, uint32_t v, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 __global__ void k_zero_u64(unsigned long long* p, uint64_t n) {
@@ -317,17 +318,19 @@ __global__ void k_zero_u64(unsigned long long* p, uint64_t n) {
         p[i] = 0;
 }
 
-// Entry k of bin b: the first posting of b with id >= k << shift.
-__global__ void k_dir(const uint64_t* bin_off, const uint32_t* post, uint64_t n_bins, uint64_t stride,
-                      uint32_t shift, uint32_t* dir) {
+// Entry k of bin b: the position in b's list of its first posting with id >=
+// k << shift.
+__global__ void k_dir(const uint32_t* bin_q, const unsigned long long* bin_cnt, const uint32_t* post, uint64_t n_bins,
+                      uint64_t stride, uint32_t shift, uint32_t* dir) {
     const uint64_t total = n_bins * stride;
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t b = t / stride, k = t - b * stride;
         const uint64_t target = (k << shift) << 1;          // posting = id << 1 | y
-        uint64_t lo = bin_off[b], hi = bin_off[b + 1];
+        const uint32_t* list = post + 4ull * bin_q[b];
+        uint64_t lo = 0, hi = bin_cnt[b];
         while (lo < hi) {
             const uint64_t mid = (lo + hi) >> 1;
-            if ((uint64_t)post[mid] < target) lo = mid + 1; else hi = mid;
+            if ((uint64_t)list[mid] < target) lo = mid + 1; else hi = mid;
         }
         dir[t] = (uint32_t)lo;
     }
@@ -349,7 +352,7 @@ struct Census {
     uint64_t D_all = 0;
     int64_t min_mass = 0, max_mass = 0;
     uint32_t max_len = 0;
-    uint64_t D = 0, n_bins = 0, post_cap = 0, dir_stride = 0, dir_nblk = 0;
+    uint64_t D = 0, n_bins = 0, post_cap = 0, quad_cap = 0, dir_stride = 0, dir_nblk = 0;
     uint32_t dir_shift = 12;
 };
 
@@ -454,6 +457,7 @@ int census(const ps_index* ix, Census& C) {
     uint64_t cap = pairs_all * width;
     if (G > 1) cap = std::min<uint64_t>(cap, C.D * (uint64_t)series * (C.max_len > 0 ? C.max_len - 1 : 0) * width);
     C.post_cap = cap;
+    C.quad_cap = (cap + 3) / 4 + C.n_bins;   // every list padded to whole quads
     C.dir_shift = directory_shift(C.n_bins, C.D);
     C.dir_nblk = (C.D >> C.dir_shift) + 1;
     C.dir_stride = (C.dir_nblk + 1 + 3) & ~3ull;
@@ -469,7 +473,7 @@ struct Scratch {
     uint64_t* key0; uint64_t* key1; uint32_t* idx0; uint32_t* idx1;
     uint32_t* l_prot; uint32_t* l_start; uint8_t* l_len; uint64_t* l_mask;
     uint64_t* pair_cnt; uint64_t* pair_off;
-    unsigned long long* bin_cnt; unsigned long long* cursor; uint32_t* run_start; uint32_t* run_end;
+    unsigned long long* bin_cnt; uint32_t* bin_q; unsigned long long* cursor; uint32_t* run_start; uint32_t* run_end;
     uint32_t* pk0; uint32_t* pk1; uint32_t* pv0; uint32_t* pv1;
     int* bad;
     void* temp; uint64_t temp_bytes;
@@ -504,6 +508,7 @@ Scratch layout_scratch(char* base, const ps_index* ix, const Census& C, uint64_t
     S.pair_cnt = (uint64_t*)take((D + 1) * 8);
     S.pair_off = (uint64_t*)take((D + 1) * 8);
     S.bin_cnt = (unsigned long long*)take((C.n_bins + 1) * 8);
+    S.bin_q = (uint32_t*)take((C.n_bins + 1) * 4);
     S.cursor = (unsigned long long*)take(C.n_bins * 8);
     S.run_start = (uint32_t*)take(C.n_bins * 4);
     S.run_end = (uint32_t*)take(C.n_bins * 4);
@@ -520,7 +525,7 @@ Scratch layout_scratch(char* base, const ps_index* ix, const Census& C, uint64_t
 
 // Workspace of the library sorts and scans at these sizes (no launch).
 uint64_t temp_bytes_for(const Census& C, uint64_t chunk, hipStream_t st, hipError_t* err) {
-    size_t a = 0, b = 0, c = 0, d = 0;
+    size_t a = 0, b = 0, c = 0;
     hipcub::DoubleBuffer<uint64_t> k64(nullptr, nullptr);
     hipcub::DoubleBuffer<uint32_t> v32(nullptr, nullptr);
     hipcub::DoubleBuffer<uint32_t> k32(nullptr, nullptr);
@@ -531,11 +536,8 @@ uint64_t temp_bytes_for(const Census& C, uint64_t chunk, hipStream_t st, hipErro
     if (e == hipSuccess)
         e = hipcub::DeviceScan::ExclusiveSum(nullptr, c, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                                              (int)(std::max<uint64_t>(C.D, 1) + 1), st);
-    if (e == hipSuccess)
-        e = hipcub::DeviceScan::ExclusiveSum(nullptr, d, (const unsigned long long*)nullptr,
-                                             (unsigned long long*)nullptr, (int)(C.n_bins + 1), st);
     *err = e;
-    return std::max(std::max(a, b), std::max(c, d)) + 4096;
+    return std::max(std::max(a, b), c) + 4096;
 }
 
 // Pairs per chunk: the caller's cap (0: the default), at least one entry's
@@ -568,7 +570,7 @@ extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const cha
         const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
         const uint64_t tb = temp_bytes_for(C, chunk, nullptr, &e);
         if (e != hipSuccess) rc = fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e));
-        *index_bytes = index_layout(C.D, C.n_bins, C.post_cap, C.n_bins * C.dir_stride).total;
+        *index_bytes = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride).total;
         *scratch_bytes = layout_scratch(nullptr, ix, C, chunk, tb).total;
     }
     delete ix;
@@ -595,7 +597,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
     const uint64_t tb = temp_bytes_for(C, chunk, st, &e);
     if (e != hipSuccess) return bail(fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e)));
-    const DevLayout lay = index_layout(C.D, C.n_bins, C.post_cap, C.n_bins * C.dir_stride);
+    const DevLayout lay = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride);
     const Scratch need = layout_scratch(nullptr, ix, C, chunk, tb);
     if (!index_block->base || index_block->bytes < lay.total)
         return bail(fail(PS_ENOMEM, "index needs %llu device bytes, block has %llu", (unsigned long long)lay.total,
@@ -614,7 +616,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     M.nterm_mod = mt.nterm_mod;
     for (size_t m = 0; m < ix->mods.size(); ++m) M.delta[m] = ix->mods[m].delta;
     int64_t* mass = (int64_t*)(base + lay.mass);
-    uint64_t* bin_off = (uint64_t*)(base + lay.bin);
+    uint32_t* bin_q = (uint32_t*)(base + lay.bin);
     uint32_t* post = (uint32_t*)(base + lay.post);
     uint32_t* dir = (uint32_t*)(base + lay.dir);
     const uint64_t n_prot = ix->prot_off.size() - 1;
@@ -666,9 +668,6 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     chk(hipStreamSynchronize(st));
     if (e != hipSuccess) return bail(fail(PS_EDEVICE, "index build: %s", hipGetErrorString(e)));
     const uint64_t n_post = poff[C.D];
-    if (n_post >= (1ull << 32))
-        return bail(fail(PS_EOVERFLOW, "index holds %llu postings; this build addresses at most 2^32",
-                         (unsigned long long)n_post));
     if (n_post > C.post_cap)
         return bail(fail(PS_EOVERFLOW, "postings exceed the computed bound (%llu > %llu)",
                          (unsigned long long)n_post, (unsigned long long)C.post_cap));
@@ -695,37 +694,55 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
                                                         (int)bit_length(C.n_bins), st));
         return std::make_pair(keys.Current(), vals.Current());
     };
-    if (n_chunks <= 1) {
+    // pass 1: postings per bin, over every chunk (a single chunk stays sorted for pass 2)
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(C.n_bins + 1)), dim3(256), 0, st, S.bin_cnt, C.n_bins + 1);
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(C.n_bins)), dim3(256), 0, st, S.cursor, C.n_bins);
+    uint64_t m_one = 0;
+    std::pair<uint32_t*, uint32_t*> kv_one{S.pk0, S.pv0};
+    for (size_t c = 0; c < n_chunks && e == hipSuccess; ++c) {
         uint64_t m = 0;
-        const uint32_t* k = S.pk0;
-        const uint32_t* v = S.pv0;
-        if (n_chunks == 1) { auto kv = sorted_chunk(0, m); k = kv.first; v = kv.second; }
-        hipLaunchKernelGGL(k_bin_runs, dim3(grid_for(C.n_bins + 1)), dim3(256), 0, st, k, m, C.n_bins,
-                           (unsigned long long*)nullptr, bin_off);
+        auto kv = sorted_chunk(c, m);
+        if (n_chunks == 1) { kv_one = kv; m_one = m; }
+        hipLaunchKernelGGL(k_bin_runs, dim3(grid_for(C.n_bins)), dim3(256), 0, st, kv.first, m, C.n_bins, S.bin_cnt);
         chk(hipGetLastError());
-        if (m) chk(hipMemcpyAsync(post, v, m * 4, hipMemcpyDeviceToDevice, st));
-    } else {
-        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(C.n_bins + 1)), dim3(256), 0, st, S.bin_cnt, C.n_bins + 1);
-        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(C.n_bins)), dim3(256), 0, st, S.cursor, C.n_bins);
-        for (size_t c = 0; c < n_chunks && e == hipSuccess; ++c) {       // pass 1: postings per bin
-            uint64_t m = 0;
-            auto kv = sorted_chunk(c, m);
-            hipLaunchKernelGGL(k_bin_runs, dim3(grid_for(C.n_bins + 1)), dim3(256), 0, st, kv.first, m, C.n_bins,
-                               S.bin_cnt, (uint64_t*)nullptr);
-            chk(hipGetLastError());
-        }
-        size_t tbytes = S.temp_bytes;
-        chk(hipcub::DeviceScan::ExclusiveSum(S.temp, tbytes, S.bin_cnt, (unsigned long long*)bin_off,
-                                             (int)(C.n_bins + 1), st));
-        for (size_t c = 0; c < n_chunks && e == hipSuccess; ++c) {       // pass 2: scatter
-            uint64_t m = 0;
-            auto kv = sorted_chunk(c, m);
-            ScatterArgs sa{kv.first, kv.second, m, S.run_start, S.run_end, bin_off, S.cursor, post};
-            hipLaunchKernelGGL(k_runs, dim3(grid_for(m)), dim3(256), 0, st, sa);
-            hipLaunchKernelGGL(k_scatter, dim3(grid_for(m)), dim3(256), 0, st, sa);
-            hipLaunchKernelGGL(k_advance, dim3(grid_for(m)), dim3(256), 0, st, sa);
-            chk(hipGetLastError());
-        }
+    }
+    // list offsets on the host: the plain CSR offsets (the index's host view) and
+    // each list's first quad on the device, lists padded to whole quads
+    std::vector<unsigned long long> cnt(C.n_bins);
+    if (C.n_bins) chk(hipMemcpyAsync(cnt.data(), S.bin_cnt, C.n_bins * 8, hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    if (e != hipSuccess) return bail(fail(PS_EDEVICE, "index build: %s", hipGetErrorString(e)));
+    std::vector<uint64_t> csr(C.n_bins + 1);
+    std::vector<uint32_t> bq(C.n_bins + 1);
+    uint64_t quads = 0;
+    for (uint64_t b = 0; b < C.n_bins; ++b) {
+        csr[b] = b ? csr[b - 1] + cnt[b - 1] : 0;
+        if (cnt[b] >= (1ull << 32))
+            return bail(fail(PS_EOVERFLOW, "fragment bin %llu holds 2^32 or more postings", (unsigned long long)b));
+        bq[b] = (uint32_t)quads;
+        quads += (cnt[b] + 3) >> 2;
+        if (quads >= kMaxQuads)
+            return bail(fail(PS_EOVERFLOW, "the postings need more than 2^32 16-byte quads"));
+    }
+    csr[C.n_bins] = C.n_bins ? csr[C.n_bins - 1] + cnt[C.n_bins - 1] : 0;
+    bq[C.n_bins] = (uint32_t)quads;
+    if (csr[C.n_bins] != n_post || quads > C.quad_cap)
+        return bail(fail(PS_EDEVICE, "index build: inconsistent posting counts"));
+    chk(hipMemcpyAsync(bin_q, bq.data(), (C.n_bins + 1) * 4, hipMemcpyHostToDevice, st));
+    if (quads) {
+        hipLaunchKernelGGL(k_fill_post, dim3(grid_for(quads * 4)), dim3(256), 0, st, post, kPostPad, quads * 4);
+        chk(hipGetLastError());
+    }
+    // pass 2: scatter every chunk's runs behind the cursors
+    for (size_t c = 0; c < n_chunks && e == hipSuccess; ++c) {
+        uint64_t m = m_one;
+        auto kv = n_chunks == 1 ? kv_one : sorted_chunk(c, m);
+        if (m == 0) continue;
+        ScatterArgs sa{kv.first, kv.second, m, S.run_start, S.run_end, bin_q, S.cursor, post};
+        hipLaunchKernelGGL(k_runs, dim3(grid_for(m)), dim3(256), 0, st, sa);
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(m)), dim3(256), 0, st, sa);
+        hipLaunchKernelGGL(k_advance, dim3(grid_for(m)), dim3(256), 0, st, sa);
+        chk(hipGetLastError());
     }
     int bad = 0;
     chk(hipMemcpyAsync(&bad, S.bad, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -735,8 +752,8 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     if (bad & 2) return bail(fail(PS_EINVAL, "a fragment ion lies outside the bin range"));
     // 5. directory
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_dir, dim3(grid_for(C.n_bins * C.dir_stride)), dim3(256), 0, st, bin_off, post,
-                           C.n_bins, C.dir_stride, C.dir_shift, dir);
+        hipLaunchKernelGGL(k_dir, dim3(grid_for(C.n_bins * C.dir_stride)), dim3(256), 0, st, bin_q, S.bin_cnt,
+                           post, C.n_bins, C.dir_stride, C.dir_shift, dir);
         chk(hipGetLastError());
     }
     // score tables; host copies of the per-entry arrays and the bin offsets
@@ -746,14 +763,13 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     chk(hipMemcpyAsync(base + lay.ls, ls.data(), ls.size() * 8, hipMemcpyHostToDevice, st));
     try {
         ix->mass.resize(C.D); ix->prot.resize(C.D); ix->start.resize(C.D); ix->len.resize(C.D); ix->mask.resize(C.D);
-        ix->bin_off.resize(C.n_bins + 1);
+        ix->bin_off.swap(csr);
     } catch (...) { return bail(fail(PS_ENOMEM, "out of host memory")); }
     chk(hipMemcpyAsync(ix->mass.data(), mass, C.D * 8, hipMemcpyDeviceToHost, st));
     chk(hipMemcpyAsync(ix->prot.data(), S.l_prot, C.D * 4, hipMemcpyDeviceToHost, st));
     chk(hipMemcpyAsync(ix->start.data(), S.l_start, C.D * 4, hipMemcpyDeviceToHost, st));
     chk(hipMemcpyAsync(ix->len.data(), S.l_len, C.D, hipMemcpyDeviceToHost, st));
     chk(hipMemcpyAsync(ix->mask.data(), S.l_mask, C.D * 8, hipMemcpyDeviceToHost, st));
-    chk(hipMemcpyAsync(ix->bin_off.data(), bin_off, (C.n_bins + 1) * 8, hipMemcpyDeviceToHost, st));
     chk(hipStreamSynchronize(st));
     if (e != hipSuccess) return bail(fail(PS_EDEVICE, "index build: %s", hipGetErrorString(e)));
     ix->n_bins = C.n_bins;
@@ -764,6 +780,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     ix->dir_stride = C.dir_stride;
     ix->device_built = true;
     ix->dev_n_post = n_post;
+    ix->dev_n_quads = quads;
     ix->dev_dir_entries = C.n_bins * C.dir_stride;
     bind_device_index(ix, base, lay);
     if (ix->sched.tile < (1u << ix->dir_shift)) ix->sched.tile = 1u << ix->dir_shift;

@@ -304,9 +304,6 @@ int index_build_host(ps_index* ix) {
             const uint64_t b = std::min<uint64_t>(nbins, bn + mt + 1);
             off2[bn + 1] = off2[bn] + (ix->bin_off[b] - ix->bin_off[a]);
         }
-        if (off2[nbins] >= (1ull << 32))
-            return fail(PS_EOVERFLOW, "merged lists hold %llu postings; this build addresses at most 2^32",
-                        (unsigned long long)off2[nbins]);
         std::vector<uint32_t> post2(off2[nbins]);
         parallel_for(nbins, T, [&](unsigned, uint64_t ba, uint64_t bb) {
             std::vector<uint32_t> tmp;
@@ -331,9 +328,16 @@ int index_build_host(ps_index* ix) {
     }
 
     // 5. tile directory: for every bin and every block of 2^dir_shift ids, the
-    // first posting at or after the block start.  A scan tile is a whole number
-    // of blocks, so every posting run's tile boundaries are direct lookups.  The
-    // grain is 4096 ids unless the directory would pass kDirBudget bytes.
+    // position in the bin's list of its first posting at or after the block
+    // start.  A scan tile is a whole number of blocks, so every posting run's
+    // tile boundaries are direct lookups.  The grain is 4096 ids unless the
+    // directory would pass kDirBudget bytes.
+    for (uint64_t bn = 0; bn < nbins; ++bn)
+        if (ix->bin_off[bn + 1] - ix->bin_off[bn] >= (1ull << 32))
+            return fail(PS_EOVERFLOW, "fragment bin %llu holds 2^32 or more postings", (unsigned long long)bn);
+    if (padded_quads(ix) >= kMaxQuads)
+        return fail(PS_EOVERFLOW, "the postings need %llu 16-byte quads; at most 2^32 are addressable",
+                    (unsigned long long)padded_quads(ix));
     ix->dir_shift = directory_shift(nbins, D);
     // Rows are padded to a multiple of four entries (16 bytes), so a row can be
     // read four tile boundaries at a time; padding repeats the bin's end.
@@ -344,12 +348,13 @@ int index_build_host(ps_index* ix) {
     parallel_for(nbins, T, [&](unsigned, uint64_t ba, uint64_t bb) {
         for (uint64_t bn = ba; bn < bb; ++bn) {
             uint32_t* d = ix->dir.data() + bn * stride;
-            uint64_t i = ix->bin_off[bn];
+            const uint64_t b0 = ix->bin_off[bn];
+            uint64_t i = b0;
             const uint64_t e = ix->bin_off[bn + 1];
             for (uint64_t k = 0; k < stride; ++k) {
                 const uint64_t first_id = k << ix->dir_shift;
                 while (i < e && (uint64_t)(ix->post[i] >> 1) < first_id) ++i;
-                d[k] = (uint32_t)i;
+                d[k] = (uint32_t)(i - b0);
             }
         }
     });
@@ -370,8 +375,15 @@ int64_t lightest_residue(const ps_index* ix, const ModTable& mt) {
     return minres;
 }
 
+uint64_t padded_quads(const ps_index* ix) {
+    if (ix->device_built) return ix->dev_n_quads;
+    uint64_t q = 0;
+    for (uint64_t b = 0; b + 1 < ix->bin_off.size(); ++b) q += (ix->bin_off[b + 1] - ix->bin_off[b] + 3) >> 2;
+    return q;
+}
+
 uint32_t directory_shift(uint64_t nbins, uint64_t D) {
-    constexpr uint64_t kDirBudget = 16ull << 30;
+    constexpr uint64_t kDirBudget = 32ull << 30;
     uint32_t sh = 12;
     while (sh < 16 && nbins * ((D >> sh) + 6) * 4 > kDirBudget) ++sh;
     return sh;
@@ -379,12 +391,12 @@ uint32_t directory_shift(uint64_t nbins, uint64_t D) {
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_post, uint64_t n_dir) {
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir) {
     DevLayout L;
     uint64_t o = 0;
     L.mass = o; o = align256(o + n_pep * sizeof(int64_t));
-    L.bin = o; o = align256(o + (n_bins + 1) * sizeof(uint64_t));
-    L.post = o; o = align256(o + n_post * sizeof(uint32_t) + 16);   // the scan reads whole aligned quads
+    L.bin = o; o = align256(o + (n_bins + 1) * sizeof(uint32_t));
+    L.post = o; o = align256(o + n_quads * 16 + 16);
     L.lf = o; o = align256(o + kLfSize * sizeof(double));
     L.ls = o; o = align256(o + kLsSize * sizeof(double));
     L.dir = o; o = align256(o + n_dir * sizeof(uint32_t));
@@ -393,13 +405,13 @@ DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_post, uint64_
 }
 
 static DevLayout index_device_layout(const ps_index* ix) {
-    return index_layout(ix->mass.size(), ix->n_bins, n_postings(ix), dir_entries(ix));
+    return index_layout(ix->mass.size(), ix->n_bins, padded_quads(ix), dir_entries(ix));
 }
 
 void bind_device_index(ps_index* ix, char* base, const DevLayout& lay) {
     DevIndex& d = ix->dev;
     d.mass = (const int64_t*)(base + lay.mass);
-    d.bin_off = (const uint64_t*)(base + lay.bin);
+    d.bin_q = (const uint32_t*)(base + lay.bin);
     d.post = (const uint32_t*)(base + lay.post);
     d.lf = (const double*)(base + lay.lf);
     d.ls = (const double*)(base + lay.ls);
@@ -534,14 +546,76 @@ extern "C" int ps_index_device_bytes(const ps_index* ix, uint64_t* bytes) {
     return PS_OK;
 }
 
+// Quad index of every bin's padded list, and the quad count last.
+static std::vector<uint32_t> bin_quads(const ps_index* ix) {
+    std::vector<uint32_t> q(ix->n_bins + 1);
+    uint64_t run = 0;
+    for (uint64_t b = 0; b < ix->n_bins; ++b) {
+        q[b] = (uint32_t)run;
+        run += (ix->bin_off[b + 1] - ix->bin_off[b] + 3) >> 2;
+    }
+    q[ix->n_bins] = (uint32_t)run;
+    return q;
+}
+
+// Host postings into device memory with every bin's list padded to whole quads
+// (filler kPostPad), through two pinned staging buffers so that filling one
+// overlaps the copy of the other.
+static hipError_t upload_padded_postings(const ps_index* ix, uint32_t* dst, hipStream_t st) {
+    constexpr uint64_t kStage = 16ull << 20;             // entries per staging buffer (64 MB)
+    uint32_t* buf[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    for (int i = 0; i < 2; ++i) {
+        chk(hipHostMalloc((void**)&buf[i], kStage * 4, hipHostMallocDefault));
+        chk(hipEventCreateWithFlags(&done[i], hipEventDisableTiming));
+    }
+    int cur = 0;
+    uint64_t fill = 0, written = 0;
+    bool pending[2] = {false, false};
+    auto flush = [&]() {
+        if (e != hipSuccess || fill == 0) return;
+        chk(hipMemcpyAsync(dst + written, buf[cur], fill * 4, hipMemcpyHostToDevice, st));
+        chk(hipEventRecord(done[cur], st));
+        pending[cur] = true;
+        written += fill;
+        fill = 0;
+        cur ^= 1;
+        if (pending[cur]) { chk(hipEventSynchronize(done[cur])); pending[cur] = false; }
+    };
+    auto append = [&](const uint32_t* src, uint64_t n, uint32_t value) {
+        while (n && e == hipSuccess) {
+            const uint64_t m = std::min(n, kStage - fill);
+            if (src) { memcpy(buf[cur] + fill, src, m * 4); src += m; }
+            else std::fill(buf[cur] + fill, buf[cur] + fill + m, value);
+            fill += m;
+            n -= m;
+            if (fill == kStage) flush();
+        }
+    };
+    for (uint64_t b = 0; b < ix->n_bins && e == hipSuccess; ++b) {
+        const uint64_t len = ix->bin_off[b + 1] - ix->bin_off[b];
+        append(ix->post.data() + ix->bin_off[b], len, 0);
+        append(nullptr, ((len + 3) & ~3ull) - len, kPostPad);
+    }
+    flush();
+    for (int i = 0; i < 2; ++i) {
+        if (pending[i]) chk(hipEventSynchronize(done[i]));
+        if (done[i]) (void)hipEventDestroy(done[i]);
+        if (buf[i]) (void)hipHostFree(buf[i]);
+    }
+    return e;
+}
+
 extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     if (!ix || !dev) return fail(PS_EINVAL, "NULL argument");
     if (ix->device_built) return fail(PS_EINVAL, "this index was built on the device and is already there");
     int rc = require_device();
     if (rc != PS_OK) return rc;
-    if (ix->post.size() >= (1ull << 32))
-        return fail(PS_EOVERFLOW, "index holds %llu postings; this build addresses at most 2^32",
-                    (unsigned long long)ix->post.size());
+    if (padded_quads(ix) >= kMaxQuads)
+        return fail(PS_EOVERFLOW, "index needs %llu posting quads; at most 2^32 are addressable",
+                    (unsigned long long)padded_quads(ix));
     const DevLayout lay = index_device_layout(ix);
     const uint64_t need = lay.total;
     if (!dev->base || dev->bytes < need)
@@ -550,6 +624,7 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     if (((uintptr_t)dev->base & 255u) != 0) return fail(PS_EINVAL, "device block must be 256-byte aligned");
     std::vector<double> lf, ls;
     score_tables(lf, ls);
+    const std::vector<uint32_t> bq = bin_quads(ix);
     char* base = (char*)dev->base;
     hipStream_t st = (hipStream_t)dev->stream;
     hipError_t e = hipSuccess;
@@ -557,11 +632,11 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
         if (e == hipSuccess && n) e = hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, st);
     };
     cp(lay.mass, ix->mass.data(), ix->mass.size() * sizeof(int64_t));
-    cp(lay.bin, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
-    cp(lay.post, ix->post.data(), ix->post.size() * sizeof(uint32_t));
+    cp(lay.bin, bq.data(), bq.size() * sizeof(uint32_t));
     cp(lay.lf, lf.data(), lf.size() * sizeof(double));
     cp(lay.ls, ls.data(), ls.size() * sizeof(double));
     cp(lay.dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = upload_padded_postings(ix, (uint32_t*)(base + lay.post), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
     bind_device_index(ix, base, lay);
@@ -649,8 +724,17 @@ extern "C" int ps_index_host_arrays(const ps_index* ix, uint64_t* bin_off, uint3
     if (!ix) return fail(PS_EINVAL, "NULL index");
     if (bin_off) memcpy(bin_off, ix->bin_off.data(), ix->bin_off.size() * sizeof(uint64_t));
     if (postings && ix->device_built) {
-        hipError_t e = hipMemcpy(postings, ix->dev.post, ix->dev_n_post * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        // the device lists are padded to whole quads: copy them, then close the gaps
+        std::vector<uint32_t> padded;
+        try { padded.resize(ix->dev_n_quads * 4); } catch (...) { return fail(PS_ENOMEM, "out of host memory"); }
+        hipError_t e = hipMemcpy(padded.data(), ix->dev.post, padded.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return fail(PS_EDEVICE, "postings to host: %s", hipGetErrorString(e));
+        uint64_t q = 0;
+        for (uint64_t b = 0; b < ix->n_bins; ++b) {
+            const uint64_t len = ix->bin_off[b + 1] - ix->bin_off[b];
+            memcpy(postings + ix->bin_off[b], padded.data() + 4 * q, len * sizeof(uint32_t));
+            q += (len + 3) >> 2;
+        }
     } else if (postings) {
         memcpy(postings, ix->post.data(), ix->post.size() * sizeof(uint32_t));
     }

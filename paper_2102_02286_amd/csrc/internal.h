@@ -43,6 +43,9 @@ constexpr int kHistBins = PS_HIST_BINS;
 constexpr uint32_t kLfSize = 65536;         // log10(n!) table, n < 65536
 constexpr uint32_t kLsSize = 1u << 20;      // log10(s) table, s < 2^20
 constexpr uint32_t kEntryInvalid = 0xFFFFFFFFu;
+constexpr uint32_t kPostPad = 0xFFFFFFFFu;  // filler after a list up to its quad boundary
+// Postings are addressed as 16-byte quads with 32-bit indices: at most 2^32 quads.
+constexpr uint64_t kMaxQuads = 1ull << 32;
 constexpr int kBlock = 256;                 // threads per workgroup for every kernel
 constexpr size_t kMaxLds = 158 * 1024;      // dynamic LDS per workgroup (160 KB on gfx950 less static use)
 
@@ -56,11 +59,14 @@ enum : uint32_t {
 // Device view of an uploaded index.
 struct DevIndex {
     const int64_t* mass;       // [n_pep], ascending
-    const uint64_t* bin_off;   // [n_bins + 1]
-    const uint32_t* post;      // [n_post], value = id << 1 | is_y, sorted within a bin
+    const uint32_t* bin_q;     // [n_bins + 1] bin b's list starts at posting 4 * bin_q[b] (lists are
+                               // padded to whole 16-byte quads; the last entry is the quad count)
+    const uint32_t* post;      // [4 * bin_q[n_bins]], value = id << 1 | is_y, sorted within a bin;
+                               // padding entries are kPostPad and lie beyond every list's end
     const double* lf;          // [kLfSize]  lf[n] = sum_{k=2..n} log10 k
     const double* ls;          // [kLsSize]  ls[s] = log10 s
-    const uint32_t* dir;       // [n_bins * dir_stride] first posting of a bin at or after each id block
+    const uint32_t* dir;       // [n_bins * dir_stride] first posting of a bin at or after each id
+                               // block, as a position inside the bin's own list
     uint32_t dir_shift;        // id block = 1 << dir_shift ids (the tile grain)
     uint32_t dir_nblk;
     uint32_t dir_stride;       // row length, a multiple of 4 (rows are 16-byte aligned)

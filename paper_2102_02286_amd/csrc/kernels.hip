@@ -259,7 +259,8 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
             float m = A.sp.mz[p0 + i], v = A.sp.inten[p0 + i];
             if (np <= kPrepLdsPeaks) s_key[i] = peak_key(m, v);
             if (!(m > 0.0f) || !(m <= 3.0e38f) || !(v >= 0.0f) || !(v <= 3.0e38f)) atomicOr(&s_flag, 1u);
-            else atomicMax(&s_imax_bits, __float_as_uint(v));   // ordered like floats for v >= 0
+            // ordered like floats for v >= 0; the sign bit is cleared so that -0 counts as +0
+            else atomicMax(&s_imax_bits, __float_as_uint(v) & 0x7FFFFFFFu);
         }
         __syncthreads();
         // the peaks: staged in LDS, or read where they are when there are more
@@ -437,15 +438,16 @@ struct ScanShared {
 };
 
 // What the lookup pass finds for one fragment-bin probe with postings in the
-// item: its bin, its posting run [s0, s1) inside the item, the peak's integer
-// intensity and the ends of the run's first two tiles.
+// item: its bin, the first quad of the bin's list, its posting run [s0, s1)
+// inside the item, the peak's integer intensity and the ends of the run's first
+// two tiles (positions inside the bin's list).
 struct SlotInit {
-    uint32_t bin, s0, s1, q, e0, e1;
+    uint32_t bin, qb, s0, s1, q, e0, e1;
 };
 
 // A slot with postings in the current tile, by rank among such slots.  Its run
 // [cur, end) is read in aligned quads of postings: flat quad position f of its
-// range reads post[base + 4 f .. base + 4 f + 3].  qx = q (its peak's
+// range reads quad base + f of the posting array.  qx = q (its peak's
 // intensity) | lead << 8 (postings before cur in its first quad) | (tail - 1)
 // << 10 (postings of the run in its last quad, 1..4).
 struct SegBase {
@@ -454,8 +456,8 @@ struct SegBase {
 
 // LDS layout (dynamic):
 //   counters (the SlotInit array before the first tile) | SegBase[seg_cap] |
-//   range starts [seg_cap] | map bits [kMapWords] (u64) | map ranks [kMapCap / 64] |
-//   candidate counters | histogram | candidate positions
+//   map bits [kMapWords] (u64) | range starts [seg_cap] | list quads [seg_cap] |
+//   map ranks [kMapCap / 64] | candidate counters | histogram | candidate positions
 //
 // The map of a chunk of kMapCap flat positions: bit b of mbits[R] is set when
 // a slot's range starts at position 64 R + b, and mrank[R] is the rank of the
@@ -466,6 +468,7 @@ struct ScanLds {
     SlotInit* init;
     SegBase* sbase;
     uint32_t* sstart;
+    uint32_t* sqb;        // [seg_cap] first quad of each slot's bin list, by slot
     unsigned long long* mbits;
     uint32_t* mrank;
     C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter, kWaveCand per wavefront
@@ -480,6 +483,7 @@ struct ScanLds {
         sbase = (SegBase*)(base + o); o += (size_t)segcap * sizeof(SegBase);
         mbits = (unsigned long long*)(base + o); o += (size_t)kMapWords * 8;
         sstart = (uint32_t*)(base + o); o += (size_t)segcap * 4;
+        sqb = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         mrank = (uint32_t*)(base + o); o += (size_t)(kMapCap / 64) * 4;
         o = (o + 15) & ~(size_t)15;
         cand_cnt = (C*)(base + o); o += (size_t)kCandCap * sizeof(C);
@@ -492,7 +496,7 @@ size_t scan_lds_bytes(const KParams& kp, bool wide) {
     const size_t csz = wide ? 8 : 4;
     const size_t head = std::max((size_t)kp.tile * csz, (size_t)kp.seg_cap * sizeof(SlotInit));
     size_t o = (head + 15) & ~(size_t)15;
-    o += (size_t)kp.seg_cap * (sizeof(SegBase) + 4) + (size_t)kMapWords * 8 + (size_t)(kMapCap / 64) * 4;
+    o += (size_t)kp.seg_cap * (sizeof(SegBase) + 8) + (size_t)kMapWords * 8 + (size_t)(kMapCap / 64) * 4;
     o = (o + 15) & ~(size_t)15;
     o += (size_t)kCandCap * csz;
     o += (size_t)kHistBins * 4;
@@ -645,7 +649,7 @@ __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C
         const unsigned long long after = L.mbits[R + 1];
         const uint32_t k = L.mrank[R] + (uint32_t)__popcll(bits & below);
         const SegBase sb = L.sbase[valid ? k : 0u];
-        g.p[r] = valid ? *(const uint4*)(ix.post + (sb.base + 4u * f)) : make_uint4(0u, 0u, 0u, 0u);
+        g.p[r] = valid ? ((const uint4*)ix.post)[sb.base + f] : make_uint4(0u, 0u, 0u, 0u);
         const bool first = (bits >> lane) & 1ull;
         const bool last = (lane < 63u ? (bits >> (lane + 1u)) : after) & 1ull;
         const uint32_t lead = first ? (sb.qx >> 8) & 3u : 0u;
@@ -728,13 +732,16 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         ++lookups;
         const uint32_t* row = ix.dir + (uint64_t)bin * stride;
         const uint32_t ka = ida >> gsh, kb = idb >> gsh;
-        const uint32_t s0 = (ida & gmask) ? lower_bound_u32(ix.post, row[ka], row[ka + 1], ida << 1) : row[ka];
-        const uint32_t s1 = (idb & gmask) ? lower_bound_u32(ix.post, row[kb], row[kb + 1], idb << 1) : row[kb];
+        const uint32_t qb = ix.bin_q[bin];
+        const uint32_t* list = ix.post + 4ull * qb;
+        const uint32_t s0 = (ida & gmask) ? lower_bound_u32(list, row[ka], row[ka + 1], ida << 1) : row[ka];
+        const uint32_t s1 = (idb & gmask) ? lower_bound_u32(list, row[kb], row[kb + 1], idb << 1) : row[kb];
         if (s1 <= s0) continue;
         postings += s1 - s0;
         const uint32_t slot = atomicAdd(&sh.nact, 1u);
         SlotInit si;
         si.bin = (uint32_t)bin;
+        si.qb = qb;
         si.s0 = s0;
         si.s1 = s1;
         si.q = e & 0xFFu;
@@ -764,6 +771,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         o_quad[u] = make_uint4(0u, 0u, 0u, 0u);
         if (u < us && j < nact) {
             const SlotInit si = L.init[j];
+            L.sqb[j] = si.qb;
             o_bq[u] = si.bin | (si.q << 24); o_s1[u] = si.s1;
             o_cur[u] = si.s0; o_end[u] = si.e0; o_nxt[u] = si.e1;
             if (quad0) o_quad[u] = quad_at(si.bin, (t0 + 3) * m);
@@ -812,9 +820,9 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         for (uint32_t u = 0; u < U; ++u) {
             const uint32_t n = quads(o_cur[u], o_end[u]);
             if (n) {
-                const uint32_t a = o_cur[u] & ~3u;      // the run's first aligned quad
+                const uint32_t a = o_cur[u] & ~3u;      // the run's first aligned quad (lists start on quads)
                 SegBase sb;
-                sb.base = a - 4u * run;
+                sb.base = L.sqb[tid * us + u] + (a >> 2) - run;   // modulo 2^32: base + f is the quad
                 sb.qx = (o_bq[u] >> 24) | (o_cur[u] & 3u) << 8 | (o_end[u] - a - 4u * (n - 1u) - 1u) << 10;
                 L.sbase[rank] = sb;
                 L.sstart[rank] = run;

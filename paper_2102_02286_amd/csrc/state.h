@@ -43,13 +43,15 @@ struct ps_index {
     std::vector<uint32_t> prot, start;
     std::vector<uint8_t> len;
     std::vector<uint64_t> mask;
-    // CSR fragment-ion index
+    // CSR fragment-ion index (host form: lists back to back; on the device each
+    // list is padded to whole 16-byte quads)
     uint64_t n_bins = 0;
     std::vector<uint64_t> bin_off;
     std::vector<uint32_t> post;
     uint32_t max_len_seen = 0;
     int64_t min_residue = 0;
-    // tile directory: dir[bin * dir_stride + k] = first posting of `bin` with id >= k << dir_shift
+    // tile directory: dir[bin * dir_stride + k] = position inside bin's list of its first posting
+    // with id >= k << dir_shift
     uint32_t dir_shift = 12;
     uint64_t dir_nblk = 0;       // blocks: entries 0..dir_nblk are meaningful
     uint64_t dir_stride = 0;     // row length, dir_nblk + 1 rounded up to a multiple of 4
@@ -61,6 +63,7 @@ struct ps_index {
     // built on the device: postings and directory exist only there
     bool device_built = false;
     uint64_t dev_n_post = 0, dev_dir_entries = 0;
+    uint64_t dev_n_quads = 0;    // padded postings on the device / 4
 };
 
 namespace ps {
@@ -70,12 +73,15 @@ int index_build_host(ps_index* ix);
 
 inline uint64_t n_postings(const ps_index* ix) { return ix->device_built ? ix->dev_n_post : ix->post.size(); }
 inline uint64_t dir_entries(const ps_index* ix) { return ix->device_built ? ix->dev_dir_entries : ix->dir.size(); }
+// Quads of the device postings: every bin's list padded to a multiple of four.
+uint64_t padded_quads(const ps_index* ix);
 
-// Device layout of an index block: [mass][bin_off][post][lf][ls][dir], each 256-byte aligned.
+// Device layout of an index block: [mass][bin_q][post][lf][ls][dir], each 256-byte aligned;
+// n_quads is the padded postings / 4.
 struct DevLayout {
     uint64_t mass, bin, post, lf, ls, dir, total;
 };
-DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_post, uint64_t n_dir);
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir);
 // Point ix->dev at an index block laid out by `lay` and mark the index on the device.
 void bind_device_index(ps_index* ix, char* base, const DevLayout& lay);
 // Modification lookup: which mod (if any) sits on each residue letter; the N-terminal mod.

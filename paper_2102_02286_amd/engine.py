@@ -466,15 +466,22 @@ class Plan:
 class Server:
     """Continuous-batching server over a resident index (see ps_server_create)."""
 
-    def __init__(self, index: HostIndex, params: capi.ps_search_params, slot_spectra: int, slot_peaks: int,
-                 pool_bytes: int, max_slots: int = 8, max_pending: int = 0, device: str = "cuda:0"):
+    def __init__(self, index: HostIndex, params: capi.ps_search_params, pool_bytes: int, run_spectra: int = 4096,
+                 run_peaks: int | None = None, max_runs: int = 4, max_committed_bytes: int = 0,
+                 device: str = "cuda:0"):
+        """pool_bytes of device memory are the arena runs reserve their workspace
+        from; queued requests are packed into runs of up to run_spectra spectra
+        and run_peaks peaks; max_runs runs overlap on their own streams; a
+        submission is refused (PS_EAGAIN) while queued plus running requests
+        would need more than max_committed_bytes (0: pool_bytes)."""
         torch = _torch()
         self.index, self.params = index, params
         self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
         dev = capi.ps_device(self.pool.data_ptr(), pool_bytes, None)
         h = C.c_void_p()
-        check(capi.ps_server_create(index.handle, C.byref(dev), C.byref(params), slot_spectra, slot_peaks,
-                                    max_slots, max_pending, C.byref(h)), "ps_server_create")
+        run_peaks = run_peaks if run_peaks is not None else run_spectra * capi.PS_MAX_PEAKS_IN
+        check(capi.ps_server_create(index.handle, C.byref(dev), C.byref(params), run_spectra, run_peaks,
+                                    max_runs, max_committed_bytes, C.byref(h)), "ps_server_create")
         self.handle = h
 
     def close(self):

@@ -162,8 +162,9 @@ def test_schedule_validation_and_tile_directory():
 
 
 def test_tile_directory_matches_postings():
-    """dir[bin][k] is the first posting of the bin whose id is >= k * 4096
-    (rows padded to a multiple of four entries, the padding repeating the end)."""
+    """dir[bin][k] is the position, inside the bin's own list, of the first
+    posting whose id is >= k * 4096 (rows padded to a multiple of four
+    entries, the padding repeating the list's length)."""
     prot = synth.make_proteome(400, seed=6)
     h = engine.HostIndex(prot.residues, prot.offsets, 2, 7, 30, engine.mods_from_synth([synth.OXIDATION]), 2)
     n_pep, _, n_bins = h.shape()
@@ -176,7 +177,7 @@ def test_tile_directory_matches_postings():
     rng = np.random.default_rng(1)
     for bn in list(rng.integers(0, n_bins, 300)) + [int(np.argmax(np.diff(off.astype(np.int64))))]:
         ids = post[off[bn]:off[bn + 1]] >> 1
-        want = off[bn] + np.searchsorted(ids, np.arange(stride) * 4096, side="left")
+        want = np.searchsorted(ids, np.arange(stride) * 4096, side="left")
         assert np.array_equal(d[bn].astype(np.uint64), want.astype(np.uint64)), bn
 
 
@@ -190,8 +191,9 @@ def test_server_and_plan_need_an_uploaded_index():
     assert rc in (capi.PS_EDEVICE, capi.PS_EINVAL) and not out.value
     rc = capi.ps_server_create(h.handle, C.byref(dev), C.byref(prm), 10, 100, 2, 0, C.byref(out))
     assert rc in (capi.PS_EDEVICE, capi.PS_EINVAL, capi.PS_ENOMEM) and not out.value
-    plain = engine.search_params(False, 1000, 1, 50, max_charge=3)
-    assert capi.ps_server_create(h.handle, C.byref(dev), C.byref(plain), 10, 100, 2, 0, C.byref(out)) == capi.PS_EINVAL
+    # argument checks come before the device check
+    assert capi.ps_server_create(h.handle, C.byref(dev), C.byref(prm), 10, 100, 0, 0, C.byref(out)) == capi.PS_EINVAL
+    assert capi.ps_server_create(h.handle, C.byref(dev), C.byref(prm), 0, 100, 2, 0, C.byref(out)) == capi.PS_EINVAL
 
 
 @pytest.mark.parametrize("T", [1, 2])
@@ -214,7 +216,7 @@ def test_merged_lists_are_neighbour_unions(T):
     d = merged.directory_array()
     for bn in range(0, nb, 97):
         ids = pm[om[bn]:om[bn + 1]] >> 1
-        assert np.array_equal(d[bn], om[bn] + np.searchsorted(ids, np.arange(d.shape[1]) * 4096).astype(np.uint64))
+        assert np.array_equal(d[bn], np.searchsorted(ids, np.arange(d.shape[1]) * 4096))
     need = C.c_uint64()
     wrong = engine.search_params(False, 1000, T + 1, 100, max_charge=3)
     assert capi.ps_workspace_bytes(merged.handle, 10, 100, C.byref(wrong), C.byref(need)) == capi.PS_EINVAL

@@ -127,3 +127,30 @@ def test_device_build_full_medium_database():
     host, dev = _both(prot, w.missed, w.min_len, w.max_len, w.mods, w.max_mods, merge_tol=w.frag_tol_bins)
     assert len(dev) == 3486494
     _assert_same_index(host, dev)
+
+
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
+def test_device_built_index_search_matches_oracle(schedule):
+    """A search on the index built on the GPU compared with the oracle
+    directly (not through the host build): the oracle digests and scores every
+    window candidate itself.  Merged lists, two modification types, the
+    chunked counting sort forced by a small chunk."""
+    import oracle
+    from tests.test_gpu_parity import assert_parity
+    w = synth.workload("medium")
+    prot = synth.make_proteome(1500, seed=21)
+    mods = [synth.OXIDATION, synth.PHOSPHO]
+    sp = w.spectra(prot, n=80, seed=17)
+    _say(f"device-built index vs the oracle, schedule {schedule}")
+    dev = engine.HostIndex.build_on_device(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
+                                           engine.mods_from_synth(mods), 2, merge_tol=w.frag_tol_bins,
+                                           chunk_pairs=1 << 22)
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, oracle.mods_from_synth(mods), 2)
+    assert len(db) == len(dev)
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3, schedule=schedule)
+    res = engine.search(dev, sp, prm)
+    oh, ost, og = db.search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared)
+    assert_parity(res, oh, ost, og)
+    assert res.postings == int(ost["pairs_total"].sum())
+    assert (ost["status"] == 0).sum() > 30

@@ -545,3 +545,104 @@ def test_other_ion_series_parity(types, T):
         res = engine.search(ix, sp, prm)
         assert_parity(res, oh, ost, og)
         assert res.postings == int(ost["pairs_total"].sum())
+
+
+def test_negative_zero_intensities_parity(small_open):
+    """-0.0 is a valid intensity equal to 0: it must neither become the most
+    intense peak nor change q, the noise cut or the top-B order."""
+    w, prot, sp, ix, db, _ = small_open
+    base = sp.subset(np.arange(0, 24))
+    inten = base.intensity.copy()
+    inten[::3] = -0.0
+    inten[1::7] = 0.0
+    sp0 = synth.Spectra(base.peak_off, base.mz, inten, base.precursor_mz, base.charge)
+    assert np.signbit(sp0.intensity).sum() > 0
+    for noise in (0, 200):
+        _say(f"-0.0 intensities, noise {noise}")
+        prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                                   max_charge=3, noise_permille=noise)
+        res = engine.search(ix, sp0, prm)
+        oh, ost, og = db.search(sp0, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                                noise_permille=noise)
+        assert_parity(res, oh, ost, og)
+        # and the same as writing +0.0
+        pos = synth.Spectra(base.peak_off, base.mz, np.abs(inten), base.precursor_mz, base.charge)
+        rp = engine.search(ix, pos, prm)
+        assert rp.hits.tobytes() == res.hits.tobytes() and rp.stats.tobytes() == res.stats.tobytes()
+
+
+def test_top_hit_in_the_open_histogram_bin_parity():
+    """A 40-residue peptide matched on every b and y ion scores past 51.1: the
+    hit lands in the open bin 511 and the tail fit stops at bin 510, on the GPU
+    as in the oracle."""
+    from tests import bruteforce as bf
+    pep = "GASPVTCLINDQEMHFYWGASPVTCLINDQEMHFYWGAGK"
+    rng = np.random.default_rng(51)
+    filler = "".join(rng.choice(list("GASPVTLINDQEMHFYWKR"), 3000))
+    proteins = [pep + "R" + filler[:1500], filler[1500:]]
+    res_arr = np.frombuffer("".join(proteins).encode(), dtype=np.uint8)
+    off = np.zeros(len(proteins) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in proteins])
+    db = oracle.Database(res_arr, off, 1, 4, 45, [], 0)
+    pid = [i for i in range(len(db)) if db.get(i)[1:4] == (0, 0, 40)][0]
+    b, y = oracle.ions(db.residue_masses(pid))
+    peaks = [(float(m) * 1e-6, 10.0) for m in np.concatenate([b, y])]
+    peaks += [(float(rng.uniform(100, 2000)), float(rng.lognormal())) for _ in range(40)]
+    sp1 = _mk([peaks, peaks[::2]], [(db.get(pid)[0] * 1e-6 + 2 * bf.PROTON_UDA * 1e-6) / 2] * 2, [2, 2])
+    for T in (0, 1):
+        ix = engine.HostIndex(res_arr, off, 1, 4, 45, [], 0, merge_tol=T).upload()
+        for schedule in (capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT):
+            for fit in (capi.PS_FIT_TAIL, capi.PS_FIT_GUMBEL):
+                _say(f"open bin: merge {T} schedule {schedule} fit {fit}")
+                prm = engine.search_params(False, 10**12, T, 200, 5, 1, max_charge=2, schedule=schedule, fit=fit)
+                res = engine.search(ix, sp1, prm)
+                oh, ost, og = db.search(sp1, False, 10**12, T, 200, 5, 1, fit=fit)
+                assert oh["hyperscore"][0, 0] > 51.1 and og[0, 511] >= 1
+                assert_parity(res, oh, ost, og)
+
+
+def test_counter_bound_overflow_is_reported():
+    """256 copies of one peak at precursor charge 8 (seven fragment charges,
+    so every charge's 256 entries share a bin) on an index of all six ion
+    series: the worst-case shared pairs (1792 entries x 3 series per terminus)
+    times 200 pass the 2^20 entries of the log10 S table, so the spectrum is
+    reported as PS_STATUS_OVERFLOW with no hits (never a saturated count) and
+    ps_results returns PS_EOVERFLOW.  The other spectra of the batch are
+    unaffected."""
+    w = synth.workload("medium")
+    prot = synth.make_proteome(300, seed=4)
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, [], 0, ion_types=63).upload()
+    db = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, [], 0)
+    normal = w.spectra(prot, n=6, seed=12)
+    crafted = [[(500.0, 7.0)] * 256]
+    lists = [list(zip(normal.mz[int(normal.peak_off[i]):int(normal.peak_off[i + 1])].tolist(),
+                      normal.intensity[int(normal.peak_off[i]):int(normal.peak_off[i + 1])].tolist()))
+             for i in range(normal.n)]
+    sp_o = _mk(lists[:3] + crafted + lists[3:], list(normal.precursor_mz[:3]) + [400.0] +
+               list(normal.precursor_mz[3:]), list(normal.charge[:3]) + [8] + list(normal.charge[3:]))
+    prm = engine.search_params(False, 500_000_000, 0, 256, 5, 4, max_charge=8)
+    import ctypes as C
+    s, keep = engine._spectra_struct(sp_o)
+    need = C.c_uint64()
+    capi.check(capi.ps_workspace_bytes(ix.handle, sp_o.n, int(sp_o.peak_off[-1]), C.byref(prm), C.byref(need)))
+    ws = engine.Workspace()
+    d = ws.get(need.value)
+    bh = C.c_void_p()
+    _say("counter-bound overflow")
+    capi.check(capi.ps_search_batch(ix.handle, C.byref(d), C.byref(s), C.byref(prm), C.byref(bh)))
+    hits = np.zeros(sp_o.n * 5, capi.HIT_DTYPE)
+    stats = np.zeros(sp_o.n, capi.STAT_DTYPE)
+    hist = np.zeros(sp_o.n * 512, np.int32)
+    rc = capi.ps_results(bh, engine.ptr(hits), engine.ptr(stats), engine.ptr(hist))
+    capi.ps_batch_free(bh)
+    assert rc == capi.PS_EOVERFLOW and "counter" in capi.last_error()
+    assert stats["status"][3] == capi.PS_STATUS_OVERFLOW
+    assert stats["n_scored"][3] == 0 and np.all(hits.reshape(-1, 5)[3]["id"] == 0xFFFFFFFF)
+    assert np.isnan(stats["evalue"][3])
+    # the rest equals the oracle on the same index series
+    keep_idx = [0, 1, 2, 4, 5, 6]
+    oh, ost, og = db.search(sp_o.subset(keep_idx), False, 500_000_000, 0, 256, 5, 4, ion_types=63)
+    from types import SimpleNamespace
+    part = SimpleNamespace(hits=hits.reshape(-1, 5)[keep_idx], stats=stats[keep_idx],
+                           hist=hist.reshape(-1, 512)[keep_idx])
+    assert_parity(part, oh, ost, og)

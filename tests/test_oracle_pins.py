@@ -841,3 +841,48 @@ def test_sampled_assembly_equals_full_assembly_when_lossless():
     # where samples were lost, the assembled histogram is the full one cut to the windows
     for i in np.nonzero(~lossless)[0]:
         assert (samp[2][i] <= full[2][i]).all() and samp[2][i].sum() < full[2][i].sum()
+
+
+def test_scores_past_51_1_land_in_the_open_last_bin():
+    """A 40-residue peptide whose every b and y ion is a peak scores
+    H = log10(39! 39! S) ~ 96, far past 51.1: it must be counted in the open
+    last histogram bin 511 (not past the array), and the tail fit must stop at
+    bin 510, the bin below the top hit's clamped bin.  Checked against the
+    brute force, which clamps with min(511, floor(10 H)) on its own."""
+    pep = "GASPVTCLINDQEMHFYWGASPVTCLINDQEMHFYWGAGK"          # no K/R inside, ends with K
+    assert len(pep) == 40
+    rng = np.random.default_rng(51)
+    filler = "".join(rng.choice(list("GASPVTLINDQEMHFYWKR"), 300))
+    proteins = [pep + "R" + filler[:150], filler[150:]]
+    rows = bf.database(proteins, 1, 4, 45, [], 0)
+    res = np.frombuffer("".join(proteins).encode(), dtype=np.uint8)
+    off = np.zeros(len(proteins) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in proteins])
+    db = oracle.Database(res, off, 1, 4, 45, [], 0)
+    assert len(db) == len(rows) and len(rows) > 30
+    src = [r for r in rows if r[1] == 0 and r[2] == 0 and r[3] == 40][0]
+    r = src[5]
+    ions = [sum(r[:i]) + bf.PROTON_UDA for i in range(1, 40)] + \
+           [sum(r[40 - i:]) + bf.WATER_UDA + bf.PROTON_UDA for i in range(1, 40)]
+    peaks = [(float(m) * 1e-6, 10.0) for m in ions]
+    peaks += [(float(rng.uniform(100, 2000)), float(rng.lognormal())) for _ in range(40)]
+    sp = _spectra([peaks], [(src[0] * 1e-6 + 2 * 1.007276) / 2], [2])
+    for T, fit in ((0, oracle.FIT_TAIL), (1, oracle.FIT_TAIL), (1, oracle.FIT_GUMBEL)):
+        hits, stats, hist = db.search(sp, False, 10**12, T, 200, 5, 1, threads=1, fit=fit)
+        want = bf.search(rows, sp.mz, sp.intensity, sp.precursor_mz[0], 2, False, 10**12, T, 200, 5, 1)
+        top = float(hits[0, 0]["hyperscore"])
+        assert top > 51.1 and int(hits[0, 0]["n_b"]) >= 39 and int(hits[0, 0]["n_y"]) >= 39
+        assert top == pytest.approx(want["top"][0][1][3], rel=1e-12)
+        assert np.array_equal(hist[0].astype(np.int64), want["hist"])
+        assert hist[0, 511] >= 1 and hist[0, 511] == sum(1 for v in want["scored"].values() if v[3] >= 51.1)
+        if fit == oracle.FIT_TAIL:
+            assert int(stats[0]["status"]) == want["status"]
+            if want["status"] == 0:
+                assert float(stats[0]["evalue"]) == pytest.approx(want["evalue"], rel=1e-9)
+            # the fit ends at bin 510: a top hit anywhere in the open bin (51.15) fits the same
+            # points, one in bin 510 (51.05) one point fewer
+            ns = int(stats[0]["n_scored"])
+            st1, ev1, w1, b1, n1 = oracle.evalue(hist[0], top, ns)
+            assert st1 == int(stats[0]["status"]) == 0
+            assert n1 == oracle.evalue(hist[0], 51.15, ns)[4] == oracle.evalue(hist[0], 51.05, ns)[4] + 1
+            assert ev1 == pytest.approx(ns * 10.0 ** (w1 * top + b1), rel=1e-12)
