@@ -342,6 +342,19 @@ int ps_search_dump(ps_index* idx, const ps_device* work, const ps_spectra* spect
 int ps_batch_timing(ps_batch* batch, double* scan_ms, uint32_t* scan_launches, uint64_t* postings,
                     uint64_t* bin_lookups);
 
+/* Work counters of a finished search (of a batch, or of a plan's last run). */
+typedef struct {
+    uint64_t postings;          /* postings streamed = sum over window candidates of shared pairs */
+    uint64_t bin_lookups;       /* fragment-bin lookups (probes with a bin inside the index) */
+    uint64_t work_items;        /* persistent work items (0 for the plain schedule) */
+    uint64_t wide_spectra;      /* spectra whose counter bound needs the 64-bit counters */
+    uint64_t overflow_spectra;  /* spectra reported PS_STATUS_OVERFLOW */
+    uint64_t reserved[3];
+} ps_counters;
+
+/* Blocks until the batch is done, then writes its counters.  PS_EINVAL for NULL. */
+int ps_batch_counters(ps_batch* batch, ps_counters* out);
+
 void ps_batch_free(ps_batch* batch);
 
 /* ---- result assembly over database partitions --------------------------- */
@@ -440,6 +453,10 @@ int ps_plan_results(ps_plan* plan, ps_hit* hits, ps_stat* stats, int32_t* hist);
  * postings streamed, bin lookups and work items of the persistent scan. */
 int ps_plan_timing(ps_plan* plan, double* graph_ms, double* scan_ms, uint64_t* postings, uint64_t* bin_lookups,
                    uint64_t* work_items);
+
+/* Blocks until the plan's last run is done, then writes its counters (as
+ * ps_batch_counters). */
+int ps_plan_counters(ps_plan* plan, ps_counters* out);
 
 /* Device pointers of the plan's results (as ps_batch_device_results), valid
  * for the last run once it is done on the plan's stream, until the next run. */

@@ -74,6 +74,11 @@ class ps_tune_trial(C.Structure):
     _fields_ = [("schedule", ps_schedule), ("scan_ms", C.c_double), ("same", C.c_int32), ("pad", C.c_int32)]
 
 
+class ps_counters(C.Structure):
+    _fields_ = [("postings", C.c_uint64), ("bin_lookups", C.c_uint64), ("work_items", C.c_uint64),
+                ("wide_spectra", C.c_uint64), ("overflow_spectra", C.c_uint64), ("reserved", C.c_uint64 * 3)]
+
+
 class ps_serve_stats(C.Structure):
     _fields_ = [("completed", C.c_uint64), ("spectra", C.c_uint64), ("runs", C.c_uint64), ("refused", C.c_uint64),
                 ("max_queue", C.c_uint64), ("streams", C.c_uint32), ("pad", C.c_uint32), ("pool_bytes", C.c_uint64),
@@ -132,6 +137,7 @@ _SIGS = [
     ("ps_assemble", C.c_int, [_P, C.c_uint32, C.POINTER(ps_part), C.c_uint64, C.c_uint32, C.c_int32, _P, _P, _P]),
     ("ps_sample", C.c_int, [_P, C.c_uint64, _P, _P, _P]),
     ("ps_batch_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint32), _U64P, _U64P]),
+    ("ps_batch_counters", C.c_int, [_P, C.POINTER(ps_counters)]),
     ("ps_batch_free", None, [_P]),
     ("ps_plan_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
     ("ps_plan_create", C.c_int, [_P, C.POINTER(ps_device), C.c_uint64, C.c_uint64, C.POINTER(ps_search_params),
@@ -141,6 +147,7 @@ _SIGS = [
     ("ps_plan_run_device", C.c_int, [_P, C.c_uint64, C.c_uint64]),
     ("ps_plan_results", C.c_int, [_P, _P, _P, _P]),
     ("ps_plan_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _U64P, _U64P, _U64P]),
+    ("ps_plan_counters", C.c_int, [_P, C.POINTER(ps_counters)]),
     ("ps_plan_device_results", C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]),
     ("ps_plan_stream", C.c_int, [_P, C.POINTER(_P)]),
     ("ps_plan_free", None, [_P]),
@@ -222,6 +229,7 @@ ps_batch_device_results = _fn("ps_batch_device_results")
 ps_assemble = _fn("ps_assemble")
 ps_sample = _fn("ps_sample")
 ps_batch_timing = _fn("ps_batch_timing")
+ps_batch_counters = _fn("ps_batch_counters")
 ps_batch_free = _fn("ps_batch_free")
 ps_plan_bytes = _fn("ps_plan_bytes")
 ps_plan_create = _fn("ps_plan_create")
@@ -230,6 +238,7 @@ ps_plan_inputs = _fn("ps_plan_inputs")
 ps_plan_run_device = _fn("ps_plan_run_device")
 ps_plan_results = _fn("ps_plan_results")
 ps_plan_timing = _fn("ps_plan_timing")
+ps_plan_counters = _fn("ps_plan_counters")
 ps_plan_device_results = _fn("ps_plan_device_results")
 ps_plan_stream = _fn("ps_plan_stream")
 ps_plan_free = _fn("ps_plan_free")

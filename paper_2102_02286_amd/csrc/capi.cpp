@@ -457,6 +457,22 @@ extern "C" int ps_batch_timing(ps_batch* B, double* scan_ms, uint32_t* launches,
     return PS_OK;
 }
 
+extern "C" int ps_batch_counters(ps_batch* B, ps_counters* out) {
+    if (!B || !out) return fail(PS_EINVAL, "NULL argument");
+    hipError_t e = hipEventSynchronize(B->ev_done);
+    if (e != hipSuccess) return fail(PS_EDEVICE, "batch failed: %s", hipGetErrorString(e));
+    memset(out, 0, sizeof *out);
+    if (B->n) {
+        const unsigned long long* c = B->h_counters;
+        out->postings = c[kCtrPostings];
+        out->bin_lookups = c[kCtrLookups];
+        out->work_items = B->schedule == PS_SCHED_PERSISTENT ? c[kCtrItems] : 0;
+        out->wide_spectra = c[kCtrWide];
+        out->overflow_spectra = c[kCtrOverflow];
+    }
+    return PS_OK;
+}
+
 extern "C" int ps_search_dump(ps_index* ix, const ps_device* work, const ps_spectra* spectra,
                               const ps_search_params* params, uint64_t cap, uint32_t* spectrum, uint32_t* id,
                               uint16_t* n_b, uint16_t* n_y, uint32_t* sum_q, uint64_t* count) {

@@ -141,7 +141,11 @@ struct Work {
     uint64_t dump_cap;
 };
 
-enum CounterSlot { kCtrPostings = 0, kCtrLookups = 1, kCtrQueue = 2, kCtrItems = 3, kCtrDump = 4 };
+enum CounterSlot {
+    kCtrPostings = 0, kCtrLookups = 1, kCtrQueue = 2, kCtrItems = 3, kCtrDump = 4,
+    kCtrWide = 5,      // spectra that need 64-bit shared-peak counters
+    kCtrOverflow = 6,  // spectra whose counter bound passes even the 64-bit form
+};
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t stream);

@@ -387,6 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
                     if (!(nbmax <= 255 && smax <= 65535)) {
                         inf.flags |= kFlagWide;
                         if (!(nbmax < kLfSize && smax < kLsSize)) inf.flags |= kFlagOverflow;
+                        atomicAdd(&A.w.counters[(inf.flags & kFlagOverflow) ? kCtrOverflow : kCtrWide], 1ull);
                     }
                 }
             }

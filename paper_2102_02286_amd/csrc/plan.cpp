@@ -250,6 +250,20 @@ extern "C" int ps_plan_timing(ps_plan* P, double* graph_ms, double* scan_ms, uin
     return PS_OK;
 }
 
+extern "C" int ps_plan_counters(ps_plan* P, ps_counters* out) {
+    if (!P || !out) return fail(PS_EINVAL, "NULL argument");
+    int rc = plan_wait(P);
+    if (rc != PS_OK) return rc;
+    memset(out, 0, sizeof *out);
+    const unsigned long long* c = P->h_counters;
+    out->postings = c[kCtrPostings];
+    out->bin_lookups = c[kCtrLookups];
+    out->work_items = P->schedule == PS_SCHED_PERSISTENT ? c[kCtrItems] : 0;
+    out->wide_spectra = c[kCtrWide];
+    out->overflow_spectra = c[kCtrOverflow];
+    return PS_OK;
+}
+
 extern "C" int ps_plan_device_results(ps_plan* P, ps_hit** hits, ps_stat** stats, int32_t** hist) {
     if (!P) return fail(PS_EINVAL, "NULL plan");
     if (hits) *hits = P->w.hits;

@@ -228,6 +228,8 @@ class Results:
     scan_ms: float
     postings: int
     lookups: int
+    wide_spectra: int = 0
+    overflow_spectra: int = 0
 
 
 def search(index: HostIndex, sp, params: capi.ps_search_params, ws: Workspace | None = None) -> Results:
@@ -279,8 +281,11 @@ def collect(batch, n: int, params: capi.ps_search_params) -> Results:
         check(rc, "ps_results")
     ms, la, po, lk = C.c_double(), C.c_uint32(), C.c_uint64(), C.c_uint64()
     check(capi.ps_batch_timing(batch, C.byref(ms), C.byref(la), C.byref(po), C.byref(lk)), "ps_batch_timing")
+    ct = capi.ps_counters()
+    check(capi.ps_batch_counters(batch, C.byref(ct)), "ps_batch_counters")
     return Results(hits.reshape(n, params.top_k), stats,
-                   hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, ms.value, po.value, lk.value)
+                   hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, ms.value, po.value, lk.value,
+                   ct.wide_spectra, ct.overflow_spectra)
 
 
 def _device_results(batch):
@@ -452,8 +457,11 @@ class Plan:
         g, sc = C.c_double(), C.c_double()
         po, lk, it = C.c_uint64(), C.c_uint64(), C.c_uint64()
         check(capi.ps_plan_timing(self.handle, C.byref(g), C.byref(sc), C.byref(po), C.byref(lk), C.byref(it)))
+        ct = capi.ps_counters()
+        check(capi.ps_plan_counters(self.handle, C.byref(ct)), "ps_plan_counters")
         r = Results(hits.reshape(n, prm.top_k), stats,
-                    hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, sc.value, po.value, lk.value)
+                    hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, sc.value, po.value, lk.value,
+                    ct.wide_spectra, ct.overflow_spectra)
         r.graph_ms = g.value
         r.items = it.value
         return r

@@ -95,6 +95,13 @@ class Spectra:
                        self.precursor_mz[idx].copy(), self.charge[idx].copy(),
                        None if self.is_noise is None else self.is_noise[idx].copy())
 
+    def slice(self, a: int, b: int) -> "Spectra":
+        """Spectra [a, b) as a new batch (contiguous peaks, offsets rebased)."""
+        p0, p1 = int(self.peak_off[a]), int(self.peak_off[b])
+        return Spectra((self.peak_off[a:b + 1] - np.uint64(p0)).copy(), self.mz[p0:p1].copy(),
+                       self.intensity[p0:p1].copy(), self.precursor_mz[a:b].copy(), self.charge[a:b].copy(),
+                       None if self.is_noise is None else self.is_noise[a:b].copy())
+
     @staticmethod
     def concat(parts: list["Spectra"]) -> "Spectra":
         off = [np.zeros(1, np.uint64)]
@@ -306,9 +313,14 @@ class Workload:
     def proteome(self) -> Proteome:
         return make_proteome(self.n_proteins, self.proteome_seed)
 
-    def spectra(self, prot: Proteome | None = None, n: int | None = None, seed: int | None = None) -> Spectra:
+    def spectra(self, prot: Proteome | None = None, n: int | None = None, seed: int | None = None,
+                charges: tuple | None = None) -> Spectra:
+        """The workload's spectra recipe with n spectra; `charges` overrides the
+        precursor charges drawn (the serving requests of the large workload use
+        2-4)."""
         prot = prot if prot is not None else self.proteome()
-        rec = self.recipe if n is None else SpectraRecipe(**{**self.recipe.__dict__, "n": n})
+        rec = SpectraRecipe(**{**self.recipe.__dict__, **({"n": n} if n is not None else {}),
+                               **({"charges": tuple(charges)} if charges is not None else {})})
         return make_spectra(prot, self.missed, self.min_len, self.max_len, self.mods,
                             self.max_mods, rec, self.spectra_seed if seed is None else seed)
 
