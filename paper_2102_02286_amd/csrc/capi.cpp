@@ -155,8 +155,6 @@ uint64_t layout_work(uint64_t n, uint64_t nnz, const KParams& kp, bool copy_inpu
     t.hist = (int32_t*)take(n * (uint64_t)kHistBins * 4);
     t.n_scored = (unsigned long long*)take(n * 8);
     t.partial = (ps_hit*)take(max_items * (uint64_t)kp.top_k * sizeof(ps_hit));
-    t.item_spec = (uint32_t*)take(max_items * 4);
-    t.item_t0 = (uint32_t*)take(max_items * 4);
     t.spec_item0 = (uint32_t*)take((n + 1) * 4);
     t.hits = (ps_hit*)take(n * (uint64_t)kp.top_k * sizeof(ps_hit));
     t.stats = (ps_stat*)take(n * sizeof(ps_stat));

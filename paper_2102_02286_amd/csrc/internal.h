@@ -130,8 +130,6 @@ struct Work {
     int32_t* hist;             // [n * 512]
     unsigned long long* n_scored;  // [n]
     ps_hit* partial;           // [n_items * top_k]
-    uint32_t* item_spec;       // [n_items] (persistent schedule) spectrum of each item
-    uint32_t* item_t0;         // [n_items] first tile
     uint32_t* spec_item0;      // [n + 1] first item of each spectrum
     ps_hit* hits;              // [n * top_k]
     ps_stat* stats;            // [n]
