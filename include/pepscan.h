@@ -357,6 +357,31 @@ int ps_batch_counters(ps_batch* batch, ps_counters* out);
 
 void ps_batch_free(ps_batch* batch);
 
+/* ---- one batch without allocations -------------------------------------- */
+
+/* Device bytes of the work area ps_search_static uses on each GPU. */
+#define PS_STATIC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate: code being captured into a hipGraph, tight
+ * serving loops, harnesses that forbid allocation.  The same search as
+ * ps_search_device (the same kernels, results equal bit for bit), enqueued on
+ * `stream` (a hipStream_t, NULL = null stream).  Every pointer is device
+ * memory the caller owns: the spectra (CSR with nnz peaks; they must stay valid
+ * until the stream reaches the end of the search), and the outputs hits[n *
+ * top_k], stats[n] and, when not NULL, hist[n * 512], which the kernels write
+ * directly (nothing is copied to the host).  Every other buffer of the search
+ * lives in one static work area of PS_STATIC_SCRATCH_BYTES that each GPU holds
+ * from its first call until the process ends.  The call allocates nothing: no
+ * device memory, no pinned host memory, no events, no host-to-device copy.
+ * Calls that overlap on one GPU share that area and race: serialise them (one
+ * stream, or wait for one call before the next).  Returns without waiting.
+ * Errors: PS_EINVAL (NULL pointer, bad parameters, index not on the device),
+ * PS_ENOMEM when the batch needs more than the static area (split the batch;
+ * about 10k spectra of 200 peaks fit on a 40M-peptide index), PS_EDEVICE.
+ * Invalid spectra are reported per spectrum (PS_STATUS_INVALID). */
+int ps_search_static(ps_index* idx, void* stream, const ps_spectra* spectra, uint64_t nnz,
+                     const ps_search_params* params, ps_hit* hits, ps_stat* stats, int32_t* hist);
+
 /* ---- result assembly over database partitions --------------------------- */
 
 /* Sampled partial histogram of one spectrum: the 256-byte intermediate result

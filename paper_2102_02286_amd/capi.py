@@ -19,6 +19,7 @@ PS_STATUS_OK, PS_STATUS_NO_HITS, PS_STATUS_FEW_POINTS, PS_STATUS_BAD_SLOPE, PS_S
     PS_STATUS_OVERFLOW = 0, 1, 2, 3, 4, 5
 PS_HIST_BINS = 512
 PS_MAX_PEAKS_IN = 4096
+PS_STATIC_SCRATCH_BYTES = 256 << 20
 PS_SCHED_PLAIN, PS_SCHED_PERSISTENT = 0, 1
 PS_FIT_TAIL, PS_FIT_GUMBEL = 0, 1
 PS_INTENSITY_LINEAR, PS_INTENSITY_SQRT = 0, 1
@@ -139,6 +140,8 @@ _SIGS = [
     ("ps_batch_timing", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint32), _U64P, _U64P]),
     ("ps_batch_counters", C.c_int, [_P, C.POINTER(ps_counters)]),
     ("ps_batch_free", None, [_P]),
+    ("ps_search_static", C.c_int, [_P, _P, C.POINTER(ps_spectra), C.c_uint64, C.POINTER(ps_search_params), _P, _P,
+                                   _P]),
     ("ps_plan_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
     ("ps_plan_create", C.c_int, [_P, C.POINTER(ps_device), C.c_uint64, C.c_uint64, C.POINTER(ps_search_params),
                                  C.POINTER(_P)]),
@@ -231,6 +234,7 @@ ps_sample = _fn("ps_sample")
 ps_batch_timing = _fn("ps_batch_timing")
 ps_batch_counters = _fn("ps_batch_counters")
 ps_batch_free = _fn("ps_batch_free")
+ps_search_static = _fn("ps_search_static")
 ps_plan_bytes = _fn("ps_plan_bytes")
 ps_plan_create = _fn("ps_plan_create")
 ps_plan_run = _fn("ps_plan_run")

@@ -147,6 +147,8 @@ enum CounterSlot {
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t stream);
+// write the actual batch size into a device header (a kernel, so it can be captured)
+hipError_t launch_set_header(BatchHdr* hdr, uint64_t n, uint64_t nnz, hipStream_t stream);
 // fill count_per_spectrum * hdr->n words (grid sized for `cap_count`)
 hipError_t launch_fill_per_spectrum(void* p, uint32_t value, uint64_t count_per_spectrum, uint64_t cap_count,
                                     const BatchHdr* hdr, hipStream_t stream);

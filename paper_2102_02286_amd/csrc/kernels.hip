@@ -153,6 +153,16 @@ hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t 
     return hipGetLastError();
 }
 
+__global__ void k_set_header(BatchHdr* hdr, unsigned long long n, unsigned long long nnz) {
+    if (threadIdx.x == 0) { hdr->n = n; hdr->nnz = nnz; }
+}
+
+hipError_t launch_set_header(BatchHdr* hdr, uint64_t n, uint64_t nnz, hipStream_t stream) {
+    hipLaunchKernelGGL(k_set_header, dim3(1), dim3(64), 0, stream, hdr, (unsigned long long)n,
+                       (unsigned long long)nnz);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_per_spectrum(uint32_t* p, uint32_t v, uint64_t per, const BatchHdr* hdr) {
     const uint64_t n = hdr->n * per;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
