@@ -197,7 +197,9 @@ typedef struct {
                                  at least the index's tile grain (ps_index_directory) */
     uint32_t tiles_per_item;  /* PS_SCHED_PERSISTENT: tiles per work item (1..4096) */
     uint32_t groups_per_cu;   /* PS_SCHED_PERSISTENT: resident workgroups per compute unit (1..8) */
-    uint32_t reserved[3];     /* must be 0 */
+    uint32_t group_threads;   /* threads per scan workgroup sharing one tile of counters: 256 (0 means
+                                 256) or 512; 512 needs tiles of at least 8192 candidates */
+    uint32_t reserved[2];     /* must be 0 */
 } ps_schedule;
 
 /* ---- errors ------------------------------------------------------------ */

@@ -64,7 +64,7 @@ class ps_search_params(C.Structure):
 
 class ps_schedule(C.Structure):
     _fields_ = [("tile", C.c_uint32), ("tiles_per_item", C.c_uint32), ("groups_per_cu", C.c_uint32),
-                ("reserved", C.c_uint32 * 3)]
+                ("group_threads", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 class ps_part(C.Structure):

@@ -46,7 +46,7 @@ bool cache_lookup(const char* path, const std::string& key, ps_schedule* out) {
         std::istringstream is(line);
         std::string k;
         ps_schedule s{};
-        if (is >> k >> s.tile >> s.tiles_per_item >> s.groups_per_cu && k == key) {
+        if (is >> k >> s.tile >> s.tiles_per_item >> s.groups_per_cu >> s.group_threads && k == key) {
             *out = s;
             return true;
         }
@@ -68,7 +68,8 @@ void cache_store(const char* path, const std::string& key, const ps_schedule& s)
     }
     std::ofstream f(path, std::ios::trunc);
     for (auto& l : keep) f << l << "\n";
-    f << key << " " << s.tile << " " << s.tiles_per_item << " " << s.groups_per_cu << "\n";
+    f << key << " " << s.tile << " " << s.tiles_per_item << " " << s.groups_per_cu << " " << s.group_threads
+      << "\n";
 }
 
 struct Outcome {
@@ -145,17 +146,26 @@ extern "C" int ps_autotune(ps_index* ix, const ps_device* work, const ps_spectra
     for (int pass = 0; pass < 2; ++pass) {
         bool improved = false;
         for (int field = 0; field < 3; ++field) {
+            // field 0: (threads per workgroup, tile) pairs, coded as threads << 16 | tile / 1024
             std::vector<uint32_t> vals;
             switch (field) {
-                case 0: vals = {4096, 8192, 16384}; break;
+                case 0: vals = {256u << 16 | 4, 256u << 16 | 8, 256u << 16 | 16, 512u << 16 | 8, 512u << 16 | 16};
+                        break;
                 case 1: if (persistent) vals = {8, 16, 32, 64, 128, 256}; break;
                 case 2: if (persistent) vals = {3, 4, 5, 6, 8}; break;
             }
             for (uint32_t v : vals) {
                 ps_schedule s = cur;
-                uint32_t* f = field == 0 ? &s.tile : field == 1 ? &s.tiles_per_item : &s.groups_per_cu;
-                if (*f == v) continue;
-                *f = v;
+                if (field == 0) {
+                    const uint32_t gt = v >> 16, tile = (v & 0xFFFFu) * 1024u;
+                    if (s.tile == tile && (s.group_threads ? s.group_threads : 256u) == gt) continue;
+                    s.tile = tile;
+                    s.group_threads = gt;
+                } else {
+                    uint32_t* f = field == 1 ? &s.tiles_per_item : &s.groups_per_cu;
+                    if (*f == v) continue;
+                    *f = v;
+                }
                 if (check_schedule(s) != PS_OK || s.tile < (1u << ix->dir_shift)) continue;
                 double ms = 0;
                 rc = measure(s, &ref, &ms);

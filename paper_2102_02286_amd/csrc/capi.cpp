@@ -107,6 +107,7 @@ int make_kparams(const ps_index* ix, const ps_search_params* p, KParams* kp, con
                     1u << ix->dir_shift);
     kp->tile = sched->tile;
     kp->tile_shift = (uint32_t)__builtin_ctz(sched->tile);
+    kp->nt = sched->group_threads ? sched->group_threads : 256;
     if (scan_lds_bytes(*kp, false) > kMaxLds)
         return fail(PS_EINVAL, "tile %u needs %zu bytes of LDS with these parameters (max %zu)", kp->tile,
                     scan_lds_bytes(*kp, false), kMaxLds);
@@ -124,6 +125,10 @@ Schedule default_schedule() {
 int check_schedule(const Schedule& s) {
     if (s.tile < 1024 || s.tile > 32768 || (s.tile & (s.tile - 1)))
         return fail(PS_EINVAL, "tile must be a power of two in 1024..32768");
+    if (s.group_threads != 0 && s.group_threads != 256 && s.group_threads != 512)
+        return fail(PS_EINVAL, "group_threads must be 256 or 512 (0 means 256)");
+    if (s.group_threads == 512 && s.tile < 8192)
+        return fail(PS_EINVAL, "512-thread workgroups need tiles of at least 8192 candidates");
     if (s.tiles_per_item < 1 || s.tiles_per_item > 4096) return fail(PS_EINVAL, "tiles_per_item must be 1..4096");
     if (s.groups_per_cu < 1 || s.groups_per_cu > 8) return fail(PS_EINVAL, "groups_per_cu must be 1..8");
     for (uint32_t r : s.reserved)

@@ -47,7 +47,7 @@ constexpr uint32_t kPostPad = 0xFFFFFFFFu;  // filler after a list up to its qua
 // Postings are addressed as 16-byte quads with 32-bit indices: at most 2^32 quads.
 constexpr uint64_t kMaxQuads = 1ull << 32;
 constexpr int kBlock = 256;                 // threads per workgroup for every kernel
-constexpr size_t kMaxLds = 158 * 1024;      // dynamic LDS per workgroup (160 KB on gfx950 less static use)
+constexpr size_t kMaxLds = 156 * 1024;      // dynamic LDS per workgroup (160 KB on gfx950 less static use)
 
 // Per-spectrum flags written by the prep kernel.
 enum : uint32_t {
@@ -117,6 +117,7 @@ struct KParams {
     uint32_t seg_cap;          // probe slots per workgroup (entries x bin offsets)
     uint32_t tile;             // candidates per LDS counter tile: a power of two, >= 1 << dir_shift
     uint32_t tile_shift;       // log2(tile)
+    uint32_t nt;               // threads per scan workgroup: 256 or 512 (tile >= 16 nt)
     int32_t fit;               // PS_FIT_TAIL or PS_FIT_GUMBEL
     uint32_t noise_permille;   // peaks below Imax * noise_permille / 1000 are dropped before top-B
     int32_t intensity;         // PS_INTENSITY_LINEAR or PS_INTENSITY_SQRT

@@ -45,16 +45,16 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t 
     return lo;
 }
 
-template <typename T>
+template <typename T, uint32_t NT = kBlock>
 __device__ __forceinline__ T block_sum(T v, T* scratch) {
-    // scratch: kBlock/64 slots
+    // scratch: NT/64 slots
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) scratch[w] = v;
     __syncthreads();
     T r = 0;
     if (threadIdx.x == 0) {
-        for (int i = 0; i < kBlock / 64; ++i) r += scratch[i];
+        for (int i = 0; i < (int)(NT / 64); ++i) r += scratch[i];
         scratch[0] = r;
     }
     __syncthreads();
@@ -430,22 +430,28 @@ struct ScanArgs {
     uint32_t per_item;         // partial lists indexed by work item (persistent schedule)
 };
 
+// The scan runs in workgroups of NT = 256 or 512 threads (4 or 8 wavefronts)
+// sharing one tile of counters; a tile has at least 16 NT ids, so the filter
+// reads whole passes of 16-byte counter groups.
 constexpr uint32_t kRounds = 2;       // gather rounds of 64 posting quads a wavefront keeps in flight
-constexpr uint32_t kCandCap = 384;    // candidates buffered per workgroup before scoring
-constexpr uint32_t kWaveCand = kCandCap / (kBlock / 64);   // each wavefront's share of the buffer
-constexpr uint32_t kMapCap = 1024;    // flat quad positions mapped to slots at a time
+constexpr uint32_t kWaveCand = 96;    // candidates each wavefront buffers before scoring
+template <uint32_t NT> constexpr uint32_t cand_cap() { return kWaveCand * (NT / 64); }
+constexpr uint32_t kMapCap = 4096;    // flat quad positions mapped to slots at a time
 // map words: one per 64 quads, plus one for the start bit just past the chunk
 constexpr uint32_t kMapWords = kMapCap / 64 + 1;
 // s_waitcnt operand (gfx9 encoding): vmcnt(0), expcnt and lgkmcnt left at their maxima
 constexpr int kWaitVmem0 = 0x0F70;
 
+template <uint32_t NT>
 struct ScanShared {
     uint32_t nact;
-    unsigned long long wsum[kBlock / 64];
-    unsigned long long red[kBlock / 64];
-    double wh[kBlock / 64][PS_MAX_TOP_K];          // per-wavefront top-k lists
-    uint32_t wid[kBlock / 64][PS_MAX_TOP_K];
-    unsigned long long wc[kBlock / 64][PS_MAX_TOP_K];
+    unsigned long long acc_post, acc_look;     // the item's postings and bin lookups
+    unsigned long long wsum[NT / 64];
+    unsigned long long red[NT / 64];
+    double wh[NT / 64][PS_MAX_TOP_K];          // per-wavefront top-k lists
+    uint32_t wid[NT / 64][PS_MAX_TOP_K];
+    unsigned long long wc[NT / 64][PS_MAX_TOP_K];
+    uint32_t head[NT / 64];                    // merge cursors of the final top-k (thread 0)
 };
 
 // What the lookup pass finds for one fragment-bin probe with postings in the
@@ -473,7 +479,7 @@ struct SegBase {
 // The map of a chunk of kMapCap flat positions: bit b of mbits[R] is set when
 // a slot's range starts at position 64 R + b, and mrank[R] is the rank of the
 // slot holding position 64 R, so the slot of any position is one popcount away.
-template <typename C>
+template <typename C, uint32_t NT>
 struct ScanLds {
     C* cnt;
     SlotInit* init;
@@ -482,9 +488,9 @@ struct ScanLds {
     uint32_t* sqb;        // [seg_cap] first quad of each slot's bin list, by slot
     unsigned long long* mbits;
     uint32_t* mrank;
-    C* cand_cnt;          // [kCandCap] counters of candidates that passed the filter, kWaveCand per wavefront
+    C* cand_cnt;          // [cand_cap] counters of candidates that passed the filter, kWaveCand per wavefront
     int32_t* hist;
-    uint32_t* cand_id;    // [kCandCap] their peptide ids
+    uint32_t* cand_id;    // [cand_cap] their peptide ids
     __device__ ScanLds(uint8_t* base, uint32_t tile, uint32_t segcap) {
         size_t o = 0;
         cnt = (C*)base;
@@ -497,7 +503,7 @@ struct ScanLds {
         sqb = (uint32_t*)(base + o); o += (size_t)segcap * 4;
         mrank = (uint32_t*)(base + o); o += (size_t)(kMapCap / 64) * 4;
         o = (o + 15) & ~(size_t)15;
-        cand_cnt = (C*)(base + o); o += (size_t)kCandCap * sizeof(C);
+        cand_cnt = (C*)(base + o); o += (size_t)cand_cap<NT>() * sizeof(C);
         hist = (int32_t*)(base + o); o += (size_t)kHistBins * 4;
         cand_id = (uint32_t*)(base + o);
     }
@@ -505,21 +511,22 @@ struct ScanLds {
 
 size_t scan_lds_bytes(const KParams& kp, bool wide) {
     const size_t csz = wide ? 8 : 4;
+    const size_t cap = (size_t)kWaveCand * (kp.nt / 64);
     const size_t head = std::max((size_t)kp.tile * csz, (size_t)kp.seg_cap * sizeof(SlotInit));
     size_t o = (head + 15) & ~(size_t)15;
     o += (size_t)kp.seg_cap * (sizeof(SegBase) + 8) + (size_t)kMapWords * 8 + (size_t)(kMapCap / 64) * 4;
     o = (o + 15) & ~(size_t)15;
-    o += (size_t)kCandCap * csz;
+    o += cap * csz;
     o += (size_t)kHistBins * 4;
-    o += (size_t)kCandCap * 4;
+    o += cap * 4;
     return (o + 15) & ~(size_t)15;
 }
 
 // Hyperscore of one candidate that passed the filter: log10(n_b! n_y! S) from
 // the fp64 tables (log10 S passed in), plus its histogram bin (width 0.1,
 // last bin open).
-template <typename C, bool DUMP>
-__device__ __forceinline__ double score_finish(const ScanArgs& A, ScanLds<C>& L, uint32_t s, uint32_t id, C c,
+template <typename C, bool DUMP, uint32_t NT>
+__device__ __forceinline__ double score_finish(const ScanArgs& A, ScanLds<C, NT>& L, uint32_t s, uint32_t id, C c,
                                                double ls_sq, uint32_t& scored) {
     const uint32_t nb = Cnt<C>::nb(c), ny = Cnt<C>::ny(c), sq = Cnt<C>::s(c);
     const double h = (A.ix.lf[nb] + A.ix.lf[ny]) + ls_sq;
@@ -539,15 +546,15 @@ __device__ __forceinline__ double score_finish(const ScanArgs& A, ScanLds<C>& L,
     return h;
 }
 
-template <typename C, bool DUMP>
-__device__ __forceinline__ double score_one(const ScanArgs& A, ScanLds<C>& L, uint32_t s, uint32_t id, C c,
+template <typename C, bool DUMP, uint32_t NT>
+__device__ __forceinline__ double score_one(const ScanArgs& A, ScanLds<C, NT>& L, uint32_t s, uint32_t id, C c,
                                             uint32_t& scored) {
-    return score_finish<C, DUMP>(A, L, s, id, c, A.ix.ls[Cnt<C>::s(c)], scored);
+    return score_finish<C, DUMP, NT>(A, L, s, id, c, A.ix.ls[Cnt<C>::s(c)], scored);
 }
 
 // Exclusive prefix sum over the workgroup in thread order; *total gets the sum.
 // Contains one barrier; `wsum` must not be in use by another pass.
-template <typename T>
+template <typename T, uint32_t NT>
 __device__ __forceinline__ T block_exclusive_scan(T v, T* wsum, T* total) {
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     T x = v;
@@ -558,7 +565,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* wsum, T* total) {
     if (lane == 63u) wsum[wave] = x;
     __syncthreads();
     T before = 0, all = 0;
-    for (uint32_t w = 0; w < kBlock / 64; ++w) {
+    for (uint32_t w = 0; w < NT / 64; ++w) {
         const T t = wsum[w];
         before += w < wave ? t : (T)0;
         all += t;
@@ -584,7 +591,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
 
 // Exclusive prefix sums over the workgroup (thread order) of a count n and of a
 // small number e <= U, with their totals.  One barrier; `wsum` must be free.
-template <uint32_t U>
+template <uint32_t U, uint32_t NT>
 __device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsigned long long* wsum, uint32_t* n_ex,
                                                   uint32_t* e_ex, uint32_t* n_all, uint32_t* e_all) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -601,7 +608,7 @@ __device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsign
     if (lane == 0) wsum[wave] = ((unsigned long long)et << 32) | ntot;
     __syncthreads();
     uint32_t nb = 0, eb = 0, na = 0, ea = 0;
-    for (uint32_t w = 0; w < kBlock / 64; ++w) {
+    for (uint32_t w = 0; w < NT / 64; ++w) {
         const unsigned long long v = wsum[w];
         const uint32_t vn = (uint32_t)v, ve = (uint32_t)(v >> 32);
         nb += w < wave ? vn : 0u;
@@ -620,8 +627,8 @@ __device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsign
 // that begins inside it.
 // A start exactly at the chunk's end is entered too (word kMapCap / 64): it
 // ends the chunk's last slot.
-template <typename C>
-__device__ __forceinline__ void map_slot(const ScanLds<C>& L, uint32_t k, uint32_t a, uint32_t b, uint32_t c0) {
+template <typename C, uint32_t NT>
+__device__ __forceinline__ void map_slot(const ScanLds<C, NT>& L, uint32_t k, uint32_t a, uint32_t b, uint32_t c0) {
     const uint32_t ce = c0 + kMapCap;
     if (a >= c0 && a <= ce) atomicOr(&L.mbits[(a - c0) >> 6], 1ull << ((a - c0) & 63u));
     if (b <= c0 || a >= ce) return;
@@ -645,8 +652,8 @@ struct Gather {
 // start bit is set and the last when the next position's is (the bit past
 // the chunk, or the end marker after the last slot): only there do postings
 // outside the run share the quad.
-template <typename C>
-__device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C>& L, Gather& g) {
+template <typename C, uint32_t NT>
+__device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C, NT>& L, Gather& g) {
     const uint32_t lane = threadIdx.x & 63u;
     const unsigned long long below = (2ull << lane) - 2ull;   // positions 1..lane of a round
 #pragma unroll
@@ -671,8 +678,8 @@ __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C
     g.next += 64u * kRounds;
 }
 
-template <typename C>
-__device__ __forceinline__ void gather_consume(const ScanLds<C>& L, const Gather& g, uint32_t tsh) {
+template <typename C, uint32_t NT>
+__device__ __forceinline__ void gather_consume(const ScanLds<C, NT>& L, const Gather& g, uint32_t tsh) {
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t w = g.mq[r / 2] >> (16u * (r % 2u));
@@ -704,8 +711,8 @@ __device__ __forceinline__ void gather_consume(const ScanLds<C>& L, const Gather
 // The directory gives every run's tile boundaries directly, so the postings
 // of tile t + 1 are mapped and loaded while tile t is filtered and scored,
 // and the boundaries of tile t + 2 are loaded one tile earlier still.
-template <typename C, bool DUMP, uint32_t U>
-__device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint32_t s, uint32_t ida,
+template <typename C, bool DUMP, uint32_t U, uint32_t NT>
+__device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>& L, uint32_t s, uint32_t ida,
                           uint32_t idb, ps_hit* out) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
@@ -722,8 +729,8 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     const uint32_t m = kp.tile >> gsh;                 // directory entries per tile
     const uint32_t t0 = ida >> tsh, t_last = (idb - 1) >> tsh;
 
-    if (tid == 0) sh.nact = 0;
-    for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) L.hist[i] = 0;
+    if (tid == 0) { sh.nact = 0; sh.acc_post = 0; sh.acc_look = 0; }
+    for (uint32_t i = tid; i < (uint32_t)kHistBins; i += NT) L.hist[i] = 0;
     __syncthreads();
 
     // end of tile u's part of a run that ends at s1
@@ -735,7 +742,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     unsigned long long lookups = 0, postings = 0;
     const uint32_t npairs = n_ent * width;
     const uint32_t gmask = (1u << gsh) - 1u;
-    for (uint32_t k = tid; k < npairs; k += kBlock) {
+    for (uint32_t k = tid; k < npairs; k += NT) {
         const uint32_t e = ent[k / width];
         if (e == kEntryInvalid) continue;
         const int64_t bin = (int64_t)(e >> 8) + (int64_t)(k % width) - T;
@@ -760,10 +767,19 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         si.e1 = t0 < t_last ? tile_end(row, t0 + 1, s1) : s1;
         L.init[slot] = si;
     }
+    // the item's postings and lookups: a wavefront sum, added in LDS
+    for (int o = 32; o > 0; o >>= 1) {
+        postings += __shfl_down(postings, o, 64);
+        lookups += __shfl_down(lookups, o, 64);
+    }
+    if (lane == 0) {
+        if (postings) atomicAdd(&sh.acc_post, postings);
+        if (lookups) atomicAdd(&sh.acc_look, lookups);
+    }
     __syncthreads();
     const uint32_t nact = sh.nact;
     // slots [tid * us, tid * us + us) belong to this thread
-    const uint32_t us = nact > kBlock ? (nact + kBlock - 1) / kBlock : 1u;
+    const uint32_t us = nact > NT ? (nact + NT - 1) / NT : 1u;
     // Each slot also holds the aligned quad of its directory row that contains
     // the entry for the end of tile t + 2 (needed when moving to tile t + 1):
     // a quad serves four tiles (one tile = m entries), and the next quad is
@@ -806,7 +822,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     // `total` flat positions
     auto share = [&](uint32_t c0, uint32_t total) {
         const uint32_t n = min(kMapCap, total - c0);
-        const uint32_t per = ((n + kBlock - 1) / kBlock) * 64u;
+        const uint32_t per = ((n + NT - 1) / NT) * 64u;
         g.c0 = c0;
         g.next = c0 + min(n, wave * per);
         g.fe = c0 + min(n, wave * per + per);
@@ -817,7 +833,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
     // quads of postings a run [cur, end) covers (0 when empty)
     auto quads = [](uint32_t cur, uint32_t end) { return end > cur ? ((cur & 3u) + (end - cur) + 3u) >> 2 : 0u; };
     auto prepare = [&]() {
-        for (uint32_t i = tid; i < kMapWords; i += kBlock) L.mbits[i] = 0ull;
+        for (uint32_t i = tid; i < kMapWords; i += NT) L.mbits[i] = 0ull;
         uint32_t mine = 0, mine_ne = 0;
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {                 // unowned slots are 0 - 0
@@ -826,7 +842,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             mine_ne += n != 0u;
         }
         uint32_t run, rank, total_n, total_ne;
-        block_scan_counts<U>(mine, mine_ne, sh.wsum, &run, &rank, &total_n, &total_ne);
+        block_scan_counts<U, NT>(mine, mine_ne, sh.wsum, &run, &rank, &total_n, &total_ne);
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
             const uint32_t n = quads(o_cur[u], o_end[u]);
@@ -837,7 +853,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
                 sb.qx = (o_bq[u] >> 24) | (o_cur[u] & 3u) << 8 | (o_end[u] - a - 4u * (n - 1u) - 1u) << 10;
                 L.sbase[rank] = sb;
                 L.sstart[rank] = run;
-                map_slot<C>(L, rank, run, run + n, 0u);
+                map_slot<C, NT>(L, rank, run, run + n, 0u);
                 run += n;
                 ++rank;
             }
@@ -847,11 +863,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         if (tid == 0 && total_n <= kMapCap) atomicOr(&L.mbits[total_n >> 6], 1ull << (total_n & 63u));   // end marker
         __syncthreads();
         share(0u, ptot);
-        gather_issue<C>(ix, L, g);
+        gather_issue<C, NT>(ix, L, g);
     };
 
     if (nact > 0) {
-        for (uint32_t i = tid; i < kp.tile; i += kBlock) L.cnt[i] = (C)0;
+        for (uint32_t i = tid; i < kp.tile; i += NT) L.cnt[i] = (C)0;
         prepare();
     }
     // The directory quad loaded in one tile is first used right after the next
@@ -868,7 +884,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             const bool ok = j < wn;
             const C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
             const uint32_t id = ok ? L.cand_id[wbuf + j] : 0u;
-            const double h = ok ? score_one<C, DUMP>(A, L, s, id, c, scored) : -INFINITY;
+            const double h = ok ? score_one<C, DUMP, NT>(A, L, s, id, c, scored) : -INFINITY;
             top.insert_lanes(ok, h, id, c, kk);
         }
         wn = 0;
@@ -878,24 +894,24 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         const uint32_t tb = t << tsh;
         // counters of tile t: the batch loaded last, then any further batches,
         // then any further chunks
-        gather_consume<C>(L, g, tsh);
+        gather_consume<C, NT>(L, g, tsh);
         while (g.next < g.fe) {
-            gather_issue<C>(ix, L, g);
-            gather_consume<C>(L, g, tsh);
+            gather_issue<C, NT>(ix, L, g);
+            gather_consume<C, NT>(L, g, tsh);
         }
         const uint32_t p_t = ptot;
         for (uint32_t c0 = kMapCap; c0 < p_t; c0 += kMapCap) {
             __syncthreads();                            // every wavefront is done with the last map
-            for (uint32_t i = tid; i < kMapWords; i += kBlock) L.mbits[i] = 0ull;
+            for (uint32_t i = tid; i < kMapWords; i += NT) L.mbits[i] = 0ull;
             __syncthreads();
-            for (uint32_t k = tid; k < nne; k += kBlock)
-                map_slot<C>(L, k, L.sstart[k], k + 1 < nne ? L.sstart[k + 1] : p_t, c0);
+            for (uint32_t k = tid; k < nne; k += NT)
+                map_slot<C, NT>(L, k, L.sstart[k], k + 1 < nne ? L.sstart[k + 1] : p_t, c0);
             if (tid == 0 && p_t - c0 <= kMapCap) atomicOr(&L.mbits[(p_t - c0) >> 6], 1ull << ((p_t - c0) & 63u));
             __syncthreads();
             share(c0, p_t);
             while (g.next < g.fe) {
-                gather_issue<C>(ix, L, g);
-                gather_consume<C>(L, g, tsh);
+                gather_issue<C, NT>(ix, L, g);
+                gather_consume<C, NT>(L, g, tsh);
             }
         }
         // end of tile t + 2 from the quad holding directory entry (t + 3) m
@@ -920,10 +936,10 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
             constexpr uint32_t kPer = 16 / sizeof(C);
             const uint32_t nvec = kp.tile / kPer;
             uint4* cv = (uint4*)L.cnt;
-            // nvec is a multiple of 4 kBlock: four steps per pass, at fixed offsets
-            for (uint32_t base0 = wave * 64u; base0 < nvec; base0 += 4u * kBlock)
+            // nvec is a multiple of 4 NT: four steps per pass, at fixed offsets
+            for (uint32_t base0 = wave * 64u; base0 < nvec; base0 += 4u * NT)
 #pragma unroll
-            for (uint32_t base = base0; base < base0 + 4u * kBlock; base += kBlock) {
+            for (uint32_t base = base0; base < base0 + 4u * NT; base += NT) {
                 const uint32_t i = base + lane;
                 const uint4 v = cv[i];
                 cv[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -975,13 +991,13 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
 
     score_buffer();                                     // what is left of the item's candidates
     // top-k of the item: the wavefronts' lists (in LDS), merged by one thread
-    const unsigned long long sc = block_sum<unsigned long long>(scored, sh.red);   // has barriers
+    const unsigned long long sc = block_sum<unsigned long long, NT>(scored, sh.red);   // has barriers
     if (tid == 0) {
-        uint32_t head[kBlock / 64];
-        for (int v = 0; v < kBlock / 64; ++v) head[v] = 0;
+        uint32_t* head = sh.head;
+        for (int v = 0; v < (int)(NT / 64); ++v) head[v] = 0;
         for (uint32_t j = 0; j < kk; ++j) {
             int best = 0;
-            for (int v = 1; v < kBlock / 64; ++v)
+            for (int v = 1; v < (int)(NT / 64); ++v)
                 if (better_hit(sh.wh[v][head[v]], sh.wid[v][head[v]], sh.wh[best][head[best]], sh.wid[best][head[best]]))
                     best = v;
             const uint32_t hh = head[best]++;
@@ -998,25 +1014,25 @@ __device__ void scan_item(const ScanArgs& A, ScanShared& sh, ScanLds<C>& L, uint
         }
         if (sc) atomicAdd(&A.w.n_scored[s], sc);
     }
-    for (uint32_t i = tid; i < (uint32_t)kHistBins; i += kBlock) {
+    for (uint32_t i = tid; i < (uint32_t)kHistBins; i += NT) {
         const int32_t v = L.hist[i];
         if (v) atomicAdd(&A.w.hist[(uint64_t)s * kHistBins + i], v);
     }
-    const unsigned long long pl = block_sum<unsigned long long>(postings, sh.red);
-    const unsigned long long lk = block_sum<unsigned long long>(lookups, sh.red);
     if (tid == 0) {
-        if (pl) atomicAdd(&A.w.counters[kCtrPostings], pl);
-        if (lk) atomicAdd(&A.w.counters[kCtrLookups], lk);
+        if (sh.acc_post) atomicAdd(&A.w.counters[kCtrPostings], sh.acc_post);
+        if (sh.acc_look) atomicAdd(&A.w.counters[kCtrLookups], sh.acc_look);
     }
     __syncthreads();
 }
 
-// Plain schedule: workgroup s searches spectrum s's whole window.
-template <typename C, bool DUMP, uint32_t U>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(U == 1 ? 6 : 1, 8))) void k_scan_plain(ScanArgs A) {
+// Plain schedule: workgroup s searches spectrum s's whole window.  With one
+// probe slot per thread the kernel asks for six resident wavefronts per SIMD
+// (at most 80 VGPRs).
+template <typename C, bool DUMP, uint32_t U, uint32_t NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(U == 1 ? 6 : 1, 8))) void k_scan_plain(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ ScanShared sh;
-    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap);
+    __shared__ ScanShared<NT> sh;
+    ScanLds<C, NT> L(lds, A.kp.tile, A.kp.seg_cap);
     const uint32_t s = blockIdx.x;
     if (s >= A.sp.hdr->n) return;
     const SpecInfo inf = A.w.info[s];
@@ -1032,37 +1048,41 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(U == 1 ?
         }
         return;
     }
-    scan_item<C, DUMP, U>(A, sh, L, s, inf.lo, inf.hi, out);
+    scan_item<C, DUMP, U, NT>(A, sh, L, s, inf.lo, inf.hi, out);
 }
 
-// Register slots per thread for a workgroup that may hold seg_cap probe slots.
-static uint32_t slots_per_thread(uint32_t seg_cap) {
-    const uint32_t u = (seg_cap + kBlock - 1) / kBlock;
+// Register slots per thread for a workgroup of nt threads that may hold
+// seg_cap probe slots.
+static uint32_t slots_per_thread(uint32_t seg_cap, uint32_t nt) {
+    const uint32_t u = (seg_cap + nt - 1) / nt;
     return u <= 1 ? 1u : u == 2 ? 2u : u == 3 ? 3u : u == 4 ? 4u : 8u;
 }
 
-template <typename C, bool DUMP, uint32_t U>
+template <typename C, bool DUMP, uint32_t U, uint32_t NT>
 static hipError_t launch_scan_plain_u(ScanArgs a, uint64_t n, hipStream_t stream) {
     const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_scan_plain<C, DUMP, U>), dim3((uint32_t)n), dim3(kBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_scan_plain<C, DUMP, U, NT>), dim3((uint32_t)n), dim3(NT), lds, stream, a);
     return hipGetLastError();
 }
 
-template <typename C, bool DUMP>
+template <typename C, bool DUMP, uint32_t NT>
 static hipError_t launch_scan_plain_t(ScanArgs a, uint64_t n, hipStream_t stream) {
-    switch (slots_per_thread(a.kp.seg_cap)) {
-        case 1: return launch_scan_plain_u<C, DUMP, 1>(a, n, stream);
-        case 2: return launch_scan_plain_u<C, DUMP, 2>(a, n, stream);
-        case 3: return launch_scan_plain_u<C, DUMP, 3>(a, n, stream);
-        case 4: return launch_scan_plain_u<C, DUMP, 4>(a, n, stream);
-        default: return launch_scan_plain_u<C, DUMP, 8>(a, n, stream);
+    switch (slots_per_thread(a.kp.seg_cap, NT)) {
+        case 1: return launch_scan_plain_u<C, DUMP, 1, NT>(a, n, stream);
+        case 2: return launch_scan_plain_u<C, DUMP, 2, NT>(a, n, stream);
+        case 3: return launch_scan_plain_u<C, DUMP, 3, NT>(a, n, stream);
+        case 4: return launch_scan_plain_u<C, DUMP, 4, NT>(a, n, stream);
+        default:
+            if constexpr (NT == 256) return launch_scan_plain_u<C, DUMP, 8, NT>(a, n, stream);
+            else return hipErrorInvalidValue;   // 512 threads hold every probe slot in 4 per thread
     }
 }
 
-// 64-bit counters take twice the LDS per candidate: halve the tile (down to
-// one directory block) until the workgroup fits.
+// 64-bit counters take twice the LDS per candidate: they run in workgroups of
+// 256 threads, halving the tile (down to one directory block) until it fits.
 static KParams wide_params(const DevIndex& ix, KParams kp) {
+    kp.nt = 256;
     while (kp.tile > (1u << ix.dir_shift) && scan_lds_bytes(kp, true) > kMaxLds) {
         kp.tile /= 2;
         kp.tile_shift -= 1;
@@ -1078,13 +1098,18 @@ hipError_t launch_scan_plain(const DevIndex& ix, const DevSpectra& sp, const KPa
     // narrow counters for every spectrum that proved it can use them, then wide
     if (!wide_only) {
         a.want_wide = 0;
-        e = dump ? launch_scan_plain_t<uint32_t, true>(a, sp.n, stream) : launch_scan_plain_t<uint32_t, false>(a, sp.n, stream);
+        if (kp.nt == 512)
+            e = dump ? launch_scan_plain_t<uint32_t, true, 512>(a, sp.n, stream)
+                     : launch_scan_plain_t<uint32_t, false, 512>(a, sp.n, stream);
+        else
+            e = dump ? launch_scan_plain_t<uint32_t, true, 256>(a, sp.n, stream)
+                     : launch_scan_plain_t<uint32_t, false, 256>(a, sp.n, stream);
         if (e != hipSuccess) return e;
     }
     a.want_wide = 1;
     a.kp = wide_params(ix, kp);
-    e = dump ? launch_scan_plain_t<unsigned long long, true>(a, sp.n, stream)
-             : launch_scan_plain_t<unsigned long long, false>(a, sp.n, stream);
+    e = dump ? launch_scan_plain_t<unsigned long long, true, 256>(a, sp.n, stream)
+             : launch_scan_plain_t<unsigned long long, false, 256>(a, sp.n, stream);
     return e;
 }
 
@@ -1144,15 +1169,15 @@ hipError_t launch_worklist(const DevSpectra& sp, const KParams& kp, const Work& 
 }
 
 // With one probe slot per thread, ask for six resident wavefronts per SIMD
-// (at most 80 VGPRs): with the LDS of six workgroups per CU this is the
+// (at most 80 VGPRs): with the LDS of the resident workgroups this is the
 // occupancy the work-queue scan runs best at.
-template <typename C, uint32_t U>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(U == 1 ? 6 : 1, 8)))
+template <typename C, uint32_t U, uint32_t NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(U == 1 ? 6 : 1, 8)))
 void k_scan_persistent(ScanArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ ScanShared sh;
+    __shared__ ScanShared<NT> sh;
     __shared__ uint32_t s_item;
-    ScanLds<C> L(lds, A.kp.tile, A.kp.seg_cap);
+    ScanLds<C, NT> L(lds, A.kp.tile, A.kp.seg_cap);
     const uint32_t n = (uint32_t)A.sp.hdr->n;
     const uint32_t total = A.w.spec_item0[n];
     const uint32_t tpi = A.tiles_per_item;
@@ -1175,28 +1200,36 @@ void k_scan_persistent(ScanArgs A) {
         const uint32_t blk = inf.lo / span + (g - A.w.spec_item0[s]);
         const uint32_t ida = max(inf.lo, blk * span);
         const uint32_t idb = min(inf.hi, (blk + 1) * span);
-        scan_item<C, false, U>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
+        scan_item<C, false, U, NT>(A, sh, L, s, ida, idb, A.w.partial + (uint64_t)g * A.kp.top_k);
     }
 }
 
-template <typename C, uint32_t U>
-static hipError_t launch_persistent_t(ScanArgs a, uint32_t grid, hipStream_t stream) {
+template <typename C, uint32_t U, uint32_t NT>
+static hipError_t launch_persistent_u(ScanArgs a, uint32_t grid, hipStream_t stream) {
     const size_t lds = scan_lds_bytes(a.kp, sizeof(C) == 8);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_scan_persistent<C, U>), dim3(grid), dim3(kBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_scan_persistent<C, U, NT>), dim3(grid), dim3(NT), lds, stream, a);
     return hipGetLastError();
+}
+
+template <uint32_t NT>
+static hipError_t launch_persistent_t(ScanArgs a, uint32_t grid, hipStream_t stream) {
+    switch (slots_per_thread(a.kp.seg_cap, NT)) {
+        case 1: return launch_persistent_u<uint32_t, 1, NT>(a, grid, stream);
+        case 2: return launch_persistent_u<uint32_t, 2, NT>(a, grid, stream);
+        case 3: return launch_persistent_u<uint32_t, 3, NT>(a, grid, stream);
+        case 4: return launch_persistent_u<uint32_t, 4, NT>(a, grid, stream);
+        default:
+            if constexpr (NT == 256) return launch_persistent_u<uint32_t, 8, NT>(a, grid, stream);
+            else return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
                                   uint32_t grid, uint32_t tiles_per_item, hipStream_t stream) {
     if (sp.n == 0) return hipSuccess;
     ScanArgs a{ix, sp, kp, w, tiles_per_item, 0u, 1u};
-    const uint32_t u = slots_per_thread(kp.seg_cap);
-    hipError_t e = u == 1 ? launch_persistent_t<uint32_t, 1>(a, grid, stream)
-                 : u == 2 ? launch_persistent_t<uint32_t, 2>(a, grid, stream)
-                 : u == 3 ? launch_persistent_t<uint32_t, 3>(a, grid, stream)
-                 : u == 4 ? launch_persistent_t<uint32_t, 4>(a, grid, stream)
-                          : launch_persistent_t<uint32_t, 8>(a, grid, stream);
+    hipError_t e = kp.nt == 512 ? launch_persistent_t<512>(a, grid, stream) : launch_persistent_t<256>(a, grid, stream);
     if (e != hipSuccess) return e;
     // spectra that need 64-bit counters: one workgroup per spectrum, slot = its item
     return launch_scan_plain(ix, sp, kp, w, false, true, true, stream);
@@ -1690,12 +1723,18 @@ hipError_t launch_sample(const int32_t* hist, const ps_stat* stats, ps_sampled* 
 
 // Allow every scan kernel the whole LDS once, before any launch or capture.
 hipError_t init_kernel_attributes() {
-#define PS_PLAIN_FNS(U)                                                                             \
-        (const void*)k_scan_plain<uint32_t, false, U>, (const void*)k_scan_plain<uint32_t, true, U>,  \
-        (const void*)k_scan_plain<unsigned long long, false, U>,                                       \
-        (const void*)k_scan_plain<unsigned long long, true, U>, (const void*)k_scan_persistent<uint32_t, U>
-    const void* fns[] = {PS_PLAIN_FNS(1), PS_PLAIN_FNS(2), PS_PLAIN_FNS(3), PS_PLAIN_FNS(4), PS_PLAIN_FNS(8)};
-#undef PS_PLAIN_FNS
+#define PS_NARROW_FNS(U, NT)                                                                           \
+        (const void*)k_scan_plain<uint32_t, false, U, NT>, (const void*)k_scan_plain<uint32_t, true, U, NT>, \
+        (const void*)k_scan_persistent<uint32_t, U, NT>
+#define PS_WIDE_FNS(U)                                                                                 \
+        (const void*)k_scan_plain<unsigned long long, false, U, 256>,                                  \
+        (const void*)k_scan_plain<unsigned long long, true, U, 256>
+    const void* fns[] = {PS_NARROW_FNS(1, 256), PS_NARROW_FNS(2, 256), PS_NARROW_FNS(3, 256), PS_NARROW_FNS(4, 256),
+                         PS_NARROW_FNS(8, 256), PS_NARROW_FNS(1, 512), PS_NARROW_FNS(2, 512), PS_NARROW_FNS(3, 512),
+                         PS_NARROW_FNS(4, 512), PS_WIDE_FNS(1), PS_WIDE_FNS(2), PS_WIDE_FNS(3), PS_WIDE_FNS(4),
+                         PS_WIDE_FNS(8)};
+#undef PS_NARROW_FNS
+#undef PS_WIDE_FNS
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
         if (e != hipSuccess) return e;

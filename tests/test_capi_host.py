@@ -149,7 +149,8 @@ def test_schedule_validation_and_tile_directory():
     n_pep, n_post, n_bins = h.shape()
     assert nbytes == n_bins * (((n_pep >> 12) + 2 + 3) // 4 * 4) * 4
     assert h.schedule().tile >= 1 << grain
-    for bad in [dict(tile=2048), dict(tile=6144), dict(tile=65536), dict(tiles_per_item=0), dict(groups_per_cu=9)]:
+    for bad in [dict(tile=2048), dict(tile=6144), dict(tile=65536), dict(tiles_per_item=0), dict(groups_per_cu=9),
+                dict(group_threads=384), dict(group_threads=512, tile=4096)]:
         with pytest.raises(capi.PsError) as e:
             h.set_schedule(**bad)
         assert e.value.code == capi.PS_EINVAL
@@ -159,6 +160,8 @@ def test_schedule_validation_and_tile_directory():
     h.set_schedule(tile=8192, tiles_per_item=7, groups_per_cu=3)
     got = h.schedule()
     assert (got.tile, got.tiles_per_item, got.groups_per_cu) == (8192, 7, 3)
+    h.set_schedule(group_threads=512)
+    assert h.schedule().group_threads == 512
 
 
 def test_tile_directory_matches_postings():

@@ -146,9 +146,10 @@ def test_small_open_permutation_and_split_invariance(small_open):
     assert r2.hits.tobytes() == r0.hits.tobytes() and r2.hist.tobytes() == r0.hist.tobytes()
 
 
-@pytest.mark.parametrize("sched", [dict(tile=4096), dict(tile=8192), dict(tile=16384), dict(tile=32768)])
+@pytest.mark.parametrize("sched", [dict(tile=4096), dict(tile=8192), dict(tile=16384), dict(tile=32768),
+                                   dict(tile=8192, group_threads=512), dict(tile=32768, group_threads=512)])
 def test_schedules_give_identical_results(small_open, sched):
-    """The tile size changes only speed."""
+    """The tile size and the workgroup size change only speed."""
     w, prot, sp, ix, db, (oh, ost, og) = small_open
     assert ix.directory()[0] == 12
     old = ix.schedule()
@@ -165,7 +166,9 @@ def test_schedules_give_identical_results(small_open, sched):
 
 
 @pytest.mark.parametrize("sched", [dict(tiles_per_item=1), dict(tiles_per_item=3, tile=8192),
-                                   dict(tiles_per_item=64, groups_per_cu=1), dict(tiles_per_item=5, groups_per_cu=8)])
+                                   dict(tiles_per_item=64, groups_per_cu=1), dict(tiles_per_item=5, groups_per_cu=8),
+                                   dict(tiles_per_item=2, tile=8192, group_threads=512),
+                                   dict(tiles_per_item=9, tile=16384, group_threads=512, groups_per_cu=3)])
 def test_persistent_schedule_parity(small_open, sched):
     """The work-queue scan splits windows into (spectrum, tile range) items;
     merged results equal the oracle for any item size."""
@@ -495,11 +498,12 @@ def small_open_merged(small_open):
 
 
 @pytest.mark.parametrize("sched", [dict(tile=4096, tiles_per_item=64), dict(tile=8192, tiles_per_item=3),
-                                   dict(tile=4096, tiles_per_item=1, groups_per_cu=8)])
+                                   dict(tile=4096, tiles_per_item=1, groups_per_cu=8),
+                                   dict(tile=8192, tiles_per_item=2, group_threads=512)])
 @pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
 def test_small_open_merged_lists_parity(small_open_merged, sched, schedule):
     w, prot, sp, ix, db, (oh, ost, og) = small_open_merged
-    ix.set_schedule(**sched)
+    ix.set_schedule(**{"group_threads": 0, **sched})
     _say(f"small open merged: {sched} schedule {schedule}")
     prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
                                max_charge=3, schedule=schedule)
