@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libpepscan.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "build.hip", "index.cpp", "capi.cpp", "plan.cpp", "server.cpp", "autotune.cpp",
+SOURCES = ["kernels.hip", "stats.hip", "build.hip", "index.cpp", "capi.cpp", "plan.cpp", "server.cpp", "autotune.cpp",
            "noalloc.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

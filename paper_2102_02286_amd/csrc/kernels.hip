@@ -9,11 +9,9 @@
 //              candidate filter (shared peaks >= k), hyperscore, wavefront
 //              top-k and the LDS score histogram (Supplementary Algorithm 3's
 //              score/heap)
-//   k_merge    merge of partial top-k lists, Savitzky-Golay smoothed survival
-//              function, linear tail fit and expect value (Superstep 4;
-//              Supplementary Algorithm 4)
-//   k_assemble the same statistics over the results of G database partitions:
-//              histogram addition and a G-way top-k merge first (Superstep 4)
+//
+// The statistics that follow the scan (merge of partial top-k lists, expect
+// values, partition assembly and sampling) are in stats.hip.
 //
 // Integer work is exact: counters are packed integer fields, the histogram is
 // integer, and hyperscores come from host-built fp64 tables, so results do not
@@ -1233,492 +1231,6 @@ hipError_t launch_scan_persistent(const DevIndex& ix, const DevSpectra& sp, cons
     if (e != hipSuccess) return e;
     // spectra that need 64-bit counters: one workgroup per spectrum, slot = its item
     return launch_scan_plain(ix, sp, kp, w, false, true, true, stream);
-}
-
-// ---------------------------------------------------------------------------
-// merge: partial top-k -> hits; histogram -> smoothed survival -> tail fit -> e-value
-// ---------------------------------------------------------------------------
-
-struct MergeArgs {
-    DevIndex ix;
-    DevSpectra sp;
-    KParams kp;
-    Work w;
-    uint32_t per_item;   // 1: partial lists per work item (spec_item0 ranges); 0: one per spectrum
-};
-
-// LDS of the expect-value stage.
-struct EvShared {
-    long long wsum[kBlock / 64];            // per wavefront: sum of smoothed numerators
-    unsigned long long wkey[kBlock / 64];   // per wavefront: best mode key
-    double v[5][kBlock / 64];               // per wavefront: least-squares sums (Gumbel: moments)
-};
-
-// Sum of x over the block, valid in every thread; uses S.v[k].  Has barriers.
-__device__ __forceinline__ double block_sum_f64(double x, int k, EvShared& S) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    if ((threadIdx.x & 63u) == 0) S.v[k][threadIdx.x >> 6] = x;
-    __syncthreads();
-    double t = 0;
-    for (int i = 0; i < kBlock / 64; ++i) t += S.v[k][i];
-    return t;
-}
-
-// log-Weibull (Gumbel) fit by moments of the smoothed histogram (numerators
-// num[u] of bins 2t + u; the common factor 1/35 cancels): mean m and variance v
-// over bin centres x_j = 0.1 j + 0.05, beta = sqrt(6 v) / pi,
-// mu = m - gamma beta, ev = N * (1 - exp(-exp(-(h1 - mu) / beta))).  Fewer than
-// 3 non-zero bins: FEW_POINTS.  Result valid in thread 0.
-__device__ void gumbel_fit(long long num0, long long num1, long long total, unsigned long long N, double h1,
-                           int& status, double& ev, EvShared& S) {
-    const uint32_t tid = threadIdx.x;
-    const long long num[2] = {num0, num1};
-    double wx = 0, pts = 0;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const double x = 0.1 * (double)(2 * (int)tid + u) + 0.05;
-        wx += (double)num[u] * x;
-        pts += num[u] > 0 ? 1.0 : 0.0;
-    }
-    const double swx = block_sum_f64(wx, 0, S);
-    const double n_pts = block_sum_f64(pts, 1, S);
-    const double m = swx / (double)total;
-    double d2 = 0;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const double d = (0.1 * (double)(2 * (int)tid + u) + 0.05) - m;
-        d2 += (double)num[u] * d * d;
-    }
-    const double sd2 = block_sum_f64(d2, 2, S);
-    if (tid == 0 && status == PS_STATUS_OK) {
-        if (n_pts < 3.0) {
-            status = PS_STATUS_FEW_POINTS;
-        } else {
-            const double v = sd2 / (double)total;
-            const double beta = sqrt(6.0 * v) / 3.14159265358979323846;
-            const double mu = m - 0.57721566490153286061 * beta;
-            ev = (double)N * -expm1(-exp(-(h1 - mu) / beta));
-        }
-    }
-}
-
-// Expect value of one spectrum (Superstep 4): the histogram hg[512] is smoothed
-// with Savitzky-Golay (-3, 12, 17, 12, -3)/35 (numerators kept exact in
-// integers, negatives set to 0), turned into a survival function, fitted by
-// least squares in log10 from the smoothed mode (lowest bin on ties) to the bin
-// below the top hit, and ev = N * 10^(w h1 + b).  Thread t owns bins 2t and
-// 2t + 1; the survival sums come from a suffix scan across the block.  `status`
-// enters as OK, INVALID, OVERFLOW or NO_HITS; only OK is refined (to FEW_POINTS
-// or BAD_SLOPE).  Every thread of the block calls it; the result is valid in
-// thread 0.  Ends with the block synchronised.
-// Kept out of line: inlined into k_merge and k_assemble it took their register
-// count past 150 and their occupancy down to three workgroups per CU (they now
-// ask for five, at 88-94 VGPRs; six would spill to scratch and add HBM traffic).
-__device__ __attribute__((noinline)) void expect_value(const int32_t* hg, unsigned long long N, double h1, int fit,
-                                                      int& status, double& ev, EvShared& S) {
-    static_assert(kHistBins == 2 * kBlock, "two histogram bins per thread");
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    long long num[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int j = 2 * (int)tid + u;
-        long long acc = 0;
-        if (N) {
-            const int c[5] = {-3, 12, 17, 12, -3};
-#pragma unroll
-            for (int t = -2; t <= 2; ++t) {
-                const int i = j + t;
-                if (i >= 0 && i < kHistBins) acc += (long long)c[t + 2] * (long long)hg[i];
-            }
-        }
-        num[u] = acc < 0 ? 0 : acc;
-    }
-    const long long pair = num[0] + num[1];
-    // suffix sum over the lanes of this wavefront: lanes >= lane
-    long long suf = pair;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const long long v = __shfl_down(suf, o, 64);
-        if (lane + (uint32_t)o < 64u) suf += v;
-    }
-    // mode: largest numerator, lowest bin on ties -> max of (value << 9 | (511 - j))
-    const unsigned long long k0 = ((unsigned long long)num[0] << 9) | (unsigned long long)(kHistBins - 1 - 2 * (int)tid);
-    const unsigned long long k1 = ((unsigned long long)num[1] << 9) | (unsigned long long)(kHistBins - 2 - 2 * (int)tid);
-    unsigned long long key = k0 > k1 ? k0 : k1;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long v = __shfl_xor(key, o, 64);
-        key = v > key ? v : key;
-    }
-    if (lane == 0) { S.wsum[wv] = suf; S.wkey[wv] = key; }
-    __syncthreads();
-    long long total = 0, later = 0;
-    unsigned long long mkey = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-        total += S.wsum[w];
-        if (w > (int)wv) later += S.wsum[w];
-        mkey = S.wkey[w] > mkey ? S.wkey[w] : mkey;
-    }
-    const int mode = kHistBins - 1 - (int)(mkey & 511ull);
-    const long long above = suf - pair + later;              // smoothed mass of bins > 2t + 1
-    const long long tail0 = pair + above, tail1 = num[1] + above;
-    ev = __builtin_nan("");
-    if (fit == PS_FIT_GUMBEL) {
-        if (status == PS_STATUS_OK) {                   // uniform: status and total are block-wide
-            if (total > 0) gumbel_fit(num[0], num[1], total, N, h1, status, ev, S);
-            else status = PS_STATUS_FEW_POINTS;
-        }
-        __syncthreads();
-        return;
-    }
-    // ---- least-squares fit of log10 survival over [mode, bin(H1) - 1]
-    double sx = 0, sy = 0, sxx = 0, sxy = 0, cnt = 0;
-    if (status == PS_STATUS_OK && total > 0) {
-        const double hb = floor(10.0 * h1);
-        const int jh = hb >= (double)(kHistBins - 1) ? kHistBins - 1 : (int)hb;
-#pragma unroll 1
-        for (int u = 0; u < 2; ++u) {                   // one log10 live at a time
-            const int j = 2 * (int)tid + u;
-            const long long tu = u ? tail1 : tail0;
-            if (j < mode || j > jh - 1 || tu <= 0) continue;
-            const double x = 0.1 * (double)j;
-            const double y = log10((double)tu / (double)total);
-            sx += x; sy += y; sxx += x * x; sxy += x * y; cnt += 1.0;
-        }
-    }
-    double v[5] = {sx, sy, sxx, sxy, cnt};
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        double x = v[k];
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-        if (lane == 0) S.v[k][wv] = x;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double t[5];
-        for (int k = 0; k < 5; ++k) { t[k] = 0; for (int i = 0; i < kBlock / 64; ++i) t[k] += S.v[k][i]; }
-        if (status == PS_STATUS_OK) {
-            const double n = t[4];
-            if (n < 3.0) {
-                status = PS_STATUS_FEW_POINTS;
-            } else {
-                const double num_w = n * t[3] - t[0] * t[1];
-                const double den = n * t[2] - t[0] * t[0];
-                const double w = num_w / den;
-                const double b = (t[1] - w * t[0]) / n;
-                if (!(w < 0.0)) status = PS_STATUS_BAD_SLOPE;
-                else ev = (double)N * pow(10.0, w * h1 + b);
-            }
-        }
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void empty_hit(ps_hit& h) {
-    h.id = 0xFFFFFFFFu; h.n_b = h.n_y = 0; h.sum_q = 0; h.pad = 0; h.hyperscore = -INFINITY;
-}
-
-// Keys of the lists being merged, staged in LDS (up to kMergeCap entries).
-constexpr uint32_t kMergeCap = 1024;
-struct TopShared {
-    double h[kMergeCap];
-    uint32_t id[kMergeCap];
-    ps_hit top[PS_MAX_TOP_K];
-};
-
-// Top k of the union of L lists of k entries, each ordered by (hyperscore
-// desc, id asc) with empty entries (id UINT32_MAX) last, into T.top.  An
-// entry's place in the union is its position in its own list plus, for every
-// other list, the number of entries there that rank before it (a binary
-// search); ids are distinct, so places are distinct.  key(c) gives (hyperscore,
-// id) of entry c = list * k + position; emit(c, place) writes entry c to
-// T.top[place].  Every thread calls it; ends with the block synchronised.
-template <typename Key, typename Emit>
-__device__ void merge_sorted_lists(uint32_t L, uint32_t k, TopShared& T, Key key, Emit emit) {
-    const uint32_t tid = threadIdx.x, M = L * k;
-    const bool staged = M <= kMergeCap;
-    if (tid < k) empty_hit(T.top[tid]);
-    if (staged)
-        for (uint32_t c = tid; c < M; c += kBlock) key(c, T.h[c], T.id[c]);
-    __syncthreads();
-    auto get = [&](uint32_t c, double& h, uint32_t& id) {
-        if (staged) { h = T.h[c]; id = T.id[c]; } else { key(c, h, id); }
-    };
-    for (uint32_t c = tid; c < M; c += kBlock) {
-        double h;
-        uint32_t id;
-        get(c, h, id);
-        if (id == 0xFFFFFFFFu) continue;
-        const uint32_t a = c / k;
-        uint32_t place = c - a * k;
-        for (uint32_t b = 0; b < L && place < k; ++b) {
-            if (b == a) continue;
-            uint32_t lo = 0, hi = k;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                double xh;
-                uint32_t xid;
-                get(b * k + mid, xh, xid);
-                if (better_hit(xh, xid, h, id)) lo = mid + 1; else hi = mid;
-            }
-            place += lo;
-        }
-        if (place < k) emit(c, place);
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_merge(MergeArgs A) {
-    __shared__ EvShared S;
-    __shared__ TopShared T;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t K = A.kp.top_k;
-    const uint64_t n_batch = A.sp.hdr->n;
-    for (uint64_t s = blockIdx.x; s < n_batch; s += gridDim.x) {
-        const SpecInfo inf = A.w.info[s];
-        const bool invalid = (inf.flags & kFlagInvalid) != 0;
-        const bool overflow = (inf.flags & kFlagOverflow) != 0;
-        // ---- top-k of the spectrum's partial lists (one per work item, each sorted)
-        uint64_t i0 = s, i1 = s + 1;
-        if (A.per_item) { i0 = A.w.spec_item0[s]; i1 = A.w.spec_item0[s + 1]; }
-        const uint32_t L = (invalid || overflow) ? 0u : (uint32_t)(i1 - i0);
-        const ps_hit* src = A.w.partial + i0 * K;
-        merge_sorted_lists(L, K, T,
-            [&](uint32_t c, double& h, uint32_t& id) { h = src[c].hyperscore; id = src[c].id; },
-            [&](uint32_t c, uint32_t place) { T.top[place] = src[c]; });
-        const unsigned long long N = (invalid || overflow) ? 0ull : A.w.n_scored[s];
-        int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
-                   : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
-        double ev;
-        expect_value(A.w.hist + s * (uint64_t)kHistBins, N, T.top[0].hyperscore, A.kp.fit, status, ev, S);
-        if (tid == 0) {
-            ps_stat st;
-            st.n_window = (invalid) ? 0ull : (unsigned long long)(inf.hi - inf.lo);
-            st.n_scored = N;
-            st.evalue = ev;
-            st.status = status;
-            st.pad = 0;
-            A.w.stats[s] = st;
-        }
-        for (uint32_t j = tid; j < K; j += kBlock) A.w.hits[s * K + j] = T.top[j];
-        __syncthreads();
-    }
-}
-
-hipError_t launch_merge(const DevIndex& ix, const DevSpectra& sp, const KParams& kp, const Work& w,
-                        bool per_item, hipStream_t stream) {
-    if (sp.n == 0) return hipSuccess;
-    MergeArgs a{ix, sp, kp, w, per_item ? 1u : 0u};
-    uint64_t grid = sp.n < (1u << 20) ? sp.n : (1u << 20);
-    hipLaunchKernelGGL(k_merge, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// result assembly over database partitions (Superstep 4; Supplementary
-// Algorithm 4): histogram addition, G-way top-k merge, expect value
-// ---------------------------------------------------------------------------
-
-struct AssembleArgs {
-    ps_part parts[PS_MAX_SHARDS];
-    uint32_t G, K;
-    int32_t fit;
-    uint64_t n;
-    ps_hit* hits;
-    ps_stat* stats;
-    int32_t* hist;   // may be NULL
-};
-
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_assemble(AssembleArgs A) {
-    __shared__ EvShared S;
-    __shared__ TopShared T;
-    __shared__ int32_t s_hist[kHistBins];
-    __shared__ unsigned long long s_scored, s_window;
-    __shared__ uint32_t s_flags;
-    const uint32_t tid = threadIdx.x, G = A.G, K = A.K;
-    for (uint64_t s = blockIdx.x; s < A.n; s += gridDim.x) {
-        if (tid == 0) { s_scored = 0; s_window = 0; s_flags = 0; }
-        __syncthreads();
-        for (uint32_t g = tid; g < G; g += kBlock) {
-            const ps_stat st = A.parts[g].stats[s];
-            atomicAdd(&s_scored, st.n_scored);
-            atomicAdd(&s_window, st.n_window);
-            if (st.status == PS_STATUS_INVALID) atomicOr(&s_flags, 1u);
-            if (st.status == PS_STATUS_OVERFLOW) atomicOr(&s_flags, 2u);
-        }
-        // histogram addition: full partition histograms share bin 0 and add one to
-        // one; a sampled one is shifted to its window [lo, lo + 120) first
-        for (uint32_t j = tid; j < (uint32_t)kHistBins; j += kBlock) {
-            int32_t acc = 0;
-            for (uint32_t g = 0; g < G; ++g) {
-                if (A.parts[g].hist) {
-                    acc += A.parts[g].hist[s * (uint64_t)kHistBins + j];
-                } else {
-                    const ps_sampled* r = A.parts[g].sampled + s;
-                    const uint32_t i = j - (uint32_t)r->lo;      // wraps above 120 below the window
-                    if (i < (uint32_t)PS_SAMPLE_BINS) acc += r->count[i];
-                }
-            }
-            s_hist[j] = acc;
-            if (A.hist) A.hist[s * (uint64_t)kHistBins + j] = acc;
-        }
-        __syncthreads();
-        const bool invalid = (s_flags & 1u) != 0, overflow = (s_flags & 2u) != 0;
-        // top-k of the partitions' lists, ids turned into whole-database ids
-        auto hit_at = [&](uint32_t c) -> const ps_hit& {
-            const uint32_t g = c / K;
-            return A.parts[g].hits[s * K + (c - g * K)];
-        };
-        auto whole_id = [&](uint32_t c, uint32_t id) -> uint32_t {
-            return id == 0xFFFFFFFFu ? id : (uint32_t)((uint64_t)id * G + c / K);
-        };
-        merge_sorted_lists((invalid || overflow) ? 0u : G, K, T,
-            [&](uint32_t c, double& h, uint32_t& id) { const ps_hit& x = hit_at(c); h = x.hyperscore; id = whole_id(c, x.id); },
-            [&](uint32_t c, uint32_t place) { ps_hit x = hit_at(c); x.id = whole_id(c, x.id); T.top[place] = x; });
-        const unsigned long long N = (invalid || overflow) ? 0ull : s_scored;
-        int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
-                   : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
-        double ev;
-        expect_value(s_hist, N, T.top[0].hyperscore, A.fit, status, ev, S);
-        if (tid == 0) {
-            ps_stat st;
-            st.n_window = invalid ? 0ull : s_window;
-            st.n_scored = N;
-            st.evalue = ev;
-            st.status = status;
-            st.pad = 0;
-            A.stats[s] = st;
-        }
-        for (uint32_t j = tid; j < K; j += kBlock) A.hits[s * K + j] = T.top[j];
-        __syncthreads();
-    }
-}
-
-hipError_t launch_assemble(const ps_part* parts, uint32_t G, uint64_t n, uint32_t K, int32_t fit, ps_hit* hits,
-                           ps_stat* stats, int32_t* hist, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    AssembleArgs a;
-    memset(&a, 0, sizeof a);
-    for (uint32_t g = 0; g < G; ++g) a.parts[g] = parts[g];
-    a.G = G; a.K = K; a.fit = fit; a.n = n; a.hits = hits; a.stats = stats; a.hist = hist;
-    const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
-    hipLaunchKernelGGL(k_assemble, dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// sampling: one wavefront per spectrum turns its 512-bin histogram into the
-// 256-byte record of the Sampling section
-// ---------------------------------------------------------------------------
-
-struct SampleArgs {
-    const int32_t* hist;
-    const ps_stat* stats;
-    ps_sampled* out;
-    uint64_t n;
-};
-
-// Wave-wide maximum of a 64-bit key.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        const unsigned long long w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
-}
-
-constexpr uint32_t kSampleWaves = kBlock / 64;
-
-__global__ __launch_bounds__(kBlock) void k_sample(SampleArgs A) {
-    __shared__ int32_t s_h[kSampleWaves][kHistBins];
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    int32_t* h = s_h[wave];
-    for (uint64_t s = (uint64_t)blockIdx.x * kSampleWaves + wave; s < A.n; s += (uint64_t)gridDim.x * kSampleWaves) {
-        // lane l holds bins 8 l .. 8 l + 7 (negative counts, which a search never
-        // writes, count as empty)
-        const int4* src = (const int4*)(A.hist + s * (uint64_t)kHistBins) + 2u * lane;
-        const int4 a = src[0], b = src[1];
-        int32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            v[i] = v[i] > 0 ? v[i] : 0;
-            h[8u * lane + i] = v[i];
-        }
-        // the three most intense bins: key = count, then the lower bin
-        uint32_t used = 0, sum = 0, t = 0;
-        for (int r = 0; r < 3; ++r) {
-            unsigned long long best = 0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const unsigned long long key =
-                    ((unsigned long long)(uint32_t)v[i] << 32) | (uint32_t)(kHistBins - 1 - (8u * lane + i));
-                if (v[i] > 0 && !((used >> i) & 1u) && key > best) best = key;
-            }
-            best = wave_max_u64(best);
-            if (best == 0) break;                                   // wave-uniform
-            const uint32_t bin = (uint32_t)(kHistBins - 1) - (uint32_t)(best & 0xFFFFFFFFull);
-            if (bin / 8u == lane) used |= 1u << (bin % 8u);
-            sum += bin;
-            ++t;
-        }
-        uint32_t first = kHistBins;
-#pragma unroll
-        for (int i = 7; i >= 0; --i)
-            if (v[i] > 0) first = 8u * lane + i;
-        first = wave_min_u32(first);
-        int lo = 0;
-        if (t) {
-            const int mean = (int)(sum / t);
-            lo = (int)first > mean - PS_SAMPLE_HEAD ? (int)first : mean - PS_SAMPLE_HEAD;
-            lo = min(lo, kHistBins - PS_SAMPLE_BINS);
-        }
-        // flags from this lane's bins
-        bool sat = false, lost = false;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int j = (int)(8u * lane) + i;
-            const bool inside = j >= lo && j < lo + PS_SAMPLE_BINS;
-            sat |= inside && v[i] > 65535;
-            lost |= !inside && v[i] > 0;
-        }
-        const uint32_t flags = (__ballot(sat) ? 1u : 0u) | (__ballot(lost) ? 2u : 0u);
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the wave's LDS writes are visible to it
-        // 64 words of the record: header, then count pairs
-        uint32_t word;
-        if (lane == 0) {
-            word = (uint32_t)lo | (flags << 16);
-        } else if (lane == 1) {
-            word = 0;
-        } else if (lane < 4) {
-            const uint64_t ns = A.stats[s].n_scored;
-            word = lane == 2 ? (uint32_t)ns : (uint32_t)(ns >> 32);
-        } else {
-            const int i = 2 * (int)(lane - 4);
-            const int32_t c0 = h[lo + i], c1 = h[lo + i + 1];
-            word = (uint32_t)min(c0, 65535) | ((uint32_t)min(c1, 65535) << 16);
-        }
-        ((uint32_t*)(A.out + s))[lane] = word;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // reads done before the next spectrum's writes
-    }
-}
-
-hipError_t launch_sample(const int32_t* hist, const ps_stat* stats, ps_sampled* out, uint64_t n, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    SampleArgs a{hist, stats, out, n};
-    const uint64_t blocks = (n + kSampleWaves - 1) / kSampleWaves;
-    const uint32_t grid = (uint32_t)(blocks < (1u << 20) ? blocks : (1u << 20));
-    hipLaunchKernelGGL(k_sample, dim3(grid), dim3(kBlock), 0, stream, a);
-    return hipGetLastError();
 }
 
 // Allow every scan kernel the whole LDS once, before any launch or capture.
