@@ -67,7 +67,7 @@ def lib():
         P = C.c_void_p
         L.orc_db_create.restype = P
         L.orc_db_create.argtypes = [P, P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
-                                    C.c_uint32, P, P, P, C.c_uint32]
+                                    C.c_uint32, P, P, P, C.c_uint32, C.c_int]
         L.orc_db_free.argtypes = [P]
         L.orc_db_size.restype = C.c_uint64
         L.orc_db_size.argtypes = [P]
@@ -97,6 +97,17 @@ def lib():
     return _lib
 
 
+def host_threads() -> int:
+    """Threads the oracle uses by default: the process's CPUs, capped by
+    OMP_NUM_THREADS where the environment sets the process's share."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(share)) if share.isdigit() and int(share) > 0 else n)
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
@@ -121,7 +132,7 @@ class Database:
     (mass, protein, start, length, site mask); id = rank."""
 
     def __init__(self, residues: np.ndarray, offsets: np.ndarray, missed: int, min_len: int,
-                 max_len: int, mods: list[ModSpec], max_mods: int):
+                 max_len: int, mods: list[ModSpec], max_mods: int, threads: int | None = None):
         L = lib()
         self._res = np.ascontiguousarray(residues, dtype=np.uint8)
         self._off = np.ascontiguousarray(offsets, dtype=np.uint64)
@@ -131,7 +142,7 @@ class Database:
         delta = np.array([m.delta_uda for m in mods] or [0], dtype=np.int64)
         self._h = L.orc_db_create(_ptr(self._res), _ptr(self._off), self._off.shape[0] - 1,
                                   missed, min_len, max_len, len(mods), _ptr(masks), _ptr(nterm),
-                                  _ptr(delta), max_mods)
+                                  _ptr(delta), max_mods, int(threads or host_threads()))
         if not self._h:
             raise ValueError("oracle rejected the database parameters")
 
@@ -184,7 +195,7 @@ class Database:
                 np.ascontiguousarray(sp.intensity, np.float32), np.ascontiguousarray(sp.precursor_mz, np.float64),
                 np.ascontiguousarray(sp.charge, np.int8)]
         rc = lib().orc_search(self._h, n, *[_ptr(a) for a in arrs], C.byref(prm),
-                              threads or os.cpu_count() or 1, _ptr(hits), _ptr(stats),
+                              threads or host_threads(), _ptr(hits), _ptr(stats),
                               _ptr(hist) if hist is not None else None)
         if rc != 0:
             raise ValueError("oracle rejected the spectra or search parameters")

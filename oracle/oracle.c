@@ -101,23 +101,23 @@ static uint32_t peptide_sites(const orc_db* db, const char* p, uint32_t len, int
     return n;
 }
 
-static void push_peptide(orc_db* db, peptide v) {
-    if (db->n_pep == db->cap_pep) {
-        db->cap_pep = db->cap_pep ? db->cap_pep * 2 : 1024;
-        db->pep = (peptide*)realloc(db->pep, db->cap_pep * sizeof(peptide));
-    }
-    db->pep[db->n_pep++] = v;
+/* Where enumerated entries go: counted only (out == NULL), or written at out[n]. */
+typedef struct { peptide* out; uint64_t n; } sink;
+
+static void push_peptide(sink* k, peptide v) {
+    if (k->out) k->out[k->n] = v;
+    ++k->n;
 }
 
 /* All site subsets of size <= max_mods (the 2^m variants of a sequence). */
-static void enumerate_variants(orc_db* db, const site* sites, uint32_t n_sites, uint32_t next,
+static void enumerate_variants(const orc_db* db, sink* k, const site* sites, uint32_t n_sites, uint32_t next,
                                uint32_t left, uint64_t mask, int64_t mass, peptide base) {
     base.mask = mask;
     base.mass = mass;
-    push_peptide(db, base);
+    push_peptide(k, base);
     if (left == 0) return;
     for (uint32_t i = next; i < n_sites; ++i)
-        enumerate_variants(db, sites, n_sites, i + 1, left - 1, mask | (1ull << i),
+        enumerate_variants(db, k, sites, n_sites, i + 1, left - 1, mask | (1ull << i),
                            mass + db->mod_delta[sites[i].mod], base);
 }
 
@@ -132,30 +132,13 @@ static int peptide_key_cmp(const void* a, const void* b) {
     return 0;
 }
 
-orc_db* orc_db_create(const char* residues, const uint64_t* prot_off, uint64_t n_prot,
-                      uint32_t missed, uint32_t min_len, uint32_t max_len,
-                      uint32_t n_mods, const uint32_t* mod_res_mask, const int32_t* mod_nterm,
-                      const int64_t* mod_delta, uint32_t max_mods) {
-    if (n_mods > ORC_MAX_MODS || min_len < 2 || max_len < min_len || max_len > 62) return NULL;
-    uint64_t total = prot_off[n_prot];
-    for (uint64_t i = 0; i < total; ++i)
-        if (residue_mass(residues[i]) < 0) return NULL;
-    orc_db* db = (orc_db*)calloc(1, sizeof(orc_db));
-    db->seq = (char*)malloc(total + 1);
-    memcpy(db->seq, residues, total);
-    db->off = (uint64_t*)malloc((n_prot + 1) * sizeof(uint64_t));
-    memcpy(db->off, prot_off, (n_prot + 1) * sizeof(uint64_t));
-    db->n_prot = n_prot;
-    db->n_mods = n_mods;
-    for (uint32_t m = 0; m < n_mods; ++m) {
-        db->mod_res_mask[m] = mod_res_mask[m];
-        db->mod_nterm[m] = mod_nterm[m];
-        db->mod_delta[m] = mod_delta[m];
-    }
+/* Every peptide of proteins [p0, p1) and its modified forms, into k. */
+static void digest_range(const orc_db* db, uint64_t p0, uint64_t p1, uint32_t missed, uint32_t min_len,
+                         uint32_t max_len, uint32_t max_mods, sink* k) {
     site sites[64];
-    for (uint64_t p = 0; p < n_prot; ++p) {
-        const char* s = db->seq + prot_off[p];
-        uint64_t n = prot_off[p + 1] - prot_off[p];
+    for (uint64_t p = p0; p < p1; ++p) {
+        const char* s = db->seq + db->off[p];
+        uint64_t n = db->off[p + 1] - db->off[p];
         for (uint64_t a = 0; a < n; ++a) {
             if (a != 0 && !cleaves_after(s, n, a - 1)) continue;   /* a must start a fragment */
             uint32_t missed_here = 0;
@@ -173,13 +156,137 @@ orc_db* orc_db_create(const char* residues, const uint64_t* prot_off, uint64_t n
                     base.start = (uint32_t)a;
                     base.len = (uint32_t)len;
                     uint32_t ns = peptide_sites(db, s + a, (uint32_t)len, a == 0, sites);
-                    enumerate_variants(db, sites, ns, 0, max_mods, 0, mass, base);
+                    enumerate_variants(db, k, sites, ns, 0, max_mods, 0, mass, base);
                 }
                 if (e < n && ++missed_here > missed) break;
             }
         }
     }
-    qsort(db->pep, db->n_pep, sizeof(peptide), peptide_key_cmp);
+}
+
+/* The database is built with several threads, which changes nothing in what it
+ * holds: each thread digests a range of proteins (a counting pass sizes the
+ * array, a second pass writes each range at its offset), and the entries are
+ * sorted by the key above -- which is unique per entry, so the order is the
+ * same for any correct sort -- in qsort-sorted chunks merged pairwise. */
+typedef struct {
+    const orc_db* db; uint64_t p0, p1; uint32_t missed, min_len, max_len, max_mods; sink k;
+} digest_job;
+
+static void* digest_worker(void* arg) {
+    digest_job* J = (digest_job*)arg;
+    digest_range(J->db, J->p0, J->p1, J->missed, J->min_len, J->max_len, J->max_mods, &J->k);
+    return NULL;
+}
+
+typedef struct { peptide* a; uint64_t n; } sort_job;
+
+static void* sort_worker(void* arg) {
+    sort_job* J = (sort_job*)arg;
+    qsort(J->a, J->n, sizeof(peptide), peptide_key_cmp);
+    return NULL;
+}
+
+typedef struct { const peptide* x; uint64_t nx; const peptide* y; uint64_t ny; peptide* out; } merge_job;
+
+static void* merge_worker(void* arg) {
+    merge_job* J = (merge_job*)arg;
+    uint64_t i = 0, j = 0, o = 0;
+    while (i < J->nx && j < J->ny) J->out[o++] = peptide_key_cmp(&J->y[j], &J->x[i]) < 0 ? J->y[j++] : J->x[i++];
+    while (i < J->nx) J->out[o++] = J->x[i++];
+    while (j < J->ny) J->out[o++] = J->y[j++];
+    return NULL;
+}
+
+/* Sorts db->pep (n entries) by the key with `threads` threads; returns 0, or -1
+ * when the merge buffer cannot be allocated. */
+static int sort_entries(orc_db* db, int threads) {
+    const uint64_t n = db->n_pep;
+    if (threads <= 1 || n < (1u << 16)) { qsort(db->pep, n, sizeof(peptide), peptide_key_cmp); return 0; }
+    uint64_t* cut = (uint64_t*)malloc(((size_t)threads + 1) * sizeof(uint64_t));
+    for (int t = 0; t <= threads; ++t) cut[t] = n * (uint64_t)t / (uint64_t)threads;
+    pthread_t* th = (pthread_t*)calloc((size_t)threads, sizeof(pthread_t));
+    sort_job* sj = (sort_job*)calloc((size_t)threads, sizeof(sort_job));
+    for (int t = 0; t < threads; ++t) {
+        sj[t].a = db->pep + cut[t]; sj[t].n = cut[t + 1] - cut[t];
+        pthread_create(&th[t], NULL, sort_worker, &sj[t]);
+    }
+    for (int t = 0; t < threads; ++t) pthread_join(th[t], NULL);
+    peptide* buf = (peptide*)malloc(n * sizeof(peptide));
+    if (!buf) { free(cut); free(th); free(sj); return -1; }
+    int runs = threads;
+    peptide* src = db->pep;
+    peptide* dst = buf;
+    merge_job* mj = (merge_job*)calloc((size_t)threads, sizeof(merge_job));
+    while (runs > 1) {
+        int m = 0;
+        for (int r = 0; r < runs; r += 2, ++m) {
+            mj[m].out = dst + cut[r];
+            mj[m].x = src + cut[r]; mj[m].nx = cut[r + 1] - cut[r];
+            if (r + 1 < runs) { mj[m].y = src + cut[r + 1]; mj[m].ny = cut[r + 2] - cut[r + 1]; }
+            else { mj[m].y = NULL; mj[m].ny = 0; }
+            pthread_create(&th[m], NULL, merge_worker, &mj[m]);
+        }
+        for (int t = 0; t < m; ++t) pthread_join(th[t], NULL);
+        int k = 0;
+        for (int r = 0; r < runs; r += 2) cut[k++] = cut[r];
+        cut[k] = n;
+        runs = k;
+        peptide* tmp = src; src = dst; dst = tmp;
+    }
+    if (src != db->pep) { memcpy(db->pep, src, n * sizeof(peptide)); }
+    free(buf); free(cut); free(th); free(sj); free(mj);
+    return 0;
+}
+
+orc_db* orc_db_create(const char* residues, const uint64_t* prot_off, uint64_t n_prot,
+                      uint32_t missed, uint32_t min_len, uint32_t max_len,
+                      uint32_t n_mods, const uint32_t* mod_res_mask, const int32_t* mod_nterm,
+                      const int64_t* mod_delta, uint32_t max_mods, int threads) {
+    if (n_mods > ORC_MAX_MODS || min_len < 2 || max_len < min_len || max_len > 62) return NULL;
+    uint64_t total = prot_off[n_prot];
+    for (uint64_t i = 0; i < total; ++i)
+        if (residue_mass(residues[i]) < 0) return NULL;
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    orc_db* db = (orc_db*)calloc(1, sizeof(orc_db));
+    db->seq = (char*)malloc(total + 1);
+    memcpy(db->seq, residues, total);
+    db->off = (uint64_t*)malloc((n_prot + 1) * sizeof(uint64_t));
+    memcpy(db->off, prot_off, (n_prot + 1) * sizeof(uint64_t));
+    db->n_prot = n_prot;
+    db->n_mods = n_mods;
+    for (uint32_t m = 0; m < n_mods; ++m) {
+        db->mod_res_mask[m] = mod_res_mask[m];
+        db->mod_nterm[m] = mod_nterm[m];
+        db->mod_delta[m] = mod_delta[m];
+    }
+    /* count, allocate, then write each thread's protein range at its offset */
+    digest_job* J = (digest_job*)calloc((size_t)threads, sizeof(digest_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)threads, sizeof(pthread_t));
+    for (int pass = 0; pass < 2; ++pass) {
+        uint64_t at = 0;
+        for (int t = 0; t < threads; ++t) {
+            J[t].db = db;
+            J[t].p0 = n_prot * (uint64_t)t / (uint64_t)threads;
+            J[t].p1 = n_prot * (uint64_t)(t + 1) / (uint64_t)threads;
+            J[t].missed = missed; J[t].min_len = min_len; J[t].max_len = max_len; J[t].max_mods = max_mods;
+            if (pass == 1) { J[t].k.out = db->pep + at; at += J[t].k.n; }
+            J[t].k.n = 0;
+            pthread_create(&th[t], NULL, digest_worker, &J[t]);
+        }
+        for (int t = 0; t < threads; ++t) pthread_join(th[t], NULL);
+        if (pass == 0) {
+            uint64_t n = 0;
+            for (int t = 0; t < threads; ++t) n += J[t].k.n;
+            db->pep = (peptide*)malloc((n ? n : 1) * sizeof(peptide));
+            db->n_pep = db->cap_pep = n;
+            if (!db->pep) { free(J); free(th); orc_db_free(db); return NULL; }
+        }
+    }
+    free(J);
+    free(th);
+    if (sort_entries(db, threads) != 0) { orc_db_free(db); return NULL; }
     return db;
 }
 
@@ -649,7 +756,12 @@ orc_db* orc_db_shard(const orc_db* src, uint32_t n_shards, uint32_t shard) {
     memcpy(db->mod_res_mask, src->mod_res_mask, sizeof db->mod_res_mask);
     memcpy(db->mod_nterm, src->mod_nterm, sizeof db->mod_nterm);
     memcpy(db->mod_delta, src->mod_delta, sizeof db->mod_delta);
-    for (uint64_t r = shard; r < src->n_pep; r += n_shards) push_peptide(db, src->pep[r]);
+    const uint64_t n = src->n_pep > shard ? (src->n_pep - shard + n_shards - 1) / n_shards : 0;
+    db->pep = (peptide*)malloc((n ? n : 1) * sizeof(peptide));
+    if (!db->pep) { orc_db_free(db); return NULL; }
+    sink k = {db->pep, 0};
+    for (uint64_t r = shard; r < src->n_pep; r += n_shards) push_peptide(&k, src->pep[r]);
+    db->n_pep = db->cap_pep = k.n;
     return db;
 }
 

@@ -42,11 +42,12 @@ typedef struct orc_db orc_db;
 /* Database: proteins concatenated in `residues` with offsets `prot_off[n+1]`.
  * Modification j: residues given by bit (letter-'A') of mod_res_mask[j], or the
  * protein N-terminus when mod_nterm[j] != 0; mass delta mod_delta[j] (uDa).
- * Returns NULL on invalid input. */
+ * `threads` worker threads digest and sort (the result does not depend on it).
+ * Returns NULL on invalid input or when memory runs out. */
 orc_db* orc_db_create(const char* residues, const uint64_t* prot_off, uint64_t n_prot,
                       uint32_t missed, uint32_t min_len, uint32_t max_len,
                       uint32_t n_mods, const uint32_t* mod_res_mask, const int32_t* mod_nterm,
-                      const int64_t* mod_delta, uint32_t max_mods);
+                      const int64_t* mod_delta, uint32_t max_mods, int threads);
 void     orc_db_free(orc_db*);
 uint64_t orc_db_size(const orc_db*);
 /* Peptide `id` (rank in the sorted key order): mass, protein, start, length, site mask. */
