@@ -342,4 +342,9 @@ def workload(name: str) -> Workload:
                         SpectraRecipe(n=1000000, charges=(2, 3), peak_count=(20, 200),
                                       mass_lognormal=(1800.0, 0.25), frag_charge2_for_z3=True),
                         False, 500_000_000, 1, 200)
+    if name == "node":          # 200k proteins, four modification types, <=3 mods: one node's share is a partition
+        return Workload("node", 200000, 2, 7, 40, [OXIDATION, PHOSPHO, ACETYL_NTERM, DEAMIDATION], 3,
+                        SpectraRecipe(n=5000000, charges=(2, 3, 4), peak_count=(20, 200),
+                                      mass_lognormal=(1800.0, 0.25), frag_charge2_for_z3=True),
+                        False, 500_000_000, 1, 200)
     raise KeyError(name)
