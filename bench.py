@@ -144,22 +144,25 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / best / 1e9
 
 
+KERNEL_SOURCE = {"k_scan_plain": "kernels.hip", "k_scan_persistent": "kernels.hip", "k_assemble": "stats.hip"}
+
+
 def measured_traffic(workload_name, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of this workload, valid only while the kernel source is the one the
-    counters were taken on."""
+    summary of this workload, valid only while the kernel's source file is the
+    one the counters were taken on."""
     path = os.path.join(ROOT, "profiles", f"scan_{workload_name}_hbm_counters.md")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
         return None
     vals = {}
     for line in open(path):
         if line.startswith("    ") and ":" in line:
             k, v = line.strip().split(":", 1)
             vals[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2102_02286_amd", "csrc", "kernels.hip")
-    now = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    src = KERNEL_SOURCE[kernel]
+    now = hashlib.sha256(open(os.path.join(ROOT, "paper_2102_02286_amd", "csrc", src), "rb").read()).hexdigest()
     key = f"traffic_bytes_per_launch {kernel}"
-    if vals.get("kernel_source_sha256") != now or key not in vals:
+    if vals.get(f"source_sha256 {src}") != now or key not in vals:
         return None
     return float(vals[key])
 
@@ -397,7 +400,7 @@ def serve(engine, capi, synth, ix, prm, pool_sp, load, capacity, n_requests, see
             "pool_bytes": int(st.pool_bytes), "peak_bytes": int(st.peak_bytes), "max_queue": int(st.max_queue)}
 
 
-def serving_leg(capi, engine, torch, synth, w, prot, ix, args):
+def serving_leg(capi, engine, torch, synth, w, prot, ix, args, plain_schedule):
     """Serving (continuous batching, admission by device memory) on the
     resident index with the serving recipe's spectra (charges 2-4).  Capacity
     is first measured with a saturating load; the Poisson loads are fractions
@@ -412,12 +415,13 @@ def serving_leg(capi, engine, torch, synth, w, prot, ix, args):
     capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(default)))
     best, _ = engine.autotune(ix, pool_sp.slice(0, 4096), prm)
     log(f"serving: persistent schedule tuned on 4096-spectrum requests: tile {best.tile}, "
-        f"{best.tiles_per_item} tiles per item, {best.groups_per_cu} groups per CU")
+        f"{best.group_threads or 256} threads per workgroup, {best.tiles_per_item} tiles per item, "
+        f"{best.groups_per_cu} groups per CU")
     # the plain batch on the same spectra, as one graph plan
     tens = device_spectra(pool_sp, torch)
     nnz = int(pool_sp.peak_off[-1])
     saved = capi.ps_schedule.from_buffer_copy(ix.schedule())
-    capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(default)))
+    capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(plain_schedule)))
     plan = engine.Plan(ix, prm_plain, n_cap=pool_sp.n, nnz_cap=nnz)
     fill_plan_inputs(plan, tens, torch)
     plan.run_device(pool_sp.n, nnz)
@@ -429,11 +433,13 @@ def serving_leg(capi, engine, torch, synth, w, prot, ix, args):
     plain_rate = 3 * pool_sp.n / (time.perf_counter() - t0)
     del plan, tens
     capi.check(capi.ps_index_set_schedule(ix.handle, C.byref(saved)))
-    log(f"serving recipe, plain graph over {pool_sp.n} spectra: {plain_rate:.0f} spectra/s")
+    log(f"serving recipe, plain graph over {pool_sp.n} spectra (the plain schedule of the headline): "
+        f"{plain_rate:.0f} spectra/s")
     out = {"recipe": f"{pool_sp.n} spectra of the large recipe with charges 2-4 (seed 2); requests are "
                      f"contiguous slices of 1-4096 spectra", "plain_batch_spectra_per_s": plain_rate,
-           "persistent_schedule": {"tile": best.tile, "tiles_per_item": best.tiles_per_item,
-                                   "groups_per_cu": best.groups_per_cu}, "loads": []}
+           "persistent_schedule": {"tile": best.tile, "group_threads": best.group_threads,
+                                   "tiles_per_item": best.tiles_per_item, "groups_per_cu": best.groups_per_cu},
+           "loads": []}
     sat = serve(engine, capi, synth, ix, prm, pool_sp, None, None, args.serving_sat_requests, 5,
                 args.serving_pool_gb << 30, args.serving_streams, args.serving_run)
     log(f"serving saturated: {sat['spectra_per_s']:.0f} spectra/s over {sat['requests']} requests "
@@ -726,7 +732,7 @@ def main():
 
     # ---- serving: continuous batching with admission by device memory
     if not args.no_serving:
-        out["serving"] = serving_leg(capi, engine, torch, synth, w, prot, ix, args)
+        out["serving"] = serving_leg(capi, engine, torch, synth, w, prot, ix, args, tuned.get("plain", default))
 
     # ---- one node's share of the largest database
     if not args.no_node_share:
