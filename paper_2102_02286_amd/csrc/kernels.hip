@@ -61,17 +61,21 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
     return r;
 }
 
-// Packed shared-peak counters.  Narrow: [n_y:8 | n_b:8 | S:16] in 32 bits;
-// wide: [n_b:16 | n_y:16 | S:32] in 64 bits.  The prep kernel proves per
-// spectrum that no field can overflow before choosing the narrow form.
+// Packed shared-peak counters.  Narrow: [n_b + n_y : 9 | n_y : 8 | S : 15] in
+// 32 bits, so that a candidate has at least k shared peaks exactly when its
+// counter is at least k << 23 (one unsigned compare in the filter); wide:
+// [n_b:16 | n_y:16 | S:32] in 64 bits.  The prep kernel proves per spectrum
+// that no field can overflow before choosing the narrow form.  key(c) is
+// monotone in n_b + n_y and key_min(k) its threshold for k shared peaks.
 template <typename C> struct Cnt;
 template <> struct Cnt<uint32_t> {
-    __device__ static uint32_t inc(uint32_t is_y, uint32_t q) { return (is_y ? (1u << 24) : (1u << 16)) + q; }
-    __device__ static uint32_t nb(uint32_t c) { return (c >> 16) & 0xFFu; }
-    __device__ static uint32_t ny(uint32_t c) { return c >> 24; }
-    __device__ static uint32_t s(uint32_t c) { return c & 0xFFFFu; }
-    // n_b + n_y: one byte dot product with weights (1, 1, 0, 0) on the two high bytes
-    __device__ static uint32_t shared(uint32_t c) { return __builtin_amdgcn_udot4(c, 0x01010000u, 0u, false); }
+    __device__ static uint32_t inc(uint32_t is_y, uint32_t q) { return (1u << 23) + (is_y << 15) + q; }
+    __device__ static uint32_t ny(uint32_t c) { return (c >> 15) & 0xFFu; }
+    __device__ static uint32_t nb(uint32_t c) { return (c >> 23) - ny(c); }
+    __device__ static uint32_t s(uint32_t c) { return c & 0x7FFFu; }
+    __device__ static uint32_t key(uint32_t c) { return c; }
+    // n_b + n_y <= 510: a threshold of 512 or more is never reached
+    __device__ static uint32_t key_min(uint32_t k) { return k < 512u ? k << 23 : 0xFFFFFFFFu; }
 };
 template <> struct Cnt<unsigned long long> {
     __device__ static unsigned long long inc(uint32_t is_y, uint32_t q) {
@@ -80,7 +84,8 @@ template <> struct Cnt<unsigned long long> {
     __device__ static uint32_t nb(unsigned long long c) { return (uint32_t)(c >> 48); }
     __device__ static uint32_t ny(unsigned long long c) { return (uint32_t)(c >> 32) & 0xFFFFu; }
     __device__ static uint32_t s(unsigned long long c) { return (uint32_t)c; }
-    __device__ static uint32_t shared(unsigned long long c) { return nb(c) + ny(c); }
+    __device__ static uint32_t key(unsigned long long c) { return nb(c) + ny(c); }
+    __device__ static uint32_t key_min(uint32_t k) { return k; }
 };
 
 // Top-k of one wavefront, distributed over its lanes: lane j < k holds the
@@ -392,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
                     if (by_len < nbmax) nbmax = by_len;
                     uint64_t smax = sq * (uint64_t)A.ix.ion_series * kpe;
                     if (200ull * nbmax < smax) smax = 200ull * nbmax;
-                    if (!(nbmax <= 255 && smax <= 65535)) {
+                    if (!(nbmax <= 255 && smax <= 32767)) {
                         inf.flags |= kFlagWide;
                         if (!(nbmax < kLfSize && smax < kLsSize)) inf.flags |= kFlagOverflow;
                         atomicAdd(&A.w.counters[(inf.flags & kFlagOverflow) ? kCtrOverflow : kCtrWide], 1ull);
@@ -634,11 +639,15 @@ __device__ __forceinline__ void map_slot(const ScanLds<C, NT>& L, uint32_t k, ui
     for (uint32_t r = (lo - c0 + 63u) >> 6; (r << 6) < hi - c0; ++r) L.mrank[r] = k;
 }
 
-// Gather state of one wavefront in the current chunk: its share [next, fe)
-// of the chunk's flat quad positions, and up to kRounds x 64 quads of
-// postings already loaded.
+// Gather state of one wavefront in the current chunk [c0, fe) of flat quad
+// positions.  The chunk is dealt out in batches of kRounds x 64 positions,
+// batch j to wavefront j mod (NT / 64), so a tile with few postings occupies
+// few wavefronts and none of them runs an empty batch; `next` is the start
+// of this wavefront's next batch.  `live` says whether the batch in flight
+// holds any position (wave-uniform), and p / mq hold its loaded postings.
 struct Gather {
     uint32_t c0, fe, next;             // quad positions
+    uint32_t live;
     uint4 p[kRounds];
     uint32_t mq[(kRounds + 1) / 2];    // round r in half r % 2: elements of the run (bits 0-3) | q << 4
 };
@@ -656,6 +665,8 @@ __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C
     const unsigned long long below = (2ull << lane) - 2ull;   // positions 1..lane of a round
 #pragma unroll
     for (uint32_t r = 0; r < (kRounds + 1) / 2; ++r) g.mq[r] = 0;
+    g.live = g.next < g.fe;
+    if (!g.live) return;                               // wave-uniform: no batch left for this wavefront
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t f = g.next + 64u * r + lane;
@@ -673,11 +684,12 @@ __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C
         const uint32_t m4 = valid ? (0xFu << lead) & (0xFu >> (4u - keep)) : 0u;
         g.mq[r / 2] |= (m4 | (sb.qx & 0xFFu) << 4) << (16u * (r % 2u));
     }
-    g.next += 64u * kRounds;
+    g.next += NT * kRounds;                            // this wavefront's next batch
 }
 
 template <typename C, uint32_t NT>
 __device__ __forceinline__ void gather_consume(const ScanLds<C, NT>& L, const Gather& g, uint32_t tsh) {
+    if (!g.live) return;                               // wave-uniform
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t w = g.mq[r / 2] >> (16u * (r % 2u));
@@ -807,7 +819,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     WaveTopK<C> top{sh.wh[wave], sh.wid[wave], sh.wc[wave]};
     top.init(kp.top_k);
     const uint32_t kk = kp.top_k;
-    const uint32_t kmin = kp.min_shared;
+    const uint32_t kkey = Cnt<C>::key_min(kp.min_shared);   // filter threshold on counter keys
     uint32_t scored = 0;
     Gather g;
     uint32_t ptot = 0;
@@ -816,14 +828,12 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     // this wavefront's first gather batch
     uint32_t nne = 0;                                   // slots with postings in the prepared tile
 
-    // this wavefront's share of the chunk [c0, c0 + kMapCap) of a tile with
-    // `total` flat positions
+    // the chunk [c0, c0 + kMapCap) of a tile with `total` flat positions, and
+    // this wavefront's first batch in it
     auto share = [&](uint32_t c0, uint32_t total) {
-        const uint32_t n = min(kMapCap, total - c0);
-        const uint32_t per = ((n + NT - 1) / NT) * 64u;
         g.c0 = c0;
-        g.next = c0 + min(n, wave * per);
-        g.fe = c0 + min(n, wave * per + per);
+        g.fe = c0 + min(kMapCap, total - c0);
+        g.next = c0 + wave * (64u * kRounds);
     };
 
     // ranks, flat ranges and the map of the first chunk of the tile whose
@@ -935,12 +945,12 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
             const uint32_t nvec = kp.tile / kPer;
             uint4* cv = (uint4*)L.cnt;
             // nvec is a multiple of 4 NT: four steps per pass, at fixed offsets
-            for (uint32_t base0 = wave * 64u; base0 < nvec; base0 += 4u * NT)
+            for (uint32_t base0 = wave * 64u; base0 < nvec; base0 += 4u * NT) {
+                uint4* cp = cv + base0 + lane;
 #pragma unroll
-            for (uint32_t base = base0; base < base0 + 4u * NT; base += NT) {
-                const uint32_t i = base + lane;
-                const uint4 v = cv[i];
-                cv[i] = make_uint4(0u, 0u, 0u, 0u);
+            for (uint32_t step = 0; step < 4u; ++step) {
+                const uint4 v = cp[step * NT];
+                cp[step * NT] = make_uint4(0u, 0u, 0u, 0u);
                 C c[kPer];
                 if constexpr (kPer == 4) {
                     c[0] = (C)v.x; c[1] = (C)v.y; c[2] = (C)v.z; c[3] = (C)v.w;
@@ -949,14 +959,15 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
                     c[1] = (C)(((unsigned long long)v.w << 32) | v.z);
                 }
                 // most counter groups hold no candidate: one test for the group first
-                uint32_t sh4[kPer];
+                uint32_t key[kPer];
                 uint32_t top = 0;
 #pragma unroll
-                for (uint32_t e = 0; e < kPer; ++e) { sh4[e] = Cnt<C>::shared(c[e]); top = max(top, sh4[e]); }
-                if (__ballot(top >= kmin) == 0ull) continue;   // wave-uniform
+                for (uint32_t e = 0; e < kPer; ++e) { key[e] = Cnt<C>::key(c[e]); top = max(top, key[e]); }
+                if (__ballot(top >= kkey) == 0ull) continue;   // wave-uniform
+                const uint32_t i = base0 + step * NT + lane;
 #pragma unroll
                 for (uint32_t e = 0; e < kPer; ++e) {
-                    const bool pass = sh4[e] >= kmin;
+                    const bool pass = key[e] >= kkey;
                     const unsigned long long msk = __ballot(pass);
                     if (msk == 0) continue;             // wave-uniform
                     if (wn > kWaveCand - 64u) score_buffer();   // room for a whole wavefront
@@ -968,6 +979,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
                     }
                     wn += (uint32_t)__popcll(msk);
                 }
+            }
             }
             if (wn >= 64u) score_buffer();
         }
