@@ -937,6 +937,23 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
         // registers reused below never wait for the loads issued next.
         __builtin_amdgcn_s_waitcnt(kWaitVmem0);
         __syncthreads();
+        if (t < t_last) {
+            // Slots move to tile t + 1 (the quad for the next tile's boundary is
+            // requested when it differs from the one just used), and tile t + 1
+            // is mapped and its first posting batch issued before tile t is
+            // filtered, so the filter hides the load latency.  The map is free:
+            // every wavefront is past the barrier above.
+            const bool fetch = t + 3 <= t_last && needs_dir(t + 3) && (((t + 4) * m) >> 2) != (idx >> 2);
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                o_cur[u] = o_end[u];
+                o_end[u] = o_nxt[u];
+                o_nxt[u] = nxt2[u];
+                const uint32_t j = tid * us + u;
+                if (fetch && u < us && j < nact) o_quad[u] = quad_at(o_bq[u] & 0xFFFFFFu, (t + 4) * m);
+            }
+            prepare();
+        }
         // candidate filter: counters are read and cleared four (narrow) or two
         // (wide) at a time; candidates with at least k_min shared peaks are
         // buffered for scoring
@@ -983,20 +1000,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
             }
             if (wn >= 64u) score_buffer();
         }
-        if (t < t_last) {
-            // slots move to tile t + 1, and the quad for the next tile's boundary
-            // is requested when it differs from the one just used
-            const bool fetch = t + 3 <= t_last && needs_dir(t + 3) && (((t + 4) * m) >> 2) != (idx >> 2);
-#pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                o_cur[u] = o_end[u];
-                o_end[u] = o_nxt[u];
-                o_nxt[u] = nxt2[u];
-                const uint32_t j = tid * us + u;
-                if (fetch && u < us && j < nact) o_quad[u] = quad_at(o_bq[u] & 0xFFFFFFu, (t + 4) * m);
-            }
-            prepare();
-        }
+        if (t < t_last) __syncthreads();               // counters clear before tile t + 1 is consumed
     }
 
     score_buffer();                                     // what is left of the item's candidates
