@@ -610,15 +610,25 @@ __device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsign
     const uint32_t ntot = __shfl(incl, 63, 64);
     if (lane == 0) wsum[wave] = ((unsigned long long)et << 32) | ntot;
     __syncthreads();
-    uint32_t nb = 0, eb = 0, na = 0, ea = 0;
-    for (uint32_t w = 0; w < NT / 64; ++w) {
-        const unsigned long long v = wsum[w];
-        const uint32_t vn = (uint32_t)v, ve = (uint32_t)(v >> 32);
-        nb += w < wave ? vn : 0u;
-        eb += w < wave ? ve : 0u;
-        na += vn;
-        ea += ve;
+    // lane w < NT / 64 takes wavefront w's totals; inclusive sums over those
+    // lanes (inside the first 16-lane DPP row) give every wavefront its
+    // offsets and the totals by lane reads
+    const unsigned long long wv = lane < NT / 64 ? wsum[lane] : 0ull;
+    uint32_t xn = (uint32_t)wv, xe = (uint32_t)(wv >> 32), t;
+    static_assert(NT / 64 <= 8, "one DPP row holds the wavefront totals");
+    // row_shr:1, 2, 4 (DPP controls 0x111, 0x112, 0x114)
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)xn, 0x111, 0xF, 0xF, false); if ((lane & 15u) >= 1u) xn += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)xe, 0x111, 0xF, 0xF, false); if ((lane & 15u) >= 1u) xe += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)xn, 0x112, 0xF, 0xF, false); if ((lane & 15u) >= 2u) xn += t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)xe, 0x112, 0xF, 0xF, false); if ((lane & 15u) >= 2u) xe += t;
+    if constexpr (NT / 64 > 4) {
+        t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)xn, 0x114, 0xF, 0xF, false); if ((lane & 15u) >= 4u) xn += t;
+        t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)xe, 0x114, 0xF, 0xF, false); if ((lane & 15u) >= 4u) xe += t;
     }
+    const uint32_t na = (uint32_t)__builtin_amdgcn_readlane((int)xn, NT / 64 - 1);
+    const uint32_t ea = (uint32_t)__builtin_amdgcn_readlane((int)xe, NT / 64 - 1);
+    const uint32_t nb = wave ? (uint32_t)__builtin_amdgcn_readlane((int)xn, (int)wave - 1) : 0u;
+    const uint32_t eb = wave ? (uint32_t)__builtin_amdgcn_readlane((int)xe, (int)wave - 1) : 0u;
     *n_ex = nb + incl - n;
     *e_ex = eb + ex;
     *n_all = na;
@@ -659,14 +669,19 @@ struct Gather {
 // start bit is set and the last when the next position's is (the bit past
 // the chunk, or the end marker after the last slot): only there do postings
 // outside the run share the quad.
-template <typename C, uint32_t NT>
+//
+// Every lane issues its loads (a lane past the chunk reads quad 0 and keeps
+// no element of it), so a batch is always kRounds loads in straight-line code
+// and the compiler can wait for an older batch while a newer one is in flight.
+// LIVE: the caller knows the wavefront has a batch left.
+template <typename C, uint32_t NT, bool LIVE = false>
 __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C, NT>& L, Gather& g) {
     const uint32_t lane = threadIdx.x & 63u;
     const unsigned long long below = (2ull << lane) - 2ull;   // positions 1..lane of a round
 #pragma unroll
     for (uint32_t r = 0; r < (kRounds + 1) / 2; ++r) g.mq[r] = 0;
-    g.live = g.next < g.fe;
-    if (!g.live) return;                               // wave-uniform: no batch left for this wavefront
+    g.live = LIVE || g.next < g.fe;
+    if (!LIVE && !g.live) return;                      // wave-uniform: no batch left for this wavefront
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t f = g.next + 64u * r + lane;
@@ -676,7 +691,7 @@ __device__ __forceinline__ void gather_issue(const DevIndex& ix, const ScanLds<C
         const unsigned long long after = L.mbits[R + 1];
         const uint32_t k = L.mrank[R] + (uint32_t)__popcll(bits & below);
         const SegBase sb = L.sbase[valid ? k : 0u];
-        g.p[r] = valid ? ((const uint4*)ix.post)[sb.base + f] : make_uint4(0u, 0u, 0u, 0u);
+        g.p[r] = ((const uint4*)ix.post)[valid ? sb.base + f : 0u];
         const bool first = (bits >> lane) & 1ull;
         const bool last = (lane < 63u ? (bits >> (lane + 1u)) : after) & 1ull;
         const uint32_t lead = first ? (sb.qx >> 8) & 3u : 0u;
@@ -874,6 +889,19 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
         gather_issue<C, NT>(ix, L, g);
     };
 
+    // Consume the batch in g, and any further batches of this wavefront in
+    // the chunk: each is requested before the one before it is consumed, so
+    // its loads are in flight meanwhile.
+    auto drain = [&]() {
+        while (g.next < g.fe) {
+            Gather h = g;
+            gather_issue<C, NT, true>(ix, L, h);
+            gather_consume<C, NT>(L, g, tsh);
+            g = h;
+        }
+        gather_consume<C, NT>(L, g, tsh);
+    };
+
     if (nact > 0) {
         for (uint32_t i = tid; i < kp.tile; i += NT) L.cnt[i] = (C)0;
         prepare();
@@ -902,11 +930,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
         const uint32_t tb = t << tsh;
         // counters of tile t: the batch loaded last, then any further batches,
         // then any further chunks
-        gather_consume<C, NT>(L, g, tsh);
-        while (g.next < g.fe) {
-            gather_issue<C, NT>(ix, L, g);
-            gather_consume<C, NT>(L, g, tsh);
-        }
+        drain();
         const uint32_t p_t = ptot;
         for (uint32_t c0 = kMapCap; c0 < p_t; c0 += kMapCap) {
             __syncthreads();                            // every wavefront is done with the last map
@@ -917,10 +941,8 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
             if (tid == 0 && p_t - c0 <= kMapCap) atomicOr(&L.mbits[(p_t - c0) >> 6], 1ull << ((p_t - c0) & 63u));
             __syncthreads();
             share(c0, p_t);
-            while (g.next < g.fe) {
-                gather_issue<C, NT>(ix, L, g);
-                gather_consume<C, NT>(L, g, tsh);
-            }
+            gather_issue<C, NT>(ix, L, g);
+            drain();
         }
         // end of tile t + 2 from the quad holding directory entry (t + 3) m
         const bool use = t + 2 <= t_last && needs_dir(t + 2);
