@@ -594,21 +594,25 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
 
 // Exclusive prefix sums over the workgroup (thread order) of a count n and of a
 // small number e <= U, with their totals.  One barrier; `wsum` must be free.
+// A wavefront that is not `active` (wave-uniform) has n = e = 0 in every
+// lane and skips its own scan: its wsum entry must already hold 0.
 template <uint32_t U, uint32_t NT>
-__device__ __forceinline__ void block_scan_counts(uint32_t n, uint32_t e, unsigned long long* wsum, uint32_t* n_ex,
-                                                  uint32_t* e_ex, uint32_t* n_all, uint32_t* e_all) {
+__device__ __forceinline__ void block_scan_counts(bool active, uint32_t n, uint32_t e, unsigned long long* wsum,
+                                                  uint32_t* n_ex, uint32_t* e_ex, uint32_t* n_all, uint32_t* e_all) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar selects below
-    const uint32_t incl = wave_inclusive_sum(n);
-    uint32_t ex = 0, et = 0;
+    uint32_t incl = 0, ex = 0, et = 0;
+    if (active) {
+        incl = wave_inclusive_sum(n);
 #pragma unroll
-    for (uint32_t b = 0; (1u << b) <= U; ++b) {        // e bit by bit: ballot + mbcnt
-        const unsigned long long m = __ballot((e >> b) & 1u);
-        ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
-        et += (uint32_t)__popcll(m) << b;
+        for (uint32_t b = 0; (1u << b) <= U; ++b) {    // e bit by bit: ballot + mbcnt
+            const unsigned long long m = __ballot((e >> b) & 1u);
+            ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+            et += (uint32_t)__popcll(m) << b;
+        }
+        const uint32_t ntot = __shfl(incl, 63, 64);
+        if (lane == 0) wsum[wave] = ((unsigned long long)et << 32) | ntot;
     }
-    const uint32_t ntot = __shfl(incl, 63, 64);
-    if (lane == 0) wsum[wave] = ((unsigned long long)et << 32) | ntot;
     __syncthreads();
     // lane w < NT / 64 takes wavefront w's totals; inclusive sums over those
     // lanes (inside the first 16-lane DPP row) give every wavefront its
@@ -805,6 +809,9 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     const uint32_t nact = sh.nact;
     // slots [tid * us, tid * us + us) belong to this thread
     const uint32_t us = nact > NT ? (nact + NT - 1) / NT : 1u;
+    // wavefronts holding no slot skip the per-tile scan; their totals are 0
+    const bool owner = wave * 64u * us < nact;
+    if (!owner && lane == 0) sh.wsum[wave] = 0ull;
     // Each slot also holds the aligned quad of its directory row that contains
     // the entry for the end of tile t + 2 (needed when moving to tile t + 1):
     // a quad serves four tiles (one tile = m entries), and the next quad is
@@ -865,7 +872,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
             mine_ne += n != 0u;
         }
         uint32_t run, rank, total_n, total_ne;
-        block_scan_counts<U, NT>(mine, mine_ne, sh.wsum, &run, &rank, &total_n, &total_ne);
+        block_scan_counts<U, NT>(owner, mine, mine_ne, sh.wsum, &run, &rank, &total_n, &total_ne);
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
             const uint32_t n = quads(o_cur[u], o_end[u]);
