@@ -11,8 +11,8 @@
  *   score histogram  ->  smoothed survival function, tail fit, expect value.
  *
  * Every step after the index build runs in HIP kernels on one gfx950 GPU.
- * The index is built on the host (Superstep 1, Supplementary Algorithm 1) and
- * then lives in device memory the caller provides.
+ * The index is built on the host or on the GPU (Superstep 1, Supplementary
+ * Algorithm 1) and then lives in device memory the caller provides.
  *
  * Conventions (all entry points):
  *   - Return codes: PS_OK (0) or one of PS_E*.  Nothing throws across the ABI.
@@ -20,9 +20,10 @@
  *   - Masses are integer micro-Dalton (uDa, 1e-6 Da) unless a name says
  *     otherwise.  Fragment bins are 0.01 Da (10000 uDa) wide, rounded half up:
  *     bin(m) = floor((m + 5000) / 10000).
- *   - Device memory: the library never allocates device memory.  Every device
- *     buffer lives inside a caller-provided block (ps_device.base/bytes); the
- *     caller keeps it alive while any object built in it is in use.
+ *   - Device memory: the library allocates no device memory, except the one
+ *     static work area of ps_search_static.  Every other device buffer lives
+ *     inside a caller-provided block (ps_device.base/bytes); the caller keeps
+ *     it alive while any object built in it is in use.
  *   - Streams: work is enqueued on ps_device.stream (a hipStream_t, NULL = the
  *     null stream).  Calls are asynchronous unless a comment says "blocks".
  *   - Thread safety: an index is immutable after build and may be shared by
@@ -299,27 +300,38 @@ void ps_index_free(ps_index* idx);
 /* ---- one batch --------------------------------------------------------- */
 
 /* Device bytes a batch of n spectra with nnz peaks needs in its workspace,
- * including a copy of the inputs. */
+ * including a copy of the inputs (the buffers of Superstep 3's search and
+ * Superstep 4's per-spectrum statistics). */
 int ps_workspace_bytes(const ps_index* idx, uint64_t n, uint64_t nnz, const ps_search_params* params,
                        uint64_t* bytes);
 
-/* Search host spectra.  Validates them (PS_EINVAL on any invalid spectrum or
- * parameter), copies them into `work` (which must hold ps_workspace_bytes) and
- * enqueues the whole search on work->stream; returns without waiting. */
+/* Search host spectra: the partial database search of Superstep 3
+ * (Supplementary Algorithm 3: pre-processing, precursor window, fragment-bin
+ * postings, shared peaks, hyperscore, top-k, score histogram) followed by the
+ * expect value of Superstep 4 (Supplementary Algorithm 4).  Validates the
+ * spectra (PS_EINVAL on any invalid spectrum or parameter), copies them into
+ * `work` (which must hold ps_workspace_bytes) and enqueues the whole search
+ * on work->stream; returns without waiting. */
 int ps_search_batch(ps_index* idx, const ps_device* work, const ps_spectra* spectra,
                     const ps_search_params* params, ps_batch** out);
 
-/* Search spectra already in device memory (every pointer of `spectra` is a
- * device pointer).  Invalid spectra are reported per spectrum
+/* The same search (Superstep 3 and Superstep 4's statistics) over spectra
+ * already in device memory (every pointer of `spectra` is a device pointer),
+ * as the GPU analogue of the paper's pre-loaded spectrum batches (Superstep 3,
+ * Buffering).  Invalid spectra are reported per spectrum
  * (PS_STATUS_INVALID) instead of rejected.  Enqueues on work->stream and
  * returns without waiting; the inputs must stay valid until ps_results. */
 int ps_search_device(ps_index* idx, const ps_device* work, const ps_spectra* spectra,
                      uint64_t nnz, const ps_search_params* params, ps_batch** out);
 
-/* Blocks until the batch is done, then writes hits[n * top_k], stats[n] and,
- * when the batch was made with want_hist, hist[n * 512] (hist may be NULL).
- * Returns PS_EOVERFLOW if any spectrum has PS_STATUS_OVERFLOW (results for the
- * other spectra are still written). */
+/* The per-spectrum results of Superstep 4: the best matches with their shared
+ * peaks, intensity sums and hyperscores, the number of candidates scored, the
+ * expect value of the top match and, optionally, the score histogram behind it
+ * (2048 bytes per spectrum, the size the Sampling section gives).  Blocks until
+ * the batch is done, then writes hits[n * top_k], stats[n] and, when the batch
+ * was made with want_hist, hist[n * 512] (hist may be NULL).  Returns
+ * PS_EOVERFLOW if any spectrum has PS_STATUS_OVERFLOW (results for the other
+ * spectra are still written). */
 int ps_results(ps_batch* batch, ps_hit* hits, ps_stat* stats, int32_t* hist);
 
 /* Device pointers of the batch's results inside its workspace, laid out as
