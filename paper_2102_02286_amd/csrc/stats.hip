@@ -172,8 +172,8 @@ __device__ uint32_t wave_top_k(uint32_t L, uint32_t k, Key key) {
 // OVERFLOW or NO_HITS; only OK is refined (to FEW_POINTS or BAD_SLOPE), and arg
 // is NaN unless the status stays OK.  Every lane of the wavefront calls it; the
 // results are the same in every lane.  `tl` is this wavefront's LDS area of
-// 8 x 64 survival sums (bin 8 l + i at tl[64 i + l]), so the fit's loop over a
-// lane's bins can stay rolled.
+// 8 x 64 survival sums (bin 8 l + i at tl[64 i + l]), from which the fit range
+// is dealt out to consecutive lanes.
 __device__ void fit_wave(const int32_t h[8], unsigned long long N, double h1, int fit, int& status, double& arg,
                          long long* tl) {
     static_assert(kHistBins == 8 * 64, "eight histogram bins per lane");
@@ -252,15 +252,19 @@ __device__ void fit_wave(const int32_t h[8], unsigned long long N, double h1, in
             tail += num[i];
             tl[64 * i + lane] = tail;
         }
-#pragma unroll 1
-        for (int i = 7; i >= 0; --i) {                 // one log10 live at a time
-            const long long tail = tl[64 * i + lane];
-            const int j = 8 * (int)lane + i;
-            if (j < mode || j > jh - 1 || tail <= 0) continue;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // every lane's sums are visible to the wave
+        // the fit range [mode, jh - 1] dealt out to consecutive lanes, so each
+        // log10 is taken by as many lanes as there are bins left to fit
+        for (int j = mode + (int)lane; j <= jh - 1; j += 64) {
+            const long long tj = tl[64 * (j & 7) + (j >> 3)];
+            if (tj <= 0) continue;
             const double xj = 0.1 * (double)j;
-            const double yj = log10((double)tail / (double)total);
+            const double yj = log10((double)tj / (double)total);
             sx += xj; sy += yj; sxx += xj * xj; sxy += xj * yj; cnt += 1.0;
         }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // reads done before the area is written again
     }
     sx = wave_sum_f64(sx);
     sy = wave_sum_f64(sy);
@@ -372,6 +376,7 @@ struct AssembleArgs {
     ps_part parts[PS_MAX_SHARDS];
     uint32_t G, K;
     int32_t fit;
+    uint32_t all_hist;   // every partition gives a full histogram
     uint64_t n;
     ps_hit* hits;
     ps_stat* stats;
@@ -399,7 +404,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         // histogram addition: full partition histograms share bin 0 and add one to
         // one; a sampled one is shifted to its window [lo, lo + 120) first
         int32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (uint32_t g = 0; g < G; ++g) {
+        if (A.all_hist) {
+            // four partitions' bins requested together (a group past G repeats
+            // partition G - 1 and adds nothing)
+            for (uint32_t g0 = 0; g0 < G; g0 += 4) {
+                int32_t v[4][8];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u)
+                    load_bins(A.parts[min(g0 + u, G - 1)].hist + s * (uint64_t)kHistBins, v[u]);
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) h[i] += g0 + u < G ? v[u][i] : 0;
+            }
+        } else for (uint32_t g = 0; g < G; ++g) {
             if (A.parts[g].hist) {
                 int32_t v[8];
                 load_bins(A.parts[g].hist + s * (uint64_t)kHistBins, v);
@@ -446,7 +464,11 @@ hipError_t launch_assemble(const ps_part* parts, uint32_t G, uint64_t n, uint32_
     if (n == 0) return hipSuccess;
     AssembleArgs a;
     memset(&a, 0, sizeof a);
-    for (uint32_t g = 0; g < G; ++g) a.parts[g] = parts[g];
+    a.all_hist = 1;
+    for (uint32_t g = 0; g < G; ++g) {
+        a.parts[g] = parts[g];
+        if (!parts[g].hist) a.all_hist = 0;
+    }
     a.G = G; a.K = K; a.fit = fit; a.n = n; a.hits = hits; a.stats = stats; a.hist = hist;
     const uint64_t blocks = (n + kStatWaves - 1) / kStatWaves;
     const uint32_t grid = (uint32_t)(blocks < (1u << 20) ? blocks : (1u << 20));
