@@ -715,13 +715,15 @@ __device__ __forceinline__ void gather_consume(const ScanLds<C, NT>& L, const Ga
         if (w & 0xFu) {
             const uint32_t q = (w >> 4) & 0xFFu;
             const uint32_t e4[4] = {g.p[r].x, g.p[r].y, g.p[r].z, g.p[r].w};
+            // Every element is added without a branch: one outside the run (a
+            // neighbouring run's posting or list padding in the same quad) adds 0
+            // to the counter its bits select.  Tiles are aligned to their size:
+            // the counter is the id modulo the tile.
 #pragma unroll
             for (uint32_t e = 0; e < 4; ++e) {
-                if ((w >> e) & 1u) {
-                    // tiles are aligned to their size: the counter is the id modulo the tile
-                    const uint32_t p = e4[e];
-                    atomicAdd(&L.cnt[__builtin_amdgcn_ubfe(p, 1u, tsh)], Cnt<C>::inc(p & 1u, q));
-                }
+                const uint32_t p = e4[e];
+                const C keep = (C)0 - (C)((w >> e) & 1u);          // all ones inside the run
+                atomicAdd(&L.cnt[__builtin_amdgcn_ubfe(p, 1u, tsh)], Cnt<C>::inc(p & 1u, q) & keep);
             }
         }
     }
