@@ -241,13 +241,16 @@ int ps_index_shape(const ps_index* idx, uint64_t* n_peptides, uint64_t* n_postin
  * one peptide's postings), then the tile directory.  More than one chunk costs
  * a second pass over the pairs but bounds the scratch memory.  The result is identical
  * to ps_index_create + ps_index_upload (every array bit for bit), already on the
- * device.  Its postings and directory stay on the device; ps_index_host_arrays
- * and ps_index_directory copy them back on request.
+ * device.  Its postings, directory and entry table stay on the device (the host
+ * keeps the proteins and the bin offsets): ps_index_host_arrays,
+ * ps_index_directory, ps_index_entry, ps_index_entries and ps_peptide copy what
+ * they need back on request, blocking.
  *
  * ps_index_build_device_bytes: device bytes of the index block (kept for the
- * index's lifetime; postings sized to an upper bound that is exact for a whole
- * database and, for a partition, its entries times the longest peptide's
- * postings) and of the scratch block (only during the build).  Needs a device
+ * index's lifetime: masses, entry table, postings sized to an upper bound that
+ * is exact for a whole database and, for a partition, its entries times the
+ * longest peptide's postings, directory) and of the scratch block (only during
+ * the build).  Needs a device
  * (it sizes the library sorts' workspace).
  * ps_index_build_device: builds into `index_block` (256-byte aligned) using
  * `scratch`; blocks until done, on index_block->stream.  Errors as

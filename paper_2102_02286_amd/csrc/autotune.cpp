@@ -32,7 +32,7 @@ namespace {
 
 std::string cache_key(const ps_index* ix, const ps_search_params* p) {
     std::ostringstream k;
-    k << "D" << ix->mass.size() << "_N" << n_postings(ix) << "_ppm" << p->window_is_ppm << "_w" << p->window
+    k << "D" << ix->n_entries << "_N" << n_postings(ix) << "_ppm" << p->window_is_ppm << "_w" << p->window
       << "_T" << p->frag_tol_bins << "_B" << p->top_peaks << "_k" << p->top_k << "_z" << p->max_charge << "_s"
       << p->schedule;
     return k.str();

@@ -471,7 +471,7 @@ struct Scratch {
     char* seq; uint64_t* prot_off; uint32_t* st_prot; uint32_t* st_pos; uint64_t* st_off;
     int64_t* g_mass; uint32_t* g_prot; uint32_t* g_start; uint8_t* g_len; uint64_t* g_mask;
     uint64_t* key0; uint64_t* key1; uint32_t* idx0; uint32_t* idx1;
-    uint32_t* l_prot; uint32_t* l_start; uint8_t* l_len; uint64_t* l_mask;
+    uint32_t* l_prot; uint32_t* l_start; uint8_t* l_len; uint64_t* l_mask;   // in the index block
     uint64_t* pair_cnt; uint64_t* pair_off;
     unsigned long long* bin_cnt; uint32_t* bin_q; unsigned long long* cursor; uint32_t* run_start; uint32_t* run_end;
     uint32_t* pk0; uint32_t* pk1; uint32_t* pv0; uint32_t* pv1;
@@ -501,10 +501,6 @@ Scratch layout_scratch(char* base, const ps_index* ix, const Census& C, uint64_t
     S.key1 = (uint64_t*)take(Da * 8);
     S.idx0 = (uint32_t*)take(Da * 4);
     S.idx1 = (uint32_t*)take(Da * 4);
-    S.l_prot = (uint32_t*)take(D * 4);
-    S.l_start = (uint32_t*)take(D * 4);
-    S.l_len = (uint8_t*)take(D);
-    S.l_mask = (uint64_t*)take(D * 8);
     S.pair_cnt = (uint64_t*)take((D + 1) * 8);
     S.pair_off = (uint64_t*)take((D + 1) * 8);
     S.bin_cnt = (unsigned long long*)take((C.n_bins + 1) * 8);
@@ -570,7 +566,7 @@ extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const cha
         const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
         const uint64_t tb = temp_bytes_for(C, chunk, nullptr, &e);
         if (e != hipSuccess) rc = fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e));
-        *index_bytes = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride).total;
+        *index_bytes = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride, true).total;
         *scratch_bytes = layout_scratch(nullptr, ix, C, chunk, tb).total;
     }
     delete ix;
@@ -597,7 +593,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
     const uint64_t tb = temp_bytes_for(C, chunk, st, &e);
     if (e != hipSuccess) return bail(fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e)));
-    const DevLayout lay = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride);
+    const DevLayout lay = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride, true);
     const Scratch need = layout_scratch(nullptr, ix, C, chunk, tb);
     if (!index_block->base || index_block->bytes < lay.total)
         return bail(fail(PS_ENOMEM, "index needs %llu device bytes, block has %llu", (unsigned long long)lay.total,
@@ -608,7 +604,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     if (((uintptr_t)index_block->base & 255u) || ((uintptr_t)scratch->base & 255u))
         return bail(fail(PS_EINVAL, "device blocks must be 256-byte aligned"));
     char* base = (char*)index_block->base;
-    const Scratch S = layout_scratch((char*)scratch->base, ix, C, chunk, tb);
+    Scratch S = layout_scratch((char*)scratch->base, ix, C, chunk, tb);
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
     const ModTable mt = mod_table(ix);
     ModArgs M{};
@@ -616,6 +612,11 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     M.nterm_mod = mt.nterm_mod;
     for (size_t m = 0; m < ix->mods.size(); ++m) M.delta[m] = ix->mods[m].delta;
     int64_t* mass = (int64_t*)(base + lay.mass);
+    // the partition's entry table is written straight into the index block
+    S.l_prot = (uint32_t*)(base + lay.prot);
+    S.l_start = (uint32_t*)(base + lay.start);
+    S.l_len = (uint8_t*)(base + lay.len);
+    S.l_mask = (uint64_t*)(base + lay.mask);
     uint32_t* bin_q = (uint32_t*)(base + lay.bin);
     uint32_t* post = (uint32_t*)(base + lay.post);
     uint32_t* dir = (uint32_t*)(base + lay.dir);
@@ -756,20 +757,13 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
                            post, C.n_bins, C.dir_stride, C.dir_shift, dir);
         chk(hipGetLastError());
     }
-    // score tables; host copies of the per-entry arrays and the bin offsets
+    // score tables; the host keeps only the bin offsets (the entry table stays
+    // on the device, where ps_index_entry and ps_peptide read it back)
     std::vector<double> lf, ls;
     score_tables(lf, ls);
     chk(hipMemcpyAsync(base + lay.lf, lf.data(), lf.size() * 8, hipMemcpyHostToDevice, st));
     chk(hipMemcpyAsync(base + lay.ls, ls.data(), ls.size() * 8, hipMemcpyHostToDevice, st));
-    try {
-        ix->mass.resize(C.D); ix->prot.resize(C.D); ix->start.resize(C.D); ix->len.resize(C.D); ix->mask.resize(C.D);
-        ix->bin_off.swap(csr);
-    } catch (...) { return bail(fail(PS_ENOMEM, "out of host memory")); }
-    chk(hipMemcpyAsync(ix->mass.data(), mass, C.D * 8, hipMemcpyDeviceToHost, st));
-    chk(hipMemcpyAsync(ix->prot.data(), S.l_prot, C.D * 4, hipMemcpyDeviceToHost, st));
-    chk(hipMemcpyAsync(ix->start.data(), S.l_start, C.D * 4, hipMemcpyDeviceToHost, st));
-    chk(hipMemcpyAsync(ix->len.data(), S.l_len, C.D, hipMemcpyDeviceToHost, st));
-    chk(hipMemcpyAsync(ix->mask.data(), S.l_mask, C.D * 8, hipMemcpyDeviceToHost, st));
+    ix->bin_off.swap(csr);
     chk(hipStreamSynchronize(st));
     if (e != hipSuccess) return bail(fail(PS_EDEVICE, "index build: %s", hipGetErrorString(e)));
     ix->n_bins = C.n_bins;
@@ -779,6 +773,11 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     ix->dir_nblk = C.dir_nblk;
     ix->dir_stride = C.dir_stride;
     ix->device_built = true;
+    ix->n_entries = C.D;
+    ix->dev_prot = S.l_prot;
+    ix->dev_start = S.l_start;
+    ix->dev_len = S.l_len;
+    ix->dev_mask = S.l_mask;
     ix->dev_n_post = n_post;
     ix->dev_n_quads = quads;
     ix->dev_dir_entries = C.n_bins * C.dir_stride;

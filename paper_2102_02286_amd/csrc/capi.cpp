@@ -180,7 +180,7 @@ uint64_t layout_work(uint64_t n, uint64_t nnz, const KParams& kp, bool copy_inpu
 uint64_t max_items_for(const ps_index* ix, uint64_t n, const KParams& kp, const Schedule& sc, int schedule) {
     if (schedule == PS_SCHED_PLAIN) return n;
     uint64_t span = (uint64_t)kp.tile * sc.tiles_per_item;
-    uint64_t per = ix->mass.size() / span + 2;    // grid-aligned items touching one window
+    uint64_t per = ix->n_entries / span + 2;    // grid-aligned items touching one window
     return n * per;
 }
 

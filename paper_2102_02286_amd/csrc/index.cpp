@@ -221,6 +221,7 @@ int index_build_host(ps_index* ix) {
     const uint64_t D_all = D;
     D = D_all > g ? (D_all - g + G - 1) / G : 0;
     ix->mass.resize(D); ix->prot.resize(D); ix->start.resize(D); ix->len.resize(D); ix->mask.resize(D);
+    ix->n_entries = D;
     for (uint64_t i = 0; i < D; ++i) {
         const PepRec& r = all[i * G + g];
         ix->mass[i] = r.mass; ix->prot[i] = r.prot; ix->start[i] = r.start;
@@ -391,7 +392,7 @@ uint32_t directory_shift(uint64_t nbins, uint64_t D) {
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir) {
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir, bool entries) {
     DevLayout L;
     uint64_t o = 0;
     L.mass = o; o = align256(o + n_pep * sizeof(int64_t));
@@ -400,12 +401,17 @@ DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64
     L.lf = o; o = align256(o + kLfSize * sizeof(double));
     L.ls = o; o = align256(o + kLsSize * sizeof(double));
     L.dir = o; o = align256(o + n_dir * sizeof(uint32_t));
+    const uint64_t ne = entries ? (n_pep > 0 ? n_pep : 1) : 0;
+    L.prot = o; o = align256(o + ne * sizeof(uint32_t));
+    L.start = o; o = align256(o + ne * sizeof(uint32_t));
+    L.mask = o; o = align256(o + ne * sizeof(uint64_t));
+    L.len = o; o = align256(o + ne);
     L.total = o;
     return L;
 }
 
 static DevLayout index_device_layout(const ps_index* ix) {
-    return index_layout(ix->mass.size(), ix->n_bins, padded_quads(ix), dir_entries(ix));
+    return index_layout(ix->n_entries, ix->n_bins, padded_quads(ix), dir_entries(ix));
 }
 
 void bind_device_index(ps_index* ix, char* base, const DevLayout& lay) {
@@ -420,7 +426,7 @@ void bind_device_index(ps_index* ix, char* base, const DevLayout& lay) {
     d.dir_nblk = (uint32_t)ix->dir_nblk;
     d.dir_stride = (uint32_t)ix->dir_stride;
     d.merge_tol = ix->merge_tol;
-    d.n_pep = ix->mass.size();
+    d.n_pep = ix->n_entries;
     d.n_bins = ix->n_bins;
     d.n_post = n_postings(ix);
     d.max_len = ix->max_len_seen;
@@ -654,56 +660,79 @@ extern "C" int ps_build_index(const ps_device* dev, const ps_db_params* params, 
 
 extern "C" int ps_index_shape(const ps_index* ix, uint64_t* n_pep, uint64_t* n_post, uint64_t* n_bins) {
     if (!ix) return fail(PS_EINVAL, "NULL index");
-    if (n_pep) *n_pep = ix->mass.size();
+    if (n_pep) *n_pep = ix->n_entries;
     if (n_post) *n_post = n_postings(ix);
     if (n_bins) *n_bins = ix->n_bins;
     return PS_OK;
 }
 
+// Entries [first, first + count) into host arrays (any may be NULL): from the
+// host table, or read back from the device for an index built there.
+static int read_entries(const ps_index* ix, uint64_t first, uint64_t count, int64_t* mass, uint32_t* protein,
+                        uint32_t* start, uint8_t* length, uint64_t* site_mask) {
+    if (!ix->device_built) {
+        if (mass) memcpy(mass, ix->mass.data() + first, count * sizeof(int64_t));
+        if (protein) memcpy(protein, ix->prot.data() + first, count * sizeof(uint32_t));
+        if (start) memcpy(start, ix->start.data() + first, count * sizeof(uint32_t));
+        if (length) memcpy(length, ix->len.data() + first, count);
+        if (site_mask) memcpy(site_mask, ix->mask.data() + first, count * sizeof(uint64_t));
+        return PS_OK;
+    }
+    if (count == 0) return PS_OK;
+    hipError_t e = hipSuccess;
+    auto get = [&](void* dst, const void* src, size_t elem) {
+        if (dst && e == hipSuccess)
+            e = hipMemcpy(dst, (const char*)src + first * elem, count * elem, hipMemcpyDeviceToHost);
+    };
+    get(mass, ix->dev.mass, sizeof(int64_t));
+    get(protein, ix->dev_prot, sizeof(uint32_t));
+    get(start, ix->dev_start, sizeof(uint32_t));
+    get(length, ix->dev_len, 1);
+    get(site_mask, ix->dev_mask, sizeof(uint64_t));
+    return e == hipSuccess ? PS_OK : fail(PS_EDEVICE, "entries to host: %s", hipGetErrorString(e));
+}
+
 extern "C" int ps_index_entry(const ps_index* ix, uint64_t id, int64_t* mass, uint32_t* protein,
                               uint32_t* start, uint32_t* length, uint64_t* site_mask) {
     if (!ix) return fail(PS_EINVAL, "NULL index");
-    if (id >= ix->mass.size()) return fail(PS_EINVAL, "id %llu out of range", (unsigned long long)id);
-    if (mass) *mass = ix->mass[id];
-    if (protein) *protein = ix->prot[id];
-    if (start) *start = ix->start[id];
-    if (length) *length = ix->len[id];
-    if (site_mask) *site_mask = ix->mask[id];
-    return PS_OK;
+    if (id >= ix->n_entries) return fail(PS_EINVAL, "id %llu out of range", (unsigned long long)id);
+    uint8_t len8 = 0;
+    const int rc = read_entries(ix, id, 1, mass, protein, start, length ? &len8 : nullptr, site_mask);
+    if (rc == PS_OK && length) *length = len8;
+    return rc;
 }
 
 extern "C" int ps_index_entries(const ps_index* ix, uint64_t first, uint64_t count, int64_t* mass, uint32_t* protein,
                                 uint32_t* start, uint8_t* length, uint64_t* site_mask) {
     if (!ix) return fail(PS_EINVAL, "NULL index");
-    const uint64_t D = ix->mass.size();
+    const uint64_t D = ix->n_entries;
     if (first > D || count > D - first)
         return fail(PS_EINVAL, "entries [%llu, %llu) out of range (%llu)", (unsigned long long)first,
                     (unsigned long long)(first + count), (unsigned long long)D);
-    if (mass) memcpy(mass, ix->mass.data() + first, count * sizeof(int64_t));
-    if (protein) memcpy(protein, ix->prot.data() + first, count * sizeof(uint32_t));
-    if (start) memcpy(start, ix->start.data() + first, count * sizeof(uint32_t));
-    if (length) memcpy(length, ix->len.data() + first, count);
-    if (site_mask) memcpy(site_mask, ix->mask.data() + first, count * sizeof(uint64_t));
-    return PS_OK;
+    return read_entries(ix, first, count, mass, protein, start, length, site_mask);
 }
 
 extern "C" int ps_peptide(const ps_index* ix, uint32_t id, char* buf, size_t cap) {
     if (!ix || !buf || cap == 0) return fail(PS_EINVAL, "NULL argument");
-    if (id >= ix->mass.size()) return fail(PS_EINVAL, "id %u out of range", id);
+    if (id >= ix->n_entries) return fail(PS_EINVAL, "id %u out of range", id);
+    uint32_t prot = 0, start = 0;
+    uint8_t len = 0;
+    uint64_t mask = 0;
+    const int rc = read_entries(ix, id, 1, nullptr, &prot, &start, &len, &mask);
+    if (rc != PS_OK) return rc;
     ModTable mt = mod_table(ix);
     std::string s;
-    const char* seq = ix->seq.data() + ix->prot_off[ix->prot[id]] + ix->start[id];
-    uint64_t mask = ix->mask[id];
+    const char* seq = ix->seq.data() + ix->prot_off[prot] + start;
     uint32_t bit = 0;
     char tmp[48];
-    if (ix->start[id] == 0 && mt.nterm_mod >= 0) {
+    if (start == 0 && mt.nterm_mod >= 0) {
         if (mask & 1ull) {
             snprintf(tmp, sizeof tmp, "n[%+.6f]", ix->mods[mt.nterm_mod].delta * 1e-6);
             s += tmp;
         }
         bit = 1;
     }
-    for (uint32_t j = 0; j < ix->len[id]; ++j) {
+    for (uint32_t j = 0; j < len; ++j) {
         s += seq[j];
         int mm = mt.res_mod[seq[j] - 'A'];
         if (mm >= 0) {

@@ -60,8 +60,14 @@ struct ps_index {
     // device copy
     bool on_device = false;
     ps::DevIndex dev{};
-    // built on the device: postings and directory exist only there
+    // entries in the index (the host vectors above hold them unless the index was built on the device)
+    uint64_t n_entries = 0;
+    // built on the device: postings, directory and the entry table exist only there
     bool device_built = false;
+    const uint32_t* dev_prot = nullptr;
+    const uint32_t* dev_start = nullptr;
+    const uint8_t* dev_len = nullptr;
+    const uint64_t* dev_mask = nullptr;
     uint64_t dev_n_post = 0, dev_dir_entries = 0;
     uint64_t dev_n_quads = 0;    // padded postings on the device / 4
 };
@@ -79,9 +85,11 @@ uint64_t padded_quads(const ps_index* ix);
 // Device layout of an index block: [mass][bin_q][post][lf][ls][dir], each 256-byte aligned;
 // n_quads is the padded postings / 4.
 struct DevLayout {
-    uint64_t mass, bin, post, lf, ls, dir, total;
+    uint64_t mass, bin, post, lf, ls, dir;
+    uint64_t prot, start, mask, len;   // the entry table, kept on the device by a device build (else empty)
+    uint64_t total;
 };
-DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir);
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir, bool entries = false);
 // Point ix->dev at an index block laid out by `lay` and mark the index on the device.
 void bind_device_index(ps_index* ix, char* base, const DevLayout& lay);
 // Modification lookup: which mod (if any) sits on each residue letter; the N-terminal mod.

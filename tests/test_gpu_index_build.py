@@ -39,6 +39,12 @@ def _assert_same_index(host, dev):
     assert host.directory() == dev.directory()
     assert np.array_equal(host.directory_array(), dev.directory_array()), "tile directories differ"
     assert host.schedule().tile == dev.schedule().tile
+    # the device-built index keeps its entry table on the device: single entries
+    # and peptide strings read back from it equal the host build's
+    n = len(host)
+    for i in sorted({0, n // 3, n // 2, n - 1} if n else set()):
+        assert host.peptide(i) == dev.peptide(i)
+        assert host.entry(i) == dev.entry(i)
 
 
 @pytest.mark.parametrize("mods,max_mods,T,chunk", [([], 0, 0, 0), ([synth.OXIDATION], 2, 1, 0), (ALL_MODS, 3, 2, 0),
