@@ -301,13 +301,17 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs A) {
         const uint32_t keep = min(alive, kp.top_peaks);
         const uint32_t n_ent = bad ? 0u : keep * cmax;
         uint32_t* gent = A.w.entries + s * (uint64_t)kp.ent_stride;
-        // top-B by (intensity desc, m/z asc, input order asc): rank = number of better peaks
+        // top-B by (intensity desc, m/z asc, input order asc): rank = number of better peaks.
+        // When every peak is kept, any order of the entries gives the same search, so a
+        // peak's entries go at its input position.
         if (!bad) {
+            const bool all_kept = keep == np;
             for (uint32_t i = tid; i < np; i += kBlock) {
                 const float mi = mz_at(i), vi = in_at(i);
                 const unsigned long long ki = key_at(i);
-                uint32_t rank = 0;
-                if (lds) {
+                uint32_t rank = all_kept ? i : 0u;
+                if (all_kept) {
+                } else if (lds) {
                     for (uint32_t j = 0; j < np; ++j) {
                         const unsigned long long kj = s_key[j];
                         rank += kj > ki || (kj == ki && j < i);
