@@ -427,10 +427,45 @@ int orc_evalue(const int32_t* hist, double top_h, uint64_t n_scored,
     return 0;
 }
 
+/* The window of ORC_SAMPLE_BINS bins the Sampling section keeps (see
+ * orc_sampled): its first bin, or -1 when no bin holds a count. */
+static int sample_window(const int32_t* hist) {
+    /* the three most intense samples (largest counts; ties go to the lower bin) */
+    int top[3];
+    int t = 0;
+    for (int r = 0; r < 3; ++r) {
+        int best = -1;
+        for (int j = 0; j < ORC_HIST_BINS; ++j) {
+            if (hist[j] <= 0) continue;
+            int used = 0;
+            for (int u = 0; u < t; ++u) used |= top[u] == j;
+            if (used) continue;
+            if (best < 0 || hist[j] > hist[best]) best = j;
+        }
+        if (best < 0) break;
+        top[t++] = best;
+    }
+    if (t == 0) return -1;
+    int sum = 0;
+    for (int u = 0; u < t; ++u) sum += top[u];
+    const int mean = sum / t;                 /* average location, floored */
+    int first = 0;
+    while (hist[first] <= 0) ++first;
+    /* the window reaches down to the head's start, but no further than
+     * ORC_SAMPLE_HEAD bins below the mean; what does not fit is tail */
+    int lo = first > mean - ORC_SAMPLE_HEAD ? first : mean - ORC_SAMPLE_HEAD;
+    if (lo > ORC_HIST_BINS - ORC_SAMPLE_BINS) lo = ORC_HIST_BINS - ORC_SAMPLE_BINS;
+    return lo;
+}
+
 /* log-Weibull (Gumbel) fit (Superstep 4; Supplementary Algorithm 4 names it
- * next to the tail fit) and expect value.  Reading: the Gumbel location mu and
- * scale beta come from the moments of the smoothed histogram hs, each bin j
- * standing at its centre x_j = 0.1 j + 0.05: mean m = sum hs x / sum hs, variance
+ * next to the tail fit) and expect value.  Reading: the fit sees the samples
+ * the Sampling section keeps, the histogram restricted to the ORC_SAMPLE_BINS-bin
+ * window of sample_window (zero outside), whose pruned far tail the fitted
+ * distribution stands in for; so a partition's 256-byte record and its full
+ * histogram give the same fit.  The Gumbel location mu and scale beta come
+ * from the moments of the smoothed restricted histogram hs, each bin j standing
+ * at its centre x_j = 0.1 j + 0.05: mean m = sum hs x / sum hs, variance
  * v = sum hs (x - m)^2 / sum hs, beta = sqrt(6 v) / pi, mu = m - gamma * beta
  * (gamma = Euler-Mascheroni).  ev = N * S(H1) with the Gumbel survival
  * S(h) = 1 - exp(-exp(-(h - mu) / beta)).  Returns 0 ok, 1 nothing scored, 2
@@ -441,8 +476,12 @@ int orc_evalue_gumbel(const int32_t* hist, double top_h, uint64_t n_scored,
     static const double kPi = 3.14159265358979323846;
     *evalue = NAN; *mu = NAN; *beta = NAN; *n_points = 0;
     if (n_scored == 0) return 1;
+    int32_t kept[ORC_HIST_BINS];
+    const int lo = sample_window(hist);
+    for (int j = 0; j < ORC_HIST_BINS; ++j)
+        kept[j] = (lo >= 0 && j >= lo && j < lo + ORC_SAMPLE_BINS && hist[j] > 0) ? hist[j] : 0;
     double hs[ORC_HIST_BINS];
-    orc_sg_smooth(hist, hs);
+    orc_sg_smooth(kept, hs);
     double w = 0.0, wx = 0.0;
     int n = 0;
     for (int j = 0; j < ORC_HIST_BINS; ++j) {
@@ -841,31 +880,8 @@ int orc_assemble(uint32_t n_shards, uint64_t n, uint32_t top_k, int32_t fit, con
 void orc_sample(const int32_t* hist, uint64_t n_scored, orc_sampled* out) {
     memset(out, 0, sizeof *out);
     out->n_scored = n_scored;
-    /* the three most intense samples (largest counts; ties go to the lower bin) */
-    int top[3];
-    int t = 0;
-    for (int r = 0; r < 3; ++r) {
-        int best = -1;
-        for (int j = 0; j < ORC_HIST_BINS; ++j) {
-            if (hist[j] <= 0) continue;
-            int used = 0;
-            for (int u = 0; u < t; ++u) used |= top[u] == j;
-            if (used) continue;
-            if (best < 0 || hist[j] > hist[best]) best = j;
-        }
-        if (best < 0) break;
-        top[t++] = best;
-    }
-    if (t == 0) return;                       /* empty distribution: nothing to keep */
-    int sum = 0;
-    for (int u = 0; u < t; ++u) sum += top[u];
-    const int mean = sum / t;                 /* average location, floored */
-    int first = 0;
-    while (hist[first] <= 0) ++first;
-    /* the window reaches down to the head's start, but no further than
-     * ORC_SAMPLE_HEAD bins below the mean; what does not fit is tail */
-    int lo = first > mean - ORC_SAMPLE_HEAD ? first : mean - ORC_SAMPLE_HEAD;
-    if (lo > ORC_HIST_BINS - ORC_SAMPLE_BINS) lo = ORC_HIST_BINS - ORC_SAMPLE_BINS;
+    const int lo = sample_window(hist);
+    if (lo < 0) return;                       /* empty distribution: nothing to keep */
     out->lo = (uint16_t)lo;
     for (int j = 0; j < ORC_HIST_BINS; ++j) {
         const int32_t v = hist[j] > 0 ? hist[j] : 0;

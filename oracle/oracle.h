@@ -17,7 +17,8 @@
  *     a score histogram (Sampling section: the 2048-byte local null
  *     distribution), Savitzky-Golay smoothing, linear tail fit and expect value
  *     (Superstep 4; Supplementary Algorithm 4), or a log-Weibull (Gumbel) fit
- *     by moments in its place (Superstep 4 names both);
+ *     by moments in its place (Superstep 4 names both), over the samples the
+ *     Sampling section keeps;
  *   - partitions and result assembly: round-robin database partitions and the
  *     histogram addition plus top-hit merge of Superstep 4 (Supplementary
  *     Algorithm 4).

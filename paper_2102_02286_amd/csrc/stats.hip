@@ -158,6 +158,54 @@ __device__ uint32_t wave_top_k(uint32_t L, uint32_t k, Key key) {
     return mine;
 }
 
+// First bin of the window of PS_SAMPLE_BINS bins the Sampling section keeps
+// (ps_sample), for a histogram held as bins 8 lane .. 8 lane + 7 in v[] (all
+// counts >= 0): the floored mean of the three largest counts' bins (ties: the
+// lower bin), the window reaching down to the first nonzero bin but no further
+// than PS_SAMPLE_HEAD bins below that mean, and ending at bin 511 at the
+// latest.  -1 when every count is 0.  Every lane calls it; the result is the
+// same in every lane.
+__device__ int sample_window_lo(const int32_t v[8]) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t used = 0, sum = 0, t = 0;
+    for (int r = 0; r < 3; ++r) {
+        unsigned long long best = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const unsigned long long key =
+                ((unsigned long long)(uint32_t)v[i] << 32) | (uint32_t)(kHistBins - 1 - (8u * lane + i));
+            if (v[i] > 0 && !((used >> i) & 1u) && key > best) best = key;
+        }
+        best = wave_max_u64(best);
+        if (best == 0) break;                                   // wave-uniform
+        const uint32_t bin = (uint32_t)(kHistBins - 1) - (uint32_t)(best & 0xFFFFFFFFull);
+        if (bin / 8u == lane) used |= 1u << (bin % 8u);
+        sum += bin;
+        ++t;
+    }
+    if (t == 0) return -1;
+    uint32_t first = kHistBins;
+#pragma unroll
+    for (int i = 7; i >= 0; --i)
+        if (v[i] > 0) first = 8u * lane + i;
+    first = wave_min_u32(first);
+    const int mean = (int)(sum / t);
+    const int lo = (int)first > mean - PS_SAMPLE_HEAD ? (int)first : mean - PS_SAMPLE_HEAD;
+    return min(lo, kHistBins - PS_SAMPLE_BINS);
+}
+
+// The window the log-Weibull fit uses for the histogram in h[] (negative
+// counts, which a search never writes, count as empty); -1 unless FIT is
+// the log-Weibull one.
+template <int FIT>
+__device__ __forceinline__ int fit_window(const int32_t h[8]) {
+    if constexpr (FIT != PS_FIT_GUMBEL) return -1;
+    int32_t v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = h[i] > 0 ? h[i] : 0;
+    return sample_window_lo(v);
+}
+
 // Fit of one spectrum's expect-value model (Superstep 4) to its histogram,
 // bins 8 lane .. 8 lane + 7 in h[]: Savitzky-Golay smoothing with
 // (-3, 12, 17, 12, -3)/35 (the integer numerators are kept, negatives set to 0;
@@ -165,7 +213,9 @@ __device__ uint32_t wave_top_k(uint32_t L, uint32_t k, Key key) {
 // least-squares line w x + b of its log10 from the smoothed mode (lowest bin on
 // ties) to the bin below the top hit, giving arg = w h1 + b for
 // ev = N * 10^arg, or the log-Weibull (Gumbel) location and scale from the
-// moments of the smoothed histogram (bin centres 0.1 j + 0.05), giving
+// moments of the smoothed histogram restricted to the window a sampled record
+// keeps (Sampling section; its first bin win_lo, from sample_window_lo on the
+// same histogram, -1 if empty; bin centres 0.1 j + 0.05), giving
 // arg = (h1 - mu) / beta for ev = N * (1 - exp(-exp(-arg))).  The exponential
 // itself is taken by k_finish_evalue, one thread per spectrum, so that its
 // registers are not held by every lane here.  `status` enters as OK, INVALID,
@@ -174,17 +224,30 @@ __device__ uint32_t wave_top_k(uint32_t L, uint32_t k, Key key) {
 // results are the same in every lane.  `tl` is this wavefront's LDS area of
 // 8 x 64 survival sums (bin 8 l + i at tl[64 i + l]), from which the fit range
 // is dealt out to consecutive lanes.
-__device__ void fit_wave(const int32_t h[8], unsigned long long N, double h1, int fit, int& status, double& arg,
+template <int FIT>
+__device__ void fit_wave(const int32_t h[8], int win_lo, unsigned long long N, double h1, int& status, double& arg,
                          long long* tl) {
     static_assert(kHistBins == 8 * 64, "eight histogram bins per lane");
     const uint32_t lane = threadIdx.x & 63u;
-    const int32_t lm2 = __shfl_up(h[6], 1, 64), lm1 = __shfl_up(h[7], 1, 64);
-    const int32_t rp0 = __shfl_down(h[0], 1, 64), rp1 = __shfl_down(h[1], 1, 64);
+    // the log-Weibull fit sees only the samples a sampled record keeps: the
+    // histogram restricted to its window (zero outside)
+    int32_t hv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) hv[i] = h[i];
+    if constexpr (FIT == PS_FIT_GUMBEL) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = 8 * (int)lane + i;
+            if (hv[i] < 0 || win_lo < 0 || j < win_lo || j >= win_lo + PS_SAMPLE_BINS) hv[i] = 0;
+        }
+    }
+    const int32_t lm2 = __shfl_up(hv[6], 1, 64), lm1 = __shfl_up(hv[7], 1, 64);
+    const int32_t rp0 = __shfl_down(hv[0], 1, 64), rp1 = __shfl_down(hv[1], 1, 64);
     int32_t x[12];
     x[0] = lane ? lm2 : 0;
     x[1] = lane ? lm1 : 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[i + 2] = h[i];
+    for (int i = 0; i < 8; ++i) x[i + 2] = hv[i];
     x[10] = lane < 63u ? rp0 : 0;
     x[11] = lane < 63u ? rp1 : 0;
     long long num[8];
@@ -213,7 +276,7 @@ __device__ void fit_wave(const int32_t h[8], unsigned long long N, double h1, in
     }
     const long long above = suf - lt;
     arg = __builtin_nan("");
-    if (fit == PS_FIT_GUMBEL) {
+    if constexpr (FIT == PS_FIT_GUMBEL) {
         if (status != PS_STATUS_OK) return;                 // uniform across the wavefront
         if (total <= 0) { status = PS_STATUS_FEW_POINTS; return; }
         double wx = 0, pts = 0;
@@ -326,6 +389,7 @@ struct MergeArgs {
     uint32_t per_item;   // 1: partial lists per work item (spec_item0 ranges); 0: one per spectrum
 };
 
+template <int FIT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_merge(MergeArgs A) {
     __shared__ long long s_tail[kStatWaves][8 * 64];
     const uint32_t lane = threadIdx.x & 63u;
@@ -340,6 +404,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         if (A.per_item) { i0 = A.w.spec_item0[s]; i1 = A.w.spec_item0[s + 1]; }
         const uint32_t L = (invalid || overflow) ? 0u : (uint32_t)(i1 - i0);
         const ps_hit* src = A.w.partial + i0 * K;
+        int32_t h[8];
+        load_bins(A.w.hist + s * (uint64_t)kHistBins, h);
+        const int win = fit_window<FIT>(h);
         const uint32_t c = wave_top_k(L, K, [&](uint32_t x) { return hit_key(src[x].hyperscore, src[x].id, x); });
         ps_hit mine;
         if (c != 0xFFFFFFFFu) mine = src[c]; else empty_hit(mine);
@@ -348,10 +415,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         const unsigned long long N = (invalid || overflow) ? 0ull : A.w.n_scored[s];
         int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
                    : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
-        int32_t h[8];
-        load_bins(A.w.hist + s * (uint64_t)kHistBins, h);
         double ev;
-        fit_wave(h, N, h1, A.kp.fit, status, ev, s_tail[threadIdx.x >> 6]);
+        fit_wave<FIT>(h, win, N, h1, status, ev, s_tail[threadIdx.x >> 6]);
         if (lane == 0) store_stat(A.w.stats + s, invalid ? 0ull : (unsigned long long)(inf.hi - inf.lo), N, ev, status);
     }
 }
@@ -362,7 +427,8 @@ hipError_t launch_merge(const DevIndex&, const DevSpectra& sp, const KParams& kp
     MergeArgs a{sp, kp, w, per_item ? 1u : 0u};
     const uint64_t blocks = (sp.n + kStatWaves - 1) / kStatWaves;
     const uint32_t grid = (uint32_t)(blocks < (1u << 20) ? blocks : (1u << 20));
-    hipLaunchKernelGGL(k_merge, dim3(grid), dim3(kBlock), 0, stream, a);
+    if (kp.fit == PS_FIT_GUMBEL) hipLaunchKernelGGL(k_merge<PS_FIT_GUMBEL>, dim3(grid), dim3(kBlock), 0, stream, a);
+    else hipLaunchKernelGGL(k_merge<PS_FIT_TAIL>, dim3(grid), dim3(kBlock), 0, stream, a);
     const hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : launch_finish(w.stats, sp.n, sp.hdr, kp.fit, stream);
 }
@@ -383,6 +449,7 @@ struct AssembleArgs {
     int32_t* hist;   // may be NULL
 };
 
+template <int FIT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_assemble(AssembleArgs A) {
     __shared__ long long s_tail[kStatWaves][8 * 64];
     const uint32_t lane = threadIdx.x & 63u, G = A.G, K = A.K;
@@ -408,14 +475,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             // four partitions' bins requested together (a group past G repeats
             // partition G - 1 and adds nothing)
             for (uint32_t g0 = 0; g0 < G; g0 += 4) {
-                int32_t v[4][8];
 #pragma unroll
-                for (uint32_t u = 0; u < 4; ++u)
-                    load_bins(A.parts[min(g0 + u, G - 1)].hist + s * (uint64_t)kHistBins, v[u]);
+                for (int half = 0; half < 2; ++half) {         // this lane's bins 4 at a time
+                    int4 q[4];
 #pragma unroll
-                for (uint32_t u = 0; u < 4; ++u)
+                    for (uint32_t u = 0; u < 4; ++u)
+                        q[u] = ((const int4*)(A.parts[min(g0 + u, G - 1)].hist + s * (uint64_t)kHistBins))
+                            [2u * lane + (uint32_t)half];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) h[i] += g0 + u < G ? v[u][i] : 0;
+                    for (uint32_t u = 0; u < 4; ++u) {
+                        const bool in = g0 + u < G;
+                        h[4 * half + 0] += in ? q[u].x : 0;
+                        h[4 * half + 1] += in ? q[u].y : 0;
+                        h[4 * half + 2] += in ? q[u].z : 0;
+                        h[4 * half + 3] += in ? q[u].w : 0;
+                    }
+                }
             }
         } else for (uint32_t g = 0; g < G; ++g) {
             if (A.parts[g].hist) {
@@ -434,6 +509,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             }
         }
         if (A.hist) store_bins(A.hist + s * (uint64_t)kHistBins, h);
+        const int win = fit_window<FIT>(h);
         // top-k of the partitions' lists, ids turned into whole-database ids
         const uint32_t c = wave_top_k((invalid || overflow) ? 0u : G, K, [&](uint32_t x) {
             const uint32_t g = x / K;
@@ -454,7 +530,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         int status = invalid ? PS_STATUS_INVALID : overflow ? PS_STATUS_OVERFLOW
                    : N == 0 ? PS_STATUS_NO_HITS : PS_STATUS_OK;
         double ev;
-        fit_wave(h, N, h1, A.fit, status, ev, s_tail[threadIdx.x >> 6]);
+        fit_wave<FIT>(h, win, N, h1, status, ev, s_tail[threadIdx.x >> 6]);
         if (lane == 0) store_stat(A.stats + s, invalid ? 0ull : window, N, ev, status);
     }
 }
@@ -472,7 +548,8 @@ hipError_t launch_assemble(const ps_part* parts, uint32_t G, uint64_t n, uint32_
     a.G = G; a.K = K; a.fit = fit; a.n = n; a.hits = hits; a.stats = stats; a.hist = hist;
     const uint64_t blocks = (n + kStatWaves - 1) / kStatWaves;
     const uint32_t grid = (uint32_t)(blocks < (1u << 20) ? blocks : (1u << 20));
-    hipLaunchKernelGGL(k_assemble, dim3(grid), dim3(kBlock), 0, stream, a);
+    if (fit == PS_FIT_GUMBEL) hipLaunchKernelGGL(k_assemble<PS_FIT_GUMBEL>, dim3(grid), dim3(kBlock), 0, stream, a);
+    else hipLaunchKernelGGL(k_assemble<PS_FIT_TAIL>, dim3(grid), dim3(kBlock), 0, stream, a);
     const hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : launch_finish(stats, n, nullptr, fit, stream);
 }
@@ -530,34 +607,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs A) {
             v[i] = v[i] > 0 ? v[i] : 0;
             h[8u * lane + i] = v[i];
         }
-        // the three most intense bins: key = count, then the lower bin
-        uint32_t used = 0, sum = 0, t = 0;
-        for (int r = 0; r < 3; ++r) {
-            unsigned long long best = 0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const unsigned long long key =
-                    ((unsigned long long)(uint32_t)v[i] << 32) | (uint32_t)(kHistBins - 1 - (8u * lane + i));
-                if (v[i] > 0 && !((used >> i) & 1u) && key > best) best = key;
-            }
-            best = wave_max_u64(best);
-            if (best == 0) break;                                   // wave-uniform
-            const uint32_t bin = (uint32_t)(kHistBins - 1) - (uint32_t)(best & 0xFFFFFFFFull);
-            if (bin / 8u == lane) used |= 1u << (bin % 8u);
-            sum += bin;
-            ++t;
-        }
-        uint32_t first = kHistBins;
-#pragma unroll
-        for (int i = 7; i >= 0; --i)
-            if (v[i] > 0) first = 8u * lane + i;
-        first = wave_min_u32(first);
-        int lo = 0;
-        if (t) {
-            const int mean = (int)(sum / t);
-            lo = (int)first > mean - PS_SAMPLE_HEAD ? (int)first : mean - PS_SAMPLE_HEAD;
-            lo = min(lo, kHistBins - PS_SAMPLE_BINS);
-        }
+        int lo = sample_window_lo(v);
+        if (lo < 0) lo = 0;                                         // an empty histogram keeps nothing
         // flags from this lane's bins
         bool sat = false, lost = false;
 #pragma unroll

@@ -558,13 +558,24 @@ def _gumbel_hist(mu, beta, total):
     return np.round(total * np.diff(cdf)).astype(np.int32)
 
 
-@pytest.mark.parametrize("mu,beta", [(20.0, 2.0), (12.5, 0.8), (24.0, 3.0)])
+def _kept(h):
+    """The histogram restricted to the window the Sampling section keeps (the
+    brute-force placement of _sample_bruteforce), zero elsewhere."""
+    lo = _sample_bruteforce(h)
+    k = np.zeros(oracle.HIST_BINS, np.int32)
+    k[lo:lo + oracle.SAMPLE_BINS] = np.maximum(h[lo:lo + oracle.SAMPLE_BINS], 0)
+    return k
+
+
+@pytest.mark.parametrize("mu,beta", [(20.0, 0.5), (12.5, 0.4), (24.0, 0.5)])
 def test_gumbel_fit_recovers_location_and_scale(mu, beta):
-    """On a histogram of an exact Gumbel(mu, beta) the moment fit returns mu and
-    beta up to binning (a few 1e-3), and the expect value is N times the Gumbel
-    survival function of scipy at the fitted parameters."""
+    """On a histogram of an exact Gumbel(mu, beta) whose samples all lie in the
+    kept window the moment fit returns mu and beta up to binning (a few 1e-3),
+    and the expect value is N times the Gumbel survival function of scipy at the
+    fitted parameters."""
     from scipy.stats import gumbel_r
     h = _gumbel_hist(mu, beta, 10**8)
+    assert np.array_equal(_kept(h), h)
     N = int(h.sum())
     top = mu + 6 * beta
     st, ev, m, b, npts = oracle.evalue_gumbel(h, top, N)
@@ -576,31 +587,69 @@ def test_gumbel_fit_recovers_location_and_scale(mu, beta):
     assert ev_far == pytest.approx(N * gumbel_r.sf(mu + 40 * beta, loc=m, scale=b), rel=1e-12)
 
 
-def test_gumbel_moments_equal_numpy_moments_of_the_smoothed_histogram():
+def test_gumbel_moments_equal_numpy_moments_of_the_smoothed_kept_histogram():
     """The fit is the moment fit of the (independently pinned) smoothed
-    histogram: compare with numpy moments over bin centres.  Mass at bin 0 makes
-    the zero padding and the clamping of the smoothing matter, and because the
+    histogram of the kept window: compare with numpy moments over bin centres.
+    Mass at bin 0 makes the zero padding and the clamping of the smoothing
+    matter; a wide Gumbel loses its far tail to the window; and because the
     quadratic Savitzky-Golay window keeps the first two moments, the raw
     histogram of a smooth interior distribution gives the same answer."""
     k_gamma = 0.5772156649015329
     x = 0.1 * np.arange(oracle.HIST_BINS) + 0.05
     for h in [np.bincount([0, 0, 0, 1, 1, 5, 5, 9], minlength=oracle.HIST_BINS).astype(np.int32) * 10,
-              _gumbel_hist(25.0, 3.0, 10**7)]:
-        hs = oracle.sg_smooth(h)
+              _gumbel_hist(25.0, 3.0, 10**7), _gumbel_hist(20.0, 2.0, 10**7)]:
+        hs = oracle.sg_smooth(_kept(h))
         m = np.sum(hs * x) / np.sum(hs)
         v = np.sum(hs * (x - m) ** 2) / np.sum(hs)
         beta = np.sqrt(6 * v) / np.pi
         st, ev, mu_f, beta_f, _ = oracle.evalue_gumbel(h, 3.0, 1000)
         assert st == 0
         assert mu_f == pytest.approx(m - k_gamma * beta, rel=1e-12) and beta_f == pytest.approx(beta, rel=1e-12)
-    # interior (no mass near either end): smoothing keeps the moments of the raw histogram
-    h = _gumbel_hist(20.0, 2.0, 10**7)
+    # interior (no mass near either end of the window): smoothing keeps the
+    # moments of the raw histogram
+    h = _gumbel_hist(20.0, 0.5, 10**7)
     m0 = np.sum(h * x) / h.sum()
     v0 = np.sum(h * (x - m0) ** 2) / h.sum()
     _, _, mu_f, beta_f, _ = oracle.evalue_gumbel(h, 30.0, int(h.sum()))
     # (up to the few sparse tail bins where smoothing goes negative and is clamped)
     assert beta_f == pytest.approx(np.sqrt(6 * v0) / np.pi, rel=2e-5)
     assert mu_f == pytest.approx(m0 - k_gamma * np.sqrt(6 * v0) / np.pi, rel=2e-5)
+
+
+def test_gumbel_fit_sees_only_the_kept_samples():
+    """Sampling section: the far tail a 256-byte record prunes is what the fitted
+    distribution stands in for.  Counts added beyond the kept window leave the
+    fit unchanged, and a record shifted back gives the full histogram's fit bit
+    for bit whenever no count saturated and the shifted-back histogram places
+    its window where the record's is (it does unless one of the three largest
+    counts was pruned) -- on random histograms of every shape."""
+    rng = np.random.default_rng(24)
+    h = _gumbel_hist(20.0, 2.0, 10**6)
+    lo = _sample_bruteforce(h)
+    far = h.copy()
+    far[lo + oracle.SAMPLE_BINS:] += 3                     # a longer tail past the window
+    assert _sample_bruteforce(far) == lo
+    a, b = oracle.evalue_gumbel(h, 30.0, 10**6), oracle.evalue_gumbel(far, 30.0, 10**6)
+    assert a[0] == b[0] == 0 and a[1:4] == b[1:4]
+    n_checked = 0
+    for _ in range(300):
+        h = np.zeros(oracle.HIST_BINS, np.int32)
+        a0 = int(rng.integers(0, oracle.HIST_BINS))
+        b0 = min(oracle.HIST_BINS, a0 + int(rng.integers(1, [30, 121, 300, 512][int(rng.integers(0, 4))])))
+        h[a0:b0] = rng.integers(0, [3, 50, 1000, 80000][int(rng.integers(0, 4))], b0 - a0)
+        n = int(h.sum())
+        rec = oracle.sample(h, [n])
+        if int(rec["flags"][0]) & 1:                       # a saturated count: the record differs
+            continue
+        back = oracle.unsample(rec)[0]
+        if _sample_bruteforce(back) != int(rec["lo"][0]):
+            continue
+        full, samp = oracle.evalue_gumbel(h, 30.0, n), oracle.evalue_gumbel(back, 30.0, n)
+        assert full[0] == samp[0]
+        if full[0] == 0:
+            assert full[1:4] == samp[1:4]
+            n_checked += 1
+    assert n_checked > 100
 
 
 def test_gumbel_special_cases():
