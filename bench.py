@@ -669,6 +669,27 @@ def main():
 
     # headline: the faster graph form; its scan kernel's HIP-event time gives the roofline
     form = max(forms, key=lambda k: forms[k]["spectra_per_s"])
+
+    # the same form with the spectra handed over in host memory (ps_plan_run copies
+    # them in, then replays the graph): the rate with the PCIe transfer, never `value`
+    def host_input_steps(prm, eager_ref):
+        use(form)
+        plan = engine.Plan(ix, prm, n_cap=sp.n, nnz_cap=nnz)
+        plan.search(sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = plan.search(sp)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert r.hits.tobytes() == eager_ref.hits.tobytes(), "host-input plan and eager results differ"
+        in_bytes = int(sp.peak_off[-1]) * 8 + sp.n * (8 + 8 + 1)
+        del plan
+        return {"spectra_per_s": sp.n * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+                "input_bytes": in_bytes}
+    pcie = host_input_steps(prm_plain if form == "plain" else prm_pers, eager[form]["res"])
+    log(f"{form} graph with host inputs: {pcie['spectra_per_s']:.0f} spectra/s, {pcie['ms_per_step']:.1f} ms/step "
+        f"({pcie['input_bytes'] / 1e6:.0f} MB of spectra copied in per step)")
     kernel = "k_scan_plain" if form == "plain" else "k_scan_persistent"
     head_scan = eager[form]["scan_ms"]
     postings, lookups = ref.postings, ref.lookups
@@ -712,6 +733,8 @@ def main():
         "forms": {k: {**forms[k], "eager_spectra_per_s": eager[k]["spectra_per_s"],
                       "eager_ms_per_step": eager[k]["ms_per_step"], "scan_ms": eager[k]["scan_ms"]}
                   for k in forms},
+        "host_inputs": {"form": form, **pcie, "note": "the headline graph with the spectra copied in from host "
+                        "memory every step (PCIe-inclusive; never the value)"},
         "schedule": {k: as_dict(tuned[k]) for k in tuned},
         "index_build": {"device_s": build_s, "entries": n_pep, "postings": n_post,
                         "device_bytes": ix.arena.numel(), "directory_bytes": dir_bytes},
