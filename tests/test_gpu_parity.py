@@ -146,6 +146,44 @@ def test_small_open_permutation_and_split_invariance(small_open):
     assert r2.hits.tobytes() == r0.hits.tobytes() and r2.hist.tobytes() == r0.hist.tobytes()
 
 
+def _protein_order(prot, perm):
+    seqs = [prot.residues[int(prot.offsets[i]):int(prot.offsets[i + 1])] for i in range(len(prot.offsets) - 1)]
+    off = np.zeros(len(perm) + 1, np.uint64)
+    off[1:] = np.cumsum([len(seqs[i]) for i in perm])
+    return np.concatenate([seqs[i] for i in perm]).astype(np.uint8), off
+
+
+def _entry_keys(ents, residues, offsets):
+    a = offsets[ents["prot"].astype(np.int64)].astype(np.int64) + ents["start"].astype(np.int64)
+    return [(bytes(residues[x:x + int(n)]), int(st) == 0, int(m))
+            for x, n, st, m in zip(a, ents["len"], ents["start"], ents["mask"])]
+
+
+def test_small_open_protein_order_invariance(small_open):
+    """Reordering the proteins renumbers the peptides but changes no spectrum's
+    scored set (as peptides with their counts), statistics or histogram."""
+    from collections import Counter
+    w, prot, sp, ix, db, _ = small_open
+    res2, off2 = _protein_order(prot, np.random.default_rng(11).permutation(len(prot.offsets) - 1))
+    ix2 = engine.HostIndex(res2, off2, w.missed, w.min_len, w.max_len, engine.mods_from_synth(w.mods),
+                           w.max_mods).upload()
+    assert len(ix2) == len(ix)
+    _say("small open: protein-order invariance")
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=3)
+    r1, r2 = engine.search(ix, sp, prm), engine.search(ix2, sp, prm)
+    assert r1.stats.tobytes() == r2.stats.tobytes()
+    assert r1.hist.tobytes() == r2.hist.tobytes()
+    assert r1.hits["hyperscore"].tobytes() == r2.hits["hyperscore"].tobytes()
+    k1 = _entry_keys(ix.entries(), prot.residues, prot.offsets)
+    k2 = _entry_keys(ix2.entries(), res2, off2)
+    sets = []
+    for index, keys in ((ix, k1), (ix2, k2)):
+        gs, gi, gb, gy, gq = engine.search_dump(index, sp, prm)
+        sets.append(Counter((int(s), keys[int(i)], int(b), int(y), int(q)) for s, i, b, y, q in zip(gs, gi, gb, gy, gq)))
+    assert sets[0] == sets[1] and len(sets[0]) > 0
+
+
 @pytest.mark.parametrize("sched", [dict(tile=4096), dict(tile=8192), dict(tile=16384), dict(tile=32768),
                                    dict(tile=8192, group_threads=512), dict(tile=32768, group_threads=512)])
 def test_schedules_give_identical_results(small_open, sched):

@@ -393,6 +393,56 @@ def test_search_invariant_under_permutations_and_splits():
     assert _same(np.concatenate([ha, hb]), h0) and _same(np.concatenate([sa, sb]), s0)
 
 
+def _permute_proteins(prot, perm):
+    """The proteome with its proteins in the order `perm`."""
+    seqs = [prot.residues[int(prot.offsets[i]):int(prot.offsets[i + 1])] for i in range(len(prot.offsets) - 1)]
+    res = np.concatenate([seqs[i] for i in perm]).astype(np.uint8)
+    off = np.zeros(len(perm) + 1, np.uint64)
+    off[1:] = np.cumsum([len(seqs[i]) for i in perm])
+    return res, off
+
+
+def _peptide_keys(table, residues, offsets):
+    """A protein-order-free name for every entry: its residues, whether it
+    starts its protein (where an N-terminal modification may sit), its sites."""
+    keys = []
+    for r in table:
+        a = int(offsets[int(r["prot"])]) + int(r["start"])
+        keys.append((bytes(residues[a:a + int(r["len"])]), int(r["start"]) == 0, int(r["mask"])))
+    return keys
+
+
+def test_search_invariant_under_protein_order():
+    """Permuting the proteins renumbers the peptides (ids follow mass, then
+    protein), but every spectrum keeps its window, its scored set (as peptides
+    with their counts), its histogram, expect value and top hyperscores."""
+    from collections import Counter
+    w = synth.workload("tiny")
+    prot = synth.make_proteome(120, seed=0)
+    mods = oracle.mods_from_synth([synth.OXIDATION, synth.ACETYL_NTERM])
+    sp = w.spectra(prot, n=30, seed=9)
+    res2, off2 = _permute_proteins(prot, np.random.default_rng(3).permutation(len(prot.offsets) - 1))
+    db1 = oracle.Database(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len, mods, 2)
+    db2 = oracle.Database(res2, off2, w.missed, w.min_len, w.max_len, mods, 2)
+    assert len(db1) == len(db2)
+    args = (True, 10, 2, 100, 5, 2)
+    h1, s1, g1 = db1.search(sp, *args, threads=4)
+    h2, s2, g2 = db2.search(sp, *args, threads=4)
+    assert _same(s1, s2) and _same(g1, g2)
+    assert _same(h1["hyperscore"], h2["hyperscore"])
+    k1 = _peptide_keys(db1.table(), prot.residues, prot.offsets)
+    k2 = _peptide_keys(db2.table(), res2, off2)
+    n_sets = 0
+    for s in range(sp.n):
+        a = db1.scored(sp, s, *args[:4], min_shared=2)
+        b = db2.scored(sp, s, *args[:4], min_shared=2)
+        ca = Counter((k1[int(i)], int(x), int(y), int(q)) for i, x, y, q in zip(*a))
+        cb = Counter((k2[int(i)], int(x), int(y), int(q)) for i, x, y, q in zip(*b))
+        assert ca == cb
+        n_sets += len(ca) > 0
+    assert n_sets >= 20
+
+
 def test_self_search_finds_source_peptide():
     """A noise-free theoretical spectrum of p shares every b/y ion with p
     (pairs >= 2(n-1)), and p ranks first unless an isobaric twin with a lower id
