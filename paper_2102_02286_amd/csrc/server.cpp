@@ -298,6 +298,9 @@ static void scheduler(ps_server* S) {
             progressed = true;
             lk.unlock();                        // staging and launches need no lock
             const int rc = enqueue_run(S, L, nnz);
+            // a run that failed part-way may have work queued on its range:
+            // it must end before complete() returns the range to the arena
+            if (rc != PS_OK) (void)hipStreamSynchronize(L.stream);
             lk.lock();
             if (rc != PS_OK) { complete(S, L, rc); S->cv_done.notify_all(); }
         }
