@@ -582,13 +582,18 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     ps_index* ix = nullptr;
     int rc = index_prepare(params, residues, prot_off, n_proteins, &ix);
     if (rc != PS_OK) return rc;
-    auto bail = [&](int code) { delete ix; return code; };
+    hipStream_t st = (hipStream_t)index_block->stream;
+    bool queued = false;                  // work on `st` may read host buffers of this function
+    auto bail = [&](int code) {
+        if (queued) (void)hipStreamSynchronize(st);
+        delete ix;
+        return code;
+    };
     rc = require_device();
     if (rc != PS_OK) return bail(rc);
     Census C;
     rc = census(ix, C);
     if (rc != PS_OK) return bail(rc);
-    hipStream_t st = (hipStream_t)index_block->stream;
     hipError_t e = hipSuccess;
     const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
     const uint64_t tb = temp_bytes_for(C, chunk, st, &e);
@@ -623,6 +628,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     const uint64_t n_prot = ix->prot_off.size() - 1;
 
     // inputs
+    queued = true;
     chk(hipMemcpyAsync(S.seq, ix->seq.data(), ix->seq.size(), hipMemcpyHostToDevice, st));
     chk(hipMemcpyAsync(S.prot_off, ix->prot_off.data(), (n_prot + 1) * 8, hipMemcpyHostToDevice, st));
     const uint64_t n_starts = C.st_prot.size();

@@ -273,6 +273,13 @@ static void batch_destroy(ps_batch* B) {
     delete B;
 }
 
+// A batch that failed after work was enqueued: that work may still read the
+// pinned buffers, so its stream is drained before they are freed.
+static void batch_abort(ps_batch* B) {
+    (void)hipStreamSynchronize(B->stream);
+    batch_destroy(B);
+}
+
 // Common batch set-up; inputs either copied from host (host_sp) or device-resident (dev_sp).
 int batch_begin(ps_index* ix, const ps_device* work, const ps_spectra* host_sp, const ps_spectra* dev_sp,
                 uint64_t dev_nnz, const ps_search_params* params, uint64_t dump_cap, ps_batch** out) {
@@ -343,11 +350,11 @@ int batch_begin(ps_index* ix, const ps_device* work, const ps_spectra* host_sp, 
             chk(hipMemcpyAsync((void*)dsp.prec, h + (n + 1) * 8 + nnz * 8, n * 8, hipMemcpyHostToDevice, B->stream));
             chk(hipMemcpyAsync((void*)dsp.charge, h + (n + 1) * 8 + nnz * 8 + n * 8, n, hipMemcpyHostToDevice, B->stream));
         }
-        if (e != hipSuccess) { batch_destroy(B); return fail(PS_EDEVICE, "input copy: %s", hipGetErrorString(e)); }
+        if (e != hipSuccess) { batch_abort(B); return fail(PS_EDEVICE, "input copy: %s", hipGetErrorString(e)); }
     }
     if (n) {
         rc = enqueue_search(B);
-        if (rc != PS_OK) { batch_destroy(B); return rc; }
+        if (rc != PS_OK) { batch_abort(B); return rc; }
     } else {
         (void)hipEventRecord(B->ev_scan0, B->stream);
         (void)hipEventRecord(B->ev_scan1, B->stream);

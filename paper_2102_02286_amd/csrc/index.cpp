@@ -644,7 +644,10 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
     cp(lay.dir, ix->dir.data(), ix->dir.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = upload_padded_postings(ix, (uint32_t*)(base + lay.post), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);                  // queued copies read lf, ls and bq
+        return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
+    }
     bind_device_index(ix, base, lay);
     return PS_OK;
 }

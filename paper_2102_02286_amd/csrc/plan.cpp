@@ -157,7 +157,11 @@ static int plan_launch(ps_plan* P) {
     }
     chk(hipMemcpyAsync(P->h_counters, P->w.counters, 8 * 8, hipMemcpyDeviceToHost, st));
     chk(hipEventRecord(P->ev_done, st));
-    if (e != hipSuccess) return fail(PS_EDEVICE, "plan launch: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        // whatever was enqueued may still use the pinned buffers: let it end
+        (void)hipStreamSynchronize(st);
+        return fail(PS_EDEVICE, "plan launch: %s", hipGetErrorString(e));
+    }
     P->in_flight = true;
     return PS_OK;
 }
@@ -191,7 +195,10 @@ extern "C" int ps_plan_run(ps_plan* P, const ps_spectra* sp) {
         }
         chk(hipMemcpyAsync((void*)P->dsp.prec, h + o_pr, n * 8, hipMemcpyHostToDevice, st));
         chk(hipMemcpyAsync((void*)P->dsp.charge, h + o_z, n, hipMemcpyHostToDevice, st));
-        if (e != hipSuccess) return fail(PS_EDEVICE, "plan input copy: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(st);              // copies already queued read the staging buffer
+            return fail(PS_EDEVICE, "plan input copy: %s", hipGetErrorString(e));
+        }
     }
     return plan_launch(P);
 }
