@@ -548,7 +548,7 @@ typedef struct {
     double   elapsed_s;       /* first submit to last completion */
 } ps_serve_stats;
 
-/* A search server over an uploaded index (BASELINE's serving loop; the paper's
+/* A search server over an uploaded index (continuous batching; the paper's
  * analogue is Superstep 3's Buffering: a producer/consumer pipeline over
  * recycled buffers, and Supplementary Algorithm 5's memory guard).  The device
  * `pool` (256-byte aligned, owned by the caller, kept alive until
