@@ -556,7 +556,7 @@ def main():
                     help="time one form only (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the index scan and its results are "
+        print(json.dumps({"error": "the search runs on one GPU: the index scan and its results are "
                                    "measured on one MI355X, so --gpus must be 1"}))
         sys.exit(2)
 
