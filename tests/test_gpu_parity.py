@@ -68,6 +68,51 @@ def test_tiny_full_batch_parity(tiny, schedule):
     assert res.postings == int(ost["pairs_total"].sum())
 
 
+class _OneCallIndex:
+    """An index from ps_build_index and the device block it lives in."""
+
+    def __init__(self, handle, arena):
+        self.handle, self.arena = handle, arena
+
+    def __del__(self):
+        if self.handle is not None and self.handle.value:
+            capi.ps_index_free(self.handle)
+            self.handle = None
+
+
+def test_one_call_build_equals_create_and_upload(tiny):
+    """ps_build_index (the index created and uploaded in one call) searches
+    exactly as ps_index_create + ps_index_upload, and as the oracle; a block
+    one byte too small is refused and leaves no index."""
+    import torch
+    w, prot, sp, ix, db = tiny
+    p, keep = engine._db_params(w.missed, w.min_len, w.max_len, [], 0)
+    res = np.ascontiguousarray(prot.residues, dtype=np.uint8)
+    off = np.ascontiguousarray(prot.offsets, dtype=np.uint64)
+    need = C.c_uint64()
+    capi.check(capi.ps_index_device_bytes(ix.handle, C.byref(need)))
+    arena = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    small = capi.ps_device(arena.data_ptr(), need.value - 1, st)
+    h = C.c_void_p()
+    _say("one-call build: a block one byte short")
+    assert capi.ps_build_index(C.byref(small), C.byref(p), capi.ptr(res), capi.ptr(off), off.shape[0] - 1,
+                               C.byref(h)) == capi.PS_ENOMEM
+    assert not h.value
+    dev = capi.ps_device(arena.data_ptr(), arena.numel(), st)
+    _say("one-call build")
+    capi.check(capi.ps_build_index(C.byref(dev), C.byref(p), capi.ptr(res), capi.ptr(off), off.shape[0] - 1,
+                                   C.byref(h)), "ps_build_index")
+    one = _OneCallIndex(h, arena)
+    assert engine.HostIndex.shape(one) == ix.shape()
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
+                               max_charge=2)
+    r1, r0 = engine.search(one, sp, prm), engine.search(ix, sp, prm)
+    assert r1.hits.tobytes() == r0.hits.tobytes() and r1.hist.tobytes() == r0.hist.tobytes()
+    oh, ost, og = db.search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared)
+    assert_parity(r1, oh, ost, og)
+
+
 def test_tiny_scored_set_dump(tiny):
     w, prot, sp, ix, db = tiny
     sub = sp.subset(np.arange(0, 200))
@@ -233,6 +278,15 @@ def test_plan_graph_replays_match_eager_and_oracle(small_open):
     prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, w.min_shared,
                                max_charge=3, schedule=capi.PS_SCHED_PERSISTENT)
     plan = engine.Plan(ix, prm, n_cap=sp.n, nnz_cap=int(sp.peak_off[-1]))
+    own = C.c_void_p()
+    capi.check(capi.ps_plan_stream(plan.handle, C.byref(own)))
+    assert own.value                                   # no stream given: the plan made its own
+    given = torch.cuda.Stream()                        # default priority
+    plan_on = engine.Plan(ix, prm, n_cap=4, nnz_cap=int(sp.peak_off[4]), stream=given)
+    got_on = C.c_void_p()
+    capi.check(capi.ps_plan_stream(plan_on.handle, C.byref(got_on)))
+    assert got_on.value == given.cuda_stream
+    del plan_on
     ranges = [(0, sp.n), (10, 50), (0, 1), (100, sp.n), (0, sp.n), (33, 34)]
     for k, (a, b) in enumerate(ranges):
         sub = sp.subset(np.arange(a, b))
