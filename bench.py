@@ -516,7 +516,10 @@ def node_share_leg(capi, engine, torch, synth, args):
         out["forms"][name] = {"spectra_per_s": sp.n / dt, "ms_per_step": dt * 1e3, "scan_ms": scan,
                               "achieved_GBs": alg / (scan * 1e-3) / 1e9,
                               "frac": alg / (scan * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "postings": res.postings, "wide_counter_spectra": res.wide_spectra,
+                              "postings": res.postings, "dense_postings": res.dense_postings,
+                              "layout_GBs": (4.0 * (res.postings - res.dense_postings) + 16.0 * res.lookups
+                                             + res.dense_reads) / (scan * 1e-3) / 1e9,
+                              "wide_counter_spectra": res.wide_spectra,
                               "schedule": {"tile": best.tile, "group_threads": best.group_threads,
                                            "tiles_per_item": best.tiles_per_item,
                                            "groups_per_cu": best.groups_per_cu}}
@@ -551,6 +554,8 @@ def main():
     ap.add_argument("--shards", type=int, default=4,
                     help="also search G round-robin database partitions and assemble them (0: skip)")
     ap.add_argument("--no-node-share", action="store_true", help="skip the node-share partition leg")
+    ap.add_argument("--no-dense-compare", action="store_true",
+                    help="skip the eager run with every list streamed (dense maps off)")
     ap.add_argument("--node-spectra", type=int, default=20000, help="spectra of the node-share slice")
     ap.add_argument("--only", choices=["plain", "persistent"], default=None,
                     help="time one form only (for profiling runs)")
@@ -633,6 +638,26 @@ def main():
             "plain and persistent results differ"
         assert eager["plain"]["res"].stats.tobytes() == eager["persistent"]["res"].stats.tobytes()
 
+    # ---- the same eager search with every list streamed as postings (dense maps
+    # off): what the maps of the y1 lists save, at identical results
+    streamed = None
+    if not args.no_dense_compare and eager:
+        name = "persistent" if "persistent" in eager else "plain"
+        prm = prm_pers if name == "persistent" else prm_plain
+        use(name)
+        ix.set_dense(False)
+        try:
+            eager_steps(capi, engine, ix, dsp, sp.n, nnz, prm, ws_dev, 1)
+            scan_ms, res = eager_steps(capi, engine, ix, dsp, sp.n, nnz, prm, ws_dev, args.steps)
+        finally:
+            ix.set_dense(True)
+        assert res.hits.tobytes() == eager[name]["res"].hits.tobytes(), "dense maps changed the results"
+        assert res.stats.tobytes() == eager[name]["res"].stats.tobytes(), "dense maps changed the results"
+        streamed = {"schedule": name, "scan_ms": float(np.mean(scan_ms)), "dense_scan_ms": eager[name]["scan_ms"],
+                    "speedup": float(np.mean(scan_ms)) / eager[name]["scan_ms"]}
+        log(f"{name} eager with every list streamed (no dense maps): scan {streamed['scan_ms']:.1f} ms vs "
+            f"{eager[name]['scan_ms']:.1f} ms with them ({streamed['speedup']:.2f}x), identical results")
+
     # ---- graph plans over the resident batch (both schedules); the faster is the headline
     def graph_steps(name, prm, eager_ref):
         use(name)
@@ -695,9 +720,14 @@ def main():
     postings, lookups = ref.postings, ref.lookups
     alg_bytes = 4.0 * postings + 16.0 * lookups
     achieved = alg_bytes / (head_scan * 1e-3) / 1e9
+    # what the layout reads: streamed postings, bin lookups, and two bits per id
+    # of every dense probe's map
+    streamed_post = postings - ref.dense_postings
+    layout_bytes = 4.0 * streamed_post + 16.0 * lookups + 1.0 * ref.dense_reads
+    layout_gbs = layout_bytes / (head_scan * 1e-3) / 1e9
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
-    lds_gops = postings / (head_scan * 1e-3) / 1e9
+    lds_gops = streamed_post / (head_scan * 1e-3) / 1e9
     out.update({
         "metric": "spectra searched/sec at 1 MI355X (serving vs plain batch), p99 latency, HBM GB/s %",
         "value": forms[form]["spectra_per_s"],
@@ -725,9 +755,16 @@ def main():
                      "bytes_per_launch": alg_bytes, "postings_per_launch": postings,
                      "bin_lookups_per_launch": lookups, "copy_GBs": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs,
+                     "layout": {"bytes_per_launch": layout_bytes, "achieved": layout_gbs,
+                                "frac": layout_gbs / HBM_PEAK_GBS, "dense_postings": ref.dense_postings,
+                                "dense_map_reads": ref.dense_reads,
+                                "note": "bytes the index layout reads: 4 B per streamed posting, 16 B per "
+                                        "bin lookup, 1 B per dense-map read; the 4-byte figure above "
+                                        "counts every posting"},
                      "lds_atomics": {"achieved_Gops": lds_gops, "peak_Gops": LDS_ATOMIC_PEAK_GOPS,
                                      "frac": lds_gops / LDS_ATOMIC_PEAK_GOPS,
-                                     "note": "one 4-byte LDS atomic per posting"}},
+                                     "note": "one 4-byte LDS atomic per streamed posting"}},
+        "streamed_only": streamed,
         "wide_counter_spectra": int(ref.wide_spectra),
         "overflow_spectra": int(ref.overflow_spectra),
         "forms": {k: {**forms[k], "eager_spectra_per_s": eager[k]["spectra_per_s"],
@@ -740,7 +777,9 @@ def main():
                         "device_bytes": ix.arena.numel(), "directory_bytes": dir_bytes},
     })
     log(f"headline: {form} graph {forms[form]['spectra_per_s']:.0f} spectra/s; roofline: {alg_bytes / 1e9:.1f} GB "
-        f"algorithmic per step in {head_scan:.1f} ms = {achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}%)")
+        f"algorithmic per step in {head_scan:.1f} ms = {achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}%); "
+        f"the layout reads {layout_bytes / 1e9:.1f} GB = {layout_gbs:.0f} GB/s ({100 * layout_gbs / HBM_PEAK_GBS:.1f}%), "
+        f"{100 * ref.dense_postings / max(postings, 1):.1f}% of postings through dense maps")
 
     # ---- partitioned database: G partition searches + on-device result assembly
     if args.shards > 1 and "plain" in eager:

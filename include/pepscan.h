@@ -298,6 +298,31 @@ int ps_index_get_schedule(const ps_index* idx, ps_schedule* schedule);
  * (the padding repeats the list's length).  Any pointer may be NULL. */
 int ps_index_directory(const ps_index* idx, uint32_t* grain_shift, uint64_t* bytes, uint32_t* dir);
 
+/* Dense lists.  Filter_2 of Superstep 3 counts, for every candidate in the
+ * window, the fragment bins it shares with the spectrum.  A few bins are
+ * shared by a large part of a tryptic database (the y1 ions of K and R hold
+ * about half of all peptides each), so their lists are nearly as long as the
+ * id range itself and take a large share of the scan.  Every list with at
+ * least n_pep / 4 postings (the longest PS_MAX_DENSE) also gets a map of two
+ * bits per peptide id on the device: one for a C-terminal (y-like) and one
+ * for an N-terminal (b-like) posting of that id.  A probe on such a list is
+ * then not streamed: the candidate filter admits every id whose other shared
+ * peaks reach min_shared less the most the map probes could add, and each
+ * admitted candidate reads its bits from the maps before it is scored or
+ * dropped.  Results are identical either way.  Map probes are used only while
+ * that lowered threshold stays at 2 or more (so with min_shared >= 3), at most
+ * four per work item; others are streamed.  A list in which an (id, terminus)
+ * pair repeats, or whose bin is 2^24 or above, keeps no map.  The maps cost
+ * ceil(n_pep / 32768) * 8192 bytes each, in the index block.
+ *
+ * ps_index_dense: the number of maps (n_dense) and their bins (bins, room for
+ * PS_MAX_DENSE, may be NULL); `enabled` says whether searches use them.
+ * ps_index_set_dense: 0 makes later searches (and plans created afterwards)
+ * stream every list, nonzero uses the maps again.  PS_EINVAL for NULL. */
+#define PS_MAX_DENSE 8
+int ps_index_dense(const ps_index* idx, uint32_t* n_dense, uint32_t* bins, int* enabled);
+int ps_index_set_dense(ps_index* idx, int enabled);
+
 void ps_index_free(ps_index* idx);
 
 /* ---- one batch --------------------------------------------------------- */
@@ -366,7 +391,9 @@ typedef struct {
     uint64_t work_items;        /* persistent work items (0 for the plain schedule) */
     uint64_t wide_spectra;      /* spectra whose counter bound needs the 64-bit counters */
     uint64_t overflow_spectra;  /* spectra reported PS_STATUS_OVERFLOW */
-    uint64_t reserved[3];
+    uint64_t dense_postings;    /* of `postings`, those counted through dense maps (ps_index_dense) */
+    uint64_t dense_reads;       /* dense-map reads: candidates times dense probes */
+    uint64_t reserved[1];
 } ps_counters;
 
 /* Blocks until the batch is done, then writes its counters.  PS_EINVAL for NULL. */

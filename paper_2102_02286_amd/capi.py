@@ -18,6 +18,7 @@ PS_OK, PS_EINVAL, PS_ENOMEM, PS_EAGAIN, PS_EDEVICE, PS_EOVERFLOW = 0, 1, 2, 3, 4
 PS_STATUS_OK, PS_STATUS_NO_HITS, PS_STATUS_FEW_POINTS, PS_STATUS_BAD_SLOPE, PS_STATUS_INVALID, \
     PS_STATUS_OVERFLOW = 0, 1, 2, 3, 4, 5
 PS_HIST_BINS = 512
+PS_MAX_DENSE = 8
 PS_MAX_PEAKS_IN = 4096
 PS_STATIC_SCRATCH_BYTES = 256 << 20
 PS_SCHED_PLAIN, PS_SCHED_PERSISTENT = 0, 1
@@ -77,7 +78,8 @@ class ps_tune_trial(C.Structure):
 
 class ps_counters(C.Structure):
     _fields_ = [("postings", C.c_uint64), ("bin_lookups", C.c_uint64), ("work_items", C.c_uint64),
-                ("wide_spectra", C.c_uint64), ("overflow_spectra", C.c_uint64), ("reserved", C.c_uint64 * 3)]
+                ("wide_spectra", C.c_uint64), ("overflow_spectra", C.c_uint64), ("dense_postings", C.c_uint64),
+                ("dense_reads", C.c_uint64), ("reserved", C.c_uint64 * 1)]
 
 
 class ps_serve_stats(C.Structure):
@@ -125,6 +127,8 @@ _SIGS = [
     ("ps_index_set_schedule", C.c_int, [_P, C.POINTER(ps_schedule)]),
     ("ps_index_get_schedule", C.c_int, [_P, C.POINTER(ps_schedule)]),
     ("ps_index_directory", C.c_int, [_P, C.POINTER(C.c_uint32), _U64P, C.c_void_p]),
+    ("ps_index_dense", C.c_int, [_P, C.POINTER(C.c_uint32), C.c_void_p, C.POINTER(C.c_int)]),
+    ("ps_index_set_dense", C.c_int, [_P, C.c_int]),
     ("ps_index_free", None, [_P]),
     ("ps_workspace_bytes", C.c_int, [_P, C.c_uint64, C.c_uint64, C.POINTER(ps_search_params), _U64P]),
     ("ps_search_batch", C.c_int, [_P, C.POINTER(ps_device), C.POINTER(ps_spectra),
@@ -222,6 +226,8 @@ ps_index_host_arrays = _fn("ps_index_host_arrays")
 ps_index_set_schedule = _fn("ps_index_set_schedule")
 ps_index_get_schedule = _fn("ps_index_get_schedule")
 ps_index_directory = _fn("ps_index_directory")
+ps_index_dense = _fn("ps_index_dense")
+ps_index_set_dense = _fn("ps_index_set_dense")
 ps_index_free = _fn("ps_index_free")
 ps_workspace_bytes = _fn("ps_workspace_bytes")
 ps_search_batch = _fn("ps_search_batch")

@@ -551,6 +551,77 @@ uint64_t chunk_pairs(const Census& C, uint64_t cap, uint32_t width) {
 
 using namespace ps;
 
+// One list's dense map: every posting sets its id's bit (C-terminal bits
+// 0-3, N-terminal bits 4-7 of byte id / 4).  flags bit 0: a bit was already
+// set (the list repeats an (id, terminus) pair, which a map cannot hold);
+// bit 1: some id has postings of both termini (a probe on the list can add 2
+// to that id's count).
+// Grid-stride: a list can hold more postings than one capped grid has threads.
+__global__ void k_dense_map(const uint32_t* list, uint64_t len, uint32_t* map, uint32_t* flags) {
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t f = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += step) {
+        const uint32_t p = list[i];
+        const uint32_t id = p >> 1;
+        const uint32_t bit = ((id >> 2) & 3u) * 8u + (id & 3u) + ((p & 1u) ? 0u : 4u);
+        const uint32_t old = atomicOr(&map[id >> 4], 1u << bit);
+        if (old & (1u << bit)) f |= 1u;
+        if (old & (1u << (bit ^ 4u))) f |= 2u;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+namespace ps {
+
+int build_dense_maps(ps_index* ix, char* base, const DevLayout& lay, hipStream_t st) {
+    ix->n_dense = 0;
+    bind_dense(ix);
+    const std::vector<uint32_t> cand = dense_candidates(ix);
+    const uint32_t nc = std::min<uint32_t>((uint32_t)cand.size(), lay.dense_cap);
+    if (nc == 0) return PS_OK;
+    // first quad of every bin's padded list
+    std::vector<uint64_t> q0(ix->n_bins + 1, 0);
+    for (uint64_t b = 0; b < ix->n_bins; ++b) q0[b + 1] = q0[b] + ((ix->bin_off[b + 1] - ix->bin_off[b] + 3) >> 2);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    uint32_t* flags = (uint32_t*)(base + lay.dense_flags);
+    chk(launch_fill_u32(base + lay.dense, 0u, (uint64_t)nc * lay.dense_stride / 4, st));
+    chk(launch_fill_u32(flags, 0u, kMaxDense, st));
+    for (uint32_t k = 0; k < nc && e == hipSuccess; ++k) {
+        const uint32_t b = cand[k];
+        const uint64_t len = ix->bin_off[b + 1] - ix->bin_off[b];
+        hipLaunchKernelGGL(k_dense_map, dim3(grid_for(len)), dim3(256), 0, st, ix->dev.post + 4 * q0[b], len,
+                           (uint32_t*)(base + lay.dense + (uint64_t)k * lay.dense_stride), flags + k);
+        chk(hipGetLastError());
+    }
+    uint32_t rep[kMaxDense] = {};
+    chk(hipMemcpyAsync(rep, flags, sizeof rep, hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    if (e != hipSuccess) return fail(PS_EDEVICE, "dense maps: %s", hipGetErrorString(e));
+    uint32_t tab[kMaxDense] = {};
+    uint32_t n = 0;
+    for (uint32_t k = 0; k < nc; ++k) {
+        if ((rep[k] & 1u) || cand[k] >= (1u << 24)) continue;   // the list stays postings only
+        ix->dense_bin[n] = cand[k];
+        tab[n] = cand[k] | ((rep[k] & 2u) ? 2u : 1u) << 24 | k << 28;
+        ++n;
+    }
+    if (n) {
+        chk(hipMemcpyAsync(flags + kMaxDense, tab, sizeof tab, hipMemcpyHostToDevice, st));
+        chk(hipStreamSynchronize(st));
+        if (e != hipSuccess) return fail(PS_EDEVICE, "dense maps: %s", hipGetErrorString(e));
+    }
+    DevIndex& d = ix->dev;
+    d.dense_tab = flags + kMaxDense;
+    d.dense_maps = (const uint8_t*)(base + lay.dense);
+    d.dense_stride = lay.dense_stride;
+    ix->n_dense = n;
+    bind_dense(ix);
+    return PS_OK;
+}
+
+}  // namespace ps
+
 extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const char* residues, const uint64_t* prot_off,
                                            uint64_t n_proteins, uint64_t chunk_pairs_cap, uint64_t* index_bytes,
                                            uint64_t* scratch_bytes) {
@@ -566,7 +637,7 @@ extern "C" int ps_index_build_device_bytes(const ps_db_params* params, const cha
         const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
         const uint64_t tb = temp_bytes_for(C, chunk, nullptr, &e);
         if (e != hipSuccess) rc = fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e));
-        *index_bytes = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride, true).total;
+        *index_bytes = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride, true, kMaxDense).total;
         *scratch_bytes = layout_scratch(nullptr, ix, C, chunk, tb).total;
     }
     delete ix;
@@ -598,7 +669,7 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     const uint64_t chunk = chunk_pairs(C, chunk_pairs_cap, 2u * ix->merge_tol + 1u);
     const uint64_t tb = temp_bytes_for(C, chunk, st, &e);
     if (e != hipSuccess) return bail(fail(PS_EDEVICE, "sort workspace query: %s", hipGetErrorString(e)));
-    const DevLayout lay = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride, true);
+    const DevLayout lay = index_layout(C.D, C.n_bins, C.quad_cap, C.n_bins * C.dir_stride, true, kMaxDense);
     const Scratch need = layout_scratch(nullptr, ix, C, chunk, tb);
     if (!index_block->base || index_block->bytes < lay.total)
         return bail(fail(PS_ENOMEM, "index needs %llu device bytes, block has %llu", (unsigned long long)lay.total,
@@ -788,6 +859,8 @@ extern "C" int ps_index_build_device(const ps_db_params* params, const char* res
     ix->dev_n_quads = quads;
     ix->dev_dir_entries = C.n_bins * C.dir_stride;
     bind_device_index(ix, base, lay);
+    rc = build_dense_maps(ix, base, lay, st);
+    if (rc != PS_OK) return bail(rc);
     if (ix->sched.tile < (1u << ix->dir_shift)) ix->sched.tile = 1u << ix->dir_shift;
     *out = ix;
     return PS_OK;

@@ -163,7 +163,7 @@ uint64_t layout_work(uint64_t n, uint64_t nnz, const KParams& kp, bool copy_inpu
     t.spec_item0 = (uint32_t*)take((n + 1) * 4);
     t.hits = (ps_hit*)take(n * (uint64_t)kp.top_k * sizeof(ps_hit));
     t.stats = (ps_stat*)take(n * sizeof(ps_stat));
-    t.counters = (unsigned long long*)take(8 * 8);
+    t.counters = (unsigned long long*)take(kNumCounters * 8);
     if (dump_cap) {
         t.dump_spec = (uint32_t*)take(dump_cap * 4);
         t.dump_id = (uint32_t*)take(dump_cap * 4);
@@ -223,7 +223,7 @@ hipError_t enqueue_kernels(const ps_index* ix, const DevSpectra& dsp, const KPar
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
     chk(launch_fill_per_spectrum(w.hist, 0, (uint64_t)kHistBins, dsp.n * (uint64_t)kHistBins, w.hdr, st));
     chk(launch_fill_per_spectrum(w.n_scored, 0, 2, dsp.n * 2, w.hdr, st));
-    chk(launch_fill_u32(w.counters, 0, 16, st));
+    chk(launch_fill_u32(w.counters, 0, 2 * kNumCounters, st));
     chk(launch_prep(ix->dev, dsp, kp, w, st));
     if (ev0) chk(hipEventRecord(ev0, st));
     const bool per_item = schedule == PS_SCHED_PERSISTENT;
@@ -252,7 +252,7 @@ int enqueue_search(ps_batch* B) {
     chk(hipMemcpyAsync(B->h_hits, w.hits, n * (uint64_t)B->kp.top_k * sizeof(ps_hit), hipMemcpyDeviceToHost, st));
     chk(hipMemcpyAsync(B->h_stats, w.stats, n * sizeof(ps_stat), hipMemcpyDeviceToHost, st));
     if (B->want_hist) chk(hipMemcpyAsync(B->h_hist, w.hist, n * (uint64_t)kHistBins * 4, hipMemcpyDeviceToHost, st));
-    chk(hipMemcpyAsync(B->h_counters, w.counters, 8 * 8, hipMemcpyDeviceToHost, st));
+    chk(hipMemcpyAsync(B->h_counters, w.counters, kNumCounters * 8, hipMemcpyDeviceToHost, st));
     chk(hipEventRecord(B->ev_done, st));
     if (e != hipSuccess) return fail(PS_EDEVICE, "enqueue: %s", hipGetErrorString(e));
     B->scan_launches = 2;
@@ -327,7 +327,7 @@ int batch_begin(ps_index* ix, const ps_device* work, const ps_spectra* host_sp, 
     chk(hipHostMalloc((void**)&B->h_hits, nh * kp.top_k * sizeof(ps_hit), hipHostMallocDefault));
     chk(hipHostMalloc((void**)&B->h_stats, nh * sizeof(ps_stat), hipHostMallocDefault));
     if (B->want_hist) chk(hipHostMalloc((void**)&B->h_hist, nh * (uint64_t)kHistBins * 4, hipHostMallocDefault));
-    chk(hipHostMalloc((void**)&B->h_counters, 8 * 8, hipHostMallocDefault));
+    chk(hipHostMalloc((void**)&B->h_counters, kNumCounters * 8, hipHostMallocDefault));
     chk(hipHostMalloc((void**)&B->h_hdr, sizeof(BatchHdr), hipHostMallocDefault));
     if (e == hipSuccess) { B->h_hdr->n = n; B->h_hdr->nnz = nnz; }
     if (e != hipSuccess) { batch_destroy(B); return fail(PS_EDEVICE, "batch set-up: %s", hipGetErrorString(e)); }
@@ -479,6 +479,8 @@ extern "C" int ps_batch_counters(ps_batch* B, ps_counters* out) {
         out->work_items = B->schedule == PS_SCHED_PERSISTENT ? c[kCtrItems] : 0;
         out->wide_spectra = c[kCtrWide];
         out->overflow_spectra = c[kCtrOverflow];
+        out->dense_postings = c[kCtrDensePost];
+        out->dense_reads = c[kCtrDenseIds];
     }
     return PS_OK;
 }

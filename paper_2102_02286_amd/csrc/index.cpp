@@ -392,7 +392,8 @@ uint32_t directory_shift(uint64_t nbins, uint64_t D) {
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir, bool entries) {
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir, bool entries,
+                       uint32_t dense_cap) {
     DevLayout L;
     uint64_t o = 0;
     L.mass = o; o = align256(o + n_pep * sizeof(int64_t));
@@ -406,12 +407,35 @@ DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64
     L.start = o; o = align256(o + ne * sizeof(uint32_t));
     L.mask = o; o = align256(o + ne * sizeof(uint64_t));
     L.len = o; o = align256(o + ne);
+    L.dense_cap = n_pep ? dense_cap : 0u;
+    L.dense_stride = align256(dense_map_bytes(n_pep));
+    L.dense = o; o = align256(o + (uint64_t)L.dense_cap * L.dense_stride);
+    L.dense_flags = o; o = align256(o + 2 * kMaxDense * sizeof(uint32_t));
     L.total = o;
     return L;
 }
 
+std::vector<uint32_t> dense_candidates(const ps_index* ix) {
+    std::vector<std::pair<uint64_t, uint32_t>> c;
+    const uint64_t D = ix->n_entries;
+    for (uint64_t b = 0; D && b + 1 < ix->bin_off.size(); ++b) {
+        const uint64_t len = ix->bin_off[b + 1] - ix->bin_off[b];
+        if (len * 4 >= D) c.push_back({len, (uint32_t)b});
+    }
+    std::sort(c.begin(), c.end(), [](const auto& a, const auto& b) { return a.first > b.first || (a.first == b.first && a.second < b.second); });
+    std::vector<uint32_t> out;
+    for (size_t i = 0; i < c.size() && i < kMaxDense; ++i) out.push_back(c[i].second);
+    return out;
+}
+
+void bind_dense(ps_index* ix) {
+    DevIndex& d = ix->dev;
+    d.n_dense = ix->dense_on ? ix->n_dense : 0u;
+}
+
 static DevLayout index_device_layout(const ps_index* ix) {
-    return index_layout(ix->n_entries, ix->n_bins, padded_quads(ix), dir_entries(ix));
+    return index_layout(ix->n_entries, ix->n_bins, padded_quads(ix), dir_entries(ix), false,
+                        (uint32_t)dense_candidates(ix).size());
 }
 
 void bind_device_index(ps_index* ix, char* base, const DevLayout& lay) {
@@ -649,6 +673,8 @@ extern "C" int ps_index_upload(ps_index* ix, const ps_device* dev) {
         return fail(PS_EDEVICE, "index upload: %s", hipGetErrorString(e));
     }
     bind_device_index(ix, base, lay);
+    rc = build_dense_maps(ix, base, lay, st);
+    if (rc != PS_OK) { ix->on_device = false; return rc; }
     return PS_OK;
 }
 
@@ -770,6 +796,21 @@ extern "C" int ps_index_host_arrays(const ps_index* ix, uint64_t* bin_off, uint3
     } else if (postings) {
         memcpy(postings, ix->post.data(), ix->post.size() * sizeof(uint32_t));
     }
+    return PS_OK;
+}
+
+extern "C" int ps_index_dense(const ps_index* ix, uint32_t* n_dense, uint32_t* bins, int* enabled) {
+    if (!ix) return fail(PS_EINVAL, "NULL index");
+    if (n_dense) *n_dense = ix->n_dense;
+    if (bins) for (uint32_t k = 0; k < ix->n_dense; ++k) bins[k] = ix->dense_bin[k];
+    if (enabled) *enabled = ix->dense_on ? 1 : 0;
+    return PS_OK;
+}
+
+extern "C" int ps_index_set_dense(ps_index* ix, int enabled) {
+    if (!ix) return fail(PS_EINVAL, "NULL index");
+    ix->dense_on = enabled != 0;
+    bind_dense(ix);
     return PS_OK;
 }
 

@@ -56,6 +56,13 @@ enum : uint32_t {
     kFlagOverflow = 4u,     // even 64-bit counters / tables cannot hold it
 };
 
+constexpr uint32_t kMaxDense = PS_MAX_DENSE;   // dense maps per index
+static_assert(kMaxDense <= 8, "a dense table entry holds a 3-bit map slot");
+constexpr uint64_t kDenseIdAlign = 32768;      // the largest tile: maps cover whole tiles
+inline uint64_t dense_map_bytes(uint64_t n_pep) {
+    return (n_pep + kDenseIdAlign - 1) / kDenseIdAlign * (kDenseIdAlign / 4);
+}
+
 // Device view of an uploaded index.
 struct DevIndex {
     const int64_t* mass;       // [n_pep], ascending
@@ -76,7 +83,21 @@ struct DevIndex {
     uint32_t ion_mult;         // most ion series on one terminus (counter bounds)
     uint32_t ion_series;       // enabled ion series
     int64_t min_residue;       // lightest residue incl. modification deltas (uDa)
+    // Dense lists: a list holding a large share of all ids is also kept as a
+    // map of two bits per id.  Byte g of a map covers ids 4g..4g+3: bit e is
+    // set when id 4g+e has a C-terminal posting in the list, bit 4+e when it
+    // has an N-terminal one.  Maps are zero up to a multiple of kDenseIdAlign
+    // ids, and a list becomes dense only if no (id, terminus) occurs twice in
+    // it, so the map holds exactly the list's postings.
+    // dense_tab[j] describes map j: bin | c << 24 | slot << 28, where c (1 or
+    // 2) is the most a probe on the list adds to one id's count and the map
+    // starts at dense_maps + slot * dense_stride.
+    const uint32_t* dense_tab;
+    const uint8_t* dense_maps;
+    uint64_t dense_stride;
+    uint32_t n_dense;          // maps in use (0: every list is scanned as postings)
 };
+
 
 // Per-spectrum summary written by the prep kernel.
 struct SpecInfo {
@@ -134,7 +155,7 @@ struct Work {
     uint32_t* spec_item0;      // [n + 1] first item of each spectrum
     ps_hit* hits;              // [n * top_k]
     ps_stat* stats;            // [n]
-    unsigned long long* counters;  // [8]: postings, bin lookups, work-queue head, items total, dump count
+    unsigned long long* counters;  // [kNumCounters], slots below
     // optional full dump of scored candidates
     uint32_t* dump_spec; uint32_t* dump_id; uint32_t* dump_cnt_lo; uint32_t* dump_cnt_hi;
     uint64_t dump_cap;
@@ -144,7 +165,10 @@ enum CounterSlot {
     kCtrPostings = 0, kCtrLookups = 1, kCtrQueue = 2, kCtrItems = 3, kCtrDump = 4,
     kCtrWide = 5,      // spectra that need 64-bit shared-peak counters
     kCtrOverflow = 6,  // spectra whose counter bound passes even the 64-bit form
+    kCtrDensePost = 7, // postings counted through dense maps (included in kCtrPostings)
+    kCtrDenseIds = 8,  // dense-map reads (candidates times dense probes)
 };
+constexpr uint32_t kNumCounters = 16;
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_fill_u32(void* p, uint32_t value, uint64_t count, hipStream_t stream);

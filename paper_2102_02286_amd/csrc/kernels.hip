@@ -444,6 +444,8 @@ constexpr uint32_t kRounds = 2;       // gather rounds of 64 posting quads a wav
 constexpr uint32_t kWaveCand = 96;    // candidates each wavefront buffers before scoring
 template <uint32_t NT> constexpr uint32_t cand_cap() { return kWaveCand * (NT / 64); }
 constexpr uint32_t kMapCap = 4096;    // flat quad positions mapped to slots at a time
+constexpr uint32_t kDenseProbes = 4;  // probes of a work item read from dense maps (others are streamed)
+constexpr uint32_t kDenseFloor = 2;   // lowest candidate-filter threshold that map probes may leave
 // map words: one per 64 quads, plus one for the start bit just past the chunk
 constexpr uint32_t kMapWords = kMapCap / 64 + 1;
 // s_waitcnt operand (gfx9 encoding): vmcnt(0), expcnt and lgkmcnt left at their maxima
@@ -452,7 +454,12 @@ constexpr int kWaitVmem0 = 0x0F70;
 template <uint32_t NT>
 struct ScanShared {
     uint32_t nact;
+    uint32_t ndense, dused;                    // map probes kept; their count bounds claimed
+    uint32_t dtab[kMaxDense];                  // the index's dense table
+    uint32_t dprobe[kDenseProbes];             // q | bound << 8 of each map probe
+    const uint8_t* dmap[kDenseProbes];         // its map
     unsigned long long acc_post, acc_look;     // the item's postings and bin lookups
+    unsigned long long acc_dpost, acc_dreads;  // postings counted from maps; map reads
     unsigned long long wsum[NT / 64];
     unsigned long long red[NT / 64];
     double wh[NT / 64][PS_MAX_TOP_K];          // per-wavefront top-k lists
@@ -614,7 +621,7 @@ __device__ __forceinline__ void block_scan_counts(bool active, uint32_t n, uint3
             ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
             et += (uint32_t)__popcll(m) << b;
         }
-        const uint32_t ntot = __shfl(incl, 63, 64);
+        const uint32_t ntot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);   // scalar: no lane address
         if (lane == 0) wsum[wave] = ((unsigned long long)et << 32) | ntot;
     }
     __syncthreads();
@@ -764,8 +771,12 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     const uint32_t m = kp.tile >> gsh;                 // directory entries per tile
     const uint32_t t0 = ida >> tsh, t_last = (idb - 1) >> tsh;
 
-    if (tid == 0) { sh.nact = 0; sh.acc_post = 0; sh.acc_look = 0; }
+    if (tid == 0) {
+        sh.nact = 0; sh.ndense = 0; sh.dused = 0;
+        sh.acc_post = 0; sh.acc_look = 0; sh.acc_dpost = 0; sh.acc_dreads = 0;
+    }
     for (uint32_t i = tid; i < (uint32_t)kHistBins; i += NT) L.hist[i] = 0;
+    if (tid < ix.n_dense) sh.dtab[tid] = ix.dense_tab[tid];
     __syncthreads();
 
     // end of tile u's part of a run that ends at s1
@@ -774,8 +785,11 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
         return edge >= idb ? s1 : min(s1, row[edge >> gsh]);
     };
 
-    unsigned long long lookups = 0, postings = 0;
+    unsigned long long lookups = 0, postings = 0, dpost = 0;
     const uint32_t npairs = n_ent * width;
+    // Map probes lower the filter's threshold by the most they can add to one
+    // id's count; they are taken only while it stays at kDenseFloor or more.
+    const uint32_t dbudget = kp.min_shared >= kDenseFloor ? kp.min_shared - kDenseFloor : 0u;
     const uint32_t gmask = (1u << gsh) - 1u;
     for (uint32_t k = tid; k < npairs; k += NT) {
         const uint32_t e = ent[k / width];
@@ -791,6 +805,23 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
         const uint32_t s1 = (idb & gmask) ? lower_bound_u32(list, row[kb], row[kb + 1], idb << 1) : row[kb];
         if (s1 <= s0) continue;
         postings += s1 - s0;
+        if (ix.n_dense && dbudget) {
+            uint32_t hit = 0;                           // the list's table entry (never 0)
+            for (uint32_t j = 0; j < ix.n_dense; ++j) {
+                const uint32_t t = sh.dtab[j];
+                if ((t & 0xFFFFFFu) == (uint32_t)bin) hit = t;
+            }
+            const uint32_t mc = (hit >> 24) & 3u;
+            if (hit && atomicAdd(&sh.dused, mc) + mc <= dbudget) {
+                const uint32_t j = atomicAdd(&sh.ndense, 1u);
+                if (j < kDenseProbes) {
+                    sh.dprobe[j] = (e & 0xFFu) | mc << 8;
+                    sh.dmap[j] = ix.dense_maps + (uint64_t)(hit >> 28) * ix.dense_stride;
+                    dpost += s1 - s0;
+                    continue;
+                }
+            }
+        }
         const uint32_t slot = atomicAdd(&sh.nact, 1u);
         SlotInit si;
         si.bin = (uint32_t)bin;
@@ -806,13 +837,19 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     for (int o = 32; o > 0; o >>= 1) {
         postings += __shfl_down(postings, o, 64);
         lookups += __shfl_down(lookups, o, 64);
+        dpost += __shfl_down(dpost, o, 64);
     }
     if (lane == 0) {
         if (postings) atomicAdd(&sh.acc_post, postings);
         if (lookups) atomicAdd(&sh.acc_look, lookups);
+        if (dpost) atomicAdd(&sh.acc_dpost, dpost);
     }
     __syncthreads();
     const uint32_t nact = sh.nact;
+    // what the map probes can add to one id's count at most
+    uint32_t dsum = 0;
+    for (uint32_t j = 0; j < min(sh.ndense, kDenseProbes); ++j) dsum += sh.dprobe[j] >> 8;
+    dsum = __builtin_amdgcn_readfirstlane(dsum);
     // slots [tid * us, tid * us + us) belong to this thread
     const uint32_t us = nact > NT ? (nact + NT - 1) / NT : 1u;
     // wavefronts holding no slot skip the per-tile scan; their totals are 0
@@ -847,7 +884,9 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     WaveTopK<C> top{sh.wh[wave], sh.wid[wave], sh.wc[wave]};
     top.init(kp.top_k);
     const uint32_t kk = kp.top_k;
-    const uint32_t kkey = Cnt<C>::key_min(kp.min_shared);   // filter threshold on counter keys
+    // filter threshold on counter keys: lowered by what the map probes can add
+    // (the exact test follows when candidates are scored)
+    const uint32_t kkey = Cnt<C>::key_min(kp.min_shared - dsum);
     uint32_t scored = 0;
     Gather g;
     uint32_t ptot = 0;
@@ -927,12 +966,33 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     // Candidates collect over tiles and are scored 64 at a time (full rounds),
     // when the buffer passes a round, when it could overflow, and at the end.
     uint32_t wn = 0;                                    // wave-uniform: candidates buffered
+    // With map probes, a buffered candidate first adds its bits from each map
+    // (C-terminal bit id % 4, N-terminal bit 4 + id % 4 of byte id / 4) and is
+    // scored only if its exact count reaches min_shared.
     auto score_buffer = [&]() {
         for (uint32_t base = 0; base < wn; base += 64u) {
             const uint32_t j = base + lane;
-            const bool ok = j < wn;
-            const C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
+            bool ok = j < wn;
+            C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
             const uint32_t id = ok ? L.cand_id[wbuf + j] : 0u;
+            const uint32_t nd = __builtin_amdgcn_readfirstlane(min(sh.ndense, kDenseProbes));
+            if (nd) {                                   // uniform
+#pragma unroll 1
+                for (uint32_t p = 0; p < nd; ++p) {
+                    // the map address, made uniform (readfirstlane returns int:
+                    // each half goes through uint32_t so that none is sign-extended)
+                    const uint64_t a = (uint64_t)sh.dmap[p];
+                    const uint32_t a_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+                    const uint32_t a_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+                    const uint8_t* mp = (const uint8_t*)((uint64_t)a_hi << 32 | (uint64_t)a_lo);
+                    const uint32_t q = __builtin_amdgcn_readfirstlane(sh.dprobe[p] & 0xFFu);
+                    const uint32_t x = ok ? (uint32_t)mp[id >> 2] >> (id & 3u) : 0u;
+                    c += ((x & 1u) ? Cnt<C>::inc(1u, q) : (C)0) + ((x & 16u) ? Cnt<C>::inc(0u, q) : (C)0);
+                }
+                const unsigned long long m = __ballot(ok);
+                if (lane == 0) atomicAdd(&sh.acc_dreads, (unsigned long long)nd * __popcll(m));
+                ok = ok && Cnt<C>::key(c) >= Cnt<C>::key_min(kp.min_shared);
+            }
             const double h = ok ? score_one<C, DUMP, NT>(A, L, s, id, c, scored) : -INFINITY;
             top.insert_lanes(ok, h, id, c, kk);
         }
@@ -1070,6 +1130,8 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     if (tid == 0) {
         if (sh.acc_post) atomicAdd(&A.w.counters[kCtrPostings], sh.acc_post);
         if (sh.acc_look) atomicAdd(&A.w.counters[kCtrLookups], sh.acc_look);
+        if (sh.acc_dpost) atomicAdd(&A.w.counters[kCtrDensePost], sh.acc_dpost);
+        if (sh.acc_dreads) atomicAdd(&A.w.counters[kCtrDenseIds], sh.acc_dreads);
     }
     __syncthreads();
 }

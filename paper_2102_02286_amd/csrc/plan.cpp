@@ -105,7 +105,7 @@ extern "C" int ps_plan_create(ps_index* ix, const ps_device* work, uint64_t n_ca
     chk(hipHostMalloc((void**)&P->h_hits, n_cap * kp.top_k * sizeof(ps_hit), hipHostMallocDefault));
     chk(hipHostMalloc((void**)&P->h_stats, n_cap * sizeof(ps_stat), hipHostMallocDefault));
     if (P->want_hist) chk(hipHostMalloc((void**)&P->h_hist, n_cap * (uint64_t)kHistBins * 4, hipHostMallocDefault));
-    chk(hipHostMalloc((void**)&P->h_counters, 8 * 8, hipHostMallocDefault));
+    chk(hipHostMalloc((void**)&P->h_counters, kNumCounters * 8, hipHostMallocDefault));
     if (e != hipSuccess) { plan_destroy(P); return fail(PS_EDEVICE, "plan set-up: %s", hipGetErrorString(e)); }
     // capture the kernel sequence once (with scan events if the runtime records them in graphs)
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -155,7 +155,7 @@ static int plan_launch(ps_plan* P) {
         if (P->want_hist)
             chk(hipMemcpyAsync(P->h_hist, P->w.hist, P->n * (uint64_t)kHistBins * 4, hipMemcpyDeviceToHost, st));
     }
-    chk(hipMemcpyAsync(P->h_counters, P->w.counters, 8 * 8, hipMemcpyDeviceToHost, st));
+    chk(hipMemcpyAsync(P->h_counters, P->w.counters, kNumCounters * 8, hipMemcpyDeviceToHost, st));
     chk(hipEventRecord(P->ev_done, st));
     if (e != hipSuccess) {
         // whatever was enqueued may still use the pinned buffers: let it end
@@ -268,6 +268,8 @@ extern "C" int ps_plan_counters(ps_plan* P, ps_counters* out) {
     out->work_items = P->schedule == PS_SCHED_PERSISTENT ? c[kCtrItems] : 0;
     out->wide_spectra = c[kCtrWide];
     out->overflow_spectra = c[kCtrOverflow];
+    out->dense_postings = c[kCtrDensePost];
+    out->dense_reads = c[kCtrDenseIds];
     return PS_OK;
 }
 

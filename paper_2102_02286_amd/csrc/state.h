@@ -70,6 +70,10 @@ struct ps_index {
     const uint64_t* dev_mask = nullptr;
     uint64_t dev_n_post = 0, dev_dir_entries = 0;
     uint64_t dev_n_quads = 0;    // padded postings on the device / 4
+    // dense maps (lists holding a large share of the ids), built on the device
+    uint32_t n_dense = 0;
+    uint32_t dense_bin[ps::kMaxDense] = {};
+    bool dense_on = true;        // searches read them (ps_index_set_dense)
 };
 
 namespace ps {
@@ -87,9 +91,23 @@ uint64_t padded_quads(const ps_index* ix);
 struct DevLayout {
     uint64_t mass, bin, post, lf, ls, dir;
     uint64_t prot, start, mask, len;   // the entry table, kept on the device by a device build (else empty)
+    uint64_t dense, dense_stride;      // dense_cap maps of dense_stride bytes
+    uint64_t dense_flags;              // u32 [kMaxDense] flags of the candidate maps, then
+                                       // u32 [kMaxDense] table of the maps in use (DevIndex::dense_tab)
+    uint32_t dense_cap;
     uint64_t total;
 };
-DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir, bool entries = false);
+DevLayout index_layout(uint64_t n_pep, uint64_t n_bins, uint64_t n_quads, uint64_t n_dir, bool entries,
+                       uint32_t dense_cap);
+// Lists that qualify as dense (at least a quarter of the ids), longest first,
+// at most kMaxDense, from the host bin offsets.
+std::vector<uint32_t> dense_candidates(const ps_index* ix);
+// Build the dense maps of the candidate lists into the index block (after
+// bind_device_index) and enable them; a list whose postings repeat an
+// (id, terminus) pair keeps no map.  Synchronizes `st`.
+int build_dense_maps(ps_index* ix, char* base, const DevLayout& lay, hipStream_t st);
+// Point the kernels' view at the maps in use (none while searches are told not to read them).
+void bind_dense(ps_index* ix);
 // Point ix->dev at an index block laid out by `lay` and mark the index on the device.
 void bind_device_index(ps_index* ix, char* base, const DevLayout& lay);
 // Modification lookup: which mod (if any) sits on each residue letter; the N-terminal mod.

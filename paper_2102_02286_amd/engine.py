@@ -171,6 +171,16 @@ class HostIndex:
         check(capi.ps_index_directory(self.handle, C.byref(g), C.byref(b), None))
         return g.value, b.value
 
+    def dense(self):
+        """(bins with a dense map, whether searches read them)."""
+        n, on = C.c_uint32(), C.c_int()
+        bins = np.zeros(capi.PS_MAX_DENSE, np.uint32)
+        check(capi.ps_index_dense(self.handle, C.byref(n), ptr(bins), C.byref(on)))
+        return bins[:n.value].copy(), bool(on.value)
+
+    def set_dense(self, enabled: bool):
+        check(capi.ps_index_set_dense(self.handle, 1 if enabled else 0), "ps_index_set_dense")
+
     def directory_array(self) -> np.ndarray:
         """Host copy of the tile directory, [n_bins, stride] with stride =
         (n_pep >> grain) + 2 rounded up to a multiple of 4."""
@@ -230,6 +240,8 @@ class Results:
     lookups: int
     wide_spectra: int = 0
     overflow_spectra: int = 0
+    dense_postings: int = 0  # of `postings`, those counted through dense maps
+    dense_reads: int = 0     # dense-map reads (candidates times dense probes)
 
 
 def search(index: HostIndex, sp, params: capi.ps_search_params, ws: Workspace | None = None) -> Results:
@@ -285,7 +297,7 @@ def collect(batch, n: int, params: capi.ps_search_params) -> Results:
     check(capi.ps_batch_counters(batch, C.byref(ct)), "ps_batch_counters")
     return Results(hits.reshape(n, params.top_k), stats,
                    hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, ms.value, po.value, lk.value,
-                   ct.wide_spectra, ct.overflow_spectra)
+                   ct.wide_spectra, ct.overflow_spectra, ct.dense_postings, ct.dense_reads)
 
 
 def _device_results(batch):
@@ -461,7 +473,7 @@ class Plan:
         check(capi.ps_plan_counters(self.handle, C.byref(ct)), "ps_plan_counters")
         r = Results(hits.reshape(n, prm.top_k), stats,
                     hist.reshape(n, capi.PS_HIST_BINS) if hist is not None else None, sc.value, po.value, lk.value,
-                    ct.wide_spectra, ct.overflow_spectra)
+                    ct.wide_spectra, ct.overflow_spectra, ct.dense_postings, ct.dense_reads)
         r.graph_ms = g.value
         r.items = it.value
         return r

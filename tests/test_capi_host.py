@@ -164,6 +164,21 @@ def test_schedule_validation_and_tile_directory():
     assert h.schedule().group_threads == 512
 
 
+def test_dense_maps_exist_only_on_the_device():
+    """Dense maps are built when the index goes to the device; a host index
+    has none, and the switch that stops searches reading them is kept."""
+    prot = synth.make_proteome(40, seed=2)
+    h = engine.HostIndex(prot.residues, prot.offsets, 1, 7, 30, [], 0)
+    bins, on = h.dense()
+    assert bins.size == 0 and on
+    h.set_dense(False)
+    assert h.dense()[1] is False
+    h.set_dense(True)
+    assert h.dense()[1] is True
+    assert capi.ps_index_dense(None, None, None, None) == capi.PS_EINVAL
+    assert capi.ps_index_set_dense(None, 0) == capi.PS_EINVAL
+
+
 def test_tile_directory_matches_postings():
     """dir[bin][k] is the position, inside the bin's own list, of the first
     posting whose id is >= k * 4096 (rows padded to a multiple of four

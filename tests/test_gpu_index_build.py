@@ -39,6 +39,14 @@ def _assert_same_index(host, dev):
     assert host.directory() == dev.directory()
     assert np.array_equal(host.directory_array(), dev.directory_array()), "tile directories differ"
     assert host.schedule().tile == dev.schedule().tile
+    # dense maps: the lists of at least n_pep / 4 postings (longest first, at
+    # most eight) without a repeated posting
+    L = np.diff(oh.astype(np.int64))
+    n_pep = len(host)
+    order = np.lexsort((np.arange(L.size), -L))
+    cand = [int(b) for b in order[:64] if n_pep and L[b] * 4 >= n_pep][:capi.PS_MAX_DENSE]
+    want = [b for b in cand if np.unique(ph[oh[b]:oh[b + 1]]).size == L[b]]
+    assert dev.dense()[0].tolist() == want
     # the device-built index keeps its entry table on the device: single entries
     # and peptide strings read back from it equal the host build's
     n = len(host)
