@@ -441,7 +441,7 @@ struct ScanArgs {
 // sharing one tile of counters; a tile has at least 16 NT ids, so the filter
 // reads whole passes of 16-byte counter groups.
 constexpr uint32_t kRounds = 2;       // gather rounds of 64 posting quads a wavefront keeps in flight
-constexpr uint32_t kWaveCand = 96;    // candidates each wavefront buffers before scoring
+constexpr uint32_t kWaveCand = 128;   // candidates each wavefront buffers before scoring (two rounds)
 template <uint32_t NT> constexpr uint32_t cand_cap() { return kWaveCand * (NT / 64); }
 constexpr uint32_t kMapCap = 4096;    // flat quad positions mapped to slots at a time
 constexpr uint32_t kDenseProbes = 4;  // probes of a work item read from dense maps (others are streamed)
@@ -861,6 +861,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     // loaded one tile before its first use.
     auto needs_dir = [&](uint32_t u) { return ((uint64_t)(u + 1) << tsh) < (uint64_t)idb; };   // end(u) < s1?
     auto quad_at = [&](uint32_t bin, uint32_t idx) {
+        asm volatile("" : "+v"(bin));                  // keep the row address inside the loop (no hoisted pair to spill)
         return *(const uint4*)(ix.dir + (uint64_t)bin * stride + (idx & ~3u));
     };
     uint32_t o_bq[U], o_s1[U], o_cur[U], o_end[U], o_nxt[U];   // o_bq = bin | q << 24
@@ -925,7 +926,12 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
                 const uint32_t a = o_cur[u] & ~3u;      // the run's first aligned quad (lists start on quads)
                 SegBase sb;
                 sb.base = L.sqb[tid * us + u] + (a >> 2) - run;   // modulo 2^32: base + f is the quad
-                sb.qx = (o_bq[u] >> 24) | (o_cur[u] & 3u) << 8 | (o_end[u] - a - 4u * (n - 1u) - 1u) << 10;
+                // the intensity is taken from o_bq here, every tile: the empty asm
+                // keeps the compiler from hoisting o_bq >> 24 out of the tile loop
+                // as a second live register (which it then spills)
+                uint32_t bq = o_bq[u];
+                asm volatile("" : "+v"(bq));
+                sb.qx = (bq >> 24) | (o_cur[u] & 3u) << 8 | (o_end[u] - a - 4u * (n - 1u) - 1u) << 10;
                 L.sbase[rank] = sb;
                 L.sstart[rank] = run;
                 map_slot<C, NT>(L, rank, run, run + n, 0u);
@@ -963,14 +969,16 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
     // anyway.  Each wavefront buffers its own candidates (kWaveCand slots from wbuf) and
     // scores them itself, so the filter needs no shared counter or barrier.
     const uint32_t wbuf = wave * kWaveCand;
-    // Candidates collect over tiles and are scored 64 at a time (full rounds),
-    // when the buffer passes a round, when it could overflow, and at the end.
+    // Candidates collect over tiles and are scored in full rounds of 64 while
+    // the item runs (the rest of a round moves to the front of the buffer), and
+    // all that is left at the end of the item.
     uint32_t wn = 0;                                    // wave-uniform: candidates buffered
     // With map probes, a buffered candidate first adds its bits from each map
     // (C-terminal bit id % 4, N-terminal bit 4 + id % 4 of byte id / 4) and is
     // scored only if its exact count reaches min_shared.
-    auto score_buffer = [&]() {
-        for (uint32_t base = 0; base < wn; base += 64u) {
+    auto score_buffer = [&](bool full_rounds) {
+        const uint32_t end = full_rounds ? wn & ~63u : wn;
+        for (uint32_t base = 0; base < end; base += 64u) {
             const uint32_t j = base + lane;
             bool ok = j < wn;
             C c = ok ? L.cand_cnt[wbuf + j] : (C)0;
@@ -996,7 +1004,14 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
             const double h = ok ? score_one<C, DUMP, NT>(A, L, s, id, c, scored) : -INFINITY;
             top.insert_lanes(ok, h, id, c, kk);
         }
-        wn = 0;
+        // what is left of a partial round moves to the front (one wavefront:
+        // every lane reads before it writes, and the ranges do not overlap)
+        const uint32_t rest = wn - end;
+        const bool mv = lane < rest;
+        const C rc = mv ? L.cand_cnt[wbuf + end + lane] : (C)0;
+        const uint32_t rid = mv ? L.cand_id[wbuf + end + lane] : 0u;
+        if (mv) { L.cand_cnt[wbuf + lane] = rc; L.cand_id[wbuf + lane] = rid; }
+        wn = rest;
     };
     const uint32_t t_end = nact > 0 ? t_last + 1 : t0;
     for (uint32_t t = t0; t < t_end; ++t) {
@@ -1082,7 +1097,7 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
                     const bool pass = key[e] >= kkey;
                     const unsigned long long msk = __ballot(pass);
                     if (msk == 0) continue;             // wave-uniform
-                    if (wn > kWaveCand - 64u) score_buffer();   // room for a whole wavefront
+                    if (wn > kWaveCand - 64u) score_buffer(true);   // room for a whole wavefront
                     const uint32_t off = wn + __builtin_amdgcn_mbcnt_hi((uint32_t)(msk >> 32),
                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0u));
                     if (pass) {
@@ -1093,12 +1108,12 @@ __device__ void scan_item(const ScanArgs& A, ScanShared<NT>& sh, ScanLds<C, NT>&
                 }
             }
             }
-            if (wn >= 64u) score_buffer();
+            if (wn >= 64u) score_buffer(true);
         }
         if (t < t_last) __syncthreads();               // counters clear before tile t + 1 is consumed
     }
 
-    score_buffer();                                     // what is left of the item's candidates
+    score_buffer(false);                                // what is left of the item's candidates
     // top-k of the item: the wavefronts' lists (in LDS), merged by one thread
     const unsigned long long sc = block_sum<unsigned long long, NT>(scored, sh.red);   // has barriers
     if (tid == 0) {
