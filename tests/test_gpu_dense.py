@@ -98,6 +98,26 @@ def test_dense_open_search_equals_postings_and_oracle(open_db, merge, schedule):
     assert c_on.postings == int(ost["pairs_total"].sum())
 
 
+@pytest.mark.parametrize("schedule", [capi.PS_SCHED_PLAIN, capi.PS_SCHED_PERSISTENT])
+def test_dense_budget_of_one_count(open_db, schedule):
+    """min_shared 3 leaves a budget of one count: an item reads at most one
+    probe from a map and streams any other, and the filter's threshold drops
+    to 2.  Results must equal the postings-only search and the oracle."""
+    w, prot, sp, db = open_db
+    ix = engine.HostIndex(prot.residues, prot.offsets, w.missed, w.min_len, w.max_len,
+                          engine.mods_from_synth(w.mods), w.max_mods, merge_tol=1).upload()
+    prm = engine.search_params(w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, 3,
+                               max_charge=3, schedule=schedule)
+    _say(f"dense: min_shared 3, schedule {schedule}")
+    r_on, r_off, c_on, c_off = _on_off(ix, sp, prm)
+    _same(r_on, r_off)
+    assert c_on.postings == c_off.postings and 0 < c_on.dense_postings < c_on.postings
+    oh, ost, og = db.search(sp, w.window_is_ppm, w.window, w.frag_tol_bins, w.top_peaks, w.top_k, 3)
+    assert r_on.hits["id"].tobytes() == oh["id"].tobytes()
+    assert np.array_equal(r_on.stats["n_scored"], ost["n_scored"])
+    assert np.array_equal(r_on.hist, og)
+
+
 @pytest.mark.parametrize("tile,threads,tpi", [(4096, 256, 1), (8192, 512, 3), (32768, 512, 2), (16384, 256, 5)])
 def test_dense_with_schedules_and_item_edges(open_db, tile, threads, tpi):
     """Work items that start and end inside tiles, several candidate buffers
