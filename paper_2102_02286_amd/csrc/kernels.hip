@@ -440,7 +440,7 @@ struct ScanArgs {
 // The scan runs in workgroups of NT = 256 or 512 threads (4 or 8 wavefronts)
 // sharing one tile of counters; a tile has at least 16 NT ids, so the filter
 // reads whole passes of 16-byte counter groups.
-constexpr uint32_t kRounds = 2;       // gather rounds of 64 posting quads a wavefront keeps in flight
+constexpr uint32_t kRounds = 1;       // gather rounds of 64 posting quads a wavefront keeps in flight
 constexpr uint32_t kWaveCand = 128;   // candidates each wavefront buffers before scoring (two rounds)
 template <uint32_t NT> constexpr uint32_t cand_cap() { return kWaveCand * (NT / 64); }
 constexpr uint32_t kMapCap = 4096;    // flat quad positions mapped to slots at a time
